@@ -1,0 +1,595 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms, brute-force path sums, the lattice Debye (linear-response) function in
+Fourier space, exact symmetries and special cases, the paper's Table 1, and
+conservation laws.  No GPU needed.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1204_2088_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def normalised_random_c(seed):
+    rng = np.random.default_rng(seed)
+    raw = rng.uniform(0.2, 1.0, size=4)
+    return raw / (raw[0] + 6 * raw[1] + 12 * raw[2] + 8 * raw[3])
+
+
+def stencil_symbol(c, kx, ky, kz):
+    """Fourier symbol of the class-weighted 27-point stencil."""
+    cx, cy, cz = np.cos(kx), np.cos(ky), np.cos(kz)
+    return (c[0] + 2 * c[1] * (cx + cy + cz) + 4 * c[2] * (cx * cy + cx * cz + cy * cz)
+            + 8 * c[3] * cx * cy * cz)
+
+
+def transfer_matrix(L, c):
+    """Bond weight between every pair of sites of an L^3 periodic box (brute force)."""
+    coords = np.array(list(itertools.product(range(L), repeat=3)))  # (z, y, x) order
+    V = len(coords)
+    T = np.zeros((V, V))
+    for i in range(V):
+        d = (coords - coords[i]) % L
+        d = np.where(d > L // 2, d - L, d)
+        ok = np.all(np.abs(d) <= 1, axis=1)
+        k = np.sum(d != 0, axis=1)
+        T[i, ok] = c[k[ok]]
+    return T
+
+
+# ---------------------------------------------------------------- stencil
+
+def test_stencil_weights_reading(orc):
+    """Tensor-product reading: normalisation 1 and per-axis variance a^2/3."""
+    a = 1.1543
+    c = orc.stencil_weights(a)
+    assert abs(c[0] + 6 * c[1] + 12 * c[2] + 8 * c[3] - 1.0) < 1e-15
+    # second moment along x: sum over offsets with dx = +-1
+    var_x = 2 * (c[1] + 4 * c[2] + 4 * c[3])
+    assert abs(var_x - a * a / 3) < 1e-15
+    al = a * a / 6
+    assert np.allclose(c, [(1 - 2 * al) ** 3, al * (1 - 2 * al) ** 2, al ** 2 * (1 - 2 * al), al ** 3], rtol=0, atol=1e-16)
+
+
+def test_sigma_fourier_symbol(orc):
+    """sigma acting on a plane wave multiplies it by the stencil symbol."""
+    c = normalised_random_c(1)
+    sys_ = orc.System(L=(6, 5, 7), types=[0], c=c)
+    Lx, Ly, Lz = sys_.L
+    z, y, x = np.meshgrid(np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing="ij")
+    for (mx, my, mz) in [(1, 0, 0), (0, 2, 3), (2, 1, 1), (3, 2, 6)]:
+        kx, ky, kz = 2 * np.pi * mx / Lx, 2 * np.pi * my / Ly, 2 * np.pi * mz / Lz
+        f = np.cos(kx * x + ky * y + kz * z)
+        out = orc.sigma(sys_, f)
+        assert np.max(np.abs(out - stencil_symbol(c, kx, ky, kz) * f)) < 1e-14
+
+
+def test_sigma_matches_brute_force_matrix(orc):
+    c = normalised_random_c(2)
+    L = 4
+    sys_ = orc.System(L=(L, L, L), types=[0], c=c)
+    f = np.random.default_rng(3).standard_normal((L, L, L))
+    T = transfer_matrix(L, c)
+    assert np.max(np.abs(orc.sigma(sys_, f).ravel() - T @ f.ravel())) < 1e-14
+
+
+# ---------------------------------------------------------------- propagators
+
+def test_homogeneous_melt_closed_form(orc):
+    """P1: constant fields give G_s = exp(-sum of w along the first s beads)."""
+    types = W.chain(3, 5)
+    sys_ = orc.System(L=(5, 4, 6), types=types, c=orc.stencil_weights(1.1543))
+    wa, wb = 0.37, -1.21
+    w = np.empty((2,) + sys_.shape)
+    w[0], w[1] = wa, wb
+    phi, Q, Qs = orc.evaluate(sys_, w, phibar_p=0.83, with_qs=True)
+    Qexact = np.exp(-(3 * wa + 5 * wb))
+    assert abs(Q / Qexact - 1) < 1e-14
+    assert np.max(np.abs(Qs / Qexact - 1)) < 1e-14
+    assert np.max(np.abs(phi[0] - 0.83 * 3 / 8)) < 1e-14
+    assert np.max(np.abs(phi[1] - 0.83 * 5 / 8)) < 1e-14
+
+
+def test_q_equal_at_every_contour_index(orc):
+    """P2: V^-1 sum_r G_s sigma[G+_{s+1}] equals Q for every s."""
+    types = W.chain(4, 4)
+    sys_ = orc.System(L=(8, 6, 5), types=types, c=orc.stencil_weights(1.1543))
+    w = W.random_fields((2,) + sys_.shape, seed=7, amplitude=1.5)
+    _, Q, Qs = orc.evaluate(sys_, w, with_qs=True)
+    assert np.max(np.abs(Qs / Q - 1)) < 1e-13
+
+
+@pytest.mark.parametrize("types", [[0, 1, 1], [0, 0, 1], [0, 1, 1, 0], [0, 0, 1, 1]])
+def test_brute_force_paths_4cubed(orc, types):
+    """P3: explicit sum over all 64^N chain paths on a 4^3 lattice."""
+    L = 4
+    c = normalised_random_c(11)
+    sys_ = orc.System(L=(L, L, L), types=types, c=c)
+    w = W.random_fields((2,) + sys_.shape, seed=5, amplitude=1.0)
+    phibar = 0.9
+    phi, Q = orc.evaluate(sys_, w, phibar_p=phibar)
+
+    V = L ** 3
+    T = transfer_matrix(L, c)
+    E = np.exp(-w.reshape(2, V))
+    N = len(types)
+    # weight of every path (R_1..R_N): prod_s E_{t_s}(R_s) prod_s T(R_{s-1}, R_s)
+    Wt = E[types[0]].copy()
+    for s in range(1, N):
+        Wt = Wt[..., None] * T.reshape((1,) * (s - 1) + (V, V)) * E[types[s]].reshape((1,) * s + (V,))
+    Qbf = Wt.sum() / V
+    assert abs(Q / Qbf - 1) < 1e-13
+    dens = np.zeros((2, V))
+    for s in range(N):
+        axes = tuple(a for a in range(N) if a != s)
+        dens[types[s]] += Wt.sum(axis=axes)
+    dens *= phibar / (N * Qbf)
+    assert np.max(np.abs(phi.reshape(2, V) - dens)) < 1e-13
+
+
+def test_linear_response_debye(orc):
+    """P4: small fields around the homogeneous melt give the lattice Debye response
+    dphi_I(k) = -(phibar/N) sum_{s in I, s'} sigma_hat(k)^|s-s'| dw_{t_s'}(k)."""
+    types = W.chain(2, 4)
+    c = normalised_random_c(4)
+    L = (8, 6, 7)
+    sys_ = orc.System(L=L, types=types, c=c)
+    eps = 1e-6
+    dw = W.random_fields((2,) + sys_.shape, seed=9, amplitude=1.0)
+    dw -= dw.mean(axis=(1, 2, 3), keepdims=True)
+    phi0, _ = orc.evaluate(sys_, np.zeros_like(dw))
+    phi1, _ = orc.evaluate(sys_, eps * dw)
+    dphi = (phi1 - phi0) / eps
+    Lx, Ly, Lz = L
+    kz = 2 * np.pi * np.fft.fftfreq(Lz)[:, None, None]
+    ky = 2 * np.pi * np.fft.fftfreq(Ly)[None, :, None]
+    kx = 2 * np.pi * np.fft.fftfreq(Lx)[None, None, :]
+    sh = stencil_symbol(c, kx, ky, kz)
+    dwk = np.fft.fftn(dw, axes=(1, 2, 3))
+    pred = np.zeros_like(dwk)
+    N = len(types)
+    for s in range(N):
+        for sp in range(N):
+            pred[types[s]] += -(1.0 / N) * sh ** abs(s - sp) * dwk[types[sp]]
+    got = np.fft.fftn(dphi, axes=(1, 2, 3))
+    assert np.max(np.abs(got - pred)) / np.max(np.abs(pred)) < 1e-5
+
+
+def test_gradient_of_objective_is_density_mismatch(orc):
+    """P5: d ln Q / d w_I(r) = -N phi_I(r) / (phibar V), by central differences."""
+    types = W.chain(2, 3)
+    sys_ = orc.System(L=(4, 5, 3), types=types, c=orc.stencil_weights(1.1543))
+    w = W.random_fields((2,) + sys_.shape, seed=21, amplitude=0.8)
+    phi, _ = orc.evaluate(sys_, w, phibar_p=1.0)
+    V, N = sys_.V, sys_.N
+    h = 1e-5
+    for (I, z, y, x) in [(0, 0, 0, 0), (1, 2, 4, 3), (0, 1, 2, 1), (1, 0, 3, 2)]:
+        wp = w.copy(); wp[I, z, y, x] += h
+        wm = w.copy(); wm[I, z, y, x] -= h
+        fd = (orc.log_q(sys_, wp) - orc.log_q(sys_, wm)) / (2 * h)
+        assert abs(fd - (-N * phi[I, z, y, x] / V)) < 1e-9
+
+
+def test_separable_field_reduces_to_1d(orc):
+    """P7: fields depending on x only reduce to a 1-D chain with marginal weights."""
+    types = W.chain(3, 2)
+    c = normalised_random_c(8)
+    Lx, Ly, Lz = 7, 4, 5
+    sys_ = orc.System(L=(Lx, Ly, Lz), types=types, c=c)
+    w1 = np.random.default_rng(2).uniform(-1, 1, size=(2, Lx))
+    w = np.ascontiguousarray(np.broadcast_to(w1[:, None, None, :], (2, Lz, Ly, Lx)))
+    phi, Q = orc.evaluate(sys_, w, phibar_p=1.0)
+    m0 = c[0] + 4 * c[1] + 4 * c[2]
+    m1 = c[1] + 4 * c[2] + 4 * c[3]
+
+    def s1(f):
+        return m0 * f + m1 * (np.roll(f, 1) + np.roll(f, -1))
+
+    E = np.exp(-w1)
+    N = len(types)
+    G = [np.ones(Lx)]
+    for s in range(1, N + 1):
+        G.append(E[types[s - 1]] * s1(G[-1]))
+    Q1 = G[N].mean()
+    Gp = np.ones(Lx)
+    dens = np.zeros((2, Lx))
+    for s in range(N, 0, -1):
+        Sg = s1(Gp)
+        dens[types[s - 1]] += G[s] * Sg
+        Gp = E[types[s - 1]] * Sg
+    dens *= 1.0 / (N * Q1)
+    assert abs(Q / Q1 - 1) < 1e-14
+    assert np.max(np.abs(phi - dens[:, None, None, :])) < 1e-14
+
+
+def test_cubic_symmetry_and_translation(orc):
+    """P8: phi[R w] = R phi[w] for axis permutations, reflections and shifts."""
+    types = W.chain(2, 3)
+    L = 5
+    sys_ = orc.System(L=(L, L, L), types=types, c=orc.stencil_weights(1.1543))
+    w = W.random_fields((2,) + sys_.shape, seed=3, amplitude=1.0)
+    phi, Q = orc.evaluate(sys_, w)
+    ops = [lambda a: np.transpose(a, (0, 2, 1, 3)), lambda a: np.transpose(a, (0, 3, 2, 1)),
+           lambda a: a[:, ::-1], lambda a: a[:, :, :, ::-1],
+           lambda a: np.roll(a, 2, axis=1), lambda a: np.roll(a, -1, axis=3)]
+    for op in ops:
+        p2, Q2 = orc.evaluate(sys_, np.ascontiguousarray(op(w)))
+        assert abs(Q2 / Q - 1) < 1e-13
+        assert np.max(np.abs(p2 - op(phi))) < 1e-14
+
+
+def test_solvent_closed_form(orc):
+    """P9: the solvent density of eq. 2 and its closed-form inverse."""
+    types = W.chain(1, 2)
+    sys_ = orc.System(L=(4, 4, 4), types=types, has_solvent=True, c=orc.stencil_weights(1.1543))
+    rng = np.random.default_rng(0)
+    phis = rng.uniform(0.5, 0.9, size=sys_.shape)
+    w = np.zeros((3,) + sys_.shape)
+    w[2] = -np.log(phis / phis.mean())
+    phi, _ = orc.evaluate(sys_, w, phibar_p=0.3, phibar_s=phis.mean())
+    assert np.max(np.abs(phi[2] - phis)) < 1e-15
+
+
+def test_inversion_round_trip(orc):
+    """P6: w_true -> phi -> w*: densities reproduced, fields equal up to a constant."""
+    types = W.chain(4, 4)
+    sys_ = orc.System(L=(8, 8, 8), types=types, c=orc.stencil_weights(1.1543))
+    wt = W.random_fields((2,) + sys_.shape, seed=12, amplitude=0.6, smooth=1)
+    wt -= wt.mean(axis=(1, 2, 3), keepdims=True)
+    phit, _ = orc.evaluate(sys_, wt, phibar_p=1.0)
+    w0 = -np.log(phit / phit.mean(axis=(1, 2, 3), keepdims=True))
+    w, st, rc = orc.invert(sys_, phit, w0, tol=1e-11, max_iter=2000)
+    assert rc == 0 and st["converged"], st
+    phi, _ = orc.evaluate(sys_, w, phibar_p=1.0)
+    rel = max(np.linalg.norm(phi[I] - phit[I]) / np.linalg.norm(phit[I]) for I in range(2))
+    assert rel <= 1e-11
+    assert abs(rel - st["residual"]) < 1e-13
+    d = (w - w.mean(axis=(1, 2, 3), keepdims=True)) - wt
+    assert np.max(np.abs(d)) < 1e-8
+
+
+def test_inversion_solution_round_trip(orc):
+    """P6 for a copolymer solution: the solvent field is the closed form."""
+    types = W.chain(1, 3)
+    sys_ = orc.System(L=(6, 6, 6), types=types, has_solvent=True, c=orc.stencil_weights(1.1543))
+    wt = W.random_fields((3,) + sys_.shape, seed=13, amplitude=0.5, smooth=1)
+    wt -= wt.mean(axis=(1, 2, 3), keepdims=True)
+    phit, _ = orc.evaluate(sys_, wt, phibar_p=0.2, phibar_s=0.8)
+    w0 = np.zeros_like(phit)
+    w, st, rc = orc.invert(sys_, phit, w0, tol=1e-10, max_iter=2000)
+    assert rc == 0, st
+    phi, _ = orc.evaluate(sys_, w, phibar_p=0.2, phibar_s=0.8)
+    assert np.max(np.abs(phi - phit)) < 1e-10
+    assert np.max(np.abs((w - w.mean(axis=(1, 2, 3), keepdims=True)) - wt)) < 1e-7
+
+
+def test_inversion_fixed_iterations_and_max_iter(orc):
+    types = W.chain(2, 2)
+    sys_ = orc.System(L=(6, 6, 6), types=types, c=orc.stencil_weights(1.1543))
+    wt = W.random_fields((2,) + sys_.shape, seed=1, amplitude=0.5)
+    phit, _ = orc.evaluate(sys_, wt - wt.mean(axis=(1, 2, 3), keepdims=True))
+    w0 = np.zeros_like(phit)
+    _, st, rc = orc.invert(sys_, phit, w0, tol=1e-30, max_iter=3)
+    assert rc == 1 and st["iterations"] == 3 and not st["converged"]
+    _, st2, rc2 = orc.invert(sys_, phit, w0, tol=1e-30, max_iter=1, fixed_iters=5)
+    assert rc2 == 0 and st2["iterations"] == 5
+
+
+# ---------------------------------------------------------------- lattice Boltzmann
+
+def test_paper_parameters_golden(orc):
+    g = json.load(open(os.path.join(GOLDEN, "paper_parameters.json")))
+    a = g["segment_length_a"]
+    c = orc.stencil_weights(a)
+    assert abs(2 * (c[1] + 4 * c[2] + 4 * c[3]) - a * a / 3) < 1e-15
+    neq = orc.lb_equilibrium(1.0, np.zeros(3))
+    assert abs(neq[0] - 1 / 3) < 1e-16
+    assert np.allclose(neq[1:7], 1 / 18, rtol=0, atol=1e-17)
+    assert np.allclose(neq[7:], 1 / 36, rtol=0, atol=1e-17)
+
+
+def test_d3q19_velocity_set(orc):
+    c = orc.lb_velocities()
+    assert len({tuple(v) for v in c}) == 19
+    n2 = np.sum(c * c, axis=1)
+    assert n2[0] == 0 and np.all(n2[1:7] == 1) and np.all(n2[7:] == 2)
+
+
+def test_equilibrium_moments(orc):
+    """P10: moments of eq. 11: rho, rho u and rho u u + rho c_s^2 I."""
+    c = orc.lb_velocities().astype(float)
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        rho = rng.uniform(0.8, 1.2)
+        u = rng.uniform(-0.1, 0.1, size=3)
+        neq = orc.lb_equilibrium(rho, u)
+        assert abs(neq.sum() - rho) < 1e-15
+        assert np.max(np.abs(neq @ c - rho * u)) < 1e-15
+        P = np.einsum("i,ia,ib->ab", neq, c, c)
+        assert np.max(np.abs(P - (rho * np.outer(u, u) + rho / 3 * np.eye(3)))) < 1e-15
+
+
+def test_table1_basis_golden_and_orthogonality(orc):
+    """Table 1: basis typed from the paper, orthogonal under sum_i w_i e_ki e_li."""
+    g = json.load(open(os.path.join(GOLDEN, "d3q19_mrt_basis.json")))
+    cv = orc.lb_velocities().astype(float)
+    Bo = orc.mrt_basis()
+    for k, (expr, _) in enumerate(g["modes"]):
+        for i in range(19):
+            cx, cy, cz = cv[i]
+            c2 = cx * cx + cy * cy + cz * cz
+            assert abs(eval(expr, {}, {"cx": cx, "cy": cy, "cz": cz, "c2": c2}) - Bo[k, i]) == 0
+    wv = orc.lb_equilibrium(1.0, np.zeros(3))
+    Gm = (Bo * wv) @ Bo.T
+    assert np.max(np.abs(Gm - np.diag(np.diag(Gm)))) < 1e-15
+    b = np.array([1, 1 / 3, 1 / 3, 1 / 3, 2 / 3, 4 / 9, 4 / 3, 1 / 9, 1 / 9, 1 / 9,
+                  2 / 3, 2 / 3, 2 / 3, 2 / 9, 2 / 9, 2 / 9, 2, 4 / 9, 4 / 3])
+    assert np.max(np.abs(np.diag(Gm) - b)) < 1e-15
+
+
+def _lb_random_state(orc, sys_, seed, amp=0.02):
+    rng = np.random.default_rng(seed)
+    n = orc.lb_rest_state(sys_) * (1 + amp * rng.uniform(-1, 1, size=(19,) + sys_.shape))
+    f = 1e-3 * rng.uniform(-1, 1, size=(3,) + sys_.shape)
+    return np.ascontiguousarray(n), np.ascontiguousarray(f)
+
+
+@pytest.mark.parametrize("mode,tau", [(0, 0.6), (0, 1.5), (1, 0.8)])
+def test_lb_mass_and_momentum(orc, mode, tau):
+    """P11: mass conserved exactly; the collision adds exactly f to the site momentum."""
+    sys_ = orc.System(L=(5, 4, 3), types=[0], tau=tau, lb_mode=mode,
+                      gamma_b=0.3, gamma_s=-0.2, gamma_ghost=0.1)
+    n, f = _lb_random_state(orc, sys_, 4)
+    n2, rho, u = orc.lb_step(sys_, n, f)
+    assert abs(n2.sum() / n.sum() - 1) < 1e-15
+    cv = orc.lb_velocities()
+    # undo streaming: post-collision population at r is n2[i] at r + c_i
+    nstar = np.stack([np.roll(n2[i], shift=(-cv[i][2], -cv[i][1], -cv[i][0]), axis=(0, 1, 2)) for i in range(19)])
+    dj = np.einsum("i...,ia->a...", nstar - n, cv.astype(float))
+    assert np.max(np.abs(dj - f)) < 5e-16
+    assert np.max(np.abs(nstar.sum(0) - n.sum(0))) < 2e-15
+    jn = np.einsum("i...,ia->a...", n, cv.astype(float))
+    assert np.max(np.abs(rho * u - (jn + 0.5 * f))) < 1e-16
+
+
+def test_lb_rest_state_is_fixed_point(orc):
+    """P12: the fluid at rest without force stays at rest (velocity exactly zero,
+    populations to the rounding of the density sum)."""
+    sys_ = orc.System(L=(4, 4, 4), types=[0], tau=0.7)
+    n = orc.lb_rest_state(sys_)
+    for _ in range(3):
+        n2, rho, u = orc.lb_step(sys_, n, None)
+        assert np.max(np.abs(n2 - n)) < 1e-16
+        assert np.all(u == 0)
+        n = n2
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.0, 1.5])
+def test_shear_wave_decay_viscosity(orc, tau):
+    """P13: a shear wave u_x(y) decays at nu k^2 with nu = (tau - 1/2)/3."""
+    L = 64
+    sys_ = orc.System(L=(1, L, 1), types=[0], tau=tau)
+    y = np.arange(L)
+    k = 2 * np.pi / L
+    U = 1e-3
+    n = np.empty((19,) + sys_.shape)
+    for j in range(L):
+        n[:, 0, j, 0] = orc.lb_equilibrium(1.0, np.array([U * np.sin(k * y[j]), 0.0, 0.0]))
+    amps = []
+    steps = 400
+    for t in range(steps):
+        n, rho, u = orc.lb_step(sys_, n, None)
+        amps.append(2.0 / L * np.sum(u[0, 0, :, 0] * np.sin(k * y)))
+    t = np.arange(steps)
+    sel = t >= 50
+    slope = np.polyfit(t[sel], np.log(np.array(amps)[sel]), 1)[0]
+    nu = -slope / k ** 2
+    assert abs(nu / ((tau - 0.5) / 3) - 1) < 0.01
+
+
+def test_taylor_green_vortex_decay(orc):
+    """P13: 2-D Taylor-Green vortex in a 3-D box decays at 2 nu k^2."""
+    L = 32
+    tau = 0.8
+    sys_ = orc.System(L=(L, L, 1), types=[0], tau=tau)
+    k = 2 * np.pi / L
+    U = 1e-3
+    x = np.arange(L)[None, :]
+    y = np.arange(L)[:, None]
+    ux = U * np.sin(k * x) * np.cos(k * y)
+    uy = -U * np.cos(k * x) * np.sin(k * y)
+    n = np.empty((19, 1, L, L))
+    for j in range(L):
+        for i in range(L):
+            n[:, 0, j, i] = orc.lb_equilibrium(1.0, np.array([ux[j, i], uy[j, i], 0.0]))
+    E = []
+    for t in range(300):
+        n, rho, u = orc.lb_step(sys_, n, None)
+        E.append(np.sum(u[0, 0] * ux + u[1, 0] * uy) / np.sum(ux * ux + uy * uy))
+    t = np.arange(300)
+    sel = t >= 30
+    slope = np.polyfit(t[sel], np.log(np.array(E)[sel]), 1)[0]
+    nu = -slope / (2 * k ** 2)
+    assert abs(nu / ((tau - 0.5) / 3) - 1) < 0.01
+
+
+@pytest.mark.parametrize("tau", [0.55, 0.8, 1.7])
+def test_mrt_with_equal_rates_is_bgk_guo(orc, tau):
+    """P14: eq. 12-14 with every non-conserved gamma = 1 - 1/tau equals BGK + Guo."""
+    g = 1 - 1 / tau
+    s_b = orc.System(L=(4, 3, 5), types=[0], tau=tau, lb_mode=0)
+    s_m = orc.System(L=(4, 3, 5), types=[0], tau=tau, lb_mode=1, gamma_b=g, gamma_s=g, gamma_ghost=g)
+    n, f = _lb_random_state(orc, s_b, 9)
+    a = orc.lb_step(s_b, n, f)
+    b = orc.lb_step(s_m, n, f)
+    for x, y in zip(a, b):
+        assert np.max(np.abs(x - y)) < 1e-15
+
+
+def test_mrt_paper_rates_at_tau_one_is_bgk(orc):
+    """At tau = 1 the Table 1 scheme (ghost rates 0) with gamma_s = gamma_b = 0 is BGK."""
+    s_b = orc.System(L=(3, 4, 3), types=[0], tau=1.0, lb_mode=0)
+    s_m = orc.System(L=(3, 4, 3), types=[0], lb_mode=1, gamma_b=0.0, gamma_s=0.0, gamma_ghost=0.0)
+    n, f = _lb_random_state(orc, s_b, 2)
+    a = orc.lb_step(s_b, n, f)
+    b = orc.lb_step(s_m, n, f)
+    assert np.max(np.abs(a[0] - b[0])) < 5e-16
+
+
+def test_mrt_shear_viscosity_eq15(orc):
+    """Eq. 15: MRT shear viscosity nu = (1 + gamma_s) / (6 (1 - gamma_s))."""
+    L = 48
+    gs = 0.25
+    sys_ = orc.System(L=(1, L, 1), types=[0], lb_mode=1, gamma_s=gs, gamma_b=0.1, gamma_ghost=0.0)
+    k = 2 * np.pi / L
+    y = np.arange(L)
+    n = np.empty((19,) + sys_.shape)
+    for j in range(L):
+        n[:, 0, j, 0] = orc.lb_equilibrium(1.0, np.array([1e-3 * np.sin(k * y[j]), 0, 0]))
+    amps = []
+    for t in range(300):
+        n, rho, u = orc.lb_step(sys_, n, None)
+        amps.append(2.0 / L * np.sum(u[0, 0, :, 0] * np.sin(k * y)))
+    t = np.arange(300)
+    sel = t >= 30
+    nu = -np.polyfit(t[sel], np.log(np.array(amps)[sel]), 1)[0] / k ** 2
+    assert abs(nu / ((1 + gs) / (6 * (1 - gs))) - 1) < 0.01
+
+
+# ---------------------------------------------------------------- convection-diffusion and mu
+
+def test_cd_mass_conservation(orc):
+    """P15: the flux form conserves every species' total exactly (to rounding)."""
+    sys_ = orc.System(L=(6, 5, 7), types=W.chain(1, 1), has_solvent=True, dt=0.01)
+    rng = np.random.default_rng(5)
+    phi = rng.uniform(0.1, 0.5, size=(3,) + sys_.shape)
+    mu = rng.standard_normal((3,) + sys_.shape)
+    u = 0.05 * rng.standard_normal((3,) + sys_.shape)
+    out = orc.cd_update(sys_, phi, mu, u)
+    assert np.max(np.abs(out.sum(axis=(1, 2, 3)) / phi.sum(axis=(1, 2, 3)) - 1)) < 1e-14
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_lax_wendroff_unit_courant_shift(orc, axis):
+    """P16: uniform u = 1 along an axis shifts phi by exactly one site."""
+    sys_ = orc.System(L=(5, 6, 4), types=W.chain(1, 1), dt=0.01)
+    rng = np.random.default_rng(axis)
+    phi = rng.uniform(0, 1, size=(2,) + sys_.shape)
+    mu = np.zeros_like(phi)
+    u = np.zeros((3,) + sys_.shape)
+    u[axis] = 1.0
+    out = orc.cd_update(sys_, phi, mu, u)
+    arr_axis = 3 - axis
+    assert np.max(np.abs(out - np.roll(phi, 1, axis=arr_axis))) < 1e-15
+
+
+def test_cd_diffusion_linear_closed_form(orc):
+    """The diffusive flux at constant phi0 is dt phi0 times the 7-point Laplacian of mu."""
+    sys_ = orc.System(L=(6, 6, 6), types=W.chain(1, 1), dt=0.01)
+    rng = np.random.default_rng(3)
+    phi = np.full((2,) + sys_.shape, 0.5)
+    mu = rng.standard_normal((2,) + sys_.shape)
+    out = orc.cd_update(sys_, phi, mu, None)
+    lap = sum(np.roll(mu, s, axis=a) for a in (1, 2, 3) for s in (1, -1)) - 6 * mu
+    assert np.max(np.abs(out - (phi + 0.01 * 0.5 * lap))) < 1e-15
+
+
+def test_mu_force_fourier(orc):
+    """Eq. 4 and 8 on a single Fourier mode: sigma multiplies by its symbol and the
+    central gradient by i sin k."""
+    L = (8, 6, 5)
+    c = orc.stencil_weights(1.1543)
+    chi = W.chi_matrix(ab=1.3, as_=0.4, bs=2.1)
+    sys_ = orc.System(L=L, types=W.chain(1, 1), has_solvent=True, c=c, chi=chi, kappa=10.0, dt=0.02)
+    Lx, Ly, Lz = L
+    z, y, x = np.meshgrid(np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing="ij")
+    kx, ky, kz = 2 * np.pi * 1 / Lx, 2 * np.pi * 2 / Ly, 2 * np.pi * 1 / Lz
+    wave = np.cos(kx * x + ky * y + kz * z)
+    amp = np.array([0.01, -0.02, 0.005])
+    base = np.array([0.3, 0.5, 0.2])
+    phi = base[:, None, None, None] + amp[:, None, None, None] * wave
+    w = np.random.default_rng(0).standard_normal((3,) + sys_.shape)
+    mu, f = orc.mu_force(sys_, phi, w)
+    sh = stencil_symbol(c, kx, ky, kz)
+    tot = phi.sum(0)
+    for I in range(3):
+        exp_mu = -w[I] + sum(chi[I, J] * (base[J] + sh * amp[J] * wave) for J in range(3)) + 10.0 * (tot - 1)
+        assert np.max(np.abs(mu[I] - exp_mu)) < 1e-14
+    # force: central difference of mu, weighted by phi, times -dt^2
+    dwave = {0: -np.sin(kx) * np.sin(kx * x + ky * y + kz * z),
+             1: -np.sin(ky) * np.sin(kx * x + ky * y + kz * z),
+             2: -np.sin(kz) * np.sin(kx * x + ky * y + kz * z)}
+    for a in range(3):
+        # gradient of -w is not a single mode; compute it directly by rolls (central difference)
+        arr_axis = 3 - a
+        grad_w = [(np.roll(w[I], -1, axis=arr_axis - 1) - np.roll(w[I], 1, axis=arr_axis - 1)) / 2 for I in range(3)]
+        expf = 0.0
+        for I in range(3):
+            gmu = -grad_w[I] + sum(chi[I, J] * sh * amp[J] for J in range(3)) * dwave[a] + 10.0 * amp.sum() * dwave[a]
+            expf = expf + phi[I] * gmu
+        assert np.max(np.abs(f[a] - (-0.02 ** 2) * expf)) < 1e-15
+
+
+# ---------------------------------------------------------------- full step
+
+def _debye(types, c, k, phibar=1.0):
+    N = len(types)
+    sh = stencil_symbol(c, *k)
+    Sm = np.zeros((2, 2))
+    for s in range(N):
+        for sp in range(N):
+            Sm[types[s], types[sp]] += phibar / N * sh ** abs(s - sp)
+    return Sm, sh
+
+
+def test_linearised_diffusive_step(orc):
+    """P17: one diffusive step (invert, mu, CD) at small amplitude equals
+    I - dt diag(phi0 lambda(k)) (S(k)^-1 + sigma_hat chi + kappa 1 1^T) per mode."""
+    types = W.chain(2, 2)
+    c = orc.stencil_weights(1.1543)
+    L = (6, 1, 1)
+    chi = W.chi_matrix(ab=1.7)
+    dt = 0.01
+    sys_ = orc.System(L=L, types=types, c=c, chi=chi, kappa=10.0, dt=dt, hydro=False)
+    eps = 1e-6
+    x = np.arange(L[0])
+    mode = 1
+    kx = 2 * np.pi * mode / L[0]
+    wave = np.cos(kx * x)[None, None, :]
+    phi = np.empty((2, 1, 1, L[0]))
+    phi[0] = 0.5 + eps * wave
+    phi[1] = 0.5 - eps * wave
+    w0 = -np.log(phi / 0.5)
+    phin, wn, _, st, _, _, rc = orc.step(sys_, phi, w0, None, tol=1e-13, max_iter=5000)
+    assert rc == 0, st
+    Sm, sh = _debye(types, c, (kx, 0.0, 0.0))
+    lam = 2 - 2 * np.cos(kx)
+    Mop = np.eye(2) - dt * lam * np.diag([0.5, 0.5]) @ (np.linalg.inv(Sm) + sh * chi[:2, :2] + 10.0 * np.ones((2, 2)))
+    pred = Mop @ np.array([eps, -eps])
+    got = np.array([(phin[I, 0, 0] * np.cos(kx * x)).sum() * 2 / L[0] for I in range(2)])
+    assert np.max(np.abs(got - pred)) / eps < 1e-5
+
+
+def test_explicit_stability_limit_reading():
+    """The explicit diffusion step at the paper's parameters is stable only for
+    dt below about 0.015 (largest eigenvalue of the linearised step at k = (pi,pi,pi))."""
+    al = 1.1543 ** 2 / 6
+    cc = [(1 - 2 * al) ** 3, al * (1 - 2 * al) ** 2, al ** 2 * (1 - 2 * al), al ** 3]
+    worst = np.inf
+    for types, chiv in [(W.chain(4, 4), 2.5), (W.chain(8, 8), 1.25), (W.chain(4, 12), 25 / 16)]:
+        f = types.count(0) / len(types)
+        k = (np.pi, np.pi, np.pi)
+        Sm, sh = _debye(types, cc, k)
+        lam = 6 * 2.0
+        chi = np.array([[0, chiv], [chiv, 0]])
+        Mlin = lam * np.diag([f, 1 - f]) @ (np.linalg.inv(Sm) + sh * chi + 10.0 * np.ones((2, 2)))
+        ev = np.max(np.real(np.linalg.eigvals(Mlin)))
+        worst = min(worst, 2.0 / ev)
+    assert 0.01 < worst < 0.0155
