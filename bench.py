@@ -1,0 +1,167 @@
+"""Benchmark: coupled LB + dynamic-SCF steps of a 64^3 A8B8 melt on one GPU.
+
+A step is one pass of the whole method (field inversion to the residual,
+chemical potential and force, LB collide-and-stream, convection-diffusion
+update) over the 64^3 periodic melt of symmetric A8B8 diblocks, chi N = 20,
+tau 0.6, initial noise +-0.01 (seed 0), propagators in FP32 with FP64
+reductions (or all FP64 with --precision fp64).
+
+value = propagator site-bead updates per second over the timed steps: every
+density-functional evaluation performs 2 N V site-bead updates (N forward and
+N backward propagator steps over V sites), counted over all evaluations the
+inversions needed, divided by the wall time of the whole steps.
+
+Prints one JSON line.  Inputs are synthetic (seeded), resident in HBM before
+the timed region starts.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "propagator site·bead updates/s + LB MLUPS; step time learned vs plain at 1e-6"
+
+
+def algorithmic_bytes_per_update(wl, prec_bytes):
+    """Bytes per site-bead update of the store-all-G scheme: each stored G_s is
+    written once and read once (prec_bytes per update), plus the polymer fields
+    read once and the polymer densities written once per evaluation (FP64),
+    spread over the 2N updates of the evaluation."""
+    n_poly = 2
+    return prec_bytes + n_poly * (8 + 8) / (2.0 * wl.N)
+
+
+def cpu_baseline(wl, w, phi, seconds):
+    from oracle import oracle as orc
+    orc.build(force=False)
+    sysw = orc.System(L=wl.L, types=wl.types, has_solvent=wl.has_solvent, a=wl.a, chi=wl.chi,
+                      kappa=wl.kappa, dt=wl.dt, tau=wl.tau)
+    pbar = phi[:2].sum(0).mean()
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        orc.evaluate(sysw, w, pbar, 0.0)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    upd = n * 2 * wl.N * wl.V
+    return {"value": upd / el, "unit": "site·bead updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} density-functional evaluations of the {wl.L[0]}^3 A8B8 melt at the GPU run's "
+                      f"final fields ({el:.1f} s, single-threaded FP64 C oracle)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--tau", type=float, default=0.6)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the method is benchmarked "
+              "on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1204_2088_amd import hsf, workloads as W
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    wl = W.melt64_a8b8(tau=args.tau, precision=args.precision)
+    phi0 = W.initial_composition(wl)
+    ctx = hsf.Context(wl, stream=stream)
+    phi_d = torch.from_numpy(phi0.ravel()).to("cuda")
+    ctx.set_densities(phi_d)
+    torch.cuda.synchronize()
+
+    print(f"# workload {wl.name} L={wl.L} N={wl.N} precision={wl.precision} tau={wl.tau} tol={wl.tol}",
+          file=sys.stderr, flush=True)
+    ctx.step(args.warmup, tol=wl.tol, max_iter=2000)
+    torch.cuda.synchronize()
+    print(f"# warmup {args.warmup} steps done", file=sys.stderr, flush=True)
+
+    if not args.no_timing:
+        ctx.set_timing(True)
+        ctx.get_timing()  # clear
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats, evals = ctx.step(args.steps, tol=wl.tol, max_iter=2000)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    timing = ctx.get_timing() if not args.no_timing else {}
+    ctx.set_timing(False)
+    print(f"# timed {args.steps} steps in {elapsed:.3f} s, {evals} evaluations", file=sys.stderr, flush=True)
+
+    V, N = wl.V, wl.N
+    updates = evals * 2 * N * V
+    value = updates / elapsed
+    prec_bytes = 4 if wl.precision == "fp32" else 8
+    b_unit = algorithmic_bytes_per_update(wl, prec_bytes)
+
+    roofline = None
+    lb_mlups = None
+    kernels = {}
+    if timing:
+        for k, (ms, cnt) in timing.items():
+            if cnt:
+                kernels[k] = {"launches": cnt, "avg_us": 1e3 * ms / cnt, "total_ms": ms}
+        if "lb" in kernels:
+            lb_mlups = V / (kernels["lb"]["avg_us"] * 1e-6) / 1e6
+        prop = {k: v for k, v in kernels.items() if k in ("fwd", "bwd")}
+        if prop:
+            dom = max(prop, key=lambda k: prop[k]["total_ms"])
+            avg_s = prop[dom]["avg_us"] * 1e-6
+            achieved = b_unit * V / avg_s / 1e9
+            roofline = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "bytes_per_update": b_unit, "updates_per_launch": V}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        w_final = ctx.get_fields().reshape((wl.nsp,) + wl.shape)
+        phi_final = ctx.get_densities().reshape((wl.nsp,) + wl.shape)
+        cpu = cpu_baseline(wl, w_final, phi_final, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "site·bead updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if wl.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "melt64_a8b8", "L": list(wl.L), "N": N, "chiN": 20, "tau": wl.tau,
+                   "propagators": wl.precision, "reductions": "fp64", "tol": wl.tol, "dt": wl.dt,
+                   "hydro": True},
+        "evals_per_step": evals / args.steps,
+        "iterations_last_step": stats[0]["iterations"],
+        "lb_mlups": lb_mlups,
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

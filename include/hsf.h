@@ -1,0 +1,215 @@
+/*
+ * hsf.h -- C ABI of the MI355X (gfx950) library for the hybrid
+ * lattice-Boltzmann / dynamic self-consistent-field (SCF) method of Zhang,
+ * Sevink and Schmid (arXiv:1204.2088).
+ *
+ * The library computes, on one GPU:
+ *   - the SCF density functional phi[w] through chain propagators
+ *     (section 2, eq. 2, eq. 16-17; 27-point linkage stencil);
+ *   - the self-consistent fields w[phi] by Fletcher-Reeves nonlinear
+ *     conjugate gradients (section 2, text after eq. 17);
+ *   - the chemical potential and thermodynamic force (eq. 4, eq. 8);
+ *   - one D3Q19 lattice-Boltzmann collide-and-stream step (eq. 9-11, with
+ *     the single-relaxation-time collision and its forcing term);
+ *   - one conservative update of the convection-diffusion equation (eq. 3);
+ *   - the coupled step that alternates the two at equal time steps.
+ *
+ * Units: lattice spacing h = 1, kT = 1, the diffusive time unit of the
+ * paper; the LB step equals the diffusive step dt.
+ *
+ * Batching: one context holds n_rep independent replicas ("runs"), each with
+ * its own box and parameters but the same chain architecture and precision.
+ * Every phase of every call covers all replicas in one kernel launch.
+ *
+ * Array layouts (all FP64 at this boundary whatever the internal precision):
+ *   site index i = x + Lx (y + Ly z), x fastest, periodic boxes;
+ *   field arrays (w, phi, mu): replicas one after another, each
+ *       [n_species][Lz][Ly][Lx] with species order A, B, then S if present;
+ *       replica r starts at element hsf_field_offset(ctx, r);
+ *   LB populations: per replica [19][Lz][Ly][Lx], start at 19 * site offset;
+ *   vector fields (u, force): per replica [3][Lz][Ly][Lx];
+ *   scalar fields (rho): per replica [Lz][Ly][Lx], start at site offset.
+ * The D3Q19 velocity order is: rest; +x, -x, +y, -y, +z, -z;
+ *   (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1),
+ *   (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1).
+ *
+ * Pointers: every data argument is either a host pointer (where = HSF_HOST;
+ * the call copies synchronously) or a device pointer on the context's GPU
+ * (where = HSF_DEVICE; the copy is ordered on the context's stream).  The
+ * caller owns the buffers it passes; the library never keeps them past the
+ * call.  The library owns all of its internal device memory.
+ *
+ * Errors: every int-returning call returns HSF_OK (0) or a negative code;
+ * hsf_last_error() gives a message.  A context is not thread safe; distinct
+ * contexts are independent.
+ */
+#ifndef HSF_H
+#define HSF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HSF_MAX_BEADS 64
+
+enum {
+    HSF_OK = 0,
+    HSF_EINVAL = -1,      /* bad argument; nothing was changed                 */
+    HSF_ENOMEM = -2,      /* device allocation failed                           */
+    HSF_EHIP = -3,        /* HIP runtime error; message has the HIP string      */
+    HSF_ENOCONV = -4,     /* inversion hit max_iter; the iterate is kept        */
+    HSF_ENONFINITE = -5   /* a NaN/Inf appeared in a reduction                  */
+};
+
+enum { HSF_HOST = 0, HSF_DEVICE = 1 };
+
+/* Precision of the propagators (E = exp(-w), G_s, G+_s).  Reductions (Q,
+ * dot products, residual), the density normalisation, the fields and all
+ * other phases stay FP64 in both modes. */
+enum { HSF_FP64 = 0, HSF_FP32 = 1 };
+
+/* Starting guess of an inversion. */
+enum {
+    HSF_WARM_CURRENT = 0, /* the fields currently held (previous step's result) */
+    HSF_WARM_LOCAL = 1    /* local ideal-gas guess w_I = -ln(phi_I / <phi_I>)   */
+};
+
+typedef struct {
+    int Lx, Ly, Lz;              /* periodic box of this replica               */
+    int n_beads;                 /* N, beads per copolymer chain (<= 64)       */
+    int types[HSF_MAX_BEADS];    /* species of bead s = 1..N at [s-1]: 0 A, 1 B */
+    int has_solvent;             /* 1: monomeric solvent S (species 2)         */
+    double a;                    /* statistical segment length; when stencil[] */
+                                 /* is all zero the weights are the tensor      */
+                                 /* product of [al, 1-2al, al], al = a^2/6      */
+    double stencil[4];           /* linkage weights: centre, face, edge, corner */
+                                 /* (must sum to 1 over the 27 offsets)         */
+    double chi[3][3];            /* Flory-Huggins chi_IJ, symmetric, zero diag  */
+    double kappa;                /* Helfand parameter kappa_H v0 / kT           */
+    double dt;                   /* time step (diffusive units) = LB step       */
+    double tau;                  /* LB single relaxation time (> 1/2)           */
+    int hydro;                   /* 1: LB flow convects the densities           */
+    int precision;               /* HSF_FP64 or HSF_FP32 (same for all replicas) */
+} hsf_params;
+
+typedef struct {
+    int iterations;              /* conjugate-gradient iterations               */
+    int evaluations;             /* density-functional evaluations              */
+    int restarts;                /* steepest-descent restarts                   */
+    int converged;               /* residual <= tol                             */
+    double residual;             /* max_I |phi_I[w] - phi_I| / |phi_I|          */
+} hsf_invert_stats;
+
+typedef struct hsf_ctx hsf_ctx;
+
+/* Create a context for n_rep replicas described by reps[0..n_rep-1] on the
+ * current HIP device.  All replicas must share n_beads, types, has_solvent and
+ * precision.  Densities start at zero, fields at zero, LB populations at rest
+ * with density 1.  Returns HSF_EINVAL on inconsistent parameters, HSF_ENOMEM
+ * when device memory is short. */
+int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out);
+
+/* Free every device buffer of the context (waits for its stream). */
+void hsf_destroy(hsf_ctx *ctx);
+
+/* Message of the last failing call on this context (never NULL). */
+const char *hsf_last_error(const hsf_ctx *ctx);
+
+/* Order all further work of this context on the given hipStream_t (NULL: the
+ * null stream).  The library never synchronises other streams. */
+int hsf_set_stream(hsf_ctx *ctx, void *hip_stream);
+
+/* Sizes and offsets, in elements, of the concatenated layouts above. */
+long long hsf_total_sites(const hsf_ctx *ctx);
+long long hsf_site_offset(const hsf_ctx *ctx, int rep);
+long long hsf_field_offset(const hsf_ctx *ctx, int rep);
+int hsf_num_species(const hsf_ctx *ctx);
+
+/* Fields w_I = U_I / kT of all replicas (eq. 2). */
+int hsf_set_fields(hsf_ctx *ctx, const double *w, int where);
+int hsf_get_fields(hsf_ctx *ctx, double *w, int where);
+
+/* Composition state phi_I = rho_I v0 of all replicas: the current densities of
+ * the dynamics and the target of hsf_invert. */
+int hsf_set_densities(hsf_ctx *ctx, const double *phi, int where);
+int hsf_get_densities(hsf_ctx *ctx, double *phi, int where);
+
+/* Density functional (eq. 2 via eq. 16-17): phi_out = phi[w] at the current
+ * fields, with the copolymer amount phibar_p = <sum_polymer phi_I> and solvent
+ * amount phibar_s = <phi_S> of the current densities (eq. 2 normalisation
+ * n_p / Phi_p).  Q_out (n_rep values, may be NULL) receives the single-chain
+ * partition function Q = V^-1 sum_r G_N(r) with G_0 = 1.  Does not change the
+ * state.  phi_out uses the field layout. */
+int hsf_evaluate(hsf_ctx *ctx, double *phi_out, double *Q_out, int where);
+
+/* Self-consistent fields for the current densities (section 2: Fletcher-Reeves
+ * nonlinear conjugate gradients on the convex objective whose gradient is
+ * phi^t - phi[w]).  The solvent field is set in closed form; polymer fields are
+ * gauge-fixed to zero mean per species.  Stops when the residual
+ * max_I |phi_I[w] - phi^t_I| / |phi^t_I| <= tol or after max_iter iterations.
+ * stats (n_rep entries, may be NULL) receives per-replica counts.  Returns
+ * HSF_ENOCONV when a replica stopped at max_iter (its iterate is kept). */
+int hsf_invert(hsf_ctx *ctx, double tol, int max_iter, int warm, hsf_invert_stats *stats);
+
+/* Chemical potentials (eq. 4) and force density (eq. 8) from the current
+ * densities and fields.  mu: field layout; force: per replica [3][V] in LB
+ * units, f = -dt^2 sum_I phi_I grad mu_I (central differences).  Either may
+ * be NULL. */
+int hsf_mu_force(hsf_ctx *ctx, double *mu, double *force, int where);
+
+/* LB populations of all replicas, per replica [19][V]. */
+int hsf_set_lb(hsf_ctx *ctx, const double *n, int where);
+int hsf_get_lb(hsf_ctx *ctx, double *n, int where);
+
+/* n_steps LB steps (eq. 10: collide, then stream) with a constant force
+ * density (per replica [3][V], NULL for none).  rho/u of the last step's
+ * pre-collision moments (eq. 9) are kept and returned by hsf_get_flow. */
+int hsf_lb_advance(hsf_ctx *ctx, int n_steps, const double *force, int where);
+
+/* Moments of the last LB step: rho per replica [V], u per replica [3][V]
+ * (u includes the half-force shift of eq. 9).  Either may be NULL. */
+int hsf_get_flow(hsf_ctx *ctx, double *rho, double *u, int where);
+
+/* One conservative convection-diffusion update (eq. 3, explicit diffusive
+ * flux, two-step Lax-Wendroff convective flux) of the current densities with
+ * the given chemical potentials (field layout) and velocity (per replica
+ * [3][V], NULL for none). */
+int hsf_cd_advance(hsf_ctx *ctx, const double *mu, const double *u, int where);
+
+/* Coupled steps: for each step, invert (warm start: previous fields), then
+ * mu and force, then (hydro on) one LB step giving u, then the
+ * convection-diffusion update.  stats (n_rep entries, may be NULL) receives
+ * the last step's inversion counts; total_evals (may be NULL) the number of
+ * density-functional evaluations over all steps and replicas. */
+int hsf_step(hsf_ctx *ctx, int n_steps, double tol, int max_iter, hsf_invert_stats *stats,
+             long long *total_evals);
+
+/* Switch convection by the LB flow on or off for every replica (the LB state
+ * is kept while off). */
+int hsf_set_hydro(hsf_ctx *ctx, int on);
+
+/* Kernel families timed by hsf_set_timing. */
+enum {
+    HSF_K_PREP = 0,   /* field preparation + first forward step          */
+    HSF_K_FWD = 1,    /* forward propagator step                         */
+    HSF_K_BWD = 2,    /* backward propagator step + density accumulation */
+    HSF_K_LB = 3,     /* fused LB collide-and-stream                     */
+    HSF_K_CD = 4,     /* convection-diffusion update                     */
+    HSF_K_COUNT = 5
+};
+
+/* Measurement aid: when on, every launch of the kernel families above is
+ * bracketed by HIP events recorded on the context's stream.  hsf_get_timing
+ * waits for the stream and returns, per family, the summed event-to-event time
+ * in milliseconds (total_ms[HSF_K_COUNT]) and the number of launches
+ * (count[HSF_K_COUNT]) since the previous read, then clears them. */
+int hsf_set_timing(hsf_ctx *ctx, int on);
+int hsf_get_timing(hsf_ctx *ctx, double *total_ms, long long *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSF_H */

@@ -1,0 +1,644 @@
+// api.hip -- C ABI of the library (declared in include/hsf.h): context and
+// buffer management, and the host-side sequencing of the kernels.  Every
+// numerical step runs in the kernels of prop.hip, ctl.hip and dyn.hip; the host
+// only orders launches and reads the per-replica status between line-search
+// trials.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "hsf_internal.h"
+
+using namespace hsf;
+
+struct hsf_ctx {
+    int n_rep = 0;
+    int precision = HSF_FP64;
+    int hydro = 1;
+    Chain ch{};
+    long long T = 0;                 // total sites over all replicas
+    std::vector<Rep> reps;
+    Rep *rep_d = nullptr;
+    RepState *st_d = nullptr;
+    RepState *st_h = nullptr;        // pinned mirror for status reads
+    Plan plan;
+    hipStream_t stream = nullptr;
+    int fields_set = 0;              // fields hold a usable warm start
+    std::string err;
+
+    // FP64 state and work arrays
+    double *w = nullptr, *phi = nullptr, *phi_tmp = nullptr, *mu = nullptr, *eval_out = nullptr;
+    double *g = nullptr, *gt = nullptr, *d = nullptr, *acc = nullptr;
+    double *nA = nullptr, *nB = nullptr, *rho = nullptr, *u = nullptr, *force = nullptr, *uin = nullptr;
+    double *part = nullptr, *partG = nullptr;
+    // propagators in the chosen precision
+    void *E = nullptr, *G = nullptr, *Gp0 = nullptr, *Gp1 = nullptr;
+    std::vector<void *> allocs;
+
+    // optional per-launch timing of the hot kernels with HIP events on the context stream
+    int timing = 0;
+    struct Mark {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;       // recorded since the last read
+    std::vector<hipEvent_t> pool;  // free events
+};
+
+namespace {
+
+int fail(hsf_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(c, expr)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((c), HSF_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));           \
+    } while (0)
+
+int dalloc(hsf_ctx *c, void **p, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(c, HSF_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    c->allocs.push_back(*p);
+    return HSF_OK;
+}
+
+// Tensor-product reading of the 27-point linkage stencil from the segment length:
+// 1-D kernel [al, 1 - 2 al, al] with al = a^2 / 6 (normalised, per-axis variance a^2/3).
+void weights_from_segment(double a, double c[4])
+{
+    const double al = a * a / 6.0, m = 1.0 - 2.0 * al;
+    c[0] = m * m * m;
+    c[1] = al * m * m;
+    c[2] = al * al * m;
+    c[3] = al * al * al;
+}
+
+size_t real_size(const hsf_ctx *c) { return c->precision == HSF_FP32 ? sizeof(float) : sizeof(double); }
+
+int copy_in(hsf_ctx *c, double *dst, const double *src, size_t n, int where)
+{
+    if (!src) return fail(c, HSF_EINVAL, "null input pointer");
+    if (where == HSF_DEVICE) {
+        HIPCHK(c, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    } else if (where == HSF_HOST) {
+        HIPCHK(c, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        return fail(c, HSF_EINVAL, "bad memory location %d", where);
+    }
+    return HSF_OK;
+}
+
+int copy_out(hsf_ctx *c, double *dst, const double *src, size_t n, int where)
+{
+    if (!dst) return fail(c, HSF_EINVAL, "null output pointer");
+    if (where == HSF_DEVICE) {
+        HIPCHK(c, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    } else if (where == HSF_HOST) {
+        HIPCHK(c, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        return fail(c, HSF_EINVAL, "bad memory location %d", where);
+    }
+    return HSF_OK;
+}
+
+int read_status(hsf_ctx *c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->st_h, c->st_d, sizeof(RepState) * c->n_rep, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HSF_OK;
+}
+
+hipEvent_t take_event(hsf_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Bracket one launch of kernel family `kind` (HSF_K_*) with events when timing is on.
+struct Timed {
+    hsf_ctx *c;
+    int kind;
+    hipEvent_t a = nullptr;
+    Timed(hsf_ctx *c_, int k) : c(c_), kind(k)
+    {
+        if (c->timing) {
+            a = take_event(c);
+            if (a) (void)hipEventRecord(a, c->stream);
+        }
+    }
+    ~Timed()
+    {
+        if (!a) return;
+        hipEvent_t b = take_event(c);
+        if (!b) return;
+        (void)hipEventRecord(b, c->stream);
+        c->marks.push_back({kind, a, b});
+    }
+};
+
+template <typename real>
+PropBufs<real> bufs(hsf_ctx *c)
+{
+    PropBufs<real> b;
+    b.E = (real *)c->E;
+    b.G = (real *)c->G;
+    b.Gp[0] = (real *)c->Gp0;
+    b.Gp[1] = (real *)c->Gp1;
+    return b;
+}
+
+// One density-functional evaluation for the active replicas.
+//   final_mode 0: densities into out (field layout); 1: gradient phi^t - phi into out
+//   (polymer layout) with the partial dot products against d.
+template <typename real>
+void run_eval(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d)
+{
+    PropBufs<real> b = bufs<real>(c);
+    const int N = c->ch.N;
+    {
+        Timed t(c, HSF_K_PREP);
+        launch_prep<real>(c->stream, c->plan, c->rep_d, c->st_d, c->ch, c->w, c->d, use_alpha, b, c->acc,
+                          c->partG);
+    }
+    for (int s = 2; s <= N; ++s) {
+        Timed t(c, HSF_K_FWD);
+        launch_fwd<real>(c->stream, c->plan, c->rep_d, c->st_d, c->ch, s, b, c->partG);
+    }
+    launch_reduce_ctl(c->stream, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_Q, c->ch, c->partG, 0.0, 0);
+    for (int s = N; s >= 1; --s) {
+        Timed t(c, HSF_K_BWD);
+        launch_bwd<real>(c->stream, c->plan, c->rep_d, c->st_d, c->ch, s, b, c->acc, final_mode, c->phi, d, out,
+                         c->part);
+    }
+}
+
+void run_eval_any(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d)
+{
+    if (c->precision == HSF_FP32)
+        run_eval<float>(c, use_alpha, final_mode, out, d);
+    else
+        run_eval<double>(c, use_alpha, final_mode, out, d);
+}
+
+void target_setup(hsf_ctx *c, double tol, int max_iter)
+{
+    launch_target_stats(c->stream, c->plan, c->rep_d, c->st_d, c->ch, c->phi, c->w, c->part);
+    launch_reduce_ctl(c->stream, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_TARGET, c->ch, c->partG, tol,
+                      max_iter);
+}
+
+int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats *stats, long long *evals_out)
+{
+    if (!(tol >= 0.0) || max_iter < 0) return fail(c, HSF_EINVAL, "bad tol %g or max_iter %d", tol, max_iter);
+    if (warm != HSF_WARM_CURRENT && warm != HSF_WARM_LOCAL) return fail(c, HSF_EINVAL, "bad warm mode %d", warm);
+    hipStream_t s = c->stream;
+    if (warm == HSF_WARM_LOCAL || !c->fields_set)
+        launch_local_guess(s, c->plan, c->rep_d, c->ch, c->phi, c->w, c->part);
+    target_setup(c, tol, max_iter);
+    launch_init_fields(s, c->plan, c->rep_d, c->st_d, c->ch, c->phi, c->w);
+    c->fields_set = 1;
+    // starting point
+    run_eval_any(c, 0, 1, c->g, nullptr);
+    launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_EVAL0, c->ch, c->partG, 0.0, 0);
+    launch_cg_update(s, c->plan, c->rep_d, c->st_d, c->ch, 1, c->w, c->g, c->gt, c->d, c->phi, c->part);
+    launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_BEGIN, c->ch, c->partG, 0.0, 0);
+    HIPCHK(c, hipGetLastError());
+    int rc = read_status(c);
+    if (rc) return rc;
+    bool any = false;
+    for (int r = 0; r < c->n_rep; ++r) any |= c->st_h[r].active != 0;
+    // every pass either advances a line search (at most 3 trials per iteration) or
+    // ends an iteration, so 3 * max_iter + 3 passes bound the loop
+    long long guard = 3LL * max_iter + 3;
+    while (any) {
+        if (--guard < 0) return fail(c, HSF_EHIP, "inversion control did not progress");
+        run_eval_any(c, 1, 1, c->gt, c->d);
+        launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_TRIAL, c->ch, c->partG, 0.0, 0);
+        HIPCHK(c, hipGetLastError());
+        if ((rc = read_status(c))) return rc;
+        bool trialing = false, pending = false;
+        for (int r = 0; r < c->n_rep; ++r) {
+            trialing |= c->st_h[r].active != 0;
+            pending |= c->st_h[r].pending != 0;
+        }
+        if (trialing) continue;
+        launch_cg_update(s, c->plan, c->rep_d, c->st_d, c->ch, 0, c->w, c->g, c->gt, c->d, c->phi, c->part);
+        launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_BEGIN, c->ch, c->partG, 0.0, 0);
+        any = pending;
+    }
+    if ((rc = read_status(c))) return rc;
+    HIPCHK(c, hipGetLastError());
+    int status = HSF_OK;
+    long long ev = 0;
+    for (int r = 0; r < c->n_rep; ++r) {
+        const RepState &S = c->st_h[r];
+        ev += S.evals;
+        if (stats) {
+            stats[r].iterations = S.iters;
+            stats[r].evaluations = S.evals;
+            stats[r].restarts = S.restarts;
+            stats[r].converged = S.converged;
+            stats[r].residual = S.res;
+        }
+        if (S.nonfinite) status = fail(c, HSF_ENONFINITE, "non-finite value in replica %d", r);
+        else if (!S.converged && status == HSF_OK)
+            status = fail(c, HSF_ENOCONV, "replica %d stopped at %d iterations, residual %g", r, S.iters, S.res);
+    }
+    if (evals_out) *evals_out += ev;
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
+{
+    if (!out) return HSF_EINVAL;
+    *out = nullptr;
+    if (!reps || n_rep <= 0) return HSF_EINVAL;
+    const hsf_params &p0 = reps[0];
+    if (p0.n_beads < 1 || p0.n_beads > HSF_MAX_BEADS) return HSF_EINVAL;
+    if (p0.precision != HSF_FP64 && p0.precision != HSF_FP32) return HSF_EINVAL;
+    for (int r = 0; r < n_rep; ++r) {
+        const hsf_params &p = reps[r];
+        if (p.n_beads != p0.n_beads || p.has_solvent != p0.has_solvent || p.precision != p0.precision ||
+            p.hydro != p0.hydro)
+            return HSF_EINVAL;
+        for (int s = 0; s < p.n_beads; ++s)
+            if (p.types[s] != p0.types[s] || p.types[s] < 0 || p.types[s] > 1) return HSF_EINVAL;
+        if (p.Lx < 1 || p.Ly < 1 || p.Lz < 1) return HSF_EINVAL;
+        if (!(p.tau > 0.5) || !(p.dt > 0.0)) return HSF_EINVAL;
+    }
+    hsf_ctx *c = new hsf_ctx();
+    c->n_rep = n_rep;
+    c->precision = p0.precision;
+    c->hydro = p0.hydro ? 1 : 0;
+    c->ch.N = p0.n_beads;
+    c->ch.nsp = p0.has_solvent ? 3 : 2;
+    for (int s = 0; s < 64; ++s) c->ch.types[s] = s < p0.n_beads ? p0.types[s] : 0;
+
+    std::vector<int> blk_rep, blk_first;
+    long long off = 0;
+    for (int r = 0; r < n_rep; ++r) {
+        const hsf_params &p = reps[r];
+        Rep R{};
+        R.Lx = p.Lx;
+        R.Ly = p.Ly;
+        R.Lz = p.Lz;
+        R.hydro = p.hydro;
+        R.V = (long long)p.Lx * p.Ly * p.Lz;
+        R.site_off = off;
+        const bool given = p.stencil[0] != 0.0 || p.stencil[1] != 0.0 || p.stencil[2] != 0.0 || p.stencil[3] != 0.0;
+        if (given)
+            for (int k = 0; k < 4; ++k) R.c[k] = p.stencil[k];
+        else
+            weights_from_segment(p.a, R.c);
+        R.csum = R.c[0] + 6.0 * R.c[1] + 12.0 * R.c[2] + 8.0 * R.c[3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) R.chi[i][j] = p.chi[i][j];
+        R.kappa = p.kappa;
+        R.dt = p.dt;
+        R.tau = p.tau;
+        c->reps.push_back(R);
+        blk_first.push_back((int)blk_rep.size());
+        const long long nb = (R.V + kBlock - 1) / kBlock;
+        for (long long b = 0; b < nb; ++b) blk_rep.push_back(r);
+        off += R.V;
+    }
+    blk_first.push_back((int)blk_rep.size());
+    c->T = off;
+    c->plan.nblocks = (int)blk_rep.size();
+
+    const long long T = c->T;
+    const int nsp = c->ch.nsp, N = c->ch.N;
+    const size_t rs = real_size(c);
+    int rc = HSF_OK;
+#define ALLOC(ptr, bytes)                                          \
+    if (rc == HSF_OK) rc = dalloc(c, (void **)&(ptr), (size_t)(bytes));
+    ALLOC(c->rep_d, sizeof(Rep) * n_rep);
+    ALLOC(c->st_d, sizeof(RepState) * n_rep);
+    ALLOC(c->plan.blk_rep, sizeof(int) * blk_rep.size());
+    ALLOC(c->plan.blk_first, sizeof(int) * blk_first.size());
+    ALLOC(c->w, sizeof(double) * nsp * T);
+    ALLOC(c->phi, sizeof(double) * nsp * T);
+    ALLOC(c->phi_tmp, sizeof(double) * nsp * T);
+    ALLOC(c->mu, sizeof(double) * nsp * T);
+    ALLOC(c->eval_out, sizeof(double) * nsp * T);
+    ALLOC(c->g, sizeof(double) * 2 * T);
+    ALLOC(c->gt, sizeof(double) * 2 * T);
+    ALLOC(c->d, sizeof(double) * 2 * T);
+    ALLOC(c->acc, sizeof(double) * 2 * T);
+    ALLOC(c->nA, sizeof(double) * 19 * T);
+    ALLOC(c->nB, sizeof(double) * 19 * T);
+    ALLOC(c->rho, sizeof(double) * T);
+    ALLOC(c->u, sizeof(double) * 3 * T);
+    ALLOC(c->uin, sizeof(double) * 3 * T);
+    ALLOC(c->force, sizeof(double) * 3 * T);
+    ALLOC(c->part, sizeof(double) * kNQ * c->plan.nblocks);
+    ALLOC(c->partG, sizeof(double) * (N + 2) * c->plan.nblocks);
+    ALLOC(c->E, rs * 2 * T);
+    ALLOC(c->G, rs * N * T);
+    ALLOC(c->Gp0, rs * T);
+    ALLOC(c->Gp1, rs * T);
+#undef ALLOC
+    if (rc == HSF_OK) {
+        hipError_t e = hipHostMalloc((void **)&c->st_h, sizeof(RepState) * n_rep, hipHostMallocDefault);
+        if (e != hipSuccess) rc = fail(c, HSF_ENOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
+    }
+    if (rc != HSF_OK) {
+        hsf_destroy(c);
+        return rc;
+    }
+    hipError_t e = hipSuccess;
+    std::vector<RepState> st0(n_rep);
+    memset(st0.data(), 0, sizeof(RepState) * n_rep);
+    if (e == hipSuccess) e = hipMemcpy(c->rep_d, c->reps.data(), sizeof(Rep) * n_rep, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->st_d, st0.data(), sizeof(RepState) * n_rep, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->plan.blk_rep, blk_rep.data(), sizeof(int) * blk_rep.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->plan.blk_first, blk_first.data(), sizeof(int) * blk_first.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(c->w, 0, sizeof(double) * nsp * T);
+    if (e == hipSuccess) e = hipMemset(c->phi, 0, sizeof(double) * nsp * T);
+    if (e == hipSuccess) e = hipMemset(c->d, 0, sizeof(double) * 2 * T);
+    if (e == hipSuccess) e = hipMemset(c->u, 0, sizeof(double) * 3 * T);
+    if (e == hipSuccess) e = hipMemset(c->rho, 0, sizeof(double) * T);
+    if (e == hipSuccess) {
+        launch_lb_rest(nullptr, c->plan, c->rep_d, c->nA);
+        e = hipDeviceSynchronize();
+    }
+    if (e != hipSuccess) {
+        rc = fail(c, HSF_EHIP, "initialisation failed: %s", hipGetErrorString(e));
+        hsf_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return HSF_OK;
+}
+
+void hsf_destroy(hsf_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    for (auto &m : c->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    for (void *p : c->allocs) (void)hipFree(p);
+    if (c->st_h) (void)hipHostFree(c->st_h);
+    delete c;
+}
+
+const char *hsf_last_error(const hsf_ctx *c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+int hsf_set_stream(hsf_ctx *c, void *stream)
+{
+    if (!c) return HSF_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return HSF_OK;
+}
+
+long long hsf_total_sites(const hsf_ctx *c) { return c ? c->T : -1; }
+
+long long hsf_site_offset(const hsf_ctx *c, int rep)
+{
+    if (!c || rep < 0 || rep > c->n_rep) return -1;
+    return rep == c->n_rep ? c->T : c->reps[rep].site_off;
+}
+
+long long hsf_field_offset(const hsf_ctx *c, int rep)
+{
+    const long long s = hsf_site_offset(c, rep);
+    return s < 0 ? -1 : s * c->ch.nsp;
+}
+
+int hsf_num_species(const hsf_ctx *c) { return c ? c->ch.nsp : -1; }
+
+int hsf_set_fields(hsf_ctx *c, const double *w, int where)
+{
+    if (!c) return HSF_EINVAL;
+    int rc = copy_in(c, c->w, w, (size_t)c->ch.nsp * c->T, where);
+    if (rc == HSF_OK) c->fields_set = 1;
+    return rc;
+}
+
+int hsf_get_fields(hsf_ctx *c, double *w, int where)
+{
+    if (!c) return HSF_EINVAL;
+    return copy_out(c, w, c->w, (size_t)c->ch.nsp * c->T, where);
+}
+
+int hsf_set_densities(hsf_ctx *c, const double *phi, int where)
+{
+    if (!c) return HSF_EINVAL;
+    return copy_in(c, c->phi, phi, (size_t)c->ch.nsp * c->T, where);
+}
+
+int hsf_get_densities(hsf_ctx *c, double *phi, int where)
+{
+    if (!c) return HSF_EINVAL;
+    return copy_out(c, phi, c->phi, (size_t)c->ch.nsp * c->T, where);
+}
+
+int hsf_evaluate(hsf_ctx *c, double *phi_out, double *Q_out, int where)
+{
+    if (!c) return HSF_EINVAL;
+    if (!phi_out) return fail(c, HSF_EINVAL, "null output");
+    hipStream_t s = c->stream;
+    // An evaluation whose propagators left the floating-point range is repeated
+    // with the per-step scales it adapted (at most three more times).
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        target_setup(c, 0.0, 0);   // phibar_p, phibar_s from the current densities; all replicas active
+        run_eval_any(c, 0, 0, c->eval_out, nullptr);
+        launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_SCALES, c->ch, c->partG, 0.0, 0);
+        int rc0 = read_status(c);
+        if (rc0) return rc0;
+        bool bad = false;
+        for (int r = 0; r < c->n_rep; ++r) bad |= c->st_h[r].nonfinite != 0;
+        if (!bad) break;
+    }
+    if (c->ch.nsp == 3) {
+        launch_solvent(s, c->plan, c->rep_d, c->st_d, c->ch, 0, c->w, c->phi, c->eval_out, c->part);
+        launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_SOLVENT, c->ch, c->partG, 0.0, 0);
+        launch_solvent(s, c->plan, c->rep_d, c->st_d, c->ch, 1, c->w, c->phi, c->eval_out, c->part);
+    }
+    HIPCHK(c, hipGetLastError());
+    int rc = copy_out(c, phi_out, c->eval_out, (size_t)c->ch.nsp * c->T, where);
+    if (rc) return rc;
+    if ((rc = read_status(c))) return rc;
+    for (int r = 0; r < c->n_rep; ++r) {
+        if (Q_out) Q_out[r] = exp(c->st_h[r].ln_q);
+        if (c->st_h[r].nonfinite) return fail(c, HSF_ENONFINITE, "non-finite Q in replica %d", r);
+    }
+    return HSF_OK;
+}
+
+int hsf_invert(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats *stats)
+{
+    if (!c) return HSF_EINVAL;
+    return invert_impl(c, tol, max_iter, warm, stats, nullptr);
+}
+
+int hsf_mu_force(hsf_ctx *c, double *mu, double *force, int where)
+{
+    if (!c) return HSF_EINVAL;
+    launch_mu(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->w, c->mu);
+    launch_force(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, c->force);
+    HIPCHK(c, hipGetLastError());
+    int rc = HSF_OK;
+    if (mu) rc = copy_out(c, mu, c->mu, (size_t)c->ch.nsp * c->T, where);
+    if (rc == HSF_OK && force) rc = copy_out(c, force, c->force, (size_t)3 * c->T, where);
+    return rc;
+}
+
+int hsf_set_lb(hsf_ctx *c, const double *n, int where)
+{
+    if (!c) return HSF_EINVAL;
+    return copy_in(c, c->nA, n, (size_t)19 * c->T, where);
+}
+
+int hsf_get_lb(hsf_ctx *c, double *n, int where)
+{
+    if (!c) return HSF_EINVAL;
+    return copy_out(c, n, c->nA, (size_t)19 * c->T, where);
+}
+
+int hsf_lb_advance(hsf_ctx *c, int n_steps, const double *force, int where)
+{
+    if (!c || n_steps < 0) return HSF_EINVAL;
+    const double *f = nullptr;
+    if (force) {
+        int rc = copy_in(c, c->uin, force, (size_t)3 * c->T, where);
+        if (rc) return rc;
+        f = c->uin;
+    }
+    for (int k = 0; k < n_steps; ++k) {
+        {
+            Timed t(c, HSF_K_LB);
+            launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, f, c->rho, c->u);
+        }
+        std::swap(c->nA, c->nB);
+    }
+    HIPCHK(c, hipGetLastError());
+    return HSF_OK;
+}
+
+int hsf_get_flow(hsf_ctx *c, double *rho, double *u, int where)
+{
+    if (!c) return HSF_EINVAL;
+    int rc = HSF_OK;
+    if (rho) rc = copy_out(c, rho, c->rho, (size_t)c->T, where);
+    if (rc == HSF_OK && u) rc = copy_out(c, u, c->u, (size_t)3 * c->T, where);
+    return rc;
+}
+
+int hsf_cd_advance(hsf_ctx *c, const double *mu, const double *u, int where)
+{
+    if (!c || !mu) return HSF_EINVAL;
+    int rc = copy_in(c, c->mu, mu, (size_t)c->ch.nsp * c->T, where);
+    if (rc) return rc;
+    const double *uu = nullptr;
+    if (u) {
+        if ((rc = copy_in(c, c->uin, u, (size_t)3 * c->T, where))) return rc;
+        uu = c->uin;
+    }
+    launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, uu, c->phi_tmp);
+    std::swap(c->phi, c->phi_tmp);
+    HIPCHK(c, hipGetLastError());
+    return HSF_OK;
+}
+
+int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats *stats, long long *total_evals)
+{
+    if (!c || n_steps < 0) return HSF_EINVAL;
+    if (total_evals) *total_evals = 0;
+    for (int k = 0; k < n_steps; ++k) {
+        int rc = invert_impl(c, tol, max_iter, HSF_WARM_CURRENT, stats, total_evals);
+        if (rc != HSF_OK) return rc;
+        launch_mu(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->w, c->mu);
+        const double *uu = nullptr;
+        if (c->hydro) {
+            launch_force(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, c->force);
+            {
+                Timed t(c, HSF_K_LB);
+                launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, c->force, c->rho, c->u);
+            }
+            std::swap(c->nA, c->nB);
+            uu = c->u;
+        }
+        {
+            Timed t(c, HSF_K_CD);
+            launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, uu, c->phi_tmp);
+        }
+        std::swap(c->phi, c->phi_tmp);
+        HIPCHK(c, hipGetLastError());
+    }
+    return HSF_OK;
+}
+
+int hsf_set_timing(hsf_ctx *c, int on)
+{
+    if (!c) return HSF_EINVAL;
+    c->timing = on ? 1 : 0;
+    return HSF_OK;
+}
+
+int hsf_get_timing(hsf_ctx *c, double *total_ms, long long *count)
+{
+    if (!c || !total_ms || !count) return HSF_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < HSF_K_COUNT; ++k) {
+        total_ms[k] = 0.0;
+        count[k] = 0;
+    }
+    for (auto &m : c->marks) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, m.a, m.b));
+        total_ms[m.kind] += ms;
+        count[m.kind] += 1;
+        c->pool.push_back(m.a);
+        c->pool.push_back(m.b);
+    }
+    c->marks.clear();
+    return HSF_OK;
+}
+
+int hsf_set_hydro(hsf_ctx *c, int on)
+{
+    if (!c) return HSF_EINVAL;
+    c->hydro = on ? 1 : 0;
+    return HSF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,411 @@
+// ctl.hip -- deterministic reductions and the per-replica control of the
+// Fletcher-Reeves inversion (section 2: the fields are determined
+// self-consistently at every step by nonlinear conjugate gradients).
+//
+// The inversion minimises the convex objective
+//   Phi(w) = (phibar_p V / N) ln Q[w] + phibar_s V ln<exp(-w_S)> + sum_I sum_r phi^t_I w_I,
+// whose gradient is phi^t - phi[w].  Line search: secant on h(alpha) = d.grad Phi(w + alpha d)
+// from alpha_0 = -(d.g) / sum d^2 phi^t; a trial is accepted when |h| <= 0.1 |h(0)|, after
+// three trials, or when the secant slope or the next alpha is not positive (extrapolation
+// capped at 8x).  beta = |g_new|^2 / |g_old|^2; restart every 50 iterations and whenever
+// the new direction would not descend (d_new.g_new = -|g_new|^2 + beta d.g_new >= 0).
+//
+// All vector work is done by site kernels that write per-block partial sums; one block
+// per replica then sums its blocks' partials in a fixed order and thread 0 runs the
+// replica's scalar logic, so every replica of a batch follows its own iteration.
+#include <math.h>
+
+#include "device_common.h"
+
+namespace hsf {
+
+// Fixed-order sum of `count` values strided by `stride` starting at base[first*stride].
+__device__ double reduce_range(const double *base, int first, int last, long long stride, int slot)
+{
+    double v = 0.0;
+    for (int b = first + (int)threadIdx.x; b < last; b += kBlock) v += base[(long long)b * stride + slot];
+    return block_sum(v);
+}
+
+// Per-step power-of-two scales for the next evaluation.  sums[s] = sum_r of the
+// stored G_{s+1} of this evaluation (its mean m_s is relative to the cumulative
+// scale used), sums[N], sums[N+1] = sum_r E_A, E_B.  Target: stored means near 1.
+// Where a mean is not usable (overflow or underflow) the growth is predicted from
+// the mean-field factor <E_{t_s}> csum instead.
+__device__ void update_scales(RepState &S, const Chain &ch, const double *sums, double V, double csum)
+{
+    int cum_old = 0, cum_new = 0;
+    for (int s = 0; s < ch.N; ++s) {
+        cum_old += S.scale_e[s];
+        const double m = sums[s] / V;
+        long target;
+        if (m > 0.0 && isfinite(m)) {
+            target = cum_old + lrint(log2(m));
+        } else {
+            const double me = sums[ch.N + ch.types[s]] / V * csum;
+            target = cum_new + ((me > 0.0 && isfinite(me)) ? lrint(log2(me)) : 0);
+        }
+        long e = target - cum_new;
+        if (e > 100) e = 100;
+        if (e < -100) e = -100;
+        S.scale_e[s] = (int)e;
+        cum_new += (int)e;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_ctl(const int *__restrict__ blk_first,
+                                                       RepState *__restrict__ st, const Rep *__restrict__ rep,
+                                                       const double *__restrict__ part, int phase, Chain ch,
+                                                       const double *__restrict__ partG, int nblocks,
+                                                       double tol, int max_iter)
+{
+    const int r = blockIdx.x;
+    RepState &S = st[r];
+    const int b0 = blk_first[r], b1 = blk_first[r + 1];
+    const double V = (double)rep[r].V;
+    __shared__ double red[kNQ];
+    __shared__ double gsum[66];
+
+    // which replicas take part in this phase (uniform per block)
+    bool take;
+    switch (phase) {
+    case PH_TARGET: take = true; break;
+    case PH_Q: case PH_EVAL0: case PH_TRIAL: case PH_SCALES: take = S.active != 0; break;
+    case PH_BEGIN: take = true; break;
+    default: take = true; break;
+    }
+    if (!take) return;
+
+    int nslots = 0;
+    switch (phase) {
+    case PH_TARGET: nslots = 6; break;
+    case PH_EVAL0: case PH_TRIAL: nslots = 4; break;
+    case PH_BEGIN: nslots = 2; break;
+    case PH_SOLVENT: nslots = 1; break;
+    default: nslots = 0; break;
+    }
+    if (phase == PH_BEGIN && !S.pending) {
+        if (threadIdx.x == 0) S.accepted = 0;
+        return;
+    }
+    for (int q = 0; q < nslots; ++q) {
+        const double t = reduce_range(part, b0, b1, kNQ, q);
+        if (threadIdx.x == 0) red[q] = t;
+    }
+    const bool want_g = phase == PH_Q || phase == PH_EVAL0 || phase == PH_TRIAL || phase == PH_SCALES;
+    if (want_g) {
+        for (int s = 0; s < ch.N + 2; ++s) {
+            const double t = reduce_range(partG + (long long)s * nblocks, b0, b1, 1, 0);
+            if (threadIdx.x == 0) gsum[s] = t;
+        }
+    }
+    if (threadIdx.x != 0) return;
+
+    switch (phase) {
+    case PH_Q: {
+        S.q = gsum[ch.N - 1] / V;
+        int cum = 0;
+        for (int s = 0; s < ch.N; ++s) cum += S.scale_e[s];
+        S.ln_q = log(S.q) + cum * 0.69314718055994530942;
+        if (!isfinite(S.q) || S.q <= 0.0) S.nonfinite = 1;
+        break;
+    }
+    case PH_TARGET: {
+        S.phibar_p = red[0] / V;
+        S.phibar_s = red[1] / V;
+        S.tnorm2[0] = red[2];
+        S.tnorm2[1] = red[3];
+        S.wmean[0] = red[4] / V;
+        S.wmean[1] = red[5] / V;
+        S.tol = tol;
+        S.max_iter = max_iter;
+        S.active = 1;
+        S.done = 0;
+        S.pending = 0;
+        S.accepted = 0;
+        S.iters = 0;
+        S.evals = 0;
+        S.restarts = 0;
+        S.converged = 0;
+        S.nonfinite = 0;
+        S.trial = 0;
+        S.alpha = 0.0;
+        S.res = INFINITY;
+        break;
+    }
+    case PH_SCALES: update_scales(S, ch, gsum, V, rep[r].csum); break;
+    case PH_SOLVENT: S.sol_mean = red[0] / V; break;
+    case PH_EVAL0: {
+        update_scales(S, ch, gsum, V, rep[r].csum);
+        S.evals += 1;
+        S.gg = red[1];
+        S.res = fmax(sqrt(red[2] / S.tnorm2[0]), sqrt(red[3] / S.tnorm2[1]));
+        S.active = 0;
+        if (!isfinite(S.res) || S.nonfinite) {
+            S.nonfinite = 1;
+            S.done = 1;
+        } else if (S.res <= S.tol) {
+            S.done = 1;
+            S.converged = 1;
+        } else if (S.max_iter <= 0) {
+            S.done = 1;
+        } else {
+            S.pending = 1;
+        }
+        break;
+    }
+    case PH_BEGIN: {
+        S.h0 = red[0];
+        S.dhd = red[1];
+        S.alpha = -S.h0 / S.dhd;
+        S.a_prev = 0.0;
+        S.h_prev = S.h0;
+        S.trial = 1;
+        S.active = 1;
+        S.accepted = 0;
+        S.pending = 0;
+        if (!isfinite(S.alpha)) {
+            S.nonfinite = 1;
+            S.done = 1;
+            S.active = 0;
+        }
+        break;
+    }
+    case PH_TRIAL: {
+        update_scales(S, ch, gsum, V, rep[r].csum);
+        S.evals += 1;
+        const double h = red[0];
+        bool accept = fabs(h) <= 0.1 * fabs(S.h0) || S.trial >= 3;
+        if (!accept) {
+            const double slope = (h - S.h_prev) / (S.alpha - S.a_prev);
+            if (!(slope > 0.0)) {
+                accept = true;
+            } else {
+                double an = S.alpha - h / slope;
+                if (!(an > 0.0)) {
+                    accept = true;
+                } else {
+                    if (an > 8.0 * S.alpha) an = 8.0 * S.alpha;
+                    S.a_prev = S.alpha;
+                    S.h_prev = h;
+                    S.alpha = an;
+                    S.trial += 1;
+                }
+            }
+        }
+        if (accept) {
+            S.active = 0;
+            S.accepted = 1;
+            S.iters += 1;
+            S.res = fmax(sqrt(red[2] / S.tnorm2[0]), sqrt(red[3] / S.tnorm2[1]));
+            if (!isfinite(S.res) || S.nonfinite) {
+                S.nonfinite = 1;
+                S.done = 1;
+                S.beta = 0.0;
+            } else if (S.res <= S.tol) {
+                S.converged = 1;
+                S.done = 1;
+                S.beta = 0.0;
+            } else {
+                const double ggn = red[1];
+                double beta = ggn / S.gg;
+                S.gg = ggn;
+                if (S.iters % 50 == 0) {
+                    beta = 0.0;
+                    S.restarts += 1;
+                } else if (-ggn + beta * h >= 0.0) {
+                    beta = 0.0;
+                    S.restarts += 1;
+                }
+                S.beta = beta;
+                if (S.iters >= S.max_iter) {
+                    S.done = 1;
+                } else {
+                    S.pending = 1;
+                }
+            }
+        }
+        break;
+    }
+    default: break;
+    }
+}
+
+void launch_reduce_ctl(hipStream_t s, int n_rep, const Plan &p, RepState *st, const Rep *rep,
+                       const double *part, int phase, Chain ch, const double *partG, double tol,
+                       int max_iter)
+{
+    hipLaunchKernelGGL(k_reduce_ctl, dim3(n_rep), dim3(kBlock), 0, s, p.blk_first, st, rep, part, phase, ch,
+                       partG, p.nblocks, tol, max_iter);
+}
+
+// Partial sums of the inversion target: sum of polymer phi^t, sum of phi^t_S,
+// |phi^t_A|^2, |phi^t_B|^2, sum of w_A and of w_B.
+__global__ __launch_bounds__(kBlock) void k_target_stats(const int *__restrict__ blk_rep,
+                                                         const int *__restrict__ blk_first,
+                                                         const Rep *__restrict__ rep, Chain ch,
+                                                         const double *__restrict__ phit,
+                                                         const double *__restrict__ w, double *__restrict__ part)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (i < V) {
+        const long long fo = off_field(R, ch.nsp);
+        const double a = phit[fo + i], bb = phit[fo + V + i];
+        v[0] = a + bb;
+        v[1] = ch.nsp == 3 ? phit[fo + 2 * V + i] : 0.0;
+        v[2] = a * a;
+        v[3] = bb * bb;
+        v[4] = w[fo + i];
+        v[5] = w[fo + V + i];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const double t = block_sum(v[q]);
+        if (threadIdx.x == 0) part[(long long)blockIdx.x * kNQ + q] = t;
+    }
+}
+
+void launch_target_stats(hipStream_t s, const Plan &p, const Rep *rep, RepState *, Chain ch,
+                         const double *phit, const double *w, double *part)
+{
+    hipLaunchKernelGGL(k_target_stats, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch,
+                       phit, w, part);
+}
+
+// Local ideal-gas starting guess w_I = -ln phi_I (the constant -ln <phi_I> is removed
+// by the gauge shift that follows).
+__global__ __launch_bounds__(kBlock) void k_local_guess(const int *__restrict__ blk_rep,
+                                                        const int *__restrict__ blk_first,
+                                                        const Rep *__restrict__ rep, Chain ch,
+                                                        const double *__restrict__ phit, double *__restrict__ w)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    if (i >= V) return;
+    const long long fo = off_field(R, ch.nsp);
+    for (int I = 0; I < 2; ++I) w[fo + I * V + i] = -log(phit[fo + I * V + i]);
+}
+
+void launch_local_guess(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phit,
+                        double *w, double *)
+{
+    hipLaunchKernelGGL(k_local_guess, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch,
+                       phit, w);
+}
+
+// Gauge shift of the polymer fields to zero mean; closed-form solvent field
+// w_S = -ln(phi^t_S / phibar_s).
+__global__ __launch_bounds__(kBlock) void k_init_fields(const int *__restrict__ blk_rep,
+                                                        const int *__restrict__ blk_first,
+                                                        const Rep *__restrict__ rep, const RepState *__restrict__ st,
+                                                        Chain ch, const double *__restrict__ phit,
+                                                        double *__restrict__ w)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    if (i >= V) return;
+    const RepState &S = st[sr.r];
+    const long long fo = off_field(R, ch.nsp);
+    w[fo + i] -= S.wmean[0];
+    w[fo + V + i] -= S.wmean[1];
+    if (ch.nsp == 3) w[fo + 2 * V + i] = -log(phit[fo + 2 * V + i] / S.phibar_s);
+}
+
+void launch_init_fields(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
+                        const double *phit, double *w)
+{
+    hipLaunchKernelGGL(k_init_fields, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st, ch,
+                       phit, w);
+}
+
+// Conjugate-gradient vector update.
+//   init = 1 (replicas pending their first iteration): d = -g
+//   init = 0 (replicas whose trial was accepted): w += alpha d, g = g_trial and,
+//            unless the replica is done, d = -g + beta d
+// Partial sums d.g and sum d^2 phi^t for the next alpha_0.
+__global__ __launch_bounds__(kBlock) void k_cg_update(const int *__restrict__ blk_rep,
+                                                      const int *__restrict__ blk_first,
+                                                      const Rep *__restrict__ rep, const RepState *__restrict__ st,
+                                                      Chain ch, int init, double *__restrict__ w,
+                                                      double *__restrict__ g, const double *__restrict__ gt,
+                                                      double *__restrict__ d, const double *__restrict__ phit,
+                                                      double *__restrict__ part)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    const RepState &S = st[sr.r];
+    if (init ? !S.pending : !S.accepted) return;
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    double dg = 0.0, dhd = 0.0;
+    if (i < V) {
+        const long long fo = off_field(R, ch.nsp), po = off_poly(R);
+        const double alpha = S.alpha, beta = S.beta;
+        const bool upd_d = init || !S.done;
+#pragma unroll
+        for (int I = 0; I < 2; ++I) {
+            const long long k = po + I * V + i;
+            double gI;
+            double dI = d[k];
+            if (init) {
+                gI = g[k];
+            } else {
+                w[fo + I * V + i] = fma(alpha, dI, w[fo + I * V + i]);
+                gI = gt[k];
+                g[k] = gI;
+            }
+            if (upd_d) {
+                dI = init ? -gI : fma(beta, dI, -gI);
+                d[k] = dI;
+            }
+            dg += dI * gI;
+            dhd += dI * dI * phit[fo + I * V + i];
+        }
+    }
+    double t = block_sum(dg);
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * kNQ + 0] = t;
+    t = block_sum(dhd);
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * kNQ + 1] = t;
+}
+
+void launch_cg_update(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int init,
+                      double *w, double *g, const double *gt, double *d, const double *phit, double *part)
+{
+    hipLaunchKernelGGL(k_cg_update, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st, ch,
+                       init, w, g, gt, d, phit, part);
+}
+
+// Solvent density of eq. 2: pass 0 sums exp(-w_S); pass 1 writes
+// phi_S = phibar_s exp(-w_S) / <exp(-w_S)> into the field-layout output.
+__global__ __launch_bounds__(kBlock) void k_solvent(const int *__restrict__ blk_rep,
+                                                    const int *__restrict__ blk_first,
+                                                    const Rep *__restrict__ rep, const RepState *__restrict__ st,
+                                                    Chain ch, int pass, const double *__restrict__ w,
+                                                    double *__restrict__ out, double *__restrict__ part)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    const long long fo = off_field(R, ch.nsp);
+    if (pass == 0) {
+        const double v = i < V ? exp(-w[fo + 2 * V + i]) : 0.0;
+        const double t = block_sum(v);
+        if (threadIdx.x == 0) part[(long long)blockIdx.x * kNQ] = t;
+    } else if (i < V) {
+        const RepState &S = st[sr.r];
+        out[fo + 2 * V + i] = S.phibar_s * exp(-w[fo + 2 * V + i]) / S.sol_mean;
+    }
+}
+
+void launch_solvent(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int pass,
+                    const double *w, const double *, double *out, double *part)
+{
+    hipLaunchKernelGGL(k_solvent, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st, ch,
+                       pass, w, out, part);
+}
+
+}  // namespace hsf

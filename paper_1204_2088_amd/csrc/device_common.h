@@ -1,0 +1,78 @@
+// common.cuh -- device helpers shared by the kernel translation units.
+#pragma once
+
+#include "hsf_internal.h"
+
+namespace hsf {
+
+// Periodic wrap of an index that is at most one step outside [0, L).
+__device__ __forceinline__ int wrap1(int i, int L) { return i < 0 ? i + L : (i >= L ? i - L : i); }
+
+// Replica and local site of the calling thread in a site plan.
+struct SiteRef {
+    int r;
+    long long i;
+};
+
+__device__ __forceinline__ SiteRef site_ref(const int *blk_rep, const int *blk_first)
+{
+    SiteRef s;
+    s.r = blk_rep[blockIdx.x];
+    s.i = (long long)(blockIdx.x - blk_first[s.r]) * kBlock + threadIdx.x;
+    return s;
+}
+
+// Deterministic block sum (fixed shuffle tree inside each 64-lane wavefront, then
+// the four wavefront sums in order).  Every thread must call it; the result is
+// valid in thread 0.
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double ws[kBlock / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) ws[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kBlock / 64; ++k) t += ws[k];
+    }
+    __syncthreads();
+    return t;
+}
+
+// 27-point linkage stencil at (x, y, z): weights by the number of non-zero offset
+// components, summed per class (centre, 6 faces, 12 edges, 8 corners).
+template <typename real>
+__device__ __forceinline__ real stencil27(const real *__restrict__ f, int x, int y, int z, int Lx,
+                                          int Ly, int Lz, real c0, real c1, real c2, real c3)
+{
+    const int xm = wrap1(x - 1, Lx), xp = wrap1(x + 1, Lx);
+    const int ym = wrap1(y - 1, Ly), yp = wrap1(y + 1, Ly);
+    const int zm = wrap1(z - 1, Lz), zp = wrap1(z + 1, Lz);
+    auto row = [&](int yy, int zz, real &ctr, real &side) {
+        const real *p = f + ((long long)zz * Ly + yy) * Lx;
+        ctr = p[x];
+        side = p[xm] + p[xp];
+    };
+    real a, s, s0, s1, s2, s3;
+    row(y, z, a, s);
+    s0 = a;
+    s1 = s;
+    s2 = 0;
+    s3 = 0;
+    // rows with exactly one of (dy, dz) non-zero
+    row(ym, z, a, s); s1 += a; s2 += s;
+    row(yp, z, a, s); s1 += a; s2 += s;
+    row(y, zm, a, s); s1 += a; s2 += s;
+    row(y, zp, a, s); s1 += a; s2 += s;
+    // rows with both non-zero
+    row(ym, zm, a, s); s2 += a; s3 += s;
+    row(ym, zp, a, s); s2 += a; s3 += s;
+    row(yp, zm, a, s); s2 += a; s3 += s;
+    row(yp, zp, a, s); s2 += a; s3 += s;
+    return c0 * s0 + c1 * s1 + c2 * s2 + c3 * s3;
+}
+
+}  // namespace hsf

@@ -1,0 +1,228 @@
+// dyn.hip -- the dynamics around the density functional:
+//   chemical potential (eq. 4) and thermodynamic force (eq. 8);
+//   D3Q19 lattice Boltzmann, moments (eq. 9), equilibrium (eq. 11), single-relaxation
+//   collision L_ij = -delta_ij / tau with its forcing term, collide then stream (eq. 10);
+//   conservative convection-diffusion update (eq. 3).
+#include <math.h>
+
+#include "device_common.h"
+
+namespace hsf {
+
+// D3Q19 velocities: rest, 6 faces, 12 edges (order documented in hsf.h).
+__device__ constexpr int kCx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__device__ constexpr int kCy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__device__ constexpr int kCz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+__device__ __forceinline__ double lb_weight(int q) { return q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+__device__ __forceinline__ void site_xyz(const Rep &R, long long i, int &x, int &y, int &z)
+{
+    x = (int)(i % R.Lx);
+    y = (int)((i / R.Lx) % R.Ly);
+    z = (int)(i / ((long long)R.Lx * R.Ly));
+}
+
+__device__ __forceinline__ long long sidx(const Rep &R, int x, int y, int z)
+{
+    return (long long)x + (long long)R.Lx * ((long long)y + (long long)R.Ly * z);
+}
+
+// mu_I = -w_I + sum_J chi_IJ sigma[phi_J] + kappa (sum_J phi_J - 1)
+__global__ __launch_bounds__(kBlock) void k_mu(const int *__restrict__ blk_rep, const int *__restrict__ blk_first,
+                                               const Rep *__restrict__ rep, Chain ch,
+                                               const double *__restrict__ phi, const double *__restrict__ w,
+                                               double *__restrict__ mu)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    if (i >= V) return;
+    int x, y, z;
+    site_xyz(R, i, x, y, z);
+    const long long fo = off_field(R, ch.nsp);
+    double sp[3] = {0, 0, 0}, tot = 0.0;
+    for (int J = 0; J < ch.nsp; ++J) {
+        sp[J] = stencil27<double>(phi + fo + J * V, x, y, z, R.Lx, R.Ly, R.Lz, R.c[0], R.c[1], R.c[2], R.c[3]);
+        tot += phi[fo + J * V + i];
+    }
+    for (int I = 0; I < ch.nsp; ++I) {
+        double inter = 0.0;
+        for (int J = 0; J < ch.nsp; ++J) inter += R.chi[I][J] * sp[J];
+        mu[fo + I * V + i] = -w[fo + I * V + i] + inter + R.kappa * (tot - 1.0);
+    }
+}
+
+// f = -dt^2 sum_I phi_I (mu_I(r + e) - mu_I(r - e)) / 2 per axis (LB units).
+__global__ __launch_bounds__(kBlock) void k_force(const int *__restrict__ blk_rep,
+                                                  const int *__restrict__ blk_first, const Rep *__restrict__ rep,
+                                                  Chain ch, const double *__restrict__ phi,
+                                                  const double *__restrict__ mu, double *__restrict__ f)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    if (i >= V) return;
+    int x, y, z;
+    site_xyz(R, i, x, y, z);
+    const long long fo = off_field(R, ch.nsp);
+    const long long nb[6] = {sidx(R, wrap1(x + 1, R.Lx), y, z), sidx(R, wrap1(x - 1, R.Lx), y, z),
+                             sidx(R, x, wrap1(y + 1, R.Ly), z), sidx(R, x, wrap1(y - 1, R.Ly), z),
+                             sidx(R, x, y, wrap1(z + 1, R.Lz)), sidx(R, x, y, wrap1(z - 1, R.Lz))};
+    double acc[3] = {0, 0, 0};
+    for (int I = 0; I < ch.nsp; ++I) {
+        const double *m = mu + fo + I * V;
+        const double p = phi[fo + I * V + i];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[a] += p * (0.5 * (m[nb[2 * a]] - m[nb[2 * a + 1]]));
+    }
+    const double k = -R.dt * R.dt;
+    const long long vo = 3LL * R.site_off;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f[vo + a * V + i] = k * acc[a];
+}
+
+// One LB step, push form: read the 19 pre-collision populations of this site,
+// take the moments of eq. 9 (u with the half-force shift), relax towards the
+// equilibrium of eq. 11 with rate 1/tau, add the forcing term
+//   F_i = (1 - 1/(2 tau)) w_i [3 (c_i - u).f + 9 (c_i.u)(c_i.f)],
+// and write each post-collision population to the neighbour it streams to.
+__global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, const int *__restrict__ blk_first,
+                                               const Rep *__restrict__ rep, const double *__restrict__ nsrc,
+                                               double *__restrict__ ndst, const double *__restrict__ f,
+                                               double *__restrict__ rho_out, double *__restrict__ u_out)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    if (i >= V) return;
+    int x, y, z;
+    site_xyz(R, i, x, y, z);
+    const long long base = 19LL * R.site_off, vo = 3LL * R.site_off;
+    double n[19];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) n[q] = nsrc[base + q * V + i];
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (f) {
+        fx = f[vo + i];
+        fy = f[vo + V + i];
+        fz = f[vo + 2 * V + i];
+    }
+    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        rho += n[q];
+        jx += kCx[q] * n[q];
+        jy += kCy[q] * n[q];
+        jz += kCz[q] * n[q];
+    }
+    const double ux = (jx + 0.5 * fx) / rho, uy = (jy + 0.5 * fy) / rho, uz = (jz + 0.5 * fz) / rho;
+    const double om = 1.0 / R.tau, fp = 1.0 - 0.5 / R.tau;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const double uf = ux * fx + uy * fy + uz * fz;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        const double cu = kCx[q] * ux + kCy[q] * uy + kCz[q] * uz;
+        const double cf = kCx[q] * fx + kCy[q] * fy + kCz[q] * fz;
+        const double wq = lb_weight(q);
+        const double neq = rho * wq * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        const double F = fp * wq * (3.0 * (cf - uf) + 9.0 * cu * cf);
+        const double ns = n[q] - om * (n[q] - neq) + F;
+        const int xd = wrap1(x + kCx[q], R.Lx), yd = wrap1(y + kCy[q], R.Ly), zd = wrap1(z + kCz[q], R.Lz);
+        ndst[base + q * V + sidx(R, xd, yd, zd)] = ns;
+    }
+    rho_out[R.site_off + i] = rho;
+    u_out[vo + i] = ux;
+    u_out[vo + V + i] = uy;
+    u_out[vo + 2 * V + i] = uz;
+}
+
+// Conservative convection-diffusion update.  Face between r and r + e_a:
+//   J = dt * (-(phi_r + phi_e)/2 (mu_e - mu_r))
+//     + [(phi_r + phi_e)/2 - ((phi u_a)_e - (phi u_a)_r)/2] (u_a,r + u_a,e)/2
+// phi_new(r) = phi(r) - sum_a (J(r + e_a/2) - J(r - e_a/2)).
+__global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, const int *__restrict__ blk_first,
+                                               const Rep *__restrict__ rep, Chain ch,
+                                               const double *__restrict__ phi, const double *__restrict__ mu,
+                                               const double *__restrict__ u, double *__restrict__ phi_out)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    if (i >= V) return;
+    int x, y, z;
+    site_xyz(R, i, x, y, z);
+    const long long fo = off_field(R, ch.nsp), vo = 3LL * R.site_off;
+    const long long nb[6] = {sidx(R, wrap1(x - 1, R.Lx), y, z), sidx(R, wrap1(x + 1, R.Lx), y, z),
+                             sidx(R, x, wrap1(y - 1, R.Ly), z), sidx(R, x, wrap1(y + 1, R.Ly), z),
+                             sidx(R, x, y, wrap1(z - 1, R.Lz)), sidx(R, x, y, wrap1(z + 1, R.Lz))};
+    const double dt = R.dt;
+    for (int I = 0; I < ch.nsp; ++I) {
+        const double *p = phi + fo + I * V;
+        const double *m = mu + fo + I * V;
+        const double pr = p[i], mr = m[i];
+        double div = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const long long lo = nb[2 * a], hi = nb[2 * a + 1];
+            // face between lo and r, then between r and hi
+            const double pl = p[lo], ph = p[hi];
+            double jl = dt * (-0.5 * (pl + pr) * (mr - m[lo]));
+            double jh = dt * (-0.5 * (pr + ph) * (m[hi] - mr));
+            if (u) {
+                const double *ua = u + vo + a * V;
+                const double ul = ua[lo], ur = ua[i], uh = ua[hi];
+                jl += (0.5 * (pl + pr) - 0.5 * (pr * ur - pl * ul)) * (0.5 * (ul + ur));
+                jh += (0.5 * (pr + ph) - 0.5 * (ph * uh - pr * ur)) * (0.5 * (ur + uh));
+            }
+            div += jh - jl;
+        }
+        phi_out[fo + I * V + i] = pr - div;
+    }
+}
+
+// Fluid at rest with density 1: n_i = w_i.
+__global__ __launch_bounds__(kBlock) void k_lb_rest(const int *__restrict__ blk_rep,
+                                                    const int *__restrict__ blk_first, const Rep *__restrict__ rep,
+                                                    double *__restrict__ n)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    if (i >= V) return;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) n[19LL * R.site_off + q * V + i] = lb_weight(q);
+}
+
+void launch_mu(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi, const double *w,
+               double *mu)
+{
+    hipLaunchKernelGGL(k_mu, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch, phi, w, mu);
+}
+
+void launch_force(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi, const double *mu,
+                  double *f)
+{
+    hipLaunchKernelGGL(k_force, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch, phi, mu, f);
+}
+
+void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc, double *ndst, const double *f,
+               double *rho, double *u)
+{
+    hipLaunchKernelGGL(k_lb, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, nsrc, ndst, f,
+                       rho, u);
+}
+
+void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi, const double *mu,
+               const double *u, double *phi_out)
+{
+    hipLaunchKernelGGL(k_cd, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch, phi, mu, u,
+                       phi_out);
+}
+
+void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n)
+{
+    hipLaunchKernelGGL(k_lb_rest, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, n);
+}
+
+}  // namespace hsf

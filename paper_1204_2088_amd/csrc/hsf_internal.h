@@ -1,0 +1,124 @@
+// hsf_internal.h -- shared definitions of the HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hsf.h"
+
+namespace hsf {
+
+constexpr int kBlock = 256;   // threads per block of every site kernel (4 wavefronts)
+constexpr int kNQ = 8;        // reduction slots per block in the partials buffer
+
+// Per-replica geometry and parameters, device resident (read-only in kernels).
+struct Rep {
+    int Lx, Ly, Lz, hydro;
+    long long V;            // Lx * Ly * Lz
+    long long site_off;     // first site of this replica in the concatenated site space
+    double c[4];            // stencil class weights: centre, face, edge, corner
+    double csum;            // c0 + 6 c1 + 12 c2 + 8 c3 (sigma applied to a constant 1)
+    double chi[3][3];
+    double kappa, dt, tau;
+};
+
+// Per-replica scalars of an evaluation and of the conjugate-gradient inversion.
+// FP64, device resident; written only by the one-block-per-replica control kernel.
+struct RepState {
+    double phibar_p, phibar_s;   // copolymer and solvent amounts of the target
+    double tnorm2[2];            // |phi^t_A|^2, |phi^t_B|^2
+    double wmean[2];             // mean of w_A, w_B before the gauge shift
+    double q;                    // stored-scale Q of the last evaluation
+    double ln_q;                 // ln Q including the per-step power-of-two scales
+    double alpha, a_prev, h_prev, h0, gg, dhd, beta;
+    double res, tol;
+    double sol_mean;             // <exp(-w_S)> for the solvent closed form
+    int trial, iters, evals, restarts;
+    int max_iter;
+    int active;                  // evaluation kernels process this replica
+    int accepted;                // a trial point was accepted in this iteration
+    int pending;                 // waiting for the start of its next iteration
+    int done;                    // inversion finished (converged or max_iter)
+    int converged;
+    int nonfinite;
+    int scale_e[64];             // per-step power-of-two exponents e_s (G_s /= 2^e_s)
+};
+
+// Launch plan of a site kernel: each block covers kBlock consecutive sites of one replica.
+struct Plan {
+    int nblocks = 0;
+    int *blk_rep = nullptr;      // device: replica of each block
+    int *blk_first = nullptr;    // device: first block of each replica, n_rep + 1 entries
+};
+
+// Chain architecture passed by value to kernels.
+struct Chain {
+    int N;
+    int nsp;                     // 2 or 3 species
+    int types[64];
+};
+
+// Kernel-side view of the per-replica layouts.
+__host__ __device__ inline long long off_field(const Rep &R, int nsp) { return (long long)nsp * R.site_off; }
+__host__ __device__ inline long long off_poly(const Rep &R) { return 2LL * R.site_off; }
+
+// --- launchers (one translation unit per family) --------------------------------
+
+// propagators: FP64 (real = double) and FP32 (real = float) instantiations
+template <typename real>
+struct PropBufs {
+    real *E;        // [rep][2][V]   exp(-w) of the polymer species
+    real *G;        // [rep][N][V]   stored forward propagators G_1..G_N
+    real *Gp[2];    // [rep][V] x 2  ping-pong backward propagators
+};
+
+template <typename real>
+void launch_prep(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
+                 const double *w, const double *d, int use_alpha, PropBufs<real> b, double *acc,
+                 double *partG);
+template <typename real>
+void launch_fwd(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int step,
+                PropBufs<real> b, double *partG);
+template <typename real>
+void launch_bwd(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int step,
+                PropBufs<real> b, double *acc, int final_mode, const double *phit, const double *d,
+                double *out, double *part);
+
+// reductions and control
+enum Phase {
+    PH_Q = 0,        // Q of the forward sweep (partials slot 0 of the G_N step)
+    PH_TARGET = 1,   // target amounts and norms, field means
+    PH_EVAL0 = 2,    // residual at the starting point
+    PH_BEGIN = 3,    // start of an iteration: alpha_0 from d.g and d H d
+    PH_TRIAL = 4,    // a trial point of the line search
+    PH_SCALES = 5,   // update of the per-step scales from the G_s means
+    PH_SOLVENT = 6   // <exp(-w_S)>
+};
+void launch_reduce_ctl(hipStream_t s, int n_rep, const Plan &p, RepState *st, const Rep *rep,
+                       const double *part, int phase, Chain ch, const double *partG, double tol,
+                       int max_iter);
+
+void launch_target_stats(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
+                         const double *phit, const double *w, double *part);
+void launch_local_guess(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phit,
+                        double *w, double *part);
+void launch_init_fields(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
+                        const double *phit, double *w);
+void launch_cg_update(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int init,
+                      double *w, double *g, const double *gt, double *d, const double *phit,
+                      double *part);
+void launch_solvent(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int pass,
+                    const double *w, const double *phi, double *out, double *part);
+
+// dynamics
+void launch_mu(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi,
+               const double *w, double *mu);
+void launch_force(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi,
+                  const double *mu, double *f);
+void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc, double *ndst,
+               const double *f, double *rho, double *u);
+void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi,
+               const double *mu, const double *u, double *phi_out);
+void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n);
+
+}  // namespace hsf

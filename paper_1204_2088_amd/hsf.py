@@ -1,0 +1,297 @@
+"""Python binding of the C ABI in ``include/hsf.h`` (argument marshalling only).
+
+Every step of the method runs in the HIP library ``libhsf.so``; this module
+converts arguments.  Data arguments are numpy arrays (host memory, copied
+synchronously) or torch tensors on the GPU (device memory, ordered on the
+context's stream).  All arrays are float64, C-contiguous, in the layouts of
+the header: fields ``(species, Lz, Ly, Lx)`` per replica, replicas
+concatenated.
+
+If the shared library is missing the import of :func:`load` raises: there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhsf.so")
+MAX_BEADS = 64
+
+HSF_OK, HSF_EINVAL, HSF_ENOMEM, HSF_EHIP, HSF_ENOCONV, HSF_ENONFINITE = 0, -1, -2, -3, -4, -5
+HOST, DEVICE = 0, 1
+FP64, FP32 = 0, 1
+WARM_CURRENT, WARM_LOCAL = 0, 1
+
+EXPORTED = [
+    "hsf_create", "hsf_destroy", "hsf_last_error", "hsf_set_stream", "hsf_total_sites",
+    "hsf_site_offset", "hsf_field_offset", "hsf_num_species", "hsf_set_fields", "hsf_get_fields",
+    "hsf_set_densities", "hsf_get_densities", "hsf_evaluate", "hsf_invert", "hsf_mu_force",
+    "hsf_set_lb", "hsf_get_lb", "hsf_lb_advance", "hsf_get_flow", "hsf_cd_advance", "hsf_step",
+    "hsf_set_hydro", "hsf_set_timing", "hsf_get_timing",
+]
+K_PREP, K_FWD, K_BWD, K_LB, K_CD, K_COUNT = 0, 1, 2, 3, 4, 5
+KERNEL_NAMES = ["prep", "fwd", "bwd", "lb", "cd"]
+
+
+class HsfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hsf error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("Lx", ctypes.c_int), ("Ly", ctypes.c_int), ("Lz", ctypes.c_int),
+        ("n_beads", ctypes.c_int), ("types", ctypes.c_int * MAX_BEADS),
+        ("has_solvent", ctypes.c_int), ("a", ctypes.c_double), ("stencil", ctypes.c_double * 4),
+        ("chi", (ctypes.c_double * 3) * 3), ("kappa", ctypes.c_double), ("dt", ctypes.c_double),
+        ("tau", ctypes.c_double), ("hydro", ctypes.c_int), ("precision", ctypes.c_int),
+    ]
+
+
+class InvertStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("evaluations", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+                ("residual", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load ``libhsf.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python -m paper_1204_2088_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    C = ctypes.c_void_p  # hsf_ctx*
+    I = ctypes.c_int
+    sig = {
+        "hsf_create": ([ctypes.POINTER(Params), I, ctypes.POINTER(C)], I),
+        "hsf_destroy": ([C], None),
+        "hsf_last_error": ([C], ctypes.c_char_p),
+        "hsf_set_stream": ([C, P], I),
+        "hsf_total_sites": ([C], ctypes.c_longlong),
+        "hsf_site_offset": ([C, I], ctypes.c_longlong),
+        "hsf_field_offset": ([C, I], ctypes.c_longlong),
+        "hsf_num_species": ([C], I),
+        "hsf_set_fields": ([C, P, I], I),
+        "hsf_get_fields": ([C, P, I], I),
+        "hsf_set_densities": ([C, P, I], I),
+        "hsf_get_densities": ([C, P, I], I),
+        "hsf_evaluate": ([C, P, P, I], I),
+        "hsf_invert": ([C, ctypes.c_double, I, I, ctypes.POINTER(InvertStats)], I),
+        "hsf_mu_force": ([C, P, P, I], I),
+        "hsf_set_lb": ([C, P, I], I),
+        "hsf_get_lb": ([C, P, I], I),
+        "hsf_lb_advance": ([C, I, P, I], I),
+        "hsf_get_flow": ([C, P, P, I], I),
+        "hsf_cd_advance": ([C, P, P, I], I),
+        "hsf_step": ([C, I, ctypes.c_double, I, ctypes.POINTER(InvertStats),
+                      ctypes.POINTER(ctypes.c_longlong)], I),
+        "hsf_set_hydro": ([C, I], I),
+        "hsf_set_timing": ([C, I], I),
+        "hsf_get_timing": ([C, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)], I),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def params_from_workload(wl, precision=None):
+    """hsf_params of one replica from a :class:`workloads.Workload`."""
+    p = Params()
+    p.Lx, p.Ly, p.Lz = (int(v) for v in wl.L)
+    p.n_beads = wl.N
+    for i, t in enumerate(wl.types):
+        p.types[i] = int(t)
+    p.has_solvent = int(bool(wl.has_solvent))
+    p.a = float(wl.a)
+    for k in range(4):
+        p.stencil[k] = 0.0
+    chi = np.asarray(wl.chi, dtype=np.float64)
+    for i in range(3):
+        for j in range(3):
+            p.chi[i][j] = float(chi[i, j])
+    p.kappa, p.dt, p.tau = float(wl.kappa), float(wl.dt), float(wl.tau)
+    p.hydro = int(bool(wl.hydro))
+    prec = precision or wl.precision
+    p.precision = FP32 if prec == "fp32" else FP64
+    return p
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a, n):
+    """(pointer, where) of a float64 buffer holding at least n elements."""
+    if a is None:
+        return None, HOST
+    if _is_torch(a):
+        import torch
+        assert a.dtype == torch.float64 and a.is_contiguous(), "need a contiguous float64 tensor"
+        assert a.numel() >= n, (a.numel(), n)
+        return ctypes.c_void_p(a.data_ptr()), (DEVICE if a.is_cuda else HOST)
+    assert isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous
+    assert a.size >= n, (a.size, n)
+    return ctypes.c_void_p(a.ctypes.data), HOST
+
+
+class Context:
+    """A set of replicas on the current GPU (a single run is one replica)."""
+
+    def __init__(self, workloads, precision=None, stream=None):
+        lib = load()
+        wls = workloads if isinstance(workloads, (list, tuple)) else [workloads]
+        arr = (Params * len(wls))(*[params_from_workload(w, precision) for w in wls])
+        h = ctypes.c_void_p()
+        rc = lib.hsf_create(arr, len(wls), ctypes.byref(h))
+        if rc != HSF_OK:
+            raise HsfError(rc, "hsf_create failed")
+        self._h = h
+        self._lib = lib
+        self.workloads = list(wls)
+        self.n_rep = len(wls)
+        self.nsp = lib.hsf_num_species(h)
+        self.T = lib.hsf_total_sites(h)
+        if stream is not None:
+            self.set_stream(stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hsf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, ok=(HSF_OK,)):
+        if rc not in ok:
+            raise HsfError(rc, self._lib.hsf_last_error(self._h).decode())
+        return rc
+
+    # sizes
+    def site_offset(self, r):
+        return self._lib.hsf_site_offset(self._h, r)
+
+    def field_offset(self, r):
+        return self._lib.hsf_field_offset(self._h, r)
+
+    def set_stream(self, stream):
+        """stream: a torch.cuda.Stream, an integer hipStream_t, or None."""
+        raw = getattr(stream, "cuda_stream", stream)
+        self._check(self._lib.hsf_set_stream(self._h, ctypes.c_void_p(raw or 0)))
+
+    # state transfer
+    def _put(self, fn, a, n):
+        p, where = _ptr(a, n)
+        self._check(fn(self._h, p, where))
+
+    def _get(self, fn, out, n, shape):
+        if out is None:
+            out = np.empty(shape, dtype=np.float64)
+        p, where = _ptr(out, n)
+        self._check(fn(self._h, p, where))
+        return out
+
+    def set_fields(self, w):
+        self._put(self._lib.hsf_set_fields, w, self.nsp * self.T)
+
+    def get_fields(self, out=None):
+        return self._get(self._lib.hsf_get_fields, out, self.nsp * self.T, (self.nsp * self.T,))
+
+    def set_densities(self, phi):
+        self._put(self._lib.hsf_set_densities, phi, self.nsp * self.T)
+
+    def get_densities(self, out=None):
+        return self._get(self._lib.hsf_get_densities, out, self.nsp * self.T, (self.nsp * self.T,))
+
+    def set_lb(self, n):
+        self._put(self._lib.hsf_set_lb, n, 19 * self.T)
+
+    def get_lb(self, out=None):
+        return self._get(self._lib.hsf_get_lb, out, 19 * self.T, (19 * self.T,))
+
+    # method
+    def evaluate(self, out=None):
+        """phi[w] (field layout) and Q per replica."""
+        if out is None:
+            out = np.empty(self.nsp * self.T)
+        q = (ctypes.c_double * self.n_rep)()
+        p, where = _ptr(out, self.nsp * self.T)
+        self._check(self._lib.hsf_evaluate(self._h, p, q, where))
+        return out, np.array(q[:])
+
+    def invert(self, tol=1e-8, max_iter=1000, warm=WARM_CURRENT, allow_noconv=False):
+        st = (InvertStats * self.n_rep)()
+        rc = self._lib.hsf_invert(self._h, float(tol), int(max_iter), int(warm), st)
+        self._check(rc, (HSF_OK, HSF_ENOCONV) if allow_noconv else (HSF_OK,))
+        return [s.as_dict() for s in st], rc
+
+    def mu_force(self, mu=None, force=None):
+        if mu is None:
+            mu = np.empty(self.nsp * self.T)
+        if force is None:
+            force = np.empty(3 * self.T)
+        pm, where = _ptr(mu, self.nsp * self.T)
+        pf, _ = _ptr(force, 3 * self.T)
+        self._check(self._lib.hsf_mu_force(self._h, pm, pf, where))
+        return mu, force
+
+    def lb_advance(self, n_steps, force=None):
+        p, where = _ptr(force, 3 * self.T)
+        self._check(self._lib.hsf_lb_advance(self._h, int(n_steps), p, where))
+
+    def get_flow(self, rho=None, u=None):
+        if rho is None:
+            rho = np.empty(self.T)
+        if u is None:
+            u = np.empty(3 * self.T)
+        pr, where = _ptr(rho, self.T)
+        pu, _ = _ptr(u, 3 * self.T)
+        self._check(self._lib.hsf_get_flow(self._h, pr, pu, where))
+        return rho, u
+
+    def cd_advance(self, mu, u=None):
+        pm, where = _ptr(mu, self.nsp * self.T)
+        pu, _ = _ptr(u, 3 * self.T)
+        self._check(self._lib.hsf_cd_advance(self._h, pm, pu, where))
+
+    def step(self, n_steps=1, tol=1e-8, max_iter=1000):
+        st = (InvertStats * self.n_rep)()
+        ev = ctypes.c_longlong(0)
+        self._check(self._lib.hsf_step(self._h, int(n_steps), float(tol), int(max_iter), st, ctypes.byref(ev)))
+        return [s.as_dict() for s in st], ev.value
+
+    def set_hydro(self, on):
+        self._check(self._lib.hsf_set_hydro(self._h, int(bool(on))))
+
+    def set_timing(self, on):
+        self._check(self._lib.hsf_set_timing(self._h, int(bool(on))))
+
+    def get_timing(self):
+        """{kernel family: (total ms, launches)} since the last read."""
+        ms = (ctypes.c_double * K_COUNT)()
+        cnt = (ctypes.c_longlong * K_COUNT)()
+        self._check(self._lib.hsf_get_timing(self._h, ms, cnt))
+        return {KERNEL_NAMES[k]: (ms[k], cnt[k]) for k in range(K_COUNT)}

@@ -1,0 +1,57 @@
+"""The C-ABI library loads and exports every entry point declared in include/hsf.h
+(no compute calls: no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "hsf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hsf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    for name in ["hsf_create", "hsf_evaluate", "hsf_invert", "hsf_step", "hsf_set_fields"]:
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1204_2088_amd import hsf
+    path = hsf.library_path()
+    if not os.path.exists(path):
+        pytest.fail(f"{path} not built (run python -m paper_1204_2088_amd.build)")
+    lib = ctypes.CDLL(path)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+    assert sorted(declared_symbols()) == sorted(hsf.EXPORTED)
+
+
+def test_binding_loads_without_gpu_calls():
+    from paper_1204_2088_amd import hsf
+    lib = hsf.load()
+    assert lib.hsf_total_sites(None) == -1
+    assert lib.hsf_num_species(None) == -1
+    assert lib.hsf_last_error(None) == b"null context"
+
+
+def test_create_rejects_bad_parameters_without_gpu():
+    """Parameter validation happens before any device call."""
+    from paper_1204_2088_amd import hsf, workloads as W
+    lib = hsf.load()
+    wl = W.melt16_a4b4()
+    p = hsf.params_from_workload(wl)
+    p.tau = 0.4  # must exceed 1/2
+    h = ctypes.c_void_p()
+    assert lib.hsf_create(ctypes.byref(p), 1, ctypes.byref(h)) == hsf.HSF_EINVAL
+    p = hsf.params_from_workload(wl)
+    p.n_beads = 0
+    assert lib.hsf_create(ctypes.byref(p), 1, ctypes.byref(h)) == hsf.HSF_EINVAL
+    arr = (hsf.Params * 2)(hsf.params_from_workload(wl), hsf.params_from_workload(wl, precision="fp32"))
+    assert lib.hsf_create(arr, 2, ctypes.byref(h)) == hsf.HSF_EINVAL
+    assert lib.hsf_create(arr, 0, ctypes.byref(h)) == hsf.HSF_EINVAL

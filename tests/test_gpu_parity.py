@@ -1,0 +1,288 @@
+"""GPU parity: the HIP library, called through the C ABI, against the FP64 oracle
+on the same seeded inputs.
+
+Tolerances: FP64 path 1e-10 relative, FP32-propagator path 1e-5 relative
+(max |difference| / max |oracle value| per species).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1204_2088_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def hsf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1204_2088_amd import hsf as H
+    H.load()
+    return H
+
+
+def osys(orc, wl, hydro=None):
+    return orc.System(L=wl.L, types=wl.types, has_solvent=wl.has_solvent, a=wl.a, chi=wl.chi,
+                      kappa=wl.kappa, dt=wl.dt, tau=wl.tau,
+                      hydro=wl.hydro if hydro is None else hydro)
+
+
+def relerr(a, b):
+    """max |a - b| / max |b| over each leading-axis slice, then the max."""
+    a = np.asarray(a).reshape(b.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    return max(np.max(np.abs(a[i] - b[i])) / np.max(np.abs(b[i])) for i in range(b.shape[0]))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def small_melt(L=(16, 16, 16), types=None, precision="fp64", chiN=20.0, noise=0.01, seed=0):
+    types = types or W.chain(4, 4)
+    return W.Workload("test", L, types, False, W.chi_matrix(ab=chiN / len(types)), tau=1.0, noise=noise,
+                      seed=seed, precision=precision)
+
+
+def small_solution(L=(12, 10, 14), precision="fp64", seed=3):
+    return W.Workload("test_sol", L, W.chain(3, 9), True, W.chi_matrix(ab=25 / 12, bs=35 / 12), tau=0.8,
+                      noise=0.005, seed=seed, phi_p=0.12, precision=precision)
+
+
+def fields_for(wl, seed, amp=1.0):
+    w = W.random_fields((wl.nsp,) + wl.shape, seed=seed, amplitude=amp, smooth=1)
+    return np.ascontiguousarray(w)
+
+
+CASES = [
+    ("melt16_a4b4", lambda p: small_melt(precision=p)),
+    ("ragged17x18x20_a3b5", lambda p: small_melt(L=(17, 18, 20), types=W.chain(3, 5), precision=p)),
+    ("thin33x1x5_a2b6", lambda p: small_melt(L=(33, 1, 5), types=W.chain(2, 6), precision=p)),
+    ("solution12x10x14_a3b9s", lambda p: small_solution(precision=p)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_evaluate_parity(hsf, orc, name, make, precision):
+    wl = make(precision)
+    say(f"[evaluate] {name} {precision}")
+    phi0 = W.initial_composition(wl)
+    w = fields_for(wl, seed=5, amp=1.5)
+    ctx = hsf.Context(wl)
+    ctx.set_densities(phi0.ravel())
+    ctx.set_fields(w.ravel())
+    got, q = ctx.evaluate()
+    pbar_p = phi0[:2].sum(0).mean()
+    pbar_s = phi0[2].mean() if wl.has_solvent else 0.0
+    ref, qref = orc.evaluate(osys(orc, wl), w, pbar_p, pbar_s)
+    tol = TOL64 if precision == "fp64" else TOL32
+    e = relerr(got, ref)
+    say(f"  rel err phi {e:.3e}  Q {q[0]:.12e} vs {qref:.12e}")
+    assert e < tol
+    assert abs(q[0] / qref - 1) < tol
+    ctx.close()
+
+
+def test_homogeneous_closed_form_gpu(hsf):
+    wl = small_melt(L=(8, 9, 10), types=W.chain(3, 5))
+    w = np.empty((2,) + wl.shape)
+    w[0], w[1] = 0.4, -0.9
+    phi = np.empty_like(w)
+    phi[0], phi[1] = 3 / 8, 5 / 8
+    ctx = hsf.Context(wl)
+    ctx.set_densities(phi.ravel())
+    ctx.set_fields(w.ravel())
+    got, q = ctx.evaluate()
+    got = got.reshape(w.shape)
+    assert abs(q[0] / np.exp(-(3 * 0.4 - 5 * 0.9)) - 1) < 1e-14
+    assert np.max(np.abs(got[0] - 3 / 8)) < 1e-14 and np.max(np.abs(got[1] - 5 / 8)) < 1e-14
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fp32_scales_extreme_fields(hsf, orc, precision):
+    """Strong fields whose raw propagator products leave the FP32 range: the
+    per-step power-of-two scales keep the densities right (second call uses
+    the scales adapted by the first)."""
+    wl = small_melt(L=(12, 12, 12), types=W.chain(8, 8), precision=precision)
+    phi0 = W.initial_composition(wl)
+    w = fields_for(wl, seed=2, amp=1.0) - 7.0  # exp(-w) ~ e^7 per bead: G_16 ~ e^112
+    ctx = hsf.Context(wl)
+    ctx.set_densities(phi0.ravel())
+    ctx.set_fields(w.ravel())
+    ref, qref = orc.evaluate(osys(orc, wl), w, 1.0, 0.0)
+    for k in range(2):
+        got, q = ctx.evaluate()
+        say(f"[extreme] {precision} call {k}: rel err {relerr(got, ref):.3e}, Q {q[0]:.6e} vs {qref:.6e}")
+    tol = TOL64 if precision == "fp64" else TOL32
+    assert relerr(got, ref) < tol
+    assert abs(q[0] / qref - 1) < tol
+
+
+def test_invert_parity_fp64(hsf, orc):
+    wl = small_melt(L=(16, 12, 10), types=W.chain(4, 4))
+    say("[invert fp64]")
+    wt = fields_for(wl, seed=7, amp=0.8)
+    wt -= wt.mean(axis=(1, 2, 3), keepdims=True)
+    sysw = osys(orc, wl)
+    phit, _ = orc.evaluate(sysw, wt, 1.0, 0.0)
+    w0 = -np.log(phit / phit.mean(axis=(1, 2, 3), keepdims=True))
+    wref, st_ref, rc = orc.invert(sysw, phit, w0, tol=1e-10, max_iter=500)
+    ctx = hsf.Context(wl)
+    ctx.set_densities(phit.ravel())
+    st, rcg = ctx.invert(tol=1e-10, max_iter=500, warm=hsf.WARM_LOCAL)
+    say(f"  gpu {st[0]}  oracle {st_ref}")
+    w = ctx.get_fields().reshape(wt.shape)
+    assert st[0]["converged"] and st[0]["residual"] <= 1e-10
+    assert st[0]["iterations"] == st_ref["iterations"]
+    assert st[0]["evaluations"] == st_ref["evaluations"]
+    assert np.max(np.abs(w - wref)) < 1e-9
+    # the GPU densities at its own fields reproduce the target
+    got, _ = ctx.evaluate()
+    assert relerr(got, phit) < 1e-9
+
+
+def test_invert_solution_fp32(hsf, orc):
+    wl = small_solution(precision="fp32")
+    say("[invert fp32 solution]")
+    phit = W.initial_composition(wl)
+    ctx = hsf.Context(wl)
+    ctx.set_densities(phit.ravel())
+    st, _ = ctx.invert(tol=1e-6, max_iter=500, warm=hsf.WARM_LOCAL)
+    say(f"  gpu {st[0]}")
+    assert st[0]["converged"]
+    w = ctx.get_fields().reshape((3,) + wl.shape)
+    # the oracle's densities at the GPU's fields reproduce the target to the tolerance
+    ref, _ = orc.evaluate(osys(orc, wl), w, phit[:2].sum(0).mean(), phit[2].mean())
+    assert relerr(ref, phit) < 2e-6
+
+
+def test_mu_force_parity(hsf, orc):
+    wl = small_solution(L=(9, 11, 7))
+    phi = W.initial_composition(wl)
+    w = fields_for(wl, seed=4)
+    ctx = hsf.Context(wl)
+    ctx.set_densities(phi.ravel())
+    ctx.set_fields(w.ravel())
+    mu, f = ctx.mu_force()
+    mref, fref = orc.mu_force(osys(orc, wl), phi, w)
+    assert relerr(mu, mref) < 1e-13
+    assert np.max(np.abs(f.reshape(fref.shape) - fref)) <= 1e-13 * np.max(np.abs(fref))
+
+
+@pytest.mark.parametrize("L,tau", [((16, 16, 16), 0.6), ((17, 5, 9), 1.5)])
+def test_lb_parity(hsf, orc, L, tau):
+    wl = small_melt(L=L).with_(tau=tau)
+    sysw = osys(orc, wl)
+    rng = np.random.default_rng(1)
+    n = orc.lb_rest_state(sysw) * (1 + 0.02 * rng.uniform(-1, 1, size=(19,) + wl.shape))
+    n = np.ascontiguousarray(n)
+    f = np.ascontiguousarray(1e-3 * rng.uniform(-1, 1, size=(3,) + wl.shape))
+    ctx = hsf.Context(wl)
+    ctx.set_lb(n.ravel())
+    ctx.lb_advance(3, f.ravel())
+    got = ctx.get_lb().reshape(n.shape)
+    rho, u = ctx.get_flow()
+    ref = n
+    for _ in range(3):
+        ref, rref, uref = orc.lb_step(sysw, ref, f)
+    assert np.max(np.abs(got - ref)) < 1e-14
+    assert np.max(np.abs(rho.reshape(rref.shape) - rref)) < 1e-14
+    assert np.max(np.abs(u.reshape(uref.shape) - uref)) < 1e-15
+    assert abs(got.sum() / n.sum() - 1) < 1e-14
+
+
+def test_cd_parity(hsf, orc):
+    wl = small_solution(L=(10, 7, 12))
+    rng = np.random.default_rng(2)
+    phi = W.initial_composition(wl)
+    mu = rng.standard_normal((3,) + wl.shape)
+    u = 0.05 * rng.standard_normal((3,) + wl.shape)
+    ctx = hsf.Context(wl)
+    ctx.set_densities(phi.ravel())
+    ctx.cd_advance(mu.ravel(), u.ravel())
+    got = ctx.get_densities().reshape(phi.shape)
+    ref = orc.cd_update(osys(orc, wl), phi, mu, u)
+    assert np.max(np.abs(got - ref)) < 1e-15
+    assert np.max(np.abs(got.sum(axis=(1, 2, 3)) / phi.sum(axis=(1, 2, 3)) - 1)) < 1e-13
+
+
+def test_melt16_trajectory_fp64(hsf, orc):
+    """16^3 A4B4 melt, chi N = 20, tau 1.0, residual 1e-8: 100 coupled steps,
+    GPU against the oracle, step by step."""
+    wl = W.melt16_a4b4()
+    say("[trajectory melt16_a4b4 fp64 100 steps]")
+    phi = W.initial_composition(wl)
+    sysw = osys(orc, wl)
+    ctx = hsf.Context(wl)
+    ctx.set_densities(phi.ravel())
+    w = -np.log(phi / phi.mean(axis=(1, 2, 3), keepdims=True))
+    ctx.set_fields(w.ravel())
+    n = orc.lb_rest_state(sysw)
+    worst = 0.0
+    for k in range(wl.steps):
+        st, _ = ctx.step(1, tol=wl.tol, max_iter=1000)
+        phi, w, n, st_ref, u, rho, rc = orc.step(sysw, phi, w, n, tol=wl.tol, max_iter=1000)
+        got = ctx.get_densities().reshape(phi.shape)
+        e = relerr(got, phi)
+        worst = max(worst, e)
+        if k % 20 == 0 or e > TOL64:
+            say(f"  step {k}: iters gpu {st[0]['iterations']} oracle {st_ref['iterations']}  rel err {e:.3e}")
+        assert st[0]["iterations"] == st_ref["iterations"], (k, st[0], st_ref)
+        assert e < TOL64, k
+    wg = ctx.get_fields().reshape(w.shape)
+    assert np.max(np.abs(wg - w)) < 1e-8
+    ng = ctx.get_lb().reshape(n.shape)
+    assert np.max(np.abs(ng - n)) < 1e-14
+    say(f"  worst rel err over 100 steps {worst:.3e}")
+
+
+def test_batched_replicas_match_single(hsf, orc):
+    """Uneven boxes in one context: each replica equals the oracle."""
+    wls = [small_solution(L=(8, 8, 8), seed=1, precision="fp64"),
+           small_solution(L=(12, 10, 6), seed=2, precision="fp64").with_(chi=W.chi_matrix(ab=1.9, bs=2.5)),
+           small_solution(L=(5, 9, 11), seed=3, precision="fp64").with_(chi=W.chi_matrix(ab=2.6, bs=2.2))]
+    ctx = hsf.Context(wls)
+    phis = [W.initial_composition(wl) for wl in wls]
+    ctx.set_densities(np.concatenate([p.ravel() for p in phis]))
+    ctx.set_fields(np.concatenate([(-np.log(p / p.mean(axis=(1, 2, 3), keepdims=True))).ravel() for p in phis]))
+    st, _ = ctx.step(3, tol=1e-9, max_iter=1000)
+    got = ctx.get_densities()
+    for r, wl in enumerate(wls):
+        sysw = osys(orc, wl)
+        phi = phis[r]
+        w = -np.log(phi / phi.mean(axis=(1, 2, 3), keepdims=True))
+        n = orc.lb_rest_state(sysw)
+        for _ in range(3):
+            phi, w, n, st_ref, _, _, _ = orc.step(sysw, phi, w, n, tol=1e-9, max_iter=1000)
+        o = ctx.field_offset(r)
+        g = got[o:o + phi.size].reshape(phi.shape)
+        e = relerr(g, phi)
+        say(f"[batch] replica {r} {wl.L}: rel err {e:.3e}, iters {st[r]['iterations']} vs {st_ref['iterations']}")
+        assert e < TOL64
+
+
+def test_full_size_melt64_fp32_sampled(hsf, orc):
+    """64^3 A8B8 melt with FP32 propagators, the bench's launch configuration:
+    one evaluation compared with the oracle at every site (the oracle runs the
+    full box in about a second), plus the FP64 path."""
+    for precision, tol in (("fp32", TOL32), ("fp64", TOL64)):
+        wl = W.melt64_a8b8(precision=precision)
+        phi0 = W.initial_composition(wl)
+        w = fields_for(wl, seed=11, amp=1.0)
+        ctx = hsf.Context(wl)
+        ctx.set_densities(phi0.ravel())
+        ctx.set_fields(w.ravel())
+        got, q = ctx.evaluate()
+        ref, qref = orc.evaluate(osys(orc, wl), w, 1.0, 0.0)
+        e = relerr(got, ref)
+        say(f"[melt64 {precision}] rel err {e:.3e}")
+        assert e < tol and abs(q[0] / qref - 1) < tol
+        ctx.close()
