@@ -159,9 +159,14 @@ def test_invert_solution_fp32(hsf, orc):
     say(f"  gpu {st[0]}")
     assert st[0]["converged"]
     w = ctx.get_fields().reshape((3,) + wl.shape)
-    # the oracle's densities at the GPU's fields reproduce the target to the tolerance
+    # the FP64 oracle's densities at the GPU's fields reproduce the target: the
+    # residual (relative L2 norm per polymer species) is within the tolerance
+    # plus the FP32 evaluation error
     ref, _ = orc.evaluate(osys(orc, wl), w, phit[:2].sum(0).mean(), phit[2].mean())
-    assert relerr(ref, phit) < 2e-6
+    res = max(np.linalg.norm(ref[I] - phit[I]) / np.linalg.norm(phit[I]) for I in range(2))
+    say(f"  FP64 residual at the GPU fields {res:.3e}")
+    assert res < 1e-6 + 2e-7
+    assert np.max(np.abs(ref[2] - phit[2])) < 1e-14
 
 
 def test_mu_force_parity(hsf, orc):
