@@ -190,6 +190,17 @@ int hsf_step(hsf_ctx *ctx, int n_steps, double tol, int max_iter, hsf_invert_sta
  * is kept while off). */
 int hsf_set_hydro(hsf_ctx *ctx, int on);
 
+/* Propagator tiling (the temporally blocked sweeps): cfg = {cx, cy, cz, k}, a
+ * core tile of cx*cy*cz sites per workgroup advanced k contour steps per launch.
+ * hsf_set_tile accepts only the configurations compiled into the library
+ * (HSF_EINVAL otherwise); results do not depend on the choice beyond rounding.
+ * hsf_autotune times one density-functional evaluation `reps` times with every
+ * configuration that fits the device's LDS and keeps the fastest (best_ms, may be
+ * NULL, receives its time).  It leaves densities, fields and LB state unchanged. */
+int hsf_set_tile(hsf_ctx *ctx, const int cfg[4]);
+int hsf_get_tile(const hsf_ctx *ctx, int cfg[4]);
+int hsf_autotune(hsf_ctx *ctx, int reps, double *best_ms);
+
 /* Kernel families timed by hsf_set_timing. */
 enum {
     HSF_K_PREP = 0,   /* field preparation + first forward step          */

@@ -6,12 +6,15 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
 #include "hsf_internal.h"
+#include "prop_block.h"
 
 using namespace hsf;
 
@@ -25,7 +28,12 @@ struct hsf_ctx {
     Rep *rep_d = nullptr;
     RepState *st_d = nullptr;
     RepState *st_h = nullptr;        // pinned mirror for status reads
-    Plan plan;
+    Plan plan;                       // site plan: kBlock consecutive sites per block
+    TileCfg tile{8, 8, 8, 2};        // propagator tile configuration in use
+    Plan tplan;                      // tile plan of `tile`
+    int max_tile_blocks = 0;         // over every configuration (sizes the partials)
+    size_t lds_limit = 65536;
+    int tuned = 0;
     hipStream_t stream = nullptr;
     int fields_set = 0;              // fields hold a usable warm start
     std::string err;
@@ -39,14 +47,26 @@ struct hsf_ctx {
     void *E = nullptr, *G = nullptr, *Gp0 = nullptr, *Gp1 = nullptr;
     std::vector<void *> allocs;
 
-    // optional per-launch timing of the hot kernels with HIP events on the context stream
-    int timing = 0;
-    struct Mark {
+    // hipGraphs of the fixed launch sequences (captured at first use, replayed after)
+    hipStream_t cap_stream = nullptr;  // own stream for capture when the caller's is the null stream
+    int use_graphs = 1;
+    struct EvPair {
         int kind;
         hipEvent_t a, b;
+        bool pooled;                   // return to the pool after reading
     };
-    std::vector<Mark> marks;       // recorded since the last read
-    std::vector<hipEvent_t> pool;  // free events
+    struct GraphSlot {
+        hipGraphExec_t exec = nullptr;
+    };
+    enum { GK_START = 0, GK_TRIAL, GK_UPDATE, GK_EVAL, GK_COUNT };
+    GraphSlot graphs[GK_COUNT];
+
+    // optional per-launch timing of the hot kernels with HIP events on the context stream
+    int timing = 0;
+    std::vector<EvPair> pending;       // recorded, not yet read
+    std::vector<hipEvent_t> pool;      // free events
+    double tot_ms[HSF_K_COUNT] = {0};
+    long long tot_cnt[HSF_K_COUNT] = {0};
 };
 
 namespace {
@@ -119,16 +139,38 @@ int copy_out(hsf_ctx *c, double *dst, const double *src, size_t n, int where)
     return HSF_OK;
 }
 
-int read_status(hsf_ctx *c)
+// Read the elapsed times of recorded event pairs (the stream has been synchronised).
+int harvest(hsf_ctx *c)
 {
-    HIPCHK(c, hipMemcpyAsync(c->st_h, c->st_d, sizeof(RepState) * c->n_rep, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto &m : c->pending) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, m.a, m.b));
+        c->tot_ms[m.kind] += ms;
+        c->tot_cnt[m.kind] += 1;
+        if (m.pooled) {
+            c->pool.push_back(m.a);
+            c->pool.push_back(m.b);
+        }
+    }
+    c->pending.clear();
     return HSF_OK;
 }
 
-hipEvent_t take_event(hsf_ctx *c)
+int sync(hsf_ctx *c)
 {
-    if (!c->pool.empty()) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return harvest(c);
+}
+
+int read_status(hsf_ctx *c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->st_h, c->st_d, sizeof(RepState) * c->n_rep, hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+hipEvent_t new_event(hsf_ctx *c, bool pooled)
+{
+    if (pooled && !c->pool.empty()) {
         hipEvent_t e = c->pool.back();
         c->pool.pop_back();
         return e;
@@ -138,27 +180,60 @@ hipEvent_t take_event(hsf_ctx *c)
     return e;
 }
 
-// Bracket one launch of kernel family `kind` (HSF_K_*) with events when timing is on.
+// Events for one launch of kernel family `kind` (HSF_K_*) when timing is on; the
+// launcher hands them to hipExtLaunchKernelGGL, which records them around the
+// kernel's own execution.
 struct Timed {
     hsf_ctx *c;
     int kind;
-    hipEvent_t a = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
     Timed(hsf_ctx *c_, int k) : c(c_), kind(k)
     {
-        if (c->timing) {
-            a = take_event(c);
-            if (a) (void)hipEventRecord(a, c->stream);
-        }
+        if (!c->timing) return;
+        a = new_event(c, true);
+        b = new_event(c, true);
+        if (!a || !b) a = b = nullptr;
     }
     ~Timed()
     {
-        if (!a) return;
-        hipEvent_t b = take_event(c);
-        if (!b) return;
-        (void)hipEventRecord(b, c->stream);
-        c->marks.push_back({kind, a, b});
+        if (a) c->pending.push_back({kind, a, b, true});
     }
 };
+
+// Run a fixed launch sequence: captured into a hipGraph at its first use, replayed after.
+template <class F>
+int run_seq(hsf_ctx *c, int kind, F &&body)
+{
+    if (!c->use_graphs || c->timing) {   // timing mode launches directly, with events per kernel
+        body();
+        HIPCHK(c, hipGetLastError());
+        return HSF_OK;
+    }
+    hsf_ctx::GraphSlot &g = c->graphs[kind];
+    if (!g.exec) {
+        hipStream_t user = c->stream;
+        if (!user && !c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipStream_t cs = user ? user : c->cap_stream;
+        if (!user) HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        c->stream = cs;
+        body();
+        c->stream = user;
+        hipGraph_t graph = nullptr;
+        hipError_t e1 = hipGetLastError();
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e1 != hipSuccess || e2 != hipSuccess)
+            return fail(c, HSF_EHIP, "graph capture failed: %s / %s", hipGetErrorString(e1), hipGetErrorString(e2));
+        hipError_t e3 = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e3 != hipSuccess) {
+            g.exec = nullptr;
+            return fail(c, HSF_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
+        }
+    }
+    HIPCHK(c, hipGraphLaunch(g.exec, c->stream));
+    return HSF_OK;
+}
 
 template <typename real>
 PropBufs<real> bufs(hsf_ctx *c)
@@ -171,28 +246,76 @@ PropBufs<real> bufs(hsf_ctx *c)
     return b;
 }
 
+// Blocks of the tile plan of configuration t for every replica.
+void tile_blocks(const hsf_ctx *c, const TileCfg &t, std::vector<int> &blk_rep, std::vector<int> &blk_first)
+{
+    blk_rep.clear();
+    blk_first.clear();
+    for (int r = 0; r < c->n_rep; ++r) {
+        const Rep &R = c->reps[r];
+        const long long nb = (long long)((R.Lx + t.cx - 1) / t.cx) * ((R.Ly + t.cy - 1) / t.cy) *
+                             ((R.Lz + t.cz - 1) / t.cz);
+        blk_first.push_back((int)blk_rep.size());
+        for (long long b = 0; b < nb; ++b) blk_rep.push_back(r);
+    }
+    blk_first.push_back((int)blk_rep.size());
+}
+
+bool tile_known(const TileCfg &t)
+{
+#define HSF_EQ(CX, CY, CZ, K) \
+    if (t.cx == CX && t.cy == CY && t.cz == CZ && t.k == K) return true;
+    HSF_TILE_CONFIGS(HSF_EQ)
+#undef HSF_EQ
+    return false;
+}
+
+// Make t the configuration in use (device tile plan rebuilt; captured graphs dropped).
+int set_tile(hsf_ctx *c, const TileCfg &t)
+{
+    std::vector<int> br, bf;
+    tile_blocks(c, t, br, bf);
+    if ((int)br.size() > c->max_tile_blocks) return fail(c, HSF_EINVAL, "tile plan larger than sized for");
+    HIPCHK(c, hipMemcpy(c->tplan.blk_rep, br.data(), sizeof(int) * br.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->tplan.blk_first, bf.data(), sizeof(int) * bf.size(), hipMemcpyHostToDevice));
+    c->tplan.nblocks = (int)br.size();
+    c->tile = t;
+    for (auto &g : c->graphs)
+        if (g.exec) {
+            (void)hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+        }
+    return HSF_OK;
+}
+
 // One density-functional evaluation for the active replicas.
 //   final_mode 0: densities into out (field layout); 1: gradient phi^t - phi into out
 //   (polymer layout) with the partial dot products against d.
+// Launches: exp of the fields, ceil(N/K) forward launches, the Q reduction,
+// ceil(N/K) backward launches (the last one normalises).
 template <typename real>
 void run_eval(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d)
 {
     PropBufs<real> b = bufs<real>(c);
-    const int N = c->ch.N;
+    const int N = c->ch.N, K = c->tile.k;
     {
         Timed t(c, HSF_K_PREP);
-        launch_prep<real>(c->stream, c->plan, c->rep_d, c->st_d, c->ch, c->w, c->d, use_alpha, b, c->acc,
-                          c->partG);
+        launch_field_exp<real>(c->stream, c->plan, c->rep_d, c->st_d, c->ch, c->w, c->d, use_alpha, b.E, t.a, t.b);
     }
-    for (int s = 2; s <= N; ++s) {
+    for (int s0 = 0; s0 < N; s0 += K) {
         Timed t(c, HSF_K_FWD);
-        launch_fwd<real>(c->stream, c->plan, c->rep_d, c->st_d, c->ch, s, b, c->partG);
+        launch_fwd_block<real>(c->tile, c->stream, c->tplan, c->rep_d, c->st_d, c->ch, s0, std::min(K, N - s0), b,
+                               c->partG, t.a, t.b);
     }
-    launch_reduce_ctl(c->stream, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_Q, c->ch, c->partG, 0.0, 0);
-    for (int s = N; s >= 1; --s) {
+    launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_Q, c->ch, c->partG, 0.0, 0);
+    int parity = 0;
+    for (int s_hi = N; s_hi >= 1; s_hi -= K) {
         Timed t(c, HSF_K_BWD);
-        launch_bwd<real>(c->stream, c->plan, c->rep_d, c->st_d, c->ch, s, b, c->acc, final_mode, c->phi, d, out,
-                         c->part);
+        const real *gin = b.Gp[parity ^ 1];
+        real *gout = b.Gp[parity];
+        launch_bwd_block<real>(c->tile, c->stream, c->tplan, c->rep_d, c->st_d, c->ch, s_hi, std::min(K, s_hi), b,
+                               gin, gout, c->acc, final_mode, c->phi, d, out, c->part, t.a, t.b);
+        parity ^= 1;
     }
 }
 
@@ -220,15 +343,20 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
         launch_local_guess(s, c->plan, c->rep_d, c->ch, c->phi, c->w, c->part);
     target_setup(c, tol, max_iter);
     launch_init_fields(s, c->plan, c->rep_d, c->st_d, c->ch, c->phi, c->w);
-    c->fields_set = 1;
-    // starting point
-    run_eval_any(c, 0, 1, c->g, nullptr);
-    launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_EVAL0, c->ch, c->partG, 0.0, 0);
-    launch_cg_update(s, c->plan, c->rep_d, c->st_d, c->ch, 1, c->w, c->g, c->gt, c->d, c->phi, c->part);
-    launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_BEGIN, c->ch, c->partG, 0.0, 0);
     HIPCHK(c, hipGetLastError());
-    int rc = read_status(c);
+    c->fields_set = 1;
+    // starting point: evaluation, residual, first direction, first alpha
+    int rc = run_seq(c, hsf_ctx::GK_START, [&] {
+        run_eval_any(c, 0, 1, c->g, nullptr);
+        launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_EVAL0, c->ch, c->partG,
+                          0.0, 0);
+        launch_cg_update(c->stream, c->plan, c->rep_d, c->st_d, c->ch, 1, c->w, c->g, c->gt, c->d, c->phi,
+                         c->part);
+        launch_reduce_ctl(c->stream, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_BEGIN, c->ch, c->partG,
+                          0.0, 0);
+    });
     if (rc) return rc;
+    if ((rc = read_status(c))) return rc;
     bool any = false;
     for (int r = 0; r < c->n_rep; ++r) any |= c->st_h[r].active != 0;
     // every pass either advances a line search (at most 3 trials per iteration) or
@@ -236,9 +364,12 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
     long long guard = 3LL * max_iter + 3;
     while (any) {
         if (--guard < 0) return fail(c, HSF_EHIP, "inversion control did not progress");
-        run_eval_any(c, 1, 1, c->gt, c->d);
-        launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_TRIAL, c->ch, c->partG, 0.0, 0);
-        HIPCHK(c, hipGetLastError());
+        rc = run_seq(c, hsf_ctx::GK_TRIAL, [&] {
+            run_eval_any(c, 1, 1, c->gt, c->d);
+            launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_TRIAL, c->ch,
+                              c->partG, 0.0, 0);
+        });
+        if (rc) return rc;
         if ((rc = read_status(c))) return rc;
         bool trialing = false, pending = false;
         for (int r = 0; r < c->n_rep; ++r) {
@@ -246,8 +377,13 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
             pending |= c->st_h[r].pending != 0;
         }
         if (trialing) continue;
-        launch_cg_update(s, c->plan, c->rep_d, c->st_d, c->ch, 0, c->w, c->g, c->gt, c->d, c->phi, c->part);
-        launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_BEGIN, c->ch, c->partG, 0.0, 0);
+        rc = run_seq(c, hsf_ctx::GK_UPDATE, [&] {
+            launch_cg_update(c->stream, c->plan, c->rep_d, c->st_d, c->ch, 0, c->w, c->g, c->gt, c->d, c->phi,
+                             c->part);
+            launch_reduce_ctl(c->stream, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_BEGIN, c->ch,
+                              c->partG, 0.0, 0);
+        });
+        if (rc) return rc;
         any = pending;
     }
     if ((rc = read_status(c))) return rc;
@@ -295,6 +431,8 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
         if (!(p.tau > 0.5) || !(p.dt > 0.0)) return HSF_EINVAL;
     }
     hsf_ctx *c = new hsf_ctx();
+    const char *ng = getenv("HSF_NO_GRAPHS");   // debugging aid: launch every kernel directly
+    c->use_graphs = (ng && ng[0] == '1') ? 0 : 1;
     c->n_rep = n_rep;
     c->precision = p0.precision;
     c->hydro = p0.hydro ? 1 : 0;
@@ -333,6 +471,21 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     blk_first.push_back((int)blk_rep.size());
     c->T = off;
     c->plan.nblocks = (int)blk_rep.size();
+    {
+        std::vector<int> br, bf;
+#define HSF_SIZE(CX, CY, CZ, K)                                             \
+    tile_blocks(c, TileCfg{CX, CY, CZ, K}, br, bf);                         \
+    c->max_tile_blocks = std::max(c->max_tile_blocks, (int)br.size());
+        HSF_TILE_CONFIGS(HSF_SIZE)
+#undef HSF_SIZE
+    }
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+            c->lds_limit = (size_t)lds;
+    }
+    const int max_blocks = std::max(c->plan.nblocks, c->max_tile_blocks);
 
     const long long T = c->T;
     const int nsp = c->ch.nsp, N = c->ch.N;
@@ -359,8 +512,10 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     ALLOC(c->u, sizeof(double) * 3 * T);
     ALLOC(c->uin, sizeof(double) * 3 * T);
     ALLOC(c->force, sizeof(double) * 3 * T);
-    ALLOC(c->part, sizeof(double) * kNQ * c->plan.nblocks);
-    ALLOC(c->partG, sizeof(double) * (N + 2) * c->plan.nblocks);
+    ALLOC(c->part, sizeof(double) * kNQ * max_blocks);
+    ALLOC(c->partG, sizeof(double) * (N + 2) * max_blocks);
+    ALLOC(c->tplan.blk_rep, sizeof(int) * c->max_tile_blocks);
+    ALLOC(c->tplan.blk_first, sizeof(int) * (n_rep + 1));
     ALLOC(c->E, rs * 2 * T);
     ALLOC(c->G, rs * N * T);
     ALLOC(c->Gp0, rs * T);
@@ -397,6 +552,18 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
         hsf_destroy(c);
         return rc;
     }
+    // propagator tiles: default, or forced by HSF_TILE=cx,cy,cz,k
+    TileCfg t0{8, 8, 8, 2};
+    const char *forced = getenv("HSF_TILE");
+    if (forced) {
+        TileCfg f{0, 0, 0, 0};
+        if (sscanf(forced, "%d,%d,%d,%d", &f.cx, &f.cy, &f.cz, &f.k) == 4 && tile_known(f)) t0 = f;
+    }
+    if (tile_lds_bytes(t0, real_size(c)) > c->lds_limit) t0 = TileCfg{8, 8, 8, 1};
+    if ((rc = set_tile(c, t0)) != HSF_OK) {
+        hsf_destroy(c);
+        return rc;
+    }
     *out = c;
     return HSF_OK;
 }
@@ -406,11 +573,15 @@ void hsf_destroy(hsf_ctx *c)
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    for (auto &m : c->marks) {
-        (void)hipEventDestroy(m.a);
-        (void)hipEventDestroy(m.b);
-    }
+    for (auto &g : c->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    for (auto &m : c->pending)
+        if (m.pooled) {
+            (void)hipEventDestroy(m.a);
+            (void)hipEventDestroy(m.b);
+        }
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (void *p : c->allocs) (void)hipFree(p);
     if (c->st_h) (void)hipHostFree(c->st_h);
     delete c;
@@ -479,11 +650,14 @@ int hsf_evaluate(hsf_ctx *c, double *phi_out, double *Q_out, int where)
     // An evaluation whose propagators left the floating-point range is repeated
     // with the per-step scales it adapted (at most three more times).
     for (int attempt = 0; attempt < 4; ++attempt) {
-        target_setup(c, 0.0, 0);   // phibar_p, phibar_s from the current densities; all replicas active
-        run_eval_any(c, 0, 0, c->eval_out, nullptr);
-        launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_SCALES, c->ch, c->partG, 0.0, 0);
-        int rc0 = read_status(c);
+        int rc0 = run_seq(c, hsf_ctx::GK_EVAL, [&] {
+            target_setup(c, 0.0, 0);   // phibar_p, phibar_s from the current densities; all replicas active
+            run_eval_any(c, 0, 0, c->eval_out, nullptr);
+            launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_SCALES, c->ch,
+                              c->partG, 0.0, 0);
+        });
         if (rc0) return rc0;
+        if ((rc0 = read_status(c))) return rc0;
         bool bad = false;
         for (int r = 0; r < c->n_rep; ++r) bad |= c->st_h[r].nonfinite != 0;
         if (!bad) break;
@@ -546,7 +720,7 @@ int hsf_lb_advance(hsf_ctx *c, int n_steps, const double *force, int where)
     for (int k = 0; k < n_steps; ++k) {
         {
             Timed t(c, HSF_K_LB);
-            launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, f, c->rho, c->u);
+            launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, f, c->rho, c->u, t.a, t.b);
         }
         std::swap(c->nA, c->nB);
     }
@@ -574,8 +748,9 @@ int hsf_cd_advance(hsf_ctx *c, const double *mu, const double *u, int where)
         uu = c->uin;
     }
     launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, uu, c->phi_tmp);
-    std::swap(c->phi, c->phi_tmp);
     HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->phi, c->phi_tmp, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice,
+                             c->stream));
     return HSF_OK;
 }
 
@@ -592,16 +767,18 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
             launch_force(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, c->force);
             {
                 Timed t(c, HSF_K_LB);
-                launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, c->force, c->rho, c->u);
+                launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, c->force, c->rho, c->u, t.a, t.b);
             }
             std::swap(c->nA, c->nB);
             uu = c->u;
         }
         {
             Timed t(c, HSF_K_CD);
-            launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, uu, c->phi_tmp);
+            launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, uu, c->phi_tmp, t.a, t.b);
         }
-        std::swap(c->phi, c->phi_tmp);
+        // the captured sequences hold the address of phi: copy the update back
+        HIPCHK(c, hipMemcpyAsync(c->phi, c->phi_tmp, sizeof(double) * c->ch.nsp * c->T,
+                                 hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipGetLastError());
     }
     return HSF_OK;
@@ -617,21 +794,82 @@ int hsf_set_timing(hsf_ctx *c, int on)
 int hsf_get_timing(hsf_ctx *c, double *total_ms, long long *count)
 {
     if (!c || !total_ms || !count) return HSF_EINVAL;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int rc = sync(c);
+    if (rc) return rc;
     for (int k = 0; k < HSF_K_COUNT; ++k) {
-        total_ms[k] = 0.0;
-        count[k] = 0;
+        total_ms[k] = c->tot_ms[k];
+        count[k] = c->tot_cnt[k];
+        c->tot_ms[k] = 0.0;
+        c->tot_cnt[k] = 0;
     }
-    for (auto &m : c->marks) {
-        float ms = 0.0f;
-        HIPCHK(c, hipEventElapsedTime(&ms, m.a, m.b));
-        total_ms[m.kind] += ms;
-        count[m.kind] += 1;
-        c->pool.push_back(m.a);
-        c->pool.push_back(m.b);
-    }
-    c->marks.clear();
     return HSF_OK;
+}
+
+int hsf_set_tile(hsf_ctx *c, const int cfg[4])
+{
+    if (!c || !cfg) return HSF_EINVAL;
+    TileCfg t{cfg[0], cfg[1], cfg[2], cfg[3]};
+    if (!tile_known(t)) return fail(c, HSF_EINVAL, "tile %d,%d,%d,%d is not instantiated", t.cx, t.cy, t.cz, t.k);
+    if (tile_lds_bytes(t, real_size(c)) > c->lds_limit) return fail(c, HSF_EINVAL, "tile exceeds the LDS limit");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return set_tile(c, t);
+}
+
+int hsf_get_tile(const hsf_ctx *c, int cfg[4])
+{
+    if (!c || !cfg) return HSF_EINVAL;
+    cfg[0] = c->tile.cx;
+    cfg[1] = c->tile.cy;
+    cfg[2] = c->tile.cz;
+    cfg[3] = c->tile.k;
+    return HSF_OK;
+}
+
+int hsf_autotune(hsf_ctx *c, int reps, double *best_ms)
+{
+    if (!c || reps < 1) return HSF_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int saved_timing = c->timing;
+    c->timing = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    TileCfg best = c->tile;
+    float best_t = 1e30f;
+    int rc = HSF_OK;
+    std::vector<TileCfg> cands;
+#define HSF_CAND(CX, CY, CZ, K) cands.push_back(TileCfg{CX, CY, CZ, K});
+    HSF_TILE_CONFIGS(HSF_CAND)
+#undef HSF_CAND
+    for (const TileCfg &t : cands) {
+        if (tile_lds_bytes(t, real_size(c)) > c->lds_limit) continue;
+        if ((rc = set_tile(c, t)) != HSF_OK) break;
+        // one evaluation per timing: exp, sweeps, Q, normalisation (state untouched)
+        target_setup(c, 0.0, 0);
+        run_eval_any(c, 0, 0, c->eval_out, nullptr);
+        (void)hipEventRecord(e0, c->stream);
+        for (int k = 0; k < reps; ++k) run_eval_any(c, 0, 0, c->eval_out, nullptr);
+        (void)hipEventRecord(e1, c->stream);
+        hipError_t e = hipEventSynchronize(e1);
+        if (e != hipSuccess) {
+            rc = fail(c, HSF_EHIP, "autotune: %s", hipGetErrorString(e));
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_t) {
+            best_t = ms;
+            best = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing = saved_timing;
+    if (rc == HSF_OK) rc = set_tile(c, best);
+    c->tuned = 1;
+    if (best_ms) *best_ms = best_t;
+    return rc;
 }
 
 int hsf_set_hydro(hsf_ctx *c, int on)

@@ -19,14 +19,6 @@
 
 namespace hsf {
 
-// Fixed-order sum of `count` values strided by `stride` starting at base[first*stride].
-__device__ double reduce_range(const double *base, int first, int last, long long stride, int slot)
-{
-    double v = 0.0;
-    for (int b = first + (int)threadIdx.x; b < last; b += kBlock) v += base[(long long)b * stride + slot];
-    return block_sum(v);
-}
-
 // Per-step power-of-two scales for the next evaluation.  sums[s] = sum_r of the
 // stored G_{s+1} of this evaluation (its mean m_s is relative to the cumulative
 // scale used), sums[N], sums[N+1] = sum_r E_A, E_B.  Target: stored means near 1.
@@ -53,6 +45,9 @@ __device__ void update_scales(RepState &S, const Chain &ch, const double *sums, 
     }
 }
 
+__device__ void control(RepState &S, int phase, const Chain &ch, const double *red, const double *gsum,
+                        double V, double csum, double tol, int max_iter);
+
 __global__ __launch_bounds__(kBlock) void k_reduce_ctl(const int *__restrict__ blk_first,
                                                        RepState *__restrict__ st, const Rep *__restrict__ rep,
                                                        const double *__restrict__ part, int phase, Chain ch,
@@ -60,46 +55,74 @@ __global__ __launch_bounds__(kBlock) void k_reduce_ctl(const int *__restrict__ b
                                                        double tol, int max_iter)
 {
     const int r = blockIdx.x;
-    RepState &S = st[r];
+    // work on an LDS copy of the replica's state: one cooperative load and store instead of
+    // a dependent global round trip per field in the scalar logic below
+    __shared__ RepState S;
+    {
+        static_assert(sizeof(RepState) % 4 == 0, "RepState is copied as 32-bit words");
+        const int *src = reinterpret_cast<const int *>(&st[r]);
+        int *dst = reinterpret_cast<int *>(&S);
+        for (int k = threadIdx.x; k < (int)(sizeof(RepState) / 4); k += kBlock) dst[k] = src[k];
+    }
+    __syncthreads();
     const int b0 = blk_first[r], b1 = blk_first[r + 1];
     const double V = (double)rep[r].V;
-    __shared__ double red[kNQ];
-    __shared__ double gsum[66];
+    __shared__ double vals[kNQ + 66];
 
     // which replicas take part in this phase (uniform per block)
     bool take;
     switch (phase) {
-    case PH_TARGET: take = true; break;
     case PH_Q: case PH_EVAL0: case PH_TRIAL: case PH_SCALES: take = S.active != 0; break;
-    case PH_BEGIN: take = true; break;
     default: take = true; break;
     }
     if (!take) return;
-
-    int nslots = 0;
-    switch (phase) {
-    case PH_TARGET: nslots = 6; break;
-    case PH_EVAL0: case PH_TRIAL: nslots = 4; break;
-    case PH_BEGIN: nslots = 2; break;
-    case PH_SOLVENT: nslots = 1; break;
-    default: nslots = 0; break;
-    }
     if (phase == PH_BEGIN && !S.pending) {
-        if (threadIdx.x == 0) S.accepted = 0;
+        if (threadIdx.x == 0) st[r].accepted = 0;
         return;
     }
-    for (int q = 0; q < nslots; ++q) {
-        const double t = reduce_range(part, b0, b1, kNQ, q);
-        if (threadIdx.x == 0) red[q] = t;
+
+    // rows to reduce: nslots slots of `part`, then ng rows of `partG` starting at g_first
+    int nslots = 0, g_first = 0, ng = 0;
+    switch (phase) {
+    case PH_TARGET: nslots = 6; break;
+    case PH_EVAL0: case PH_TRIAL: nslots = 4; ng = ch.N + 2; break;
+    case PH_SCALES: ng = ch.N + 2; break;
+    case PH_Q: g_first = ch.N - 1; ng = 1; break;
+    case PH_BEGIN: nslots = 2; break;
+    case PH_SOLVENT: nslots = 1; break;
+    default: break;
     }
-    const bool want_g = phase == PH_Q || phase == PH_EVAL0 || phase == PH_TRIAL || phase == PH_SCALES;
-    if (want_g) {
-        for (int s = 0; s < ch.N + 2; ++s) {
-            const double t = reduce_range(partG + (long long)s * nblocks, b0, b1, 1, 0);
-            if (threadIdx.x == 0) gsum[s] = t;
+    // one row per wavefront at a time: lanes stride over the replica's blocks, then a
+    // fixed shuffle tree; the order of additions is fixed, so results are reproducible
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int row = wid; row < nslots + ng; row += kBlock / 64) {
+        double v = 0.0;
+        if (row < nslots) {
+            for (int b = b0 + lane; b < b1; b += 64) v += part[(long long)b * kNQ + row];
+        } else {
+            const double *base = partG + (long long)(g_first + row - nslots) * nblocks;
+            for (int b = b0 + lane; b < b1; b += 64) v += base[b];
         }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (lane == 0) vals[row] = v;
     }
-    if (threadIdx.x != 0) return;
+    __syncthreads();
+    const double *red = vals;
+    const double *gsum = vals + nslots - g_first;   // gsum[s] = sum of stored G_{s+1}
+    if (threadIdx.x == 0) control(S, phase, ch, red, gsum, V, rep[r].csum, tol, max_iter);
+    __syncthreads();
+    {
+        const int *src = reinterpret_cast<const int *>(&S);
+        int *dst = reinterpret_cast<int *>(&st[r]);
+        for (int k = threadIdx.x; k < (int)(sizeof(RepState) / 4); k += kBlock) dst[k] = src[k];
+    }
+}
+
+// Scalar logic of one replica after the reductions of a phase (runs in one thread).
+__device__ void control(RepState &S, int phase, const Chain &ch, const double *red, const double *gsum,
+                        double V, double csum, double tol, int max_iter)
+{
 
     switch (phase) {
     case PH_Q: {
@@ -133,10 +156,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce_ctl(const int *__restrict__ b
         S.res = INFINITY;
         break;
     }
-    case PH_SCALES: update_scales(S, ch, gsum, V, rep[r].csum); break;
+    case PH_SCALES: update_scales(S, ch, gsum, V, csum); break;
     case PH_SOLVENT: S.sol_mean = red[0] / V; break;
     case PH_EVAL0: {
-        update_scales(S, ch, gsum, V, rep[r].csum);
+        update_scales(S, ch, gsum, V, csum);
         S.evals += 1;
         S.gg = red[1];
         S.res = fmax(sqrt(red[2] / S.tnorm2[0]), sqrt(red[3] / S.tnorm2[1]));
@@ -172,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_ctl(const int *__restrict__ b
         break;
     }
     case PH_TRIAL: {
-        update_scales(S, ch, gsum, V, rep[r].csum);
+        update_scales(S, ch, gsum, V, csum);
         S.evals += 1;
         const double h = red[0];
         bool accept = fabs(h) <= 0.1 * fabs(S.h0) || S.trial >= 3;

@@ -3,6 +3,7 @@
 //   D3Q19 lattice Boltzmann, moments (eq. 9), equilibrium (eq. 11), single-relaxation
 //   collision L_ij = -delta_ij / tau with its forcing term, collide then stream (eq. 10);
 //   conservative convection-diffusion update (eq. 3).
+#include <hip/hip_ext.h>
 #include <math.h>
 
 #include "device_common.h"
@@ -207,17 +208,25 @@ void launch_force(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const 
 }
 
 void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc, double *ndst, const double *f,
-               double *rho, double *u)
+               double *rho, double *u, hipEvent_t e0, hipEvent_t e1)
 {
-    hipLaunchKernelGGL(k_lb, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, nsrc, ndst, f,
-                       rho, u);
+    if (e0)
+        hipExtLaunchKernelGGL(k_lb, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep,
+                              nsrc, ndst, f, rho, u);
+    else
+        hipLaunchKernelGGL(k_lb, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, nsrc, ndst, f,
+                           rho, u);
 }
 
 void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi, const double *mu,
-               const double *u, double *phi_out)
+               const double *u, double *phi_out, hipEvent_t e0, hipEvent_t e1)
 {
-    hipLaunchKernelGGL(k_cd, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch, phi, mu, u,
-                       phi_out);
+    if (e0)
+        hipExtLaunchKernelGGL(k_cd, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep,
+                              ch, phi, mu, u, phi_out);
+    else
+        hipLaunchKernelGGL(k_cd, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch, phi, mu, u,
+                           phi_out);
 }
 
 void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n)

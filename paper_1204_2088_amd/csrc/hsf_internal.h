@@ -72,18 +72,6 @@ struct PropBufs {
     real *Gp[2];    // [rep][V] x 2  ping-pong backward propagators
 };
 
-template <typename real>
-void launch_prep(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
-                 const double *w, const double *d, int use_alpha, PropBufs<real> b, double *acc,
-                 double *partG);
-template <typename real>
-void launch_fwd(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int step,
-                PropBufs<real> b, double *partG);
-template <typename real>
-void launch_bwd(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int step,
-                PropBufs<real> b, double *acc, int final_mode, const double *phit, const double *d,
-                double *out, double *part);
-
 // reductions and control
 enum Phase {
     PH_Q = 0,        // Q of the forward sweep (partials slot 0 of the G_N step)
@@ -116,9 +104,10 @@ void launch_mu(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const dou
 void launch_force(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi,
                   const double *mu, double *f);
 void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc, double *ndst,
-               const double *f, double *rho, double *u);
+               const double *f, double *rho, double *u, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi,
-               const double *mu, const double *u, double *phi_out);
+               const double *mu, const double *u, double *phi_out, hipEvent_t e0 = nullptr,
+               hipEvent_t e1 = nullptr);
 void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n);
 
 }  // namespace hsf

@@ -1,0 +1,43 @@
+// prop_block.h -- tile configurations of the temporally blocked propagator kernels.
+#pragma once
+
+#include "hsf_internal.h"
+
+namespace hsf {
+
+// Core tile (cx, cy, cz) and contour steps per launch (k).
+struct TileCfg {
+    int cx, cy, cz, k;
+};
+
+// The instantiated configurations (X(cx, cy, cz, k)); the autotuner picks one per context.
+#define HSF_TILE_CONFIGS(X) \
+    X(8, 8, 8, 1)           \
+    X(8, 8, 8, 2)           \
+    X(8, 8, 8, 3)           \
+    X(8, 8, 8, 4)           \
+    X(16, 8, 8, 2)          \
+    X(16, 8, 4, 2)          \
+    X(32, 8, 4, 1)          \
+    X(32, 4, 4, 2)
+
+// Bytes of LDS a configuration needs (two staged regions + FP64 core accumulators).
+inline size_t tile_lds_bytes(const TileCfg &t, size_t real_bytes)
+{
+    const size_t nr = (size_t)(t.cx + 2 * t.k) * (t.cy + 2 * t.k) * (t.cz + 2 * t.k);
+    return 2 * nr * real_bytes + 2 * (size_t)t.cx * t.cy * t.cz * sizeof(double);
+}
+
+template <typename real>
+void launch_field_exp(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, const double *w,
+                      const double *d, int use_alpha, real *E, hipEvent_t e0, hipEvent_t e1);
+template <typename real>
+void launch_fwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
+                      int s0, int n, PropBufs<real> b, double *partG, hipEvent_t e0, hipEvent_t e1);
+template <typename real>
+void launch_bwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
+                      int s_hi, int n, PropBufs<real> b, const real *gin, real *gout, double *acc, int final_mode,
+                      const double *phit, const double *d, double *out, double *part, hipEvent_t e0,
+                      hipEvent_t e1);
+
+}  // namespace hsf

@@ -1,0 +1,402 @@
+// prop_block.hip -- temporally blocked propagator sweeps (eq. 16-17).
+//
+// One launch advances K contour steps.  Each block owns a core tile of
+// CX x CY x CZ sites and stages the propagator on the core plus a halo of K
+// sites per side in LDS; level k (k = 1..K) applies the 27-point linkage
+// stencil on the region that shrinks by one site per side per level, so the
+// core after K levels is exact.  Every level writes its core to the global
+// store G_s (forward) or adds G_s sigma[G+_{s+1}] into per-core accumulators
+// (backward); the next launch starts from the stored core planes.  Halo sites
+// are recomputed by neighbouring blocks (the price of fewer launches).
+//
+// Scaling: stored G_s = G_s / 2^(e_1+..+e_s), stored G+_s = G+_s 2^(e_1+..+e_{s-1}) /
+// 2^(e_1+..+e_N): the same per-step power of two divides both sweeps, so every
+// product G_s sigma[G+_{s+1}] carries one common factor that cancels in phi.
+#include <hip/hip_ext.h>
+
+#include "device_common.h"
+#include "prop_block.h"
+
+namespace hsf {
+
+template <typename real>
+__device__ __forceinline__ real pow2_neg_b(int e)
+{
+    return (real)ldexp(1.0, -e);
+}
+
+__device__ __forceinline__ int wrapn(int v, int L)
+{
+    v %= L;
+    return v < 0 ? v + L : v;
+}
+
+// Tile of this block: replica, core origin, and per-axis global offsets of the region.
+template <int CX, int CY, int CZ, int K>
+struct TileCtx {
+    static constexpr int NX = CX + 2 * K, NY = CY + 2 * K, NZ = CZ + 2 * K;
+    int r;
+    int x0, y0, z0;
+};
+
+// Region of level k: positions [k, N - k) per axis in region coordinates.
+template <int CX, int CY, int CZ, int K, typename F>
+__device__ __forceinline__ void for_region(int k, F &&f)
+{
+    constexpr int NX = CX + 2 * K, NY = CY + 2 * K, NZ = CZ + 2 * K;
+    const int mx = NX - 2 * k, my = NY - 2 * k, mz = NZ - 2 * k;
+    const int m = mx * my * mz;
+    for (int t = threadIdx.x; t < m; t += kBlock) {
+        const int px = k + t % mx;
+        const int rest = t / mx;
+        const int py = k + rest % my;
+        const int pz = k + rest / my;
+        f(px, py, pz);
+    }
+}
+
+template <typename real, int NX, int NY>
+__device__ __forceinline__ real stencil_lds(const real *buf, int px, int py, int pz, real c0, real c1, real c2,
+                                            real c3)
+{
+    constexpr int SY = NX, SZ = NX * NY;
+    const real *p = buf + pz * SZ + py * SY + px;
+    auto row = [&](int off, real &ctr, real &side) {
+        ctr = p[off];
+        side = p[off - 1] + p[off + 1];
+    };
+    real a, s, s0, s1, s2, s3;
+    row(0, a, s);
+    s0 = a;
+    s1 = s;
+    s2 = 0;
+    s3 = 0;
+    row(-SY, a, s); s1 += a; s2 += s;
+    row(SY, a, s); s1 += a; s2 += s;
+    row(-SZ, a, s); s1 += a; s2 += s;
+    row(SZ, a, s); s1 += a; s2 += s;
+    row(-SY - SZ, a, s); s2 += a; s3 += s;
+    row(-SY + SZ, a, s); s2 += a; s3 += s;
+    row(SY - SZ, a, s); s2 += a; s3 += s;
+    row(SY + SZ, a, s); s2 += a; s3 += s;
+    return c0 * s0 + c1 * s1 + c2 * s2 + c3 * s3;
+}
+
+// Decode the tile of this block from the tile plan.
+template <int CX, int CY, int CZ>
+__device__ __forceinline__ bool tile_of(const int *blk_rep, const int *blk_first, const Rep *rep, int &r, int &x0,
+                                        int &y0, int &z0)
+{
+    r = blk_rep[blockIdx.x];
+    const Rep &R = rep[r];
+    const int ntx = (R.Lx + CX - 1) / CX, nty = (R.Ly + CY - 1) / CY;
+    int lb = blockIdx.x - blk_first[r];
+    x0 = (lb % ntx) * CX;
+    lb /= ntx;
+    y0 = (lb % nty) * CY;
+    z0 = (lb / nty) * CZ;
+    return true;
+}
+
+// Per-axis site offsets of the region positions (global index = ox[px] + oy[py] + oz[pz]).
+template <int NX, int NY, int NZ>
+__device__ __forceinline__ void region_offsets(const Rep &R, int x0, int y0, int z0, int K, int *ox, int *oy,
+                                               int *oz)
+{
+    for (int t = threadIdx.x; t < NX + NY + NZ; t += kBlock) {
+        if (t < NX) ox[t] = wrapn(x0 - K + t, R.Lx);
+        else if (t < NX + NY) oy[t - NX] = wrapn(y0 - K + (t - NX), R.Ly) * R.Lx;
+        else oz[t - NX - NY] = wrapn(z0 - K + (t - NX - NY), R.Lz) * R.Lx * R.Ly;
+    }
+}
+
+// Forward sweep, steps s0+1 .. s0+nsteps (nsteps <= K).  G_{s0} is read from the
+// store (G_0 = 1 when s0 = 0).  Partial sums per block: stored G_s over the core
+// (rows s-1 of partG) and, when s0 = 0, E_A and E_B over the core (rows N, N+1).
+template <typename real, int CX, int CY, int CZ, int K>
+__global__ __launch_bounds__(kBlock) void k_fwd_block(const int *__restrict__ blk_rep,
+                                                      const int *__restrict__ blk_first,
+                                                      const Rep *__restrict__ rep,
+                                                      const RepState *__restrict__ st, Chain ch, int s0,
+                                                      int nsteps, PropBufs<real> b, double *__restrict__ partG,
+                                                      int nblocks)
+{
+    constexpr int NX = CX + 2 * K, NY = CY + 2 * K, NZ = CZ + 2 * K, NR = NX * NY * NZ;
+    __shared__ real buf[2][NR];
+    __shared__ int ox[NX], oy[NY], oz[NZ];
+    int r, x0, y0, z0;
+    tile_of<CX, CY, CZ>(blk_rep, blk_first, rep, r, x0, y0, z0);
+    if (!st[r].active) return;
+    const Rep &R = rep[r];
+    const int V = (int)R.V;
+    region_offsets<NX, NY, NZ>(R, x0, y0, z0, K, ox, oy, oz);
+    const real c0 = (real)R.c[0], c1 = (real)R.c[1], c2 = (real)R.c[2], c3 = (real)R.c[3];
+    real *G = b.G + (long long)ch.N * R.site_off;
+    const real *E = b.E + off_poly(R);
+    __syncthreads();
+    // stage G_{s0} on the full region
+    if (s0 == 0) {
+        for (int t = threadIdx.x; t < NR; t += kBlock) buf[0][t] = (real)1;
+    } else {
+        const real *src = G + (long long)(s0 - 1) * V;
+        for (int t = threadIdx.x; t < NR; t += kBlock) {
+            const int px = t % NX, py = (t / NX) % NY, pz = t / (NX * NY);
+            buf[0][t] = src[ox[px] + oy[py] + oz[pz]];
+        }
+    }
+    __syncthreads();
+    const int cx1 = min(CX, R.Lx - x0), cy1 = min(CY, R.Ly - y0), cz1 = min(CZ, R.Lz - z0);
+    double esum[2] = {0.0, 0.0};
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+        if (k > nsteps) break;
+        const int s = s0 + k;
+        const real *Et = E + ch.types[s - 1] * V;
+        const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
+        const real *in = buf[(k - 1) & 1];
+        real *out = buf[k & 1];
+        double gsum = 0.0;
+        for_region<CX, CY, CZ, K>(k, [&](int px, int py, int pz) {
+            const int site = ox[px] + oy[py] + oz[pz];
+            const real S = stencil_lds<real, NX, NY>(in, px, py, pz, c0, c1, c2, c3);
+            const real g = Et[site] * S * sc;
+            out[pz * NX * NY + py * NX + px] = g;
+            const int qx = px - K, qy = py - K, qz = pz - K;
+            if (qx >= 0 && qx < cx1 && qy >= 0 && qy < cy1 && qz >= 0 && qz < cz1) {
+                G[(long long)(s - 1) * V + site] = g;
+                gsum += (double)g;
+                if (s == 1) {
+                    esum[0] += (double)E[site];
+                    esum[1] += (double)E[V + site];
+                }
+            }
+        });
+        const double t = block_sum(gsum);   // contains __syncthreads: the level is complete
+        if (threadIdx.x == 0) partG[(long long)(s - 1) * nblocks + blockIdx.x] = t;
+    }
+    if (s0 == 0) {
+        double t = block_sum(esum[0]);
+        if (threadIdx.x == 0) partG[(long long)ch.N * nblocks + blockIdx.x] = t;
+        t = block_sum(esum[1]);
+        if (threadIdx.x == 0) partG[(long long)(ch.N + 1) * nblocks + blockIdx.x] = t;
+    }
+}
+
+// Backward sweep, steps s_hi down to s_hi - nsteps + 1.  G+_{s_hi+1} is read from
+// the ping-pong plane gin (G+_{N+1} = 1).  Accumulates G_s sigma[G+_{s+1}] per
+// core site and species in LDS, then adds them to acc (or sets acc for the
+// first launch).  The launch that reaches s = 1 normalises the densities:
+// final_mode 0 writes phi (field layout), final_mode 1 writes g = phi^t - phi
+// (polymer layout) with block partial sums d.g, g.g, |g_A|^2, |g_B|^2.
+template <typename real, int CX, int CY, int CZ, int K>
+__global__ __launch_bounds__(kBlock) void k_bwd_block(const int *__restrict__ blk_rep,
+                                                      const int *__restrict__ blk_first,
+                                                      const Rep *__restrict__ rep,
+                                                      const RepState *__restrict__ st, Chain ch, int s_hi,
+                                                      int nsteps, PropBufs<real> b, const real *__restrict__ gin,
+                                                      real *__restrict__ gout, double *__restrict__ acc,
+                                                      int final_mode, const double *__restrict__ phit,
+                                                      const double *__restrict__ d, double *__restrict__ out,
+                                                      double *__restrict__ part)
+{
+    constexpr int NX = CX + 2 * K, NY = CY + 2 * K, NZ = CZ + 2 * K, NR = NX * NY * NZ;
+    constexpr int NC = CX * CY * CZ;
+    __shared__ real buf[2][NR];
+    __shared__ double accl[2][NC];
+    __shared__ int ox[NX], oy[NY], oz[NZ];
+    int r, x0, y0, z0;
+    tile_of<CX, CY, CZ>(blk_rep, blk_first, rep, r, x0, y0, z0);
+    if (!st[r].active) return;
+    const Rep &R = rep[r];
+    const int V = (int)R.V;
+    const int N = ch.N;
+    region_offsets<NX, NY, NZ>(R, x0, y0, z0, K, ox, oy, oz);
+    const real c0 = (real)R.c[0], c1 = (real)R.c[1], c2 = (real)R.c[2], c3 = (real)R.c[3];
+    const real *G = b.G + (long long)N * R.site_off;
+    const real *E = b.E + off_poly(R);
+    for (int t = threadIdx.x; t < 2 * NC; t += kBlock) (&accl[0][0])[t] = 0.0;
+    __syncthreads();
+    if (s_hi == N) {
+        for (int t = threadIdx.x; t < NR; t += kBlock) buf[0][t] = (real)1;
+    } else {
+        const real *src = gin + R.site_off;
+        for (int t = threadIdx.x; t < NR; t += kBlock) {
+            const int px = t % NX, py = (t / NX) % NY, pz = t / (NX * NY);
+            buf[0][t] = src[ox[px] + oy[py] + oz[pz]];
+        }
+    }
+    __syncthreads();
+    const int cx1 = min(CX, R.Lx - x0), cy1 = min(CY, R.Ly - y0), cz1 = min(CZ, R.Lz - z0);
+    int last_k = 0;
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+        if (k > nsteps) break;
+        last_k = k;
+        const int s = s_hi - k + 1;
+        const int ts = ch.types[s - 1];
+        const real *Et = E + ts * V;
+        const real *Gs = G + (long long)(s - 1) * V;
+        const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
+        const real *in = buf[(k - 1) & 1];
+        real *o = buf[k & 1];
+        for_region<CX, CY, CZ, K>(k, [&](int px, int py, int pz) {
+            const int site = ox[px] + oy[py] + oz[pz];
+            const real S = stencil_lds<real, NX, NY>(in, px, py, pz, c0, c1, c2, c3);
+            if (s > 1) o[pz * NX * NY + py * NX + px] = Et[site] * S * sc;
+            const int qx = px - K, qy = py - K, qz = pz - K;
+            if (qx >= 0 && qx < CX && qy >= 0 && qy < CY && qz >= 0 && qz < CZ)
+                accl[ts][(qz * CY + qy) * CX + qx] += (double)Gs[site] * (double)S;
+        });
+        __syncthreads();
+    }
+    const int s_lo = s_hi - last_k + 1;
+    // core outputs: G+_{s_lo} for the next launch, accumulators, final densities
+    const real *fin = buf[last_k & 1];
+    const long long fo = off_field(R, ch.nsp), po = off_poly(R);
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};
+    const double coef = st[r].phibar_p / ((double)N * st[r].q);
+    for (int t = threadIdx.x; t < NC; t += kBlock) {
+        const int qx = t % CX, qy = (t / CX) % CY, qz = t / (CX * CY);
+        if (qx >= cx1 || qy >= cy1 || qz >= cz1) continue;
+        const int px = qx + K, py = qy + K, pz = qz + K;
+        const int site = ox[px] + oy[py] + oz[pz];
+        if (s_lo > 1) gout[R.site_off + site] = fin[pz * NX * NY + py * NX + px];
+        double a[2] = {accl[0][t], accl[1][t]};
+        if (s_hi != N) {
+            a[0] += acc[po + site];
+            a[1] += acc[po + V + site];
+        }
+        if (s_lo > 1) {
+            acc[po + site] = a[0];
+            acc[po + V + site] = a[1];
+        } else {
+#pragma unroll
+            for (int I = 0; I < 2; ++I) {
+                const double ph = coef * a[I];
+                if (final_mode == 0) {
+                    out[fo + (long long)I * V + site] = ph;
+                } else {
+                    const double gI = phit[fo + (long long)I * V + site] - ph;
+                    out[po + (long long)I * V + site] = gI;
+                    if (d) sums[0] += d[po + (long long)I * V + site] * gI;
+                    sums[1] += gI * gI;
+                    sums[2 + I] += gI * gI;
+                }
+            }
+        }
+    }
+    if (s_lo == 1 && final_mode == 1) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double t = block_sum(sums[q]);
+            if (threadIdx.x == 0) part[(long long)blockIdx.x * kNQ + q] = t;
+        }
+    }
+}
+
+// E = exp(-(w + alpha d)) of the polymer species, all sites of the active replicas.
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_field_exp(const int *__restrict__ blk_rep,
+                                                      const int *__restrict__ blk_first,
+                                                      const Rep *__restrict__ rep,
+                                                      const RepState *__restrict__ st, Chain ch,
+                                                      const double *__restrict__ w, const double *__restrict__ d,
+                                                      int use_alpha, real *__restrict__ E)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    if (!st[sr.r].active) return;
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    if (i >= V) return;
+    const long long fo = off_field(R, ch.nsp), po = off_poly(R);
+    const double alpha = st[sr.r].alpha;
+#pragma unroll
+    for (int I = 0; I < 2; ++I) {
+        double x = w[fo + I * V + i];
+        if (use_alpha) x = fma(alpha, d[po + I * V + i], x);
+        E[po + I * V + i] = (real)exp(-x);
+    }
+}
+
+// ---- launchers ---------------------------------------------------------------------
+
+template <typename real, int CX, int CY, int CZ, int K>
+struct BlockKernels {
+    static void fwd(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int s0, int n,
+                    PropBufs<real> b, double *partG, hipEvent_t e0, hipEvent_t e1)
+    {
+        if (e0)
+            hipExtLaunchKernelGGL((k_fwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1,
+                                  0, p.blk_rep, p.blk_first, rep, st, ch, s0, n, b, partG, p.nblocks);
+        else
+            hipLaunchKernelGGL((k_fwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep,
+                               p.blk_first, rep, st, ch, s0, n, b, partG, p.nblocks);
+    }
+    static void bwd(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int s_hi, int n,
+                    PropBufs<real> b, const real *gin, real *gout, double *acc, int final_mode, const double *phit,
+                    const double *d, double *out, double *part, hipEvent_t e0, hipEvent_t e1)
+    {
+        if (e0)
+            hipExtLaunchKernelGGL((k_bwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1,
+                                  0, p.blk_rep, p.blk_first, rep, st, ch, s_hi, n, b, gin, gout, acc, final_mode,
+                                  phit, d, out, part);
+        else
+            hipLaunchKernelGGL((k_bwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep,
+                               p.blk_first, rep, st, ch, s_hi, n, b, gin, gout, acc, final_mode, phit, d, out,
+                               part);
+    }
+};
+
+template <typename real>
+void launch_field_exp(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, const double *w,
+                      const double *d, int use_alpha, real *E, hipEvent_t e0, hipEvent_t e1)
+{
+    if (e0)
+        hipExtLaunchKernelGGL(k_field_exp<real>, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep,
+                              p.blk_first, rep, st, ch, w, d, use_alpha, E);
+    else
+        hipLaunchKernelGGL(k_field_exp<real>, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st,
+                           ch, w, d, use_alpha, E);
+}
+
+template <typename real>
+void launch_fwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
+                      int s0, int n, PropBufs<real> b, double *partG, hipEvent_t e0, hipEvent_t e1)
+{
+#define HSF_CASE(CX, CY, CZ, K)                                                                   \
+    if (cfg.cx == CX && cfg.cy == CY && cfg.cz == CZ && cfg.k == K)                               \
+        return BlockKernels<real, CX, CY, CZ, K>::fwd(s, p, rep, st, ch, s0, n, b, partG, e0, e1);
+    HSF_TILE_CONFIGS(HSF_CASE)
+#undef HSF_CASE
+}
+
+template <typename real>
+void launch_bwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
+                      int s_hi, int n, PropBufs<real> b, const real *gin, real *gout, double *acc, int final_mode,
+                      const double *phit, const double *d, double *out, double *part, hipEvent_t e0,
+                      hipEvent_t e1)
+{
+#define HSF_CASE(CX, CY, CZ, K)                                                                        \
+    if (cfg.cx == CX && cfg.cy == CY && cfg.cz == CZ && cfg.k == K)                                    \
+        return BlockKernels<real, CX, CY, CZ, K>::bwd(s, p, rep, st, ch, s_hi, n, b, gin, gout, acc,       \
+                                                      final_mode, phit, d, out, part, e0, e1);
+    HSF_TILE_CONFIGS(HSF_CASE)
+#undef HSF_CASE
+}
+
+#define HSF_INST(real)                                                                                    \
+    template void launch_field_exp<real>(hipStream_t, const Plan &, const Rep *, RepState *, Chain,       \
+                                         const double *, const double *, int, real *, hipEvent_t,         \
+                                         hipEvent_t);                                                     \
+    template void launch_fwd_block<real>(const TileCfg &, hipStream_t, const Plan &, const Rep *,         \
+                                         RepState *, Chain, int, int, PropBufs<real>, double *,           \
+                                         hipEvent_t, hipEvent_t);                                         \
+    template void launch_bwd_block<real>(const TileCfg &, hipStream_t, const Plan &, const Rep *,         \
+                                         RepState *, Chain, int, int, PropBufs<real>, const real *,       \
+                                         real *, double *, int, const double *, const double *, double *, \
+                                         double *, hipEvent_t, hipEvent_t);
+HSF_INST(double)
+HSF_INST(float)
+#undef HSF_INST
+
+}  // namespace hsf

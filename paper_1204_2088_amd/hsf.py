@@ -30,7 +30,7 @@ EXPORTED = [
     "hsf_site_offset", "hsf_field_offset", "hsf_num_species", "hsf_set_fields", "hsf_get_fields",
     "hsf_set_densities", "hsf_get_densities", "hsf_evaluate", "hsf_invert", "hsf_mu_force",
     "hsf_set_lb", "hsf_get_lb", "hsf_lb_advance", "hsf_get_flow", "hsf_cd_advance", "hsf_step",
-    "hsf_set_hydro", "hsf_set_timing", "hsf_get_timing",
+    "hsf_set_hydro", "hsf_set_timing", "hsf_get_timing", "hsf_set_tile", "hsf_get_tile", "hsf_autotune",
 ]
 K_PREP, K_FWD, K_BWD, K_LB, K_CD, K_COUNT = 0, 1, 2, 3, 4, 5
 KERNEL_NAMES = ["prep", "fwd", "bwd", "lb", "cd"]
@@ -104,6 +104,9 @@ def load():
                       ctypes.POINTER(ctypes.c_longlong)], I),
         "hsf_set_hydro": ([C, I], I),
         "hsf_set_timing": ([C, I], I),
+        "hsf_set_tile": ([C, ctypes.POINTER(ctypes.c_int)], I),
+        "hsf_get_tile": ([C, ctypes.POINTER(ctypes.c_int)], I),
+        "hsf_autotune": ([C, I, ctypes.POINTER(ctypes.c_double)], I),
         "hsf_get_timing": ([C, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)], I),
     }
     for name, (args, res) in sig.items():
@@ -285,6 +288,21 @@ class Context:
 
     def set_hydro(self, on):
         self._check(self._lib.hsf_set_hydro(self._h, int(bool(on))))
+
+    def set_tile(self, cfg):
+        arr = (ctypes.c_int * 4)(*[int(v) for v in cfg])
+        self._check(self._lib.hsf_set_tile(self._h, arr))
+
+    def get_tile(self):
+        arr = (ctypes.c_int * 4)()
+        self._check(self._lib.hsf_get_tile(self._h, arr))
+        return tuple(arr[:])
+
+    def autotune(self, reps=3):
+        """Pick the fastest propagator tiling for this context; returns (cfg, ms per evaluation)."""
+        ms = ctypes.c_double(0.0)
+        self._check(self._lib.hsf_autotune(self._h, int(reps), ctypes.byref(ms)))
+        return self.get_tile(), ms.value
 
     def set_timing(self, on):
         self._check(self._lib.hsf_set_timing(self._h, int(bool(on))))
