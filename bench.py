@@ -143,10 +143,12 @@ def main():
         if prop:
             dom = max(prop, key=lambda k: prop[k]["total_ms"])
             avg_s = prop[dom]["avg_us"] * 1e-6
-            achieved = b_unit * V / avg_s / 1e9
+            steps_per_launch = max(1, tile[3])
+            units = V * steps_per_launch * ctx.n_rep
+            achieved = b_unit * units / avg_s / 1e9
             roofline = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                        "bytes_per_update": b_unit, "updates_per_launch": V}
+                        "bytes_per_update": b_unit, "updates_per_launch": units}
 
     cpu = None
     if not args.no_cpu_baseline:

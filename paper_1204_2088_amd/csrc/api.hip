@@ -279,6 +279,8 @@ int set_tile(hsf_ctx *c, const TileCfg &t)
     HIPCHK(c, hipMemcpy(c->tplan.blk_rep, br.data(), sizeof(int) * br.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->tplan.blk_first, bf.data(), sizeof(int) * bf.size(), hipMemcpyHostToDevice));
     c->tplan.nblocks = (int)br.size();
+    c->tplan.n_rep = c->n_rep;
+    c->tplan.rep0 = c->reps[0];
     c->tile = t;
     for (auto &g : c->graphs)
         if (g.exec) {
@@ -294,10 +296,10 @@ int set_tile(hsf_ctx *c, const TileCfg &t)
 // Launches: exp of the fields, ceil(N/K) forward launches, the Q reduction,
 // ceil(N/K) backward launches (the last one normalises).
 template <typename real>
-void run_eval(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d)
+void run_eval(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d, int sums)
 {
     PropBufs<real> b = bufs<real>(c);
-    const int N = c->ch.N, K = c->tile.k;
+    const int N = c->ch.N, K = std::max(1, c->tile.k);
     {
         Timed t(c, HSF_K_PREP);
         launch_field_exp<real>(c->stream, c->plan, c->rep_d, c->st_d, c->ch, c->w, c->d, use_alpha, b.E, t.a, t.b);
@@ -305,7 +307,7 @@ void run_eval(hsf_ctx *c, int use_alpha, int final_mode, double *out, const doub
     for (int s0 = 0; s0 < N; s0 += K) {
         Timed t(c, HSF_K_FWD);
         launch_fwd_block<real>(c->tile, c->stream, c->tplan, c->rep_d, c->st_d, c->ch, s0, std::min(K, N - s0), b,
-                               c->partG, t.a, t.b);
+                               c->partG, sums, t.a, t.b);
     }
     launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_Q, c->ch, c->partG, 0.0, 0);
     int parity = 0;
@@ -319,12 +321,13 @@ void run_eval(hsf_ctx *c, int use_alpha, int final_mode, double *out, const doub
     }
 }
 
-void run_eval_any(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d)
+// sums: also produce the per-step propagator sums that update the FP32 scales
+void run_eval_any(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d, int sums)
 {
     if (c->precision == HSF_FP32)
-        run_eval<float>(c, use_alpha, final_mode, out, d);
+        run_eval<float>(c, use_alpha, final_mode, out, d, sums);
     else
-        run_eval<double>(c, use_alpha, final_mode, out, d);
+        run_eval<double>(c, use_alpha, final_mode, out, d, sums);
 }
 
 void target_setup(hsf_ctx *c, double tol, int max_iter)
@@ -347,7 +350,7 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
     c->fields_set = 1;
     // starting point: evaluation, residual, first direction, first alpha
     int rc = run_seq(c, hsf_ctx::GK_START, [&] {
-        run_eval_any(c, 0, 1, c->g, nullptr);
+        run_eval_any(c, 0, 1, c->g, nullptr, 1);
         launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_EVAL0, c->ch, c->partG,
                           0.0, 0);
         launch_cg_update(c->stream, c->plan, c->rep_d, c->st_d, c->ch, 1, c->w, c->g, c->gt, c->d, c->phi,
@@ -365,7 +368,7 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
     while (any) {
         if (--guard < 0) return fail(c, HSF_EHIP, "inversion control did not progress");
         rc = run_seq(c, hsf_ctx::GK_TRIAL, [&] {
-            run_eval_any(c, 1, 1, c->gt, c->d);
+            run_eval_any(c, 1, 1, c->gt, c->d, 0);
             launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_TRIAL, c->ch,
                               c->partG, 0.0, 0);
         });
@@ -471,6 +474,8 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     blk_first.push_back((int)blk_rep.size());
     c->T = off;
     c->plan.nblocks = (int)blk_rep.size();
+    c->plan.n_rep = n_rep;
+    c->plan.rep0 = c->reps[0];
     {
         std::vector<int> br, bf;
 #define HSF_SIZE(CX, CY, CZ, K)                                             \
@@ -652,7 +657,7 @@ int hsf_evaluate(hsf_ctx *c, double *phi_out, double *Q_out, int where)
     for (int attempt = 0; attempt < 4; ++attempt) {
         int rc0 = run_seq(c, hsf_ctx::GK_EVAL, [&] {
             target_setup(c, 0.0, 0);   // phibar_p, phibar_s from the current densities; all replicas active
-            run_eval_any(c, 0, 0, c->eval_out, nullptr);
+            run_eval_any(c, 0, 0, c->eval_out, nullptr, 1);
             launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_SCALES, c->ch,
                               c->partG, 0.0, 0);
         });
@@ -844,13 +849,29 @@ int hsf_autotune(hsf_ctx *c, int reps, double *best_ms)
     for (const TileCfg &t : cands) {
         if (tile_lds_bytes(t, real_size(c)) > c->lds_limit) continue;
         if ((rc = set_tile(c, t)) != HSF_OK) break;
-        // one evaluation per timing: exp, sweeps, Q, normalisation (state untouched)
+        // `reps` evaluations (exp, sweeps, Q, normalisation; state untouched), captured in a
+        // graph and replayed as the inversion replays them
         target_setup(c, 0.0, 0);
-        run_eval_any(c, 0, 0, c->eval_out, nullptr);
-        (void)hipEventRecord(e0, c->stream);
-        for (int k = 0; k < reps; ++k) run_eval_any(c, 0, 0, c->eval_out, nullptr);
-        (void)hipEventRecord(e1, c->stream);
-        hipError_t e = hipEventSynchronize(e1);
+        run_eval_any(c, 0, 0, c->eval_out, nullptr, 0);
+        hipStream_t user = c->stream;
+        if (!user && !c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipStream_t cs = user ? user : c->cap_stream;
+        HIPCHK(c, hipStreamSynchronize(user));
+        HIPCHK(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        c->stream = cs;
+        for (int k = 0; k < reps; ++k) run_eval_any(c, 0, 0, c->eval_out, nullptr, 0);
+        c->stream = user;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, c->stream);   // warm
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (exec) (void)hipGraphExecDestroy(exec);
         if (e != hipSuccess) {
             rc = fail(c, HSF_EHIP, "autotune: %s", hipGetErrorString(e));
             break;

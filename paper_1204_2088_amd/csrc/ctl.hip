@@ -19,6 +19,14 @@
 
 namespace hsf {
 
+// Nearest integer to log2(m), m > 0 finite, from the binary exponent.
+__device__ __forceinline__ long round_log2(double m)
+{
+    int e = 0;
+    const double f = frexp(m, &e);   // m = f 2^e, f in [0.5, 1)
+    return f < 0.70710678118654752440 ? e - 1 : e;
+}
+
 // Per-step power-of-two scales for the next evaluation.  sums[s] = sum_r of the
 // stored G_{s+1} of this evaluation (its mean m_s is relative to the cumulative
 // scale used), sums[N], sums[N+1] = sum_r E_A, E_B.  Target: stored means near 1.
@@ -32,10 +40,10 @@ __device__ void update_scales(RepState &S, const Chain &ch, const double *sums, 
         const double m = sums[s] / V;
         long target;
         if (m > 0.0 && isfinite(m)) {
-            target = cum_old + lrint(log2(m));
+            target = cum_old + round_log2(m);
         } else {
             const double me = sums[ch.N + ch.types[s]] / V * csum;
-            target = cum_new + ((me > 0.0 && isfinite(me)) ? lrint(log2(me)) : 0);
+            target = cum_new + ((me > 0.0 && isfinite(me)) ? round_log2(me) : 0);
         }
         long e = target - cum_new;
         if (e > 100) e = 100;
@@ -85,7 +93,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce_ctl(const int *__restrict__ b
     int nslots = 0, g_first = 0, ng = 0;
     switch (phase) {
     case PH_TARGET: nslots = 6; break;
-    case PH_EVAL0: case PH_TRIAL: nslots = 4; ng = ch.N + 2; break;
+    case PH_EVAL0: nslots = 4; ng = ch.N + 2; break;
+    case PH_TRIAL: nslots = 4; break;
     case PH_SCALES: ng = ch.N + 2; break;
     case PH_Q: g_first = ch.N - 1; ng = 1; break;
     case PH_BEGIN: nslots = 2; break;
@@ -195,7 +204,6 @@ __device__ void control(RepState &S, int phase, const Chain &ch, const double *r
         break;
     }
     case PH_TRIAL: {
-        update_scales(S, ch, gsum, V, csum);
         S.evals += 1;
         const double h = red[0];
         bool accept = fabs(h) <= 0.1 * fabs(S.h0) || S.trial >= 3;

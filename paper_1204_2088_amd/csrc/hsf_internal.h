@@ -49,6 +49,9 @@ struct Plan {
     int nblocks = 0;
     int *blk_rep = nullptr;      // device: replica of each block
     int *blk_first = nullptr;    // device: first block of each replica, n_rep + 1 entries
+    int n_rep = 0;
+    Rep rep0{};                  // replica 0 by value: kernels of a one-replica context read
+                                 // their geometry from the kernel arguments, not from memory
 };
 
 // Chain architecture passed by value to kernels.

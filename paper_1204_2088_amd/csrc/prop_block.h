@@ -5,13 +5,18 @@
 
 namespace hsf {
 
-// Core tile (cx, cy, cz) and contour steps per launch (k).
+// Core tile (cx, cy, cz) and contour steps per launch (k).  k = 0 selects the direct
+// kernels: one contour step per launch, neighbours read through the caches, a block
+// covers cx x cy sites of one plane (cz = 1, cx * cy = 256).
 struct TileCfg {
     int cx, cy, cz, k;
 };
 
 // The instantiated configurations (X(cx, cy, cz, k)); the autotuner picks one per context.
 #define HSF_TILE_CONFIGS(X) \
+    X(64, 4, 1, 0)          \
+    X(32, 8, 1, 0)          \
+    X(16, 16, 1, 0)         \
     X(8, 8, 8, 1)           \
     X(8, 8, 8, 2)           \
     X(8, 8, 8, 3)           \
@@ -24,6 +29,7 @@ struct TileCfg {
 // Bytes of LDS a configuration needs (two staged regions + FP64 core accumulators).
 inline size_t tile_lds_bytes(const TileCfg &t, size_t real_bytes)
 {
+    if (t.k == 0) return 0;
     const size_t nr = (size_t)(t.cx + 2 * t.k) * (t.cy + 2 * t.k) * (t.cz + 2 * t.k);
     return 2 * nr * real_bytes + 2 * (size_t)t.cx * t.cy * t.cz * sizeof(double);
 }
@@ -33,7 +39,7 @@ void launch_field_exp(hipStream_t s, const Plan &p, const Rep *rep, RepState *st
                       const double *d, int use_alpha, real *E, hipEvent_t e0, hipEvent_t e1);
 template <typename real>
 void launch_fwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
-                      int s0, int n, PropBufs<real> b, double *partG, hipEvent_t e0, hipEvent_t e1);
+                      int s0, int n, PropBufs<real> b, double *partG, int sums, hipEvent_t e0, hipEvent_t e1);
 template <typename real>
 void launch_bwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
                       int s_hi, int n, PropBufs<real> b, const real *gin, real *gout, double *acc, int final_mode,

@@ -111,15 +111,16 @@ __device__ __forceinline__ void region_offsets(const Rep &R, int x0, int y0, int
 }
 
 // Forward sweep, steps s0+1 .. s0+nsteps (nsteps <= K).  G_{s0} is read from the
-// store (G_0 = 1 when s0 = 0).  Partial sums per block: stored G_s over the core
-// (rows s-1 of partG) and, when s0 = 0, E_A and E_B over the core (rows N, N+1).
+// store (G_0 = 1 when s0 = 0).  Partial sums per block (when `sums` is set, for the
+// scale update): stored G_s over the core (rows s-1 of partG) and, when s0 = 0, E_A and
+// E_B over the core (rows N, N+1); the row of G_N (for Q) is always written.
 template <typename real, int CX, int CY, int CZ, int K>
 __global__ __launch_bounds__(kBlock) void k_fwd_block(const int *__restrict__ blk_rep,
                                                       const int *__restrict__ blk_first,
                                                       const Rep *__restrict__ rep,
                                                       const RepState *__restrict__ st, Chain ch, int s0,
                                                       int nsteps, PropBufs<real> b, double *__restrict__ partG,
-                                                      int nblocks)
+                                                      int nblocks, int sums)
 {
     constexpr int NX = CX + 2 * K, NY = CY + 2 * K, NZ = CZ + 2 * K, NR = NX * NY * NZ;
     __shared__ real buf[2][NR];
@@ -171,10 +172,14 @@ __global__ __launch_bounds__(kBlock) void k_fwd_block(const int *__restrict__ bl
                 }
             }
         });
-        const double t = block_sum(gsum);   // contains __syncthreads: the level is complete
-        if (threadIdx.x == 0) partG[(long long)(s - 1) * nblocks + blockIdx.x] = t;
+        if (sums || s == ch.N) {
+            const double t = block_sum(gsum);   // contains __syncthreads: the level is complete
+            if (threadIdx.x == 0) partG[(long long)(s - 1) * nblocks + blockIdx.x] = t;
+        } else {
+            __syncthreads();
+        }
     }
-    if (s0 == 0) {
+    if (s0 == 0 && sums) {
         double t = block_sum(esum[0]);
         if (threadIdx.x == 0) partG[(long long)ch.N * nblocks + blockIdx.x] = t;
         t = block_sum(esum[1]);
@@ -295,21 +300,27 @@ __global__ __launch_bounds__(kBlock) void k_bwd_block(const int *__restrict__ bl
 }
 
 // E = exp(-(w + alpha d)) of the polymer species, all sites of the active replicas.
-template <typename real>
+template <typename real, bool SINGLE>
 __global__ __launch_bounds__(kBlock) void k_field_exp(const int *__restrict__ blk_rep,
                                                       const int *__restrict__ blk_first,
                                                       const Rep *__restrict__ rep,
                                                       const RepState *__restrict__ st, Chain ch,
                                                       const double *__restrict__ w, const double *__restrict__ d,
-                                                      int use_alpha, real *__restrict__ E)
+                                                      int use_alpha, real *__restrict__ E, Rep rep0)
 {
-    const SiteRef sr = site_ref(blk_rep, blk_first);
-    if (!st[sr.r].active) return;
-    const Rep &R = rep[sr.r];
+    SiteRef sr;
+    if (SINGLE) {
+        sr.r = 0;
+        sr.i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    } else {
+        sr = site_ref(blk_rep, blk_first);
+        if (!st[sr.r].active) return;
+    }
+    const Rep &R = SINGLE ? rep0 : rep[sr.r];
     const long long V = R.V, i = sr.i;
     if (i >= V) return;
     const long long fo = off_field(R, ch.nsp), po = off_poly(R);
-    const double alpha = st[sr.r].alpha;
+    const double alpha = use_alpha ? st[sr.r].alpha : 0.0;
 #pragma unroll
     for (int I = 0; I < 2; ++I) {
         double x = w[fo + I * V + i];
@@ -318,32 +329,197 @@ __global__ __launch_bounds__(kBlock) void k_field_exp(const int *__restrict__ bl
     }
 }
 
+// One contour step per launch without LDS staging: the 27 neighbours come through the
+// caches.  Block tile CX x CY sites of one z-plane (CX * CY = kBlock threads).
+// Tile of this block for the direct kernels.  SINGLE: one replica whose descriptor is a
+// kernel argument (no dependent loads before the stencil), and it is active whenever a
+// kernel is launched.
+template <int CX, int CY, bool SINGLE>
+__device__ __forceinline__ bool direct_tile(const int *blk_rep, const int *blk_first, const Rep *rep,
+                                            const RepState *st, const Rep &rep0, int &r, const Rep *&R, int &x0,
+                                            int &y0, int &z0)
+{
+    if (SINGLE) {
+        r = 0;
+        R = &rep0;
+        const int ntx = (rep0.Lx + CX - 1) / CX, nty = (rep0.Ly + CY - 1) / CY;
+        int lb = blockIdx.x;
+        x0 = (lb % ntx) * CX;
+        lb /= ntx;
+        y0 = (lb % nty) * CY;
+        z0 = lb / nty;
+        return true;
+    }
+    tile_of<CX, CY, 1>(blk_rep, blk_first, rep, r, x0, y0, z0);
+    R = &rep[r];
+    return st[r].active != 0;
+}
+
+template <typename real, int CX, int CY, bool SINGLE>
+__global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ blk_rep,
+                                                       const int *__restrict__ blk_first,
+                                                       const Rep *__restrict__ rep,
+                                                       const RepState *__restrict__ st, Chain ch, int s,
+                                                       PropBufs<real> b, double *__restrict__ partG, int nblocks,
+                                                       int sums, Rep rep0)
+{
+    static_assert(CX * CY == kBlock, "one site per thread");
+    int r, x0, y0, z0;
+    const Rep *Rp;
+    if (!direct_tile<CX, CY, SINGLE>(blk_rep, blk_first, rep, st, rep0, r, Rp, x0, y0, z0)) return;
+    const Rep &R = *Rp;
+    const int V = (int)R.V;
+    const int x = x0 + (int)threadIdx.x % CX, y = y0 + (int)threadIdx.x / CX, z = z0;
+    real *G = b.G + (long long)ch.N * R.site_off;
+    const real *E = b.E + off_poly(R);
+    double gsum = 0.0, esum[2] = {0.0, 0.0};
+    if (x < R.Lx && y < R.Ly) {
+        const int site = x + R.Lx * (y + R.Ly * z);
+        real S;
+        if (s == 1)
+            S = (real)R.csum;
+        else
+            S = stencil27<real>(G + (long long)(s - 2) * V, x, y, z, R.Lx, R.Ly, R.Lz, (real)R.c[0], (real)R.c[1],
+                                (real)R.c[2], (real)R.c[3]);
+        const real g = E[ch.types[s - 1] * V + site] * S * pow2_neg_b<real>(st[r].scale_e[s - 1]);
+        G[(long long)(s - 1) * V + site] = g;
+        gsum = (double)g;
+        if (s == 1 && sums) {
+            esum[0] = (double)E[site];
+            esum[1] = (double)E[V + site];
+        }
+    }
+    if (sums || s == ch.N) {
+        const double t = block_sum(gsum);
+        if (threadIdx.x == 0) partG[(long long)(s - 1) * nblocks + blockIdx.x] = t;
+    }
+    if (s == 1 && sums) {
+        double t = block_sum(esum[0]);
+        if (threadIdx.x == 0) partG[(long long)ch.N * nblocks + blockIdx.x] = t;
+        t = block_sum(esum[1]);
+        if (threadIdx.x == 0) partG[(long long)(ch.N + 1) * nblocks + blockIdx.x] = t;
+    }
+}
+
+template <typename real, int CX, int CY, bool SINGLE>
+__global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ blk_rep,
+                                                       const int *__restrict__ blk_first,
+                                                       const Rep *__restrict__ rep,
+                                                       const RepState *__restrict__ st, Chain ch, int s,
+                                                       PropBufs<real> b, const real *__restrict__ gin,
+                                                       real *__restrict__ gout, double *__restrict__ acc,
+                                                       int final_mode, const double *__restrict__ phit,
+                                                       const double *__restrict__ d, double *__restrict__ out,
+                                                       double *__restrict__ part, Rep rep0)
+{
+    static_assert(CX * CY == kBlock, "one site per thread");
+    int r, x0, y0, z0;
+    const Rep *Rp;
+    if (!direct_tile<CX, CY, SINGLE>(blk_rep, blk_first, rep, st, rep0, r, Rp, x0, y0, z0)) return;
+    const Rep &R = *Rp;
+    const int V = (int)R.V;
+    const int N = ch.N;
+    const int ts = ch.types[s - 1];
+    const int x = x0 + (int)threadIdx.x % CX, y = y0 + (int)threadIdx.x / CX, z = z0;
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};
+    if (x < R.Lx && y < R.Ly) {
+        const int site = x + R.Lx * (y + R.Ly * z);
+        const long long po = off_poly(R);
+        real S;
+        if (s == N)
+            S = (real)R.csum;
+        else
+            S = stencil27<real>(gin + R.site_off, x, y, z, R.Lx, R.Ly, R.Lz, (real)R.c[0], (real)R.c[1],
+                                (real)R.c[2], (real)R.c[3]);
+        const real *G = b.G + (long long)N * R.site_off;
+        const double term = (double)G[(long long)(s - 1) * V + site] * (double)S;
+        if (s > 1) {
+            gout[R.site_off + site] = b.E[po + ts * V + site] * S * pow2_neg_b<real>(st[r].scale_e[s - 1]);
+            if (s == N) {
+                acc[po + (long long)ts * V + site] = term;
+                acc[po + (long long)(1 - ts) * V + site] = 0.0;
+            } else {
+                acc[po + (long long)ts * V + site] += term;
+            }
+        } else {
+            double a[2] = {0.0, 0.0};
+            if (N > 1) {
+                a[0] = acc[po + site];
+                a[1] = acc[po + V + site];
+            }
+            a[ts] += term;
+            const double coef = st[r].phibar_p / ((double)N * st[r].q);
+            const long long fo = off_field(R, ch.nsp);
+#pragma unroll
+            for (int I = 0; I < 2; ++I) {
+                const double ph = coef * a[I];
+                if (final_mode == 0) {
+                    out[fo + (long long)I * V + site] = ph;
+                } else {
+                    const double gI = phit[fo + (long long)I * V + site] - ph;
+                    out[po + (long long)I * V + site] = gI;
+                    if (d) sums[0] += d[po + (long long)I * V + site] * gI;
+                    sums[1] += gI * gI;
+                    sums[2 + I] += gI * gI;
+                }
+            }
+        }
+    }
+    if (s == 1 && final_mode == 1) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double t = block_sum(sums[q]);
+            if (threadIdx.x == 0) part[(long long)blockIdx.x * kNQ + q] = t;
+        }
+    }
+}
+
 // ---- launchers ---------------------------------------------------------------------
 
 template <typename real, int CX, int CY, int CZ, int K>
 struct BlockKernels {
     static void fwd(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int s0, int n,
-                    PropBufs<real> b, double *partG, hipEvent_t e0, hipEvent_t e1)
+                    PropBufs<real> b, double *partG, int sums, hipEvent_t e0, hipEvent_t e1)
     {
-        if (e0)
-            hipExtLaunchKernelGGL((k_fwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1,
-                                  0, p.blk_rep, p.blk_first, rep, st, ch, s0, n, b, partG, p.nblocks);
-        else
-            hipLaunchKernelGGL((k_fwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep,
-                               p.blk_first, rep, st, ch, s0, n, b, partG, p.nblocks);
+        if constexpr (K == 0) {
+            auto kern = p.n_rep == 1 ? k_fwd_direct<real, CX, CY, true> : k_fwd_direct<real, CX, CY, false>;
+            if (e0)
+                hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first,
+                                      rep, st, ch, s0 + 1, b, partG, p.nblocks, sums, p.rep0);
+            else
+                hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st, ch,
+                                   s0 + 1, b, partG, p.nblocks, sums, p.rep0);
+        } else {
+            if (e0)
+                hipExtLaunchKernelGGL((k_fwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, e0,
+                                      e1, 0, p.blk_rep, p.blk_first, rep, st, ch, s0, n, b, partG, p.nblocks, sums);
+            else
+                hipLaunchKernelGGL((k_fwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s,
+                                   p.blk_rep, p.blk_first, rep, st, ch, s0, n, b, partG, p.nblocks, sums);
+        }
     }
     static void bwd(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int s_hi, int n,
                     PropBufs<real> b, const real *gin, real *gout, double *acc, int final_mode, const double *phit,
                     const double *d, double *out, double *part, hipEvent_t e0, hipEvent_t e1)
     {
-        if (e0)
-            hipExtLaunchKernelGGL((k_bwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1,
-                                  0, p.blk_rep, p.blk_first, rep, st, ch, s_hi, n, b, gin, gout, acc, final_mode,
-                                  phit, d, out, part);
-        else
-            hipLaunchKernelGGL((k_bwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep,
-                               p.blk_first, rep, st, ch, s_hi, n, b, gin, gout, acc, final_mode, phit, d, out,
-                               part);
+        if constexpr (K == 0) {
+            auto kern = p.n_rep == 1 ? k_bwd_direct<real, CX, CY, true> : k_bwd_direct<real, CX, CY, false>;
+            if (e0)
+                hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first,
+                                      rep, st, ch, s_hi, b, gin, gout, acc, final_mode, phit, d, out, part, p.rep0);
+            else
+                hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st, ch,
+                                   s_hi, b, gin, gout, acc, final_mode, phit, d, out, part, p.rep0);
+        } else {
+            if (e0)
+                hipExtLaunchKernelGGL((k_bwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, e0,
+                                      e1, 0, p.blk_rep, p.blk_first, rep, st, ch, s_hi, n, b, gin, gout, acc,
+                                      final_mode, phit, d, out, part);
+            else
+                hipLaunchKernelGGL((k_bwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s,
+                                   p.blk_rep, p.blk_first, rep, st, ch, s_hi, n, b, gin, gout, acc, final_mode,
+                                   phit, d, out, part);
+        }
     }
 };
 
@@ -351,21 +527,22 @@ template <typename real>
 void launch_field_exp(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, const double *w,
                       const double *d, int use_alpha, real *E, hipEvent_t e0, hipEvent_t e1)
 {
+    auto kern = p.n_rep == 1 ? k_field_exp<real, true> : k_field_exp<real, false>;
     if (e0)
-        hipExtLaunchKernelGGL(k_field_exp<real>, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep,
-                              p.blk_first, rep, st, ch, w, d, use_alpha, E);
+        hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep, st,
+                              ch, w, d, use_alpha, E, p.rep0);
     else
-        hipLaunchKernelGGL(k_field_exp<real>, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st,
-                           ch, w, d, use_alpha, E);
+        hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st, ch, w, d,
+                           use_alpha, E, p.rep0);
 }
 
 template <typename real>
 void launch_fwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
-                      int s0, int n, PropBufs<real> b, double *partG, hipEvent_t e0, hipEvent_t e1)
+                      int s0, int n, PropBufs<real> b, double *partG, int sums, hipEvent_t e0, hipEvent_t e1)
 {
 #define HSF_CASE(CX, CY, CZ, K)                                                                   \
     if (cfg.cx == CX && cfg.cy == CY && cfg.cz == CZ && cfg.k == K)                               \
-        return BlockKernels<real, CX, CY, CZ, K>::fwd(s, p, rep, st, ch, s0, n, b, partG, e0, e1);
+        return BlockKernels<real, CX, CY, CZ, K>::fwd(s, p, rep, st, ch, s0, n, b, partG, sums, e0, e1);
     HSF_TILE_CONFIGS(HSF_CASE)
 #undef HSF_CASE
 }
@@ -389,7 +566,7 @@ void launch_bwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Re
                                          const double *, const double *, int, real *, hipEvent_t,         \
                                          hipEvent_t);                                                     \
     template void launch_fwd_block<real>(const TileCfg &, hipStream_t, const Plan &, const Rep *,         \
-                                         RepState *, Chain, int, int, PropBufs<real>, double *,           \
+                                         RepState *, Chain, int, int, PropBufs<real>, double *, int,      \
                                          hipEvent_t, hipEvent_t);                                         \
     template void launch_bwd_block<real>(const TileCfg &, hipStream_t, const Plan &, const Rep *,         \
                                          RepState *, Chain, int, int, PropBufs<real>, const real *,       \

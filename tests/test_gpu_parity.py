@@ -324,8 +324,8 @@ def test_graph_replays_match_direct_launches(hsf, orc, monkeypatch):
             assert np.array_equal(x, y)
 
 
-TILES = [(8, 8, 8, 1), (8, 8, 8, 2), (8, 8, 8, 3), (8, 8, 8, 4), (16, 8, 8, 2), (16, 8, 4, 2), (32, 8, 4, 1),
-         (32, 4, 4, 2)]
+TILES = [(64, 4, 1, 0), (32, 8, 1, 0), (16, 16, 1, 0), (8, 8, 8, 1), (8, 8, 8, 2), (8, 8, 8, 3), (8, 8, 8, 4),
+         (16, 8, 8, 2), (16, 8, 4, 2), (32, 8, 4, 1), (32, 4, 4, 2)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -342,8 +342,6 @@ def test_every_tile_configuration(hsf, orc, precision):
         ctx.set_densities(phi0.ravel())
         ctx.set_fields(w.ravel())
         for t in TILES:
-            if precision == "fp64" and t == (8, 8, 8, 4):
-                pass
             try:
                 ctx.set_tile(t)
             except hsf.HsfError:
