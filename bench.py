@@ -1,15 +1,19 @@
-"""Benchmark: coupled LB + dynamic-SCF steps of a 64^3 A8B8 melt on one GPU.
+"""Benchmark: coupled LB + dynamic-SCF steps on one GPU.
 
-A step is one pass of the whole method (field inversion to the residual,
-chemical potential and force, LB collide-and-stream, convection-diffusion
-update) over the 64^3 periodic melt of symmetric A8B8 diblocks, chi N = 20,
-tau 0.6, initial noise +-0.01 (seed 0), propagators in FP32 with FP64
-reductions (or all FP64 with --precision fp64).
+Default workload: the 64^3 periodic melt of symmetric A8B8 diblocks, chi N = 20,
+initial noise +-0.01 (seed 0), at the two viscosity settings tau = 0.6 and
+tau = 1.5, run together as two replicas of one batched context, propagators in
+FP32 with FP64 reductions (the mixed-precision arm).  The all-FP64 arm of the
+same comparison is timed after it and reported in its own field.
+
+A step is one pass of the whole method over every replica: field inversion to
+the residual, chemical potential and force, LB collide-and-stream, and the
+convection-diffusion update.
 
 value = propagator site-bead updates per second over the timed steps: every
 density-functional evaluation performs 2 N V site-bead updates (N forward and
-N backward propagator steps over V sites), counted over all evaluations the
-inversions needed, divided by the wall time of the whole steps.
+N backward propagator steps over V sites); the count runs over all evaluations
+the inversions needed in all replicas, divided by the wall time of the steps.
 
 Prints one JSON line.  Inputs are synthetic (seeded), resident in HBM before
 the timed region starts.
@@ -38,24 +42,82 @@ def algorithmic_bytes_per_update(wl, prec_bytes):
     return prec_bytes + n_poly * (8 + 8) / (2.0 * wl.N)
 
 
+def make_workloads(name, precision):
+    from paper_1204_2088_amd import workloads as W
+    if name == "melt64_a8b8":
+        return [W.melt64_a8b8(tau=0.6, precision=precision), W.melt64_a8b8(tau=1.5, precision=precision)]
+    if name == "melt64_a8b8_tau0.6":
+        return [W.melt64_a8b8(tau=0.6, precision=precision)]
+    if name == "melt16_a4b4":
+        return [W.melt16_a4b4().with_(precision=precision)]
+    if name == "melt96_a4b12":
+        return [W.melt96_a4b12().with_(precision=precision)]
+    if name == "vesicle128_a3b9s":
+        return [W.vesicle128_a3b9s().with_(precision=precision)]
+    if name == "batch48_a3b9s":
+        return [w.with_(precision=precision) for w in W.batch48_a3b9s()]
+    raise SystemExit(f"unknown workload {name}")
+
+
 def cpu_baseline(wl, w, phi, seconds):
     from oracle import oracle as orc
     orc.build(force=False)
     sysw = orc.System(L=wl.L, types=wl.types, has_solvent=wl.has_solvent, a=wl.a, chi=wl.chi,
                       kappa=wl.kappa, dt=wl.dt, tau=wl.tau)
     pbar = phi[:2].sum(0).mean()
+    pbs = phi[2].mean() if wl.has_solvent else 0.0
     n = 0
     t0 = time.perf_counter()
     while True:
-        orc.evaluate(sysw, w, pbar, 0.0)
+        orc.evaluate(sysw, w, pbar, pbs)
         n += 1
         el = time.perf_counter() - t0
         if el >= seconds:
             break
     upd = n * 2 * wl.N * wl.V
     return {"value": upd / el, "unit": "site·bead updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} density-functional evaluations of the {wl.L[0]}^3 A8B8 melt at the GPU run's "
-                      f"final fields ({el:.1f} s, single-threaded FP64 C oracle)"}
+            "sample": f"{n} density-functional evaluations of the {wl.L[0]}x{wl.L[1]}x{wl.L[2]} {wl.name} system at "
+                      f"the GPU run's final fields of replica 0 ({el:.1f} s, single-threaded FP64 C oracle)"}
+
+
+def run_arm(hsf, torch, wls, steps, warmup, timing, log, precond=False):
+    """Build a batched context, autotune, warm up, time `steps` coupled steps."""
+    from paper_1204_2088_amd import workloads as W
+    stream = torch.cuda.current_stream()
+    ctx = hsf.Context(wls, stream=stream)
+    ctx.set_solver(precond=precond)
+    phi0 = np.concatenate([W.initial_composition(w).ravel() for w in wls])
+    ctx.set_densities(torch.from_numpy(phi0).to("cuda"))
+    torch.cuda.synchronize()
+    tile, tune_ms = ctx.autotune(reps=3)
+    log(f"# {wls[0].name} x{len(wls)} {wls[0].precision}: autotuned tile {tile} ({tune_ms:.3f} ms per evaluation)")
+    tol = wls[0].tol
+    ctx.step(warmup, tol=tol, max_iter=4000)   # also captures the launch graphs
+    torch.cuda.synchronize()
+    ctx.get_work(reset=True)
+    t0 = time.perf_counter()
+    stats, evals = ctx.step(steps, tol=tol, max_iter=4000)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    _, site_evals = ctx.get_work(reset=True)
+    log(f"# timed {steps} steps in {elapsed:.3f} s, {evals} evaluations")
+    timing_out = {}
+    t_elapsed = None
+    t_steps = 0
+    if timing:
+        # kernel-timing region: the same run continued with every hot kernel launched
+        # directly and bracketed by HIP events (hipExtLaunchKernelGGL) on its stream
+        t_steps = max(1, steps // 2)
+        ctx.set_timing(True)
+        ctx.get_timing()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        ctx.step(t_steps, tol=tol, max_iter=4000)
+        torch.cuda.synchronize()
+        t_elapsed = time.perf_counter() - ta
+        timing_out = ctx.get_timing()
+        ctx.set_timing(False)
+    return ctx, tile, tune_ms, stats, (evals, site_evals), elapsed, timing_out, t_steps, t_elapsed
 
 
 def main():
@@ -63,11 +125,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="melt64_a8b8")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--tau", type=float, default=0.6)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing")
+    ap.add_argument("--no-fp64-arm", action="store_true", help="skip the all-FP64 arm")
+    ap.add_argument("--precond", action="store_true", help="diagonally preconditioned inversion")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -76,56 +140,21 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1204_2088_amd import hsf, workloads as W
+    from paper_1204_2088_amd import hsf
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    wl = W.melt64_a8b8(tau=args.tau, precision=args.precision)
-    phi0 = W.initial_composition(wl)
-    ctx = hsf.Context(wl, stream=stream)
-    phi_d = torch.from_numpy(phi0.ravel()).to("cuda")
-    ctx.set_densities(phi_d)
-    torch.cuda.synchronize()
+    wls = make_workloads(args.workload, args.precision)
+    wl = wls[0]
+    ctx, tile, tune_ms, stats, (evals, site_evals), elapsed, timing, t_steps, t_elapsed = run_arm(
+        hsf, torch, wls, args.steps, args.warmup, not args.no_timing, log, args.precond)
 
-    print(f"# workload {wl.name} L={wl.L} N={wl.N} precision={wl.precision} tau={wl.tau} tol={wl.tol}",
-          file=sys.stderr, flush=True)
-    # propagator tiling picked by the library's autotuner on this shape
-    tile, tune_ms = ctx.autotune(reps=3)
-    print(f"# autotuned tile {tile} ({tune_ms:.3f} ms per evaluation)", file=sys.stderr, flush=True)
-
-    # warmup: captures the launch graphs of the inversion
-    ctx.step(args.warmup, tol=wl.tol, max_iter=2000)
-    torch.cuda.synchronize()
-    print(f"# warmup {args.warmup} steps done", file=sys.stderr, flush=True)
-
-    # timed region: whole coupled steps, launch sequences replayed from hipGraphs
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats, evals = ctx.step(args.steps, tol=wl.tol, max_iter=2000)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    print(f"# timed {args.steps} steps in {elapsed:.3f} s, {evals} evaluations", file=sys.stderr, flush=True)
-
-    # kernel-timing region: the same steps continued with every hot kernel launched
-    # directly and bracketed by HIP events on its stream (hipExtLaunchKernelGGL)
-    timing = {}
-    t_steps = 0
-    t_elapsed = None
-    if not args.no_timing:
-        t_steps = max(1, args.steps // 2)
-        ctx.set_timing(True)
-        ctx.get_timing()
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        ctx.step(t_steps, tol=wl.tol, max_iter=2000)
-        torch.cuda.synchronize()
-        t_elapsed = time.perf_counter() - ta
-        timing = ctx.get_timing()
-        ctx.set_timing(False)
-
-    V, N = wl.V, wl.N
-    updates = evals * 2 * N * V
+    V_total = sum(w.V for w in wls)
+    N = wl.N
+    # every evaluation of every replica counts 2 N V_r site-bead updates
+    updates = 2 * N * site_evals
     value = updates / elapsed
     prec_bytes = 4 if wl.precision == "fp32" else 8
     b_unit = algorithmic_bytes_per_update(wl, prec_bytes)
@@ -138,13 +167,13 @@ def main():
             if cnt:
                 kernels[k] = {"launches": cnt, "avg_us": 1e3 * ms / cnt, "total_ms": ms}
         if "lb" in kernels:
-            lb_mlups = V / (kernels["lb"]["avg_us"] * 1e-6) / 1e6
+            lb_mlups = V_total / (kernels["lb"]["avg_us"] * 1e-6) / 1e6
         prop = {k: v for k, v in kernels.items() if k in ("fwd", "bwd")}
         if prop:
             dom = max(prop, key=lambda k: prop[k]["total_ms"])
             avg_s = prop[dom]["avg_us"] * 1e-6
             steps_per_launch = max(1, tile[3])
-            units = V * steps_per_launch * ctx.n_rep
+            units = V_total * steps_per_launch
             achieved = b_unit * units / avg_s / 1e9
             roofline = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -152,9 +181,22 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        w_final = ctx.get_fields().reshape((wl.nsp,) + wl.shape)
-        phi_final = ctx.get_densities().reshape((wl.nsp,) + wl.shape)
+        nsp = wl.nsp
+        w_final = ctx.get_fields()[:nsp * wl.V].reshape((nsp,) + wl.shape)
+        phi_final = ctx.get_densities()[:nsp * wl.V].reshape((nsp,) + wl.shape)
         cpu = cpu_baseline(wl, w_final, phi_final, args.cpu_seconds)
+    ctx.close()
+
+    fp64_arm = None
+    if args.workload.startswith("melt64_a8b8") and args.precision == "fp32" and not args.no_fp64_arm:
+        wls64 = make_workloads(args.workload, "fp64")
+        steps64 = max(2, args.steps // 5)
+        c64, tile64, _, st64, (ev64, se64), el64, _, _, _ = run_arm(hsf, torch, wls64, steps64, 3, False, log,
+                                                                   args.precond)
+        fp64_arm = {"value": 2 * N * se64 / el64, "unit": "site·bead updates/s",
+                    "steps": steps64, "ms_per_step": 1e3 * el64 / steps64, "evals_per_step": ev64 / steps64,
+                    "tol": wls64[0].tol, "tile": list(tile64)}
+        c64.close()
 
     out = {
         "metric": METRIC,
@@ -169,21 +211,23 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if wl.precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "melt64_a8b8", "L": list(wl.L), "N": N, "chiN": 20, "tau": wl.tau,
-                   "propagators": wl.precision, "reductions": "fp64", "tol": wl.tol, "dt": wl.dt,
-                   "hydro": True},
+        "config": {"workload": args.workload, "L": list(wl.L), "N": N, "replicas": len(wls),
+                   "tau": [w.tau for w in wls], "propagators": wl.precision, "reductions": "fp64",
+                   "tol": wl.tol, "dt": wl.dt, "hydro": True,
+                   "solver": "preconditioned FR" if args.precond else "FR"},
         "evals_per_step": evals / args.steps,
-        "iterations_last_step": stats[0]["iterations"],
+        "iterations_last_step": [s["iterations"] for s in stats][:8],
         "lb_mlups": lb_mlups,
         "tile": {"core": list(tile[:3]), "steps_per_launch": tile[3], "autotune_ms_per_eval": tune_ms},
         "kernels": kernels,
-        "kernel_timing_region": {"steps": t_steps, "ms_per_step": (1e3 * t_elapsed / t_steps) if t_elapsed else None,
+        "kernel_timing_region": {"steps": t_steps,
+                                 "ms_per_step": (1e3 * t_elapsed / t_steps) if t_elapsed else None,
                                  "launch": "direct, one event pair per hot kernel"},
         "roofline": roofline,
+        "fp64_arm": fp64_arm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

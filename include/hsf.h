@@ -190,6 +190,19 @@ int hsf_step(hsf_ctx *ctx, int n_steps, double tol, int max_iter, hsf_invert_sta
  * is kept while off). */
 int hsf_set_hydro(hsf_ctx *ctx, int on);
 
+/* Inversion variant.  0 (default): plain Fletcher-Reeves on the gradient
+ * g = phi^t - phi[w].  HSF_SOLVER_PRECOND: the steepest-descent vector is
+ * z = g / phi^t (diagonal preconditioning by the target densities), with
+ * beta = (g_new.z_new)/(g_old.z_old); same line search and stopping test. */
+enum { HSF_SOLVER_PRECOND = 1 };
+int hsf_set_solver(hsf_ctx *ctx, int flags);
+
+/* Work done by inversions since creation or the last reset: the number of
+ * density-functional evaluations over all replicas, and the sum over replicas of
+ * evaluations times sites (each evaluation performs 2 N site-bead updates per
+ * site).  reset != 0 clears both counters after reading. */
+int hsf_get_work(hsf_ctx *ctx, long long *evals, double *site_evals, int reset);
+
 /* Propagator tiling (the temporally blocked sweeps): cfg = {cx, cy, cz, k}, a
  * core tile of cx*cy*cz sites per workgroup advanced k contour steps per launch.
  * hsf_set_tile accepts only the configurations compiled into the library

@@ -40,6 +40,7 @@ typedef struct {
     double gamma_b, gamma_s, gamma_ghost; /* MRT relaxation parameters        */
     int lb_mode;                 /* 0: BGK + Guo forcing, 1: MRT (Table 1)    */
     int hydro;                   /* 1: convection by the LB velocity          */
+    int precond;                 /* 1: inversion preconditioned by diag(phi^t) */
 } orc_sys;
 
 typedef struct {
@@ -218,6 +219,9 @@ static double residual(const orc_sys *s, const double *g, const double *phit)
  *     positive; extrapolation is capped at 8x the current alpha;
  *   - Fletcher-Reeves beta = |g_new|^2 / |g_old|^2, restart (d = -g) every 50
  *     iterations and whenever d.g >= 0;
+ *   - optional diagonal preconditioning (precond = 1): the steepest-descent
+ *     vector is z = g / phi^t instead of g, so d = -z + beta d with
+ *     beta = (g_new.z_new) / (g_old.z_old) and restarts set d = -z;
  *   - stop when max_I |phi_I - phi^t_I| / |phi^t_I| <= tol.
  * With fixed_iters > 0 exactly that many iterations are taken whatever the
  * residual ("mirror" mode, to follow another implementation's trajectory).
@@ -268,14 +272,17 @@ int orc_invert(const orc_sys *s, const double *phit, double *w, double tol, int 
     if (fixed_iters <= 0 && loc.residual <= tol) status = 0;
 
     if (status != 0) {
-        for (long i = 0; i < n; ++i) d[i] = -g[i];
-        double gg = dot(g, g, n);
+        /* z = M^-1 g with M = diag(phi^t) when preconditioned, else z = g */
+#define ZI(i) (s->precond ? g[i] / phit[i] : g[i])
+        for (long i = 0; i < n; ++i) d[i] = -ZI(i);
+        double gg = 0.0;
+        for (long i = 0; i < n; ++i) gg += g[i] * ZI(i);
         int limit = fixed_iters > 0 ? fixed_iters : max_iter;
         memcpy(wt, w, sizeof(double) * V * ns);
         for (int k = 1; k <= limit; ++k) {
             double h0 = dot(d, g, n);
             if (h0 >= 0.0) {
-                for (long i = 0; i < n; ++i) d[i] = -g[i];
+                for (long i = 0; i < n; ++i) d[i] = -ZI(i);
                 h0 = -gg;
                 loc.restarts++;
             }
@@ -307,15 +314,17 @@ int orc_invert(const orc_sys *s, const double *phit, double *w, double tol, int 
                 status = 0;
                 break;
             }
-            double gg_new = dot(g, g, n);
+            double gg_new = 0.0;
+            for (long i = 0; i < n; ++i) gg_new += g[i] * ZI(i);
             double beta = gg_new / gg;
             gg = gg_new;
             if (k % 50 == 0) {
                 beta = 0.0;
                 loc.restarts++;
             }
-            for (long i = 0; i < n; ++i) d[i] = -g[i] + beta * d[i];
+            for (long i = 0; i < n; ++i) d[i] = -ZI(i) + beta * d[i];
         }
+#undef ZI
         if (fixed_iters > 0) status = 0;
     }
     loc.converged = (loc.residual <= tol);

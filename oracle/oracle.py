@@ -45,6 +45,7 @@ class _Sys(ctypes.Structure):
         ("kappa", ctypes.c_double), ("dt", ctypes.c_double), ("tau", ctypes.c_double),
         ("gamma_b", ctypes.c_double), ("gamma_s", ctypes.c_double),
         ("gamma_ghost", ctypes.c_double), ("lb_mode", ctypes.c_int), ("hydro", ctypes.c_int),
+        ("precond", ctypes.c_int),
     ]
 
 
@@ -121,6 +122,7 @@ class System:
     gamma_ghost: float = 0.0
     lb_mode: int = 0
     hydro: bool = True
+    precond: bool = False
 
     @property
     def V(self):
@@ -165,6 +167,7 @@ class System:
         s.gamma_b, s.gamma_s, s.gamma_ghost = float(self.gamma_b), float(self.gamma_s), float(self.gamma_ghost)
         s.lb_mode = int(self.lb_mode)
         s.hydro = int(bool(self.hydro))
+        s.precond = int(bool(self.precond))
         return s
 
 

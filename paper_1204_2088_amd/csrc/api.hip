@@ -62,6 +62,8 @@ struct hsf_ctx {
     GraphSlot graphs[GK_COUNT];
 
     // optional per-launch timing of the hot kernels with HIP events on the context stream
+    long long work_evals = 0;          // density-functional evaluations, all replicas
+    double work_site_evals = 0.0;      // sum over replicas of evaluations x sites
     int timing = 0;
     std::vector<EvPair> pending;       // recorded, not yet read
     std::vector<hipEvent_t> pool;      // free events
@@ -396,6 +398,8 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
     for (int r = 0; r < c->n_rep; ++r) {
         const RepState &S = c->st_h[r];
         ev += S.evals;
+        c->work_evals += S.evals;
+        c->work_site_evals += (double)S.evals * (double)c->reps[r].V;
         if (stats) {
             stats[r].iterations = S.iters;
             stats[r].evaluations = S.evals;
@@ -891,6 +895,34 @@ int hsf_autotune(hsf_ctx *c, int reps, double *best_ms)
     c->tuned = 1;
     if (best_ms) *best_ms = best_t;
     return rc;
+}
+
+int hsf_set_solver(hsf_ctx *c, int flags)
+{
+    if (!c || (flags & ~HSF_SOLVER_PRECOND)) return HSF_EINVAL;
+    const int pc = (flags & HSF_SOLVER_PRECOND) ? 1 : 0;
+    if (pc != c->ch.precond) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->ch.precond = pc;
+        for (auto &g : c->graphs)   // the flag is a kernel argument of the captured sequences
+            if (g.exec) {
+                (void)hipGraphExecDestroy(g.exec);
+                g.exec = nullptr;
+            }
+    }
+    return HSF_OK;
+}
+
+int hsf_get_work(hsf_ctx *c, long long *evals, double *site_evals, int reset)
+{
+    if (!c) return HSF_EINVAL;
+    if (evals) *evals = c->work_evals;
+    if (site_evals) *site_evals = c->work_site_evals;
+    if (reset) {
+        c->work_evals = 0;
+        c->work_site_evals = 0.0;
+    }
+    return HSF_OK;
 }
 
 int hsf_set_hydro(hsf_ctx *c, int on)

@@ -7,8 +7,9 @@
 // whose gradient is phi^t - phi[w].  Line search: secant on h(alpha) = d.grad Phi(w + alpha d)
 // from alpha_0 = -(d.g) / sum d^2 phi^t; a trial is accepted when |h| <= 0.1 |h(0)|, after
 // three trials, or when the secant slope or the next alpha is not positive (extrapolation
-// capped at 8x).  beta = |g_new|^2 / |g_old|^2; restart every 50 iterations and whenever
-// the new direction would not descend (d_new.g_new = -|g_new|^2 + beta d.g_new >= 0).
+// capped at 8x).  beta = (g_new.z_new) / (g_old.z_old) with z = g, or z = g / phi^t in the
+// diagonally preconditioned variant; restart every 50 iterations and whenever the new
+// direction would not descend (d_new.g_new = -g_new.z_new + beta d.g_new >= 0).
 //
 // All vector work is done by site kernels that write per-block partial sums; one block
 // per replica then sums its blocks' partials in a fixed order and thread 0 runs the
@@ -354,10 +355,10 @@ void launch_init_fields(hipStream_t s, const Plan &p, const Rep *rep, RepState *
                        phit, w);
 }
 
-// Conjugate-gradient vector update.
-//   init = 1 (replicas pending their first iteration): d = -g
+// Conjugate-gradient vector update, z = g (or g / phi^t when preconditioned).
+//   init = 1 (replicas pending their first iteration): d = -z
 //   init = 0 (replicas whose trial was accepted): w += alpha d, g = g_trial and,
-//            unless the replica is done, d = -g + beta d
+//            unless the replica is done, d = -z + beta d
 // Partial sums d.g and sum d^2 phi^t for the next alpha_0.
 __global__ __launch_bounds__(kBlock) void k_cg_update(const int *__restrict__ blk_rep,
                                                       const int *__restrict__ blk_first,
@@ -390,7 +391,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const int *__restrict__ bl
                 g[k] = gI;
             }
             if (upd_d) {
-                dI = init ? -gI : fma(beta, dI, -gI);
+                const double zI = ch.precond ? gI / phit[fo + I * V + i] : gI;
+                dI = init ? -zI : fma(beta, dI, -zI);
                 d[k] = dI;
             }
             dg += dI * gI;

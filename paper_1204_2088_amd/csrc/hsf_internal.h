@@ -58,6 +58,7 @@ struct Plan {
 struct Chain {
     int N;
     int nsp;                     // 2 or 3 species
+    int precond;                 // inversion preconditioned by diag(phi^t)
     int types[64];
 };
 

@@ -192,7 +192,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd_block(const int *__restrict__ bl
 // core site and species in LDS, then adds them to acc (or sets acc for the
 // first launch).  The launch that reaches s = 1 normalises the densities:
 // final_mode 0 writes phi (field layout), final_mode 1 writes g = phi^t - phi
-// (polymer layout) with block partial sums d.g, g.g, |g_A|^2, |g_B|^2.
+// (polymer layout) with block partial sums d.g, g.z, |g_A|^2, |g_B|^2, where
+// z = g / phi^t when the inversion is preconditioned and z = g otherwise.
 template <typename real, int CX, int CY, int CZ, int K>
 __global__ __launch_bounds__(kBlock) void k_bwd_block(const int *__restrict__ blk_rep,
                                                       const int *__restrict__ blk_first,
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_block(const int *__restrict__ bl
                     const double gI = phit[fo + (long long)I * V + site] - ph;
                     out[po + (long long)I * V + site] = gI;
                     if (d) sums[0] += d[po + (long long)I * V + site] * gI;
-                    sums[1] += gI * gI;
+                    sums[1] += ch.precond ? gI * gI / phit[fo + (long long)I * V + site] : gI * gI;
                     sums[2 + I] += gI * gI;
                 }
             }
@@ -459,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ b
                     const double gI = phit[fo + (long long)I * V + site] - ph;
                     out[po + (long long)I * V + site] = gI;
                     if (d) sums[0] += d[po + (long long)I * V + site] * gI;
-                    sums[1] += gI * gI;
+                    sums[1] += ch.precond ? gI * gI / phit[fo + (long long)I * V + site] : gI * gI;
                     sums[2 + I] += gI * gI;
                 }
             }

@@ -31,7 +31,9 @@ EXPORTED = [
     "hsf_set_densities", "hsf_get_densities", "hsf_evaluate", "hsf_invert", "hsf_mu_force",
     "hsf_set_lb", "hsf_get_lb", "hsf_lb_advance", "hsf_get_flow", "hsf_cd_advance", "hsf_step",
     "hsf_set_hydro", "hsf_set_timing", "hsf_get_timing", "hsf_set_tile", "hsf_get_tile", "hsf_autotune",
+    "hsf_set_solver", "hsf_get_work",
 ]
+SOLVER_PRECOND = 1
 K_PREP, K_FWD, K_BWD, K_LB, K_CD, K_COUNT = 0, 1, 2, 3, 4, 5
 KERNEL_NAMES = ["prep", "fwd", "bwd", "lb", "cd"]
 
@@ -104,6 +106,8 @@ def load():
                       ctypes.POINTER(ctypes.c_longlong)], I),
         "hsf_set_hydro": ([C, I], I),
         "hsf_set_timing": ([C, I], I),
+        "hsf_set_solver": ([C, I], I),
+        "hsf_get_work": ([C, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double), I], I),
         "hsf_set_tile": ([C, ctypes.POINTER(ctypes.c_int)], I),
         "hsf_get_tile": ([C, ctypes.POINTER(ctypes.c_int)], I),
         "hsf_autotune": ([C, I, ctypes.POINTER(ctypes.c_double)], I),
@@ -303,6 +307,17 @@ class Context:
         ms = ctypes.c_double(0.0)
         self._check(self._lib.hsf_autotune(self._h, int(reps), ctypes.byref(ms)))
         return self.get_tile(), ms.value
+
+    def set_solver(self, precond=False):
+        """Plain Fletcher-Reeves (default) or the diagonally preconditioned variant."""
+        self._check(self._lib.hsf_set_solver(self._h, SOLVER_PRECOND if precond else 0))
+
+    def get_work(self, reset=False):
+        """(evaluations, sum over replicas of evaluations x sites) since the last reset."""
+        ev = ctypes.c_longlong(0)
+        se = ctypes.c_double(0.0)
+        self._check(self._lib.hsf_get_work(self._h, ctypes.byref(ev), ctypes.byref(se), int(bool(reset))))
+        return ev.value, se.value
 
     def set_timing(self, on):
         self._check(self._lib.hsf_set_timing(self._h, int(bool(on))))
