@@ -30,6 +30,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM-side bytes per launch of the dominant propagator kernel, from the counter runs
+# summarised in profiles/propagator_melt64_a8b8_x2_fp32_traffic.md (FETCH_SIZE scaled by
+# 2.0 and WRITE_SIZE by 1.0 after a calibration copy).  Valid only for that workload,
+# precision, tiling and kernel; anything else reports null.
+MEASURED_TRAFFIC = {("melt64_a8b8", "fp32", (64, 4, 1, 0), "bwd"): 19.16e6}
 METRIC = "propagator site·bead updates/s + LB MLUPS; step time learned vs plain at 1e-6"
 
 
@@ -80,7 +86,7 @@ def cpu_baseline(wl, w, phi, seconds):
                       f"the GPU run's final fields of replica 0 ({el:.1f} s, single-threaded FP64 C oracle)"}
 
 
-def run_arm(hsf, torch, wls, steps, warmup, timing, log, precond=False):
+def run_arm(hsf, torch, wls, steps, warmup, timing, log, precond=False, tile=None):
     """Build a batched context, autotune, warm up, time `steps` coupled steps."""
     from paper_1204_2088_amd import workloads as W
     stream = torch.cuda.current_stream()
@@ -89,8 +95,13 @@ def run_arm(hsf, torch, wls, steps, warmup, timing, log, precond=False):
     phi0 = np.concatenate([W.initial_composition(w).ravel() for w in wls])
     ctx.set_densities(torch.from_numpy(phi0).to("cuda"))
     torch.cuda.synchronize()
-    tile, tune_ms = ctx.autotune(reps=3)
-    log(f"# {wls[0].name} x{len(wls)} {wls[0].precision}: autotuned tile {tile} ({tune_ms:.3f} ms per evaluation)")
+    if tile is None:
+        tile, tune_ms = ctx.autotune(reps=5)
+        log(f"# {wls[0].name} x{len(wls)} {wls[0].precision}: autotuned tile {tile} ({tune_ms:.3f} ms per evaluation)")
+    else:
+        ctx.set_tile(tile)
+        tile, tune_ms = ctx.get_tile(), None
+        log(f"# {wls[0].name} x{len(wls)} {wls[0].precision}: tile {tile} (given)")
     tol = wls[0].tol
     ctx.step(warmup, tol=tol, max_iter=4000)   # also captures the launch graphs
     torch.cuda.synchronize()
@@ -132,7 +143,21 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing")
     ap.add_argument("--no-fp64-arm", action="store_true", help="skip the all-FP64 arm")
     ap.add_argument("--precond", action="store_true", help="diagonally preconditioned inversion")
+    ap.add_argument("--tile", default=None, help="cx,cy,cz,k: use this propagator tiling instead of autotuning")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "copies": 5}))
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the method is benchmarked "
@@ -149,7 +174,8 @@ def main():
     wls = make_workloads(args.workload, args.precision)
     wl = wls[0]
     ctx, tile, tune_ms, stats, (evals, site_evals), elapsed, timing, t_steps, t_elapsed = run_arm(
-        hsf, torch, wls, args.steps, args.warmup, not args.no_timing, log, args.precond)
+        hsf, torch, wls, args.steps, args.warmup, not args.no_timing, log, args.precond,
+        tuple(int(v) for v in args.tile.split(",")) if args.tile else None)
 
     V_total = sum(w.V for w in wls)
     N = wl.N
@@ -175,8 +201,11 @@ def main():
             steps_per_launch = max(1, tile[3])
             units = V_total * steps_per_launch
             achieved = b_unit * units / avg_s / 1e9
+            traffic = MEASURED_TRAFFIC.get((args.workload, wl.precision, tuple(tile), dom))
             roofline = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                        "traffic_unit": "bytes per launch (counters)",
+                        "algorithmic_bytes_per_launch": b_unit * units,
                         "bytes_per_update": b_unit, "updates_per_launch": units}
 
     cpu = None

@@ -871,18 +871,21 @@ int hsf_autotune(hsf_ctx *c, int reps, double *best_ms)
         if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (graph) (void)hipGraphDestroy(graph);
         if (e == hipSuccess) e = hipGraphLaunch(exec, c->stream);   // warm
-        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-        if (e == hipSuccess) e = hipGraphLaunch(exec, c->stream);
-        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 1e30f;
+        for (int trial = 0; trial < 2 && e == hipSuccess; ++trial) {   // best of two replays
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess) e = hipGraphLaunch(exec, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t_ms = 0.0f;
+            if (e == hipSuccess) (void)hipEventElapsedTime(&t_ms, e0, e1);
+            ms = std::min(ms, t_ms / reps);
+        }
         if (exec) (void)hipGraphExecDestroy(exec);
         if (e != hipSuccess) {
             rc = fail(c, HSF_EHIP, "autotune: %s", hipGetErrorString(e));
             break;
         }
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        ms /= reps;
         if (ms < best_t) {
             best_t = ms;
             best = t;
