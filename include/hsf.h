@@ -72,8 +72,12 @@ enum { HSF_FP64 = 0, HSF_FP32 = 1 };
 
 /* Starting guess of an inversion. */
 enum {
-    HSF_WARM_CURRENT = 0, /* the fields currently held (previous step's result) */
-    HSF_WARM_LOCAL = 1    /* local ideal-gas guess w_I = -ln(phi_I / <phi_I>)   */
+    HSF_WARM_CURRENT = 0,   /* the fields currently held (previous step's result)   */
+    HSF_WARM_LOCAL = 1,     /* local ideal-gas guess w_I = -ln(phi_I / <phi_I>)     */
+    HSF_WARM_EXTRAP = 2,    /* linear extrapolation 2 w^n - w^(n-1) of the previous */
+                            /* two inversions' results                              */
+    HSF_WARM_NET = 3,       /* polymer fields predicted by the attached network     */
+    HSF_WARM_NET_DELTA = 4  /* w^n + net(phi^(n+1)) - net(phi^n)                    */
 };
 
 typedef struct {
@@ -213,6 +217,44 @@ int hsf_get_work(hsf_ctx *ctx, long long *evals, double *site_evals, int reset);
 int hsf_set_tile(hsf_ctx *ctx, const int cfg[4]);
 int hsf_get_tile(const hsf_ctx *ctx, int cfg[4]);
 int hsf_autotune(hsf_ctx *ctx, int reps, double *best_ms);
+
+/* Warm start used by hsf_step's inversions (default HSF_WARM_CURRENT). */
+int hsf_set_warm(hsf_ctx *ctx, int warm);
+
+/* ---- learned warm start -------------------------------------------------------
+ * A 4-level U-Net on the periodic lattice (3x3x3 convolutions, SiLU, 2x2x2 average
+ * pooling, nearest upsampling, additive skips; widths w1..w4 <= 32) mapping the
+ * densities [in_ch][L^3] to the polymer fields [out_ch][L^3].  Convolutions run on
+ * the BF16 matrix cores with FP32 accumulation; master weights and Adam moments are
+ * FP32.  Tensors at this boundary are FP32 [batch][channel][Lz][Ly][Lx] on cubic
+ * periodic boxes with L a multiple of 8.  The parameter vector holds, for the 15
+ * convolutions in order (e1a, e1b, e2a, e2b, e3a, e3b, e4a, e4b, d3a, d3b, d2a, d2b,
+ * d1a, d1b, out), W[co][ci][27] with k = 9 (dz+1) + 3 (dy+1) + (dx+1), then b[co].
+ * This is a build addition; the inversion from its prediction is the same
+ * Fletcher-Reeves iteration to the same residual. */
+typedef struct hsf_net hsf_net;
+int hsf_net_create(int in_ch, int out_ch, const int widths[4], unsigned long long seed, hsf_net **out);
+void hsf_net_destroy(hsf_net *net);
+const char *hsf_net_last_error(const hsf_net *net);
+int hsf_net_set_stream(hsf_net *net, void *hip_stream);
+long long hsf_net_num_params(const hsf_net *net);
+int hsf_net_set_params(hsf_net *net, const float *params, int where);
+/* Input normalisation applied inside every forward pass: x_c = (in_c - shift[c]) *
+ * scale[c] (host arrays of in_ch values; default shift 0, scale 1). */
+int hsf_net_set_input_norm(hsf_net *net, const float *shift, const float *scale);
+int hsf_net_get_params(hsf_net *net, float *params, int where);
+/* out = net(in) for `batch` samples */
+int hsf_net_forward(hsf_net *net, const float *in, float *out, int batch, int L, int where);
+/* mean square error over batch, channels and sites, and its gradient with respect
+ * to the parameters (grad may be NULL) */
+int hsf_net_loss_grad(hsf_net *net, const float *in, const float *target, int batch, int L, double *loss,
+                      float *grad, int where);
+/* one Adam step (beta 0.9, 0.999, eps 1e-8) on the mean square error */
+int hsf_net_train_step(hsf_net *net, const float *in, const float *target, int batch, int L, float lr,
+                       double *loss, int where);
+/* Attach a network (in_ch = species, out_ch = 2) to a context for the NET warm
+ * starts; the context does not own it.  NULL detaches. */
+int hsf_attach_net(hsf_ctx *ctx, hsf_net *net);
 
 /* Kernel families timed by hsf_set_timing. */
 enum {

@@ -1,0 +1,85 @@
+"""FP64 CPU reference of the warm-start network (plain PyTorch CPU operations).
+
+TEST INFRASTRUCTURE ONLY (imported by the test suite).  It shares no code with the
+HIP library: it builds the same topology from torch.nn.functional primitives on
+float64 tensors and differentiates it with autograd.  With `bf16=True` the
+operands of every convolution (input and weights) are rounded to bfloat16 before
+the float64 convolution, which is what the GPU's matrix cores consume.
+
+Topology (widths w1..w4; c(.) = SiLU(periodic 3x3x3 convolution + bias)):
+  e1 = c(c(x)); e2 = c(c(pool e1)); e3 = c(c(pool e2)); e4 = c(c(pool e3))
+  d3 = c(c(up e4) + e3); d2 = c(c(up d3) + e2); d1 = c(c(up d2) + e1); out = conv(d1)
+pool: 2x2x2 average; up: nearest.  Parameter vector layout: per convolution (in the
+order above, 15 of them) W[co][ci][27] with k = 9 (dz+1) + 3 (dy+1) + (dx+1), then b[co].
+"""
+import numpy as np
+import torch
+import torch.nn.functional as F
+
+
+def layer_shapes(in_ch, out_ch, widths):
+    w1, w2, w3, w4 = widths
+    return [(in_ch, w1), (w1, w1), (w1, w2), (w2, w2), (w2, w3), (w3, w3), (w3, w4), (w4, w4),
+            (w4, w3), (w3, w3), (w3, w2), (w2, w2), (w2, w1), (w1, w1), (w1, out_ch)]
+
+
+def num_params(in_ch, out_ch, widths):
+    return sum(co * ci * 27 + co for ci, co in layer_shapes(in_ch, out_ch, widths))
+
+
+def unpack(params, in_ch, out_ch, widths):
+    """List of (W[co][ci][3][3][3], b[co]) float64 tensors from the flat vector."""
+    p = params if isinstance(params, torch.Tensor) else torch.as_tensor(np.asarray(params, dtype=np.float64))
+    out, off = [], 0
+    for ci, co in layer_shapes(in_ch, out_ch, widths):
+        n = co * ci * 27
+        W = p[off:off + n].reshape(co, ci, 3, 3, 3)   # [kz][ky][kx] = offsets (dz+1, dy+1, dx+1)
+        off += n
+        b = p[off:off + co]
+        off += co
+        out.append((W, b))
+    return out
+
+
+def to_bf16(t):
+    return t.to(torch.bfloat16).to(torch.float64)
+
+
+def conv_periodic(x, W, b, bf16=False):
+    """out[o][x] = b[o] + sum_{c,k} W[o][c][k] x[c][x + off_k] on a periodic box
+    (cross-correlation, as the forward convolution of the network)."""
+    if bf16:
+        x, W = to_bf16(x), to_bf16(W)
+    xp = F.pad(x, (1, 1, 1, 1, 1, 1), mode="circular")
+    return F.conv3d(xp, W, b)
+
+
+def forward(params, x, in_ch, out_ch, widths, bf16=False, shift=None, scale=None):
+    """x: float64 tensor [B][in_ch][L][L][L] -> [B][out_ch][L][L][L].  The input is
+    first normalised per channel, (x - shift) * scale (identity by default)."""
+    layers = unpack(params, in_ch, out_ch, widths) if not isinstance(params, list) else params
+    if shift is not None:
+        x = (x - torch.as_tensor(shift, dtype=torch.float64).reshape(1, -1, 1, 1, 1)) * \
+            torch.as_tensor(scale, dtype=torch.float64).reshape(1, -1, 1, 1, 1)
+    c = lambda i, h: F.silu(conv_periodic(h, *layers[i], bf16=bf16))
+    pool = lambda h: F.avg_pool3d(h, 2)
+    up = lambda h: h.repeat_interleave(2, 2).repeat_interleave(2, 3).repeat_interleave(2, 4)
+    e1 = c(1, c(0, x))
+    e2 = c(3, c(2, pool(e1)))
+    e3 = c(5, c(4, pool(e2)))
+    e4 = c(7, c(6, pool(e3)))
+    d3 = c(9, c(8, up(e4)) + e3)
+    d2 = c(11, c(10, up(d3)) + e2)
+    d1 = c(13, c(12, up(d2)) + e1)
+    return conv_periodic(d1, *layers[14], bf16=bf16)
+
+
+def loss_and_grad(params, x, target, in_ch, out_ch, widths, bf16=False, shift=None, scale=None):
+    """Mean square error over all outputs and its gradient (flat, float64)."""
+    p = torch.tensor(np.asarray(params, dtype=np.float64), requires_grad=True)
+    layers = unpack(p, in_ch, out_ch, widths)
+    out = forward(layers, torch.as_tensor(x, dtype=torch.float64), in_ch, out_ch, widths, bf16, shift, scale)
+    t = torch.as_tensor(target, dtype=torch.float64)
+    loss = ((out - t) ** 2).mean()
+    loss.backward()
+    return float(loss.detach()), p.grad.detach().numpy().copy()

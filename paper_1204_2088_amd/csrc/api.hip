@@ -62,6 +62,13 @@ struct hsf_ctx {
     GraphSlot graphs[GK_COUNT];
 
     // optional per-launch timing of the hot kernels with HIP events on the context stream
+    // warm starts
+    int step_warm = HSF_WARM_CURRENT;  // used by hsf_step
+    double *w_prev = nullptr;          // fields after the previous inversion (extrapolation)
+    int have_prev = 0;
+    hsf_net *net = nullptr;            // attached network (not owned)
+    float *net_pred[2] = {nullptr, nullptr};   // current / previous predictions [rep][2][V]
+    int have_pred = 0;
     long long work_evals = 0;          // density-functional evaluations, all replicas
     double work_site_evals = 0.0;      // sum over replicas of evaluations x sites
     int timing = 0;
@@ -339,11 +346,40 @@ void target_setup(hsf_ctx *c, double tol, int max_iter)
                       max_iter);
 }
 
+// Starting fields from the network (NET: the prediction; NET_DELTA: the current fields
+// plus the change of the prediction since the previous call).
+int net_warm(hsf_ctx *c, int warm)
+{
+    if (!c->net) return fail(c, HSF_EINVAL, "no network attached");
+    float *cur = c->net_pred[0], *prev = c->net_pred[1];
+    for (int r = 0; r < c->n_rep; ++r) {
+        const Rep &R = c->reps[r];
+        if (R.Lx != R.Ly || R.Lx != R.Lz || R.Lx % 8)
+            return fail(c, HSF_EINVAL, "network warm start needs cubic boxes with L a multiple of 8");
+        const long long fo = (long long)c->ch.nsp * R.site_off, po = 2LL * R.site_off;
+        int rc = net_predict(c->net, c->stream, c->phi + fo, c->ch.nsp, R.Lx, cur + po);
+        if (rc) return fail(c, rc, "network prediction failed");
+        const int delta = warm == HSF_WARM_NET_DELTA && c->have_pred && c->fields_set;
+        net_warm_from_net(c->stream, c->w + fo, cur + po, prev + po, R.V, delta ? 1 : 0);
+    }
+    std::swap(c->net_pred[0], c->net_pred[1]);   // this prediction is the next call's previous one
+    c->have_pred = 1;
+    c->fields_set = 1;
+    HIPCHK(c, hipGetLastError());
+    return HSF_OK;
+}
+
 int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats *stats, long long *evals_out)
 {
     if (!(tol >= 0.0) || max_iter < 0) return fail(c, HSF_EINVAL, "bad tol %g or max_iter %d", tol, max_iter);
-    if (warm != HSF_WARM_CURRENT && warm != HSF_WARM_LOCAL) return fail(c, HSF_EINVAL, "bad warm mode %d", warm);
+    if (warm < HSF_WARM_CURRENT || warm > HSF_WARM_NET_DELTA) return fail(c, HSF_EINVAL, "bad warm mode %d", warm);
     hipStream_t s = c->stream;
+    if (warm == HSF_WARM_NET || warm == HSF_WARM_NET_DELTA) {
+        int rc = net_warm(c, warm);
+        if (rc) return rc;
+    } else if (warm == HSF_WARM_EXTRAP && c->have_prev && c->fields_set) {
+        launch_extrapolate(s, c->plan, c->rep_d, c->ch, c->w, c->w_prev);
+    }
     if (warm == HSF_WARM_LOCAL || !c->fields_set)
         launch_local_guess(s, c->plan, c->rep_d, c->ch, c->phi, c->w, c->part);
     target_setup(c, tol, max_iter);
@@ -393,6 +429,9 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
     }
     if ((rc = read_status(c))) return rc;
     HIPCHK(c, hipGetLastError());
+    // keep the result for the extrapolated warm start of the next inversion
+    HIPCHK(c, hipMemcpyAsync(c->w_prev, c->w, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice, s));
+    c->have_prev = 1;
     int status = HSF_OK;
     long long ev = 0;
     for (int r = 0; r < c->n_rep; ++r) {
@@ -529,6 +568,9 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     ALLOC(c->G, rs * N * T);
     ALLOC(c->Gp0, rs * T);
     ALLOC(c->Gp1, rs * T);
+    ALLOC(c->w_prev, sizeof(double) * nsp * T);
+    ALLOC(c->net_pred[0], sizeof(float) * 2 * T);
+    ALLOC(c->net_pred[1], sizeof(float) * 2 * T);
 #undef ALLOC
     if (rc == HSF_OK) {
         hipError_t e = hipHostMalloc((void **)&c->st_h, sizeof(RepState) * n_rep, hipHostMallocDefault);
@@ -768,7 +810,7 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
     if (!c || n_steps < 0) return HSF_EINVAL;
     if (total_evals) *total_evals = 0;
     for (int k = 0; k < n_steps; ++k) {
-        int rc = invert_impl(c, tol, max_iter, HSF_WARM_CURRENT, stats, total_evals);
+        int rc = invert_impl(c, tol, max_iter, c->step_warm, stats, total_evals);
         if (rc != HSF_OK) return rc;
         launch_mu(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->w, c->mu);
         const double *uu = nullptr;
@@ -913,6 +955,21 @@ int hsf_set_solver(hsf_ctx *c, int flags)
                 g.exec = nullptr;
             }
     }
+    return HSF_OK;
+}
+
+int hsf_set_warm(hsf_ctx *c, int warm)
+{
+    if (!c || warm < HSF_WARM_CURRENT || warm > HSF_WARM_NET_DELTA) return HSF_EINVAL;
+    c->step_warm = warm;
+    return HSF_OK;
+}
+
+int hsf_attach_net(hsf_ctx *c, hsf_net *net)
+{
+    if (!c) return HSF_EINVAL;
+    c->net = net;
+    c->have_pred = 0;
     return HSF_OK;
 }
 

@@ -113,5 +113,12 @@ void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const dou
                const double *mu, const double *u, double *phi_out, hipEvent_t e0 = nullptr,
                hipEvent_t e1 = nullptr);
 void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n);
+void launch_extrapolate(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, double *w, const double *w_prev);
 
+}  // namespace hsf
+
+struct hsf_net;
+namespace hsf {
+int net_predict(hsf_net *n, hipStream_t s, const double *phi, int nsp, int L, float *pred);
+void net_warm_from_net(hipStream_t s, double *w, const float *p, const float *p_prev, long long V, int mode);
 }  // namespace hsf

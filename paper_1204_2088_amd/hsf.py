@@ -31,8 +31,11 @@ EXPORTED = [
     "hsf_set_densities", "hsf_get_densities", "hsf_evaluate", "hsf_invert", "hsf_mu_force",
     "hsf_set_lb", "hsf_get_lb", "hsf_lb_advance", "hsf_get_flow", "hsf_cd_advance", "hsf_step",
     "hsf_set_hydro", "hsf_set_timing", "hsf_get_timing", "hsf_set_tile", "hsf_get_tile", "hsf_autotune",
-    "hsf_set_solver", "hsf_get_work",
+    "hsf_set_solver", "hsf_get_work", "hsf_set_warm", "hsf_net_create", "hsf_net_destroy",
+    "hsf_net_last_error", "hsf_net_set_stream", "hsf_net_num_params", "hsf_net_set_params",
+    "hsf_net_get_params", "hsf_net_set_input_norm", "hsf_net_forward", "hsf_net_loss_grad", "hsf_net_train_step", "hsf_attach_net",
 ]
+WARM_EXTRAP, WARM_NET, WARM_NET_DELTA = 2, 3, 4
 SOLVER_PRECOND = 1
 K_PREP, K_FWD, K_BWD, K_LB, K_CD, K_COUNT = 0, 1, 2, 3, 4, 5
 KERNEL_NAMES = ["prep", "fwd", "bwd", "lb", "cd"]
@@ -107,6 +110,19 @@ def load():
         "hsf_set_hydro": ([C, I], I),
         "hsf_set_timing": ([C, I], I),
         "hsf_set_solver": ([C, I], I),
+        "hsf_set_warm": ([C, I], I),
+        "hsf_net_create": ([I, I, ctypes.POINTER(ctypes.c_int), ctypes.c_ulonglong, ctypes.POINTER(C)], I),
+        "hsf_net_destroy": ([C], None),
+        "hsf_net_last_error": ([C], ctypes.c_char_p),
+        "hsf_net_set_stream": ([C, P], I),
+        "hsf_net_num_params": ([C], ctypes.c_longlong),
+        "hsf_net_set_params": ([C, P, I], I),
+        "hsf_net_get_params": ([C, P, I], I),
+        "hsf_net_set_input_norm": ([C, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)], I),
+        "hsf_net_forward": ([C, P, P, I, I, I], I),
+        "hsf_net_loss_grad": ([C, P, P, I, I, ctypes.POINTER(ctypes.c_double), P, I], I),
+        "hsf_net_train_step": ([C, P, P, I, I, ctypes.c_float, ctypes.POINTER(ctypes.c_double), I], I),
+        "hsf_attach_net": ([C, C], I),
         "hsf_get_work": ([C, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double), I], I),
         "hsf_set_tile": ([C, ctypes.POINTER(ctypes.c_int)], I),
         "hsf_get_tile": ([C, ctypes.POINTER(ctypes.c_int)], I),
@@ -141,6 +157,20 @@ def params_from_workload(wl, precision=None):
     prec = precision or wl.precision
     p.precision = FP32 if prec == "fp32" else FP64
     return p
+
+
+def _ptr32(a, n):
+    """(pointer, where) of a float32 buffer holding at least n elements."""
+    if a is None:
+        return None, HOST
+    if _is_torch(a):
+        import torch
+        assert a.dtype == torch.float32 and a.is_contiguous(), "need a contiguous float32 tensor"
+        assert a.numel() >= n, (a.numel(), n)
+        return ctypes.c_void_p(a.data_ptr()), (DEVICE if a.is_cuda else HOST)
+    assert isinstance(a, np.ndarray) and a.dtype == np.float32 and a.flags.c_contiguous
+    assert a.size >= n, (a.size, n)
+    return ctypes.c_void_p(a.ctypes.data), HOST
 
 
 def _is_torch(a):
@@ -319,6 +349,14 @@ class Context:
         self._check(self._lib.hsf_get_work(self._h, ctypes.byref(ev), ctypes.byref(se), int(bool(reset))))
         return ev.value, se.value
 
+    def set_warm(self, warm):
+        """Warm start of hsf_step's inversions (WARM_CURRENT, WARM_EXTRAP, WARM_NET, WARM_NET_DELTA)."""
+        self._check(self._lib.hsf_set_warm(self._h, int(warm)))
+
+    def attach_net(self, net):
+        self._check(self._lib.hsf_attach_net(self._h, net._h if net is not None else None))
+        self._net = net   # keep it alive while attached
+
     def set_timing(self, on):
         self._check(self._lib.hsf_set_timing(self._h, int(bool(on))))
 
@@ -328,3 +366,76 @@ class Context:
         cnt = (ctypes.c_longlong * K_COUNT)()
         self._check(self._lib.hsf_get_timing(self._h, ms, cnt))
         return {KERNEL_NAMES[k]: (ms[k], cnt[k]) for k in range(K_COUNT)}
+
+
+class Net:
+    """The warm-start U-Net (FP32 boundary arrays [batch][channel][L][L][L])."""
+
+    def __init__(self, in_ch, out_ch=2, widths=(8, 16, 24, 32), seed=0, stream=None):
+        lib = load()
+        w = (ctypes.c_int * 4)(*[int(v) for v in widths])
+        h = ctypes.c_void_p()
+        rc = lib.hsf_net_create(int(in_ch), int(out_ch), w, ctypes.c_ulonglong(seed), ctypes.byref(h))
+        if rc != HSF_OK:
+            raise HsfError(rc, "hsf_net_create failed")
+        self._h, self._lib = h, lib
+        self.in_ch, self.out_ch, self.widths = in_ch, out_ch, tuple(widths)
+        self.n_params = lib.hsf_net_num_params(h)
+        if stream is not None:
+            raw = getattr(stream, "cuda_stream", stream)
+            self._check(lib.hsf_net_set_stream(h, ctypes.c_void_p(raw or 0)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hsf_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != HSF_OK:
+            raise HsfError(rc, self._lib.hsf_net_last_error(self._h).decode())
+
+    def set_params(self, p):
+        ptr, where = _ptr32(p, self.n_params)
+        self._check(self._lib.hsf_net_set_params(self._h, ptr, where))
+
+    def set_input_norm(self, shift, scale):
+        sh = (ctypes.c_float * self.in_ch)(*[float(v) for v in shift])
+        sc = (ctypes.c_float * self.in_ch)(*[float(v) for v in scale])
+        self._check(self._lib.hsf_net_set_input_norm(self._h, sh, sc))
+
+    def get_params(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        ptr, where = _ptr32(out, self.n_params)
+        self._check(self._lib.hsf_net_get_params(self._h, ptr, where))
+        return out
+
+    def forward(self, x, batch, L, out=None):
+        if out is None:
+            out = np.empty(batch * self.out_ch * L ** 3, dtype=np.float32)
+        pi, where = _ptr32(x, batch * self.in_ch * L ** 3)
+        po, _ = _ptr32(out, batch * self.out_ch * L ** 3)
+        self._check(self._lib.hsf_net_forward(self._h, pi, po, int(batch), int(L), where))
+        return out
+
+    def loss_grad(self, x, target, batch, L, with_grad=True):
+        grad = np.empty(self.n_params, dtype=np.float32) if with_grad else None
+        loss = ctypes.c_double(0.0)
+        pi, where = _ptr32(x, batch * self.in_ch * L ** 3)
+        pt, _ = _ptr32(target, batch * self.out_ch * L ** 3)
+        pg, _ = _ptr32(grad, self.n_params)
+        self._check(self._lib.hsf_net_loss_grad(self._h, pi, pt, int(batch), int(L), ctypes.byref(loss), pg, where))
+        return loss.value, grad
+
+    def train_step(self, x, target, batch, L, lr):
+        loss = ctypes.c_double(0.0)
+        pi, where = _ptr32(x, batch * self.in_ch * L ** 3)
+        pt, _ = _ptr32(target, batch * self.out_ch * L ** 3)
+        self._check(self._lib.hsf_net_train_step(self._h, pi, pt, int(batch), int(L), ctypes.c_float(lr),
+                                                 ctypes.byref(loss), where))
+        return loss.value
