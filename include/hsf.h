@@ -74,11 +74,21 @@ enum { HSF_FP64 = 0, HSF_FP32 = 1 };
 enum {
     HSF_WARM_CURRENT = 0,   /* the fields currently held (previous step's result)   */
     HSF_WARM_LOCAL = 1,     /* local ideal-gas guess w_I = -ln(phi_I / <phi_I>)     */
-    HSF_WARM_EXTRAP = 2,    /* linear extrapolation 2 w^n - w^(n-1) of the previous */
-                            /* two inversions' results                              */
-    HSF_WARM_NET = 3,       /* polymer fields predicted by the attached network     */
-    HSF_WARM_NET_DELTA = 4  /* w^n + net(phi^(n+1)) - net(phi^n)                    */
+    HSF_WARM_EXTRAP = 2,    /* w + w^n - w^(n-1): linear extrapolation from the     */
+                            /* previous two inversions' results                     */
+    HSF_WARM_NET = 3,       /* polymer fields = net(phi) (network with nsp inputs)  */
+    HSF_WARM_NET_DELTA = 4, /* w + r net(phi^n, (phi - phi^n) / r)                  */
+    HSF_WARM_NET_EXTRAP = 5 /* w + w^n - w^(n-1)                                    */
+                            /*   + r net(phi^n, (phi - 2 phi^n + phi^(n-1)) / r)    */
 };
+/* In the warm starts, w are the fields held, phi the target densities of the new
+ * inversion, w^n, phi^n (w^(n-1), phi^(n-1)) the converged fields and targets of
+ * the latest (the one before) inversion, and r the rms over species and sites of
+ * the density difference fed to the network.  NET_DELTA and NET_EXTRAP take a
+ * network with 2 nsp inputs and 2 outputs that predicts the field change per unit
+ * density change (the linear response of the inversion).  Modes that lack history
+ * fall back: NET_EXTRAP to NET_DELTA after one inversion, NET_DELTA and EXTRAP to
+ * the current fields.  hsf_set_fields clears the history. */
 
 typedef struct {
     int Lx, Ly, Lz;              /* periodic box of this replica               */
@@ -252,8 +262,11 @@ int hsf_net_loss_grad(hsf_net *net, const float *in, const float *target, int ba
 /* one Adam step (beta 0.9, 0.999, eps 1e-8) on the mean square error */
 int hsf_net_train_step(hsf_net *net, const float *in, const float *target, int batch, int L, float lr,
                        double *loss, int where);
-/* Attach a network (in_ch = species, out_ch = 2) to a context for the NET warm
- * starts; the context does not own it.  NULL detaches. */
+/* Attach a network to a context for the NET warm starts (in_ch = nsp for
+ * HSF_WARM_NET, 2 nsp for HSF_WARM_NET_DELTA and HSF_WARM_NET_EXTRAP; out_ch = 2);
+ * the context does not own it.  NULL detaches.  The inputs the network sees for
+ * one replica are FP32 [channel][V]: HSF_WARM_NET the target densities; the delta
+ * modes phi^n (nsp channels) followed by the density difference divided by r. */
 int hsf_attach_net(hsf_ctx *ctx, hsf_net *net);
 
 /* Kernel families timed by hsf_set_timing. */

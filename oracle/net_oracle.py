@@ -42,7 +42,10 @@ def unpack(params, in_ch, out_ch, widths):
 
 
 def to_bf16(t):
-    return t.to(torch.bfloat16).to(torch.float64)
+    """Value rounded to bfloat16 (round to nearest even); the derivative of the
+    rounding is taken as one, so gradients pass through it unrounded in float64."""
+    r = t.detach().to(torch.bfloat16).to(torch.float64)
+    return t + (r - t.detach())
 
 
 def conv_periodic(x, W, b, bf16=False):

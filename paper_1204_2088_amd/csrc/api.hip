@@ -43,6 +43,7 @@ struct hsf_ctx {
     double *g = nullptr, *gt = nullptr, *d = nullptr, *acc = nullptr;
     double *nA = nullptr, *nB = nullptr, *rho = nullptr, *u = nullptr, *force = nullptr, *uin = nullptr;
     double *part = nullptr, *partG = nullptr;
+    int part_cap = 0;                  // doubles in `part`
     // propagators in the chosen precision
     void *E = nullptr, *G = nullptr, *Gp0 = nullptr, *Gp1 = nullptr;
     std::vector<void *> allocs;
@@ -64,11 +65,13 @@ struct hsf_ctx {
     // optional per-launch timing of the hot kernels with HIP events on the context stream
     // warm starts
     int step_warm = HSF_WARM_CURRENT;  // used by hsf_step
-    double *w_prev = nullptr;          // fields after the previous inversion (extrapolation)
-    int have_prev = 0;
+    // converged fields and target densities of the last two inversions ([0] the latest)
+    double *w_hist[2] = {nullptr, nullptr}, *phi_hist[2] = {nullptr, nullptr};
+    int n_hist = 0;                    // how many of them are valid
     hsf_net *net = nullptr;            // attached network (not owned)
-    float *net_pred[2] = {nullptr, nullptr};   // current / previous predictions [rep][2][V]
-    int have_pred = 0;
+    float *net_in = nullptr;           // network input, [2 nsp][V] per replica
+    float *net_pred = nullptr;         // network output, [2][V] per replica
+    double *net_rms = nullptr;         // per replica: rms of the density difference
     long long work_evals = 0;          // density-functional evaluations, all replicas
     double work_site_evals = 0.0;      // sum over replicas of evaluations x sites
     int timing = 0;
@@ -346,24 +349,52 @@ void target_setup(hsf_ctx *c, double tol, int max_iter)
                       max_iter);
 }
 
-// Starting fields from the network (NET: the prediction; NET_DELTA: the current fields
-// plus the change of the prediction since the previous call).
-int net_warm(hsf_ctx *c, int warm)
+// Starting fields of an inversion (the warm start), before the gauge is fixed.
+//   EXTRAP      w += w^n - w^(n-1)
+//   NET         polymer fields = net(phi)
+//   NET_DELTA   w += r net(phi^n, (phi - phi^n) / r)
+//   NET_EXTRAP  w += w^n - w^(n-1) + r net(phi^n, (phi - 2 phi^n + phi^(n-1)) / r)
+// with w^n, phi^n the converged fields and target densities of the latest inversion
+// and r the rms of the density difference.  Without enough history the modes fall
+// back: NET_EXTRAP to NET_DELTA, NET_DELTA and EXTRAP to the current fields.
+int warm_start(hsf_ctx *c, int warm)
 {
+    hipStream_t s = c->stream;
+    const int nsp = c->ch.nsp;
+    if (warm == HSF_WARM_EXTRAP) {
+        if (c->n_hist >= 2 && c->fields_set)
+            for (int r = 0; r < c->n_rep; ++r) {
+                const long long fo = (long long)nsp * c->reps[r].site_off;
+                net_shift_fields(s, c->w + fo, c->w_hist[0] + fo, c->w_hist[1] + fo, 2 * c->reps[r].V);
+            }
+        return HSF_OK;
+    }
+    if (warm != HSF_WARM_NET && warm != HSF_WARM_NET_DELTA && warm != HSF_WARM_NET_EXTRAP) return HSF_OK;
     if (!c->net) return fail(c, HSF_EINVAL, "no network attached");
-    float *cur = c->net_pred[0], *prev = c->net_pred[1];
+    int mode = 0;   // 0: absolute, 1: first difference, 2: second difference
+    if (warm == HSF_WARM_NET_DELTA || warm == HSF_WARM_NET_EXTRAP) {
+        if (!c->fields_set || c->n_hist < 1) return HSF_OK;
+        mode = (warm == HSF_WARM_NET_EXTRAP && c->n_hist >= 2) ? 2 : 1;
+    }
+    int in_ch = 0, out_ch = 0;
+    net_channels(c->net, &in_ch, &out_ch);
+    const int want = mode == 0 ? nsp : 2 * nsp;
+    if (in_ch != want || out_ch != 2)
+        return fail(c, HSF_EINVAL, "network has %d inputs and %d outputs; this warm start needs %d and 2", in_ch,
+                    out_ch, want);
+    const int max_parts = c->part_cap;
     for (int r = 0; r < c->n_rep; ++r) {
         const Rep &R = c->reps[r];
         if (R.Lx != R.Ly || R.Lx != R.Lz || R.Lx % 8)
             return fail(c, HSF_EINVAL, "network warm start needs cubic boxes with L a multiple of 8");
-        const long long fo = (long long)c->ch.nsp * R.site_off, po = 2LL * R.site_off;
-        int rc = net_predict(c->net, c->stream, c->phi + fo, c->ch.nsp, R.Lx, cur + po);
+        const long long fo = (long long)nsp * R.site_off, po = 2LL * R.site_off;
+        float *x = c->net_in + 2 * fo, *pred = c->net_pred + po;
+        net_warm_input(s, c->phi + fo, c->phi_hist[0] + fo, c->phi_hist[1] + fo, nsp, R.V, mode, c->part,
+                       max_parts, c->net_rms + r, x);
+        int rc = net_predict(c->net, s, x, want, R.Lx, pred);
         if (rc) return fail(c, rc, "network prediction failed");
-        const int delta = warm == HSF_WARM_NET_DELTA && c->have_pred && c->fields_set;
-        net_warm_from_net(c->stream, c->w + fo, cur + po, prev + po, R.V, delta ? 1 : 0);
+        net_warm_apply(s, c->w + fo, pred, R.V, mode, c->net_rms + r, c->w_hist[0] + fo, c->w_hist[1] + fo);
     }
-    std::swap(c->net_pred[0], c->net_pred[1]);   // this prediction is the next call's previous one
-    c->have_pred = 1;
     c->fields_set = 1;
     HIPCHK(c, hipGetLastError());
     return HSF_OK;
@@ -372,14 +403,9 @@ int net_warm(hsf_ctx *c, int warm)
 int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats *stats, long long *evals_out)
 {
     if (!(tol >= 0.0) || max_iter < 0) return fail(c, HSF_EINVAL, "bad tol %g or max_iter %d", tol, max_iter);
-    if (warm < HSF_WARM_CURRENT || warm > HSF_WARM_NET_DELTA) return fail(c, HSF_EINVAL, "bad warm mode %d", warm);
+    if (warm < HSF_WARM_CURRENT || warm > HSF_WARM_NET_EXTRAP) return fail(c, HSF_EINVAL, "bad warm mode %d", warm);
     hipStream_t s = c->stream;
-    if (warm == HSF_WARM_NET || warm == HSF_WARM_NET_DELTA) {
-        int rc = net_warm(c, warm);
-        if (rc) return rc;
-    } else if (warm == HSF_WARM_EXTRAP && c->have_prev && c->fields_set) {
-        launch_extrapolate(s, c->plan, c->rep_d, c->ch, c->w, c->w_prev);
-    }
+    if (int rc = warm_start(c, warm)) return rc;
     if (warm == HSF_WARM_LOCAL || !c->fields_set)
         launch_local_guess(s, c->plan, c->rep_d, c->ch, c->phi, c->w, c->part);
     target_setup(c, tol, max_iter);
@@ -429,9 +455,12 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
     }
     if ((rc = read_status(c))) return rc;
     HIPCHK(c, hipGetLastError());
-    // keep the result for the extrapolated warm start of the next inversion
-    HIPCHK(c, hipMemcpyAsync(c->w_prev, c->w, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice, s));
-    c->have_prev = 1;
+    // keep the result and its target for the warm starts of the next inversions
+    std::swap(c->w_hist[0], c->w_hist[1]);
+    std::swap(c->phi_hist[0], c->phi_hist[1]);
+    HIPCHK(c, hipMemcpyAsync(c->w_hist[0], c->w, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->phi_hist[0], c->phi, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice, s));
+    c->n_hist = std::min(c->n_hist + 1, 2);
     int status = HSF_OK;
     long long ev = 0;
     for (int r = 0; r < c->n_rep; ++r) {
@@ -561,6 +590,7 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     ALLOC(c->uin, sizeof(double) * 3 * T);
     ALLOC(c->force, sizeof(double) * 3 * T);
     ALLOC(c->part, sizeof(double) * kNQ * max_blocks);
+    c->part_cap = kNQ * max_blocks;
     ALLOC(c->partG, sizeof(double) * (N + 2) * max_blocks);
     ALLOC(c->tplan.blk_rep, sizeof(int) * c->max_tile_blocks);
     ALLOC(c->tplan.blk_first, sizeof(int) * (n_rep + 1));
@@ -568,9 +598,13 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     ALLOC(c->G, rs * N * T);
     ALLOC(c->Gp0, rs * T);
     ALLOC(c->Gp1, rs * T);
-    ALLOC(c->w_prev, sizeof(double) * nsp * T);
-    ALLOC(c->net_pred[0], sizeof(float) * 2 * T);
-    ALLOC(c->net_pred[1], sizeof(float) * 2 * T);
+    for (int h = 0; h < 2; ++h) {
+        ALLOC(c->w_hist[h], sizeof(double) * nsp * T);
+        ALLOC(c->phi_hist[h], sizeof(double) * nsp * T);
+    }
+    ALLOC(c->net_in, sizeof(float) * 2 * nsp * T);
+    ALLOC(c->net_pred, sizeof(float) * 2 * T);
+    ALLOC(c->net_rms, sizeof(double) * n_rep);
 #undef ALLOC
     if (rc == HSF_OK) {
         hipError_t e = hipHostMalloc((void **)&c->st_h, sizeof(RepState) * n_rep, hipHostMallocDefault);
@@ -671,7 +705,10 @@ int hsf_set_fields(hsf_ctx *c, const double *w, int where)
 {
     if (!c) return HSF_EINVAL;
     int rc = copy_in(c, c->w, w, (size_t)c->ch.nsp * c->T, where);
-    if (rc == HSF_OK) c->fields_set = 1;
+    if (rc == HSF_OK) {
+        c->fields_set = 1;
+        c->n_hist = 0;   // fields set from outside: the inversion history no longer applies
+    }
     return rc;
 }
 
@@ -960,7 +997,7 @@ int hsf_set_solver(hsf_ctx *c, int flags)
 
 int hsf_set_warm(hsf_ctx *c, int warm)
 {
-    if (!c || warm < HSF_WARM_CURRENT || warm > HSF_WARM_NET_DELTA) return HSF_EINVAL;
+    if (!c || warm < HSF_WARM_CURRENT || warm > HSF_WARM_NET_EXTRAP) return HSF_EINVAL;
     c->step_warm = warm;
     return HSF_OK;
 }
@@ -969,7 +1006,6 @@ int hsf_attach_net(hsf_ctx *c, hsf_net *net)
 {
     if (!c) return HSF_EINVAL;
     c->net = net;
-    c->have_pred = 0;
     return HSF_OK;
 }
 

@@ -445,27 +445,4 @@ void launch_solvent(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, 
 
 namespace hsf {
 
-// w = 2 w - w_prev for the polymer species (linear extrapolation of the fields).
-__global__ __launch_bounds__(kBlock) void k_extrapolate(const int *__restrict__ blk_rep,
-                                                        const int *__restrict__ blk_first,
-                                                        const Rep *__restrict__ rep, Chain ch,
-                                                        double *__restrict__ w, const double *__restrict__ w_prev)
-{
-    const SiteRef sr = site_ref(blk_rep, blk_first);
-    const Rep &R = rep[sr.r];
-    const long long V = R.V, i = sr.i;
-    if (i >= V) return;
-    const long long fo = off_field(R, ch.nsp);
-    for (int I = 0; I < 2; ++I) {
-        const long long k = fo + I * V + i;
-        w[k] = 2.0 * w[k] - w_prev[k];
-    }
-}
-
-void launch_extrapolate(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, double *w, const double *w_prev)
-{
-    hipLaunchKernelGGL(k_extrapolate, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch, w,
-                       w_prev);
-}
-
 }  // namespace hsf

@@ -113,12 +113,16 @@ void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const dou
                const double *mu, const double *u, double *phi_out, hipEvent_t e0 = nullptr,
                hipEvent_t e1 = nullptr);
 void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n);
-void launch_extrapolate(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, double *w, const double *w_prev);
 
 }  // namespace hsf
 
 struct hsf_net;
 namespace hsf {
-int net_predict(hsf_net *n, hipStream_t s, const double *phi, int nsp, int L, float *pred);
-void net_warm_from_net(hipStream_t s, double *w, const float *p, const float *p_prev, long long V, int mode);
+int net_predict(hsf_net *n, hipStream_t s, const float *x, int in_ch, int L, float *pred);
+int net_channels(const hsf_net *n, int *in_ch, int *out_ch);
+void net_warm_input(hipStream_t s, const double *phi, const double *h0, const double *h1, int nsp, long long V,
+                    int mode, double *part, int max_parts, double *rms, float *x);
+void net_warm_apply(hipStream_t s, double *w, const float *p, long long V, int mode, const double *rms,
+                    const double *wh0, const double *wh1);
+void net_shift_fields(hipStream_t s, double *w, const double *wh0, const double *wh1, long long n);
 }  // namespace hsf

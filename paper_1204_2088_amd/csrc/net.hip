@@ -68,8 +68,10 @@ struct hsf_net {
     Tensor x0, y[kLayers], a[kLayers], p1, p2, p3, u3, u2, u1, t3, t2, t1;
     Tensor dy[kLayers], da[kLayers], dp1, dp2, dp3, du3, du2, du1, dt3, dt2, dt1, dout;
     float *target = nullptr, *wpart = nullptr;
+    double *bpart = nullptr;         // per-channel partial sums of the bias gradient
     double *loss_part = nullptr, *loss_host = nullptr;
     int weights_staged = 0;
+    int training = 0;                // the current forward pass feeds a backward pass
 };
 
 namespace {
@@ -111,6 +113,15 @@ void free_acts(hsf_net *n)
     for (void *p : n->act_allocs) (void)hipFree(p);
     n->act_allocs.clear();
     n->cur_B = n->cur_L = 0;
+    // forget every pointer into the freed buffers (a later allocation without the
+    // gradient tensors must not find stale ones)
+    for (Tensor *t : {&n->x0, &n->p1, &n->p2, &n->p3, &n->u3, &n->u2, &n->u1, &n->t3, &n->t2, &n->t1, &n->dp1,
+                      &n->dp2, &n->dp3, &n->du3, &n->du2, &n->du1, &n->dt3, &n->dt2, &n->dt1, &n->dout})
+        *t = Tensor();
+    for (int l = 0; l < kLayers; ++l) n->y[l] = n->a[l] = n->dy[l] = n->da[l] = Tensor();
+    n->target = n->wpart = nullptr;
+    n->bpart = nullptr;
+    n->loss_part = nullptr;
 }
 
 // (Re)allocate the activation and gradient tensors for batch B on an L^3 box.
@@ -159,9 +170,11 @@ int ensure_acts(hsf_net *n, int B, int L, bool grads)
         size_t wp = 0;
         for (int l = 0; l < kLayers; ++l) {
             const Layer &Ly = n->layer[l];
-            wp = std::max(wp, (size_t)net_wgrad_blocks(B, L >> Ly.level) * Ly.cop * Ly.kp);
+            wp = std::max(wp, (size_t)net_wgrad_slices(B, L >> Ly.level, Ly.cop, Ly.kp) * Ly.cop * Ly.kp);
         }
         if (rc == HSF_OK) rc = nalloc(n, n->act_allocs, (void **)&n->wpart, sizeof(float) * wp);
+        if (rc == HSF_OK)
+            rc = nalloc(n, n->act_allocs, (void **)&n->bpart, sizeof(double) * net_channel_parts(kNetMaxWidth));
         const size_t lb = ((size_t)B * n->out_ch * vol(L, 0) + 255) / 256;
         if (rc == HSF_OK) rc = nalloc(n, n->act_allocs, (void **)&n->loss_part, sizeof(double) * lb);
     }
@@ -186,10 +199,13 @@ int stage_weights(hsf_net *n)
     return HSF_OK;
 }
 
+// Forward of layer l.  The pre-activation y[l] is kept only when a backward pass
+// follows (training); inference writes the activation alone.
 void conv(hsf_net *n, int l, const Tensor &in, int B)
 {
     const Layer &Ly = n->layer[l];
-    net_conv_fwd(n->stream, in.p, B, Ly.ci, Ly.cip, Ly.Wm, Ly.kp, Ly.co, Ly.cop, n->params + Ly.b_off, n->y[l].p,
+    float *y = (Ly.act && !n->training) ? nullptr : n->y[l].p;
+    net_conv_fwd(n->stream, in.p, B, Ly.ci, Ly.cip, Ly.Wm, Ly.kp, Ly.co, Ly.cop, n->params + Ly.b_off, y,
                  Ly.act ? n->a[l].p : nullptr, n->cur_L >> Ly.level);
 }
 
@@ -234,7 +250,7 @@ void conv_bwd(hsf_net *n, int l, const Tensor &in, float *din)
     const int B = n->cur_B, Ll = n->cur_L >> Ly.level;
     net_conv_wgrad(n->stream, in.p, B, Ly.ci, Ly.cip, n->dy[l].p, Ly.co, Ly.cop, Ly.kp, Ll, n->wpart, Ly.dWm);
     net_unstage_grad(n->stream, Ly.dWm, Ly.co, Ly.ci, Ly.cip, Ly.kp, n->grad + Ly.w_off);
-    net_channel_sum(n->stream, n->dy[l].p, B, Ly.co, vol(n->cur_L, Ly.level), n->grad + Ly.b_off);
+    net_channel_sum(n->stream, n->dy[l].p, B, Ly.co, vol(n->cur_L, Ly.level), n->bpart, n->grad + Ly.b_off);
     if (din)
         net_conv_fwd(n->stream, n->dy[l].p, B, Ly.co, Ly.cip_t, Ly.Wt, Ly.kp_t, Ly.ci, Ly.cop_t, nullptr, din,
                      nullptr, Ll);
@@ -321,7 +337,9 @@ int loss_and_grad(hsf_net *n, double *loss)
         int rc = stage_weights(n);
         if (rc) return rc;
     }
+    n->training = 1;
     forward(n);
+    n->training = 0;
     const long long cnt = numel(n, n->dout);
     const int blocks = net_mse(n->stream, n->y[14].p, n->target, n->dout.p, cnt, 1.0f / (float)cnt, n->loss_part);
     backward(n);
@@ -524,11 +542,11 @@ int hsf_net_train_step(hsf_net *n, const float *in, const float *target, int bat
 
 namespace hsf {
 
-// Predict the two polymer fields of one replica from its densities (FP64, [nsp][V]).
-// pred receives [2][V] FP32 (device).  Returns an HSF code.
-int net_predict(hsf_net *n, hipStream_t s, const double *phi, int nsp, int L, float *pred)
+// Prediction for one replica: x is the prepared FP32 input [in_ch][V] (device), pred
+// receives [out_ch][V] FP32 (device).  Returns an HSF code.
+int net_predict(hsf_net *n, hipStream_t s, const float *x, int in_ch, int L, float *pred)
 {
-    if (!n || nsp != n->in_ch || n->out_ch != 2) return HSF_EINVAL;
+    if (!n || in_ch != n->in_ch) return HSF_EINVAL;
     int rc = check_box(n, 1, L);
     if (rc) return rc;
     hipStream_t saved = n->stream;
@@ -537,11 +555,21 @@ int net_predict(hsf_net *n, hipStream_t s, const double *phi, int nsp, int L, fl
         n->stream = saved;
         return rc;
     }
-    net_f64_to_f32(s, phi, n->x0.p, (long long)nsp * vol(L, 0));
-    forward(n);
-    hipError_t e = hipMemcpyAsync(pred, n->y[14].p, sizeof(float) * 2 * vol(L, 0), hipMemcpyDeviceToDevice, s);
+    hipError_t e = hipMemcpyAsync(n->x0.p, x, sizeof(float) * in_ch * vol(L, 0), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) {
+        forward(n);
+        e = hipMemcpyAsync(pred, n->y[14].p, sizeof(float) * n->out_ch * vol(L, 0), hipMemcpyDeviceToDevice, s);
+    }
     n->stream = saved;
     return e == hipSuccess ? HSF_OK : HSF_EHIP;
+}
+
+int net_channels(const hsf_net *n, int *in_ch, int *out_ch)
+{
+    if (!n) return HSF_EINVAL;
+    *in_ch = n->in_ch;
+    *out_ch = n->out_ch;
+    return HSF_OK;
 }
 
 }  // namespace hsf

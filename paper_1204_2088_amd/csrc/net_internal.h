@@ -9,7 +9,7 @@ constexpr int kNetMaxWidth = 32;   // widest layer the weight-gradient kernel su
 
 void net_conv_fwd(hipStream_t s, const float *X, int B, int ci, int cip, const __bf16 *Wm, int kp, int co, int cop,
                   const float *bias, float *Y, float *A, int L);
-int net_wgrad_blocks(int B, int L);
+int net_wgrad_slices(int B, int L, int cop, int kp);
 void net_conv_wgrad(hipStream_t s, const float *X, int B, int ci, int cip, const float *dY, int co, int cop, int kp,
                     int L, float *part, float *dWm);
 void net_silu_bwd(hipStream_t s, const float *dA, const float *Y, float *dY, long long n);
@@ -18,15 +18,21 @@ void net_pool_bwd(hipStream_t s, const float *dout, float *din, int L, long long
 void net_up(hipStream_t s, const float *in, float *out, int L, long long n_out);
 void net_up_bwd(hipStream_t s, const float *dout, float *din, int L, long long n_in);
 void net_add(hipStream_t s, const float *a, const float *b, float *c, long long n);
-void net_channel_sum(hipStream_t s, const float *g, int B, int C, long long V, float *out);
+int net_channel_parts(int C);
+void net_channel_sum(hipStream_t s, const float *g, int B, int C, long long V, double *part, float *out);
 int net_mse(hipStream_t s, const float *p, const float *t, float *dp, long long n, float inv_count, double *part);
 void net_adam(hipStream_t s, float *w, const float *g, float *m, float *v, long long n, float lr, float b1, float b2,
               float eps, float c1, float c2);
 void net_stage_weights(hipStream_t s, const float *W, int co, int ci, int cip, int kp, int cop_rows, __bf16 *Wm,
                        int cip_t, int kp_t, int cop_rows_t, __bf16 *Wt);
 void net_unstage_grad(hipStream_t s, const float *dWm, int co, int ci, int cip, int kp, float *dW);
-void net_warm_from_net(hipStream_t s, double *w, const float *p, const float *p_prev, long long V, int mode);
-void net_f64_to_f32(hipStream_t s, const double *a, float *b, long long n);
+// Warm start from the network.  mode 0: input phi; 1: (h0, (phi - h0) / rms);
+// 2: (h0, (phi - 2 h0 + h1) / rms), rms computed on the device into *rms.
+void net_warm_input(hipStream_t s, const double *phi, const double *h0, const double *h1, int nsp, long long V,
+                    int mode, double *part, int max_parts, double *rms, float *x);
+void net_warm_apply(hipStream_t s, double *w, const float *p, long long V, int mode, const double *rms,
+                    const double *wh0, const double *wh1);
+void net_shift_fields(hipStream_t s, double *w, const double *wh0, const double *wh1, long long n);
 void net_affine(hipStream_t s, float *x, int C, long long V, long long n, const float *shift, const float *scale);
 
 }  // namespace hsf

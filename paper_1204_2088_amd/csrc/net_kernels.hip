@@ -13,6 +13,7 @@
 // row l % 16, k = 8 (l / 16) + j; B (32 x 16): column l % 16, same k; C (16 x 16):
 // column l % 16, rows 4 (l / 16) + i.
 #include <hip/hip_ext.h>
+#include <algorithm>
 #include <math.h>
 
 #include "net_internal.h"
@@ -37,11 +38,59 @@ __device__ __forceinline__ float silu_grad(float y)
 
 // ---------------------------------------------------------------- forward convolution
 // Y[b][co][x] = bias[co] + sum_{ci,k} W[co][ci][k] X[b][ci][x + off_k]; optional
-// A = silu(Y).  Block: a TX x TY x TZ tile of one sample (128 sites, 8 MFMA column
-// tiles, two per wave); the input tile with a one-site halo is staged in LDS as BF16
-// [halo site][cip].
+// A = silu(Y); Y may be null when only A is needed (inference).  Block: a TX x TY x TZ tile of one sample (128 sites, 8 MFMA column
+// tiles, two per wave).  The input tile with a one-site halo is staged in LDS as BF16
+// [halo site][cip]; the weights follow in slabs of kSlab K chunks (32 rows of K
+// each), [cop][kSlab * 32 + 8] (the 8 extra columns stagger the rows over the LDS
+// banks), so the K loop reads only LDS.
 constexpr int TX = 8, TY = 4, TZ = 4, TS = TX * TY * TZ;
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HS = HX * HY * HZ;
+constexpr int kSlab = 9;
+constexpr int kSlabRow = kSlab * 32 + 8;
+
+// periodic index for -L <= v < 2L (boxes at least one tile wide), general otherwise
+__device__ __forceinline__ int wrap_tile(int v, int L, bool small)
+{
+    if (small) return wrapL(v, L);
+    return v < 0 ? v + L : (v >= L ? v - L : v);
+}
+
+size_t conv_fwd_lds(int cip, int cop) { return (size_t)(HS * cip + cop * kSlabRow) * sizeof(__bf16); }
+
+// Stage the input tile of one sample with its one-site halo into LDS as BF16, either
+// site-major xs[h][cip] (forward) or channel-major xs[c][HS] (weight gradient);
+// channels ci..cip-1 are zero.  Loads are issued eight per thread before any is used,
+// so their latencies overlap.
+template <bool SITE_MAJOR>
+__device__ __forceinline__ void stage_halo(const float *__restrict__ Xb, long long V, int ci, int cip, int L, int x0,
+                                           int y0, int z0, __bf16 *xs)
+{
+    const bool small = L < TX;
+    const int total = HS * cip;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * 256;
+            v[u] = 0.0f;
+            const int h = e % HS, c = e / HS;
+            if (e < total && c < ci) {
+                const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+                const int gx = wrap_tile(x0 + hx - 1, L, small), gy = wrap_tile(y0 + hy - 1, L, small),
+                          gz = wrap_tile(z0 + hz - 1, L, small);
+                v[u] = Xb[(long long)c * V + gx + (long long)L * (gy + (long long)L * gz)];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * 256;
+            if (e < total) {
+                const int h = e % HS, c = e / HS;
+                xs[SITE_MAJOR ? h * cip + c : c * HS + h] = (__bf16)v[u];
+            }
+        }
+    }
+}
 
 __global__ __launch_bounds__(256) void k_conv_fwd(const float *__restrict__ X, int ci, int cip,
                                                    const __bf16 *__restrict__ Wm, int kp, int co, int cop,
@@ -51,6 +100,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float *__restrict__ X, i
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16 *xs = reinterpret_cast<__bf16 *>(smem);   // [HS][cip]
+    __bf16 *ws = xs + HS * cip;                       // [cop][kSlabRow]
     const int b = blockIdx.x / tiles_per_sample;
     int t = blockIdx.x % tiles_per_sample;
     const int x0 = (t % tiles_x) * TX;
@@ -58,19 +108,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float *__restrict__ X, i
     const int y0 = (t % tiles_y) * TY;
     const int z0 = (t / tiles_y) * TZ;
     const long long V = (long long)L * L * L;
-    const float *Xb = X + (long long)b * ci * V;
-    // stage the halo tile
-    for (int e = threadIdx.x; e < HS * cip; e += 256) {
-        const int h = e % HS, c = e / HS;
-        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
-        float v = 0.0f;
-        if (c < ci) {
-            const int gx = wrapL(x0 + hx - 1, L), gy = wrapL(y0 + hy - 1, L), gz = wrapL(z0 + hz - 1, L);
-            v = Xb[(long long)c * V + gx + (long long)L * (gy + (long long)L * gz)];
-        }
-        xs[h * cip + c] = (__bf16)v;
-    }
-    __syncthreads();
+    stage_halo<true>(X + (long long)b * ci * V, V, ci, cip, L, x0, y0, z0, xs);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane >> 4, col = lane & 15;
     const int nmt = cop / 16;
@@ -87,26 +125,51 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float *__restrict__ X, i
         const int tx = n % TX, ty = (n / TX) % TY, tz = n / (TX * TY);
         hbase[q] = (tz + 1) * HX * HY + (ty + 1) * HX + (tx + 1);
     }
-    for (int kc = 0; kc < kp; kc += 32) {
-        const int kk = kc + 8 * grp;
-        int k = kk / cip;
-        const int c0 = kk - k * cip;
-        if (k > 26) k = 13;   // padding rows of K: zero weights, any finite input
-        const int off = ((k / 9) - 1) * HX * HY + (((k / 3) % 3) - 1) * HX + ((k % 3) - 1);
-        bf16x8 bv[2];
+    for (int k0 = 0; k0 < kp; k0 += kSlab * 32) {
+        const int klen = min(kSlab * 32, kp - k0);
+        __syncthreads();   // previous slab consumed
+        const int vec_per_row = klen / 8, nvec = cop * vec_per_row;
+        for (int e0 = threadIdx.x; e0 < nvec; e0 += 256 * 4) {   // four 16-byte loads in flight
+            bf16x8 wv[4];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) bv[q] = *reinterpret_cast<const bf16x8 *>(xs + (hbase[q] + off) * cip + c0);
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * 256;
+                if (e < nvec) {
+                    const int r = e / vec_per_row, v8 = e - r * vec_per_row;
+                    wv[u] = *reinterpret_cast<const bf16x8 *>(Wm + (long long)r * kp + k0 + 8 * v8);
+                }
+            }
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            if (m >= nmt) break;
-            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Wm + (long long)(m * 16 + col) * kp + kk);
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * 256;
+                if (e < nvec) {
+                    const int r = e / vec_per_row, v8 = e - r * vec_per_row;
+                    *reinterpret_cast<bf16x8 *>(ws + r * kSlabRow + 8 * v8) = wv[u];
+                }
+            }
+        }
+        __syncthreads();
+        for (int kc = 0; kc < klen; kc += 32) {
+            const int kk = k0 + kc + 8 * grp;
+            int k = kk / cip;
+            const int c0 = kk - k * cip;
+            if (k > 26) k = 13;   // padding rows of K: zero weights, any finite input
+            const int off = ((k / 9) - 1) * HX * HY + (((k / 3) % 3) - 1) * HX + ((k % 3) - 1);
+            bf16x8 bv[2];
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
-                acc[q][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[q], acc[q][m], 0, 0, 0);
+            for (int q = 0; q < 2; ++q) bv[q] = *reinterpret_cast<const bf16x8 *>(xs + (hbase[q] + off) * cip + c0);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                if (m >= nmt) break;
+                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(ws + (m * 16 + col) * kSlabRow + kc + 8 * grp);
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    acc[q][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[q], acc[q][m], 0, 0, 0);
+            }
         }
     }
     // epilogue: lane holds rows 4 grp + i of each M tile, column = its site
-    float *Yb = Y + (long long)b * co * V;
+    float *Yb = Y ? Y + (long long)b * co * V : nullptr;
     float *Ab = A ? A + (long long)b * co * V : nullptr;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -123,7 +186,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float *__restrict__ X, i
                 const int o = m * 16 + 4 * grp + i;
                 if (o >= co) continue;
                 const float y = acc[q][m][i] + (bias ? bias[o] : 0.0f);
-                Yb[(long long)o * V + site] = y;
+                if (Yb) Yb[(long long)o * V + site] = y;
                 if (Ab) Ab[(long long)o * V + site] = silu(y);
             }
         }
@@ -163,24 +226,24 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const float *__restrict__ X,
         const int y0 = (t % tiles_y) * TY;
         const int z0 = (t / tiles_y) * TZ;
         __syncthreads();
-        for (int e = threadIdx.x; e < HS * cip; e += 256) {
-            const int h = e % HS, c = e / HS;
-            const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
-            float v = 0.0f;
-            if (c < ci) {
-                const int gx = wrapL(x0 + hx - 1, L), gy = wrapL(y0 + hy - 1, L), gz = wrapL(z0 + hz - 1, L);
-                v = X[((long long)b * ci + c) * V + gx + (long long)L * (gy + (long long)L * gz)];
+        stage_halo<false>(X + (long long)b * ci * V, V, ci, cip, L, x0, y0, z0, xs);
+        for (int e0 = threadIdx.x; e0 < TS * cop; e0 += 256 * 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * 256;
+                const int n = e % TS, o = e / TS;
+                const int tx = n % TX, ty = (n / TX) % TY, tz = n / (TX * TY);
+                const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
+                v[u] = 0.0f;
+                if (e < TS * cop && o < co && gx < L && gy < L && gz < L)   // sites outside the box add nothing
+                    v[u] = dY[((long long)b * co + o) * V + gx + (long long)L * (gy + (long long)L * gz)];
             }
-            xs[c * HS + h] = (__bf16)v;
-        }
-        for (int e = threadIdx.x; e < TS * cop; e += 256) {
-            const int n = e % TS, o = e / TS;
-            const int tx = n % TX, ty = (n / TX) % TY, tz = n / (TX * TY);
-            const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
-            float v = 0.0f;
-            if (o < co && gx < L && gy < L && gz < L)   // sites outside the box contribute nothing
-                v = dY[((long long)b * co + o) * V + gx + (long long)L * (gy + (long long)L * gz)];
-            ys[o * TS + n] = (__bf16)v;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * 256;
+                if (e < TS * cop) ys[(e / TS) * TS + e % TS] = (__bf16)v[u];
+            }
         }
         __syncthreads();
         for (int kc = 0; kc < TS; kc += 32) {
@@ -223,14 +286,25 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const float *__restrict__ X,
     }
 }
 
-// out[e] = sum_b part[b][e] (fixed order), e < n.
-__global__ void k_sum_blocks(const float *__restrict__ part, int nblk, long long n, float *__restrict__ out)
+// out[e] = sum_b part[b][e], e < n, in a fixed order: thread (j, e) sums the partials
+// b = j, j + 8, ... of element e; the 8 sums are then added in order j = 0..7.
+__global__ __launch_bounds__(256) void k_sum_blocks(const float *__restrict__ part, int nblk, long long n,
+                                                    float *__restrict__ out)
 {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
+    __shared__ float red[8][32];
+    const int el = threadIdx.x & 31, j = threadIdx.x >> 5;
+    const long long e = (long long)blockIdx.x * 32 + el;
     float s = 0.0f;
-    for (int b = 0; b < nblk; ++b) s += part[(long long)b * n + e];
-    out[e] = s;
+    if (e < n)
+        for (int b = j; b < nblk; b += 8) s += part[(long long)b * n + e];
+    red[j][el] = s;
+    __syncthreads();
+    if (j == 0 && e < n) {
+        float t = red[0][el];
+#pragma unroll
+        for (int q = 1; q < 8; ++q) t += red[q][el];
+        out[e] = t;
+    }
 }
 
 // ---------------------------------------------------------------- element-wise parts
@@ -307,14 +381,22 @@ __global__ void k_add(const float *__restrict__ a, const float *__restrict__ b, 
     if (e < n) c[e] = a[e] + (b ? b[e] : c[e]);
 }
 
-// per-channel sum over batch and sites: out[c] = sum_{b,x} g[b][c][x] (one block per channel)
-__global__ __launch_bounds__(256) void k_channel_sum(const float *__restrict__ g, int B, int C, long long V,
-                                                     float *__restrict__ out)
+// Per-channel sum over batch and sites, out[c] = sum_{b,x} g[b][c][x], in two fixed-order
+// stages: block (c, j) sums slice j of the B V values of channel c into part[c][j];
+// k_channel_final adds the slices in order.
+constexpr int kChanSlices = 64;
+
+__global__ __launch_bounds__(256) void k_channel_partial(const float *__restrict__ g, int B, int C, long long V,
+                                                         double *__restrict__ part)
 {
-    const int c = blockIdx.x;
+    const int c = blockIdx.x / kChanSlices, j = blockIdx.x % kChanSlices;
+    const long long n = (long long)B * V, per = (n + kChanSlices - 1) / kChanSlices;
+    const long long lo = j * per, hi = min(n, lo + per);
     double s = 0.0;
-    for (int b = 0; b < B; ++b)
-        for (long long x = threadIdx.x; x < V; x += 256) s += g[((long long)b * C + c) * V + x];
+    for (long long e = lo + threadIdx.x; e < hi; e += 256) {
+        const long long b = e / V, x = e - b * V;
+        s += g[(b * C + c) * V + x];
+    }
     __shared__ double red[256];
     red[threadIdx.x] = s;
     __syncthreads();
@@ -322,7 +404,16 @@ __global__ __launch_bounds__(256) void k_channel_sum(const float *__restrict__ g
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[c] = (float)red[0];
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_channel_final(const double *__restrict__ part, int C, float *__restrict__ out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    double s = 0.0;
+    for (int j = 0; j < kChanSlices; ++j) s += part[c * kChanSlices + j];
+    out[c] = (float)s;
 }
 
 // squared error: per-block partial sums of (p - t)^2 and dp = 2 (p - t) / count
@@ -400,13 +491,92 @@ __global__ void k_unstage_grad(const float *__restrict__ dWm, int co, int ci, in
 
 // Warm start from the network's prediction p (FP32, 2 polymer channels):
 //   mode 0: w_I = p_I;  mode 1: w_I += p_I - p_prev_I
-__global__ void k_warm_from_net(double *__restrict__ w, const float *__restrict__ p,
-                                const float *__restrict__ p_prev, long long V, int mode)
+// ---------------------------------------------------------------- warm start
+// Difference of densities used as the network's second input group:
+//   mode 1: delta = phi - h0                (first difference)
+//   mode 2: delta = phi - 2 h0 + h1         (second difference)
+__device__ __forceinline__ double warm_delta(const double *phi, const double *h0, const double *h1, long long e,
+                                             int mode)
+{
+    return mode == 2 ? (phi[e] - 2.0 * h0[e] + h1[e]) : (phi[e] - h0[e]);
+}
+
+// Per-block partial sums of delta^2 over the nsp x V values of one replica.
+__global__ __launch_bounds__(256) void k_delta_sumsq(const double *__restrict__ phi, const double *__restrict__ h0,
+                                                     const double *__restrict__ h1, long long n, int mode,
+                                                     double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+        const double d = warm_delta(phi, h0, h1, e, mode);
+        acc += d * d;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// rms = sqrt(sum of the partials / n), floored so that a zero difference divides safely.
+__global__ __launch_bounds__(256) void k_delta_rms(const double *__restrict__ part, int nparts, long long n,
+                                                   double *__restrict__ rms)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rms[0] = fmax(sqrt(red[0] / (double)n), 1e-300);
+}
+
+// Network input of one replica ([channel][V] FP32):
+//   mode 0: x = phi                                   (nsp channels)
+//   mode 1, 2: x = (h0, delta / rms)                  (2 nsp channels)
+__global__ void k_net_input(const double *__restrict__ phi, const double *__restrict__ h0,
+                            const double *__restrict__ h1, long long n, int mode, const double *__restrict__ rms,
+                            float *__restrict__ x)
 {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 2 * V) return;
-    if (mode == 0) w[e] = (double)p[e];
-    else w[e] += (double)p[e] - (double)p_prev[e];
+    if (e >= n) return;
+    if (mode == 0) {
+        x[e] = (float)phi[e];
+        return;
+    }
+    x[e] = (float)h0[e];
+    x[n + e] = (float)(warm_delta(phi, h0, h1, e, mode) / rms[0]);
+}
+
+// Apply the prediction p ([2][V]) to the polymer fields w ([2][V] of the replica):
+//   mode 0: w = p;  mode 1: w += rms p;  mode 2: w += (wh0 - wh1) + rms p.
+__global__ void k_warm_apply(double *__restrict__ w, const float *__restrict__ p, long long n, int mode,
+                             const double *__restrict__ rms, const double *__restrict__ wh0,
+                             const double *__restrict__ wh1)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    if (mode == 0) {
+        w[e] = (double)p[e];
+        return;
+    }
+    double v = w[e] + rms[0] * (double)p[e];
+    if (mode == 2) v += wh0[e] - wh1[e];
+    w[e] = v;
+}
+
+// w += wh0 - wh1 (plain extrapolation of the fields)
+__global__ void k_shift_fields(double *__restrict__ w, const double *__restrict__ wh0,
+                               const double *__restrict__ wh1, long long n)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) w[e] += wh0[e] - wh1[e];
 }
 
 // x[b][c][v] = (x - shift[c]) * scale[c]  (input normalisation of the network)
@@ -419,12 +589,6 @@ __global__ void k_affine(float *__restrict__ x, int C, long long V, long long n,
     x[e] = (x[e] - shift[c]) * scale[c];
 }
 
-// float <-> double copies
-__global__ void k_f64_to_f32(const double *__restrict__ a, float *__restrict__ b, long long n)
-{
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) b[e] = (float)a[e];
-}
 
 // ---------------------------------------------------------------- launchers
 static inline unsigned nb(long long n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -434,17 +598,20 @@ void net_conv_fwd(hipStream_t s, const float *X, int B, int ci, int cip, const _
 {
     const int tx = (L + TX - 1) / TX, ty = (L + TY - 1) / TY, tz = (L + TZ - 1) / TZ;
     const int tps = tx * ty * tz;
-    const size_t lds = (size_t)HS * cip * sizeof(__bf16);
-    hipLaunchKernelGGL(k_conv_fwd, dim3(B * tps), dim3(256), lds, s, X, ci, cip, Wm, kp, co, cop, bias, Y, A, L, tx,
-                       ty, tps);
+    hipLaunchKernelGGL(k_conv_fwd, dim3(B * tps), dim3(256), conv_fwd_lds(cip, cop), s, X, ci, cip, Wm, kp, co, cop,
+                       bias, Y, A, L, tx, ty, tps);
 }
 
-// number of site slices of the weight gradient (partials buffer: slices x cop x kp floats)
-int net_wgrad_blocks(int B, int L)
+// Site slices of the weight gradient: enough blocks (groups x slices, about 1024) to
+// fill the chip, each covering at least one site tile.  The partials buffer holds
+// slices x cop x kp floats.
+int net_wgrad_slices(int B, int L, int cop, int kp)
 {
     const int tx = (L + TX - 1) / TX, ty = (L + TY - 1) / TY, tz = (L + TZ - 1) / TZ;
-    const int n = B * tx * ty * tz;
-    return n < 64 ? n : 64;
+    const int n_tiles = B * tx * ty * tz;
+    const int groups = ((cop / 16) * (kp / 16) + 15) / 16;
+    const int want = std::max(1, 1024 / groups);
+    return std::min(n_tiles, want);
 }
 
 void net_conv_wgrad(hipStream_t s, const float *X, int B, int ci, int cip, const float *dY, int co, int cop, int kp,
@@ -452,13 +619,13 @@ void net_conv_wgrad(hipStream_t s, const float *X, int B, int ci, int cip, const
 {
     const int tx = (L + TX - 1) / TX, ty = (L + TY - 1) / TY, tz = (L + TZ - 1) / TZ;
     const int tps = tx * ty * tz, n_tiles = B * tps;
-    const int slices = net_wgrad_blocks(B, L);
+    const int slices = net_wgrad_slices(B, L, cop, kp);
     const int ntiles = (cop / 16) * (kp / 16), groups = (ntiles + 15) / 16;
     const size_t lds = ((size_t)cip * HS + (size_t)cop * TS) * sizeof(__bf16);
     hipLaunchKernelGGL(k_conv_wgrad, dim3(groups * slices), dim3(256), lds, s, X, ci, cip, dY, co, cop, kp, L, tx,
                        ty, tps, n_tiles, groups, slices, part);
     const long long n = (long long)cop * kp;
-    hipLaunchKernelGGL(k_sum_blocks, dim3(nb(n, 256)), dim3(256), 0, s, part, slices, n, dWm);
+    hipLaunchKernelGGL(k_sum_blocks, dim3(nb(n, 32)), dim3(256), 0, s, part, slices, n, dWm);
 }
 
 void net_silu_bwd(hipStream_t s, const float *dA, const float *Y, float *dY, long long n)
@@ -491,9 +658,12 @@ void net_add(hipStream_t s, const float *a, const float *b, float *c, long long 
     hipLaunchKernelGGL(k_add, dim3(nb(n, 256)), dim3(256), 0, s, a, b, c, n);
 }
 
-void net_channel_sum(hipStream_t s, const float *g, int B, int C, long long V, float *out)
+int net_channel_parts(int C) { return C * kChanSlices; }
+
+void net_channel_sum(hipStream_t s, const float *g, int B, int C, long long V, double *part, float *out)
 {
-    hipLaunchKernelGGL(k_channel_sum, dim3(C), dim3(256), 0, s, g, B, C, V, out);
+    hipLaunchKernelGGL(k_channel_partial, dim3(C * kChanSlices), dim3(256), 0, s, g, B, C, V, part);
+    hipLaunchKernelGGL(k_channel_final, dim3(1), dim3(64), 0, s, part, C, out);
 }
 
 int net_mse(hipStream_t s, const float *p, const float *t, float *dp, long long n, float inv_count, double *part)
@@ -523,9 +693,27 @@ void net_unstage_grad(hipStream_t s, const float *dWm, int co, int ci, int cip, 
     hipLaunchKernelGGL(k_unstage_grad, dim3(nb(n, 256)), dim3(256), 0, s, dWm, co, ci, cip, kp, dW);
 }
 
-void net_warm_from_net(hipStream_t s, double *w, const float *p, const float *p_prev, long long V, int mode)
+void net_warm_input(hipStream_t s, const double *phi, const double *h0, const double *h1, int nsp, long long V,
+                    int mode, double *part, int max_parts, double *rms, float *x)
 {
-    hipLaunchKernelGGL(k_warm_from_net, dim3(nb(2 * V, 256)), dim3(256), 0, s, w, p, p_prev, V, mode);
+    const long long n = (long long)nsp * V;
+    if (mode != 0) {
+        const int nparts = (int)std::min<long long>(max_parts, std::max<long long>(1, nb(n, 256)));
+        hipLaunchKernelGGL(k_delta_sumsq, dim3(nparts), dim3(256), 0, s, phi, h0, h1, n, mode, part);
+        hipLaunchKernelGGL(k_delta_rms, dim3(1), dim3(256), 0, s, part, nparts, n, rms);
+    }
+    hipLaunchKernelGGL(k_net_input, dim3(nb(n, 256)), dim3(256), 0, s, phi, h0, h1, n, mode, rms, x);
+}
+
+void net_warm_apply(hipStream_t s, double *w, const float *p, long long V, int mode, const double *rms,
+                    const double *wh0, const double *wh1)
+{
+    hipLaunchKernelGGL(k_warm_apply, dim3(nb(2 * V, 256)), dim3(256), 0, s, w, p, 2 * V, mode, rms, wh0, wh1);
+}
+
+void net_shift_fields(hipStream_t s, double *w, const double *wh0, const double *wh1, long long n)
+{
+    hipLaunchKernelGGL(k_shift_fields, dim3(nb(n, 256)), dim3(256), 0, s, w, wh0, wh1, n);
 }
 
 void net_affine(hipStream_t s, float *x, int C, long long V, long long n, const float *shift, const float *scale)
@@ -533,9 +721,5 @@ void net_affine(hipStream_t s, float *x, int C, long long V, long long n, const 
     hipLaunchKernelGGL(k_affine, dim3(nb(n, 256)), dim3(256), 0, s, x, C, V, n, shift, scale);
 }
 
-void net_f64_to_f32(hipStream_t s, const double *a, float *b, long long n)
-{
-    hipLaunchKernelGGL(k_f64_to_f32, dim3(nb(n, 256)), dim3(256), 0, s, a, b, n);
-}
 
 }  // namespace hsf

@@ -35,7 +35,7 @@ EXPORTED = [
     "hsf_net_last_error", "hsf_net_set_stream", "hsf_net_num_params", "hsf_net_set_params",
     "hsf_net_get_params", "hsf_net_set_input_norm", "hsf_net_forward", "hsf_net_loss_grad", "hsf_net_train_step", "hsf_attach_net",
 ]
-WARM_EXTRAP, WARM_NET, WARM_NET_DELTA = 2, 3, 4
+WARM_EXTRAP, WARM_NET, WARM_NET_DELTA, WARM_NET_EXTRAP = 2, 3, 4, 5
 SOLVER_PRECOND = 1
 K_PREP, K_FWD, K_BWD, K_LB, K_CD, K_COUNT = 0, 1, 2, 3, 4, 5
 KERNEL_NAMES = ["prep", "fwd", "bwd", "lb", "cd"]
@@ -350,7 +350,8 @@ class Context:
         return ev.value, se.value
 
     def set_warm(self, warm):
-        """Warm start of hsf_step's inversions (WARM_CURRENT, WARM_EXTRAP, WARM_NET, WARM_NET_DELTA)."""
+        """Warm start of hsf_step's inversions (WARM_CURRENT, WARM_LOCAL, WARM_EXTRAP, WARM_NET,
+        WARM_NET_DELTA, WARM_NET_EXTRAP)."""
         self._check(self._lib.hsf_set_warm(self._h, int(warm)))
 
     def attach_net(self, net):
