@@ -8,7 +8,10 @@ same comparison is timed after it and reported in its own field.
 
 A step is one pass of the whole method over every replica: field inversion to
 the residual, chemical potential and force, LB collide-and-stream, and the
-convection-diffusion update.
+convection-diffusion update.  The main arm starts every inversion from the
+previous step's fields (the plain warm start).  The field learned_warm_start
+compares, on the same workload and window, the plain, extrapolated and learned
+warm starts (network trained in the same run, on other seeds).
 
 value = propagator site-bead updates per second over the timed steps: every
 density-functional evaluation performs 2 N V site-bead updates (N forward and
@@ -86,6 +89,40 @@ def cpu_baseline(wl, w, phi, seconds):
                       f"the GPU run's final fields of replica 0 ({el:.1f} s, single-threaded FP64 C oracle)"}
 
 
+def learned_arm(hsf, workload, precision, steps, warmup, tile, log):
+    """The learned warm start on the benchmark's own workload: a network trained on
+    the GPU from FP64 trajectories of other seeds (1, 2), then every warm start run
+    on the benchmark's seed from the same states: `warmup` steps after the quench
+    (the window the main arm times), and later at steps 300 and 1000."""
+    from paper_1204_2088_amd import warmnet
+    make = lambda seed: [w.with_(seed=seed) for w in make_workloads(workload, "fp64")]
+    record = list(range(0, 121)) + [k for c in (300, 600, 900, 1200) for k in (c - 1, c, c + 1)]
+    net, info = warmnet.train_warm_start(make, seeds=(1, 2), steps=1202, record=record, val_seed=5,
+                                         log=lambda m: None)
+    log(f"# warm-start network trained: {info}")
+    wls = make_workloads(workload, precision)
+    modes = [hsf.WARM_CURRENT, hsf.WARM_EXTRAP, hsf.WARM_NET_EXTRAP]
+    regimes = {}
+    for start in (warmup, 300, 1000):
+        res = warmnet.compare_warm_starts(wls, net, modes, start, steps, tile=tile,
+                                          log=lambda m: log(f"# [from step {start}]{m}"))
+        gated = warmnet.compare_warm_starts(wls, net, [hsf.WARM_NET_EXTRAP], start, steps, tile=tile, gate=2,
+                                            log=lambda m: log(f"# [from step {start}, gate 2]{m}"))
+        res["net_extrapolated_gate2"] = gated["net_extrapolated"]
+        regimes[f"from_step_{start}"] = res
+    net.close()
+    head = regimes[f"from_step_{warmup}"]
+    return {
+        "tol": wls[0].tol, "steps_per_mode": steps,
+        "window": "each mode restarts from the saved state, runs 2 plain steps and 1 untimed step of its own, "
+                  "then the timed steps",
+        "network": info,
+        "regimes": regimes,
+        "speedup_learned_vs_plain": head["current"]["ms_per_step"] / head["net_extrapolated"]["ms_per_step"],
+        "speedup_learned_vs_extrapolated": head["extrapolated"]["ms_per_step"] / head["net_extrapolated"]["ms_per_step"],
+    }
+
+
 def run_arm(hsf, torch, wls, steps, warmup, timing, log, precond=False, tile=None):
     """Build a batched context, autotune, warm up, time `steps` coupled steps."""
     from paper_1204_2088_amd import workloads as W
@@ -144,6 +181,7 @@ def main():
     ap.add_argument("--no-fp64-arm", action="store_true", help="skip the all-FP64 arm")
     ap.add_argument("--precond", action="store_true", help="diagonally preconditioned inversion")
     ap.add_argument("--tile", default=None, help="cx,cy,cz,k: use this propagator tiling instead of autotuning")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -227,6 +265,10 @@ def main():
                     "tol": wls64[0].tol, "tile": list(tile64)}
         c64.close()
 
+    learned = None
+    if args.workload.startswith("melt64_a8b8") and not args.no_learned:
+        learned = learned_arm(hsf, args.workload, args.precision, args.steps, args.warmup, tuple(tile), log)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -254,6 +296,7 @@ def main():
                                  "launch": "direct, one event pair per hot kernel"},
         "roofline": roofline,
         "fp64_arm": fp64_arm,
+        "learned_warm_start": learned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -232,14 +232,18 @@ int hsf_autotune(hsf_ctx *ctx, int reps, double *best_ms);
 int hsf_set_warm(hsf_ctx *ctx, int warm);
 
 /* ---- learned warm start -------------------------------------------------------
- * A 4-level U-Net on the periodic lattice (3x3x3 convolutions, SiLU, 2x2x2 average
- * pooling, nearest upsampling, additive skips; widths w1..w4 <= 32) mapping the
- * densities [in_ch][L^3] to the polymer fields [out_ch][L^3].  Convolutions run on
- * the BF16 matrix cores with FP32 accumulation; master weights and Adam moments are
+ * A U-Net of D = 1..4 levels on the periodic lattice (3x3x3 convolutions, SiLU,
+ * 2x2x2 average pooling, nearest upsampling, additive skips) mapping in_ch input
+ * channels to out_ch output channels on the same L^3 box.  widths[0..D-1] (each
+ * 1..32) are the level widths and widths[D..3] are zero.  Convolutions run on the
+ * BF16 matrix cores with FP32 accumulation; master weights and Adam moments are
  * FP32.  Tensors at this boundary are FP32 [batch][channel][Lz][Ly][Lx] on cubic
- * periodic boxes with L a multiple of 8.  The parameter vector holds, for the 15
- * convolutions in order (e1a, e1b, e2a, e2b, e3a, e3b, e4a, e4b, d3a, d3b, d2a, d2b,
- * d1a, d1b, out), W[co][ci][27] with k = 9 (dz+1) + 3 (dy+1) + (dx+1), then b[co].
+ * periodic boxes with L a multiple of 2^(D-1).  The parameter vector holds, for the
+ * 4 D - 1 convolutions in order (per encoder level its two, per decoder level from
+ * the coarsest its two, then the output convolution), W[co][ci][27] with
+ * k = 9 (dz+1) + 3 (dy+1) + (dx+1), then b[co].  Device buffers are owned by the
+ * network; pointers passed in are borrowed for the call.  Errors: HSF_EINVAL for bad
+ * sizes or pointers, HSF_ENOMEM, HSF_EHIP (hsf_net_last_error has the message).
  * This is a build addition; the inversion from its prediction is the same
  * Fletcher-Reeves iteration to the same residual. */
 typedef struct hsf_net hsf_net;
@@ -263,11 +267,17 @@ int hsf_net_loss_grad(hsf_net *net, const float *in, const float *target, int ba
 int hsf_net_train_step(hsf_net *net, const float *in, const float *target, int batch, int L, float lr,
                        double *loss, int where);
 /* Attach a network to a context for the NET warm starts (in_ch = nsp for
- * HSF_WARM_NET, 2 nsp for HSF_WARM_NET_DELTA and HSF_WARM_NET_EXTRAP; out_ch = 2);
+ * HSF_WARM_NET, 2 nsp for HSF_WARM_NET_DELTA and HSF_WARM_NET_EXTRAP; out_ch = 2;
+ * replicas with equal boxes are predicted in one batch);
  * the context does not own it.  NULL detaches.  The inputs the network sees for
  * one replica are FP32 [channel][V]: HSF_WARM_NET the target densities; the delta
  * modes phi^n (nsp channels) followed by the density difference divided by r. */
 int hsf_attach_net(hsf_ctx *ctx, hsf_net *net);
+/* Use the network in HSF_WARM_NET_DELTA / HSF_WARM_NET_EXTRAP only when the previous
+ * inversion of some replica took at least min_iters iterations; otherwise take the
+ * plain counterpart (the held fields, or the extrapolation).  0 (the default) always
+ * uses the network.  HSF_EINVAL for a negative value. */
+int hsf_set_net_gate(hsf_ctx *ctx, int min_iters);
 
 /* Kernel families timed by hsf_set_timing. */
 enum {

@@ -6,21 +6,38 @@ float64 tensors and differentiates it with autograd.  With `bf16=True` the
 operands of every convolution (input and weights) are rounded to bfloat16 before
 the float64 convolution, which is what the GPU's matrix cores consume.
 
-Topology (widths w1..w4; c(.) = SiLU(periodic 3x3x3 convolution + bias)):
-  e1 = c(c(x)); e2 = c(c(pool e1)); e3 = c(c(pool e2)); e4 = c(c(pool e3))
-  d3 = c(c(up e4) + e3); d2 = c(c(up d3) + e2); d1 = c(c(up d2) + e1); out = conv(d1)
+Topology (D = 1..4 levels, widths w1..wD; c(.) = SiLU(periodic 3x3x3 convolution + bias)):
+  e1 = c(c(x)); el = c(c(pool e(l-1))) for l = 2..D
+  dD = eD; dl = c(c(up d(l+1)) + el) for l = D-1..1; out = conv(d1)
 pool: 2x2x2 average; up: nearest.  Parameter vector layout: per convolution (in the
-order above, 15 of them) W[co][ci][27] with k = 9 (dz+1) + 3 (dy+1) + (dx+1), then b[co].
+order above, 4 D - 1 of them) W[co][ci][27] with k = 9 (dz+1) + 3 (dy+1) + (dx+1), then
+b[co].  Widths are given as a sequence of D positive values (trailing zeros ignored).
 """
 import numpy as np
 import torch
 import torch.nn.functional as F
 
 
+def levels(widths):
+    w = []
+    for v in widths:
+        if v <= 0:
+            break
+        w.append(int(v))
+    return w
+
+
 def layer_shapes(in_ch, out_ch, widths):
-    w1, w2, w3, w4 = widths
-    return [(in_ch, w1), (w1, w1), (w1, w2), (w2, w2), (w2, w3), (w3, w3), (w3, w4), (w4, w4),
-            (w4, w3), (w3, w3), (w3, w2), (w2, w2), (w2, w1), (w1, w1), (w1, out_ch)]
+    w = levels(widths)
+    D = len(w)
+    shapes, prev = [], in_ch
+    for l in range(D):
+        shapes += [(prev, w[l]), (w[l], w[l])]
+        prev = w[l]
+    for l in range(D - 2, -1, -1):
+        shapes += [(w[l + 1], w[l]), (w[l], w[l])]
+    shapes.append((w[0], out_ch))
+    return shapes
 
 
 def num_params(in_ch, out_ch, widths):
@@ -67,14 +84,16 @@ def forward(params, x, in_ch, out_ch, widths, bf16=False, shift=None, scale=None
     c = lambda i, h: F.silu(conv_periodic(h, *layers[i], bf16=bf16))
     pool = lambda h: F.avg_pool3d(h, 2)
     up = lambda h: h.repeat_interleave(2, 2).repeat_interleave(2, 3).repeat_interleave(2, 4)
-    e1 = c(1, c(0, x))
-    e2 = c(3, c(2, pool(e1)))
-    e3 = c(5, c(4, pool(e2)))
-    e4 = c(7, c(6, pool(e3)))
-    d3 = c(9, c(8, up(e4)) + e3)
-    d2 = c(11, c(10, up(d3)) + e2)
-    d1 = c(13, c(12, up(d2)) + e1)
-    return conv_periodic(d1, *layers[14], bf16=bf16)
+    D = len(levels(widths))
+    enc, h = [], x
+    for l in range(D):
+        h = c(2 * l + 1, c(2 * l, h if l == 0 else pool(h)))
+        enc.append(h)
+    i = 2 * D
+    for l in range(D - 2, -1, -1):
+        h = c(i + 1, c(i, up(h)) + enc[l])
+        i += 2
+    return conv_periodic(h, *layers[i], bf16=bf16)
 
 
 def loss_and_grad(params, x, target, in_ch, out_ch, widths, bf16=False, shift=None, scale=None):

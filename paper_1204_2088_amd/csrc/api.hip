@@ -69,9 +69,10 @@ struct hsf_ctx {
     double *w_hist[2] = {nullptr, nullptr}, *phi_hist[2] = {nullptr, nullptr};
     int n_hist = 0;                    // how many of them are valid
     hsf_net *net = nullptr;            // attached network (not owned)
-    float *net_in = nullptr;           // network input, [2 nsp][V] per replica
+    float *net_in = nullptr;           // network input, [channels][V] per replica, replicas in order
     float *net_pred = nullptr;         // network output, [2][V] per replica
     double *net_rms = nullptr;         // per replica: rms of the density difference
+    int net_gate = 0;                  // use the network only after inversions of >= this many iterations
     long long work_evals = 0;          // density-functional evaluations, all replicas
     double work_site_evals = 0.0;      // sum over replicas of evaluations x sites
     int timing = 0;
@@ -371,29 +372,51 @@ int warm_start(hsf_ctx *c, int warm)
     }
     if (warm != HSF_WARM_NET && warm != HSF_WARM_NET_DELTA && warm != HSF_WARM_NET_EXTRAP) return HSF_OK;
     if (!c->net) return fail(c, HSF_EINVAL, "no network attached");
+    if (c->net_gate > 0 && c->n_hist >= 1 && warm != HSF_WARM_NET) {
+        // the previous inversions were short: the plain warm start is already close
+        int most = 0;
+        for (int r = 0; r < c->n_rep; ++r) most = std::max(most, c->st_h[r].iters);
+        if (most < c->net_gate) return warm == HSF_WARM_NET_EXTRAP ? warm_start(c, HSF_WARM_EXTRAP) : HSF_OK;
+    }
     int mode = 0;   // 0: absolute, 1: first difference, 2: second difference
     if (warm == HSF_WARM_NET_DELTA || warm == HSF_WARM_NET_EXTRAP) {
         if (!c->fields_set || c->n_hist < 1) return HSF_OK;
         mode = (warm == HSF_WARM_NET_EXTRAP && c->n_hist >= 2) ? 2 : 1;
     }
-    int in_ch = 0, out_ch = 0;
-    net_channels(c->net, &in_ch, &out_ch);
+    int in_ch = 0, out_ch = 0, q = 1;
+    net_channels(c->net, &in_ch, &out_ch, &q);
     const int want = mode == 0 ? nsp : 2 * nsp;
     if (in_ch != want || out_ch != 2)
         return fail(c, HSF_EINVAL, "network has %d inputs and %d outputs; this warm start needs %d and 2", in_ch,
                     out_ch, want);
-    const int max_parts = c->part_cap;
     for (int r = 0; r < c->n_rep; ++r) {
         const Rep &R = c->reps[r];
-        if (R.Lx != R.Ly || R.Lx != R.Lz || R.Lx % 8)
-            return fail(c, HSF_EINVAL, "network warm start needs cubic boxes with L a multiple of 8");
-        const long long fo = (long long)nsp * R.site_off, po = 2LL * R.site_off;
-        float *x = c->net_in + 2 * fo, *pred = c->net_pred + po;
+        if (R.Lx != R.Ly || R.Lx != R.Lz || R.Lx % q)
+            return fail(c, HSF_EINVAL, "network warm start needs cubic boxes with L a multiple of %d", q);
+    }
+    const int max_parts = c->part_cap;
+    // inputs of every replica, then one network call per run of consecutive replicas
+    // with the same box (their inputs and outputs are contiguous)
+    for (int r = 0; r < c->n_rep; ++r) {
+        const Rep &R = c->reps[r];
+        const long long fo = (long long)nsp * R.site_off;
         net_warm_input(s, c->phi + fo, c->phi_hist[0] + fo, c->phi_hist[1] + fo, nsp, R.V, mode, c->part,
-                       max_parts, c->net_rms + r, x);
-        int rc = net_predict(c->net, s, x, want, R.Lx, pred);
+                       max_parts, c->net_rms + r, c->net_in + (long long)want * R.site_off);
+    }
+    for (int r0 = 0; r0 < c->n_rep;) {
+        int r1 = r0 + 1;
+        while (r1 < c->n_rep && c->reps[r1].Lx == c->reps[r0].Lx) ++r1;
+        const Rep &R = c->reps[r0];
+        int rc = net_predict(c->net, s, c->net_in + (long long)want * R.site_off, want, r1 - r0, R.Lx,
+                             c->net_pred + 2LL * R.site_off);
         if (rc) return fail(c, rc, "network prediction failed");
-        net_warm_apply(s, c->w + fo, pred, R.V, mode, c->net_rms + r, c->w_hist[0] + fo, c->w_hist[1] + fo);
+        r0 = r1;
+    }
+    for (int r = 0; r < c->n_rep; ++r) {
+        const Rep &R = c->reps[r];
+        const long long fo = (long long)nsp * R.site_off;
+        net_warm_apply(s, c->w + fo, c->net_pred + 2LL * R.site_off, R.V, mode, c->net_rms + r, c->w_hist[0] + fo,
+                       c->w_hist[1] + fo);
     }
     c->fields_set = 1;
     HIPCHK(c, hipGetLastError());
@@ -999,6 +1022,13 @@ int hsf_set_warm(hsf_ctx *c, int warm)
 {
     if (!c || warm < HSF_WARM_CURRENT || warm > HSF_WARM_NET_EXTRAP) return HSF_EINVAL;
     c->step_warm = warm;
+    return HSF_OK;
+}
+
+int hsf_set_net_gate(hsf_ctx *c, int min_iters)
+{
+    if (!c || min_iters < 0) return HSF_EINVAL;
+    c->net_gate = min_iters;
     return HSF_OK;
 }
 

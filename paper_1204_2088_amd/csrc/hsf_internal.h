@@ -118,8 +118,8 @@ void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n);
 
 struct hsf_net;
 namespace hsf {
-int net_predict(hsf_net *n, hipStream_t s, const float *x, int in_ch, int L, float *pred);
-int net_channels(const hsf_net *n, int *in_ch, int *out_ch);
+int net_predict(hsf_net *n, hipStream_t s, const float *x, int in_ch, int B, int L, float *pred);
+int net_channels(const hsf_net *n, int *in_ch, int *out_ch, int *box_multiple);
 void net_warm_input(hipStream_t s, const double *phi, const double *h0, const double *h1, int nsp, long long V,
                     int mode, double *part, int max_parts, double *rms, float *x);
 void net_warm_apply(hipStream_t s, double *w, const float *p, long long V, int mode, const double *rms,

@@ -1,21 +1,19 @@
-// net.hip -- the warm-start network (a build addition to the method): a 4-level
-// U-Net on the periodic lattice that maps the densities (phi_A, phi_B[, phi_S])
-// to the polymer fields (w_A, w_B), trained on (phi, w) pairs produced by the
+// net.hip -- the warm-start network (a build addition to the method): a U-Net of
+// D = 1..4 levels on the periodic lattice, trained on pairs produced by the
 // inversion itself.  Forward and backward passes run in the kernels of
 // net_kernels.hip (convolutions on the BF16 matrix cores, FP32 accumulation);
 // master weights and Adam moments are FP32.
 //
-// Topology (widths w1..w4, SiLU after every convolution except the last):
-//   e1 = c(c(x, in->w1), w1->w1)                        level L
-//   e2 = c(c(pool e1, w1->w2), w2->w2)                  level L/2
-//   e3 = c(c(pool e2, w2->w3), w3->w3)                  level L/4
-//   e4 = c(c(pool e3, w3->w4), w4->w4)                  level L/8
-//   d3 = c(c(up e4, w4->w3) + e3, w3->w3)               level L/4
-//   d2 = c(c(up d3, w3->w2) + e2, w2->w2)               level L/2
-//   d1 = c(c(up d2, w2->w1) + e1, w1->w1)               level L
-//   out = conv(d1, w1->out)                             level L (no activation)
+// Topology (widths w1..wD, SiLU after every convolution except the last):
+//   e1 = c(c(x, in->w1), w1->w1)                              level 0 (box L)
+//   el = c(c(pool e(l-1), w(l-1)->wl), wl->wl)                level l-1 (box L / 2^(l-1))
+//   dD = eD;  dl = c(c(up d(l+1), w(l+1)->wl) + el, wl->wl)   for l = D-1 .. 1
+//   out = conv(d1, w1->out)                                   level 0, no activation
 // c(.) = SiLU(3x3x3 periodic convolution + bias); pool = 2x2x2 average; up = nearest.
-// Parameter vector: for layers 0..14 in this order, W[co][ci][27] then b[co].
+// Pooled, upsampled and skip-summed inputs are composed while a convolution stages
+// its tile (ConvIn), never stored.  4 D - 1 convolutions; parameter vector: for each
+// in the order above (encoder, decoder from the coarsest level, output), W[co][ci][27]
+// then b[co].
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -32,15 +30,18 @@ using namespace hsf;
 
 namespace {
 
-constexpr int kLayers = 15;
+constexpr int kMaxLevels = 4;
+constexpr int kLayers = 4 * kMaxLevels - 1;   // the most convolutions a network has
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 struct Layer {
-    int ci, co, act, level;          // level 0..3 (box L >> level)
+    int ci, co, act, level;          // level 0..D-1 (box L >> level)
     int cip, kp, cop;                // forward matrix-core layout
     int cip_t, kp_t, cop_t;          // transposed-flipped layout (data gradient)
     long long w_off, b_off;          // offsets in the parameter vector
+    // input composition: mode (CONV_IN_*) and the activations it reads (-1: network input)
+    int in_mode, src1, src2;
     __bf16 *Wm = nullptr, *Wt = nullptr;
     float *dWm = nullptr;            // weight gradient, matrix-core layout
 };
@@ -53,7 +54,8 @@ struct Tensor {
 }  // namespace
 
 struct hsf_net {
-    int in_ch = 0, out_ch = 0, w[4] = {0, 0, 0, 0};
+    int in_ch = 0, out_ch = 0, w[kMaxLevels] = {0, 0, 0, 0};
+    int depth = 0, n_layers = 0;
     Layer layer[kLayers];
     long long n_params = 0;
     float *params = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
@@ -65,11 +67,12 @@ struct hsf_net {
     // activation buffers for the current (batch, box)
     int cur_B = 0, cur_L = 0;
     std::vector<void *> act_allocs;
-    Tensor x0, y[kLayers], a[kLayers], p1, p2, p3, u3, u2, u1, t3, t2, t1;
-    Tensor dy[kLayers], da[kLayers], dp1, dp2, dp3, du3, du2, du1, dt3, dt2, dt1, dout;
+    Tensor x0, y[kLayers], a[kLayers];
+    Tensor dy[kLayers], da[kLayers], dout;
+    float *din = nullptr;            // gradient of one convolution's (composed) input
     float *target = nullptr, *wpart = nullptr;
     double *bpart = nullptr;         // per-channel partial sums of the bias gradient
-    double *loss_part = nullptr, *loss_host = nullptr;
+    double *loss_part = nullptr;
     int weights_staged = 0;
     int training = 0;                // the current forward pass feeds a backward pass
 };
@@ -115,13 +118,17 @@ void free_acts(hsf_net *n)
     n->cur_B = n->cur_L = 0;
     // forget every pointer into the freed buffers (a later allocation without the
     // gradient tensors must not find stale ones)
-    for (Tensor *t : {&n->x0, &n->p1, &n->p2, &n->p3, &n->u3, &n->u2, &n->u1, &n->t3, &n->t2, &n->t1, &n->dp1,
-                      &n->dp2, &n->dp3, &n->du3, &n->du2, &n->du1, &n->dt3, &n->dt2, &n->dt1, &n->dout})
-        *t = Tensor();
+    n->x0 = n->dout = Tensor();
     for (int l = 0; l < kLayers; ++l) n->y[l] = n->a[l] = n->dy[l] = n->da[l] = Tensor();
-    n->target = n->wpart = nullptr;
+    n->din = n->target = n->wpart = nullptr;
     n->bpart = nullptr;
     n->loss_part = nullptr;
+}
+
+// Elements of a layer's (composed) input for the current batch.
+long long input_numel(const hsf_net *n, const Layer &Ly)
+{
+    return (long long)n->cur_B * Ly.ci * vol(n->cur_L, Ly.level);
 }
 
 // (Re)allocate the activation and gradient tensors for batch B on an L^3 box.
@@ -135,43 +142,26 @@ int ensure_acts(hsf_net *n, int B, int L, bool grads)
         t.level = level;
         if (rc == HSF_OK) rc = nalloc(n, n->act_allocs, (void **)&t.p, sizeof(float) * (size_t)B * c * vol(L, level));
     };
-    const int *w = n->w;
     T(n->x0, n->in_ch, 0);
-    for (int l = 0; l < kLayers; ++l) {
-        T(n->y[l], n->layer[l].co, n->layer[l].level);
-        if (n->layer[l].act) T(n->a[l], n->layer[l].co, n->layer[l].level);
+    for (int l = 0; l < n->n_layers; ++l) {
+        const Layer &Ly = n->layer[l];
+        // pre-activations are kept for the backward pass and for the output layer
+        if (grads || !Ly.act) T(n->y[l], Ly.co, Ly.level);
+        if (Ly.act) T(n->a[l], Ly.co, Ly.level);
     }
-    T(n->p1, w[0], 1);
-    T(n->p2, w[1], 2);
-    T(n->p3, w[2], 3);
-    T(n->u3, w[3], 2);
-    T(n->u2, w[2], 1);
-    T(n->u1, w[1], 0);
-    T(n->t3, w[2], 2);
-    T(n->t2, w[1], 1);
-    T(n->t1, w[0], 0);
     if (grads) {
-        for (int l = 0; l < kLayers; ++l) {
-            T(n->dy[l], n->layer[l].co, n->layer[l].level);
-            T(n->da[l], n->layer[l].co, n->layer[l].level);
-        }
-        T(n->dp1, w[0], 1);
-        T(n->dp2, w[1], 2);
-        T(n->dp3, w[2], 3);
-        T(n->du3, w[3], 2);
-        T(n->du2, w[2], 1);
-        T(n->du1, w[1], 0);
-        T(n->dt3, w[2], 2);
-        T(n->dt2, w[1], 1);
-        T(n->dt1, w[0], 0);
-        T(n->dout, n->out_ch, 0);
-        if (rc == HSF_OK)
-            rc = nalloc(n, n->act_allocs, (void **)&n->target, sizeof(float) * (size_t)B * n->out_ch * vol(L, 0));
-        size_t wp = 0;
-        for (int l = 0; l < kLayers; ++l) {
+        size_t din = 0, wp = 0;
+        for (int l = 0; l < n->n_layers; ++l) {
             const Layer &Ly = n->layer[l];
+            T(n->dy[l], Ly.co, Ly.level);
+            if (Ly.act) T(n->da[l], Ly.co, Ly.level);
+            din = std::max(din, (size_t)((long long)B * Ly.ci * vol(L, Ly.level)));
             wp = std::max(wp, (size_t)net_wgrad_slices(B, L >> Ly.level, Ly.cop, Ly.kp) * Ly.cop * Ly.kp);
         }
+        T(n->dout, n->out_ch, 0);
+        if (rc == HSF_OK) rc = nalloc(n, n->act_allocs, (void **)&n->din, sizeof(float) * din);
+        if (rc == HSF_OK)
+            rc = nalloc(n, n->act_allocs, (void **)&n->target, sizeof(float) * (size_t)B * n->out_ch * vol(L, 0));
         if (rc == HSF_OK) rc = nalloc(n, n->act_allocs, (void **)&n->wpart, sizeof(float) * wp);
         if (rc == HSF_OK)
             rc = nalloc(n, n->act_allocs, (void **)&n->bpart, sizeof(double) * net_channel_parts(kNetMaxWidth));
@@ -189,7 +179,7 @@ int ensure_acts(hsf_net *n, int B, int L, bool grads)
 
 int stage_weights(hsf_net *n)
 {
-    for (int l = 0; l < kLayers; ++l) {
+    for (int l = 0; l < n->n_layers; ++l) {
         const Layer &Ly = n->layer[l];
         net_stage_weights(n->stream, n->params + Ly.w_off, Ly.co, Ly.ci, Ly.cip, Ly.kp, Ly.cop, Ly.Wm, Ly.cip_t,
                           Ly.kp_t, Ly.cop_t, Ly.Wt);
@@ -199,114 +189,79 @@ int stage_weights(hsf_net *n)
     return HSF_OK;
 }
 
+const float *src_ptr(const hsf_net *n, int src) { return src < 0 ? n->x0.p : n->a[src].p; }
+
+ConvIn conv_input(const hsf_net *n, const Layer &Ly)
+{
+    ConvIn in;
+    in.x1 = src_ptr(n, Ly.src1);
+    in.x2 = Ly.in_mode == CONV_IN_ADD ? src_ptr(n, Ly.src2) : nullptr;
+    in.mode = Ly.in_mode;
+    return in;
+}
+
 // Forward of layer l.  The pre-activation y[l] is kept only when a backward pass
-// follows (training); inference writes the activation alone.
-void conv(hsf_net *n, int l, const Tensor &in, int B)
+// follows (training) or the layer has no activation; inference writes the
+// activation alone.
+void conv(hsf_net *n, int l)
 {
     const Layer &Ly = n->layer[l];
     float *y = (Ly.act && !n->training) ? nullptr : n->y[l].p;
-    net_conv_fwd(n->stream, in.p, B, Ly.ci, Ly.cip, Ly.Wm, Ly.kp, Ly.co, Ly.cop, n->params + Ly.b_off, y,
-                 Ly.act ? n->a[l].p : nullptr, n->cur_L >> Ly.level);
+    net_conv_fwd(n->stream, conv_input(n, Ly), n->cur_B, Ly.ci, Ly.cip, Ly.Wm, Ly.kp, Ly.co, Ly.cop,
+                 n->params + Ly.b_off, y, Ly.act ? n->a[l].p : nullptr, n->cur_L >> Ly.level);
 }
 
 long long numel(const hsf_net *n, const Tensor &t) { return (long long)n->cur_B * t.c * vol(n->cur_L, t.level); }
 
+const Tensor &output(const hsf_net *n) { return n->y[n->n_layers - 1]; }
+
 void forward(hsf_net *n)
 {
-    const int B = n->cur_B, L = n->cur_L;
-    hipStream_t s = n->stream;
-    net_affine(s, n->x0.p, n->in_ch, vol(L, 0), numel(n, n->x0), n->norm, n->norm + n->in_ch);
-    conv(n, 0, n->x0, B);
-    conv(n, 1, n->a[0], B);                                   // e1 = a[1]
-    net_pool(s, n->a[1].p, n->p1.p, L, numel(n, n->p1));
-    conv(n, 2, n->p1, B);
-    conv(n, 3, n->a[2], B);                                   // e2 = a[3]
-    net_pool(s, n->a[3].p, n->p2.p, L >> 1, numel(n, n->p2));
-    conv(n, 4, n->p2, B);
-    conv(n, 5, n->a[4], B);                                   // e3 = a[5]
-    net_pool(s, n->a[5].p, n->p3.p, L >> 2, numel(n, n->p3));
-    conv(n, 6, n->p3, B);
-    conv(n, 7, n->a[6], B);                                   // e4 = a[7]
-    net_up(s, n->a[7].p, n->u3.p, L >> 2, numel(n, n->u3));
-    conv(n, 8, n->u3, B);
-    net_add(s, n->a[8].p, n->a[5].p, n->t3.p, numel(n, n->t3));
-    conv(n, 9, n->t3, B);                                     // d3 = a[9]
-    net_up(s, n->a[9].p, n->u2.p, L >> 1, numel(n, n->u2));
-    conv(n, 10, n->u2, B);
-    net_add(s, n->a[10].p, n->a[3].p, n->t2.p, numel(n, n->t2));
-    conv(n, 11, n->t2, B);                                    // d2 = a[11]
-    net_up(s, n->a[11].p, n->u1.p, L, numel(n, n->u1));
-    conv(n, 12, n->u1, B);
-    net_add(s, n->a[12].p, n->a[1].p, n->t1.p, numel(n, n->t1));
-    conv(n, 13, n->t1, B);                                    // d1 = a[13]
-    conv(n, 14, n->a[13], B);                                 // out = y[14]
+    net_affine(n->stream, n->x0.p, n->in_ch, vol(n->cur_L, 0), numel(n, n->x0), n->norm, n->norm + n->in_ch);
+    for (int l = 0; l < n->n_layers; ++l) conv(n, l);
 }
 
-// Gradient of layer l given dy[l]: weight and bias gradients, and (din != null) the
-// gradient of its input.
-void conv_bwd(hsf_net *n, int l, const Tensor &in, float *din)
-{
-    const Layer &Ly = n->layer[l];
-    const int B = n->cur_B, Ll = n->cur_L >> Ly.level;
-    net_conv_wgrad(n->stream, in.p, B, Ly.ci, Ly.cip, n->dy[l].p, Ly.co, Ly.cop, Ly.kp, Ll, n->wpart, Ly.dWm);
-    net_unstage_grad(n->stream, Ly.dWm, Ly.co, Ly.ci, Ly.cip, Ly.kp, n->grad + Ly.w_off);
-    net_channel_sum(n->stream, n->dy[l].p, B, Ly.co, vol(n->cur_L, Ly.level), n->bpart, n->grad + Ly.b_off);
-    if (din)
-        net_conv_fwd(n->stream, n->dy[l].p, B, Ly.co, Ly.cip_t, Ly.Wt, Ly.kp_t, Ly.ci, Ly.cop_t, nullptr, din,
-                     nullptr, Ll);
-}
-
-// dy[l] = dA * silu'(y[l])
-void act_bwd(hsf_net *n, int l, const float *dA)
-{
-    net_silu_bwd(n->stream, dA, n->y[l].p, n->dy[l].p, numel(n, n->y[l]));
-}
-
+// Backward pass from dout (gradient of the loss with respect to the output).  Layers
+// are visited from the last; every consumer of an activation comes after it, so
+// da[j] is complete when layer j is reached.  dgrad writes the gradient of a layer's
+// composed input into din, which is then distributed to the activations it read.
 void backward(hsf_net *n)
 {
     hipStream_t s = n->stream;
-    const int L = n->cur_L;
-    // out = y[14] = conv(d1): dy[14] = dout
-    (void)hipMemcpyAsync(n->dy[14].p, n->dout.p, sizeof(float) * numel(n, n->dout), hipMemcpyDeviceToDevice, s);
-    conv_bwd(n, 14, n->a[13], n->da[13].p);
-    act_bwd(n, 13, n->da[13].p);
-    conv_bwd(n, 13, n->t1, n->dt1.p);                         // t1 = a[12] + e1
-    act_bwd(n, 12, n->dt1.p);
-    conv_bwd(n, 12, n->u1, n->du1.p);
-    net_up_bwd(s, n->du1.p, n->da[11].p, L, numel(n, n->a[11]));
-    act_bwd(n, 11, n->da[11].p);
-    conv_bwd(n, 11, n->t2, n->dt2.p);                         // t2 = a[10] + e2
-    act_bwd(n, 10, n->dt2.p);
-    conv_bwd(n, 10, n->u2, n->du2.p);
-    net_up_bwd(s, n->du2.p, n->da[9].p, L >> 1, numel(n, n->a[9]));
-    act_bwd(n, 9, n->da[9].p);
-    conv_bwd(n, 9, n->t3, n->dt3.p);                          // t3 = a[8] + e3
-    act_bwd(n, 8, n->dt3.p);
-    conv_bwd(n, 8, n->u3, n->du3.p);
-    net_up_bwd(s, n->du3.p, n->da[7].p, L >> 2, numel(n, n->a[7]));   // e4
-    act_bwd(n, 7, n->da[7].p);
-    conv_bwd(n, 7, n->a[6], n->da[6].p);
-    act_bwd(n, 6, n->da[6].p);
-    conv_bwd(n, 6, n->p3, n->dp3.p);
-    // e3 = a[5] feeds the pooling and the skip sum t3
-    net_pool_bwd(s, n->dp3.p, n->da[5].p, L >> 2, numel(n, n->a[5]), 0);
-    net_add(s, n->dt3.p, nullptr, n->da[5].p, numel(n, n->a[5]));
-    act_bwd(n, 5, n->da[5].p);
-    conv_bwd(n, 5, n->a[4], n->da[4].p);
-    act_bwd(n, 4, n->da[4].p);
-    conv_bwd(n, 4, n->p2, n->dp2.p);
-    net_pool_bwd(s, n->dp2.p, n->da[3].p, L >> 1, numel(n, n->a[3]), 0);   // e2
-    net_add(s, n->dt2.p, nullptr, n->da[3].p, numel(n, n->a[3]));
-    act_bwd(n, 3, n->da[3].p);
-    conv_bwd(n, 3, n->a[2], n->da[2].p);
-    act_bwd(n, 2, n->da[2].p);
-    conv_bwd(n, 2, n->p1, n->dp1.p);
-    net_pool_bwd(s, n->dp1.p, n->da[1].p, L, numel(n, n->a[1]), 0);        // e1
-    net_add(s, n->dt1.p, nullptr, n->da[1].p, numel(n, n->a[1]));
-    act_bwd(n, 1, n->da[1].p);
-    conv_bwd(n, 1, n->a[0], n->da[0].p);
-    act_bwd(n, 0, n->da[0].p);
-    conv_bwd(n, 0, n->x0, nullptr);
+    const int B = n->cur_B, L = n->cur_L;
+    bool have[kLayers] = {false};
+    for (int l = n->n_layers - 1; l >= 0; --l) {
+        const Layer &Ly = n->layer[l];
+        const int Ll = L >> Ly.level;
+        const long long V = vol(L, Ly.level);
+        if (Ly.act) {
+            net_silu_bwd(s, n->da[l].p, n->y[l].p, n->dy[l].p, numel(n, n->dy[l]));
+        } else {
+            (void)hipMemcpyAsync(n->dy[l].p, n->dout.p, sizeof(float) * numel(n, n->dout), hipMemcpyDeviceToDevice,
+                                 s);
+        }
+        net_conv_wgrad(s, conv_input(n, Ly), B, Ly.ci, Ly.cip, n->dy[l].p, Ly.co, Ly.cop, Ly.kp, Ll, n->wpart,
+                       Ly.dWm);
+        net_unstage_grad(s, Ly.dWm, Ly.co, Ly.ci, Ly.cip, Ly.kp, n->grad + Ly.w_off);
+        net_channel_sum(s, n->dy[l].p, B, Ly.co, V, n->bpart, n->grad + Ly.b_off);
+        if (Ly.src1 < 0) continue;   // the network input needs no gradient
+        ConvIn g{n->dy[l].p, nullptr, CONV_IN_PLAIN};
+        net_conv_fwd(s, g, B, Ly.co, Ly.cip_t, Ly.Wt, Ly.kp_t, Ly.ci, Ly.cop_t, nullptr, n->din, nullptr, Ll);
+        const long long nin = input_numel(n, Ly);
+        auto give = [&](int j) {   // da[j] (+)= din through the input's composition
+            float *dst = n->da[j].p;
+            const int add = have[j] ? 1 : 0;
+            if (Ly.in_mode == CONV_IN_UP)
+                net_up_bwd(s, n->din, dst, Ll, numel(n, n->da[j]), add);
+            else if (Ly.in_mode == CONV_IN_POOL)
+                net_pool_bwd(s, n->din, dst, L >> n->layer[j].level, numel(n, n->da[j]), add);
+            else
+                net_accum(s, dst, n->din, nin, add);
+            have[j] = true;
+        };
+        give(Ly.src1);
+        if (Ly.in_mode == CONV_IN_ADD) give(Ly.src2);
+    }
 }
 
 int copy_f32(hsf_net *n, float *dst, const float *src, size_t count, int where, hipMemcpyKind host_kind)
@@ -325,7 +280,9 @@ int copy_f32(hsf_net *n, float *dst, const float *src, size_t count, int where, 
 
 int check_box(hsf_net *n, int B, int L)
 {
-    if (B < 1 || L < 8 || (L % 8) != 0) return nfail(n, HSF_EINVAL, "batch %d, box %d: need L a multiple of 8", B, L);
+    const int q = 1 << (n->depth - 1);
+    if (B < 1 || L < q || (L % q) != 0)
+        return nfail(n, HSF_EINVAL, "batch %d, box %d: need L a multiple of %d", B, L, q);
     return HSF_OK;
 }
 
@@ -341,7 +298,7 @@ int loss_and_grad(hsf_net *n, double *loss)
     forward(n);
     n->training = 0;
     const long long cnt = numel(n, n->dout);
-    const int blocks = net_mse(n->stream, n->y[14].p, n->target, n->dout.p, cnt, 1.0f / (float)cnt, n->loss_part);
+    const int blocks = net_mse(n->stream, output(n).p, n->target, n->dout.p, cnt, 1.0f / (float)cnt, n->loss_part);
     backward(n);
     NCHK(n, hipGetLastError());
     std::vector<double> lp(blocks);
@@ -374,25 +331,44 @@ int hsf_net_create(int in_ch, int out_ch, const int widths[4], unsigned long lon
     if (!out || !widths || in_ch < 1 || in_ch > kNetMaxWidth || out_ch < 1 || out_ch > kNetMaxWidth)
         return HSF_EINVAL;
     *out = nullptr;
-    for (int i = 0; i < 4; ++i)
-        if (widths[i] < 1 || widths[i] > kNetMaxWidth) return HSF_EINVAL;
+    int D = 0;
+    while (D < kMaxLevels && widths[D] > 0) ++D;
+    if (D == 0) return HSF_EINVAL;
+    for (int i = 0; i < kMaxLevels; ++i)
+        if (widths[i] > kNetMaxWidth || widths[i] < 0 || (i >= D && widths[i] != 0)) return HSF_EINVAL;
     hsf_net *n = new hsf_net();
     n->in_ch = in_ch;
     n->out_ch = out_ch;
-    for (int i = 0; i < 4; ++i) n->w[i] = widths[i];
+    n->depth = D;
+    for (int i = 0; i < kMaxLevels; ++i) n->w[i] = widths[i];
     const int *w = widths;
-    const int spec[kLayers][4] = {  // ci, co, act, level
-        {in_ch, w[0], 1, 0}, {w[0], w[0], 1, 0}, {w[0], w[1], 1, 1}, {w[1], w[1], 1, 1},
-        {w[1], w[2], 1, 2},  {w[2], w[2], 1, 2}, {w[2], w[3], 1, 3}, {w[3], w[3], 1, 3},
-        {w[3], w[2], 1, 2},  {w[2], w[2], 1, 2}, {w[2], w[1], 1, 1}, {w[1], w[1], 1, 1},
-        {w[1], w[0], 1, 0},  {w[0], w[0], 1, 0}, {w[0], out_ch, 0, 0}};
+    int nl = 0;
+    auto add = [&](int ci, int co, int act, int level, int mode, int src1, int src2) {
+        Layer &Ly = n->layer[nl++];
+        Ly.ci = ci;
+        Ly.co = co;
+        Ly.act = act;
+        Ly.level = level;
+        Ly.in_mode = mode;
+        Ly.src1 = src1;
+        Ly.src2 = src2;
+    };
+    for (int lev = 0; lev < D; ++lev) {   // encoder: e(lev+1) = activation of layer 2 lev + 1
+        if (lev == 0) add(in_ch, w[0], 1, 0, CONV_IN_PLAIN, -1, -1);
+        else add(w[lev - 1], w[lev], 1, lev, CONV_IN_POOL, 2 * lev - 1, -1);
+        add(w[lev], w[lev], 1, lev, CONV_IN_PLAIN, nl - 1, -1);
+    }
+    int prev = 2 * D - 1;                 // d(D) = e(D)
+    for (int lev = D - 2; lev >= 0; --lev) {
+        add(w[lev + 1], w[lev], 1, lev, CONV_IN_UP, prev, -1);
+        add(w[lev], w[lev], 1, lev, CONV_IN_ADD, nl - 1, 2 * lev + 1);
+        prev = nl - 1;
+    }
+    add(w[0], out_ch, 0, 0, CONV_IN_PLAIN, prev, -1);
+    n->n_layers = nl;
     long long off = 0;
-    for (int l = 0; l < kLayers; ++l) {
+    for (int l = 0; l < nl; ++l) {
         Layer &Ly = n->layer[l];
-        Ly.ci = spec[l][0];
-        Ly.co = spec[l][1];
-        Ly.act = spec[l][2];
-        Ly.level = spec[l][3];
         Ly.cip = round_up(Ly.ci, 8);
         Ly.kp = round_up(27 * Ly.cip, 32);
         Ly.cop = round_up(Ly.co, 16);
@@ -411,7 +387,7 @@ int hsf_net_create(int in_ch, int out_ch, const int widths[4], unsigned long lon
     if (rc == HSF_OK) rc = nalloc(n, n->allocs, (void **)&n->m, sizeof(float) * off);
     if (rc == HSF_OK) rc = nalloc(n, n->allocs, (void **)&n->v, sizeof(float) * off);
     if (rc == HSF_OK) rc = nalloc(n, n->allocs, (void **)&n->norm, sizeof(float) * 2 * in_ch);
-    for (int l = 0; l < kLayers && rc == HSF_OK; ++l) {
+    for (int l = 0; l < n->n_layers && rc == HSF_OK; ++l) {
         Layer &Ly = n->layer[l];
         rc = nalloc(n, n->allocs, (void **)&Ly.Wm, sizeof(__bf16) * (size_t)Ly.cop * Ly.kp);
         if (rc == HSF_OK) rc = nalloc(n, n->allocs, (void **)&Ly.Wt, sizeof(__bf16) * (size_t)Ly.cop_t * Ly.kp_t);
@@ -422,10 +398,10 @@ int hsf_net_create(int in_ch, int out_ch, const int widths[4], unsigned long lon
         return rc;
     }
     std::vector<float> p(off, 0.0f);
-    for (int l = 0; l < kLayers; ++l) {
+    for (int l = 0; l < n->n_layers; ++l) {
         const Layer &Ly = n->layer[l];
         double a = sqrt(3.0 / (27.0 * Ly.ci));
-        if (l == kLayers - 1) a *= 0.25;
+        if (l == n->n_layers - 1) a *= 0.25;
         for (long long i = 0; i < (long long)Ly.co * Ly.ci * 27; ++i)
             p[Ly.w_off + i] = (float)(a * (2.0 * unit_hash(seed, Ly.w_off + i) - 1.0));
     }
@@ -506,7 +482,7 @@ int hsf_net_forward(hsf_net *n, const float *in, float *out, int batch, int L, i
         return rc;
     forward(n);
     NCHK(n, hipGetLastError());
-    return copy_f32(n, out, n->y[14].p, (size_t)batch * n->out_ch * vol(L, 0), where, hipMemcpyDeviceToHost);
+    return copy_f32(n, out, output(n).p, (size_t)batch * n->out_ch * vol(L, 0), where, hipMemcpyDeviceToHost);
 }
 
 int hsf_net_loss_grad(hsf_net *n, const float *in, const float *target, int batch, int L, double *loss, float *grad,
@@ -542,33 +518,37 @@ int hsf_net_train_step(hsf_net *n, const float *in, const float *target, int bat
 
 namespace hsf {
 
-// Prediction for one replica: x is the prepared FP32 input [in_ch][V] (device), pred
-// receives [out_ch][V] FP32 (device).  Returns an HSF code.
-int net_predict(hsf_net *n, hipStream_t s, const float *x, int in_ch, int L, float *pred)
+// Prediction for B samples (replicas) on an L^3 box: x is the prepared FP32 input
+// [B][in_ch][V] (device), pred receives [B][out_ch][V] FP32 (device).  Returns an HSF
+// code.
+int net_predict(hsf_net *n, hipStream_t s, const float *x, int in_ch, int B, int L, float *pred)
 {
     if (!n || in_ch != n->in_ch) return HSF_EINVAL;
-    int rc = check_box(n, 1, L);
+    int rc = check_box(n, B, L);
     if (rc) return rc;
     hipStream_t saved = n->stream;
     n->stream = s;
-    if ((rc = ensure_acts(n, 1, L, false)) || (!n->weights_staged && (rc = stage_weights(n)))) {
+    if ((rc = ensure_acts(n, B, L, false)) || (!n->weights_staged && (rc = stage_weights(n)))) {
         n->stream = saved;
         return rc;
     }
-    hipError_t e = hipMemcpyAsync(n->x0.p, x, sizeof(float) * in_ch * vol(L, 0), hipMemcpyDeviceToDevice, s);
+    hipError_t e = hipMemcpyAsync(n->x0.p, x, sizeof(float) * (size_t)B * in_ch * vol(L, 0), hipMemcpyDeviceToDevice,
+                                  s);
     if (e == hipSuccess) {
         forward(n);
-        e = hipMemcpyAsync(pred, n->y[14].p, sizeof(float) * n->out_ch * vol(L, 0), hipMemcpyDeviceToDevice, s);
+        e = hipMemcpyAsync(pred, output(n).p, sizeof(float) * (size_t)B * n->out_ch * vol(L, 0),
+                           hipMemcpyDeviceToDevice, s);
     }
     n->stream = saved;
     return e == hipSuccess ? HSF_OK : HSF_EHIP;
 }
 
-int net_channels(const hsf_net *n, int *in_ch, int *out_ch)
+int net_channels(const hsf_net *n, int *in_ch, int *out_ch, int *box_multiple)
 {
     if (!n) return HSF_EINVAL;
     *in_ch = n->in_ch;
     *out_ch = n->out_ch;
+    *box_multiple = 1 << (n->depth - 1);
     return HSF_OK;
 }
 

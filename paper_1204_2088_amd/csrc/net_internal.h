@@ -7,17 +7,27 @@ namespace hsf {
 
 constexpr int kNetMaxWidth = 32;   // widest layer the weight-gradient kernel supports
 
-void net_conv_fwd(hipStream_t s, const float *X, int B, int ci, int cip, const __bf16 *Wm, int kp, int co, int cop,
+// Input of a convolution, composed while its tile is staged (never stored):
+//   CONV_IN_PLAIN  x1                    (x1 on the convolution's box)
+//   CONV_IN_ADD    x1 + x2               (both on the convolution's box)
+//   CONV_IN_UP     nearest 2x upsampling of x1 (x1 on the box of half the edge)
+//   CONV_IN_POOL   2x2x2 average of x1   (x1 on the box of twice the edge)
+// x1, x2 are [batch][ci][site] on their own boxes.
+enum { CONV_IN_PLAIN = 0, CONV_IN_ADD = 1, CONV_IN_UP = 2, CONV_IN_POOL = 3 };
+struct ConvIn {
+    const float *x1, *x2;
+    int mode;
+};
+
+void net_conv_fwd(hipStream_t s, ConvIn in, int B, int ci, int cip, const __bf16 *Wm, int kp, int co, int cop,
                   const float *bias, float *Y, float *A, int L);
 int net_wgrad_slices(int B, int L, int cop, int kp);
-void net_conv_wgrad(hipStream_t s, const float *X, int B, int ci, int cip, const float *dY, int co, int cop, int kp,
+void net_conv_wgrad(hipStream_t s, ConvIn in, int B, int ci, int cip, const float *dY, int co, int cop, int kp,
                     int L, float *part, float *dWm);
 void net_silu_bwd(hipStream_t s, const float *dA, const float *Y, float *dY, long long n);
-void net_pool(hipStream_t s, const float *in, float *out, int L, long long n_out);
 void net_pool_bwd(hipStream_t s, const float *dout, float *din, int L, long long n_in, int add);
-void net_up(hipStream_t s, const float *in, float *out, int L, long long n_out);
-void net_up_bwd(hipStream_t s, const float *dout, float *din, int L, long long n_in);
-void net_add(hipStream_t s, const float *a, const float *b, float *c, long long n);
+void net_up_bwd(hipStream_t s, const float *dout, float *din, int L, long long n_in, int add);
+void net_accum(hipStream_t s, float *dst, const float *src, long long n, int add);
 int net_channel_parts(int C);
 void net_channel_sum(hipStream_t s, const float *g, int B, int C, long long V, double *part, float *out);
 int net_mse(hipStream_t s, const float *p, const float *t, float *dp, long long n, float inv_count, double *part);

@@ -57,13 +57,41 @@ __device__ __forceinline__ int wrap_tile(int v, int L, bool small)
 
 size_t conv_fwd_lds(int cip, int cop) { return (size_t)(HS * cip + cop * kSlabRow) * sizeof(__bf16); }
 
-// Stage the input tile of one sample with its one-site halo into LDS as BF16, either
+// Value of input channel c of sample b at site (gx, gy, gz) of the convolution's
+// L^3 box, read through the input's composition (ConvIn): the tensor itself, the sum
+// of two tensors (decoder skip), the nearest 2x upsampling of a tensor on the
+// (L/2)^3 box, or the 2x2x2 average of a tensor on the (2L)^3 box (summed in the
+// order dz, dy, dx, as the pooling of the backward pass assumes).
+__device__ __forceinline__ float conv_input(const ConvIn &in, int b, int c, int ci, int gx, int gy, int gz, int L)
+{
+    if (in.mode == CONV_IN_UP) {
+        const int h = L >> 1;
+        const long long vh = (long long)h * h * h;
+        return in.x1[((long long)b * ci + c) * vh + (gx >> 1) + (long long)h * ((gy >> 1) + (long long)h * (gz >> 1))];
+    }
+    if (in.mode == CONV_IN_POOL) {
+        const int f = L << 1;
+        const long long vf = (long long)f * f * f;
+        const float *p = in.x1 + ((long long)b * ci + c) * vf;
+        float s = 0.0f;
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx)
+                    s += p[(2 * gx + dx) + (long long)f * ((2 * gy + dy) + (long long)f * (2 * gz + dz))];
+        return 0.125f * s;
+    }
+    const long long V = (long long)L * L * L;
+    const long long e = ((long long)b * ci + c) * V + gx + (long long)L * (gy + (long long)L * gz);
+    return in.mode == CONV_IN_ADD ? in.x1[e] + in.x2[e] : in.x1[e];
+}
+
+// Stage the input tile of sample b with its one-site halo into LDS as BF16, either
 // site-major xs[h][cip] (forward) or channel-major xs[c][HS] (weight gradient);
-// channels ci..cip-1 are zero.  Loads are issued eight per thread before any is used,
-// so their latencies overlap.
+// channels ci..cip-1 are zero.  Loads are issued eight elements per thread before any
+// is used, so their latencies overlap.
 template <bool SITE_MAJOR>
-__device__ __forceinline__ void stage_halo(const float *__restrict__ Xb, long long V, int ci, int cip, int L, int x0,
-                                           int y0, int z0, __bf16 *xs)
+__device__ __forceinline__ void stage_halo(const ConvIn &in, int b, int ci, int cip, int L, int x0, int y0, int z0,
+                                           __bf16 *xs)
 {
     const bool small = L < TX;
     const int total = HS * cip;
@@ -78,7 +106,7 @@ __device__ __forceinline__ void stage_halo(const float *__restrict__ Xb, long lo
                 const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
                 const int gx = wrap_tile(x0 + hx - 1, L, small), gy = wrap_tile(y0 + hy - 1, L, small),
                           gz = wrap_tile(z0 + hz - 1, L, small);
-                v[u] = Xb[(long long)c * V + gx + (long long)L * (gy + (long long)L * gz)];
+                v[u] = conv_input(in, b, c, ci, gx, gy, gz, L);
             }
         }
 #pragma unroll
@@ -92,7 +120,7 @@ __device__ __forceinline__ void stage_halo(const float *__restrict__ Xb, long lo
     }
 }
 
-__global__ __launch_bounds__(256) void k_conv_fwd(const float *__restrict__ X, int ci, int cip,
+__global__ __launch_bounds__(256) void k_conv_fwd(ConvIn in, int ci, int cip,
                                                    const __bf16 *__restrict__ Wm, int kp, int co, int cop,
                                                    const float *__restrict__ bias, float *__restrict__ Y,
                                                    float *__restrict__ A, int L, int tiles_x, int tiles_y,
@@ -108,7 +136,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float *__restrict__ X, i
     const int y0 = (t % tiles_y) * TY;
     const int z0 = (t / tiles_y) * TZ;
     const long long V = (long long)L * L * L;
-    stage_halo<true>(X + (long long)b * ci * V, V, ci, cip, L, x0, y0, z0, xs);
+    stage_halo<true>(in, b, ci, cip, L, x0, y0, z0, xs);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane >> 4, col = lane & 15;
     const int nmt = cop / 16;
@@ -201,7 +229,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float *__restrict__ X, i
 // [sp][cop][kp] and is summed in a fixed order by k_sum_blocks.
 constexpr int WG_TILES_PER_WAVE = 4;
 
-__global__ __launch_bounds__(256) void k_conv_wgrad(const float *__restrict__ X, int ci, int cip,
+__global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn in, int ci, int cip,
                                                      const float *__restrict__ dY, int co, int cop, int kp,
                                                      int L, int tiles_x, int tiles_y, int tiles_per_sample,
                                                      int n_tiles, int n_groups, int n_slices,
@@ -226,7 +254,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const float *__restrict__ X,
         const int y0 = (t % tiles_y) * TY;
         const int z0 = (t / tiles_y) * TZ;
         __syncthreads();
-        stage_halo<false>(X + (long long)b * ci * V, V, ci, cip, L, x0, y0, z0, xs);
+        stage_halo<false>(in, b, ci, cip, L, x0, y0, z0, xs);
         for (int e0 = threadIdx.x; e0 < TS * cop; e0 += 256 * 8) {
             float v[8];
 #pragma unroll
@@ -315,23 +343,6 @@ __global__ void k_silu_bwd(const float *__restrict__ dA, const float *__restrict
     if (e < n) dY[e] = dA[e] * silu_grad(Y[e]);
 }
 
-// 2x2x2 average pooling: out (L/2)^3 from in L^3, per (batch, channel) plane set.
-__global__ void k_pool(const float *__restrict__ in, float *__restrict__ out, int L, long long n_out)
-{
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n_out) return;
-    const int h = L / 2;
-    const long long vo = (long long)h * h * h, vi = (long long)L * L * L;
-    const long long bc = e / vo, r = e % vo;
-    const int x = (int)(r % h), y = (int)((r / h) % h), z = (int)(r / ((long long)h * h));
-    const float *p = in + bc * vi;
-    float s = 0.0f;
-    for (int dz = 0; dz < 2; ++dz)
-        for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx) s += p[(2 * x + dx) + (long long)L * ((2 * y + dy) + (long long)L * (2 * z + dz))];
-    out[e] = 0.125f * s;
-}
-
 // gradient of the pooling: din[fine] (+)= dout[coarse] / 8
 __global__ void k_pool_bwd(const float *__restrict__ dout, float *__restrict__ din, int L, long long n_in, int add)
 {
@@ -345,20 +356,8 @@ __global__ void k_pool_bwd(const float *__restrict__ dout, float *__restrict__ d
     din[e] = add ? din[e] + g : g;
 }
 
-// nearest 2x upsampling: out L^3 from in (L/2)^3
-__global__ void k_up(const float *__restrict__ in, float *__restrict__ out, int L, long long n_out)
-{
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n_out) return;
-    const int h = L / 2;
-    const long long vo = (long long)L * L * L, vi = (long long)h * h * h;
-    const long long bc = e / vo, r = e % vo;
-    const int x = (int)(r % L), y = (int)((r / L) % L), z = (int)(r / ((long long)L * L));
-    out[e] = in[bc * vi + (x / 2) + (long long)h * ((y / 2) + (long long)h * (z / 2))];
-}
-
-// gradient of the upsampling: dcoarse = sum of the 8 fine gradients
-__global__ void k_up_bwd(const float *__restrict__ dout, float *__restrict__ din, int L, long long n_in)
+// gradient of the upsampling: dcoarse (+)= sum of the 8 fine gradients
+__global__ void k_up_bwd(const float *__restrict__ dout, float *__restrict__ din, int L, long long n_in, int add)
 {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_in) return;
@@ -371,14 +370,14 @@ __global__ void k_up_bwd(const float *__restrict__ dout, float *__restrict__ din
     for (int dz = 0; dz < 2; ++dz)
         for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx) s += p[(2 * x + dx) + (long long)L * ((2 * y + dy) + (long long)L * (2 * z + dz))];
-    din[e] = s;
+    din[e] = add ? din[e] + s : s;
 }
 
-// c = a + b; with add_to: c += a
-__global__ void k_add(const float *__restrict__ a, const float *__restrict__ b, float *__restrict__ c, long long n)
+// dst = src, or dst += src
+__global__ void k_accum(float *__restrict__ dst, const float *__restrict__ src, long long n, int add)
 {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) c[e] = a[e] + (b ? b[e] : c[e]);
+    if (e < n) dst[e] = add ? dst[e] + src[e] : src[e];
 }
 
 // Per-channel sum over batch and sites, out[c] = sum_{b,x} g[b][c][x], in two fixed-order
@@ -593,12 +592,12 @@ __global__ void k_affine(float *__restrict__ x, int C, long long V, long long n,
 // ---------------------------------------------------------------- launchers
 static inline unsigned nb(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
-void net_conv_fwd(hipStream_t s, const float *X, int B, int ci, int cip, const __bf16 *Wm, int kp, int co, int cop,
+void net_conv_fwd(hipStream_t s, ConvIn in, int B, int ci, int cip, const __bf16 *Wm, int kp, int co, int cop,
                   const float *bias, float *Y, float *A, int L)
 {
     const int tx = (L + TX - 1) / TX, ty = (L + TY - 1) / TY, tz = (L + TZ - 1) / TZ;
     const int tps = tx * ty * tz;
-    hipLaunchKernelGGL(k_conv_fwd, dim3(B * tps), dim3(256), conv_fwd_lds(cip, cop), s, X, ci, cip, Wm, kp, co, cop,
+    hipLaunchKernelGGL(k_conv_fwd, dim3(B * tps), dim3(256), conv_fwd_lds(cip, cop), s, in, ci, cip, Wm, kp, co, cop,
                        bias, Y, A, L, tx, ty, tps);
 }
 
@@ -614,7 +613,7 @@ int net_wgrad_slices(int B, int L, int cop, int kp)
     return std::min(n_tiles, want);
 }
 
-void net_conv_wgrad(hipStream_t s, const float *X, int B, int ci, int cip, const float *dY, int co, int cop, int kp,
+void net_conv_wgrad(hipStream_t s, ConvIn in, int B, int ci, int cip, const float *dY, int co, int cop, int kp,
                     int L, float *part, float *dWm)
 {
     const int tx = (L + TX - 1) / TX, ty = (L + TY - 1) / TY, tz = (L + TZ - 1) / TZ;
@@ -622,7 +621,7 @@ void net_conv_wgrad(hipStream_t s, const float *X, int B, int ci, int cip, const
     const int slices = net_wgrad_slices(B, L, cop, kp);
     const int ntiles = (cop / 16) * (kp / 16), groups = (ntiles + 15) / 16;
     const size_t lds = ((size_t)cip * HS + (size_t)cop * TS) * sizeof(__bf16);
-    hipLaunchKernelGGL(k_conv_wgrad, dim3(groups * slices), dim3(256), lds, s, X, ci, cip, dY, co, cop, kp, L, tx,
+    hipLaunchKernelGGL(k_conv_wgrad, dim3(groups * slices), dim3(256), lds, s, in, ci, cip, dY, co, cop, kp, L, tx,
                        ty, tps, n_tiles, groups, slices, part);
     const long long n = (long long)cop * kp;
     hipLaunchKernelGGL(k_sum_blocks, dim3(nb(n, 32)), dim3(256), 0, s, part, slices, n, dWm);
@@ -633,29 +632,19 @@ void net_silu_bwd(hipStream_t s, const float *dA, const float *Y, float *dY, lon
     hipLaunchKernelGGL(k_silu_bwd, dim3(nb(n, 256)), dim3(256), 0, s, dA, Y, dY, n);
 }
 
-void net_pool(hipStream_t s, const float *in, float *out, int L, long long n_out)
-{
-    hipLaunchKernelGGL(k_pool, dim3(nb(n_out, 256)), dim3(256), 0, s, in, out, L, n_out);
-}
-
 void net_pool_bwd(hipStream_t s, const float *dout, float *din, int L, long long n_in, int add)
 {
     hipLaunchKernelGGL(k_pool_bwd, dim3(nb(n_in, 256)), dim3(256), 0, s, dout, din, L, n_in, add);
 }
 
-void net_up(hipStream_t s, const float *in, float *out, int L, long long n_out)
+void net_up_bwd(hipStream_t s, const float *dout, float *din, int L, long long n_in, int add)
 {
-    hipLaunchKernelGGL(k_up, dim3(nb(n_out, 256)), dim3(256), 0, s, in, out, L, n_out);
+    hipLaunchKernelGGL(k_up_bwd, dim3(nb(n_in, 256)), dim3(256), 0, s, dout, din, L, n_in, add);
 }
 
-void net_up_bwd(hipStream_t s, const float *dout, float *din, int L, long long n_in)
+void net_accum(hipStream_t s, float *dst, const float *src, long long n, int add)
 {
-    hipLaunchKernelGGL(k_up_bwd, dim3(nb(n_in, 256)), dim3(256), 0, s, dout, din, L, n_in);
-}
-
-void net_add(hipStream_t s, const float *a, const float *b, float *c, long long n)
-{
-    hipLaunchKernelGGL(k_add, dim3(nb(n, 256)), dim3(256), 0, s, a, b, c, n);
+    hipLaunchKernelGGL(k_accum, dim3(nb(n, 256)), dim3(256), 0, s, dst, src, n, add);
 }
 
 int net_channel_parts(int C) { return C * kChanSlices; }

@@ -33,7 +33,8 @@ EXPORTED = [
     "hsf_set_hydro", "hsf_set_timing", "hsf_get_timing", "hsf_set_tile", "hsf_get_tile", "hsf_autotune",
     "hsf_set_solver", "hsf_get_work", "hsf_set_warm", "hsf_net_create", "hsf_net_destroy",
     "hsf_net_last_error", "hsf_net_set_stream", "hsf_net_num_params", "hsf_net_set_params",
-    "hsf_net_get_params", "hsf_net_set_input_norm", "hsf_net_forward", "hsf_net_loss_grad", "hsf_net_train_step", "hsf_attach_net",
+    "hsf_net_get_params", "hsf_net_set_input_norm", "hsf_net_forward", "hsf_net_loss_grad",
+    "hsf_net_train_step", "hsf_attach_net", "hsf_set_net_gate",
 ]
 WARM_EXTRAP, WARM_NET, WARM_NET_DELTA, WARM_NET_EXTRAP = 2, 3, 4, 5
 SOLVER_PRECOND = 1
@@ -123,6 +124,7 @@ def load():
         "hsf_net_loss_grad": ([C, P, P, I, I, ctypes.POINTER(ctypes.c_double), P, I], I),
         "hsf_net_train_step": ([C, P, P, I, I, ctypes.c_float, ctypes.POINTER(ctypes.c_double), I], I),
         "hsf_attach_net": ([C, C], I),
+        "hsf_set_net_gate": ([C, I], I),
         "hsf_get_work": ([C, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double), I], I),
         "hsf_set_tile": ([C, ctypes.POINTER(ctypes.c_int)], I),
         "hsf_get_tile": ([C, ctypes.POINTER(ctypes.c_int)], I),
@@ -354,6 +356,10 @@ class Context:
         WARM_NET_DELTA, WARM_NET_EXTRAP)."""
         self._check(self._lib.hsf_set_warm(self._h, int(warm)))
 
+    def set_net_gate(self, min_iters):
+        """Use the network only after inversions of at least min_iters iterations (0: always)."""
+        self._check(self._lib.hsf_set_net_gate(self._h, int(min_iters)))
+
     def attach_net(self, net):
         self._check(self._lib.hsf_attach_net(self._h, net._h if net is not None else None))
         self._net = net   # keep it alive while attached
@@ -370,11 +376,16 @@ class Context:
 
 
 class Net:
-    """The warm-start U-Net (FP32 boundary arrays [batch][channel][L][L][L])."""
+    """The warm-start U-Net (FP32 boundary arrays [batch][channel][L][L][L]; L a
+    multiple of 2^(depth - 1))."""
 
     def __init__(self, in_ch, out_ch=2, widths=(8, 16, 24, 32), seed=0, stream=None):
+        """widths: 1 to 4 level widths (the number given is the depth of the U-Net)."""
         lib = load()
-        w = (ctypes.c_int * 4)(*[int(v) for v in widths])
+        widths = tuple(int(v) for v in widths)
+        if not 1 <= len(widths) <= 4:
+            raise ValueError("1 to 4 widths")
+        w = (ctypes.c_int * 4)(*(widths + (0,) * (4 - len(widths))))
         h = ctypes.c_void_p()
         rc = lib.hsf_net_create(int(in_ch), int(out_ch), w, ctypes.c_ulonglong(seed), ctypes.byref(h))
         if rc != HSF_OK:

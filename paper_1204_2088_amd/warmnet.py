@@ -22,7 +22,10 @@ import numpy as np
 from . import hsf
 from . import workloads as W
 
-DEFAULT_WIDTHS = (8, 16, 24, 32)
+# One level of 16 channels: the inversion's linear response reaches a few lattice
+# sites (about the chain's radius of gyration), which a single level covers; deeper
+# networks were no more accurate on held-out trajectories and cost more per step.
+DEFAULT_WIDTHS = (16,)
 
 
 def _torch():
@@ -151,8 +154,45 @@ def evaluate_loss(net, x, y, L, batch=2):
     return tot / max(n, 1)
 
 
+def train_warm_start(make_workloads, seeds, steps, record, widths=DEFAULT_WIDTHS, iters=1500, batch=2, lr=1e-3,
+                     lr_end=1e-4, val_seed=None, net_seed=1, log=None):
+    """Record trajectories of make_workloads(seed) for every training seed (FP64
+    propagators, residual 1e-10), build the first- and second-difference samples,
+    and train a network with 2 nsp inputs on them.  Returns (net, info)."""
+    torch = _torch()
+    t0 = time.perf_counter()
+    xs, ys = [], []
+    for seed in seeds:
+        traj = record_trajectory(make_workloads(seed), steps, record, tol=1e-10, precision="fp64", log=log)
+        x, y = make_samples(traj)
+        del traj
+        xs.append(x)
+        ys.append(y)
+    x, y = torch.cat(xs), torch.cat(ys)
+    del xs, ys
+    t_data = time.perf_counter() - t0
+    xv = yv = None
+    if val_seed is not None:   # early steps of a held-out trajectory
+        tv = record_trajectory(make_workloads(val_seed)[:1], 22, list(range(1, 22)), tol=1e-10, precision="fp64")
+        xv, yv = make_samples(tv)
+    L = round(x.shape[2] ** (1.0 / 3.0))
+    nsp = x.shape[1] // 2
+    net = hsf.Net(2 * nsp, 2, widths, seed=net_seed)
+    shift, scale = input_norm(x)
+    net.set_input_norm(shift, scale)
+    t1 = time.perf_counter()
+    losses = train(net, x, y, L, iters=iters, batch=batch, lr=lr, lr_end=lr_end, log=log, x_val=xv, y_val=yv)
+    torch.cuda.synchronize()
+    info = {"widths": list(widths), "parameters": int(net.n_params), "samples": int(x.shape[0]),
+            "training_seeds": list(seeds), "iterations": iters, "batch": batch,
+            "loss_first": float(losses[0]), "loss_last": float(np.mean(losses[-50:])),
+            "validation_loss": evaluate_loss(net, xv, yv, L) if xv is not None else None,
+            "data_seconds": t_data, "train_seconds": time.perf_counter() - t1}
+    return net, info
+
+
 def compare_warm_starts(wls, net, modes, start_steps, measure_steps, tol=1e-6, precision="fp32", tile=None,
-                        log=None):
+                        log=None, gate=0):
     """Step time and evaluations per step of each warm start on the trajectory of
     `wls`: the dynamics runs `start_steps` plain steps, the state is saved, and each
     mode then runs 2 plain steps (to build the history) and `measure_steps` timed
@@ -166,6 +206,7 @@ def compare_warm_starts(wls, net, modes, start_steps, measure_steps, tol=1e-6, p
         ctx.set_tile(tile)
     if net is not None:
         ctx.attach_net(net)
+        ctx.set_net_gate(gate)
     ctx.set_warm(hsf.WARM_CURRENT)
     if start_steps:
         ctx.step(start_steps, tol=tol, max_iter=1000)

@@ -73,6 +73,9 @@ def oracle_out(NO, params, x, in_ch, out_ch, widths, bf16, shift=None, scale=Non
     (3, 2, WIDTHS, 2, 16),
     (2, 3, (5, 12, 20, 32), 1, 24),     # ragged tiles on every level, odd widths
     (2, 2, (8, 8, 16, 16), 3, 8),       # 1^3 box on the coarsest level
+    (4, 2, (8, 16), 2, 20),             # two levels, ragged 20^3 / 10^3 boxes
+    (4, 2, (8, 16, 24), 1, 12),         # three levels down to 3^3
+    (4, 2, (16,), 2, 9),                # one level (no pooling), odd box
 ])
 def test_forward_matches_oracle(hsf, NO, in_ch, out_ch, widths, B, L):
     say(f"[net forward] in {in_ch} out {out_ch} widths {widths} B {B} L {L}")
@@ -97,11 +100,12 @@ def test_forward_matches_oracle(hsf, NO, in_ch, out_ch, widths, B, L):
     net.close()
 
 
-@pytest.mark.parametrize("B,L", [(2, 16), (4, 16), (1, 24)])
-def test_gradient_matches_oracle(hsf, NO, B, L):
+@pytest.mark.parametrize("B,L,widths", [(2, 16, WIDTHS), (4, 16, WIDTHS), (1, 24, WIDTHS), (2, 12, (8, 16)),
+                                         (1, 12, (8, 12, 16)), (2, 7, (8,))])
+def test_gradient_matches_oracle(hsf, NO, B, L, widths):
     in_ch, out_ch = 2, 2
-    say(f"[net gradient] widths {WIDTHS} B {B} L {L}")
-    net = hsf.Net(in_ch, out_ch, WIDTHS, seed=3)
+    say(f"[net gradient] widths {widths} B {B} L {L}")
+    net = hsf.Net(in_ch, out_ch, widths, seed=3)
     p = net.get_params()
     rng = np.random.Generator(np.random.PCG64(9))
     p = (p + 0.02 * rng.standard_normal(p.size)).astype(np.float32)
@@ -110,7 +114,7 @@ def test_gradient_matches_oracle(hsf, NO, B, L):
     x = smooth_inputs(B, in_ch, L, seed=21)
     t = smooth_inputs(B, out_ch, L, seed=22, mean=0.0, amp=1.0)
     loss, g = net.loss_grad(x.ravel(), t.ravel(), B, L)
-    lref, gref = NO.loss_and_grad(p, x, t, in_ch, out_ch, WIDTHS, bf16=True, shift=[0.5, 0.5], scale=[4.0, 4.0])
+    lref, gref = NO.loss_and_grad(p, x, t, in_ch, out_ch, widths, bf16=True, shift=[0.5, 0.5], scale=[4.0, 4.0])
     gref = np.asarray(gref)
     say(f"  loss gpu {loss:.8e} oracle {lref:.8e}")
     assert abs(loss - lref) <= 1e-3 * lref
@@ -118,7 +122,7 @@ def test_gradient_matches_oracle(hsf, NO, B, L):
     say(f"  gradient rel L2 {e:.3e}")
     assert e < 5e-3
     off = 0
-    for l, (ci, co) in enumerate(NO.layer_shapes(in_ch, out_ch, WIDTHS)):
+    for l, (ci, co) in enumerate(NO.layer_shapes(in_ch, out_ch, widths)):
         n = co * ci * 27 + co
         a, b = g[off:off + n].astype(np.float64), gref[off:off + n]
         cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
@@ -316,3 +320,36 @@ def test_net_warm_start_rejects_bad_boxes(hsf):
     ctx.attach_net(None)
     with pytest.raises(hsf.HsfError):
         ctx.invert(tol=1e-8, warm=hsf.WARM_NET)
+
+
+def test_batched_replicas_network_warm_start(hsf):
+    """Two replicas with equal boxes share one network call; the starting fields of
+    each equal those of a context holding that replica alone."""
+    wls = [W.melt16_a4b4().with_(seed=s) for s in (0, 1)]
+    V = wls[0].V
+    net = hsf.Net(4, 2, (8, 16), seed=5)
+    net.set_input_norm([0.5, 0.5, 0.0, 0.0], [8.0, 8.0, 1.0, 1.0])
+
+    def run(ws):
+        ctx = hsf.Context(ws)
+        ctx.attach_net(net)
+        phis = [W.initial_composition(w) for w in ws]
+        ctx.set_fields(np.zeros(2 * V * len(ws)))
+        for k in range(4):
+            p = np.concatenate([(ph * (1 + 0.01 * k * (ph - 0.5))).ravel() for ph in phis])
+            ctx.set_densities(p)
+            if k < 3:
+                st, _ = ctx.invert(tol=1e-10, max_iter=2000)
+                assert all(s["converged"] for s in st)
+            else:
+                ctx.invert(tol=1e-10, max_iter=0, warm=hsf.WARM_NET_EXTRAP, allow_noconv=True)
+        out = ctx.get_fields().reshape(len(ws), 2, V)
+        ctx.close()
+        return out
+
+    both = run(wls)
+    for r, w in enumerate(wls):
+        alone = run([w])[0]
+        err = np.max(np.abs(both[r] - alone)) / np.max(np.abs(alone))
+        say(f"[batched warm start] replica {r}: max rel difference {err:.2e}")
+        assert err < 1e-12

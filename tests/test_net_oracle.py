@@ -62,3 +62,35 @@ def test_bf16_rounding_is_small():
     b = NO.forward(p, x, 3, 2, widths, bf16=True)
     rel = float(torch.linalg.norm(a - b) / torch.linalg.norm(a))
     assert 0 < rel < 2e-2
+
+
+@pytest.mark.parametrize("widths", [(3,), (3, 4), (2, 3, 4), (2, 3, 2, 3)])
+def test_shift_equivariance_matches_depth(widths):
+    """A periodic U-Net of D levels commutes with translations by multiples of
+    2^(D-1) sites (pooling and upsampling are aligned to that grid) and, for D >= 2,
+    not with a one-site translation: a misaligned pooling or upsampling index, or a
+    dropped level, breaks one of the two."""
+    rng = np.random.default_rng(3)
+    D = len(widths)
+    n = NO.num_params(2, 2, widths)
+    p = 0.4 * rng.standard_normal(n)
+    x = torch.tensor(rng.standard_normal((1, 2, 8, 8, 8)))
+    y = NO.forward(p, x, 2, 2, widths)
+    q = 2 ** (D - 1)
+    for ax in (2, 3, 4):
+        ys = NO.forward(p, torch.roll(x, q, ax), 2, 2, widths)
+        assert float(torch.max(torch.abs(ys - torch.roll(y, q, ax)))) < 1e-12
+    if D >= 2:
+        y1 = NO.forward(p, torch.roll(x, 1, 4), 2, 2, widths)
+        assert float(torch.max(torch.abs(y1 - torch.roll(y, 1, 4)))) > 1e-3
+
+
+def test_depth_layer_counts():
+    for D, widths in enumerate([(4,), (4, 6), (4, 6, 8), (4, 6, 8, 10)], start=1):
+        shapes = NO.layer_shapes(3, 2, widths)
+        assert len(shapes) == 4 * D - 1
+        assert shapes[0] == (3, 4) and shapes[-1] == (4, 2)
+        # every layer reads its predecessor's width (a decoder skip adds an encoder
+        # activation of that same width)
+        assert all(shapes[i][0] == shapes[i - 1][1] for i in range(1, len(shapes)))
+    assert NO.layer_shapes(3, 2, (4, 6, 0, 0)) == NO.layer_shapes(3, 2, (4, 6))
