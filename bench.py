@@ -182,6 +182,9 @@ def main():
     ap.add_argument("--precond", action="store_true", help="diagonally preconditioned inversion")
     ap.add_argument("--tile", default=None, help="cx,cy,cz,k: use this propagator tiling instead of autotuning")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
+    ap.add_argument("--net-probe", default=None, metavar="WIDTHS",
+                    help="only time the warm-start network of these level widths (e.g. 16 or 8,16,24,32): "
+                         "forward passes and Adam steps on two 64^3 samples")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -195,6 +198,31 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "copies": 5}))
+        return
+
+    if args.net_probe:
+        import torch
+        from paper_1204_2088_amd import hsf
+        widths = tuple(int(v) for v in args.net_probe.split(","))
+        net = hsf.Net(4, 2, widths, seed=1)
+        B, L = 2, 64
+        g = torch.Generator(device="cuda")
+        g.manual_seed(0)
+        x = torch.rand(B * 4 * L ** 3, dtype=torch.float32, device="cuda", generator=g)
+        t = torch.rand(B * 2 * L ** 3, dtype=torch.float32, device="cuda", generator=g)
+        y = torch.empty_like(t)
+        out = {"net_probe": list(widths), "parameters": int(net.n_params), "batch": B, "L": L}
+        for name, fn, reps in (("forward", lambda: net.forward(x, B, L, out=y), 20),
+                               ("train_step", lambda: net.train_step(x, t, B, L, 1e-4), 10)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            out[f"{name}_ms"] = 1e3 * (time.perf_counter() - t0) / reps
+        print(json.dumps(out))
         return
 
     if args.gpus != 1:
