@@ -89,31 +89,49 @@ def cpu_baseline(wl, w, phi, seconds):
                       f"the GPU run's final fields of replica 0 ({el:.1f} s, single-threaded FP64 C oracle)"}
 
 
-def learned_arm(hsf, workload, precision, steps, warmup, tile, log):
+# Recipes of the learned warm start per benchmark workload: the trajectories it is
+# trained on (FP64, residual 1e-10, other seeds than the benchmark's 0), the steps
+# recorded, training length, and the states (steps after the quench) where the warm
+# starts are compared.
+LEARNED = {
+    "melt64_a8b8": dict(train=lambda W, seed: [w.with_(seed=seed) for w in make_workloads("melt64_a8b8", "fp64")],
+                        seeds=(1, 2), steps=1202, iters=1500,
+                        record=list(range(0, 121)) + [k for c in (300, 600, 900, 1200) for k in (c - 1, c, c + 1)],
+                        later=(300, 1000)),
+    # the 128^3 vesicle-forming solution, network trained on 64^3 runs of the same chemistry
+    "vesicle128_a3b9s": dict(train=lambda W, seed: [W.vesicle128_a3b9s(L=64).with_(seed=seed, precision="fp64")],
+                             seeds=(1, 2, 3), steps=602, iters=3000,
+                             record=list(range(0, 121)) + [k for c in (300, 600) for k in (c - 1, c, c + 1)],
+                             later=(200,)),
+}
+
+
+def learned_arm(hsf, workload, precision, steps, warmup, tile, log, precond=False):
     """The learned warm start on the benchmark's own workload: a network trained on
-    the GPU from FP64 trajectories of other seeds (1, 2), then every warm start run
-    on the benchmark's seed from the same states: `warmup` steps after the quench
-    (the window the main arm times), and later at steps 300 and 1000."""
+    the GPU from FP64 trajectories of other seeds, then every warm start run on the
+    benchmark's seed from the same states: `warmup` steps after the quench (the
+    window the main arm times) and later ones."""
     from paper_1204_2088_amd import warmnet
-    make = lambda seed: [w.with_(seed=seed) for w in make_workloads(workload, "fp64")]
-    record = list(range(0, 121)) + [k for c in (300, 600, 900, 1200) for k in (c - 1, c, c + 1)]
-    net, info = warmnet.train_warm_start(make, seeds=(1, 2), steps=1202, record=record, val_seed=5,
-                                         log=lambda m: None)
+    from paper_1204_2088_amd import workloads as W
+    rc = LEARNED[workload]
+    net, info = warmnet.train_warm_start(lambda seed: rc["train"](W, seed), seeds=rc["seeds"], steps=rc["steps"],
+                                         record=rc["record"], iters=rc["iters"], val_seed=5, log=None,
+                                         precond=precond)
     log(f"# warm-start network trained: {info}")
     wls = make_workloads(workload, precision)
     modes = [hsf.WARM_CURRENT, hsf.WARM_EXTRAP, hsf.WARM_NET_EXTRAP]
     regimes = {}
-    for start in (warmup, 300, 1000):
-        res = warmnet.compare_warm_starts(wls, net, modes, start, steps, tile=tile,
+    for start in (warmup,) + tuple(rc["later"]):
+        res = warmnet.compare_warm_starts(wls, net, modes, start, steps, tile=tile, precond=precond,
                                           log=lambda m: log(f"# [from step {start}]{m}"))
         gated = warmnet.compare_warm_starts(wls, net, [hsf.WARM_NET_EXTRAP], start, steps, tile=tile, gate=2,
-                                            log=lambda m: log(f"# [from step {start}, gate 2]{m}"))
+                                            precond=precond, log=lambda m: log(f"# [from step {start}, gate 2]{m}"))
         res["net_extrapolated_gate2"] = gated["net_extrapolated"]
         regimes[f"from_step_{start}"] = res
     net.close()
     head = regimes[f"from_step_{warmup}"]
     return {
-        "tol": wls[0].tol, "steps_per_mode": steps,
+        "tol": wls[0].tol, "steps_per_mode": steps, "solver": "preconditioned FR" if precond else "FR",
         "window": "each mode restarts from the saved state, runs 2 plain steps and 1 untimed step of its own, "
                   "then the timed steps",
         "network": info,
@@ -294,8 +312,9 @@ def main():
         c64.close()
 
     learned = None
-    if args.workload.startswith("melt64_a8b8") and not args.no_learned:
-        learned = learned_arm(hsf, args.workload, args.precision, args.steps, args.warmup, tuple(tile), log)
+    if args.workload in LEARNED and not args.no_learned:
+        learned = learned_arm(hsf, args.workload, args.precision, args.steps, args.warmup, tuple(tile), log,
+                              precond=args.precond)
 
     out = {
         "metric": METRIC,

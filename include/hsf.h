@@ -256,6 +256,11 @@ int hsf_net_set_params(hsf_net *net, const float *params, int where);
 /* Input normalisation applied inside every forward pass: x_c = (in_c - shift[c]) *
  * scale[c] (host arrays of in_ch values; default shift 0, scale 1). */
 int hsf_net_set_input_norm(hsf_net *net, const float *shift, const float *scale);
+/* Output scale applied at the end of every forward pass: out_c *= scale[c] (host array
+ * of out_ch values; default 1).  A network is trained on targets divided by the scale
+ * with the scale at 1 (hsf_net_loss_grad and hsf_net_train_step refuse, HSF_EINVAL,
+ * while a scale other than 1 is set) and deployed with it. */
+int hsf_net_set_output_scale(hsf_net *net, const float *scale);
 int hsf_net_get_params(hsf_net *net, float *params, int where);
 /* out = net(in) for `batch` samples */
 int hsf_net_forward(hsf_net *net, const float *in, float *out, int batch, int L, int where);

@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_target_stats(const int *__restrict__
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         const double t = block_sum(v[q]);
-        if (threadIdx.x == 0) part[(long long)blockIdx.x * kNQ + q] = t;
+        if (threadIdx.x == 0) part[(long long)plan_block() * kNQ + q] = t;
     }
 }
 
@@ -400,9 +400,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const int *__restrict__ bl
         }
     }
     double t = block_sum(dg);
-    if (threadIdx.x == 0) part[(long long)blockIdx.x * kNQ + 0] = t;
+    if (threadIdx.x == 0) part[(long long)plan_block() * kNQ + 0] = t;
     t = block_sum(dhd);
-    if (threadIdx.x == 0) part[(long long)blockIdx.x * kNQ + 1] = t;
+    if (threadIdx.x == 0) part[(long long)plan_block() * kNQ + 1] = t;
 }
 
 void launch_cg_update(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int init,
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_solvent(const int *__restrict__ blk_
     if (pass == 0) {
         const double v = i < V ? exp(-w[fo + 2 * V + i]) : 0.0;
         const double t = block_sum(v);
-        if (threadIdx.x == 0) part[(long long)blockIdx.x * kNQ] = t;
+        if (threadIdx.x == 0) part[(long long)plan_block() * kNQ] = t;
     } else if (i < V) {
         const RepState &S = st[sr.r];
         out[fo + 2 * V + i] = S.phibar_s * exp(-w[fo + 2 * V + i]) / S.sol_mean;

@@ -8,6 +8,16 @@ namespace hsf {
 // Periodic wrap of an index that is at most one step outside [0, L).
 __device__ __forceinline__ int wrap1(int i, int L) { return i < 0 ? i + L : (i >= L ? i - L : i); }
 
+// Work item (tile or site block) of this block.  Blocks are dealt to the chip's eight
+// XCDs round robin (block b runs on XCD b mod 8), each with its own L2; this bijection
+// gives every XCD a contiguous range of work items, so neighbouring tiles, whose halos
+// overlap, share an L2.  Partial results are indexed by the work item.
+__device__ __forceinline__ int plan_block()
+{
+    const int n = (int)gridDim.x, q = n >> 3, rr = n & 7, xcd = (int)blockIdx.x & 7, slot = (int)blockIdx.x >> 3;
+    return xcd * q + (xcd < rr ? xcd : rr) + slot;
+}
+
 // Replica and local site of the calling thread in a site plan.
 struct SiteRef {
     int r;
@@ -17,8 +27,9 @@ struct SiteRef {
 __device__ __forceinline__ SiteRef site_ref(const int *blk_rep, const int *blk_first)
 {
     SiteRef s;
-    s.r = blk_rep[blockIdx.x];
-    s.i = (long long)(blockIdx.x - blk_first[s.r]) * kBlock + threadIdx.x;
+    const int pb = plan_block();
+    s.r = blk_rep[pb];
+    s.i = (long long)(pb - blk_first[s.r]) * kBlock + threadIdx.x;
     return s;
 }
 

@@ -59,7 +59,8 @@ struct hsf_net {
     Layer layer[kLayers];
     long long n_params = 0;
     float *params = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
-    float *norm = nullptr;           // device: input shift[in_ch], scale[in_ch]
+    float *norm = nullptr;           // device: input shift[in_ch], scale[in_ch], output zero[out_ch], scale[out_ch]
+    int out_scaled = 0;              // an output scale other than 1 is set
     long long adam_t = 0;
     hipStream_t stream = nullptr;
     std::string err;
@@ -219,6 +220,11 @@ void forward(hsf_net *n)
 {
     net_affine(n->stream, n->x0.p, n->in_ch, vol(n->cur_L, 0), numel(n, n->x0), n->norm, n->norm + n->in_ch);
     for (int l = 0; l < n->n_layers; ++l) conv(n, l);
+    if (n->out_scaled) {
+        const Tensor &y = output(n);
+        const float *o = n->norm + 2 * n->in_ch;
+        net_affine(n->stream, y.p, n->out_ch, vol(n->cur_L, 0), numel(n, y), o, o + n->out_ch);
+    }
 }
 
 // Backward pass from dout (gradient of the loss with respect to the output).  Layers
@@ -294,6 +300,7 @@ int loss_and_grad(hsf_net *n, double *loss)
         int rc = stage_weights(n);
         if (rc) return rc;
     }
+    if (n->out_scaled) return nfail(n, HSF_EINVAL, "training needs the output scale reset to 1");
     n->training = 1;
     forward(n);
     n->training = 0;
@@ -386,7 +393,7 @@ int hsf_net_create(int in_ch, int out_ch, const int widths[4], unsigned long lon
     if (rc == HSF_OK) rc = nalloc(n, n->allocs, (void **)&n->grad, sizeof(float) * off);
     if (rc == HSF_OK) rc = nalloc(n, n->allocs, (void **)&n->m, sizeof(float) * off);
     if (rc == HSF_OK) rc = nalloc(n, n->allocs, (void **)&n->v, sizeof(float) * off);
-    if (rc == HSF_OK) rc = nalloc(n, n->allocs, (void **)&n->norm, sizeof(float) * 2 * in_ch);
+    if (rc == HSF_OK) rc = nalloc(n, n->allocs, (void **)&n->norm, sizeof(float) * 2 * (in_ch + out_ch));
     for (int l = 0; l < n->n_layers && rc == HSF_OK; ++l) {
         Layer &Ly = n->layer[l];
         rc = nalloc(n, n->allocs, (void **)&Ly.Wm, sizeof(__bf16) * (size_t)Ly.cop * Ly.kp);
@@ -405,10 +412,11 @@ int hsf_net_create(int in_ch, int out_ch, const int widths[4], unsigned long lon
         for (long long i = 0; i < (long long)Ly.co * Ly.ci * 27; ++i)
             p[Ly.w_off + i] = (float)(a * (2.0 * unit_hash(seed, Ly.w_off + i) - 1.0));
     }
-    std::vector<float> nrm(2 * in_ch, 0.0f);
-    for (int c = 0; c < in_ch; ++c) nrm[in_ch + c] = 1.0f;   // identity normalisation
+    std::vector<float> nrm(2 * (in_ch + out_ch), 0.0f);   // identity normalisation and scale
+    for (int c = 0; c < in_ch; ++c) nrm[in_ch + c] = 1.0f;
+    for (int c = 0; c < out_ch; ++c) nrm[2 * in_ch + out_ch + c] = 1.0f;
     hipError_t e = hipMemcpy(n->params, p.data(), sizeof(float) * off, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(n->norm, nrm.data(), sizeof(float) * 2 * in_ch, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(n->norm, nrm.data(), sizeof(float) * nrm.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(n->m, 0, sizeof(float) * off);
     if (e == hipSuccess) e = hipMemset(n->v, 0, sizeof(float) * off);
     if (e == hipSuccess) e = hipMemset(n->grad, 0, sizeof(float) * off);
@@ -462,6 +470,22 @@ int hsf_net_set_input_norm(hsf_net *n, const float *shift, const float *scale)
     }
     NCHK(n, hipMemcpyAsync(n->norm, nrm.data(), sizeof(float) * nrm.size(), hipMemcpyHostToDevice, n->stream));
     NCHK(n, hipStreamSynchronize(n->stream));
+    return HSF_OK;
+}
+
+int hsf_net_set_output_scale(hsf_net *n, const float *scale)
+{
+    if (!n || !scale) return HSF_EINVAL;
+    std::vector<float> v(2 * n->out_ch, 0.0f);
+    int scaled = 0;
+    for (int c = 0; c < n->out_ch; ++c) {
+        v[n->out_ch + c] = scale[c];
+        scaled |= scale[c] != 1.0f;
+    }
+    NCHK(n, hipMemcpyAsync(n->norm + 2 * n->in_ch, v.data(), sizeof(float) * v.size(), hipMemcpyHostToDevice,
+                           n->stream));
+    NCHK(n, hipStreamSynchronize(n->stream));
+    n->out_scaled = scaled;
     return HSF_OK;
 }
 

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <math.h>
 
+#include "device_common.h"
 #include "net_internal.h"
 
 namespace hsf {
@@ -55,7 +56,6 @@ __device__ __forceinline__ int wrap_tile(int v, int L, bool small)
     return v < 0 ? v + L : (v >= L ? v - L : v);
 }
 
-size_t conv_fwd_lds(int cip, int cop) { return (size_t)(HS * cip + cop * kSlabRow) * sizeof(__bf16); }
 
 // Value of input channel c of sample b at site (gx, gy, gz) of the convolution's
 // L^3 box, read through the input's composition (ConvIn): the tensor itself, the sum
@@ -85,13 +85,11 @@ __device__ __forceinline__ float conv_input(const ConvIn &in, int b, int c, int 
     return in.mode == CONV_IN_ADD ? in.x1[e] + in.x2[e] : in.x1[e];
 }
 
-// Stage the input tile of sample b with its one-site halo into LDS as BF16, either
-// site-major xs[h][cip] (forward) or channel-major xs[c][HS] (weight gradient);
-// channels ci..cip-1 are zero.  Loads are issued eight elements per thread before any
-// is used, so their latencies overlap.
-template <bool SITE_MAJOR>
-__device__ __forceinline__ void stage_halo(const ConvIn &in, int b, int ci, int cip, int L, int x0, int y0, int z0,
-                                           __bf16 *xs)
+// Stage the input tile of sample b with its one-site halo into LDS as BF16,
+// channel-major xs[c][HS] (weight gradient); channels ci..cip-1 are zero.  Loads are
+// issued eight elements per thread before any is used, so their latencies overlap.
+__device__ __forceinline__ void stage_halo_cm(const ConvIn &in, int b, int ci, int cip, int L, int x0, int y0,
+                                              int z0, __bf16 *xs)
 {
     const bool small = L < TX;
     const int total = HS * cip;
@@ -112,50 +110,172 @@ __device__ __forceinline__ void stage_halo(const ConvIn &in, int b, int ci, int 
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = e0 + u * 256;
+            if (e < total) xs[(e / HS) * HS + e % HS] = (__bf16)v[u];
+        }
+    }
+}
+
+// A BX x BY x BZ tile site-major, xs[h][cip] with its one-site halo (forward): a work
+// item is one halo site and eight consecutive channels, written to LDS as one 16-byte
+// vector (consecutive items fill consecutive vectors); two items (16 loads) per thread
+// are in flight at once.
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ void stage_halo_sm(const ConvIn &in, int b, int ci, int cip, int L, int x0, int y0,
+                                              int z0, __bf16 *xs)
+{
+    constexpr int GX = BX + 2, GY = BY + 2, GS = GX * GY * (BZ + 2);
+    constexpr int BMAX = BX > BY ? (BX > BZ ? BX : BZ) : (BY > BZ ? BY : BZ);
+    const bool small = L < BMAX;
+    const int oct = cip / 8, total = GS * oct;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * 2) {
+        float v[2][8];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = e0 + u * 256;
+            const int c8 = e % oct, h = e / oct;
+            const bool ok = e < total;
+            const int hx = h % GX, hy = (h / GX) % GY, hz = h / (GX * GY);
+            const int gx = wrap_tile(x0 + hx - 1, L, small), gy = wrap_tile(y0 + hy - 1, L, small),
+                      gz = wrap_tile(z0 + hz - 1, L, small);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int c = c8 * 8 + j;
+                v[u][j] = (ok && c < ci) ? conv_input(in, b, c, ci, gx, gy, gz, L) : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = e0 + u * 256;
             if (e < total) {
-                const int h = e % HS, c = e / HS;
-                xs[SITE_MAJOR ? h * cip + c : c * HS + h] = (__bf16)v[u];
+                bf16x8 pk;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) pk[j] = (__bf16)v[u][j];
+                *reinterpret_cast<bf16x8 *>(xs + (e / oct) * cip + (e % oct) * 8) = pk;
             }
         }
     }
 }
 
-__global__ __launch_bounds__(256) void k_conv_fwd(ConvIn in, int ci, int cip,
-                                                   const __bf16 *__restrict__ Wm, int kp, int co, int cop,
-                                                   const float *__restrict__ bias, float *__restrict__ Y,
-                                                   float *__restrict__ A, int L, int tiles_x, int tiles_y,
-                                                   int tiles_per_sample)
+// Row-vector staging of the same tile: aligned float4 loads of 4 consecutive x sites
+// per channel, for plain and summed inputs on boxes at least a tile wide with L a
+// multiple of 4 (three times fewer load instructions than one site per load).
+typedef float floatv4 __attribute__((ext_vector_type(4)));
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ void stage_halo_rows(const ConvIn &in, int b, int ci, int cip, int L, int x0, int y0,
+                                                int z0, __bf16 *xs)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __bf16 *xs = reinterpret_cast<__bf16 *>(smem);   // [HS][cip]
-    __bf16 *ws = xs + HS * cip;                       // [cop][kSlabRow]
-    const int b = blockIdx.x / tiles_per_sample;
-    int t = blockIdx.x % tiles_per_sample;
-    const int x0 = (t % tiles_x) * TX;
-    t /= tiles_x;
-    const int y0 = (t % tiles_y) * TY;
-    const int z0 = (t / tiles_y) * TZ;
+    constexpr int GX = BX + 2, GY = BY + 2, GZ = BZ + 2;
+    constexpr int NG = (BX + 8) / 4;   // float4 groups covering x in [x0 - 4, x0 + BX + 4)
+    const int oct = cip / 8, total = GY * GZ * NG * oct;
     const long long V = (long long)L * L * L;
-    stage_halo<true>(in, b, ci, cip, L, x0, y0, z0, xs);
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * 2) {
+        floatv4 v[2][8];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = e0 + u * 256;
+            const bool ok = e < total;
+            const int c8 = e % oct, r = e / oct;
+            const int g = r % NG, row = r / NG;
+            const int hy = row % GY, hz = row / GY;
+            int xb = x0 - 4 + 4 * g;   // a multiple of 4; wraps as a whole group
+            xb = xb < 0 ? xb + L : (xb >= L ? xb - L : xb);
+            const int gy = wrap_tile(y0 + hy - 1, L, false), gz = wrap_tile(z0 + hz - 1, L, false);
+            const long long site = xb + (long long)L * (gy + (long long)L * gz);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int c = c8 * 8 + j;
+                v[u][j] = floatv4{0.f, 0.f, 0.f, 0.f};
+                if (ok && c < ci) {
+                    const long long a = ((long long)b * ci + c) * V + site;
+                    v[u][j] = *reinterpret_cast<const floatv4 *>(in.x1 + a);
+                    if (in.mode == CONV_IN_ADD) v[u][j] += *reinterpret_cast<const floatv4 *>(in.x2 + a);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = e0 + u * 256;
+            if (e < total) {
+                const int c8 = e % oct, r = e / oct;
+                const int g = r % NG, row = r / NG;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int hx = 4 * g + q - 3;   // halo x position of this site
+                    if (hx >= 0 && hx < GX) {
+                        bf16x8 pk;
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) pk[j] = (__bf16)v[u][j][q];
+                        *reinterpret_cast<bf16x8 *>(xs + (row * GX + hx) * cip + c8 * 8) = pk;
+                    }
+                }
+            }
+        }
+    }
+}
+
+constexpr int kMaxKGroups = 27 * 32 / 8 + 4;   // K rows / 8 for cip <= 32, rounded up to 32 rows
+
+template <int BX, int BY, int BZ>
+constexpr size_t conv_fwd_lds_t(int cip, int cop)
+{
+    return (size_t)((BX + 2) * (BY + 2) * (BZ + 2) * cip + cop * kSlabRow) * sizeof(__bf16) +
+           kMaxKGroups * sizeof(int);
+}
+
+// Block: a BX x BY x BZ tile of one sample; its 16-site MFMA column tiles are dealt to
+// the four waves (NTW each), each with up to two 16-channel output tiles (cop <= 32).
+template <int BX, int BY, int BZ>
+__global__ __launch_bounds__(256) void k_conv_fwd(ConvIn in, int ci, int cip, const __bf16 *__restrict__ Wm, int kp,
+                                                   int co, int cop, const float *__restrict__ bias,
+                                                   float *__restrict__ Y, float *__restrict__ A, int L, int tiles_x,
+                                                   int tiles_y, int tiles_per_sample)
+{
+    constexpr int BS = BX * BY * BZ, GX = BX + 2, GY = BY + 2, GS = GX * GY * (BZ + 2);
+    constexpr int NTW = BS / 64;   // column tiles per wave
+    static_assert(BS % 64 == 0 && BX % 8 == 0, "tile shape");
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16 *xs = reinterpret_cast<__bf16 *>(smem);   // [GS][cip]
+    __bf16 *ws = xs + GS * cip;                       // [cop][kSlabRow]
+    int *koff = reinterpret_cast<int *>(ws + cop * kSlabRow);   // [kp / 8]
+    const int bid = plan_block();   // neighbouring tiles on one XCD
+    const int b = bid / tiles_per_sample;
+    int t = bid % tiles_per_sample;
+    const int x0 = (t % tiles_x) * BX;
+    t /= tiles_x;
+    const int y0 = (t % tiles_y) * BY;
+    const int z0 = (t / tiles_y) * BZ;
+    const long long V = (long long)L * L * L;
+    // LDS element offset, relative to a site's halo position times cip, of each group of
+    // eight K rows (tap k, channels c0..c0+7); padding rows point at the centre tap
+    // (zero weights there)
+    for (int g = threadIdx.x; g < kp / 8; g += 256) {
+        int k = (8 * g) / cip;
+        const int c0 = 8 * g - k * cip;
+        if (k > 26) k = 13;
+        koff[g] = (((k / 9) - 1) * GX * GY + (((k / 3) % 3) - 1) * GX + ((k % 3) - 1)) * cip + c0;
+    }
+    if ((in.mode == CONV_IN_PLAIN || in.mode == CONV_IN_ADD) && L % 4 == 0 && L >= BX && L >= BY && L >= BZ)
+        stage_halo_rows<BX, BY, BZ>(in, b, ci, cip, L, x0, y0, z0, xs);
+    else
+        stage_halo_sm<BX, BY, BZ>(in, b, ci, cip, L, x0, y0, z0, xs);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane >> 4, col = lane & 15;
     const int nmt = cop / 16;
-    floatx4 acc[2][4];
+    floatx4 acc[NTW][2];
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < NTW; ++q) acc[q][0] = acc[q][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // this lane's sites (column of the B operand): LDS element offsets of their halo
+    // positions
+    int hbase[NTW];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) acc[q][m] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // this lane's two sites (column of the B operand), as halo-tile positions
-    int hbase[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int n = (wave * 2 + q) * 16 + col;
-        const int tx = n % TX, ty = (n / TX) % TY, tz = n / (TX * TY);
-        hbase[q] = (tz + 1) * HX * HY + (ty + 1) * HX + (tx + 1);
+    for (int q = 0; q < NTW; ++q) {
+        const int n = (wave * NTW + q) * 16 + col;
+        const int tx = n % BX, ty = (n / BX) % BY, tz = n / (BX * BY);
+        hbase[q] = ((tz + 1) * GX * GY + (ty + 1) * GX + (tx + 1)) * cip;
     }
     for (int k0 = 0; k0 < kp; k0 += kSlab * 32) {
         const int klen = min(kSlab * 32, kp - k0);
-        __syncthreads();   // previous slab consumed
+        __syncthreads();   // previous slab consumed (and, the first time, the halo staged)
         const int vec_per_row = klen / 8, nvec = cop * vec_per_row;
         for (int e0 = threadIdx.x; e0 < nvec; e0 += 256 * 4) {   // four 16-byte loads in flight
             bf16x8 wv[4];
@@ -177,22 +297,18 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvIn in, int ci, int cip,
             }
         }
         __syncthreads();
+        const __bf16 *wa = ws + col * kSlabRow + 8 * grp;
+        const int *kg = koff + k0 / 8 + grp;
         for (int kc = 0; kc < klen; kc += 32) {
-            const int kk = k0 + kc + 8 * grp;
-            int k = kk / cip;
-            const int c0 = kk - k * cip;
-            if (k > 26) k = 13;   // padding rows of K: zero weights, any finite input
-            const int off = ((k / 9) - 1) * HX * HY + (((k / 3) % 3) - 1) * HX + ((k % 3) - 1);
-            bf16x8 bv[2];
+            const int off = kg[kc / 8];
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(wa + kc);
+            bf16x8 a1 = a0;
+            if (nmt > 1) a1 = *reinterpret_cast<const bf16x8 *>(wa + 16 * kSlabRow + kc);
 #pragma unroll
-            for (int q = 0; q < 2; ++q) bv[q] = *reinterpret_cast<const bf16x8 *>(xs + (hbase[q] + off) * cip + c0);
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                if (m >= nmt) break;
-                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(ws + (m * 16 + col) * kSlabRow + kc + 8 * grp);
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-                    acc[q][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[q], acc[q][m], 0, 0, 0);
+            for (int q = 0; q < NTW; ++q) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(xs + hbase[q] + off);
+                acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv, acc[q][0], 0, 0, 0);
+                if (nmt > 1) acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv, acc[q][1], 0, 0, 0);
             }
         }
     }
@@ -200,14 +316,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvIn in, int ci, int cip,
     float *Yb = Y ? Y + (long long)b * co * V : nullptr;
     float *Ab = A ? A + (long long)b * co * V : nullptr;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int n = (wave * 2 + q) * 16 + col;
-        const int tx = n % TX, ty = (n / TX) % TY, tz = n / (TX * TY);
+    for (int q = 0; q < NTW; ++q) {
+        const int n = (wave * NTW + q) * 16 + col;
+        const int tx = n % BX, ty = (n / BX) % BY, tz = n / (BX * BY);
         const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
         if (gx >= L || gy >= L || gz >= L) continue;
         const long long site = gx + (long long)L * (gy + (long long)L * gz);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < 2; ++m) {
             if (m >= nmt) break;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -254,7 +370,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn in, int ci, int cip,
         const int y0 = (t % tiles_y) * TY;
         const int z0 = (t / tiles_y) * TZ;
         __syncthreads();
-        stage_halo<false>(in, b, ci, cip, L, x0, y0, z0, xs);
+        stage_halo_cm(in, b, ci, cip, L, x0, y0, z0, xs);
         for (int e0 = threadIdx.x; e0 < TS * cop; e0 += 256 * 8) {
             float v[8];
 #pragma unroll
@@ -592,13 +708,44 @@ __global__ void k_affine(float *__restrict__ x, int C, long long V, long long n,
 // ---------------------------------------------------------------- launchers
 static inline unsigned nb(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Largest dynamic LDS a block may use on the current device (queried once).
+static size_t lds_limit()
+{
+    static size_t lim = 0;
+    if (!lim) {
+        int dev = 0, v = 0;
+        lim = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            lim = std::min<size_t>((size_t)v, 65536);
+    }
+    return lim;
+}
+
+template <int BX, int BY, int BZ>
+static void conv_fwd_launch(hipStream_t s, ConvIn in, int B, int ci, int cip, const __bf16 *Wm, int kp, int co,
+                            int cop, const float *bias, float *Y, float *A, int L)
+{
+    const int tx = (L + BX - 1) / BX, ty = (L + BY - 1) / BY, tz = (L + BZ - 1) / BZ;
+    const int tps = tx * ty * tz;
+    const size_t lds = conv_fwd_lds_t<BX, BY, BZ>(cip, cop);
+    hipLaunchKernelGGL((k_conv_fwd<BX, BY, BZ>), dim3(B * tps), dim3(256), lds, s, in, ci, cip, Wm, kp, co, cop, bias,
+                       Y, A, L, tx, ty, tps);
+}
+
+// Tile per layer: the largest of 16x8x4, 8x8x4, 8x4x4 that the box fills and whose LDS
+// (halo tile plus one weight slab) fits.  Larger tiles re-read fewer halo sites and
+// stage the weights for more sites.
 void net_conv_fwd(hipStream_t s, ConvIn in, int B, int ci, int cip, const __bf16 *Wm, int kp, int co, int cop,
                   const float *bias, float *Y, float *A, int L)
 {
-    const int tx = (L + TX - 1) / TX, ty = (L + TY - 1) / TY, tz = (L + TZ - 1) / TZ;
-    const int tps = tx * ty * tz;
-    hipLaunchKernelGGL(k_conv_fwd, dim3(B * tps), dim3(256), conv_fwd_lds(cip, cop), s, in, ci, cip, Wm, kp, co, cop,
-                       bias, Y, A, L, tx, ty, tps);
+    const size_t lim = lds_limit();
+    if (L >= 16 && conv_fwd_lds_t<16, 8, 4>(cip, cop) <= lim)
+        conv_fwd_launch<16, 8, 4>(s, in, B, ci, cip, Wm, kp, co, cop, bias, Y, A, L);
+    else if (L >= 8 && conv_fwd_lds_t<8, 8, 4>(cip, cop) <= lim)
+        conv_fwd_launch<8, 8, 4>(s, in, B, ci, cip, Wm, kp, co, cop, bias, Y, A, L);
+    else
+        conv_fwd_launch<8, 4, 4>(s, in, B, ci, cip, Wm, kp, co, cop, bias, Y, A, L);
 }
 
 // Site slices of the weight gradient: enough blocks (groups x slices, about 1024) to

@@ -87,10 +87,10 @@ template <int CX, int CY, int CZ>
 __device__ __forceinline__ bool tile_of(const int *blk_rep, const int *blk_first, const Rep *rep, int &r, int &x0,
                                         int &y0, int &z0)
 {
-    r = blk_rep[blockIdx.x];
+    r = blk_rep[plan_block()];
     const Rep &R = rep[r];
     const int ntx = (R.Lx + CX - 1) / CX, nty = (R.Ly + CY - 1) / CY;
-    int lb = blockIdx.x - blk_first[r];
+    int lb = plan_block() - blk_first[r];
     x0 = (lb % ntx) * CX;
     lb /= ntx;
     y0 = (lb % nty) * CY;
@@ -174,16 +174,16 @@ __global__ __launch_bounds__(kBlock) void k_fwd_block(const int *__restrict__ bl
         });
         if (sums || s == ch.N) {
             const double t = block_sum(gsum);   // contains __syncthreads: the level is complete
-            if (threadIdx.x == 0) partG[(long long)(s - 1) * nblocks + blockIdx.x] = t;
+            if (threadIdx.x == 0) partG[(long long)(s - 1) * nblocks + plan_block()] = t;
         } else {
             __syncthreads();
         }
     }
     if (s0 == 0 && sums) {
         double t = block_sum(esum[0]);
-        if (threadIdx.x == 0) partG[(long long)ch.N * nblocks + blockIdx.x] = t;
+        if (threadIdx.x == 0) partG[(long long)ch.N * nblocks + plan_block()] = t;
         t = block_sum(esum[1]);
-        if (threadIdx.x == 0) partG[(long long)(ch.N + 1) * nblocks + blockIdx.x] = t;
+        if (threadIdx.x == 0) partG[(long long)(ch.N + 1) * nblocks + plan_block()] = t;
     }
 }
 
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_block(const int *__restrict__ bl
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const double t = block_sum(sums[q]);
-            if (threadIdx.x == 0) part[(long long)blockIdx.x * kNQ + q] = t;
+            if (threadIdx.x == 0) part[(long long)plan_block() * kNQ + q] = t;
         }
     }
 }
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_field_exp(const int *__restrict__ bl
     SiteRef sr;
     if (SINGLE) {
         sr.r = 0;
-        sr.i = (long long)blockIdx.x * kBlock + threadIdx.x;
+        sr.i = (long long)plan_block() * kBlock + threadIdx.x;
     } else {
         sr = site_ref(blk_rep, blk_first);
         if (!st[sr.r].active) return;
@@ -344,7 +344,7 @@ __device__ __forceinline__ bool direct_tile(const int *blk_rep, const int *blk_f
         r = 0;
         R = &rep0;
         const int ntx = (rep0.Lx + CX - 1) / CX, nty = (rep0.Ly + CY - 1) / CY;
-        int lb = blockIdx.x;
+        int lb = plan_block();
         x0 = (lb % ntx) * CX;
         lb /= ntx;
         y0 = (lb % nty) * CY;
@@ -392,13 +392,13 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ b
     }
     if (sums || s == ch.N) {
         const double t = block_sum(gsum);
-        if (threadIdx.x == 0) partG[(long long)(s - 1) * nblocks + blockIdx.x] = t;
+        if (threadIdx.x == 0) partG[(long long)(s - 1) * nblocks + plan_block()] = t;
     }
     if (s == 1 && sums) {
         double t = block_sum(esum[0]);
-        if (threadIdx.x == 0) partG[(long long)ch.N * nblocks + blockIdx.x] = t;
+        if (threadIdx.x == 0) partG[(long long)ch.N * nblocks + plan_block()] = t;
         t = block_sum(esum[1]);
-        if (threadIdx.x == 0) partG[(long long)(ch.N + 1) * nblocks + blockIdx.x] = t;
+        if (threadIdx.x == 0) partG[(long long)(ch.N + 1) * nblocks + plan_block()] = t;
     }
 }
 
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ b
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const double t = block_sum(sums[q]);
-            if (threadIdx.x == 0) part[(long long)blockIdx.x * kNQ + q] = t;
+            if (threadIdx.x == 0) part[(long long)plan_block() * kNQ + q] = t;
         }
     }
 }

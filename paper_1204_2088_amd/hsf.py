@@ -33,7 +33,7 @@ EXPORTED = [
     "hsf_set_hydro", "hsf_set_timing", "hsf_get_timing", "hsf_set_tile", "hsf_get_tile", "hsf_autotune",
     "hsf_set_solver", "hsf_get_work", "hsf_set_warm", "hsf_net_create", "hsf_net_destroy",
     "hsf_net_last_error", "hsf_net_set_stream", "hsf_net_num_params", "hsf_net_set_params",
-    "hsf_net_get_params", "hsf_net_set_input_norm", "hsf_net_forward", "hsf_net_loss_grad",
+    "hsf_net_get_params", "hsf_net_set_input_norm", "hsf_net_set_output_scale", "hsf_net_forward", "hsf_net_loss_grad",
     "hsf_net_train_step", "hsf_attach_net", "hsf_set_net_gate",
 ]
 WARM_EXTRAP, WARM_NET, WARM_NET_DELTA, WARM_NET_EXTRAP = 2, 3, 4, 5
@@ -120,6 +120,7 @@ def load():
         "hsf_net_set_params": ([C, P, I], I),
         "hsf_net_get_params": ([C, P, I], I),
         "hsf_net_set_input_norm": ([C, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)], I),
+        "hsf_net_set_output_scale": ([C, ctypes.POINTER(ctypes.c_float)], I),
         "hsf_net_forward": ([C, P, P, I, I, I], I),
         "hsf_net_loss_grad": ([C, P, P, I, I, ctypes.POINTER(ctypes.c_double), P, I], I),
         "hsf_net_train_step": ([C, P, P, I, I, ctypes.c_float, ctypes.POINTER(ctypes.c_double), I], I),
@@ -420,6 +421,10 @@ class Net:
         sh = (ctypes.c_float * self.in_ch)(*[float(v) for v in shift])
         sc = (ctypes.c_float * self.in_ch)(*[float(v) for v in scale])
         self._check(self._lib.hsf_net_set_input_norm(self._h, sh, sc))
+
+    def set_output_scale(self, scale):
+        sc = (ctypes.c_float * self.out_ch)(*[float(v) for v in scale])
+        self._check(self._lib.hsf_net_set_output_scale(self._h, sc))
 
     def get_params(self):
         out = np.empty(self.n_params, dtype=np.float32)

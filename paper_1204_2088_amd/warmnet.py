@@ -47,13 +47,14 @@ def initial_state(ctx, wls):
     return phi, w
 
 
-def record_trajectory(wls, steps, record, tol=1e-10, precision="fp64", log=None):
+def record_trajectory(wls, steps, record, tol=1e-10, precision="fp64", log=None, precond=False):
     """Run the coupled dynamics of the replicas `wls` for `steps` steps (extrapolated
     warm start) and keep, for every step index in `record`, the target densities and
     converged fields of that step's inversion as device tensors [rep][nsp][V] (FP64).
     Returns {k: (phi, w)}."""
     torch = _torch()
     ctx = hsf.Context(wls, precision=precision)
+    ctx.set_solver(precond=precond)
     phi0, w0 = initial_state(ctx, wls)
     ctx.set_densities(phi0)
     ctx.set_fields(w0)
@@ -155,7 +156,7 @@ def evaluate_loss(net, x, y, L, batch=2):
 
 
 def train_warm_start(make_workloads, seeds, steps, record, widths=DEFAULT_WIDTHS, iters=1500, batch=2, lr=1e-3,
-                     lr_end=1e-4, val_seed=None, net_seed=1, log=None):
+                     lr_end=1e-4, val_seed=None, net_seed=1, log=None, precond=False, tol=1e-10):
     """Record trajectories of make_workloads(seed) for every training seed (FP64
     propagators, residual 1e-10), build the first- and second-difference samples,
     and train a network with 2 nsp inputs on them.  Returns (net, info)."""
@@ -163,7 +164,8 @@ def train_warm_start(make_workloads, seeds, steps, record, widths=DEFAULT_WIDTHS
     t0 = time.perf_counter()
     xs, ys = [], []
     for seed in seeds:
-        traj = record_trajectory(make_workloads(seed), steps, record, tol=1e-10, precision="fp64", log=log)
+        traj = record_trajectory(make_workloads(seed), steps, record, tol=tol, precision="fp64", log=log,
+                                 precond=precond)
         x, y = make_samples(traj)
         del traj
         xs.append(x)
@@ -173,32 +175,44 @@ def train_warm_start(make_workloads, seeds, steps, record, widths=DEFAULT_WIDTHS
     t_data = time.perf_counter() - t0
     xv = yv = None
     if val_seed is not None:   # early steps of a held-out trajectory
-        tv = record_trajectory(make_workloads(val_seed)[:1], 22, list(range(1, 22)), tol=1e-10, precision="fp64")
+        tv = record_trajectory(make_workloads(val_seed)[:1], 22, list(range(1, 22)), tol=tol, precision="fp64",
+                               precond=precond)
         xv, yv = make_samples(tv)
     L = round(x.shape[2] ** (1.0 / 3.0))
     nsp = x.shape[1] // 2
     net = hsf.Net(2 * nsp, 2, widths, seed=net_seed)
     shift, scale = input_norm(x)
     net.set_input_norm(shift, scale)
+    # targets per output channel to unit rms (the fields of a dilute species respond far
+    # more strongly than the others); the scale goes back on as the network's output scale
+    out_rms = [max(float(y[:, c].pow(2).mean().sqrt()), 1e-30) for c in range(y.shape[1])]
+    inv = torch.tensor([1.0 / v for v in out_rms], dtype=torch.float32, device=y.device).view(1, -1, 1)
+    y = y * inv
+    if yv is not None:
+        yv = yv * inv
     t1 = time.perf_counter()
     losses = train(net, x, y, L, iters=iters, batch=batch, lr=lr, lr_end=lr_end, log=log, x_val=xv, y_val=yv)
+    val = evaluate_loss(net, xv, yv, L) if xv is not None else None
+    net.set_output_scale(out_rms)
     torch.cuda.synchronize()
     info = {"widths": list(widths), "parameters": int(net.n_params), "samples": int(x.shape[0]),
             "training_seeds": list(seeds), "iterations": iters, "batch": batch,
             "loss_first": float(losses[0]), "loss_last": float(np.mean(losses[-50:])),
-            "validation_loss": evaluate_loss(net, xv, yv, L) if xv is not None else None,
+            "validation_loss": val, "loss_units": "mean square error of targets scaled to unit rms per channel",
+            "target_rms": out_rms,
             "data_seconds": t_data, "train_seconds": time.perf_counter() - t1}
     return net, info
 
 
 def compare_warm_starts(wls, net, modes, start_steps, measure_steps, tol=1e-6, precision="fp32", tile=None,
-                        log=None, gate=0):
+                        log=None, gate=0, precond=False, max_iter=1000):
     """Step time and evaluations per step of each warm start on the trajectory of
     `wls`: the dynamics runs `start_steps` plain steps, the state is saved, and each
     mode then runs 2 plain steps (to build the history) and `measure_steps` timed
     steps from that same state.  Returns {mode: {...}}."""
     torch = _torch()
     ctx = hsf.Context(wls, precision=precision)
+    ctx.set_solver(precond=precond)
     phi0, w0 = initial_state(ctx, wls)
     ctx.set_densities(phi0)
     ctx.set_fields(w0)
@@ -209,30 +223,33 @@ def compare_warm_starts(wls, net, modes, start_steps, measure_steps, tol=1e-6, p
         ctx.set_net_gate(gate)
     ctx.set_warm(hsf.WARM_CURRENT)
     if start_steps:
-        ctx.step(start_steps, tol=tol, max_iter=1000)
+        ctx.step(start_steps, tol=tol, max_iter=max_iter)
     snap = (ctx.get_densities(), ctx.get_fields(), ctx.get_lb())
     out = {}
-    names = {hsf.WARM_CURRENT: "current", hsf.WARM_EXTRAP: "extrapolated", hsf.WARM_NET_DELTA: "net_delta",
-             hsf.WARM_NET_EXTRAP: "net_extrapolated"}
+    names = {hsf.WARM_CURRENT: "current", hsf.WARM_LOCAL: "local", hsf.WARM_EXTRAP: "extrapolated",
+             hsf.WARM_NET: "net", hsf.WARM_NET_DELTA: "net_delta", hsf.WARM_NET_EXTRAP: "net_extrapolated"}
     for mode in modes:
         ctx.set_densities(snap[0])
         ctx.set_fields(snap[1])
         ctx.set_lb(snap[2])
         ctx.set_warm(hsf.WARM_CURRENT)
-        ctx.step(2, tol=tol, max_iter=1000)
+        ctx.step(2, tol=tol, max_iter=max_iter)
         ctx.set_warm(mode)
-        ctx.step(1, tol=tol, max_iter=1000)   # warm-up of this mode's launch sequences
-        evs, its = [], []
+        ctx.step(1, tol=tol, max_iter=max_iter)   # warm-up of this mode's launch sequences
+        evs, its, ts = [], [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(measure_steps):
-            st, ev = ctx.step(1, tol=tol, max_iter=1000)
+            ta = time.perf_counter()
+            st, ev = ctx.step(1, tol=tol, max_iter=max_iter)
+            ts.append(time.perf_counter() - ta)   # the step returns after its last status read
             evs.append(ev)
             its.append([s["iterations"] for s in st])
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         res = {"ms_per_step": 1e3 * el / measure_steps, "evals_per_step": float(np.mean(evs)),
-               "iterations_per_replica": float(np.mean(its))}
+               "iterations_per_replica": float(np.mean(its)),
+               "ms_median": 1e3 * float(np.median(ts)), "ms_p95": 1e3 * float(np.percentile(ts, 95))}
         out[names.get(mode, str(mode))] = res
         if log:
             log(f"  warm start {names.get(mode, mode)}: {res['ms_per_step']:.3f} ms/step, "

@@ -353,3 +353,19 @@ def test_batched_replicas_network_warm_start(hsf):
         err = np.max(np.abs(both[r] - alone)) / np.max(np.abs(alone))
         say(f"[batched warm start] replica {r}: max rel difference {err:.2e}")
         assert err < 1e-12
+
+
+def test_output_scale(hsf):
+    """The output scale multiplies each output channel after the last convolution, and
+    training is refused while a scale other than 1 is set."""
+    net = hsf.Net(2, 2, (8, 16), seed=3)
+    x = smooth_inputs(1, 2, 16, seed=4)
+    t = smooth_inputs(1, 2, 16, seed=5)
+    y1 = net.forward(x.ravel(), 1, 16).reshape(2, -1)
+    net.set_output_scale([3.0, 0.25])
+    y2 = net.forward(x.ravel(), 1, 16).reshape(2, -1)
+    assert np.array_equal(y2[0], y1[0] * np.float32(3.0)) and np.array_equal(y2[1], y1[1] * np.float32(0.25))
+    with pytest.raises(hsf.HsfError):
+        net.train_step(x.ravel(), t.ravel(), 1, 16, 1e-3)
+    net.set_output_scale([1.0, 1.0])
+    net.train_step(x.ravel(), t.ravel(), 1, 16, 1e-3)
