@@ -59,6 +59,8 @@ def make_workloads(name, precision):
         return [W.melt64_a8b8(tau=0.6, precision=precision)]
     if name == "melt16_a4b4":
         return [W.melt16_a4b4().with_(precision=precision)]
+    if name == "melt192_a8b8":
+        return [W.melt192_a8b8(precision=precision)]
     if name == "melt96_a4b12":
         return [W.melt96_a4b12().with_(precision=precision)]
     if name == "vesicle128_a3b9s":

@@ -7,7 +7,7 @@ namespace hsf {
 
 // Core tile (cx, cy, cz) and contour steps per launch (k).  k = 0 selects the direct
 // kernels: one contour step per launch, neighbours read through the caches, a block
-// covers cx x cy sites of one plane (cz = 1, cx * cy = 256).
+// covers cx x cy columns (cx * cy = 256) of cz planes.
 struct TileCfg {
     int cx, cy, cz, k;
 };
@@ -17,6 +17,10 @@ struct TileCfg {
     X(64, 4, 1, 0)          \
     X(32, 8, 1, 0)          \
     X(16, 16, 1, 0)         \
+    X(64, 4, 2, 0)          \
+    X(64, 4, 4, 0)          \
+    X(32, 8, 4, 0)          \
+    X(64, 4, 8, 0)          \
     X(8, 8, 8, 1)           \
     X(8, 8, 8, 2)           \
     X(8, 8, 8, 3)           \

@@ -330,12 +330,16 @@ __global__ __launch_bounds__(kBlock) void k_field_exp(const int *__restrict__ bl
     }
 }
 
-// One contour step per launch without LDS staging: the 27 neighbours come through the
-// caches.  Block tile CX x CY sites of one z-plane (CX * CY = kBlock threads).
+// One contour step per launch without LDS staging: the neighbours come through the
+// caches.  Block tile CX x CY sites of a plane (CX * CY = kBlock threads, one (x, y)
+// column each) and CZ consecutive planes per thread.  With CZ > 1 a thread forms, for
+// every plane it touches, the in-plane class sums (centre, 4 edge-sharing, 4 corner
+// neighbours: 9 loads) once and combines three consecutive planes per site, so a site
+// costs 9 (CZ + 2) / CZ loads instead of 27.
 // Tile of this block for the direct kernels.  SINGLE: one replica whose descriptor is a
 // kernel argument (no dependent loads before the stencil), and it is active whenever a
 // kernel is launched.
-template <int CX, int CY, bool SINGLE>
+template <int CX, int CY, int CZ, bool SINGLE>
 __device__ __forceinline__ bool direct_tile(const int *blk_rep, const int *blk_first, const Rep *rep,
                                             const RepState *st, const Rep &rep0, int &r, const Rep *&R, int &x0,
                                             int &y0, int &z0)
@@ -348,15 +352,52 @@ __device__ __forceinline__ bool direct_tile(const int *blk_rep, const int *blk_f
         x0 = (lb % ntx) * CX;
         lb /= ntx;
         y0 = (lb % nty) * CY;
-        z0 = lb / nty;
+        z0 = (lb / nty) * CZ;
         return true;
     }
-    tile_of<CX, CY, 1>(blk_rep, blk_first, rep, r, x0, y0, z0);
+    tile_of<CX, CY, CZ>(blk_rep, blk_first, rep, r, x0, y0, z0);
     R = &rep[r];
     return st[r].active != 0;
 }
 
-template <typename real, int CX, int CY, bool SINGLE>
+// In-plane class sums of f around (x, y) in plane z (9 loads).
+template <typename real>
+__device__ __forceinline__ void plane_sums(const real *__restrict__ f, int x, int y, int z, int Lx, int Ly,
+                                           real &a0, real &a1, real &a2)
+{
+    const int xm = wrap1(x - 1, Lx), xp = wrap1(x + 1, Lx);
+    const int ym = wrap1(y - 1, Ly), yp = wrap1(y + 1, Ly);
+    const real *p0 = f + ((long long)z * Ly + y) * Lx;
+    const real *pm = f + ((long long)z * Ly + ym) * Lx;
+    const real *pp = f + ((long long)z * Ly + yp) * Lx;
+    a0 = p0[x];
+    a1 = (p0[xm] + p0[xp]) + (pm[x] + pp[x]);
+    a2 = (pm[xm] + pm[xp]) + (pp[xm] + pp[xp]);
+}
+
+// The stencil at the sites (x, y, z0 + j), j < nz (<= CZ), of f into S[j].
+template <typename real, int CZ>
+__device__ __forceinline__ void column_stencil(const real *__restrict__ f, int x, int y, int z0, int nz, const Rep &R,
+                                               real *S)
+{
+    const real c0 = (real)R.c[0], c1 = (real)R.c[1], c2 = (real)R.c[2], c3 = (real)R.c[3];
+    if (CZ == 1) {
+        S[0] = stencil27<real>(f, x, y, z0, R.Lx, R.Ly, R.Lz, c0, c1, c2, c3);
+        return;
+    }
+    real a0[CZ + 2], a1[CZ + 2], a2[CZ + 2];
+#pragma unroll
+    for (int q = 0; q < CZ + 2; ++q) {
+        a0[q] = a1[q] = a2[q] = (real)0;
+        if (q <= nz + 1) plane_sums<real>(f, x, y, wrap1(z0 - 1 + q, R.Lz), R.Lx, R.Ly, a0[q], a1[q], a2[q]);
+    }
+#pragma unroll
+    for (int j = 0; j < CZ; ++j)
+        S[j] = c0 * a0[j + 1] + c1 * (a1[j + 1] + (a0[j] + a0[j + 2])) + c2 * (a2[j + 1] + (a1[j] + a1[j + 2])) +
+               c3 * (a2[j] + a2[j + 2]);
+}
+
+template <typename real, int CX, int CY, int CZ, bool SINGLE>
 __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ blk_rep,
                                                        const int *__restrict__ blk_first,
                                                        const Rep *__restrict__ rep,
@@ -364,30 +405,38 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ b
                                                        PropBufs<real> b, double *__restrict__ partG, int nblocks,
                                                        int sums, Rep rep0)
 {
-    static_assert(CX * CY == kBlock, "one site per thread");
+    static_assert(CX * CY == kBlock, "one column per thread");
     int r, x0, y0, z0;
     const Rep *Rp;
-    if (!direct_tile<CX, CY, SINGLE>(blk_rep, blk_first, rep, st, rep0, r, Rp, x0, y0, z0)) return;
+    if (!direct_tile<CX, CY, CZ, SINGLE>(blk_rep, blk_first, rep, st, rep0, r, Rp, x0, y0, z0)) return;
     const Rep &R = *Rp;
     const int V = (int)R.V;
-    const int x = x0 + (int)threadIdx.x % CX, y = y0 + (int)threadIdx.x / CX, z = z0;
+    const int x = x0 + (int)threadIdx.x % CX, y = y0 + (int)threadIdx.x / CX;
+    const int nz = min(CZ, R.Lz - z0);
     real *G = b.G + (long long)ch.N * R.site_off;
     const real *E = b.E + off_poly(R);
     double gsum = 0.0, esum[2] = {0.0, 0.0};
     if (x < R.Lx && y < R.Ly) {
-        const int site = x + R.Lx * (y + R.Ly * z);
-        real S;
-        if (s == 1)
-            S = (real)R.csum;
-        else
-            S = stencil27<real>(G + (long long)(s - 2) * V, x, y, z, R.Lx, R.Ly, R.Lz, (real)R.c[0], (real)R.c[1],
-                                (real)R.c[2], (real)R.c[3]);
-        const real g = E[ch.types[s - 1] * V + site] * S * pow2_neg_b<real>(st[r].scale_e[s - 1]);
-        G[(long long)(s - 1) * V + site] = g;
-        gsum = (double)g;
-        if (s == 1 && sums) {
-            esum[0] = (double)E[site];
-            esum[1] = (double)E[V + site];
+        real S[CZ];
+        if (s == 1) {
+#pragma unroll
+            for (int j = 0; j < CZ; ++j) S[j] = (real)R.csum;
+        } else {
+            column_stencil<real, CZ>(G + (long long)(s - 2) * V, x, y, z0, nz, R, S);
+        }
+        const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
+        const real *Es = E + ch.types[s - 1] * V;
+#pragma unroll
+        for (int j = 0; j < CZ; ++j) {
+            if (j >= nz) break;
+            const int site = x + R.Lx * (y + R.Ly * (z0 + j));
+            const real g = Es[site] * S[j] * sc;
+            G[(long long)(s - 1) * V + site] = g;
+            gsum += (double)g;
+            if (s == 1 && sums) {
+                esum[0] += (double)E[site];
+                esum[1] += (double)E[V + site];
+            }
         }
     }
     if (sums || s == ch.N) {
@@ -402,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ b
     }
 }
 
-template <typename real, int CX, int CY, bool SINGLE>
+template <typename real, int CX, int CY, int CZ, bool SINGLE>
 __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ blk_rep,
                                                        const int *__restrict__ blk_first,
                                                        const Rep *__restrict__ rep,
@@ -413,55 +462,62 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ b
                                                        const double *__restrict__ d, double *__restrict__ out,
                                                        double *__restrict__ part, Rep rep0)
 {
-    static_assert(CX * CY == kBlock, "one site per thread");
+    static_assert(CX * CY == kBlock, "one column per thread");
     int r, x0, y0, z0;
     const Rep *Rp;
-    if (!direct_tile<CX, CY, SINGLE>(blk_rep, blk_first, rep, st, rep0, r, Rp, x0, y0, z0)) return;
+    if (!direct_tile<CX, CY, CZ, SINGLE>(blk_rep, blk_first, rep, st, rep0, r, Rp, x0, y0, z0)) return;
     const Rep &R = *Rp;
     const int V = (int)R.V;
     const int N = ch.N;
     const int ts = ch.types[s - 1];
-    const int x = x0 + (int)threadIdx.x % CX, y = y0 + (int)threadIdx.x / CX, z = z0;
+    const int x = x0 + (int)threadIdx.x % CX, y = y0 + (int)threadIdx.x / CX;
+    const int nz = min(CZ, R.Lz - z0);
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
     if (x < R.Lx && y < R.Ly) {
-        const int site = x + R.Lx * (y + R.Ly * z);
         const long long po = off_poly(R);
-        real S;
-        if (s == N)
-            S = (real)R.csum;
-        else
-            S = stencil27<real>(gin + R.site_off, x, y, z, R.Lx, R.Ly, R.Lz, (real)R.c[0], (real)R.c[1],
-                                (real)R.c[2], (real)R.c[3]);
-        const real *G = b.G + (long long)N * R.site_off;
-        const double term = (double)G[(long long)(s - 1) * V + site] * (double)S;
-        if (s > 1) {
-            gout[R.site_off + site] = b.E[po + ts * V + site] * S * pow2_neg_b<real>(st[r].scale_e[s - 1]);
-            if (s == N) {
-                acc[po + (long long)ts * V + site] = term;
-                acc[po + (long long)(1 - ts) * V + site] = 0.0;
-            } else {
-                acc[po + (long long)ts * V + site] += term;
-            }
-        } else {
-            double a[2] = {0.0, 0.0};
-            if (N > 1) {
-                a[0] = acc[po + site];
-                a[1] = acc[po + V + site];
-            }
-            a[ts] += term;
-            const double coef = st[r].phibar_p / ((double)N * st[r].q);
-            const long long fo = off_field(R, ch.nsp);
+        real S[CZ];
+        if (s == N) {
 #pragma unroll
-            for (int I = 0; I < 2; ++I) {
-                const double ph = coef * a[I];
-                if (final_mode == 0) {
-                    out[fo + (long long)I * V + site] = ph;
+            for (int j = 0; j < CZ; ++j) S[j] = (real)R.csum;
+        } else {
+            column_stencil<real, CZ>(gin + R.site_off, x, y, z0, nz, R, S);
+        }
+        const real *G = b.G + (long long)N * R.site_off;
+        const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
+        const double coef = st[r].phibar_p / ((double)N * st[r].q);
+        const long long fo = off_field(R, ch.nsp);
+#pragma unroll
+        for (int j = 0; j < CZ; ++j) {
+            if (j >= nz) break;
+            const int site = x + R.Lx * (y + R.Ly * (z0 + j));
+            const double term = (double)G[(long long)(s - 1) * V + site] * (double)S[j];
+            if (s > 1) {
+                gout[R.site_off + site] = b.E[po + ts * V + site] * S[j] * sc;
+                if (s == N) {
+                    acc[po + (long long)ts * V + site] = term;
+                    acc[po + (long long)(1 - ts) * V + site] = 0.0;
                 } else {
-                    const double gI = phit[fo + (long long)I * V + site] - ph;
-                    out[po + (long long)I * V + site] = gI;
-                    if (d) sums[0] += d[po + (long long)I * V + site] * gI;
-                    sums[1] += ch.precond ? gI * gI / phit[fo + (long long)I * V + site] : gI * gI;
-                    sums[2 + I] += gI * gI;
+                    acc[po + (long long)ts * V + site] += term;
+                }
+            } else {
+                double a[2] = {0.0, 0.0};
+                if (N > 1) {
+                    a[0] = acc[po + site];
+                    a[1] = acc[po + V + site];
+                }
+                a[ts] += term;
+#pragma unroll
+                for (int I = 0; I < 2; ++I) {
+                    const double ph = coef * a[I];
+                    if (final_mode == 0) {
+                        out[fo + (long long)I * V + site] = ph;
+                    } else {
+                        const double gI = phit[fo + (long long)I * V + site] - ph;
+                        out[po + (long long)I * V + site] = gI;
+                        if (d) sums[0] += d[po + (long long)I * V + site] * gI;
+                        sums[1] += ch.precond ? gI * gI / phit[fo + (long long)I * V + site] : gI * gI;
+                        sums[2 + I] += gI * gI;
+                    }
                 }
             }
         }
@@ -483,7 +539,7 @@ struct BlockKernels {
                     PropBufs<real> b, double *partG, int sums, hipEvent_t e0, hipEvent_t e1)
     {
         if constexpr (K == 0) {
-            auto kern = p.n_rep == 1 ? k_fwd_direct<real, CX, CY, true> : k_fwd_direct<real, CX, CY, false>;
+            auto kern = p.n_rep == 1 ? k_fwd_direct<real, CX, CY, CZ, true> : k_fwd_direct<real, CX, CY, CZ, false>;
             if (e0)
                 hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first,
                                       rep, st, ch, s0 + 1, b, partG, p.nblocks, sums, p.rep0);
@@ -504,7 +560,7 @@ struct BlockKernels {
                     const double *d, double *out, double *part, hipEvent_t e0, hipEvent_t e1)
     {
         if constexpr (K == 0) {
-            auto kern = p.n_rep == 1 ? k_bwd_direct<real, CX, CY, true> : k_bwd_direct<real, CX, CY, false>;
+            auto kern = p.n_rep == 1 ? k_bwd_direct<real, CX, CY, CZ, true> : k_bwd_direct<real, CX, CY, CZ, false>;
             if (e0)
                 hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first,
                                       rep, st, ch, s_hi, b, gin, gout, acc, final_mode, phit, d, out, part, p.rep0);

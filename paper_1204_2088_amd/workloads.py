@@ -89,6 +89,15 @@ def melt64_a8b8(tau=0.6, precision="fp32"):
                     tol=1e-6 if precision == "fp32" else 1e-8, steps=2000)
 
 
+def melt192_a8b8(precision="fp32"):
+    """192^3 A8B8 melt, chi N = 20, tau 1.0: a box whose propagator store (16 x 7.1 M
+    sites, 453 MB in FP32) and LB populations (2 x 1.08 GB) exceed the on-package caches,
+    so the kernels stream from HBM."""
+    return Workload("melt192_a8b8", (192, 192, 192), chain(8, 8), False, chi_matrix(ab=20 / 16),
+                    tau=1.0, noise=0.01, seed=0, precision=precision,
+                    tol=1e-6 if precision == "fp32" else 1e-8, steps=100)
+
+
 def melt96_a4b12(hydro=True):
     """96^3 asymmetric A4B12 melt, chi N = 25, tau 1.0, FP32, noise 0.005."""
     return Workload("melt96_a4b12", (96, 96, 96), chain(4, 12), False, chi_matrix(ab=25 / 16),

@@ -324,8 +324,9 @@ def test_graph_replays_match_direct_launches(hsf, orc, monkeypatch):
             assert np.array_equal(x, y)
 
 
-TILES = [(64, 4, 1, 0), (32, 8, 1, 0), (16, 16, 1, 0), (8, 8, 8, 1), (8, 8, 8, 2), (8, 8, 8, 3), (8, 8, 8, 4),
-         (16, 8, 8, 2), (16, 8, 4, 2), (32, 8, 4, 1), (32, 4, 4, 2)]
+TILES = [(64, 4, 1, 0), (32, 8, 1, 0), (16, 16, 1, 0), (64, 4, 2, 0), (64, 4, 4, 0), (32, 8, 4, 0), (64, 4, 8, 0),
+         (8, 8, 8, 1), (8, 8, 8, 2), (8, 8, 8, 3), (8, 8, 8, 4), (16, 8, 8, 2), (16, 8, 4, 2), (32, 8, 4, 1),
+         (32, 4, 4, 2)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -352,6 +353,33 @@ def test_every_tile_configuration(hsf, orc, precision):
             tol = TOL64 if precision == "fp64" else TOL32
             assert e < tol and abs(q[0] / qref - 1) < tol, (t, L)
         ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_every_tile_configuration_batched(hsf, orc, precision):
+    """The same with two replicas of uneven boxes in one context (the replica of each
+    block comes from the tile plan, not a kernel argument)."""
+    types = W.chain(3, 4)
+    wls = [small_melt(L=(17, 18, 20), types=types, precision=precision, seed=1),
+           small_melt(L=(5, 3, 9), types=types, precision=precision, seed=2)]
+    ws = [fields_for(wl, seed=9 + r, amp=1.2) for r, wl in enumerate(wls)]
+    refs = [orc.evaluate(osys(orc, wl), w, 1.0, 0.0) for wl, w in zip(wls, ws)]
+    ctx = hsf.Context(wls)
+    ctx.set_densities(np.concatenate([W.initial_composition(wl).ravel() for wl in wls]))
+    ctx.set_fields(np.concatenate([w.ravel() for w in ws]))
+    tol = TOL64 if precision == "fp64" else TOL32
+    for t in TILES:
+        try:
+            ctx.set_tile(t)
+        except hsf.HsfError:
+            continue
+        got, q = ctx.evaluate()
+        for r, (wl, (ref, qref)) in enumerate(zip(wls, refs)):
+            fo = ctx.field_offset(r)
+            e = relerr(got[fo:fo + 2 * wl.V], ref)
+            say(f"[tile {t} batched] replica {r} {precision}: rel err {e:.3e}")
+            assert e < tol and abs(q[r] / qref - 1) < tol, (t, r)
+    ctx.close()
 
 
 def test_autotune_keeps_results(hsf, orc):
