@@ -482,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ b
         } else {
             column_stencil<real, CZ>(gin + R.site_off, x, y, z0, nz, R, S);
         }
-        const real *G = b.G + (long long)N * R.site_off;
+        real *G = b.G + (long long)N * R.site_off;
         const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
         const double coef = st[r].phibar_p / ((double)N * st[r].q);
         const long long fo = off_field(R, ch.nsp);
@@ -490,22 +490,18 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ b
         for (int j = 0; j < CZ; ++j) {
             if (j >= nz) break;
             const int site = x + R.Lx * (y + R.Ly * (z0 + j));
-            const double term = (double)G[(long long)(s - 1) * V + site] * (double)S[j];
+            real *Gs = G + (long long)(s - 1) * V + site;
             if (s > 1) {
                 gout[R.site_off + site] = b.E[po + ts * V + site] * S[j] * sc;
-                if (s == N) {
-                    acc[po + (long long)ts * V + site] = term;
-                    acc[po + (long long)(1 - ts) * V + site] = 0.0;
-                } else {
-                    acc[po + (long long)ts * V + site] += term;
-                }
+                // the density term G_s sigma[G+_{s+1}] replaces G_s in the store (G_s is
+                // not read again in this evaluation); step 1 sums them
+                *Gs = *Gs * S[j];
             } else {
+                // terms of steps N .. 2 in that order, then step 1's (the order of an
+                // accumulation along the backward sweep)
                 double a[2] = {0.0, 0.0};
-                if (N > 1) {
-                    a[0] = acc[po + site];
-                    a[1] = acc[po + V + site];
-                }
-                a[ts] += term;
+                for (int q = N; q >= 2; --q) a[ch.types[q - 1]] += (double)G[(long long)(q - 1) * V + site];
+                a[ts] += (double)*Gs * (double)S[j];
 #pragma unroll
                 for (int I = 0; I < 2; ++I) {
                     const double ph = coef * a[I];
