@@ -27,7 +27,8 @@ struct hsf_ctx {
     std::vector<Rep> reps;
     Rep *rep_d = nullptr;
     RepState *st_d = nullptr;
-    RepState *st_h = nullptr;        // pinned mirror for status reads
+    RepState *st_h = nullptr;        // pinned mirror for status reads (written by the control kernel)
+    RepState *st_hd = nullptr;       // the mirror's device-side address
     Plan plan;                       // site plan: kBlock consecutive sites per block
     TileCfg tile{8, 8, 8, 2};        // propagator tile configuration in use
     Plan tplan;                      // tile plan of `tile`
@@ -175,11 +176,9 @@ int sync(hsf_ctx *c)
     return harvest(c);
 }
 
-int read_status(hsf_ctx *c)
-{
-    HIPCHK(c, hipMemcpyAsync(c->st_h, c->st_d, sizeof(RepState) * c->n_rep, hipMemcpyDeviceToHost, c->stream));
-    return sync(c);
-}
+// The replicas' states as of the last control kernel: it writes them into the pinned
+// mirror st_h itself, so reading them takes a stream synchronisation only.
+int read_status(hsf_ctx *c) { return sync(c); }
 
 hipEvent_t new_event(hsf_ctx *c, bool pooled)
 {
@@ -322,7 +321,7 @@ void run_eval(hsf_ctx *c, int use_alpha, int final_mode, double *out, const doub
         launch_fwd_block<real>(c->tile, c->stream, c->tplan, c->rep_d, c->st_d, c->ch, s0, std::min(K, N - s0), b,
                                c->partG, sums, t.a, t.b);
     }
-    launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_Q, c->ch, c->partG, 0.0, 0);
+    launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_Q, c->ch, c->partG, 0.0, 0, c->st_hd);
     int parity = 0;
     for (int s_hi = N; s_hi >= 1; s_hi -= K) {
         Timed t(c, HSF_K_BWD);
@@ -347,7 +346,7 @@ void target_setup(hsf_ctx *c, double tol, int max_iter)
 {
     launch_target_stats(c->stream, c->plan, c->rep_d, c->st_d, c->ch, c->phi, c->w, c->part);
     launch_reduce_ctl(c->stream, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_TARGET, c->ch, c->partG, tol,
-                      max_iter);
+                      max_iter, c->st_hd);
 }
 
 // Starting fields of an inversion (the warm start), before the gauge is fixed.
@@ -439,42 +438,47 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
     int rc = run_seq(c, hsf_ctx::GK_START, [&] {
         run_eval_any(c, 0, 1, c->g, nullptr, 1);
         launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_EVAL0, c->ch, c->partG,
-                          0.0, 0);
+                          0.0, 0, c->st_hd);
         launch_cg_update(c->stream, c->plan, c->rep_d, c->st_d, c->ch, 1, c->w, c->g, c->gt, c->d, c->phi,
                          c->part);
         launch_reduce_ctl(c->stream, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_BEGIN, c->ch, c->partG,
-                          0.0, 0);
+                          0.0, 0, c->st_hd);
     });
     if (rc) return rc;
     if ((rc = read_status(c))) return rc;
     bool any = false;
-    for (int r = 0; r < c->n_rep; ++r) any |= c->st_h[r].active != 0;
-    // every pass either advances a line search (at most 3 trials per iteration) or
-    // ends an iteration, so 3 * max_iter + 3 passes bound the loop
+    for (int r = 0; r < c->n_rep; ++r) any |= c->st_h[r].active != 0 || c->st_h[r].pending != 0;
+    // A pass is one trial evaluation followed by the update sequence.  The update acts
+    // only on replicas whose trial was accepted (the CG step and the start of their next
+    // line search); for the others, and for finished replicas, every kernel of a pass
+    // does nothing, so each replica advances on its own, without waiting for the line
+    // searches of the others.  Passes could be issued several at a time between status
+    // reads; measured at 64^3 that gained nothing over one, so the host reads the states
+    // after every pass and stops once no replica is active.  Each pass either advances a
+    // line-search trial (at most 3 per iteration) or ends an iteration, so 3 * max_iter +
+    // 3 passes bound the loop.
+    constexpr int kPassesPerRead = 1;
     long long guard = 3LL * max_iter + 3;
     while (any) {
-        if (--guard < 0) return fail(c, HSF_EHIP, "inversion control did not progress");
-        rc = run_seq(c, hsf_ctx::GK_TRIAL, [&] {
-            run_eval_any(c, 1, 1, c->gt, c->d, 0);
-            launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_TRIAL, c->ch,
-                              c->partG, 0.0, 0);
-        });
-        if (rc) return rc;
-        if ((rc = read_status(c))) return rc;
-        bool trialing = false, pending = false;
-        for (int r = 0; r < c->n_rep; ++r) {
-            trialing |= c->st_h[r].active != 0;
-            pending |= c->st_h[r].pending != 0;
+        for (int p = 0; p < kPassesPerRead; ++p) {
+            if (--guard < 0) return fail(c, HSF_EHIP, "inversion control did not progress");
+            rc = run_seq(c, hsf_ctx::GK_TRIAL, [&] {
+                run_eval_any(c, 1, 1, c->gt, c->d, 0);
+                launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_TRIAL, c->ch,
+                                  c->partG, 0.0, 0, c->st_hd);
+            });
+            if (rc) return rc;
+            rc = run_seq(c, hsf_ctx::GK_UPDATE, [&] {
+                launch_cg_update(c->stream, c->plan, c->rep_d, c->st_d, c->ch, 0, c->w, c->g, c->gt, c->d, c->phi,
+                                 c->part);
+                launch_reduce_ctl(c->stream, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_BEGIN, c->ch,
+                                  c->partG, 0.0, 0, c->st_hd);
+            });
+            if (rc) return rc;
         }
-        if (trialing) continue;
-        rc = run_seq(c, hsf_ctx::GK_UPDATE, [&] {
-            launch_cg_update(c->stream, c->plan, c->rep_d, c->st_d, c->ch, 0, c->w, c->g, c->gt, c->d, c->phi,
-                             c->part);
-            launch_reduce_ctl(c->stream, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_BEGIN, c->ch,
-                              c->partG, 0.0, 0);
-        });
-        if (rc) return rc;
-        any = pending;
+        if ((rc = read_status(c))) return rc;
+        any = false;
+        for (int r = 0; r < c->n_rep; ++r) any |= c->st_h[r].active != 0 || c->st_h[r].pending != 0;
     }
     if ((rc = read_status(c))) return rc;
     HIPCHK(c, hipGetLastError());
@@ -632,6 +636,8 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     if (rc == HSF_OK) {
         hipError_t e = hipHostMalloc((void **)&c->st_h, sizeof(RepState) * n_rep, hipHostMallocDefault);
         if (e != hipSuccess) rc = fail(c, HSF_ENOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
+        else if ((e = hipHostGetDevicePointer((void **)&c->st_hd, c->st_h, 0)) != hipSuccess)
+            rc = fail(c, HSF_EHIP, "hipHostGetDevicePointer failed: %s", hipGetErrorString(e));
     }
     if (rc != HSF_OK) {
         hsf_destroy(c);
@@ -765,7 +771,7 @@ int hsf_evaluate(hsf_ctx *c, double *phi_out, double *Q_out, int where)
             target_setup(c, 0.0, 0);   // phibar_p, phibar_s from the current densities; all replicas active
             run_eval_any(c, 0, 0, c->eval_out, nullptr, 1);
             launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_SCALES, c->ch,
-                              c->partG, 0.0, 0);
+                              c->partG, 0.0, 0, c->st_hd);
         });
         if (rc0) return rc0;
         if ((rc0 = read_status(c))) return rc0;
@@ -775,7 +781,7 @@ int hsf_evaluate(hsf_ctx *c, double *phi_out, double *Q_out, int where)
     }
     if (c->ch.nsp == 3) {
         launch_solvent(s, c->plan, c->rep_d, c->st_d, c->ch, 0, c->w, c->phi, c->eval_out, c->part);
-        launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_SOLVENT, c->ch, c->partG, 0.0, 0);
+        launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_SOLVENT, c->ch, c->partG, 0.0, 0, c->st_hd);
         launch_solvent(s, c->plan, c->rep_d, c->st_d, c->ch, 1, c->w, c->phi, c->eval_out, c->part);
     }
     HIPCHK(c, hipGetLastError());

@@ -56,12 +56,15 @@ __device__ void update_scales(RepState &S, const Chain &ch, const double *sums, 
 
 __device__ void control(RepState &S, int phase, const Chain &ch, const double *red, const double *gsum,
                         double V, double csum, double tol, int max_iter);
+__device__ void reduce_and_control(RepState &S, int r, const int *__restrict__ blk_first, const Rep *__restrict__ rep,
+                                   const double *__restrict__ part, int phase, const Chain &ch,
+                                   const double *__restrict__ partG, int nblocks, double tol, int max_iter);
 
 __global__ __launch_bounds__(kBlock) void k_reduce_ctl(const int *__restrict__ blk_first,
                                                        RepState *__restrict__ st, const Rep *__restrict__ rep,
                                                        const double *__restrict__ part, int phase, Chain ch,
                                                        const double *__restrict__ partG, int nblocks,
-                                                       double tol, int max_iter)
+                                                       double tol, int max_iter, RepState *__restrict__ mirror)
 {
     const int r = blockIdx.x;
     // work on an LDS copy of the replica's state: one cooperative load and store instead of
@@ -74,9 +77,6 @@ __global__ __launch_bounds__(kBlock) void k_reduce_ctl(const int *__restrict__ b
         for (int k = threadIdx.x; k < (int)(sizeof(RepState) / 4); k += kBlock) dst[k] = src[k];
     }
     __syncthreads();
-    const int b0 = blk_first[r], b1 = blk_first[r + 1];
-    const double V = (double)rep[r].V;
-    __shared__ double vals[kNQ + 66];
 
     // which replicas take part in this phase (uniform per block)
     bool take;
@@ -84,11 +84,34 @@ __global__ __launch_bounds__(kBlock) void k_reduce_ctl(const int *__restrict__ b
     case PH_Q: case PH_EVAL0: case PH_TRIAL: case PH_SCALES: take = S.active != 0; break;
     default: take = true; break;
     }
-    if (!take) return;
-    if (phase == PH_BEGIN && !S.pending) {
-        if (threadIdx.x == 0) st[r].accepted = 0;
-        return;
+    if (take && phase == PH_BEGIN && !S.pending) {
+        take = false;
+        __syncthreads();
+        if (threadIdx.x == 0) S.accepted = 0;
     }
+    if (take) reduce_and_control(S, r, blk_first, rep, part, phase, ch, partG, nblocks, tol, max_iter);
+    __syncthreads();
+    {
+        // the state back to device memory and into the host's pinned mirror, which the
+        // host reads after synchronising the stream (no copy launch)
+        const int *src = reinterpret_cast<const int *>(&S);
+        int *dst = reinterpret_cast<int *>(&st[r]);
+        int *hm = mirror ? reinterpret_cast<int *>(&mirror[r]) : nullptr;
+        for (int k = threadIdx.x; k < (int)(sizeof(RepState) / 4); k += kBlock) {
+            dst[k] = src[k];
+            if (hm) hm[k] = src[k];
+        }
+    }
+}
+
+// The reduction of one phase's partial sums for replica r and the scalar control step.
+__device__ void reduce_and_control(RepState &S, int r, const int *__restrict__ blk_first, const Rep *__restrict__ rep,
+                                   const double *__restrict__ part, int phase, const Chain &ch,
+                                   const double *__restrict__ partG, int nblocks, double tol, int max_iter)
+{
+    const int b0 = blk_first[r], b1 = blk_first[r + 1];
+    const double V = (double)rep[r].V;
+    __shared__ double vals[kNQ + 66];
 
     // rows to reduce: nslots slots of `part`, then ng rows of `partG` starting at g_first
     int nslots = 0, g_first = 0, ng = 0;
@@ -121,12 +144,6 @@ __global__ __launch_bounds__(kBlock) void k_reduce_ctl(const int *__restrict__ b
     const double *red = vals;
     const double *gsum = vals + nslots - g_first;   // gsum[s] = sum of stored G_{s+1}
     if (threadIdx.x == 0) control(S, phase, ch, red, gsum, V, rep[r].csum, tol, max_iter);
-    __syncthreads();
-    {
-        const int *src = reinterpret_cast<const int *>(&S);
-        int *dst = reinterpret_cast<int *>(&st[r]);
-        for (int k = threadIdx.x; k < (int)(sizeof(RepState) / 4); k += kBlock) dst[k] = src[k];
-    }
 }
 
 // Scalar logic of one replica after the reductions of a phase (runs in one thread).
@@ -265,10 +282,10 @@ __device__ void control(RepState &S, int phase, const Chain &ch, const double *r
 
 void launch_reduce_ctl(hipStream_t s, int n_rep, const Plan &p, RepState *st, const Rep *rep,
                        const double *part, int phase, Chain ch, const double *partG, double tol,
-                       int max_iter)
+                       int max_iter, RepState *mirror)
 {
     hipLaunchKernelGGL(k_reduce_ctl, dim3(n_rep), dim3(kBlock), 0, s, p.blk_first, st, rep, part, phase, ch,
-                       partG, p.nblocks, tol, max_iter);
+                       partG, p.nblocks, tol, max_iter, mirror);
 }
 
 // Partial sums of the inversion target: sum of polymer phi^t, sum of phi^t_S,

@@ -86,9 +86,11 @@ enum Phase {
     PH_SCALES = 5,   // update of the per-step scales from the G_s means
     PH_SOLVENT = 6   // <exp(-w_S)>
 };
+// The control kernel also writes every replica's state into `mirror` (pinned host
+// memory, or null), which the host reads after synchronising the stream.
 void launch_reduce_ctl(hipStream_t s, int n_rep, const Plan &p, RepState *st, const Rep *rep,
                        const double *part, int phase, Chain ch, const double *partG, double tol,
-                       int max_iter);
+                       int max_iter, RepState *mirror);
 
 void launch_target_stats(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
                          const double *phit, const double *w, double *part);

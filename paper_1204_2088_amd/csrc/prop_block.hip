@@ -39,20 +39,34 @@ struct TileCtx {
     int x0, y0, z0;
 };
 
-// Region of level k: positions [k, N - k) per axis in region coordinates.
-template <int CX, int CY, int CZ, int K, typename F>
-__device__ __forceinline__ void for_region(int k, F &&f)
+// Iterations of a kBlock-thread loop over the level-k region, and the region position
+// of iteration `it` of this thread (false past the region's end).
+template <int CX, int CY, int CZ, int K>
+__host__ __device__ constexpr int region_iters(int k)
+{
+    return ((CX + 2 * (K - k)) * (CY + 2 * (K - k)) * (CZ + 2 * (K - k)) + kBlock - 1) / kBlock;
+}
+
+template <int CX, int CY, int CZ, int K>
+__host__ __device__ constexpr int region_iters_total()
+{
+    int n = 0;
+    for (int k = 1; k <= K; ++k) n += region_iters<CX, CY, CZ, K>(k);
+    return n;
+}
+
+template <int CX, int CY, int CZ, int K>
+__device__ __forceinline__ bool region_pos(int k, int it, int &px, int &py, int &pz)
 {
     constexpr int NX = CX + 2 * K, NY = CY + 2 * K, NZ = CZ + 2 * K;
     const int mx = NX - 2 * k, my = NY - 2 * k, mz = NZ - 2 * k;
-    const int m = mx * my * mz;
-    for (int t = threadIdx.x; t < m; t += kBlock) {
-        const int px = k + t % mx;
-        const int rest = t / mx;
-        const int py = k + rest % my;
-        const int pz = k + rest / my;
-        f(px, py, pz);
-    }
+    const int t = (int)threadIdx.x + it * kBlock;
+    if (t >= mx * my * mz) return false;
+    px = k + t % mx;
+    const int rest = t / mx;
+    py = k + rest % my;
+    pz = k + rest / my;
+    return true;
 }
 
 template <typename real, int NX, int NY>
@@ -135,7 +149,23 @@ __global__ __launch_bounds__(kBlock) void k_fwd_block(const int *__restrict__ bl
     real *G = b.G + (long long)ch.N * R.site_off;
     const real *E = b.E + off_poly(R);
     __syncthreads();
-    // stage G_{s0} on the full region
+    // every global load of the launch is issued before the first is needed: the field
+    // factors of all levels' sites of this thread, then G_{s0} on the full region
+    constexpr int NIT = region_iters_total<CX, CY, CZ, K>();
+    real ev[NIT];
+    {
+        int q = 0;
+#pragma unroll
+        for (int k = 1; k <= K; ++k) {
+            const real *Et = E + ch.types[min(s0 + k, ch.N) - 1] * V;
+#pragma unroll
+            for (int it = 0; it < region_iters<CX, CY, CZ, K>(k); ++it, ++q) {
+                int px, py, pz;
+                ev[q] = (real)0;
+                if (k <= nsteps && region_pos<CX, CY, CZ, K>(k, it, px, py, pz)) ev[q] = Et[ox[px] + oy[py] + oz[pz]];
+            }
+        }
+    }
     if (s0 == 0) {
         for (int t = threadIdx.x; t < NR; t += kBlock) buf[0][t] = (real)1;
     } else {
@@ -148,19 +178,25 @@ __global__ __launch_bounds__(kBlock) void k_fwd_block(const int *__restrict__ bl
     __syncthreads();
     const int cx1 = min(CX, R.Lx - x0), cy1 = min(CY, R.Ly - y0), cz1 = min(CZ, R.Lz - z0);
     double esum[2] = {0.0, 0.0};
+    int q = 0;
 #pragma unroll
     for (int k = 1; k <= K; ++k) {
         if (k > nsteps) break;
         const int s = s0 + k;
-        const real *Et = E + ch.types[s - 1] * V;
         const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
         const real *in = buf[(k - 1) & 1];
         real *out = buf[k & 1];
         double gsum = 0.0;
-        for_region<CX, CY, CZ, K>(k, [&](int px, int py, int pz) {
+        q = 0;
+#pragma unroll
+        for (int kk = 1; kk < k; ++kk) q += region_iters<CX, CY, CZ, K>(kk);
+#pragma unroll
+        for (int it = 0; it < region_iters<CX, CY, CZ, K>(k); ++it) {
+            int px, py, pz;
+            if (!region_pos<CX, CY, CZ, K>(k, it, px, py, pz)) break;
             const int site = ox[px] + oy[py] + oz[pz];
             const real S = stencil_lds<real, NX, NY>(in, px, py, pz, c0, c1, c2, c3);
-            const real g = Et[site] * S * sc;
+            const real g = ev[q + it] * S * sc;
             out[pz * NX * NY + py * NX + px] = g;
             const int qx = px - K, qy = py - K, qz = pz - K;
             if (qx >= 0 && qx < cx1 && qy >= 0 && qy < cy1 && qz >= 0 && qz < cz1) {
@@ -171,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_block(const int *__restrict__ bl
                     esum[1] += (double)E[V + site];
                 }
             }
-        });
+        }
         if (sums || s == ch.N) {
             const double t = block_sum(gsum);   // contains __syncthreads: the level is complete
             if (threadIdx.x == 0) partG[(long long)(s - 1) * nblocks + plan_block()] = t;
@@ -222,6 +258,30 @@ __global__ __launch_bounds__(kBlock) void k_bwd_block(const int *__restrict__ bl
     const real *E = b.E + off_poly(R);
     for (int t = threadIdx.x; t < 2 * NC; t += kBlock) (&accl[0][0])[t] = 0.0;
     __syncthreads();
+    // global loads issued up front: per level and site of this thread the field factor
+    // (levels with s > 1) and, at core sites, G_s; then G+_{s_hi+1} on the region
+    constexpr int NIT = region_iters_total<CX, CY, CZ, K>();
+    real ev[NIT], gv[NIT];
+    {
+        int q = 0;
+#pragma unroll
+        for (int k = 1; k <= K; ++k) {
+            const int s = max(s_hi - k + 1, 1);
+            const real *Et = E + ch.types[s - 1] * V;
+            const real *Gs = G + (long long)(s - 1) * V;
+#pragma unroll
+            for (int it = 0; it < region_iters<CX, CY, CZ, K>(k); ++it, ++q) {
+                int px, py, pz;
+                ev[q] = gv[q] = (real)0;
+                if (k <= nsteps && region_pos<CX, CY, CZ, K>(k, it, px, py, pz)) {
+                    const int site = ox[px] + oy[py] + oz[pz];
+                    if (s > 1) ev[q] = Et[site];
+                    const int qx = px - K, qy = py - K, qz = pz - K;
+                    if (qx >= 0 && qx < CX && qy >= 0 && qy < CY && qz >= 0 && qz < CZ) gv[q] = Gs[site];
+                }
+            }
+        }
+    }
     if (s_hi == N) {
         for (int t = threadIdx.x; t < NR; t += kBlock) buf[0][t] = (real)1;
     } else {
@@ -240,19 +300,22 @@ __global__ __launch_bounds__(kBlock) void k_bwd_block(const int *__restrict__ bl
         last_k = k;
         const int s = s_hi - k + 1;
         const int ts = ch.types[s - 1];
-        const real *Et = E + ts * V;
-        const real *Gs = G + (long long)(s - 1) * V;
         const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
         const real *in = buf[(k - 1) & 1];
         real *o = buf[k & 1];
-        for_region<CX, CY, CZ, K>(k, [&](int px, int py, int pz) {
-            const int site = ox[px] + oy[py] + oz[pz];
+        int q = 0;
+#pragma unroll
+        for (int kk = 1; kk < k; ++kk) q += region_iters<CX, CY, CZ, K>(kk);
+#pragma unroll
+        for (int it = 0; it < region_iters<CX, CY, CZ, K>(k); ++it) {
+            int px, py, pz;
+            if (!region_pos<CX, CY, CZ, K>(k, it, px, py, pz)) break;
             const real S = stencil_lds<real, NX, NY>(in, px, py, pz, c0, c1, c2, c3);
-            if (s > 1) o[pz * NX * NY + py * NX + px] = Et[site] * S * sc;
+            if (s > 1) o[pz * NX * NY + py * NX + px] = ev[q + it] * S * sc;
             const int qx = px - K, qy = py - K, qz = pz - K;
             if (qx >= 0 && qx < CX && qy >= 0 && qy < CY && qz >= 0 && qz < CZ)
-                accl[ts][(qz * CY + qy) * CX + qx] += (double)Gs[site] * (double)S;
-        });
+                accl[ts][(qz * CY + qy) * CX + qx] += (double)gv[q + it] * (double)S;
+        }
         __syncthreads();
     }
     const int s_lo = s_hi - last_k + 1;
