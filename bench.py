@@ -204,6 +204,9 @@ def main():
     ap.add_argument("--precond", action="store_true", help="diagonally preconditioned inversion")
     ap.add_argument("--tile", default=None, help="cx,cy,cz,k: use this propagator tiling instead of autotuning")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
+    ap.add_argument("--lb", default="bgk", choices=["bgk", "mrt"],
+                    help="LB collision: BGK, or the MRT scheme with the shear viscosity of the workload's tau, "
+                         "the same bulk eigenvalue and the kinetic modes relaxed completely")
     ap.add_argument("--net-probe", default=None, metavar="WIDTHS",
                     help="only time the warm-start network of these level widths (e.g. 16 or 8,16,24,32): "
                          "forward passes and Adam steps on two 64^3 samples")
@@ -260,6 +263,9 @@ def main():
 
     torch.cuda.set_device(0)
     wls = make_workloads(args.workload, args.precision)
+    if args.lb == "mrt":
+        from paper_1204_2088_amd import workloads as W
+        wls = [w.with_(lb="mrt", gammas=W.mrt_gammas(w.tau)) for w in wls]
     wl = wls[0]
     ctx, tile, tune_ms, stats, (evals, site_evals), elapsed, timing, t_steps, t_elapsed = run_arm(
         hsf, torch, wls, args.steps, args.warmup, not args.no_timing, log, args.precond,
@@ -336,7 +342,7 @@ def main():
         "config": {"workload": args.workload, "L": list(wl.L), "N": N, "replicas": len(wls),
                    "tau": [w.tau for w in wls], "propagators": wl.precision, "reductions": "fp64",
                    "tol": wl.tol, "dt": wl.dt, "hydro": True,
-                   "solver": "preconditioned FR" if args.precond else "FR"},
+                   "solver": "preconditioned FR" if args.precond else "FR", "lb": args.lb},
         "evals_per_step": evals / args.steps,
         "iterations_last_step": [s["iterations"] for s in stats][:8],
         "lb_mlups": lb_mlups,

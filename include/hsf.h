@@ -10,7 +10,8 @@
  *     conjugate gradients (section 2, text after eq. 17);
  *   - the chemical potential and thermodynamic force (eq. 4, eq. 8);
  *   - one D3Q19 lattice-Boltzmann collide-and-stream step (eq. 9-11, with
- *     the single-relaxation-time collision and its forcing term);
+ *     the single-relaxation-time collision and its forcing term, or the
+ *     multiple-relaxation-time collision of eq. 12-14 in the basis of Table 1);
  *   - one conservative update of the convection-diffusion equation (eq. 3);
  *   - the coupled step that alternates the two at equal time steps.
  *
@@ -106,7 +107,18 @@ typedef struct {
     double tau;                  /* LB single relaxation time (> 1/2)           */
     int hydro;                   /* 1: LB flow convects the densities           */
     int precision;               /* HSF_FP64 or HSF_FP32 (same for all replicas) */
+    int lb_mode;                 /* HSF_LB_BGK (tau) or HSF_LB_MRT (gammas)     */
+    double gamma_s, gamma_b;     /* MRT: eigenvalues of the shear (modes 5-9)   */
+                                 /* and bulk (mode 4) stress relaxation, in     */
+                                 /* (-1, 1): nu = (1 + gamma_s)/(6 (1 - gamma_s)) */
+    double gamma_ghost;          /* MRT: the kinetic (ghost) modes 10-18         */
 } hsf_params;
+
+/* LB collision: BGK with the forcing of eq. 14 at every rate 1 - 1/tau, or the
+ * multiple-relaxation-time scheme of eq. 12-14 in the basis of Table 1 with the
+ * independent eigenvalues gamma_s, gamma_b, gamma_ghost (conserved modes 0-3: 1;
+ * the forcing term uses gamma_s and gamma_b as in eq. 14). */
+enum { HSF_LB_BGK = 0, HSF_LB_MRT = 1 };
 
 typedef struct {
     int iterations;              /* conjugate-gradient iterations               */

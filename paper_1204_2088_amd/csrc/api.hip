@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -531,6 +532,10 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
             if (p.types[s] != p0.types[s] || p.types[s] < 0 || p.types[s] > 1) return HSF_EINVAL;
         if (p.Lx < 1 || p.Ly < 1 || p.Lz < 1) return HSF_EINVAL;
         if (!(p.tau > 0.5) || !(p.dt > 0.0)) return HSF_EINVAL;
+        if (p.lb_mode != HSF_LB_BGK && p.lb_mode != HSF_LB_MRT) return HSF_EINVAL;
+        if (p.lb_mode == HSF_LB_MRT && !(std::fabs(p.gamma_s) < 1.0 && std::fabs(p.gamma_b) < 1.0 &&
+                                         std::fabs(p.gamma_ghost) < 1.0))
+            return HSF_EINVAL;
     }
     hsf_ctx *c = new hsf_ctx();
     const char *ng = getenv("HSF_NO_GRAPHS");   // debugging aid: launch every kernel directly
@@ -564,6 +569,10 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
         R.kappa = p.kappa;
         R.dt = p.dt;
         R.tau = p.tau;
+        R.lb_mode = p.lb_mode;
+        R.gamma_s = p.gamma_s;
+        R.gamma_b = p.gamma_b;
+        R.gamma_ghost = p.gamma_ghost;
         c->reps.push_back(R);
         blk_first.push_back((int)blk_rep.size());
         const long long nb = (R.V + kBlock - 1) / kBlock;

@@ -11,11 +11,12 @@
 namespace hsf {
 
 // D3Q19 velocities: rest, 6 faces, 12 edges (order documented in hsf.h).
-__device__ constexpr int kCx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-__device__ constexpr int kCy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-__device__ constexpr int kCz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int kCx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int kCy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int kCz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
-__device__ __forceinline__ double lb_weight(int q) { return q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+// Weights of eq. 11.
+__host__ __device__ constexpr double lb_w(int q) { return q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
 __device__ __forceinline__ void site_xyz(const Rep &R, long long i, int &x, int &y, int &z)
 {
@@ -83,6 +84,108 @@ __global__ __launch_bounds__(kBlock) void k_force(const int *__restrict__ blk_re
     for (int a = 0; a < 3; ++a) f[vo + a * V + i] = k * acc[a];
 }
 
+// Multiple-relaxation-time collision (eq. 12-14) in the orthogonal basis of Table 1:
+// e_k(c) for k = 0..18, orthogonal under the weights w_i; b_k = sum_i w_i e_k(c_i)^2.
+__host__ __device__ constexpr double mrt_e(int k, int cx, int cy, int cz)
+{
+    const double x = cx, y = cy, z = cz, c2 = x * x + y * y + z * z;
+    switch (k) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return c2 - 1.0;
+    case 5: return x * x - y * y;
+    case 6: return c2 - 3.0 * z * z;
+    case 7: return x * y;
+    case 8: return x * z;
+    case 9: return y * z;
+    case 10: return (3.0 * c2 - 5.0) * x;
+    case 11: return (3.0 * c2 - 5.0) * y;
+    case 12: return (3.0 * c2 - 5.0) * z;
+    case 13: return (y * y - z * z) * x;
+    case 14: return (z * z - x * x) * y;
+    case 15: return (x * x - y * y) * z;
+    case 16: return 3.0 * c2 * c2 - 6.0 * c2 + 1.0;
+    case 17: return (2.0 * c2 - 3.0) * (x * x - y * y);
+    default: return (2.0 * c2 - 3.0) * (c2 - 3.0 * z * z);
+    }
+}
+
+
+// The basis at the 19 velocities and 1 / b_k, as compile-time tables (the unrolled
+// projections below index them with constants).
+struct MrtTable {
+    double e[19][19];   // [k][q]
+    double binv[19];
+};
+
+constexpr MrtTable make_mrt_table()
+{
+    MrtTable t{};
+    for (int k = 0; k < 19; ++k) {
+        double b = 0.0;
+        for (int q = 0; q < 19; ++q) {
+            t.e[k][q] = mrt_e(k, kCx[q], kCy[q], kCz[q]);
+            b += lb_w(q) * t.e[k][q] * t.e[k][q];
+        }
+        t.binv[k] = 1.0 / b;
+    }
+    return t;
+}
+
+__device__ constexpr MrtTable kMrt = make_mrt_table();
+
+// Post-collision populations of one site for the MRT scheme: n* = n_eq + w_i sum_k
+// e_k(c_i) m*_k / b_k with m*_k = gamma_k (n - n_eq)_k + (Delta^f)_k, where the forcing
+// Delta^f_i = (w_i / c_s^2) [f.c_i + Sigma : (c_i c_i - c_s^2 1) / (2 c_s^2)] and
+// Sigma = (1 + gamma_s)/2 (u f + f u - 2/3 (u.f) 1) + (1 + gamma_b)/3 (u.f) 1 (eq. 14).
+__device__ __forceinline__ void mrt_collide(const double *n, double rho, double ux, double uy, double uz, double fx,
+                                            double fy, double fz, const Rep &R, double *ns)
+{
+    const double gs = R.gamma_s, gb = R.gamma_b, gg = R.gamma_ghost;
+    const double uu = ux * ux + uy * uy + uz * uz, uf = ux * fx + uy * fy + uz * fz;
+    // Sigma (symmetric)
+    const double as = 0.5 * (1.0 + gs), ab = (1.0 + gb) / 3.0;
+    const double sxx = as * (2.0 * ux * fx - 2.0 / 3.0 * uf) + ab * uf;
+    const double syy = as * (2.0 * uy * fy - 2.0 / 3.0 * uf) + ab * uf;
+    const double szz = as * (2.0 * uz * fz - 2.0 / 3.0 * uf) + ab * uf;
+    const double sxy = as * (ux * fy + uy * fx), sxz = as * (ux * fz + uz * fx), syz = as * (uy * fz + uz * fy);
+    const double trs = sxx + syy + szz;
+    double dn[19], df[19], neq[19];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        const double cx = kCx[q], cy = kCy[q], cz = kCz[q];
+        const double cu = cx * ux + cy * uy + cz * uz;
+        neq[q] = rho * lb_w(q) * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        dn[q] = n[q] - neq[q];
+        // Sigma : (c c - 1/3) = c.Sigma.c - tr(Sigma)/3
+        const double scc = cx * cx * sxx + cy * cy * syy + cz * cz * szz +
+                           2.0 * (cx * cy * sxy + cx * cz * sxz + cy * cz * syz) - trs / 3.0;
+        df[q] = 3.0 * lb_w(q) * (cx * fx + cy * fy + cz * fz + 1.5 * scc);
+    }
+    double ms[19];
+#pragma unroll
+    for (int k = 0; k < 19; ++k) {
+        double m = 0.0, mf = 0.0;
+#pragma unroll
+        for (int q = 0; q < 19; ++q) {
+            const double e = kMrt.e[k][q];
+            m += e * dn[q];
+            mf += e * df[q];
+        }
+        const double g = k <= 3 ? 1.0 : (k == 4 ? gb : (k <= 9 ? gs : gg));
+        ms[k] = (g * m + mf) * kMrt.binv[k];
+    }
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < 19; ++k) a += kMrt.e[k][q] * ms[k];
+        ns[q] = neq[q] + lb_w(q) * a;
+    }
+}
+
 // One LB step, push form: read the 19 pre-collision populations of this site,
 // take the moments of eq. 9 (u with the half-force shift), relax towards the
 // equilibrium of eq. 11 with rate 1/tau, add the forcing term
@@ -118,19 +221,29 @@ __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, 
         jz += kCz[q] * n[q];
     }
     const double ux = (jx + 0.5 * fx) / rho, uy = (jy + 0.5 * fy) / rho, uz = (jz + 0.5 * fz) / rho;
-    const double om = 1.0 / R.tau, fp = 1.0 - 0.5 / R.tau;
-    const double uu = ux * ux + uy * uy + uz * uz;
-    const double uf = ux * fx + uy * fy + uz * fz;
+    if (R.lb_mode == HSF_LB_MRT) {
+        double ns[19];
+        mrt_collide(n, rho, ux, uy, uz, fx, fy, fz, R, ns);
 #pragma unroll
-    for (int q = 0; q < 19; ++q) {
-        const double cu = kCx[q] * ux + kCy[q] * uy + kCz[q] * uz;
-        const double cf = kCx[q] * fx + kCy[q] * fy + kCz[q] * fz;
-        const double wq = lb_weight(q);
-        const double neq = rho * wq * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        const double F = fp * wq * (3.0 * (cf - uf) + 9.0 * cu * cf);
-        const double ns = n[q] - om * (n[q] - neq) + F;
-        const int xd = wrap1(x + kCx[q], R.Lx), yd = wrap1(y + kCy[q], R.Ly), zd = wrap1(z + kCz[q], R.Lz);
-        ndst[base + q * V + sidx(R, xd, yd, zd)] = ns;
+        for (int q = 0; q < 19; ++q) {
+            const int xd = wrap1(x + kCx[q], R.Lx), yd = wrap1(y + kCy[q], R.Ly), zd = wrap1(z + kCz[q], R.Lz);
+            ndst[base + q * V + sidx(R, xd, yd, zd)] = ns[q];
+        }
+    } else {
+        const double om = 1.0 / R.tau, fp = 1.0 - 0.5 / R.tau;
+        const double uu = ux * ux + uy * uy + uz * uz;
+        const double uf = ux * fx + uy * fy + uz * fz;
+#pragma unroll
+        for (int q = 0; q < 19; ++q) {
+            const double cu = kCx[q] * ux + kCy[q] * uy + kCz[q] * uz;
+            const double cf = kCx[q] * fx + kCy[q] * fy + kCz[q] * fz;
+            const double wq = lb_w(q);
+            const double neq = rho * wq * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+            const double F = fp * wq * (3.0 * (cf - uf) + 9.0 * cu * cf);
+            const double ns = n[q] - om * (n[q] - neq) + F;
+            const int xd = wrap1(x + kCx[q], R.Lx), yd = wrap1(y + kCy[q], R.Ly), zd = wrap1(z + kCz[q], R.Lz);
+            ndst[base + q * V + sidx(R, xd, yd, zd)] = ns;
+        }
     }
     rho_out[R.site_off + i] = rho;
     u_out[vo + i] = ux;
@@ -192,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_lb_rest(const int *__restrict__ blk_
     const long long V = R.V, i = sr.i;
     if (i >= V) return;
 #pragma unroll
-    for (int q = 0; q < 19; ++q) n[19LL * R.site_off + q * V + i] = lb_weight(q);
+    for (int q = 0; q < 19; ++q) n[19LL * R.site_off + q * V + i] = lb_w(q);
 }
 
 void launch_mu(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi, const double *w,

@@ -20,6 +20,8 @@ struct Rep {
     double csum;            // c0 + 6 c1 + 12 c2 + 8 c3 (sigma applied to a constant 1)
     double chi[3][3];
     double kappa, dt, tau;
+    int lb_mode;            // HSF_LB_BGK or HSF_LB_MRT
+    double gamma_s, gamma_b, gamma_ghost;
 };
 
 // Per-replica scalars of an evaluation and of the conjugate-gradient inversion.

@@ -38,6 +38,7 @@ EXPORTED = [
 ]
 WARM_EXTRAP, WARM_NET, WARM_NET_DELTA, WARM_NET_EXTRAP = 2, 3, 4, 5
 SOLVER_PRECOND = 1
+LB_BGK, LB_MRT = 0, 1
 K_PREP, K_FWD, K_BWD, K_LB, K_CD, K_COUNT = 0, 1, 2, 3, 4, 5
 KERNEL_NAMES = ["prep", "fwd", "bwd", "lb", "cd"]
 
@@ -55,6 +56,8 @@ class Params(ctypes.Structure):
         ("has_solvent", ctypes.c_int), ("a", ctypes.c_double), ("stencil", ctypes.c_double * 4),
         ("chi", (ctypes.c_double * 3) * 3), ("kappa", ctypes.c_double), ("dt", ctypes.c_double),
         ("tau", ctypes.c_double), ("hydro", ctypes.c_int), ("precision", ctypes.c_int),
+        ("lb_mode", ctypes.c_int), ("gamma_s", ctypes.c_double), ("gamma_b", ctypes.c_double),
+        ("gamma_ghost", ctypes.c_double),
     ]
 
 
@@ -159,6 +162,8 @@ def params_from_workload(wl, precision=None):
     p.hydro = int(bool(wl.hydro))
     prec = precision or wl.precision
     p.precision = FP32 if prec == "fp32" else FP64
+    p.lb_mode = LB_MRT if wl.lb == "mrt" else LB_BGK
+    p.gamma_s, p.gamma_b, p.gamma_ghost = (float(v) for v in wl.gammas)
     return p
 
 

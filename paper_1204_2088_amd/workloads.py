@@ -45,6 +45,8 @@ class Workload:
     kappa: float = 10.0
     a: float = 1.1543
     hydro: bool = True
+    lb: str = "bgk"              # LB collision: "bgk" (tau) or "mrt" (gammas)
+    gammas: tuple = (0.0, 0.0, 0.0)   # MRT eigenvalues (shear, bulk, ghost)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -66,6 +68,14 @@ class Workload:
 
     def with_(self, **kw):
         return replace(self, **kw)
+
+
+def mrt_gammas(tau, tau_bulk=None, ghost=0.0):
+    """MRT eigenvalues with the shear viscosity of the BGK relaxation time tau
+    (gamma_s = 1 - 1/tau, nu = (tau - 1/2)/3), the bulk one from tau_bulk (default
+    tau) and the kinetic modes at `ghost` (0: relaxed completely every step)."""
+    tb = tau if tau_bulk is None else tau_bulk
+    return (1.0 - 1.0 / tau, 1.0 - 1.0 / tb, ghost)
 
 
 def chi_matrix(ab=0.0, as_=0.0, bs=0.0):

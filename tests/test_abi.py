@@ -55,3 +55,37 @@ def test_create_rejects_bad_parameters_without_gpu():
     arr = (hsf.Params * 2)(hsf.params_from_workload(wl), hsf.params_from_workload(wl, precision="fp32"))
     assert lib.hsf_create(arr, 2, ctypes.byref(h)) == hsf.HSF_EINVAL
     assert lib.hsf_create(arr, 0, ctypes.byref(h)) == hsf.HSF_EINVAL
+
+
+def test_param_structs_match_header(tmp_path):
+    """The ctypes structures of the binding have the sizes and field offsets of the
+    C declarations (compiled from include/hsf.h with the host C compiler)."""
+    import ctypes
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no host C compiler")
+    from paper_1204_2088_amd import hsf
+    structs = {"hsf_params": hsf.Params, "hsf_invert_stats": hsf.InvertStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hsf.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([gcc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln.strip():
+            parts = ln.split()
+            got[tuple(parts[:-1])] = int(parts[-1])
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -209,6 +209,60 @@ def test_lb_parity(hsf, orc, L, tau):
     assert abs(got.sum() / n.sum() - 1) < 1e-14
 
 
+@pytest.mark.parametrize("gammas", [(0.3, -0.2, 0.1), (-0.5, 0.4, -0.3), (0.0, 0.0, 0.0)])
+def test_lb_mrt_parity(hsf, orc, gammas):
+    """The multiple-relaxation-time collision of eq. 12-14 in the basis of Table 1,
+    with independent shear, bulk and kinetic-mode eigenvalues, against the oracle's."""
+    wl = small_melt(L=(9, 7, 11)).with_(lb="mrt", gammas=gammas)
+    sysw = osys(orc, wl)
+    sysw.lb_mode = 1
+    sysw.gamma_s, sysw.gamma_b, sysw.gamma_ghost = gammas
+    rng = np.random.default_rng(4)
+    n = orc.lb_rest_state(sysw) * (1 + 0.03 * rng.uniform(-1, 1, size=(19,) + wl.shape))
+    n = np.ascontiguousarray(n)
+    f = np.ascontiguousarray(2e-3 * rng.uniform(-1, 1, size=(3,) + wl.shape))
+    ctx = hsf.Context(wl)
+    ctx.set_lb(n.ravel())
+    ctx.lb_advance(3, f.ravel())
+    got = ctx.get_lb().reshape(n.shape)
+    rho, u = ctx.get_flow()
+    ref = n
+    for _ in range(3):
+        ref, rref, uref = orc.lb_step(sysw, ref, f)
+    e = np.max(np.abs(got - ref))
+    say(f"[lb mrt {gammas}] max |dn| {e:.2e}")
+    assert e < 1e-14
+    assert np.max(np.abs(rho.reshape(rref.shape) - rref)) < 1e-14
+    assert np.max(np.abs(u.reshape(uref.shape) - uref)) < 1e-15
+    assert abs(got.sum() / n.sum() - 1) < 1e-14
+
+
+def test_mrt_trajectory_fp64(hsf, orc):
+    """Ten coupled steps of the 16^3 A4B4 melt with the MRT collision (shear viscosity of
+    tau = 0.8, bulk eigenvalue of tau 1.2, kinetic modes relaxed completely), GPU
+    against the oracle in mirror mode."""
+    g = W.mrt_gammas(0.8, 1.2, 0.0)
+    wl = W.melt16_a4b4().with_(lb="mrt", gammas=g)
+    sysw = osys(orc, wl)
+    sysw.lb_mode = 1
+    sysw.gamma_s, sysw.gamma_b, sysw.gamma_ghost = g
+    phi = W.initial_composition(wl)
+    ctx = hsf.Context(wl)
+    ctx.set_densities(phi.ravel())
+    w = -np.log(phi / phi.mean(axis=(1, 2, 3), keepdims=True))
+    ctx.set_fields(w.ravel())
+    n = orc.lb_rest_state(sysw)
+    for k in range(10):
+        st, _ = ctx.step(1, tol=wl.tol, max_iter=1000)
+        phi, w, n, st_ref, u, rho, rc = orc.step(sysw, phi, w, n, tol=wl.tol, max_iter=1000,
+                                                 fixed_iters=st[0]["iterations"])
+        got = ctx.get_densities().reshape(phi.shape)
+        assert relerr(got, phi) < TOL64, k
+    ng = ctx.get_lb().reshape(n.shape)
+    assert np.max(np.abs(ng - n)) < 1e-13
+    say(f"[mrt trajectory] max |dn| after 10 steps {np.max(np.abs(ng - n)):.2e}")
+
+
 def test_cd_parity(hsf, orc):
     wl = small_solution(L=(10, 7, 12))
     rng = np.random.default_rng(2)
