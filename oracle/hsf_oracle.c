@@ -381,6 +381,92 @@ void orc_mu_force(const orc_sys *s, const double *phi, const double *w, double *
             }
 }
 
+/*
+ * Free-energy density v0 F / (kT V) of eq. 1 on the lattice (v0 = 1, kT = 1,
+ * integrals as site sums), at fields w and volume fractions phi:
+ *   F = -n_p ln Phi_p - n_s ln Phi_s + ln n_p! + ln n_s!
+ *       - sum_I sum_r phi_I w_I
+ *       + 1/2 sum_IJ chi_IJ sum_r phi_I sigma[phi_J]
+ *       + kappa/2 sum_r (sum_I phi_I - 1)^2
+ * with Phi_p = sum_r G_N(r) = V Q[w] (the single-chain partition function of the
+ * copolymer in the fields), Phi_s = sum_r exp(-w_S), n_p = phibar_p V / N chains
+ * and n_s = phibar_s V solvent beads (phibar from the given phi), ln n! = lgamma(n + 1).
+ * The interaction kernel is the linkage stencil with eps0_IJ = chi_IJ (the same
+ * reading as the chemical potential of eq. 4, which is the derivative of this F).
+ * Returns NAN on allocation failure.
+ */
+double orc_free_energy(const orc_sys *s, const double *w, const double *phi)
+{
+    long V = vol(s);
+    int ns = nsp(s);
+    double pbar_p = 0.0, pbar_s = 0.0;
+    for (long r = 0; r < V; ++r) {
+        for (int I = 0; I < s->n_poly; ++I) pbar_p += phi[(long)I * V + r];
+        if (s->has_solvent) pbar_s += phi[(long)s->n_poly * V + r];
+    }
+    pbar_p /= (double)V;
+    pbar_s /= (double)V;
+    double *tmp = malloc(sizeof(double) * V * ns);
+    double *sp = malloc(sizeof(double) * V * ns);
+    if (!tmp || !sp) {
+        free(tmp);
+        free(sp);
+        return NAN;
+    }
+    double q = NAN;
+    if (orc_evaluate(s, w, pbar_p, pbar_s, tmp, &q, NULL) != 0) q = NAN;
+    const double np = pbar_p * (double)V / (double)s->N, nsol = pbar_s * (double)V;
+    double F = -np * log((double)V * q) + lgamma(np + 1.0);
+    if (s->has_solvent) {
+        double zs = 0.0;
+        const double *wS = w + (long)s->n_poly * V;
+        for (long r = 0; r < V; ++r) zs += exp(-wS[r]);
+        F += -nsol * log(zs) + lgamma(nsol + 1.0);
+    }
+    for (int J = 0; J < ns; ++J) orc_sigma(s, phi + (long)J * V, sp + (long)J * V);
+    double fw = 0.0, fi = 0.0, fk = 0.0;
+    for (long r = 0; r < V; ++r) {
+        double tot = 0.0;
+        for (int I = 0; I < ns; ++I) {
+            const double pI = phi[(long)I * V + r];
+            tot += pI;
+            fw += pI * w[(long)I * V + r];
+            for (int J = 0; J < ns; ++J) fi += 0.5 * s->chi[I][J] * pI * sp[(long)J * V + r];
+        }
+        fk += 0.5 * s->kappa * (tot - 1.0) * (tot - 1.0);
+    }
+    F += -fw + fi + fk;
+    free(tmp);
+    free(sp);
+    return F / (double)V;
+}
+
+/*
+ * Order parameters of the composition phi [species][V] (phi^0_I: the spatial mean
+ * of phi_I): the melt's S = sqrt(V^-1 sum_r sum_I (phi_I - phi^0_I)^2) and the
+ * solution's S = V^-1 sum_r |phi_A + phi_B - phi^0_A - phi^0_B|.
+ */
+void orc_order_params(const orc_sys *s, const double *phi, double *s_melt, double *s_sol)
+{
+    long V = vol(s);
+    int ns = nsp(s);
+    double mean[3] = {0.0, 0.0, 0.0};
+    for (int I = 0; I < ns; ++I) {
+        for (long r = 0; r < V; ++r) mean[I] += phi[(long)I * V + r];
+        mean[I] /= (double)V;
+    }
+    double sq = 0.0, ab = 0.0;
+    for (long r = 0; r < V; ++r) {
+        for (int I = 0; I < ns; ++I) {
+            const double d = phi[(long)I * V + r] - mean[I];
+            sq += d * d;
+        }
+        ab += fabs(phi[r] + phi[V + r] - mean[0] - mean[1]);
+    }
+    *s_melt = sqrt(sq / (double)V);
+    *s_sol = ab / (double)V;
+}
+
 /* D3Q19 velocity set (rest, 6 faces, 12 edges) and weights of eq. 11. */
 static const int CV[19][3] = {
     {0, 0, 0},

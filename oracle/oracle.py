@@ -82,6 +82,10 @@ def _load():
         lib.orc_lb_step.argtypes = [S, _P, _P, _P, _P, _P]
         lib.orc_lb_equilibrium.argtypes = [ctypes.c_double, _P, _P]
         lib.orc_lb_velocity.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        lib.orc_free_energy.argtypes = [S, _P, _P]
+        lib.orc_free_energy.restype = ctypes.c_double
+        lib.orc_order_params.argtypes = [S, _P, _P, _P]
+        lib.orc_order_params.restype = None
         lib.orc_mrt_basis.argtypes = [ctypes.c_int, ctypes.c_int]
         lib.orc_mrt_basis.restype = ctypes.c_double
         lib.orc_cd_update.argtypes = [S, _P, _P, _P, _P]
@@ -197,6 +201,23 @@ def evaluate(sys: System, w, phibar_p=1.0, phibar_s=0.0, with_qs=False):
     if rc != 0:
         raise MemoryError("oracle evaluate failed")
     return (phi, q.value, qs) if with_qs else (phi, q.value)
+
+
+def free_energy(sys: System, w, phi):
+    """Free-energy density v0 F / (kT V) of eq. 1 at fields w and volume fractions phi."""
+    w = _arr(w, (sys.nsp,) + sys.shape)
+    phi = _arr(phi, (sys.nsp,) + sys.shape)
+    s = sys.cstruct()
+    return _load().orc_free_energy(ctypes.byref(s), _ptr(w), _ptr(phi))
+
+
+def order_params(sys: System, phi):
+    """(S of the melt, S of the solution) of the composition phi."""
+    phi = _arr(phi, (sys.nsp,) + sys.shape)
+    a, b = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    s = sys.cstruct()
+    _load().orc_order_params(ctypes.byref(s), _ptr(phi), ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def log_q(sys: System, w):

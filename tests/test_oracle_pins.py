@@ -593,3 +593,110 @@ def test_explicit_stability_limit_reading():
         ev = np.max(np.real(np.linalg.eigvals(Mlin)))
         worst = min(worst, 2.0 / ev)
     assert 0.01 < worst < 0.0155
+
+
+# ---- observables: free-energy density (eq. 1) and order parameters ---------------
+
+
+def test_free_energy_homogeneous_closed_form(orc):
+    """Homogeneous state, zero fields: Q = 1, so v0 F/(kT V) is the ideal translational
+    term plus the mean-field interaction of the bulk fractions (melt and solution)."""
+    from math import lgamma, log
+    for has_s, types, fr in ((False, W.chain(3, 5), (0.375, 0.625)), (True, W.chain(2, 4), (0.04, 0.08, 0.88))):
+        chi = W.chi_matrix(ab=1.7, as_=0.3, bs=2.9)
+        sys_ = orc.System(L=(5, 4, 6), types=types, has_solvent=has_s, chi=chi, kappa=10.0,
+                          c=orc.stencil_weights(1.1543))
+        V = 5 * 4 * 6
+        phi = np.empty((sys_.nsp,) + sys_.shape)
+        for I, f in enumerate(fr):
+            phi[I] = f
+        w = np.zeros_like(phi)
+        f = orc.free_energy(sys_, w, phi)
+        pp = fr[0] + fr[1]
+        npc = pp * V / len(types)
+        expect = -npc * log(V) + lgamma(npc + 1.0)
+        if has_s:
+            ns = fr[2] * V
+            expect += -ns * log(V) + lgamma(ns + 1.0)
+        inter = sum(0.5 * chi[I, J] * fr[I] * fr[J] for I in range(len(fr)) for J in range(len(fr)))
+        expect = expect / V + inter + 0.5 * 10.0 * (sum(fr) - 1.0) ** 2
+        assert abs(f - expect) < 1e-13 * max(1.0, abs(expect)), (has_s, f, expect)
+
+
+def test_free_energy_gauge_invariant(orc):
+    """A constant added to a polymer field changes ln Q and the sum of phi w by
+    amounts that cancel (catches a wrong sign or a missing chain count)."""
+    sys_ = orc.System(L=(6, 5, 4), types=W.chain(2, 3), has_solvent=True,
+                      chi=W.chi_matrix(ab=1.2, bs=2.0), c=orc.stencil_weights(1.1543))
+    w = W.random_fields((3,) + sys_.shape, seed=3, amplitude=0.8, smooth=1)
+    phi, _ = orc.evaluate(sys_, w, phibar_p=0.2, phibar_s=0.8)
+    f0 = orc.free_energy(sys_, w, phi)
+    w2 = w.copy()
+    w2[0] += 0.37
+    w2[1] -= 1.1
+    w2[2] += 0.6
+    f1 = orc.free_energy(sys_, w2, phi)
+    assert abs(f1 - f0) < 1e-12 * max(1.0, abs(f0))
+
+
+def test_free_energy_derivative_is_chemical_potential(orc):
+    """At self-consistent fields w[phi] the derivative of F along a composition
+    change eta (each species' total fixed) is sum_I sum_r mu_I eta_I with mu the
+    chemical potential of eq. 4: central differences of F with the fields re-inverted
+    at phi +- eps eta."""
+    types = W.chain(2, 2)
+    sys_ = orc.System(L=(6, 6, 6), types=types, chi=W.chi_matrix(ab=1.4), kappa=10.0,
+                      c=orc.stencil_weights(1.1543))
+    wt = W.random_fields((2,) + sys_.shape, seed=5, amplitude=0.5, smooth=2)
+    phi, _ = orc.evaluate(sys_, wt, phibar_p=1.0)
+    eta = W.random_fields((2,) + sys_.shape, seed=6, amplitude=1.0, smooth=2)
+    eta -= eta.mean(axis=(1, 2, 3), keepdims=True)
+
+    def F_at(p):
+        w0 = -np.log(p / p.mean(axis=(1, 2, 3), keepdims=True))
+        w, st, rc = orc.invert(sys_, p, w0, tol=1e-13, max_iter=5000)
+        assert rc == 0, st
+        return orc.free_energy(sys_, w, p) * sys_.V, w
+
+    eps = 1e-4
+    fp, _ = F_at(phi + eps * eta)
+    fm, _ = F_at(phi - eps * eta)
+    _, w = F_at(phi)
+    mu, _ = orc.mu_force(sys_, phi, w)
+    d_fd = (fp - fm) / (2 * eps)
+    d_mu = float(np.sum(mu * eta))
+    assert abs(d_fd - d_mu) < 1e-6 * max(1.0, abs(d_mu)), (d_fd, d_mu)
+
+
+def test_order_parameters_single_mode(orc):
+    """phi_A = 1/2 + A cos(k x), phi_B = 1 - phi_A: the melt order parameter (rms of the
+    deviations from the species means, summed over species) is A, since each species
+    contributes A^2/2 to the mean square; the solution order parameter (mean |deviation|
+    of phi_A + phi_B) is 0 because the copolymer total is constant.  A homogeneous state
+    gives 0 for both."""
+    sys_ = orc.System(L=(8, 3, 2), types=W.chain(2, 2), c=orc.stencil_weights(1.1543))
+    A = 0.07
+    x = np.arange(8)
+    phi = np.empty((2,) + sys_.shape)
+    phi[0] = (0.5 + A * np.cos(2 * np.pi * x / 8))[None, None, :]
+    phi[1] = 1.0 - phi[0]
+    s_melt, s_sol = orc.order_params(sys_, phi)
+    assert abs(s_melt - A) < 1e-15
+    assert s_sol < 1e-15
+    assert orc.order_params(sys_, np.full((2,) + sys_.shape, 0.5)) == (0.0, 0.0)
+
+
+def test_order_parameters_solution_mode(orc):
+    """Solution with phi_A = 0.1 + B cos(2 pi x / 8), phi_B = 0.1 and the solvent taking
+    the rest: the copolymer total deviates by B cos, whose mean modulus over the eight
+    planes is B (1 + sqrt 2) / 4; the rms order parameter over the three species is B."""
+    sys_ = orc.System(L=(8, 2, 3), types=W.chain(1, 2), has_solvent=True, c=orc.stencil_weights(1.1543))
+    B = 0.03
+    x = np.arange(8)
+    phi = np.empty((3,) + sys_.shape)
+    phi[0] = (0.1 + B * np.cos(2 * np.pi * x / 8))[None, None, :]
+    phi[1] = 0.1
+    phi[2] = 1.0 - phi[0] - phi[1]
+    s_melt, s_sol = orc.order_params(sys_, phi)
+    assert abs(s_melt - B) < 1e-15
+    assert abs(s_sol - B * (1 + np.sqrt(2)) / 4) < 1e-15
