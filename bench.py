@@ -190,6 +190,30 @@ def run_arm(hsf, torch, wls, steps, warmup, timing, log, precond=False, tile=Non
     return ctx, tile, tune_ms, stats, (evals, site_evals), elapsed, timing_out, t_steps, t_elapsed
 
 
+def measure_observables(ctx, torch, wl, V_total, reps=10):
+    """Free-energy density and order parameters of the final state, and the cost of the
+    call: each runs one evaluation (for Q) and two FP64 site passes, so the passes cost
+    the difference to a plain evaluation.  Algorithmic bytes of the passes: phi and w
+    once, then phi again (3 nsp doubles per site)."""
+    out_dev = torch.empty(ctx.nsp * ctx.T, dtype=torch.float64, device="cuda")
+    res = {}
+    for name, fn in (("observables", ctx.observables), ("evaluate", lambda: ctx.evaluate(out=out_dev))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = 1e3 * (time.perf_counter() - t0) / reps
+    f, sm, ss = ctx.observables()
+    pass_ms = max(res["observables"] - res["evaluate"], 1e-9)
+    pass_bytes = 3 * wl.nsp * 8 * V_total
+    return {"free_energy": f.tolist()[:8], "s_melt": sm.tolist()[:8], "s_sol": ss.tolist()[:8],
+            "ms_per_call": res["observables"], "evaluate_ms_per_call": res["evaluate"],
+            "passes_ms": pass_ms, "passes_algorithmic_bytes": pass_bytes,
+            "passes_gbs": pass_bytes / (pass_ms * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +326,8 @@ def main():
                         "algorithmic_bytes_per_launch": b_unit * units,
                         "bytes_per_update": b_unit, "updates_per_launch": units}
 
+    observables = measure_observables(ctx, torch, wl, V_total)
+
     cpu = None
     if not args.no_cpu_baseline:
         nsp = wl.nsp
@@ -354,6 +380,7 @@ def main():
         "roofline": roofline,
         "fp64_arm": fp64_arm,
         "learned_warm_start": learned,
+        "observables": observables,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -170,6 +170,24 @@ int hsf_get_densities(hsf_ctx *ctx, double *phi, int where);
  * state.  phi_out uses the field layout. */
 int hsf_evaluate(hsf_ctx *ctx, double *phi_out, double *Q_out, int where);
 
+/* Observables of the current state (w, phi), n_rep values each (host memory, any
+ * may be NULL):
+ *   free_energy: the free-energy density v0 F / (kT V) of eq. 1 on the lattice,
+ *     -n_p ln(V Q[w]) + ln n_p! - n_s ln sum_r exp(-w_S) + ln n_s!
+ *     - sum_I sum_r phi_I w_I + 1/2 sum_IJ chi_IJ sum_r phi_I sigma[phi_J]
+ *     + kappa/2 sum_r (sum_I phi_I - 1)^2, all over V, with n_p = phibar_p V / N,
+ *     n_s = phibar_s V (phibar from phi) and sigma the linkage stencil; at
+ *     self-consistent fields its derivative with respect to phi_I is the chemical
+ *     potential of eq. 4;
+ *   s_melt: sqrt(V^-1 sum_r sum_I (phi_I - <phi_I>)^2), the rms composition
+ *     deviation (the melt's order parameter);
+ *   s_sol: V^-1 sum_r |phi_A + phi_B - <phi_A> - <phi_B>|, the mean deviation of
+ *     the copolymer total (the solution's order parameter).
+ * Runs one density-functional evaluation (as hsf_evaluate) for Q and <exp(-w_S)>;
+ * Q is computed with the context's propagator precision, the sums in FP64.
+ * Does not change the state.  HSF_ENONFINITE when Q is not finite. */
+int hsf_observables(hsf_ctx *ctx, double *free_energy, double *s_melt, double *s_sol);
+
 /* Self-consistent fields for the current densities (section 2: Fletcher-Reeves
  * nonlinear conjugate gradients on the convex objective whose gradient is
  * phi^t - phi[w]).  The solvent field is set in closed form; polymer fields are

@@ -46,6 +46,7 @@ struct hsf_ctx {
     double *nA = nullptr, *nB = nullptr, *rho = nullptr, *u = nullptr, *force = nullptr, *uin = nullptr;
     double *part = nullptr, *partG = nullptr;
     int part_cap = 0;                  // doubles in `part`
+    double *obs = nullptr;             // observables scratch; results in its last 3 n_rep doubles
     // propagators in the chosen precision
     void *E = nullptr, *G = nullptr, *Gp0 = nullptr, *Gp1 = nullptr;
     std::vector<void *> allocs;
@@ -511,6 +512,35 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
     return status;
 }
 
+// One evaluation of the density functional at the current fields, with phibar from the
+// current densities, into eval_out; ln Q, phibar and <exp(-w_S)> stay in the replica
+// states.  An evaluation whose propagators left the floating-point range is repeated
+// with the per-step scales it adapted (at most three more times).
+int evaluate_impl(hsf_ctx *c)
+{
+    hipStream_t s = c->stream;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        int rc0 = run_seq(c, hsf_ctx::GK_EVAL, [&] {
+            target_setup(c, 0.0, 0);   // phibar_p, phibar_s from the current densities; all replicas active
+            run_eval_any(c, 0, 0, c->eval_out, nullptr, 1);
+            launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_SCALES, c->ch,
+                              c->partG, 0.0, 0, c->st_hd);
+        });
+        if (rc0) return rc0;
+        if ((rc0 = read_status(c))) return rc0;
+        bool bad = false;
+        for (int r = 0; r < c->n_rep; ++r) bad |= c->st_h[r].nonfinite != 0;
+        if (!bad) break;
+    }
+    if (c->ch.nsp == 3) {
+        launch_solvent(s, c->plan, c->rep_d, c->st_d, c->ch, 0, c->w, c->phi, c->eval_out, c->part);
+        launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_SOLVENT, c->ch, c->partG, 0.0, 0, c->st_hd);
+        launch_solvent(s, c->plan, c->rep_d, c->st_d, c->ch, 1, c->w, c->phi, c->eval_out, c->part);
+    }
+    HIPCHK(c, hipGetLastError());
+    return HSF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -641,6 +671,7 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     ALLOC(c->net_in, sizeof(float) * 2 * nsp * T);
     ALLOC(c->net_pred, sizeof(float) * 2 * T);
     ALLOC(c->net_rms, sizeof(double) * n_rep);
+    ALLOC(c->obs, sizeof(double) * observables_scratch_doubles(n_rep));
 #undef ALLOC
     if (rc == HSF_OK) {
         hipError_t e = hipHostMalloc((void **)&c->st_h, sizeof(RepState) * n_rep, hipHostMallocDefault);
@@ -772,34 +803,33 @@ int hsf_evaluate(hsf_ctx *c, double *phi_out, double *Q_out, int where)
 {
     if (!c) return HSF_EINVAL;
     if (!phi_out) return fail(c, HSF_EINVAL, "null output");
-    hipStream_t s = c->stream;
-    // An evaluation whose propagators left the floating-point range is repeated
-    // with the per-step scales it adapted (at most three more times).
-    for (int attempt = 0; attempt < 4; ++attempt) {
-        int rc0 = run_seq(c, hsf_ctx::GK_EVAL, [&] {
-            target_setup(c, 0.0, 0);   // phibar_p, phibar_s from the current densities; all replicas active
-            run_eval_any(c, 0, 0, c->eval_out, nullptr, 1);
-            launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_SCALES, c->ch,
-                              c->partG, 0.0, 0, c->st_hd);
-        });
-        if (rc0) return rc0;
-        if ((rc0 = read_status(c))) return rc0;
-        bool bad = false;
-        for (int r = 0; r < c->n_rep; ++r) bad |= c->st_h[r].nonfinite != 0;
-        if (!bad) break;
-    }
-    if (c->ch.nsp == 3) {
-        launch_solvent(s, c->plan, c->rep_d, c->st_d, c->ch, 0, c->w, c->phi, c->eval_out, c->part);
-        launch_reduce_ctl(s, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_SOLVENT, c->ch, c->partG, 0.0, 0, c->st_hd);
-        launch_solvent(s, c->plan, c->rep_d, c->st_d, c->ch, 1, c->w, c->phi, c->eval_out, c->part);
-    }
-    HIPCHK(c, hipGetLastError());
-    int rc = copy_out(c, phi_out, c->eval_out, (size_t)c->ch.nsp * c->T, where);
+    int rc = evaluate_impl(c);
     if (rc) return rc;
+    if ((rc = copy_out(c, phi_out, c->eval_out, (size_t)c->ch.nsp * c->T, where))) return rc;
     if ((rc = read_status(c))) return rc;
     for (int r = 0; r < c->n_rep; ++r) {
         if (Q_out) Q_out[r] = exp(c->st_h[r].ln_q);
         if (c->st_h[r].nonfinite) return fail(c, HSF_ENONFINITE, "non-finite Q in replica %d", r);
+    }
+    return HSF_OK;
+}
+
+int hsf_observables(hsf_ctx *c, double *free_energy, double *s_melt, double *s_sol)
+{
+    if (!c) return HSF_EINVAL;
+    int rc = evaluate_impl(c);
+    if (rc) return rc;
+    double *out = c->obs + observables_scratch_doubles(c->n_rep) - 3 * (size_t)c->n_rep;
+    launch_observables(c->stream, c->plan, c->n_rep, c->rep_d, c->st_d, c->ch, c->w, c->phi, c->part, c->obs, out);
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> h(3 * (size_t)c->n_rep);
+    if ((rc = copy_out(c, h.data(), out, h.size(), HSF_HOST))) return rc;
+    if ((rc = read_status(c))) return rc;
+    for (int r = 0; r < c->n_rep; ++r) {
+        if (c->st_h[r].nonfinite) return fail(c, HSF_ENONFINITE, "non-finite Q in replica %d", r);
+        if (free_energy) free_energy[r] = h[3 * r];
+        if (s_melt) s_melt[r] = h[3 * r + 1];
+        if (s_sol) s_sol[r] = h[3 * r + 2];
     }
     return HSF_OK;
 }

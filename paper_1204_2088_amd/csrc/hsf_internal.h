@@ -118,6 +118,13 @@ void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const dou
                hipEvent_t e1 = nullptr);
 void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n);
 
+// observables: the free-energy density and order parameters of (w, phi) into
+// out[3 r .. 3 r + 2]; uses the Q, phibar and <exp(-w_S)> of the last evaluation in st.
+// scratch holds observables_scratch_doubles(n_rep) doubles (out may point into its tail).
+void launch_observables(hipStream_t s, const Plan &p, int n_rep, const Rep *rep, const RepState *st, Chain ch,
+                        const double *w, const double *phi, double *part, double *scratch, double *out);
+size_t observables_scratch_doubles(int n_rep);
+
 }  // namespace hsf
 
 struct hsf_net;

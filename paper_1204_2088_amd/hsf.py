@@ -28,7 +28,7 @@ WARM_CURRENT, WARM_LOCAL = 0, 1
 EXPORTED = [
     "hsf_create", "hsf_destroy", "hsf_last_error", "hsf_set_stream", "hsf_total_sites",
     "hsf_site_offset", "hsf_field_offset", "hsf_num_species", "hsf_set_fields", "hsf_get_fields",
-    "hsf_set_densities", "hsf_get_densities", "hsf_evaluate", "hsf_invert", "hsf_mu_force",
+    "hsf_set_densities", "hsf_get_densities", "hsf_evaluate", "hsf_observables", "hsf_invert", "hsf_mu_force",
     "hsf_set_lb", "hsf_get_lb", "hsf_lb_advance", "hsf_get_flow", "hsf_cd_advance", "hsf_step",
     "hsf_set_hydro", "hsf_set_timing", "hsf_get_timing", "hsf_set_tile", "hsf_get_tile", "hsf_autotune",
     "hsf_set_solver", "hsf_get_work", "hsf_set_warm", "hsf_net_create", "hsf_net_destroy",
@@ -102,6 +102,7 @@ def load():
         "hsf_set_densities": ([C, P, I], I),
         "hsf_get_densities": ([C, P, I], I),
         "hsf_evaluate": ([C, P, P, I], I),
+        "hsf_observables": ([C, P, P, P], I),
         "hsf_invert": ([C, ctypes.c_double, I, I, ctypes.POINTER(InvertStats)], I),
         "hsf_mu_force": ([C, P, P, I], I),
         "hsf_set_lb": ([C, P, I], I),
@@ -286,6 +287,14 @@ class Context:
         p, where = _ptr(out, self.nsp * self.T)
         self._check(self._lib.hsf_evaluate(self._h, p, q, where))
         return out, np.array(q[:])
+
+    def observables(self):
+        """Free-energy density (eq. 1), melt and solution order parameters per replica."""
+        f = (ctypes.c_double * self.n_rep)()
+        sm = (ctypes.c_double * self.n_rep)()
+        ss = (ctypes.c_double * self.n_rep)()
+        self._check(self._lib.hsf_observables(self._h, f, sm, ss))
+        return np.array(f[:]), np.array(sm[:]), np.array(ss[:])
 
     def invert(self, tol=1e-8, max_iter=1000, warm=WARM_CURRENT, allow_noconv=False):
         st = (InvertStats * self.n_rep)()

@@ -700,3 +700,24 @@ def test_order_parameters_solution_mode(orc):
     s_melt, s_sol = orc.order_params(sys_, phi)
     assert abs(s_melt - B) < 1e-15
     assert abs(s_sol - B * (1 + np.sqrt(2)) / 4) < 1e-15
+
+
+def test_free_energy_decreases_under_diffusion(orc):
+    """Without convection the composition dynamics of eq. 3 relaxes the free energy:
+    along the oracle's coupled steps (hydrodynamics off) F at self-consistent fields
+    never increases (at these early times the short-wavelength part of the initial
+    noise decays, so the order parameter need not grow)."""
+    wl = W.Workload("pin", (8, 8, 8), W.chain(4, 4), False, W.chi_matrix(ab=20 / 8), tau=1.0, noise=0.01,
+                    seed=0, precision="fp64")
+    sys_ = orc.System(L=wl.L, types=wl.types, chi=wl.chi, kappa=wl.kappa, dt=wl.dt, tau=wl.tau, hydro=0,
+                      c=orc.stencil_weights(wl.a))
+    phi = W.initial_composition(wl)
+    w = -np.log(phi / phi.mean(axis=(1, 2, 3), keepdims=True))
+    fs = []
+    for _ in range(20):
+        phi, w, _, st, _, _, rc = orc.step(sys_, phi, w, tol=1e-10, max_iter=3000)
+        assert rc == 0, st
+        ws, st, rc = orc.invert(sys_, phi, w, tol=1e-11, max_iter=3000)
+        assert rc == 0, st
+        fs.append(orc.free_energy(sys_, ws, phi))
+    assert np.all(np.diff(fs) < 0.0), np.diff(fs)
