@@ -41,6 +41,11 @@ typedef struct {
     int lb_mode;                 /* 0: BGK + Guo forcing, 1: MRT (Table 1)    */
     int hydro;                   /* 1: convection by the LB velocity          */
     int precond;                 /* 1: inversion preconditioned by diag(phi^t) */
+    int noise;                   /* bit 0: composition noise (eq. 5), bit 1: LB mode noise (eq. 13) */
+    double omega;                /* noise scaling parameter Omega = h^3 / v0 (sec. 3) */
+    unsigned long long seed;     /* generator key, first word */
+    unsigned long long rep;      /* generator key, second word (replica index) */
+    unsigned long long step;     /* time-step word of the generator counter */
 } orc_sys;
 
 typedef struct {
@@ -467,6 +472,71 @@ void orc_order_params(const orc_sys *s, const double *phi, double *s_melt, doubl
     *s_sol = ab / (double)V;
 }
 
+/*
+ * Counter-based random numbers for the thermal noise: Philox4x64 with 10 rounds
+ * (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+ * SC11).  A round multiplies counter words 0 and 2 by two fixed odd constants
+ * (128-bit products), and forms the new words from the high halves xored with
+ * words 1 / 3 and the round key, and the low halves; the key is advanced by two
+ * Weyl increments between rounds.
+ */
+typedef unsigned long long u64;
+
+static void mulhilo64(u64 a, u64 b, u64 *hi, u64 *lo)
+{
+    unsigned __int128 p = (unsigned __int128)a * b;
+    *hi = (u64)(p >> 64);
+    *lo = (u64)p;
+}
+
+void orc_philox4x64(const u64 ctr[4], const u64 key[2], u64 out[4])
+{
+    const u64 M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const u64 W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    u64 x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3], k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        u64 h0, l0, h1, l1;
+        mulhilo64(M0, x0, &h0, &l0);
+        mulhilo64(M1, x2, &h1, &l1);
+        const u64 y0 = h1 ^ x1 ^ k0, y1 = l1, y2 = h0 ^ x3 ^ k1, y3 = l0;
+        x0 = y0;
+        x1 = y1;
+        x2 = y2;
+        x3 = y3;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+/*
+ * Four independent standard normal numbers for (site, purpose) of the current
+ * step: key (seed, rep), counter (site, step, purpose, 0); the four 64-bit words
+ * give two Box-Muller pairs, the radius from u1 = (top 53 bits + 1) 2^-53 in (0, 1]
+ * and the angle 2 pi u2 with u2 = (top 53 bits) 2^-53 in [0, 1).
+ * Purposes: 0-3 the LB modes 4-18 (mode k takes number k - 4), 4 + I the bonds
+ * (x, y, z) of species I.
+ */
+void orc_normals(const orc_sys *s, u64 site_index, u64 purpose, double z[4])
+{
+    const u64 ctr[4] = {site_index, s->step, purpose, 0ULL}, key[2] = {s->seed, s->rep};
+    u64 r[4];
+    orc_philox4x64(ctr, key, r);
+    const double two53 = 1.0 / 9007199254740992.0;
+    for (int p = 0; p < 2; ++p) {
+        const double u1 = (double)((r[2 * p] >> 11) + 1ULL) * two53;
+        const double u2 = (double)(r[2 * p + 1] >> 11) * two53;
+        const double rad = sqrt(-2.0 * log(u1)), ang = 6.283185307179586 * u2;
+        z[2 * p] = rad * cos(ang);
+        z[2 * p + 1] = rad * sin(ang);
+    }
+}
+
 /* D3Q19 velocity set (rest, 6 faces, 12 edges) and weights of eq. 11. */
 static const int CV[19][3] = {
     {0, 0, 0},
@@ -538,7 +608,9 @@ double orc_mrt_basis(int k, int i) { return basis(k, i); }
  *   of Table 1, gamma_0..3 = 1, gamma_4 = gamma_b, gamma_5..9 = gamma_s, the
  *   kinetic (ghost) modes gamma_10..18 = gamma_ghost, and no mode noise.
  */
-static void collide(const orc_sys *s, const double n[19], const double f[3], double nout[19],
+static void lb_noise(const orc_sys *s, long r, double rho, double nout[19]);
+
+static void collide(const orc_sys *s, long r, const double n[19], const double f[3], double nout[19],
                     double *rho_out, double u[3])
 {
     double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -560,6 +632,7 @@ static void collide(const orc_sys *s, const double n[19], const double f[3], dou
             double neq = equilibrium(i, rho, u);
             nout[i] = n[i] - (n[i] - neq) / tau + F;
         }
+        if (s->noise & 2) lb_noise(s, r, rho, nout);
         return;
     }
     double gk[19];
@@ -601,6 +674,37 @@ static void collide(const orc_sys *s, const double n[19], const double f[3], dou
         for (int k = 0; k < 19; ++k) acc += mstar[k] * basis(k, i) / bk[k];
         nout[i] = neq[i] + wgt(i) * acc;
     }
+    if (s->noise & 2) lb_noise(s, r, rho, nout);
+}
+
+/*
+ * Mode noise of eq. 13 added to the post-collision populations of site r: mode
+ * k >= 4 of the Table 1 basis receives phi_k r_k with
+ * phi_k = sqrt(rho kT b_k (1 - gamma_k^2) / c_s^2) (h = 1), which the reconstruction
+ * n_i = n_eq + w_i sum_k m_k e_ki / b_k carries to the populations.  gamma_k as in
+ * the collision (BGK: 1 - 1/tau for every non-conserved mode).  kT in LB units is
+ * dt^2 / Omega (mass unit m0 h^3 / v0 with LB density 1, time unit the step, and
+ * m0 = kT tau^2 / h^2 of sec. 3).  A negative density gives no noise.
+ */
+static void lb_noise(const orc_sys *s, long r, double rho, double nout[19])
+{
+    const double kT = s->dt * s->dt / s->omega, cs2 = 1.0 / 3.0;
+    double z[16];
+    for (int p = 0; p < 4; ++p) orc_normals(s, (u64)r, (u64)p, z + 4 * p);
+    double amp[19];
+    for (int k = 4; k < 19; ++k) {
+        double g = s->lb_mode == 0 ? 1.0 - 1.0 / s->tau
+                                   : (k == 4 ? s->gamma_b : (k <= 9 ? s->gamma_s : s->gamma_ghost));
+        double b = 0.0;
+        for (int i = 0; i < 19; ++i) b += wgt(i) * basis(k, i) * basis(k, i);
+        const double phik = sqrt(fmax(rho, 0.0) * kT * b * (1.0 - g * g) / cs2);
+        amp[k] = phik * z[k - 4] / b;
+    }
+    for (int i = 0; i < 19; ++i) {
+        double acc = 0.0;
+        for (int k = 4; k < 19; ++k) acc += amp[k] * basis(k, i);
+        nout[i] += wgt(i) * acc;
+    }
 }
 
 /*
@@ -621,7 +725,7 @@ void orc_lb_step(const orc_sys *s, const double *n, const double *f, double *nou
                 for (int i = 0; i < 19; ++i) nl[i] = n[(long)i * V + r];
                 if (f)
                     for (int a = 0; a < 3; ++a) fl[a] = f[(long)a * V + r];
-                collide(s, nl, fl, ns_, &rl, ul);
+                collide(s, r, nl, fl, ns_, &rl, ul);
                 for (int i = 0; i < 19; ++i)
                     nout[(long)i * V + site(s, x + CV[i][0], y + CV[i][1], z + CV[i][2])] = ns_[i];
                 if (rho) rho[r] = rl;
@@ -643,6 +747,15 @@ void orc_lb_step(const orc_sys *s, const double *n, const double *f, double *nou
  *   phi_new(r) = phi(r) - sum_a [ dt (J^D(r+) - J^D(r-)) + (J^C(r+) - J^C(r-)) ]
  * u is the LB velocity, i.e. the displacement per step in lattice units.
  * phi, mu, phi_out: [species][V]; u: [3][V] or NULL (no convection).
+ *
+ * Composition noise (noise bit 0), eq. 5 with M = kT = 1: the cited algorithm for
+ * xi_I is not reproduced in the paper; reading: a random flux on every bond, the one
+ * between r and r + e_a owned by r,
+ *   J^N = sqrt(2 dt max(phi_bond, 0) / Omega) g,  phi_bond = (phi(r) + phi(r+e)) / 2,
+ * with g the species' standard normal number for that bond, added to the face flux.
+ * Its divergence has the covariance (2 dt / Omega) (-div phi grad) of eq. 5 integrated
+ * over a step (delta(r - r') = 1 / h^3 on the lattice and phi = rho v0 give the factor
+ * v0 / h^3 = 1 / Omega), and it conserves each species' amount exactly.
  */
 void orc_cd_update(const orc_sys *s, const double *phi, const double *mu, const double *u, double *phi_out)
 {
@@ -656,6 +769,8 @@ void orc_cd_update(const orc_sys *s, const double *phi, const double *mu, const 
                 for (int x = 0; x < s->Lx; ++x) {
                     long r = site(s, x, y, z);
                     double div = 0.0;
+                    double zr[4] = {0.0, 0.0, 0.0, 0.0};
+                    if (s->noise & 1) orc_normals(s, (u64)r, (u64)(4 + I), zr);
                     for (int a = 0; a < 3; ++a) {
                         int e[3] = {a == 0, a == 1, a == 2};
                         /* faces r - e/2 (between rm and r) and r + e/2 (between r and rp) */
@@ -673,6 +788,16 @@ void orc_cd_update(const orc_sys *s, const double *phi, const double *mu, const 
                                 jc = half * 0.5 * (ua + ub);
                             }
                             J[side] = s->dt * jd + jc;
+                            if (s->noise & 1) {
+                                /* the bond's number belongs to its lower site A */
+                                double g = zr[a];
+                                if (side == 0) {
+                                    double zo[4];
+                                    orc_normals(s, (u64)A, (u64)(4 + I), zo);
+                                    g = zo[a];
+                                }
+                                J[side] += sqrt(2.0 * s->dt * fmax(0.5 * (p[A] + p[B]), 0.0) / s->omega) * g;
+                            }
                         }
                         div += J[1] - J[0];
                     }

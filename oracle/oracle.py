@@ -46,6 +46,8 @@ class _Sys(ctypes.Structure):
         ("gamma_b", ctypes.c_double), ("gamma_s", ctypes.c_double),
         ("gamma_ghost", ctypes.c_double), ("lb_mode", ctypes.c_int), ("hydro", ctypes.c_int),
         ("precond", ctypes.c_int),
+        ("noise", ctypes.c_int), ("omega", ctypes.c_double), ("seed", ctypes.c_ulonglong),
+        ("rep", ctypes.c_ulonglong), ("step", ctypes.c_ulonglong),
     ]
 
 
@@ -92,6 +94,11 @@ def _load():
         lib.orc_step.argtypes = [S, _P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                  ctypes.POINTER(InvertStats), _P, _P]
         lib.orc_step.restype = ctypes.c_int
+        U64 = ctypes.POINTER(ctypes.c_ulonglong)
+        lib.orc_philox4x64.argtypes = [U64, U64, U64]
+        lib.orc_philox4x64.restype = None
+        lib.orc_normals.argtypes = [S, ctypes.c_ulonglong, ctypes.c_ulonglong, _P]
+        lib.orc_normals.restype = None
         _lib = lib
     return _lib
 
@@ -127,6 +134,11 @@ class System:
     lb_mode: int = 0
     hydro: bool = True
     precond: bool = False
+    noise: int = 0                # bit 0: composition noise (eq. 5), bit 1: LB mode noise (eq. 13)
+    omega: float = 400.0          # noise scaling parameter Omega = h^3 / v0
+    seed: int = 0                 # generator key word 0
+    rep: int = 0                  # generator key word 1 (replica index)
+    step: int = 0                 # generator counter word 1 (time step)
 
     @property
     def V(self):
@@ -172,6 +184,9 @@ class System:
         s.lb_mode = int(self.lb_mode)
         s.hydro = int(bool(self.hydro))
         s.precond = int(bool(self.precond))
+        s.noise = int(self.noise)
+        s.omega = float(self.omega)
+        s.seed, s.rep, s.step = int(self.seed), int(self.rep), int(self.step)
         return s
 
 
@@ -307,6 +322,23 @@ def step(sys: System, phi, w, n=None, tol=1e-8, max_iter=1000, fixed_iters=0):
     if rc < 0:
         raise MemoryError("oracle step failed")
     return phi, w, n, st.as_dict(), u, rho, rc
+
+
+def philox4x64(ctr, key):
+    """Philox4x64-10 of the 4-word counter and 2-word key (four 64-bit words)."""
+    c = (ctypes.c_ulonglong * 4)(*[int(v) for v in ctr])
+    k = (ctypes.c_ulonglong * 2)(*[int(v) for v in key])
+    o = (ctypes.c_ulonglong * 4)()
+    _load().orc_philox4x64(c, k, o)
+    return [int(v) for v in o]
+
+
+def normals(sys: System, site, purpose):
+    """The four standard normal numbers of (site, purpose) at the system's step."""
+    z = np.empty(4)
+    s = sys.cstruct()
+    _load().orc_normals(ctypes.byref(s), int(site), int(purpose), _ptr(z))
+    return z
 
 
 def lb_rest_state(sys: System, rho0=1.0):

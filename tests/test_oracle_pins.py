@@ -721,3 +721,188 @@ def test_free_energy_decreases_under_diffusion(orc):
         assert rc == 0, st
         fs.append(orc.free_energy(sys_, ws, phi))
     assert np.all(np.diff(fs) < 0.0), np.diff(fs)
+
+
+# ---- thermal noise: generator, LB mode noise (eq. 13), composition noise (eq. 5) ----
+
+
+def test_philox_matches_numpy(orc):
+    """The oracle's Philox4x64-10 against numpy's implementation of the same published
+    generator (numpy advances its 256-bit counter by one before the first block)."""
+    M = (1 << 64) - 1
+    cases = [((1, 0, 0, 0), (0, 0)), ((5, 7, 9, 11), (1, 2)), ((12345, 1 << 63, 3, M), (M, 42)),
+             ((0, 9, 4, 0), (0xDEADBEEF, 17))]
+    for ctr, key in cases:
+        start = [ctr[0] - 1, ctr[1], ctr[2], ctr[3]] if ctr[0] else [M, ctr[1] - 1, ctr[2], ctr[3]]
+        bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(start, dtype=np.uint64))
+        assert orc.philox4x64(ctr, key) == [int(v) for v in bg.random_raw(4)], (ctr, key)
+
+
+def test_normals_are_standard_and_independent(orc):
+    """Box-Muller numbers of 20000 (site, purpose) counters: standard normal by the
+    Kolmogorov-Smirnov test, first moments within sampling error, the four numbers of a
+    call and numbers of neighbouring counters uncorrelated, and distinct keys and steps
+    give different numbers."""
+    from scipy import stats
+    s = orc.System(L=(4, 4, 4), types=W.chain(1, 1), seed=7, rep=1, step=3)
+    z = np.array([orc.normals(s, site, p) for site in range(10000) for p in (0, 4)])
+    flat = z.ravel()
+    n = flat.size
+    assert abs(flat.mean()) < 5 / np.sqrt(n)
+    assert abs(flat.var() - 1) < 5 * np.sqrt(2 / n)
+    assert stats.kstest(flat, "norm").pvalue > 1e-4
+    c = np.corrcoef(np.concatenate([z[0::2], z[1::2]], axis=1).T)
+    assert np.max(np.abs(c - np.eye(8))) < 6 / np.sqrt(z.shape[0] / 2)
+    base = orc.normals(s, 5, 0)
+    for kw in ({"seed": 8}, {"rep": 2}, {"step": 4}):
+        other = orc.System(L=(4, 4, 4), types=W.chain(1, 1), **{**{"seed": 7, "rep": 1, "step": 3}, **kw})
+        assert not np.allclose(orc.normals(other, 5, 0), base)
+    assert not np.allclose(orc.normals(s, 6, 0), base) and not np.allclose(orc.normals(s, 5, 1), base)
+
+
+def _unstream(n):
+    """Post-collision populations at their source sites from the streamed ones."""
+    out = np.empty_like(n)
+    for q in range(19):
+        c = orc_velocity(q)
+        out[q] = np.roll(n[q], shift=(-c[2], -c[1], -c[0]), axis=(0, 1, 2))
+    return out
+
+
+def orc_velocity(q):
+    import ctypes
+    from oracle import oracle as O
+    c = (ctypes.c_int * 3)()
+    O._load().orc_lb_velocity(q, c)
+    return list(c)
+
+
+LB_NOISE_CASES = [
+    ("bgk_tau0.8", dict(lb_mode=0, tau=0.8)),
+    ("mrt", dict(lb_mode=1, gamma_s=0.3, gamma_b=-0.2, gamma_ghost=0.0)),
+]
+
+
+@pytest.mark.parametrize("name,kw", LB_NOISE_CASES, ids=[c[0] for c in LB_NOISE_CASES])
+def test_lb_noise_conserves_mass_and_momentum(orc, name, kw):
+    """The mode noise enters only the non-conserved modes: at every site the noise
+    changes neither the density nor the momentum of the post-collision populations."""
+    s0 = orc.System(L=(6, 5, 4), types=W.chain(1, 1), dt=0.01, omega=1.0, seed=3, step=2, **kw)
+    s1 = orc.System(L=(6, 5, 4), types=W.chain(1, 1), dt=0.01, omega=1.0, seed=3, step=2, noise=2, **kw)
+    rng = np.random.default_rng(0)
+    n = orc.lb_rest_state(s0) * (1 + 0.05 * rng.standard_normal((19,) + s0.shape))
+    f = 1e-3 * rng.standard_normal((3,) + s0.shape)
+    d = _unstream(orc.lb_step(s1, n, f)[0] - orc.lb_step(s0, n, f)[0])
+    assert np.max(np.abs(d)) > 1e-5
+    cs = np.array([orc_velocity(q) for q in range(19)], dtype=float)
+    assert np.max(np.abs(d.sum(0))) < 1e-15
+    assert np.max(np.abs(np.einsum("qa,qzyx->azyx", cs, d))) < 1e-15
+
+
+@pytest.mark.parametrize("name,kw", LB_NOISE_CASES, ids=[c[0] for c in LB_NOISE_CASES])
+def test_lb_noise_mode_variances(orc, name, kw):
+    """At rest with density 1, the noise of mode k has variance
+    phi_k^2 = rho kT b_k (1 - gamma_k^2) / c_s^2 with kT = dt^2 / Omega (eq. 13), and
+    distinct modes are uncorrelated (12^3 sites x 4 steps)."""
+    L = (12, 12, 12)
+    cs = np.array([orc_velocity(q) for q in range(19)], dtype=float)
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    E = np.array([[orc.mrt_basis()[k][q] for q in range(19)] for k in range(19)])
+    b = (w * E * E).sum(1)
+    dt, omega = 0.01, 400.0
+    kT = dt * dt / omega
+    if kw["lb_mode"] == 0:
+        g = np.full(19, 1 - 1 / kw["tau"])
+    else:
+        g = np.array([1.0] * 4 + [kw["gamma_b"]] + [kw["gamma_s"]] * 5 + [kw["gamma_ghost"]] * 9)
+    samples = []
+    for step in range(4):
+        s1 = orc.System(L=L, types=W.chain(1, 1), dt=dt, omega=omega, seed=11, step=step, noise=2, **kw)
+        n = orc.lb_rest_state(s1)
+        d = _unstream(orc.lb_step(s1, n)[0] - orc.lb_step(orc.System(L=L, types=W.chain(1, 1), dt=dt, **kw), n)[0])
+        samples.append(np.einsum("kq,qzyx->kzyx", E, d).reshape(19, -1))
+    m = np.concatenate(samples, axis=1)
+    nsamp = m.shape[1]
+    var = (m * m).mean(1)
+    expect = kT * b * (1 - g * g) * 3.0
+    assert np.all(np.abs(var[:4]) < 1e-28)
+    assert np.all(np.abs(var[4:] / expect[4:] - 1) < 6 * np.sqrt(2 / nsamp)), var[4:] / expect[4:]
+    c = np.corrcoef(m[4:])
+    assert np.max(np.abs(c - np.eye(15))) < 6 / np.sqrt(nsamp)
+    assert cs.shape == (19, 3)
+
+
+@pytest.mark.parametrize("name,kw", LB_NOISE_CASES, ids=[c[0] for c in LB_NOISE_CASES])
+def test_lb_equipartition(orc, name, kw):
+    """Fluctuation-dissipation of the fluctuating LB (eq. 7 via eq. 13): a fluid at rest
+    driven by the mode noise reaches <u_a^2> = kT / rho per velocity component (less
+    the 1/V of the conserved total momentum) and <delta rho^2> = rho kT / c_s^2."""
+    L = (8, 8, 8)
+    V = 512
+    dt, omega = 0.01, 1.0
+    kT = dt * dt / omega
+    n = orc.lb_rest_state(orc.System(L=L, types=W.chain(1, 1), **kw))
+    u2, r2, cnt = 0.0, 0.0, 0
+    for step in range(700):
+        s = orc.System(L=L, types=W.chain(1, 1), dt=dt, omega=omega, seed=5, step=step, noise=2, **kw)
+        n, rho, u = orc.lb_step(s, n)
+        if step >= 100:
+            u2 += (u * u).mean()
+            r2 += ((rho - 1.0) ** 2).mean()
+            cnt += 1
+    u2 /= cnt
+    r2 /= cnt
+    assert abs(u2 / (kT * (1 - 1 / V)) - 1) < 0.05, u2 / kT
+    assert abs(r2 / (3 * kT * (1 - 1 / V)) - 1) < 0.05, r2 / kT
+
+
+def test_cd_noise_conserves_and_has_bond_covariance(orc):
+    """Composition noise alone (mu = 0, no flow): each species' amount is unchanged to
+    rounding, and the increments have the covariance (2 dt phi / Omega) times the
+    7-point -Laplacian: 6 on a site, -1 between face neighbours, 0 between edge
+    neighbours and between species."""
+    L = (8, 8, 8)
+    dt, omega, p0 = 0.01, 400.0, 0.5
+    s2 = 2 * dt * p0 / omega
+    phi = np.full((2, 8, 8, 8), p0)
+    mu = np.zeros_like(phi)
+    d = []
+    for step in range(60):
+        s = orc.System(L=L, types=W.chain(1, 1), dt=dt, omega=omega, seed=9, step=step, noise=1)
+        out = orc.cd_update(s, phi, mu)
+        assert np.all(np.abs((out - phi).sum(axis=(1, 2, 3))) < 1e-14)
+        d.append(out - phi)
+    d = np.array(d)                                   # [step][species][z][y][x]
+    nsamp = d.shape[0] * d.shape[1] * 512
+    var = (d * d).mean() / s2
+    nn = np.mean([(d * np.roll(d, 1, axis=ax)).mean() for ax in (2, 3, 4)]) / s2
+    edge = (d * np.roll(np.roll(d, 1, axis=3), 1, axis=4)).mean() / s2
+    cross = (d[:, 0] * d[:, 1]).mean() / s2
+    tol = 6 * np.sqrt(40 / nsamp)
+    assert abs(var - 6) < 6 * tol and abs(nn + 1) < tol and abs(edge) < tol and abs(cross) < tol, (var, nn, edge, cross)
+
+
+def test_cd_noise_fluctuation_dissipation(orc):
+    """Eq. 5 pairs the composition noise with the diffusive flux: an ideal gas
+    (mu = ln phi, supplied by the test) diffusing with the noise reaches, mode by mode,
+    the stationary variance of the explicit scheme, (phi0 / Omega) 2 / (2 - dt lambda_k)
+    with lambda_k the eigenvalues of the 7-point -Laplacian (phi0 / Omega per site in the
+    limit dt -> 0), here averaged over sites."""
+    L = (8, 8, 8)
+    dt, omega, p0 = 0.1, 1e4, 0.5
+    k = 2 * np.pi * np.fft.fftfreq(8)
+    lam = sum(2 * (1 - np.cos(kk)) for kk in np.meshgrid(k, k, k, indexing="ij"))
+    c = (p0 / omega) * 2 / (2 - dt * lam)
+    c[0, 0, 0] = 0.0                                   # the amount is conserved
+    expect = c.sum() / 512
+    phi = np.full((2, 8, 8, 8), p0)
+    acc, cnt = 0.0, 0
+    for step in range(1500):
+        s = orc.System(L=L, types=W.chain(1, 1), dt=dt, omega=omega, seed=2, step=step, noise=1)
+        phi = orc.cd_update(s, phi, np.log(phi))
+        if step >= 300:
+            acc += ((phi - phi.mean(axis=(1, 2, 3), keepdims=True)) ** 2).mean()
+            cnt += 1
+    got = acc / cnt
+    assert abs(got / expect - 1) < 0.04, (got, expect, p0 / omega)
+    assert abs(got / (p0 / omega) - 1) > 0.1        # the dt correction is resolved
