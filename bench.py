@@ -145,12 +145,14 @@ def learned_arm(hsf, workload, precision, steps, warmup, tile, log, precond=Fals
     }
 
 
-def run_arm(hsf, torch, wls, steps, warmup, timing, log, precond=False, tile=None):
+def run_arm(hsf, torch, wls, steps, warmup, timing, log, precond=False, tile=None, noise_omega=None):
     """Build a batched context, autotune, warm up, time `steps` coupled steps."""
     from paper_1204_2088_amd import workloads as W
     stream = torch.cuda.current_stream()
     ctx = hsf.Context(wls, stream=stream)
     ctx.set_solver(precond=precond)
+    if noise_omega:
+        ctx.set_noise(cd=True, lb=True, omega=noise_omega, seed=2012)
     phi0 = np.concatenate([W.initial_composition(w).ravel() for w in wls])
     ctx.set_densities(torch.from_numpy(phi0).to("cuda"))
     torch.cuda.synchronize()
@@ -231,6 +233,9 @@ def main():
     ap.add_argument("--lb", default="bgk", choices=["bgk", "mrt"],
                     help="LB collision: BGK, or the MRT scheme with the shear viscosity of the workload's tau, "
                          "the same bulk eigenvalue and the kinetic modes relaxed completely")
+    ap.add_argument("--noise", type=float, default=None, metavar="OMEGA",
+                    help="thermal noise in both the compositions (eq. 5) and the LB modes (eq. 13) "
+                         "with noise scaling parameter OMEGA (the paper uses 400)")
     ap.add_argument("--net-probe", default=None, metavar="WIDTHS",
                     help="only time the warm-start network of these level widths (e.g. 16 or 8,16,24,32): "
                          "forward passes and Adam steps on two 64^3 samples")
@@ -293,7 +298,7 @@ def main():
     wl = wls[0]
     ctx, tile, tune_ms, stats, (evals, site_evals), elapsed, timing, t_steps, t_elapsed = run_arm(
         hsf, torch, wls, args.steps, args.warmup, not args.no_timing, log, args.precond,
-        tuple(int(v) for v in args.tile.split(",")) if args.tile else None)
+        tuple(int(v) for v in args.tile.split(",")) if args.tile else None, args.noise)
 
     V_total = sum(w.V for w in wls)
     N = wl.N
@@ -368,7 +373,8 @@ def main():
         "config": {"workload": args.workload, "L": list(wl.L), "N": N, "replicas": len(wls),
                    "tau": [w.tau for w in wls], "propagators": wl.precision, "reductions": "fp64",
                    "tol": wl.tol, "dt": wl.dt, "hydro": True,
-                   "solver": "preconditioned FR" if args.precond else "FR", "lb": args.lb},
+                   "solver": "preconditioned FR" if args.precond else "FR", "lb": args.lb,
+                   "noise_omega": args.noise},
         "evals_per_step": evals / args.steps,
         "iterations_last_step": [s["iterations"] for s in stats][:8],
         "lb_mlups": lb_mlups,

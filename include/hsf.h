@@ -230,6 +230,32 @@ int hsf_cd_advance(hsf_ctx *ctx, const double *mu, const double *u, int where);
 int hsf_step(hsf_ctx *ctx, int n_steps, double tol, int max_iter, hsf_invert_stats *stats,
              long long *total_evals);
 
+/* Thermal noise (off by default).  flags: HSF_NOISE_CD adds the composition noise
+ * xi_I of eq. 5 to every convection-diffusion update, HSF_NOISE_LB the mode noise
+ * phi_k r_k of eq. 13 to every LB collision; omega > 0 is the noise scaling parameter
+ * Omega = h^3 / v0 (sec. 3).  In lattice units (h = 1, M = kT = 1 for eq. 3):
+ *   LB: mode k >= 4 of the Table 1 basis gets sqrt(rho kT_LB b_k (1 - gamma_k^2) / c_s^2)
+ *       r_k, kT_LB = dt^2 / Omega (the unit map of the force density), gamma_k of the
+ *       collision (BGK: 1 - 1/tau for every non-conserved mode); mass and momentum are
+ *       untouched;
+ *   CD: each bond between r and r + e_a carries an extra flux
+ *       sqrt(2 dt max((phi_I(r) + phi_I(r + e_a)) / 2, 0) / Omega) g, whose divergence
+ *       has the covariance (2 dt / Omega)(-div phi_I grad) of eq. 5 over a step and
+ *       conserves each species exactly.
+ * Normal numbers: Philox4x64-10 (Salmon et al., SC11) of counter (site, step, purpose, 0)
+ * under key (seed, replica index), two Box-Muller pairs per counter (radius from
+ * ((x >> 11) + 1) 2^-53, angle 2 pi (x >> 11) 2^-53); purposes 0-3 the LB modes 4-18
+ * (mode k takes number k - 4), 4 + I the bonds (x, y, z) of species I, a bond's numbers
+ * being those of its lower site.  `step` is the step word of the next draw; every LB
+ * step of hsf_lb_advance, every hsf_cd_advance and every coupled step of hsf_step
+ * (both noises of it) uses the current value and then advances it by one, while noise
+ * is on.  Waits for the context's stream.  HSF_EINVAL for unknown flags or a
+ * non-positive Omega with noise on; flags = 0 switches noise off. */
+enum { HSF_NOISE_CD = 1, HSF_NOISE_LB = 2 };
+int hsf_set_noise(hsf_ctx *ctx, int flags, double omega, unsigned long long seed, unsigned long long step);
+/* The step word of the next noise draw (to resume a run with the same numbers). */
+int hsf_get_noise_step(const hsf_ctx *ctx, unsigned long long *step);
+
 /* Switch convection by the LB flow on or off for every replica (the LB state
  * is kept while off). */
 int hsf_set_hydro(hsf_ctx *ctx, int on);

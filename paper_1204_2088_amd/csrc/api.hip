@@ -23,6 +23,9 @@ struct hsf_ctx {
     int n_rep = 0;
     int precision = HSF_FP64;
     int hydro = 1;
+    int noise = 0;                   // HSF_NOISE_* flags
+    unsigned long long noise_step = 0;  // generator step word of the next noise draw
+    double *noise_flux = nullptr;    // bond fluxes of the composition noise, 3 nsp T (allocated when first on)
     Chain ch{};
     long long T = 0;                 // total sites over all replicas
     std::vector<Rep> reps;
@@ -876,9 +879,11 @@ int hsf_lb_advance(hsf_ctx *c, int n_steps, const double *force, int where)
     for (int k = 0; k < n_steps; ++k) {
         {
             Timed t(c, HSF_K_LB);
-            launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, f, c->rho, c->u, t.a, t.b);
+            launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, f, c->rho, c->u, (c->noise & HSF_NOISE_LB) != 0,
+                      c->noise_step, t.a, t.b);
         }
         std::swap(c->nA, c->nB);
+        if (c->noise) ++c->noise_step;
     }
     HIPCHK(c, hipGetLastError());
     return HSF_OK;
@@ -903,7 +908,9 @@ int hsf_cd_advance(hsf_ctx *c, const double *mu, const double *u, int where)
         if ((rc = copy_in(c, c->uin, u, (size_t)3 * c->T, where))) return rc;
         uu = c->uin;
     }
-    launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, uu, c->phi_tmp);
+    launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, uu, c->phi_tmp,
+              (c->noise & HSF_NOISE_CD) ? c->noise_flux : nullptr, c->noise_step);
+    if (c->noise) ++c->noise_step;
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->phi, c->phi_tmp, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice,
                              c->stream));
@@ -923,15 +930,18 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
             launch_force(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, c->force);
             {
                 Timed t(c, HSF_K_LB);
-                launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, c->force, c->rho, c->u, t.a, t.b);
+                launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, c->force, c->rho, c->u,
+                          (c->noise & HSF_NOISE_LB) != 0, c->noise_step, t.a, t.b);
             }
             std::swap(c->nA, c->nB);
             uu = c->u;
         }
         {
             Timed t(c, HSF_K_CD);
-            launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, uu, c->phi_tmp, t.a, t.b);
+            launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, uu, c->phi_tmp,
+                      (c->noise & HSF_NOISE_CD) ? c->noise_flux : nullptr, c->noise_step, t.a, t.b);
         }
+        if (c->noise) ++c->noise_step;   // both noises of a coupled step share its step word
         // the captured sequences hold the address of phi: copy the update back
         HIPCHK(c, hipMemcpyAsync(c->phi, c->phi_tmp, sizeof(double) * c->ch.nsp * c->T,
                                  hipMemcpyDeviceToDevice, c->stream));
@@ -1093,6 +1103,35 @@ int hsf_get_work(hsf_ctx *c, long long *evals, double *site_evals, int reset)
         c->work_evals = 0;
         c->work_site_evals = 0.0;
     }
+    return HSF_OK;
+}
+
+int hsf_set_noise(hsf_ctx *c, int flags, double omega, unsigned long long seed, unsigned long long step)
+{
+    if (!c) return HSF_EINVAL;
+    if (flags & ~(HSF_NOISE_CD | HSF_NOISE_LB)) return fail(c, HSF_EINVAL, "unknown noise flags %d", flags);
+    if (flags && !(omega > 0.0 && std::isfinite(omega))) return fail(c, HSF_EINVAL, "noise needs Omega > 0");
+    HIPCHK(c, hipStreamSynchronize(c->stream));   // kernels in flight read the replica table
+    if ((flags & HSF_NOISE_CD) && !c->noise_flux) {
+        int rc = dalloc(c, (void **)&c->noise_flux, sizeof(double) * 3 * c->ch.nsp * c->T);
+        if (rc) return rc;
+    }
+    for (auto &R : c->reps) {
+        R.omega = flags ? omega : 0.0;
+        R.seed = seed;
+    }
+    HIPCHK(c, hipMemcpy(c->rep_d, c->reps.data(), sizeof(Rep) * c->n_rep, hipMemcpyHostToDevice));
+    c->plan.rep0 = c->reps[0];
+    c->tplan.rep0 = c->reps[0];
+    c->noise = flags;
+    c->noise_step = step;
+    return HSF_OK;
+}
+
+int hsf_get_noise_step(const hsf_ctx *c, unsigned long long *step)
+{
+    if (!c || !step) return HSF_EINVAL;
+    *step = c->noise_step;
     return HSF_OK;
 }
 

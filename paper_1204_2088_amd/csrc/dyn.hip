@@ -2,11 +2,13 @@
 //   chemical potential (eq. 4) and thermodynamic force (eq. 8);
 //   D3Q19 lattice Boltzmann, moments (eq. 9), equilibrium (eq. 11), single-relaxation
 //   collision L_ij = -delta_ij / tau with its forcing term, collide then stream (eq. 10);
-//   conservative convection-diffusion update (eq. 3).
+//   conservative convection-diffusion update (eq. 3);
+//   optional thermal noise: LB mode noise (eq. 13) and composition noise (eq. 5).
 #include <hip/hip_ext.h>
 #include <math.h>
 
 #include "device_common.h"
+#include "philox.h"
 
 namespace hsf {
 
@@ -186,15 +188,47 @@ __device__ __forceinline__ void mrt_collide(const double *n, double rho, double 
     }
 }
 
+// Mode noise of eq. 13 added to the post-collision populations ns of site i of replica r:
+// mode k >= 4 receives phi_k r_k, phi_k = sqrt(rho kT b_k (1 - gamma_k^2) / c_s^2), carried
+// to the populations as w_q e_k(c_q) phi_k r_k / b_k.  kT = dt^2 / Omega in LB units;
+// gamma_k of the collision (BGK: 1 - 1/tau for every non-conserved mode).  r_k are the
+// normal numbers of purposes 0-3 (mode k takes number k - 4).
+__device__ __forceinline__ void lb_mode_noise(const Rep &R, int r, long long i, unsigned long long step,
+                                              double rho, double *ns)
+{
+    double z[16];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) normals4(R.seed, (uint64_t)r, (uint64_t)i, step, (uint64_t)p, z + 4 * p);
+    const double rk = 3.0 * fmax(rho, 0.0) * (R.dt * R.dt / R.omega);
+    const bool mrt = R.lb_mode == HSF_LB_MRT;
+    const double gbgk = 1.0 - 1.0 / R.tau;
+    double a[19];
+#pragma unroll
+    for (int k = 4; k < 19; ++k) {
+        const double g = mrt ? (k == 4 ? R.gamma_b : (k <= 9 ? R.gamma_s : R.gamma_ghost)) : gbgk;
+        a[k] = sqrt(rk * (1.0 - g * g) * kMrt.binv[k]) * z[k - 4];
+    }
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 4; k < 19; ++k) acc += kMrt.e[k][q] * a[k];
+        ns[q] += lb_w(q) * acc;
+    }
+}
+
 // One LB step, push form: read the 19 pre-collision populations of this site,
 // take the moments of eq. 9 (u with the half-force shift), relax towards the
 // equilibrium of eq. 11 with rate 1/tau, add the forcing term
 //   F_i = (1 - 1/(2 tau)) w_i [3 (c_i - u).f + 9 (c_i.u)(c_i.f)],
-// and write each post-collision population to the neighbour it streams to.
+// and write each post-collision population to the neighbour it streams to.  NOISE adds
+// the mode noise of eq. 13 before streaming.
+template <bool NOISE>
 __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, const int *__restrict__ blk_first,
                                                const Rep *__restrict__ rep, const double *__restrict__ nsrc,
                                                double *__restrict__ ndst, const double *__restrict__ f,
-                                               double *__restrict__ rho_out, double *__restrict__ u_out)
+                                               double *__restrict__ rho_out, double *__restrict__ u_out,
+                                               unsigned long long step)
 {
     const SiteRef sr = site_ref(blk_rep, blk_first);
     const Rep &R = rep[sr.r];
@@ -221,14 +255,9 @@ __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, 
         jz += kCz[q] * n[q];
     }
     const double ux = (jx + 0.5 * fx) / rho, uy = (jy + 0.5 * fy) / rho, uz = (jz + 0.5 * fz) / rho;
+    double ns[19];
     if (R.lb_mode == HSF_LB_MRT) {
-        double ns[19];
         mrt_collide(n, rho, ux, uy, uz, fx, fy, fz, R, ns);
-#pragma unroll
-        for (int q = 0; q < 19; ++q) {
-            const int xd = wrap1(x + kCx[q], R.Lx), yd = wrap1(y + kCy[q], R.Ly), zd = wrap1(z + kCz[q], R.Lz);
-            ndst[base + q * V + sidx(R, xd, yd, zd)] = ns[q];
-        }
     } else {
         const double om = 1.0 / R.tau, fp = 1.0 - 0.5 / R.tau;
         const double uu = ux * ux + uy * uy + uz * uz;
@@ -240,10 +269,14 @@ __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, 
             const double wq = lb_w(q);
             const double neq = rho * wq * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
             const double F = fp * wq * (3.0 * (cf - uf) + 9.0 * cu * cf);
-            const double ns = n[q] - om * (n[q] - neq) + F;
-            const int xd = wrap1(x + kCx[q], R.Lx), yd = wrap1(y + kCy[q], R.Ly), zd = wrap1(z + kCz[q], R.Lz);
-            ndst[base + q * V + sidx(R, xd, yd, zd)] = ns;
+            ns[q] = n[q] - om * (n[q] - neq) + F;
         }
+    }
+    if (NOISE) lb_mode_noise(R, sr.r, i, step, rho, ns);
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        const int xd = wrap1(x + kCx[q], R.Lx), yd = wrap1(y + kCy[q], R.Ly), zd = wrap1(z + kCz[q], R.Lz);
+        ndst[base + q * V + sidx(R, xd, yd, zd)] = ns[q];
     }
     rho_out[R.site_off + i] = rho;
     u_out[vo + i] = ux;
@@ -255,10 +288,14 @@ __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, 
 //   J = dt * (-(phi_r + phi_e)/2 (mu_e - mu_r))
 //     + [(phi_r + phi_e)/2 - ((phi u_a)_e - (phi u_a)_r)/2] (u_a,r + u_a,e)/2
 // phi_new(r) = phi(r) - sum_a (J(r + e_a/2) - J(r - e_a/2)).
+// NOISE adds the composition noise of eq. 5 as a random flux on every bond, drawn
+// beforehand by k_cd_noise into jn.
+template <bool NOISE>
 __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, const int *__restrict__ blk_first,
                                                const Rep *__restrict__ rep, Chain ch,
                                                const double *__restrict__ phi, const double *__restrict__ mu,
-                                               const double *__restrict__ u, double *__restrict__ phi_out)
+                                               const double *__restrict__ u, double *__restrict__ phi_out,
+                                               const double *__restrict__ jn)
 {
     const SiteRef sr = site_ref(blk_rep, blk_first);
     const Rep &R = rep[sr.r];
@@ -276,6 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, 
         const double *m = mu + fo + I * V;
         const double pr = p[i], mr = m[i];
         double div = 0.0;
+        const double *jI = NOISE ? jn + 3 * fo + 3 * I * V : nullptr;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const long long lo = nb[2 * a], hi = nb[2 * a + 1];
@@ -289,9 +327,45 @@ __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, 
                 jl += (0.5 * (pl + pr) - 0.5 * (pr * ur - pl * ul)) * (0.5 * (ul + ur));
                 jh += (0.5 * (pr + ph) - 0.5 * (ph * uh - pr * ur)) * (0.5 * (ur + uh));
             }
+            if (NOISE) {
+                jl += jI[a * V + lo];
+                jh += jI[a * V + i];
+            }
             div += jh - jl;
         }
         phi_out[fo + I * V + i] = pr - div;
+    }
+}
+
+// Composition noise of eq. 5 as random bond fluxes: the bond between site s and
+// s + e_a of species I carries jn = sqrt(2 dt max(phi_bond, 0) / Omega) g with
+// phi_bond = (phi_I(s) + phi_I(s + e_a)) / 2 and g number a of the normal numbers of
+// (site s, purpose 4 + I).  Its divergence conserves each species exactly and has the
+// covariance (2 dt / Omega)(-div phi grad) of eq. 5 over a step.
+// Layout of jn: per replica [species][3][V] at 3 nsp site_off.
+__global__ __launch_bounds__(kBlock) void k_cd_noise(const int *__restrict__ blk_rep,
+                                                     const int *__restrict__ blk_first,
+                                                     const Rep *__restrict__ rep, Chain ch,
+                                                     const double *__restrict__ phi, double *__restrict__ jn,
+                                                     unsigned long long step)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    if (i >= V) return;
+    int x, y, z;
+    site_xyz(R, i, x, y, z);
+    const long long fo = off_field(R, ch.nsp);
+    const long long up[3] = {sidx(R, wrap1(x + 1, R.Lx), y, z), sidx(R, x, wrap1(y + 1, R.Ly), z),
+                             sidx(R, x, y, wrap1(z + 1, R.Lz))};
+    for (int I = 0; I < ch.nsp; ++I) {
+        const double *p = phi + fo + I * V;
+        double g[4];
+        normals4(R.seed, (uint64_t)sr.r, (uint64_t)i, step, (uint64_t)(4 + I), g);
+        const double pr = p[i];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            jn[3 * fo + (3 * I + a) * V + i] = sqrt(2.0 * R.dt * fmax(0.5 * (pr + p[up[a]]), 0.0) / R.omega) * g[a];
     }
 }
 
@@ -321,25 +395,38 @@ void launch_force(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const 
 }
 
 void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc, double *ndst, const double *f,
-               double *rho, double *u, hipEvent_t e0, hipEvent_t e1)
+               double *rho, double *u, bool noise, unsigned long long step, hipEvent_t e0, hipEvent_t e1)
 {
+    auto kern = noise ? k_lb<true> : k_lb<false>;
     if (e0)
-        hipExtLaunchKernelGGL(k_lb, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep,
-                              nsrc, ndst, f, rho, u);
+        hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep,
+                              nsrc, ndst, f, rho, u, step);
     else
-        hipLaunchKernelGGL(k_lb, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, nsrc, ndst, f,
-                           rho, u);
+        hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, nsrc, ndst, f,
+                           rho, u, step);
 }
 
 void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi, const double *mu,
-               const double *u, double *phi_out, hipEvent_t e0, hipEvent_t e1)
+               const double *u, double *phi_out, double *noise_flux, unsigned long long step, hipEvent_t e0,
+               hipEvent_t e1)
 {
-    if (e0)
-        hipExtLaunchKernelGGL(k_cd, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep,
-                              ch, phi, mu, u, phi_out);
+    // with noise the events bracket both kernels: e0 at the start of the flux draw
+    if (noise_flux) {
+        if (e0)
+            hipExtLaunchKernelGGL(k_cd_noise, dim3(p.nblocks), dim3(kBlock), 0, s, e0, nullptr, 0, p.blk_rep,
+                                  p.blk_first, rep, ch, phi, noise_flux, step);
+        else
+            hipLaunchKernelGGL(k_cd_noise, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch,
+                               phi, noise_flux, step);
+        e0 = nullptr;
+    }
+    auto kern = noise_flux ? k_cd<true> : k_cd<false>;
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep,
+                              ch, phi, mu, u, phi_out, (const double *)noise_flux);
     else
-        hipLaunchKernelGGL(k_cd, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch, phi, mu, u,
-                           phi_out);
+        hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch, phi, mu, u,
+                           phi_out, (const double *)noise_flux);
 }
 
 void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n)

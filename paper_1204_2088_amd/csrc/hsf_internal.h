@@ -22,6 +22,8 @@ struct Rep {
     double kappa, dt, tau;
     int lb_mode;            // HSF_LB_BGK or HSF_LB_MRT
     double gamma_s, gamma_b, gamma_ghost;
+    double omega;           // noise scaling parameter Omega (noise kernels only)
+    unsigned long long seed;  // generator key word 0 (word 1 is the replica index)
 };
 
 // Per-replica scalars of an evaluation and of the conjugate-gradient inversion.
@@ -111,11 +113,16 @@ void launch_mu(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const dou
                const double *w, double *mu);
 void launch_force(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi,
                   const double *mu, double *f);
+// noise: draw the thermal noise of this step (eq. 13 for LB, eq. 5 for CD) with
+// generator step word `step`
 void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc, double *ndst,
-               const double *f, double *rho, double *u, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+               const double *f, double *rho, double *u, bool noise, unsigned long long step,
+               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// noise_flux: scratch for the composition noise's bond fluxes (3 nsp T doubles), or null
+// for no noise
 void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi,
-               const double *mu, const double *u, double *phi_out, hipEvent_t e0 = nullptr,
-               hipEvent_t e1 = nullptr);
+               const double *mu, const double *u, double *phi_out, double *noise_flux, unsigned long long step,
+               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n);
 
 // observables: the free-energy density and order parameters of (w, phi) into

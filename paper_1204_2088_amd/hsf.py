@@ -30,7 +30,7 @@ EXPORTED = [
     "hsf_site_offset", "hsf_field_offset", "hsf_num_species", "hsf_set_fields", "hsf_get_fields",
     "hsf_set_densities", "hsf_get_densities", "hsf_evaluate", "hsf_observables", "hsf_invert", "hsf_mu_force",
     "hsf_set_lb", "hsf_get_lb", "hsf_lb_advance", "hsf_get_flow", "hsf_cd_advance", "hsf_step",
-    "hsf_set_hydro", "hsf_set_timing", "hsf_get_timing", "hsf_set_tile", "hsf_get_tile", "hsf_autotune",
+    "hsf_set_hydro", "hsf_set_noise", "hsf_get_noise_step", "hsf_set_timing", "hsf_get_timing", "hsf_set_tile", "hsf_get_tile", "hsf_autotune",
     "hsf_set_solver", "hsf_get_work", "hsf_set_warm", "hsf_net_create", "hsf_net_destroy",
     "hsf_net_last_error", "hsf_net_set_stream", "hsf_net_num_params", "hsf_net_set_params",
     "hsf_net_get_params", "hsf_net_set_input_norm", "hsf_net_set_output_scale", "hsf_net_forward", "hsf_net_loss_grad",
@@ -39,6 +39,7 @@ EXPORTED = [
 WARM_EXTRAP, WARM_NET, WARM_NET_DELTA, WARM_NET_EXTRAP = 2, 3, 4, 5
 SOLVER_PRECOND = 1
 LB_BGK, LB_MRT = 0, 1
+NOISE_CD, NOISE_LB = 1, 2
 K_PREP, K_FWD, K_BWD, K_LB, K_CD, K_COUNT = 0, 1, 2, 3, 4, 5
 KERNEL_NAMES = ["prep", "fwd", "bwd", "lb", "cd"]
 
@@ -113,6 +114,8 @@ def load():
         "hsf_step": ([C, I, ctypes.c_double, I, ctypes.POINTER(InvertStats),
                       ctypes.POINTER(ctypes.c_longlong)], I),
         "hsf_set_hydro": ([C, I], I),
+        "hsf_set_noise": ([C, I, ctypes.c_double, ctypes.c_ulonglong, ctypes.c_ulonglong], I),
+        "hsf_get_noise_step": ([C, ctypes.POINTER(ctypes.c_ulonglong)], I),
         "hsf_set_timing": ([C, I], I),
         "hsf_set_solver": ([C, I], I),
         "hsf_set_warm": ([C, I], I),
@@ -336,6 +339,16 @@ class Context:
         ev = ctypes.c_longlong(0)
         self._check(self._lib.hsf_step(self._h, int(n_steps), float(tol), int(max_iter), st, ctypes.byref(ev)))
         return [s.as_dict() for s in st], ev.value
+
+    def set_noise(self, cd=True, lb=True, omega=400.0, seed=0, step=0):
+        """Thermal noise: composition noise (eq. 5) and/or LB mode noise (eq. 13)."""
+        flags = (NOISE_CD if cd else 0) | (NOISE_LB if lb else 0)
+        self._check(self._lib.hsf_set_noise(self._h, flags, float(omega), int(seed), int(step)))
+
+    def noise_step(self):
+        v = ctypes.c_ulonglong()
+        self._check(self._lib.hsf_get_noise_step(self._h, ctypes.byref(v)))
+        return int(v.value)
 
     def set_hydro(self, on):
         self._check(self._lib.hsf_set_hydro(self._h, int(bool(on))))
