@@ -14,7 +14,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -345,3 +345,70 @@ def lb_rest_state(sys: System, rho0=1.0):
     """Populations at rest with density rho0 (equilibrium of eq. 11 at u = 0)."""
     neq = lb_equilibrium(rho0, np.zeros(3))
     return np.ascontiguousarray(np.broadcast_to(neq[:, None, None, None], (19,) + sys.shape).copy())
+
+
+# ---------------------------------------------------------------------------
+# Crank-Nicolson diffusion (section 2: the diffusive part of eq. 3 is integrated
+# with the implicit Crank-Nicolson scheme, convection with explicit two-step
+# Lax-Wendroff).  With B(phi, mu) the diffusive rate div(phi grad mu) of the
+# conservative face fluxes of orc_cd_update (M = 1) and J^C the convective flux,
+#   phi^{n+1} = phi^n + dt/2 [B(phi^n, mu^n) + B(phi^{n+1}, mu^{n+1})] - div J^C(phi^n, u^n) + xi^n,
+# where mu^{n+1} = mu[phi^{n+1}] requires the self-consistent fields of phi^{n+1}.
+# The unknowns are those fields: phi^{n+1} = phi[w], and
+#   F(w) = phi[w] - dt/2 B(phi[w], mu(phi[w], w)) - rhs = 0,
+#   rhs = phi^n + dt/2 B(phi^n, mu^n) - div J^C + xi^n.
+# This oracle solves F = 0 by Newton's method with the full Jacobian by forward
+# differences (one column per unknown) and a least-squares solve (the fields'
+# per-species constants are a null space of F); it is meant for small boxes.
+# ---------------------------------------------------------------------------
+
+def _diffusive_rate(sys: System, phi, mu):
+    """B(phi, mu) = div(phi grad mu) of the explicit step's face fluxes (no flow, no noise)."""
+    s1 = replace(sys, dt=1.0, noise=0)
+    return cd_update(s1, phi, mu) - _arr(phi, (sys.nsp,) + sys.shape)
+
+
+def cn_residual(sys: System, w, rhs, phibar_p, phibar_s):
+    """F(w) and phi[w] of the Crank-Nicolson equation."""
+    p, _ = evaluate(sys, w, phibar_p, phibar_s)
+    mu, _ = mu_force(sys, p, w)
+    return p - 0.5 * sys.dt * _diffusive_rate(sys, p, mu) - rhs, p
+
+
+def cn_step(sys: System, phi, w, n=None, tol=1e-12, max_newton=20, invert_tol=1e-13, h=1e-7):
+    """One coupled step with Crank-Nicolson diffusion.  Order as in `step`: invert
+    phi^n, mu^n and the force, the LB step (hydro on, n given) giving u^n, then the CD
+    update, here implicit.  Returns (phi^{n+1}, w^{n+1}, n^{n+1}, info) with
+    phi^{n+1} = phi[w^{n+1}] and info = {"newton": iterations, "residual": max |F|,
+    "evaluations": density evaluations of the Newton solve}."""
+    shape = (sys.nsp,) + sys.shape
+    phi = _arr(phi, shape).copy()
+    w, st, rc = invert(sys, phi, w, tol=invert_tol, max_iter=20000)
+    if rc != 0:
+        raise RuntimeError(f"inversion of phi^n failed: {st}")
+    pbar_p = phi[:2].sum(0).mean()
+    pbar_s = phi[2].mean() if sys.has_solvent else 0.0
+    mu, f = mu_force(sys, phi, w)
+    u = None
+    if sys.hydro and n is not None:
+        n, _, u = lb_step(sys, n, f)
+    full = cd_update(sys, phi, mu, u)                      # phi + dt B - div J^C + xi
+    rhs = full - 0.5 * sys.dt * _diffusive_rate(sys, phi, mu)
+    evals = 0
+    x = w.ravel().copy()
+    for it in range(max_newton + 1):
+        F, p = cn_residual(sys, x.reshape(shape), rhs, pbar_p, pbar_s)
+        evals += 1
+        res = np.max(np.abs(F))
+        if res <= tol or it == max_newton:
+            break
+        Fv = F.ravel()
+        J = np.empty((Fv.size, x.size))
+        for j in range(x.size):
+            xp = x.copy()
+            xp[j] += h
+            J[:, j] = (cn_residual(sys, xp.reshape(shape), rhs, pbar_p, pbar_s)[0].ravel() - Fv) / h
+        evals += x.size
+        dx = np.linalg.lstsq(J, -Fv, rcond=1e-12)[0]
+        x = x + dx
+    return p, x.reshape(shape), n, {"newton": it, "residual": res, "evaluations": evals}

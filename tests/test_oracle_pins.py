@@ -906,3 +906,62 @@ def test_cd_noise_fluctuation_dissipation(orc):
     got = acc / cnt
     assert abs(got / expect - 1) < 0.04, (got, expect, p0 / omega)
     assert abs(got / (p0 / omega) - 1) > 0.1        # the dt correction is resolved
+
+
+# ---- Crank-Nicolson diffusion --------------------------------------------------------
+
+
+@pytest.mark.parametrize("dt,mode,sign", [(0.2, 1, -1), (0.4, 1, -1), (0.4, 3, 1)])
+def test_cn_linearised_step(orc, dt, mode, sign):
+    """At small amplitude one Crank-Nicolson step multiplies each Fourier mode by
+    (1 + dt/2 K)^-1 (1 - dt/2 K), K = lambda(k) diag(phi0) (S(k)^-1 + sigma_hat chi + kappa 1 1^T)
+    the generator of the linearised diffusive step; dt = 0.4 lies far beyond the
+    explicit scheme's stability limit (about 0.015): for the shortest compressive wave
+    (A and B in phase) the explicit step would amplify the mode, the implicit one damps
+    it."""
+    types = W.chain(2, 2)
+    c = orc.stencil_weights(1.1543)
+    L = (6, 1, 1)
+    chi = W.chi_matrix(ab=1.7)
+    sys_ = orc.System(L=L, types=types, c=c, chi=chi, kappa=10.0, dt=dt, hydro=False)
+    eps = 1e-6
+    x = np.arange(L[0])
+    kx = 2 * np.pi * mode / L[0]
+    wave = np.cos(kx * x)[None, None, :]
+    phi = np.empty((2, 1, 1, L[0]))
+    phi[0] = 0.5 + eps * wave
+    phi[1] = 0.5 + sign * eps * wave
+    phin, wn, _, info = orc.cn_step(sys_, phi, -np.log(phi / 0.5), tol=1e-15)
+    Sm, sh = _debye(types, c, (kx, 0.0, 0.0))
+    lam = 2 - 2 * np.cos(kx)
+    K = lam * np.diag([0.5, 0.5]) @ (np.linalg.inv(Sm) + sh * chi[:2, :2] + 10.0 * np.ones((2, 2)))
+    Mcn = np.linalg.solve(np.eye(2) + 0.5 * dt * K, np.eye(2) - 0.5 * dt * K)
+    pred = Mcn @ np.array([eps, sign * eps])
+    norm = 1.0 if 2 * mode == L[0] else 2.0        # cos(pi x) has mean square 1
+    got = np.array([(phin[I, 0, 0] * np.cos(kx * x)).sum() * norm / L[0] for I in range(2)])
+    assert np.max(np.abs(got - pred)) / eps < 1e-5, (got / eps, pred / eps)
+    assert np.max(np.abs(got)) < eps
+    if mode == 3:
+        explicit = (np.eye(2) - dt * K) @ np.array([1.0, 1.0])
+        assert np.max(np.abs(explicit)) > 1.5      # the explicit step would amplify this mode
+
+
+def test_cn_consistent_with_explicit_step(orc):
+    """For small dt the implicit and explicit steps agree to first order: the relative
+    difference of their increments halves with dt (solution with solvent, 5x4x6)."""
+    wl = W.Workload("pin_sol", (5, 4, 6), W.chain(2, 4), True, W.chi_matrix(ab=2.0, bs=2.5), tau=1.0,
+                    noise=0.02, seed=2, phi_p=0.2, precision="fp64")
+    phi = W.initial_composition(wl)
+    r = []
+    for dt in (2e-3, 1e-3):
+        s = orc.System(L=wl.L, types=wl.types, has_solvent=True, chi=wl.chi, kappa=10.0, dt=dt, hydro=False,
+                       c=orc.stencil_weights(wl.a))
+        w0 = -np.log(phi / phi.mean(axis=(1, 2, 3), keepdims=True))
+        pc, _, _, info = orc.cn_step(s, phi, w0, tol=1e-15)
+        pe, _, _, _, _, _, rc = orc.step(s, phi, w0, None, tol=1e-13, max_iter=20000)
+        assert rc == 0
+        # each species' amount is kept exactly
+        assert np.max(np.abs(pc.sum(axis=(1, 2, 3)) - phi.sum(axis=(1, 2, 3)))) < 1e-12
+        r.append(np.max(np.abs((pc - phi) - (pe - phi))) / np.max(np.abs(pe - phi)))
+    assert 1.8 < r[0] / r[1] < 2.2, r
+    assert r[0] < 0.05
