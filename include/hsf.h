@@ -230,6 +230,36 @@ int hsf_cd_advance(hsf_ctx *ctx, const double *mu, const double *u, int where);
 int hsf_step(hsf_ctx *ctx, int n_steps, double tol, int max_iter, hsf_invert_stats *stats,
              long long *total_evals);
 
+/* Integrator of the convection-diffusion update of hsf_step (section 2).
+ * HSF_CD_EXPLICIT (default): the explicit conservative step of hsf_cd_advance.
+ * HSF_CD_CRANK_NICOLSON: the diffusive part implicit (Crank-Nicolson), convection by
+ * the explicit two-step Lax-Wendroff flux and the noise of the step explicit:
+ *   phi^{n+1} = phi^n + dt/2 [B(phi^n, mu^n) + B(phi^{n+1}, mu^{n+1})] - div J^C(phi^n, u^n) + xi^n,
+ * B(phi, mu) = div(phi grad mu) with the face fluxes of the explicit step and
+ * mu^{n+1} = mu[phi^{n+1}] (eq. 4 at the self-consistent fields of phi^{n+1}).  The
+ * unknowns are those fields: phi^{n+1} = phi[w] with
+ *   F(w) = phi[w] - dt/2 B(phi[w], mu(phi[w], w)) - rhs = 0,
+ * solved for all replicas jointly by Newton's method with GMRES(krylov_dim) on
+ * forward-difference Jacobian products (one density-functional evaluation each),
+ * Krylov tolerance 1e-3 relative, corrections halved while they do not reduce ||F||,
+ * until rms(F) <= tol or max_newton iterations (then hsf_step returns HSF_ENOCONV and
+ * keeps the last iterate).  After the step the densities are phi[w^{n+1}] and the fields
+ * w^{n+1}, so the next step's inversion starts converged.  Needs an FP64 context (the
+ * finite differences need evaluations accurate far below the perturbation); HSF_EINVAL
+ * for FP32 contexts, tol <= 0, max_newton < 1 or krylov_dim outside [2, 64].  Device
+ * memory: (krylov_dim + 6) nsp T doubles, allocated at the first call. */
+enum { HSF_CD_EXPLICIT = 0, HSF_CD_CRANK_NICOLSON = 1 };
+int hsf_set_integrator(hsf_ctx *ctx, int scheme, double tol, int max_newton, int krylov_dim);
+
+typedef struct {
+    int newton;                  /* Newton iterations of the last Crank-Nicolson solve   */
+    int krylov;                  /* Jacobian products (GMRES iterations), all Newton steps */
+    long long evaluations;       /* density-functional evaluations, all replicas          */
+    double residual;             /* final rms of F                                        */
+    int converged;               /* residual <= tol                                       */
+} hsf_cn_stats;
+int hsf_get_cn_stats(const hsf_ctx *ctx, hsf_cn_stats *stats);
+
 /* Thermal noise (off by default).  flags: HSF_NOISE_CD adds the composition noise
  * xi_I of eq. 5 to every convection-diffusion update, HSF_NOISE_LB the mode noise
  * phi_k r_k of eq. 13 to every LB collision; omega > 0 is the noise scaling parameter

@@ -26,6 +26,15 @@ struct hsf_ctx {
     int noise = 0;                   // HSF_NOISE_* flags
     unsigned long long noise_step = 0;  // generator step word of the next noise draw
     double *noise_flux = nullptr;    // bond fluxes of the composition noise, 3 nsp T (allocated when first on)
+    // Crank-Nicolson diffusion (hsf_set_integrator); buffers of n = nsp T doubles
+    int integrator = HSF_CD_EXPLICIT;
+    double cn_tol = 1e-10, cn_eta = 1e-3;
+    int cn_max_newton = 20, cn_m = 40, cn_alloc_m = 0;
+    double *cn_rhs = nullptr, *cn_F = nullptr, *cn_Ft = nullptr, *cn_wbase = nullptr, *cn_half = nullptr;
+    double *cn_V = nullptr;          // Krylov basis, (m + 1) n
+    double *cn_part = nullptr, *cn_dots = nullptr, *cn_coef = nullptr;
+    double *cn_dots_h = nullptr;     // pinned host copy of the dot products
+    hsf_cn_stats cn_last{};
     Chain ch{};
     long long T = 0;                 // total sites over all replicas
     std::vector<Rep> reps;
@@ -544,6 +553,195 @@ int evaluate_impl(hsf_ctx *c)
     return HSF_OK;
 }
 
+// ---- Crank-Nicolson diffusion: Newton-Krylov solve for the fields of phi^{n+1} ----
+//
+// F(w) = phi[w] - dt/2 B(phi[w], mu(phi[w], w)) - rhs, rhs = phi^n + dt/2 B^n - div J^C + xi,
+// with B the diffusive rate of the explicit step's face fluxes.  Newton's method on the
+// fields of all replicas jointly; each correction from restarted GMRES(m) on the
+// forward-difference Jacobian J v = (F(w + eps v) - F(w)) / eps, classical Gram-Schmidt
+// applied twice, to ||J dw + F|| <= eta ||F||; the correction is halved (at most four
+// times) while it does not reduce ||F||.  F keeps each species' amount (its per-species
+// sums vanish) and is blind to per-species constants in w, so the Krylov vectors stay
+// in the zero-sum subspace.  Stops at rms(F) <= tol.
+
+long long cn_n(const hsf_ctx *c) { return (long long)c->ch.nsp * c->T; }
+
+// out_h[j] = <V_j, x>, j < k
+int cn_dots(hsf_ctx *c, const double *V, int k, const double *x, double *out_h)
+{
+    launch_dots(c->stream, V, k, cn_n(c), x, c->cn_part, c->cn_dots);
+    HIPCHK(c, hipMemcpyAsync(c->cn_dots_h, c->cn_dots, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+    int rc = sync(c);
+    if (rc) return rc;
+    for (int j = 0; j < k; ++j) out_h[j] = c->cn_dots_h[j];
+    return HSF_OK;
+}
+
+// y += sum_j coef_h[j] V_j
+int cn_axpy(hsf_ctx *c, double *y, const double *V, int k, const double *coef_h)
+{
+    for (int j = 0; j < k; ++j) c->cn_dots_h[j] = coef_h[j];
+    HIPCHK(c, hipMemcpyAsync(c->cn_coef, c->cn_dots_h, sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
+    launch_multi_axpy(c->stream, y, V, k, cn_n(c), c->cn_coef, 1.0);
+    HIPCHK(c, hipGetLastError());
+    return sync(c);   // the pinned staging buffer is reused by the next call
+}
+
+// F_out = F(current fields c->w); leaves phi[w] in eval_out
+int cn_residual(hsf_ctx *c, double *F_out, long long *evals)
+{
+    int rc = evaluate_impl(c);
+    if (rc) return rc;
+    for (int r = 0; r < c->n_rep; ++r)
+        if (c->st_h[r].nonfinite) return fail(c, HSF_ENONFINITE, "non-finite Q in replica %d", r);
+    *evals += c->n_rep;
+    c->work_evals += c->n_rep;
+    for (int r = 0; r < c->n_rep; ++r) c->work_site_evals += (double)c->reps[r].V;
+    launch_mu(c->stream, c->plan, c->rep_d, c->ch, c->eval_out, c->w, c->mu);
+    launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->eval_out, c->mu, nullptr, c->cn_half, nullptr, 0, nullptr,
+              nullptr, 0.5);
+    launch_cn_residual(c->stream, F_out, c->eval_out, c->cn_half, c->cn_rhs, cn_n(c));
+    HIPCHK(c, hipGetLastError());
+    return HSF_OK;
+}
+
+double cn_norm(hsf_ctx *c, const double *x, int *rc)
+{
+    double d = 0.0;
+    *rc = cn_dots(c, x, 1, x, &d);
+    return sqrt(d);
+}
+
+// Solve F(w) = 0 starting from the current fields; on success the fields hold w^{n+1}
+// and the densities phi[w^{n+1}].  c->cn_rhs must hold the right-hand side.
+int cn_solve(hsf_ctx *c, long long *evals_out)
+{
+    const long long n = cn_n(c);
+    const int m = c->cn_m;
+    const double rtn = sqrt((double)n);
+    hsf_cn_stats st{};
+    long long evals = 0;
+    int rc = cn_residual(c, c->cn_F, &evals);
+    if (rc) return rc;
+    double fnorm = cn_norm(c, c->cn_F, &rc);
+    if (rc) return rc;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    for (;;) {
+        st.residual = fnorm / rtn;
+        if (!std::isfinite(fnorm)) return fail(c, HSF_ENONFINITE, "non-finite Crank-Nicolson residual");
+        if (st.residual <= c->cn_tol) {
+            st.converged = 1;
+            break;
+        }
+        if (st.newton >= c->cn_max_newton) break;
+        ++st.newton;
+        const double wnorm = cn_norm(c, c->w, &rc);
+        if (rc) return rc;
+        const double eps = 1.4901161193847656e-8 * (1.0 + wnorm);   // sqrt(2^-52) (1 + ||w||)
+        // w_base: the Newton iterate; the Krylov basis spans corrections to it
+        HIPCHK(c, hipMemcpyAsync(c->cn_wbase, c->w, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+        // GMRES(m) for J dw = -F with x0 = 0
+        double beta = fnorm;
+        launch_lincomb(c->stream, c->cn_V, -1.0 / beta, c->cn_F, 0.0, c->cn_F, n);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            double *vj = c->cn_V + (long long)j * n, *vn = c->cn_V + (long long)(j + 1) * n;
+            // J v_j by a forward difference (v_j has unit norm)
+            launch_lincomb(c->stream, c->w, 1.0, c->cn_wbase, eps, vj, n);
+            if ((rc = cn_residual(c, c->cn_Ft, &evals))) return rc;
+            launch_lincomb(c->stream, vn, 1.0 / eps, c->cn_Ft, -1.0 / eps, c->cn_F, n);
+            ++st.krylov;
+            // classical Gram-Schmidt, twice, with the coefficients kept on the device; one
+            // copy of both coefficient sets and the norm to the host
+            const int stride = kMaxKrylov + 1;
+            double *d1 = c->cn_dots, *d2 = c->cn_dots + stride, *dn = c->cn_dots + 2 * stride;
+            launch_dots(c->stream, c->cn_V, j + 1, n, vn, c->cn_part, d1);
+            launch_multi_axpy(c->stream, vn, c->cn_V, j + 1, n, d1, -1.0);
+            launch_dots(c->stream, c->cn_V, j + 1, n, vn, c->cn_part, d2);
+            launch_multi_axpy(c->stream, vn, c->cn_V, j + 1, n, d2, -1.0);
+            launch_dots(c->stream, vn, 1, n, vn, c->cn_part, dn);
+            HIPCHK(c, hipMemcpyAsync(c->cn_dots_h, c->cn_dots, sizeof(double) * 3 * stride, hipMemcpyDeviceToHost,
+                                     c->stream));
+            if ((rc = sync(c))) return rc;
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = c->cn_dots_h[i] + c->cn_dots_h[stride + i];
+            const double hn = sqrt(c->cn_dots_h[2 * stride]);
+            H[(size_t)(j + 1) * m + j] = hn;
+            if (hn > 0.0) launch_lincomb(c->stream, vn, 1.0 / hn, vn, 0.0, vn, n);
+            // Givens rotations of the new column
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+            const double r = hypot(a, b);
+            cs[j] = r > 0.0 ? a / r : 1.0;
+            sn[j] = r > 0.0 ? b / r : 0.0;
+            H[(size_t)j * m + j] = r;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            if (fabs(g[j + 1]) <= c->cn_eta * beta || hn == 0.0) break;
+        }
+        // y = R^-1 g, dw = sum y_i v_i
+        for (int i = k - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int l = i + 1; l < k; ++l) t -= H[(size_t)i * m + l] * y[l];
+            y[i] = t / H[(size_t)i * m + i];
+        }
+        // trial w = w_base + lambda dw, halving lambda while ||F|| does not decrease
+        double lambda = 1.0;
+        for (int tries = 0;; ++tries) {
+            HIPCHK(c, hipMemcpyAsync(c->w, c->cn_wbase, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+            std::vector<double> ly(k);
+            for (int i = 0; i < k; ++i) ly[i] = lambda * y[i];
+            if ((rc = cn_axpy(c, c->w, c->cn_V, k, ly.data()))) return rc;
+            if ((rc = cn_residual(c, c->cn_Ft, &evals))) return rc;
+            const double fn = cn_norm(c, c->cn_Ft, &rc);
+            if (rc) return rc;
+            if ((std::isfinite(fn) && fn < fnorm) || tries == 4) {
+                fnorm = fn;
+                std::swap(c->cn_F, c->cn_Ft);
+                break;
+            }
+            lambda *= 0.5;
+        }
+    }
+    // eval_out holds phi at the accepted fields: the new densities
+    HIPCHK(c, hipMemcpyAsync(c->phi, c->eval_out, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    st.evaluations = evals;
+    c->cn_last = st;
+    if (evals_out) *evals_out += evals;
+    return st.converged ? HSF_OK : fail(c, HSF_ENOCONV, "Crank-Nicolson step: rms residual %.3e after %d Newton "
+                                                        "iterations", st.residual, st.newton);
+}
+
+int cn_alloc(hsf_ctx *c, int m)
+{
+    if (c->cn_alloc_m >= m) return HSF_OK;
+    const long long n = cn_n(c);
+    int rc = HSF_OK;
+    if (!c->cn_rhs) {
+        for (double **p : {&c->cn_rhs, &c->cn_F, &c->cn_Ft, &c->cn_wbase, &c->cn_half})
+            if (rc == HSF_OK) rc = dalloc(c, (void **)p, sizeof(double) * n);
+        if (rc == HSF_OK) rc = dalloc(c, (void **)&c->cn_dots, sizeof(double) * 3 * (kMaxKrylov + 1));
+        if (rc == HSF_OK) rc = dalloc(c, (void **)&c->cn_coef, sizeof(double) * (kMaxKrylov + 1));
+        if (rc == HSF_OK) rc = dalloc(c, (void **)&c->cn_part, sizeof(double) * (kMaxKrylov + 1) * vec_dot_blocks());
+        if (rc == HSF_OK && hipHostMalloc((void **)&c->cn_dots_h, sizeof(double) * 3 * (kMaxKrylov + 1),
+                                          hipHostMallocDefault) != hipSuccess)
+            rc = fail(c, HSF_ENOMEM, "hipHostMalloc failed");
+        if (rc) return rc;
+    }
+    // the Krylov basis grows to the largest dimension asked for (the old one is kept in
+    // the allocation list and freed with the context)
+    if ((rc = dalloc(c, (void **)&c->cn_V, sizeof(double) * (m + 1) * n))) return rc;
+    c->cn_alloc_m = m;
+    return HSF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -741,6 +939,7 @@ void hsf_destroy(hsf_ctx *c)
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (void *p : c->allocs) (void)hipFree(p);
     if (c->st_h) (void)hipHostFree(c->st_h);
+    if (c->cn_dots_h) (void)hipHostFree(c->cn_dots_h);
     delete c;
 }
 
@@ -936,6 +1135,17 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
             std::swap(c->nA, c->nB);
             uu = c->u;
         }
+        if (c->integrator == HSF_CD_CRANK_NICOLSON) {
+            // right-hand side phi^n + dt/2 B^n - div J^C + xi, then the implicit solve
+            launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, uu, c->cn_rhs,
+                      (c->noise & HSF_NOISE_CD) ? c->noise_flux : nullptr, c->noise_step, nullptr, nullptr, 0.5);
+            if (c->noise) ++c->noise_step;
+            long long ev = 0;
+            rc = cn_solve(c, &ev);
+            if (total_evals) *total_evals += ev;
+            if (rc != HSF_OK) return rc;
+            continue;
+        }
         {
             Timed t(c, HSF_K_CD);
             launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, uu, c->phi_tmp,
@@ -1103,6 +1313,36 @@ int hsf_get_work(hsf_ctx *c, long long *evals, double *site_evals, int reset)
         c->work_evals = 0;
         c->work_site_evals = 0.0;
     }
+    return HSF_OK;
+}
+
+int hsf_set_integrator(hsf_ctx *c, int scheme, double tol, int max_newton, int krylov_dim)
+{
+    if (!c) return HSF_EINVAL;
+    if (scheme == HSF_CD_EXPLICIT) {
+        c->integrator = scheme;
+        return HSF_OK;
+    }
+    if (scheme != HSF_CD_CRANK_NICOLSON) return fail(c, HSF_EINVAL, "unknown integrator %d", scheme);
+    if (c->precision != HSF_FP64)
+        return fail(c, HSF_EINVAL, "the Crank-Nicolson solve needs FP64 propagators (finite-difference Jacobian)");
+    if (!(tol > 0.0) || max_newton < 1 || krylov_dim < 2 || krylov_dim > kMaxKrylov)
+        return fail(c, HSF_EINVAL, "bad Crank-Nicolson parameters (tol %g, max_newton %d, krylov_dim %d)", tol,
+                    max_newton, krylov_dim);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int rc = cn_alloc(c, krylov_dim);
+    if (rc) return rc;
+    c->integrator = scheme;
+    c->cn_tol = tol;
+    c->cn_max_newton = max_newton;
+    c->cn_m = krylov_dim;
+    return HSF_OK;
+}
+
+int hsf_get_cn_stats(const hsf_ctx *c, hsf_cn_stats *st)
+{
+    if (!c || !st) return HSF_EINVAL;
+    *st = c->cn_last;
     return HSF_OK;
 }
 

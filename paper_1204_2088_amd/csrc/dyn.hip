@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, 
                                                const Rep *__restrict__ rep, Chain ch,
                                                const double *__restrict__ phi, const double *__restrict__ mu,
                                                const double *__restrict__ u, double *__restrict__ phi_out,
-                                               const double *__restrict__ jn)
+                                               const double *__restrict__ jn, double diff_scale)
 {
     const SiteRef sr = site_ref(blk_rep, blk_first);
     const Rep &R = rep[sr.r];
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, 
     const long long nb[6] = {sidx(R, wrap1(x - 1, R.Lx), y, z), sidx(R, wrap1(x + 1, R.Lx), y, z),
                              sidx(R, x, wrap1(y - 1, R.Ly), z), sidx(R, x, wrap1(y + 1, R.Ly), z),
                              sidx(R, x, y, wrap1(z - 1, R.Lz)), sidx(R, x, y, wrap1(z + 1, R.Lz))};
-    const double dt = R.dt;
+    const double dt = R.dt * diff_scale;   // diffusive flux over dt (or dt/2 in the CN step)
     for (int I = 0; I < ch.nsp; ++I) {
         const double *p = phi + fo + I * V;
         const double *m = mu + fo + I * V;
@@ -408,7 +408,7 @@ void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc,
 
 void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi, const double *mu,
                const double *u, double *phi_out, double *noise_flux, unsigned long long step, hipEvent_t e0,
-               hipEvent_t e1)
+               hipEvent_t e1, double diff_scale)
 {
     // with noise the events bracket both kernels: e0 at the start of the flux draw
     if (noise_flux) {
@@ -423,10 +423,10 @@ void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const dou
     auto kern = noise_flux ? k_cd<true> : k_cd<false>;
     if (e0 || e1)
         hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep,
-                              ch, phi, mu, u, phi_out, (const double *)noise_flux);
+                              ch, phi, mu, u, phi_out, (const double *)noise_flux, diff_scale);
     else
         hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch, phi, mu, u,
-                           phi_out, (const double *)noise_flux);
+                           phi_out, (const double *)noise_flux, diff_scale);
 }
 
 void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n)

@@ -119,11 +119,25 @@ void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc,
                const double *f, double *rho, double *u, bool noise, unsigned long long step,
                hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // noise_flux: scratch for the composition noise's bond fluxes (3 nsp T doubles), or null
-// for no noise
+// for no noise; diff_scale multiplies dt in the diffusive flux (1/2 in the CN step)
 void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi,
                const double *mu, const double *u, double *phi_out, double *noise_flux, unsigned long long step,
-               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, double diff_scale = 1.0);
 void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n);
+
+// vector kernels of the Crank-Nicolson Newton-Krylov solve (cn.hip); vectors of n doubles
+constexpr int kMaxKrylov = 64;
+int vec_dot_blocks();
+// out[j] = <V_j, x> for j < k (V: k vectors of n doubles); part: k * vec_dot_blocks() doubles
+void launch_dots(hipStream_t s, const double *V, int k, long long n, const double *x, double *part, double *out);
+// y += scale sum_j coef[j] V_j (coef: k doubles in device memory)
+void launch_multi_axpy(hipStream_t s, double *y, const double *V, int k, long long n, const double *coef,
+                       double scale);
+// out = a x + b y
+void launch_lincomb(hipStream_t s, double *out, double a, const double *x, double b, const double *y, long long n);
+// F = p - (half - p) - rhs
+void launch_cn_residual(hipStream_t s, double *F, const double *p, const double *half, const double *rhs,
+                        long long n);
 
 // observables: the free-energy density and order parameters of (w, phi) into
 // out[3 r .. 3 r + 2]; uses the Q, phibar and <exp(-w_S)> of the last evaluation in st.

@@ -30,7 +30,7 @@ EXPORTED = [
     "hsf_site_offset", "hsf_field_offset", "hsf_num_species", "hsf_set_fields", "hsf_get_fields",
     "hsf_set_densities", "hsf_get_densities", "hsf_evaluate", "hsf_observables", "hsf_invert", "hsf_mu_force",
     "hsf_set_lb", "hsf_get_lb", "hsf_lb_advance", "hsf_get_flow", "hsf_cd_advance", "hsf_step",
-    "hsf_set_hydro", "hsf_set_noise", "hsf_get_noise_step", "hsf_set_timing", "hsf_get_timing", "hsf_set_tile", "hsf_get_tile", "hsf_autotune",
+    "hsf_set_hydro", "hsf_set_noise", "hsf_get_noise_step", "hsf_set_integrator", "hsf_get_cn_stats", "hsf_set_timing", "hsf_get_timing", "hsf_set_tile", "hsf_get_tile", "hsf_autotune",
     "hsf_set_solver", "hsf_get_work", "hsf_set_warm", "hsf_net_create", "hsf_net_destroy",
     "hsf_net_last_error", "hsf_net_set_stream", "hsf_net_num_params", "hsf_net_set_params",
     "hsf_net_get_params", "hsf_net_set_input_norm", "hsf_net_set_output_scale", "hsf_net_forward", "hsf_net_loss_grad",
@@ -40,6 +40,7 @@ WARM_EXTRAP, WARM_NET, WARM_NET_DELTA, WARM_NET_EXTRAP = 2, 3, 4, 5
 SOLVER_PRECOND = 1
 LB_BGK, LB_MRT = 0, 1
 NOISE_CD, NOISE_LB = 1, 2
+CD_EXPLICIT, CD_CRANK_NICOLSON = 0, 1
 K_PREP, K_FWD, K_BWD, K_LB, K_CD, K_COUNT = 0, 1, 2, 3, 4, 5
 KERNEL_NAMES = ["prep", "fwd", "bwd", "lb", "cd"]
 
@@ -48,6 +49,14 @@ class HsfError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"hsf error {code}: {msg}")
         self.code = code
+
+
+class CnStats(ctypes.Structure):
+    _fields_ = [("newton", ctypes.c_int), ("krylov", ctypes.c_int), ("evaluations", ctypes.c_longlong),
+                ("residual", ctypes.c_double), ("converged", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Params(ctypes.Structure):
@@ -116,6 +125,8 @@ def load():
         "hsf_set_hydro": ([C, I], I),
         "hsf_set_noise": ([C, I, ctypes.c_double, ctypes.c_ulonglong, ctypes.c_ulonglong], I),
         "hsf_get_noise_step": ([C, ctypes.POINTER(ctypes.c_ulonglong)], I),
+        "hsf_set_integrator": ([C, I, ctypes.c_double, I, I], I),
+        "hsf_get_cn_stats": ([C, ctypes.POINTER(CnStats)], I),
         "hsf_set_timing": ([C, I], I),
         "hsf_set_solver": ([C, I], I),
         "hsf_set_warm": ([C, I], I),
@@ -339,6 +350,16 @@ class Context:
         ev = ctypes.c_longlong(0)
         self._check(self._lib.hsf_step(self._h, int(n_steps), float(tol), int(max_iter), st, ctypes.byref(ev)))
         return [s.as_dict() for s in st], ev.value
+
+    def set_integrator(self, crank_nicolson=True, tol=1e-10, max_newton=20, krylov_dim=40):
+        """Crank-Nicolson (implicit) or explicit diffusion in the coupled steps."""
+        scheme = CD_CRANK_NICOLSON if crank_nicolson else CD_EXPLICIT
+        self._check(self._lib.hsf_set_integrator(self._h, scheme, float(tol), int(max_newton), int(krylov_dim)))
+
+    def cn_stats(self):
+        st = CnStats()
+        self._check(self._lib.hsf_get_cn_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
 
     def set_noise(self, cd=True, lb=True, omega=400.0, seed=0, step=0):
         """Thermal noise: composition noise (eq. 5) and/or LB mode noise (eq. 13)."""

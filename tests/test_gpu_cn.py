@@ -1,0 +1,165 @@
+"""GPU parity of the Crank-Nicolson step (section 2: implicit diffusion of eq. 3) against
+the oracle, through the C ABI.
+
+The GPU solves F(w) = 0 by Newton-Krylov (GMRES on finite-difference Jacobian products),
+the oracle by Newton with the full finite-difference Jacobian: different algorithms for
+the same equation, so the comparison is of the solution.  Both solve to residuals near
+1e-12; the densities then agree to 1e-9 absolute (the solve's conditioning times the
+residuals), which the tests use.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1204_2088_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_PHI = 1e-9
+
+
+@pytest.fixture(scope="module")
+def hsf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1204_2088_amd import hsf as H
+    H.load()
+    return H
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def osys(orc, wl, **kw):
+    s = orc.System(L=wl.L, types=wl.types, has_solvent=wl.has_solvent, a=wl.a, chi=wl.chi,
+                   kappa=wl.kappa, dt=wl.dt, tau=wl.tau, hydro=wl.hydro)
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def melt(L, types=None, dt=0.4, hydro=False, seed=0):
+    types = types or W.chain(4, 4)
+    return W.Workload("cn_melt", L, types, False, W.chi_matrix(ab=20.0 / len(types)), tau=1.0, noise=0.05,
+                      seed=seed, precision="fp64", dt=dt, hydro=hydro)
+
+
+def solution(L, dt=0.2, hydro=True, seed=3):
+    return W.Workload("cn_sol", L, W.chain(3, 9), True, W.chi_matrix(ab=25 / 12, bs=35 / 12), tau=0.8,
+                      noise=0.01, seed=seed, phi_p=0.12, precision="fp64", dt=dt, hydro=hydro)
+
+
+def gauge(w, nsp):
+    w = w.reshape(nsp, -1)
+    return w - w.mean(axis=1, keepdims=True)
+
+
+def one_step(hsf, orc, wl, noise=False):
+    phi = W.initial_composition(wl)
+    w0 = -np.log(phi / phi.mean(axis=(1, 2, 3), keepdims=True))
+    ctx = hsf.Context(wl)
+    ctx.set_hydro(wl.hydro)
+    ctx.set_integrator(True, tol=1e-12, max_newton=30, krylov_dim=40)
+    kw = {}
+    if noise:
+        ctx.set_noise(cd=True, lb=True, omega=400.0, seed=17, step=0)
+        kw = dict(noise=3, omega=400.0, seed=17, step=0)
+    ctx.set_densities(phi.ravel())
+    ctx.set_fields(w0.ravel())
+    st, ev = ctx.step(1, tol=1e-12, max_iter=5000)
+    cs = ctx.cn_stats()
+    got = ctx.get_densities().reshape(phi.shape)
+    gw = ctx.get_fields()
+    n = None
+    if wl.hydro:
+        n = orc.lb_rest_state(osys(orc, wl))
+    ref, wref, nref, info = orc.cn_step(osys(orc, wl, **kw), phi, w0, n, tol=1e-13)
+    e = np.max(np.abs(got - ref))
+    ew = np.max(np.abs(gauge(gw, wl.nsp)[:2] - gauge(wref, wl.nsp)[:2]))
+    say(f"  gpu: {cs}; oracle: {info}")
+    say(f"  max |dphi| {e:.2e} (step changed phi by {np.max(np.abs(ref - phi)):.2e}), max |dw| {ew:.2e}")
+    assert cs["converged"] and cs["residual"] <= 1e-12
+    assert e < TOL_PHI and ew < 1e3 * TOL_PHI
+    # each species' amount is kept
+    assert np.max(np.abs(got.sum(axis=(1, 2, 3)) - phi.sum(axis=(1, 2, 3)))) < 1e-10
+    if wl.hydro:
+        assert np.max(np.abs(ctx.get_lb().reshape(nref.shape) - nref)) < 1e-13
+    ctx.close()
+
+
+def test_cn_step_melt(hsf, orc):
+    """8^3 A4B4 melt, dt = 0.4 (far beyond the explicit limit), no flow."""
+    say("[cn step] melt 8^3 a4b4 dt 0.4")
+    one_step(hsf, orc, melt((8, 8, 8)))
+
+
+def test_cn_step_ragged_solution_with_flow(hsf, orc):
+    """7x6x5 A3B9 + S solution, dt = 0.2, with the LB flow convecting explicitly."""
+    say("[cn step] solution 7x6x5 dt 0.2 hydro")
+    one_step(hsf, orc, solution((7, 6, 5)))
+
+
+def test_cn_step_with_noise(hsf, orc):
+    """6x5x7 A2B4 melt, dt = 0.4, LB flow, both thermal noises (Omega = 400)."""
+    say("[cn step] melt 6x5x7 a2b4 dt 0.4 hydro + noise")
+    one_step(hsf, orc, melt((6, 5, 7), W.chain(2, 4), hydro=True), noise=True)
+
+
+def test_cn_batched_replicas(hsf, orc):
+    """Two replicas of different boxes solved jointly: each matches its own oracle step."""
+    wls = [melt((8, 6, 5), seed=1), melt((5, 7, 6), seed=2)]
+    say("[cn batched]")
+    phis = [W.initial_composition(w) for w in wls]
+    w0s = [-np.log(p / p.mean(axis=(1, 2, 3), keepdims=True)) for p in phis]
+    ctx = hsf.Context(wls)
+    ctx.set_hydro(False)
+    ctx.set_integrator(True, tol=1e-12, max_newton=30, krylov_dim=40)
+    ctx.set_densities(np.concatenate([p.ravel() for p in phis]))
+    ctx.set_fields(np.concatenate([w.ravel() for w in w0s]))
+    ctx.step(1, tol=1e-12, max_iter=5000)
+    got = ctx.get_densities()
+    off = 0
+    for r, wl in enumerate(wls):
+        ref, _, _, info = orc.cn_step(osys(orc, wl), phis[r], w0s[r], tol=1e-13)
+        g = got[off:off + ref.size].reshape(ref.shape)
+        off += ref.size
+        e = np.max(np.abs(g - ref))
+        say(f"  replica {r} L={wl.L}: max |dphi| {e:.2e}")
+        assert e < TOL_PHI
+    ctx.close()
+
+
+def test_cn_trajectory_matches_explicit(hsf, orc):
+    """16^3 A4B4 melt to t = 2: five Crank-Nicolson steps of dt = 0.4 against 200
+    explicit steps of dt = 0.01 on the GPU; the difference is a small fraction of the
+    composition change (second-order time error), and the implicit run needs far fewer
+    density-functional evaluations."""
+    wl = melt((16, 16, 16))
+    phi0 = W.initial_composition(wl)
+    say("[cn trajectory] melt 16^3 a4b4, t = 2")
+
+    def run(cn, dt, steps):
+        ctx = hsf.Context(wl.with_(dt=dt))
+        ctx.set_hydro(False)
+        if cn:
+            ctx.set_integrator(True, tol=1e-10, max_newton=30, krylov_dim=40)
+        ctx.set_densities(phi0.ravel())
+        total = 0
+        for _ in range(steps):
+            st, ev = ctx.step(1, tol=1e-10, max_iter=5000)
+            total += ev
+        p = ctx.get_densities().reshape(phi0.shape)
+        ctx.close()
+        return p, total
+
+    pc, ec = run(True, 0.4, 5)
+    pe, ee = run(False, 0.01, 200)
+    change = np.max(np.abs(pe - phi0))
+    d = np.max(np.abs(pc - pe))
+    say(f"  max |CN - explicit| {d:.3e}, change {change:.3e}; evaluations CN {ec}, explicit {ee}")
+    assert d < 0.02 * change
+    assert ec < ee / 3
