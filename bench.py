@@ -192,6 +192,38 @@ def run_arm(hsf, torch, wls, steps, warmup, timing, log, precond=False, tile=Non
     return ctx, tile, tune_ms, stats, (evals, site_evals), elapsed, timing_out, t_steps, t_elapsed
 
 
+def cn_arm(hsf, torch, wls, dt, steps, warmup, log):
+    """Crank-Nicolson diffusion (FP64 propagators, Newton-Krylov) at a large time step on
+    the same workload: simulated time per wall-clock second, to set against the explicit
+    scheme's dt / ms_per_step."""
+    from paper_1204_2088_amd import workloads as W
+    wls = [w.with_(precision="fp64", dt=dt) for w in wls]
+    ctx = hsf.Context(wls, stream=torch.cuda.current_stream())
+    ctx.set_integrator(True, tol=1e-8, max_newton=30, krylov_dim=40)
+    ctx.set_densities(torch.from_numpy(np.concatenate([W.initial_composition(w).ravel() for w in wls])).to("cuda"))
+    tile, _ = ctx.autotune(reps=3)
+    ctx.step(warmup, tol=1e-9, max_iter=4000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    newton = krylov = 0
+    evals = 0
+    for _ in range(steps):
+        _, ev = ctx.step(1, tol=1e-9, max_iter=4000)
+        cs = ctx.cn_stats()
+        newton += cs["newton"]
+        krylov += cs["krylov"]
+        evals += ev
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    f, sm, _ = ctx.observables()
+    ctx.close()
+    log(f"# crank-nicolson dt {dt}: {1e3 * el / steps:.2f} ms per step, {evals / steps:.1f} evaluations")
+    return {"dt": dt, "steps": steps, "ms_per_step": 1e3 * el / steps, "evals_per_step": evals / steps,
+            "newton_per_step": newton / steps, "krylov_per_step": krylov / steps,
+            "sim_time_per_s": dt * steps / el, "propagators": "fp64", "newton_tol_rms": 1e-8,
+            "tile": list(tile), "free_energy_end": f.tolist()[:8], "s_melt_end": sm.tolist()[:8]}
+
+
 def measure_observables(ctx, torch, wl, V_total, reps=10):
     """Free-energy density and order parameters of the final state, and the cost of the
     call: each runs one evaluation (for Q) and two FP64 site passes, so the passes cost
@@ -233,6 +265,8 @@ def main():
     ap.add_argument("--lb", default="bgk", choices=["bgk", "mrt"],
                     help="LB collision: BGK, or the MRT scheme with the shear viscosity of the workload's tau, "
                          "the same bulk eigenvalue and the kinetic modes relaxed completely")
+    ap.add_argument("--no-cn-arm", action="store_true", help="skip the Crank-Nicolson (dt 0.4) arm")
+    ap.add_argument("--cn-dt", type=float, default=0.4, help="time step of the Crank-Nicolson arm")
     ap.add_argument("--noise", type=float, default=None, metavar="OMEGA",
                     help="thermal noise in both the compositions (eq. 5) and the LB modes (eq. 13) "
                          "with noise scaling parameter OMEGA (the paper uses 400)")
@@ -352,6 +386,12 @@ def main():
                     "tol": wls64[0].tol, "tile": list(tile64)}
         c64.close()
 
+    cn = None
+    if not args.no_cn_arm and args.workload.startswith("melt64"):
+        cn = cn_arm(hsf, torch, wls, args.cn_dt, 5, 1, log)
+        cn["explicit_sim_time_per_s"] = wl.dt * args.steps / elapsed
+        cn["speedup_sim_time"] = cn["sim_time_per_s"] / cn["explicit_sim_time_per_s"]
+
     learned = None
     if args.workload in LEARNED and not args.no_learned:
         learned = learned_arm(hsf, args.workload, args.precision, args.steps, args.warmup, tuple(tile), log,
@@ -387,6 +427,7 @@ def main():
         "fp64_arm": fp64_arm,
         "learned_warm_start": learned,
         "observables": observables,
+        "crank_nicolson": cn,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
