@@ -243,8 +243,9 @@ int hsf_step(hsf_ctx *ctx, int n_steps, double tol, int max_iter, hsf_invert_sta
  * forward-difference Jacobian products (one density-functional evaluation each),
  * Krylov tolerance 1e-3 relative, corrections halved while they do not reduce ||F||,
  * until rms(F) <= tol or max_newton iterations (then hsf_step returns HSF_ENOCONV and
- * keeps the last iterate).  After the step the densities are phi[w^{n+1}] and the fields
- * w^{n+1}, so the next step's inversion starts converged.  Needs an FP64 context (the
+ * keeps the last iterate).  Newton starts from w^n.  After the step the densities are
+ * phi[w^{n+1}] and the fields w^{n+1}, so the next step's inversion starts converged
+ * (with Crank-Nicolson it always starts from the current fields).  Needs an FP64 context (the
  * finite differences need evaluations accurate far below the perturbation); HSF_EINVAL
  * for FP32 contexts, tol <= 0, max_newton < 1 or krylov_dim outside [2, 64].  Device
  * memory: (krylov_dim + 6) nsp T doubles, allocated at the first call. */

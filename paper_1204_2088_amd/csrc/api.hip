@@ -1121,7 +1121,10 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
     if (!c || n_steps < 0) return HSF_EINVAL;
     if (total_evals) *total_evals = 0;
     for (int k = 0; k < n_steps; ++k) {
-        int rc = invert_impl(c, tol, max_iter, c->step_warm, stats, total_evals);
+        // with Crank-Nicolson the fields of phi^n are already converged (phi^n = phi[w^n]
+        // after an implicit step): the inversion only confirms them
+        const bool implicit = c->integrator == HSF_CD_CRANK_NICOLSON;
+        int rc = invert_impl(c, tol, max_iter, implicit ? HSF_WARM_CURRENT : c->step_warm, stats, total_evals);
         if (rc != HSF_OK) return rc;
         launch_mu(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->w, c->mu);
         const double *uu = nullptr;

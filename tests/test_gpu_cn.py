@@ -163,3 +163,4 @@ def test_cn_trajectory_matches_explicit(hsf, orc):
     say(f"  max |CN - explicit| {d:.3e}, change {change:.3e}; evaluations CN {ec}, explicit {ee}")
     assert d < 0.02 * change
     assert ec < ee / 3
+
