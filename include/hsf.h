@@ -245,10 +245,14 @@ int hsf_step(hsf_ctx *ctx, int n_steps, double tol, int max_iter, hsf_invert_sta
  * until rms(F) <= tol or max_newton iterations (then hsf_step returns HSF_ENOCONV and
  * keeps the last iterate).  Newton starts from w^n.  After the step the densities are
  * phi[w^{n+1}] and the fields w^{n+1}, so the next step's inversion starts converged
- * (with Crank-Nicolson it always starts from the current fields).  Needs an FP64 context (the
- * finite differences need evaluations accurate far below the perturbation); HSF_EINVAL
- * for FP32 contexts, tol <= 0, max_newton < 1 or krylov_dim outside [2, 64].  Device
- * memory: (krylov_dim + 6) nsp T doubles, allocated at the first call. */
+ * (with Crank-Nicolson it always starts from the current fields).  The forward-difference
+ * step is sqrt(2^-52) (1 + ||w||) with FP64 propagators; with FP32 propagators it is
+ * 1e-4 (1 + ||w||), so that the evaluation's rounding stays small against the difference,
+ * and the residual stalls at a few 1e-6 (the FP32 evaluation error carried through the
+ * compressibility and the diffusive stencil): tol >= 1e-5 there.
+ * HSF_EINVAL for tol <= 0 (or below 1e-5 with FP32 propagators), max_newton < 1 or
+ * krylov_dim outside [2, 64].  Device memory: (krylov_dim + 6) nsp T doubles, allocated
+ * at the first call. */
 enum { HSF_CD_EXPLICIT = 0, HSF_CD_CRANK_NICOLSON = 1 };
 int hsf_set_integrator(hsf_ctx *ctx, int scheme, double tol, int max_newton, int krylov_dim);
 

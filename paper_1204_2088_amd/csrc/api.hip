@@ -637,7 +637,10 @@ int cn_solve(hsf_ctx *c, long long *evals_out)
         ++st.newton;
         const double wnorm = cn_norm(c, c->w, &rc);
         if (rc) return rc;
-        const double eps = 1.4901161193847656e-8 * (1.0 + wnorm);   // sqrt(2^-52) (1 + ||w||)
+        // forward-difference step: sqrt(2^-52) (1 + ||w||) with FP64 propagators; with FP32
+        // ones the evaluation's rounding (about 1e-7 relative) needs a step large enough
+        // that it stays a small part of the difference: 1e-4 (1 + ||w||)
+        const double eps = (c->precision == HSF_FP64 ? 1.4901161193847656e-8 : 1e-4) * (1.0 + wnorm);
         // w_base: the Newton iterate; the Krylov basis spans corrections to it
         HIPCHK(c, hipMemcpyAsync(c->cn_wbase, c->w, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
         // GMRES(m) for J dw = -F with x0 = 0
@@ -1327,8 +1330,8 @@ int hsf_set_integrator(hsf_ctx *c, int scheme, double tol, int max_newton, int k
         return HSF_OK;
     }
     if (scheme != HSF_CD_CRANK_NICOLSON) return fail(c, HSF_EINVAL, "unknown integrator %d", scheme);
-    if (c->precision != HSF_FP64)
-        return fail(c, HSF_EINVAL, "the Crank-Nicolson solve needs FP64 propagators (finite-difference Jacobian)");
+    if (c->precision != HSF_FP64 && tol < 1e-5)
+        return fail(c, HSF_EINVAL, "with FP32 propagators the Crank-Nicolson tolerance must be at least 1e-5");
     if (!(tol > 0.0) || max_newton < 1 || krylov_dim < 2 || krylov_dim > kMaxKrylov)
         return fail(c, HSF_EINVAL, "bad Crank-Nicolson parameters (tol %g, max_newton %d, krylov_dim %d)", tol,
                     max_newton, krylov_dim);

@@ -164,3 +164,45 @@ def test_cn_trajectory_matches_explicit(hsf, orc):
     assert d < 0.02 * change
     assert ec < ee / 3
 
+
+
+def test_cn_fp32_propagators(hsf):
+    """With FP32 propagators the Newton solve converges to rms(F) <= 1e-5 and lands within
+    that of the FP64 solution (16^3 melt, three steps of dt 0.4), far inside the time
+    discretisation error at this step (about 2e-4 after five steps)."""
+    wl = melt((16, 16, 16))
+    phi0 = W.initial_composition(wl)
+    say("[cn fp32] melt 16^3 a4b4 dt 0.4")
+    out = {}
+    for prec, tol in (("fp64", 1e-11), ("fp32", 1e-5)):
+        ctx = hsf.Context(wl.with_(precision=prec))
+        ctx.set_hydro(False)
+        ctx.set_integrator(True, tol=tol, max_newton=30, krylov_dim=40)
+        ctx.set_densities(phi0.ravel())
+        evs = []
+        for _ in range(3):
+            _, ev = ctx.step(1, tol=1e-6 if prec == "fp32" else 1e-11, max_iter=5000)
+            evs.append(ev)
+            assert ctx.cn_stats()["converged"]
+        out[prec] = (ctx.get_densities(), evs)
+        ctx.close()
+    d = np.max(np.abs(out["fp32"][0] - out["fp64"][0]))
+    say(f"  max |phi32 - phi64| {d:.2e}; evaluations fp64 {out['fp64'][1]}, fp32 {out['fp32'][1]}")
+    assert d < 5e-5
+
+
+def test_cn_rejects_bad_parameters(hsf):
+    """Error paths of the integrator and noise settings (host-side checks, no kernel runs)."""
+    wl32 = melt((6, 6, 6)).with_(precision="fp32")
+    ctx = hsf.Context(wl32)
+    for args in [dict(tol=1e-6), dict(tol=0.0), dict(max_newton=0), dict(krylov_dim=1), dict(krylov_dim=65)]:
+        kw = dict(tol=1e-5, max_newton=20, krylov_dim=40)
+        kw.update(args)
+        with pytest.raises(hsf.HsfError):
+            ctx.set_integrator(True, **kw)
+    with pytest.raises(hsf.HsfError):
+        ctx.set_noise(cd=True, lb=False, omega=0.0)
+    with pytest.raises(hsf.HsfError):
+        ctx.set_noise(cd=True, lb=True, omega=float("nan"))
+    ctx.set_integrator(False)
+    ctx.close()
