@@ -306,7 +306,7 @@ int set_tile(hsf_ctx *c, const TileCfg &t)
     HIPCHK(c, hipMemcpy(c->tplan.blk_first, bf.data(), sizeof(int) * bf.size(), hipMemcpyHostToDevice));
     c->tplan.nblocks = (int)br.size();
     c->tplan.n_rep = c->n_rep;
-    c->tplan.rep0 = c->reps[0];
+    set_plan_args(c->tplan, c->reps.data(), c->n_rep, bf.data());
     c->tile = t;
     for (auto &g : c->graphs)
         if (g.exec) {
@@ -817,7 +817,7 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     c->T = off;
     c->plan.nblocks = (int)blk_rep.size();
     c->plan.n_rep = n_rep;
-    c->plan.rep0 = c->reps[0];
+    set_plan_args(c->plan, c->reps.data(), n_rep, blk_first.data());
     {
         std::vector<int> br, bf;
 #define HSF_SIZE(CX, CY, CZ, K)                                             \
@@ -1367,8 +1367,8 @@ int hsf_set_noise(hsf_ctx *c, int flags, double omega, unsigned long long seed, 
         R.seed = seed;
     }
     HIPCHK(c, hipMemcpy(c->rep_d, c->reps.data(), sizeof(Rep) * c->n_rep, hipMemcpyHostToDevice));
-    c->plan.rep0 = c->reps[0];
-    c->tplan.rep0 = c->reps[0];
+    for (Plan *pl : {&c->plan, &c->tplan})
+        for (int r = 0; r < pl->args.n; ++r) pl->args.rep[r] = c->reps[r];
     c->noise = flags;
     c->noise_step = step;
     return HSF_OK;

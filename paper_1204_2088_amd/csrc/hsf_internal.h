@@ -48,15 +48,35 @@ struct RepState {
     int scale_e[64];             // per-step power-of-two exponents e_s (G_s /= 2^e_s)
 };
 
+// The replicas of a small batch by value: the hot kernels take them as kernel arguments,
+// so a block finds its replica and geometry without dependent loads from device memory
+// before its first data load (each such load costs a trip to the last-level cache at
+// the start of a kernel).  Larger batches read the tables in device memory.
+constexpr int kArgReps = 4;
+struct ArgReps {
+    int n;                       // replicas, or 0 when the batch is larger than kArgReps
+    int blk_first[kArgReps + 1]; // first block of each replica in the plan
+    Rep rep[kArgReps];
+};
+
 // Launch plan of a site kernel: each block covers kBlock consecutive sites of one replica.
 struct Plan {
     int nblocks = 0;
     int *blk_rep = nullptr;      // device: replica of each block
     int *blk_first = nullptr;    // device: first block of each replica, n_rep + 1 entries
     int n_rep = 0;
-    Rep rep0{};                  // replica 0 by value: kernels of a one-replica context read
-                                 // their geometry from the kernel arguments, not from memory
+    ArgReps args{};              // the batch by value when n_rep <= kArgReps
 };
+
+// Fill p.args from the host copies of the replicas and the plan's block offsets.
+inline void set_plan_args(Plan &p, const Rep *reps, int n_rep, const int *blk_first_host)
+{
+    p.args = ArgReps{};
+    if (n_rep > kArgReps) return;
+    p.args.n = n_rep;
+    for (int r = 0; r < n_rep; ++r) p.args.rep[r] = reps[r];
+    for (int r = 0; r <= n_rep; ++r) p.args.blk_first[r] = blk_first_host[r];
+}
 
 // Chain architecture passed by value to kernels.
 struct Chain {

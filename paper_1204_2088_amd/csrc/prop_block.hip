@@ -363,33 +363,71 @@ __global__ __launch_bounds__(kBlock) void k_bwd_block(const int *__restrict__ bl
     }
 }
 
+// Replica of plan block pb and its descriptor, from a batch in the kernel arguments
+// (constant indices only, so the descriptor stays in scalar registers).
+__device__ __forceinline__ int arg_replica(const ArgReps &a, int pb)
+{
+    int r = 0;
+#pragma unroll
+    for (int k = 1; k < kArgReps; ++k)
+        if (k < a.n && pb >= a.blk_first[k]) r = k;
+    return r;
+}
+
+// The active flag of replica r as a vector load: its wait then joins the data loads of
+// the step (a scalar load's result is waited for as soon as it is tested, which would put
+// a round trip to memory before the first data load).
+__device__ __forceinline__ int active_vec(const RepState *st, int r)
+{
+    return __hip_atomic_load(const_cast<int *>(&st[r].active), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ Rep arg_rep(const ArgReps &a, int r)
+{
+    static_assert(kArgReps == 4, "arg_rep selects among four replicas");
+    return r == 0 ? a.rep[0] : (r == 1 ? a.rep[1] : (r == 2 ? a.rep[2] : a.rep[3]));
+}
+
 // E = exp(-(w + alpha d)) of the polymer species, all sites of the active replicas.
-template <typename real, bool SINGLE>
+// ARGS: the batch is in the kernel arguments; the replica's active flag is then read
+// alongside the fields and checked before the store.
+template <typename real, bool ARGS>
 __global__ __launch_bounds__(kBlock) void k_field_exp(const int *__restrict__ blk_rep,
                                                       const int *__restrict__ blk_first,
                                                       const Rep *__restrict__ rep,
                                                       const RepState *__restrict__ st, Chain ch,
                                                       const double *__restrict__ w, const double *__restrict__ d,
-                                                      int use_alpha, real *__restrict__ E, Rep rep0)
+                                                      int use_alpha, real *__restrict__ E, ArgReps ar)
 {
-    SiteRef sr;
-    if (SINGLE) {
-        sr.r = 0;
-        sr.i = (long long)plan_block() * kBlock + threadIdx.x;
+    int r;
+    long long i;
+    Rep R;
+    int act = 1;   // read without a branch, tested before the store
+    if (ARGS) {
+        const int pb = plan_block();
+        r = arg_replica(ar, pb);
+        R = arg_rep(ar, r);
+        i = (long long)(pb - ar.blk_first[r]) * kBlock + threadIdx.x;
+        act = active_vec(st, r) | (ar.n == 1);
     } else {
-        sr = site_ref(blk_rep, blk_first);
-        if (!st[sr.r].active) return;
+        const SiteRef sr = site_ref(blk_rep, blk_first);
+        r = sr.r;
+        i = sr.i;
+        if (!st[r].active) return;
+        R = rep[r];
     }
-    const Rep &R = SINGLE ? rep0 : rep[sr.r];
-    const long long V = R.V, i = sr.i;
+    const long long V = R.V;
     if (i >= V) return;
     const long long fo = off_field(R, ch.nsp), po = off_poly(R);
-    const double alpha = use_alpha ? st[sr.r].alpha : 0.0;
+    double x[2];
+#pragma unroll
+    for (int I = 0; I < 2; ++I) x[I] = w[fo + I * V + i];
+    const double alpha = use_alpha ? st[r].alpha : 0.0;
+    if (!act) return;
 #pragma unroll
     for (int I = 0; I < 2; ++I) {
-        double x = w[fo + I * V + i];
-        if (use_alpha) x = fma(alpha, d[po + I * V + i], x);
-        E[po + I * V + i] = (real)exp(-x);
+        if (use_alpha) x[I] = fma(alpha, d[po + I * V + i], x[I]);
+        E[po + I * V + i] = (real)exp(-x[I]);
     }
 }
 
@@ -399,28 +437,35 @@ __global__ __launch_bounds__(kBlock) void k_field_exp(const int *__restrict__ bl
 // every plane it touches, the in-plane class sums (centre, 4 edge-sharing, 4 corner
 // neighbours: 9 loads) once and combines three consecutive planes per site, so a site
 // costs 9 (CZ + 2) / CZ loads instead of 27.
-// Tile of this block for the direct kernels.  SINGLE: one replica whose descriptor is a
-// kernel argument (no dependent loads before the stencil), and it is active whenever a
-// kernel is launched.
-template <int CX, int CY, int CZ, bool SINGLE>
-__device__ __forceinline__ bool direct_tile(const int *blk_rep, const int *blk_first, const Rep *rep,
-                                            const RepState *st, const Rep &rep0, int &r, const Rep *&R, int &x0,
-                                            int &y0, int &z0)
+// Tile of this block for the direct kernels and whether its replica is active.  ARGS:
+// the batch is in the kernel arguments, so the stencil's loads need no dependent load
+// before them; a one-replica context is active whenever a kernel is launched, the flag
+// of a larger batch is loaded alongside the data and checked before the first store
+// (the caller returns then, uniformly for the block).  Otherwise the tile plan and the
+// descriptors come from device memory and an inactive replica returns at once.
+template <int CX, int CY, int CZ, bool ARGS>
+__device__ __forceinline__ void direct_tile(const int *blk_rep, const int *blk_first, const Rep *rep,
+                                            const RepState *st, const ArgReps &ar, int &r, Rep &R, int &x0,
+                                            int &y0, int &z0, int &act)
 {
-    if (SINGLE) {
-        r = 0;
-        R = &rep0;
-        const int ntx = (rep0.Lx + CX - 1) / CX, nty = (rep0.Ly + CY - 1) / CY;
-        int lb = plan_block();
-        x0 = (lb % ntx) * CX;
-        lb /= ntx;
-        y0 = (lb % nty) * CY;
-        z0 = (lb / nty) * CZ;
-        return true;
+    const int pb = plan_block();
+    int lb;
+    if (ARGS) {
+        r = arg_replica(ar, pb);
+        R = arg_rep(ar, r);
+        lb = pb - ar.blk_first[r];
+        act = active_vec(st, r) | (ar.n == 1);   // no branch: the wait comes at the test
+    } else {
+        r = blk_rep[pb];
+        R = rep[r];
+        lb = pb - blk_first[r];
+        act = st[r].active;
     }
-    tile_of<CX, CY, CZ>(blk_rep, blk_first, rep, r, x0, y0, z0);
-    R = &rep[r];
-    return st[r].active != 0;
+    const int ntx = (R.Lx + CX - 1) / CX, nty = (R.Ly + CY - 1) / CY;
+    x0 = (lb % ntx) * CX;
+    lb /= ntx;
+    y0 = (lb % nty) * CY;
+    z0 = (lb / nty) * CZ;
 }
 
 // In-plane class sums of f around (x, y) in plane z (9 loads).
@@ -449,10 +494,19 @@ __device__ __forceinline__ void column_stencil(const real *__restrict__ f, int x
         return;
     }
     real a0[CZ + 2], a1[CZ + 2], a2[CZ + 2];
+    // planes z0 - 1 .. z0 + nz.  Short columns (CZ <= 2, the latency-bound small boxes):
+    // past a short last chunk the plane index is clamped rather than branched on, so the
+    // loads of every plane are issued together and wait once (values past the chunk are
+    // not used).  Longer columns load plane by plane: issuing all of them at once costs
+    // registers, and the occupancy that large boxes need to hide memory latency.
 #pragma unroll
     for (int q = 0; q < CZ + 2; ++q) {
-        a0[q] = a1[q] = a2[q] = (real)0;
-        if (q <= nz + 1) plane_sums<real>(f, x, y, wrap1(z0 - 1 + q, R.Lz), R.Lx, R.Ly, a0[q], a1[q], a2[q]);
+        if (CZ <= 2) {
+            plane_sums<real>(f, x, y, wrap1(min(z0 - 1 + q, z0 + nz), R.Lz), R.Lx, R.Ly, a0[q], a1[q], a2[q]);
+        } else {
+            a0[q] = a1[q] = a2[q] = (real)0;
+            if (q <= nz + 1) plane_sums<real>(f, x, y, wrap1(z0 - 1 + q, R.Lz), R.Lx, R.Ly, a0[q], a1[q], a2[q]);
+        }
     }
 #pragma unroll
     for (int j = 0; j < CZ; ++j)
@@ -460,40 +514,52 @@ __device__ __forceinline__ void column_stencil(const real *__restrict__ f, int x
                c3 * (a2[j] + a2[j + 2]);
 }
 
-template <typename real, int CX, int CY, int CZ, bool SINGLE>
+template <typename real, int CX, int CY, int CZ, bool ARGS>
 __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ blk_rep,
                                                        const int *__restrict__ blk_first,
                                                        const Rep *__restrict__ rep,
                                                        const RepState *__restrict__ st, Chain ch, int s,
                                                        PropBufs<real> b, double *__restrict__ partG, int nblocks,
-                                                       int sums, Rep rep0)
+                                                       int sums, ArgReps ar)
 {
     static_assert(CX * CY == kBlock, "one column per thread");
     int r, x0, y0, z0;
-    const Rep *Rp;
-    if (!direct_tile<CX, CY, CZ, SINGLE>(blk_rep, blk_first, rep, st, rep0, r, Rp, x0, y0, z0)) return;
-    const Rep &R = *Rp;
+    Rep R;
+    int act;
+    direct_tile<CX, CY, CZ, ARGS>(blk_rep, blk_first, rep, st, ar, r, R, x0, y0, z0, act);
+    if (!ARGS && !act) return;
     const int V = (int)R.V;
     const int x = x0 + (int)threadIdx.x % CX, y = y0 + (int)threadIdx.x / CX;
     const int nz = min(CZ, R.Lz - z0);
+    const bool in = x < R.Lx && y < R.Ly;
     real *G = b.G + (long long)ch.N * R.site_off;
     const real *E = b.E + off_poly(R);
-    double gsum = 0.0, esum[2] = {0.0, 0.0};
-    if (x < R.Lx && y < R.Ly) {
-        real S[CZ];
+    const real *Es = E + ch.types[s - 1] * V;
+    // all loads of the step before the active check and the stores
+    real S[CZ], Ev[CZ];
+#pragma unroll
+    for (int j = 0; j < CZ; ++j) S[j] = Ev[j] = (real)0;
+    if (in) {
         if (s == 1) {
 #pragma unroll
             for (int j = 0; j < CZ; ++j) S[j] = (real)R.csum;
         } else {
             column_stencil<real, CZ>(G + (long long)(s - 2) * V, x, y, z0, nz, R, S);
         }
-        const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
-        const real *Es = E + ch.types[s - 1] * V;
+        if (CZ <= 2) {   // short columns: the field factors join the stencil's loads
+#pragma unroll
+            for (int j = 0; j < CZ; ++j) Ev[j] = Es[x + R.Lx * (y + R.Ly * min(z0 + j, z0 + nz - 1))];
+        }
+    }
+    const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
+    if (!act) return;   // uniform for the block
+    double gsum = 0.0, esum[2] = {0.0, 0.0};
+    if (in) {
 #pragma unroll
         for (int j = 0; j < CZ; ++j) {
             if (j >= nz) break;
             const int site = x + R.Lx * (y + R.Ly * (z0 + j));
-            const real g = Es[site] * S[j] * sc;
+            const real g = (CZ <= 2 ? Ev[j] : Es[site]) * S[j] * sc;
             G[(long long)(s - 1) * V + site] = g;
             gsum += (double)g;
             if (s == 1 && sums) {
@@ -514,7 +580,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ b
     }
 }
 
-template <typename real, int CX, int CY, int CZ, bool SINGLE>
+template <typename real, int CX, int CY, int CZ, bool ARGS>
 __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ blk_rep,
                                                        const int *__restrict__ blk_first,
                                                        const Rep *__restrict__ rep,
@@ -523,30 +589,47 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ b
                                                        real *__restrict__ gout, double *__restrict__ acc,
                                                        int final_mode, const double *__restrict__ phit,
                                                        const double *__restrict__ d, double *__restrict__ out,
-                                                       double *__restrict__ part, Rep rep0)
+                                                       double *__restrict__ part, ArgReps ar)
 {
     static_assert(CX * CY == kBlock, "one column per thread");
     int r, x0, y0, z0;
-    const Rep *Rp;
-    if (!direct_tile<CX, CY, CZ, SINGLE>(blk_rep, blk_first, rep, st, rep0, r, Rp, x0, y0, z0)) return;
-    const Rep &R = *Rp;
+    Rep R;
+    int act;
+    direct_tile<CX, CY, CZ, ARGS>(blk_rep, blk_first, rep, st, ar, r, R, x0, y0, z0, act);
+    if (!ARGS && !act) return;
     const int V = (int)R.V;
     const int N = ch.N;
     const int ts = ch.types[s - 1];
     const int x = x0 + (int)threadIdx.x % CX, y = y0 + (int)threadIdx.x / CX;
     const int nz = min(CZ, R.Lz - z0);
-    double sums[4] = {0.0, 0.0, 0.0, 0.0};
-    if (x < R.Lx && y < R.Ly) {
-        const long long po = off_poly(R);
-        real S[CZ];
+    const bool in = x < R.Lx && y < R.Ly;
+    const long long po = off_poly(R);
+    real *G = b.G + (long long)N * R.site_off;
+    // the step's loads (stencil, field factor, stored G_s) before the active check
+    real S[CZ], Ev[CZ], Gv[CZ];
+#pragma unroll
+    for (int j = 0; j < CZ; ++j) S[j] = Ev[j] = Gv[j] = (real)0;
+    if (in) {
         if (s == N) {
 #pragma unroll
             for (int j = 0; j < CZ; ++j) S[j] = (real)R.csum;
         } else {
             column_stencil<real, CZ>(gin + R.site_off, x, y, z0, nz, R, S);
         }
-        real *G = b.G + (long long)N * R.site_off;
-        const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
+        if (CZ <= 2 && s > 1) {   // short columns: all the step's loads go out together
+#pragma unroll
+            for (int j = 0; j < CZ; ++j) {
+                // clamped past a short last chunk (those values are not used)
+                const int site = x + R.Lx * (y + R.Ly * min(z0 + j, z0 + nz - 1));
+                Ev[j] = b.E[po + ts * V + site];
+                Gv[j] = G[(long long)(s - 1) * V + site];
+            }
+        }
+    }
+    const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
+    if (!act) return;   // uniform for the block
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};
+    if (in) {
         const double coef = st[r].phibar_p / ((double)N * st[r].q);
         const long long fo = off_field(R, ch.nsp);
 #pragma unroll
@@ -555,10 +638,12 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ b
             const int site = x + R.Lx * (y + R.Ly * (z0 + j));
             real *Gs = G + (long long)(s - 1) * V + site;
             if (s > 1) {
-                gout[R.site_off + site] = b.E[po + ts * V + site] * S[j] * sc;
+                const real e = CZ <= 2 ? Ev[j] : b.E[po + ts * V + site];
+                const real gs = CZ <= 2 ? Gv[j] : *Gs;
+                gout[R.site_off + site] = e * S[j] * sc;
                 // the density term G_s sigma[G+_{s+1}] replaces G_s in the store (G_s is
                 // not read again in this evaluation); step 1 sums them
-                *Gs = *Gs * S[j];
+                *Gs = gs * S[j];
             } else {
                 // terms of steps N .. 2 in that order, then step 1's (the order of an
                 // accumulation along the backward sweep)
@@ -598,13 +683,13 @@ struct BlockKernels {
                     PropBufs<real> b, double *partG, int sums, hipEvent_t e0, hipEvent_t e1)
     {
         if constexpr (K == 0) {
-            auto kern = p.n_rep == 1 ? k_fwd_direct<real, CX, CY, CZ, true> : k_fwd_direct<real, CX, CY, CZ, false>;
+            auto kern = p.args.n ? k_fwd_direct<real, CX, CY, CZ, true> : k_fwd_direct<real, CX, CY, CZ, false>;
             if (e0)
                 hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first,
-                                      rep, st, ch, s0 + 1, b, partG, p.nblocks, sums, p.rep0);
+                                      rep, st, ch, s0 + 1, b, partG, p.nblocks, sums, p.args);
             else
                 hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st, ch,
-                                   s0 + 1, b, partG, p.nblocks, sums, p.rep0);
+                                   s0 + 1, b, partG, p.nblocks, sums, p.args);
         } else {
             if (e0)
                 hipExtLaunchKernelGGL((k_fwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, e0,
@@ -619,13 +704,13 @@ struct BlockKernels {
                     const double *d, double *out, double *part, hipEvent_t e0, hipEvent_t e1)
     {
         if constexpr (K == 0) {
-            auto kern = p.n_rep == 1 ? k_bwd_direct<real, CX, CY, CZ, true> : k_bwd_direct<real, CX, CY, CZ, false>;
+            auto kern = p.args.n ? k_bwd_direct<real, CX, CY, CZ, true> : k_bwd_direct<real, CX, CY, CZ, false>;
             if (e0)
                 hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first,
-                                      rep, st, ch, s_hi, b, gin, gout, acc, final_mode, phit, d, out, part, p.rep0);
+                                      rep, st, ch, s_hi, b, gin, gout, acc, final_mode, phit, d, out, part, p.args);
             else
                 hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st, ch,
-                                   s_hi, b, gin, gout, acc, final_mode, phit, d, out, part, p.rep0);
+                                   s_hi, b, gin, gout, acc, final_mode, phit, d, out, part, p.args);
         } else {
             if (e0)
                 hipExtLaunchKernelGGL((k_bwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, e0,
@@ -643,13 +728,13 @@ template <typename real>
 void launch_field_exp(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, const double *w,
                       const double *d, int use_alpha, real *E, hipEvent_t e0, hipEvent_t e1)
 {
-    auto kern = p.n_rep == 1 ? k_field_exp<real, true> : k_field_exp<real, false>;
+    auto kern = p.args.n ? k_field_exp<real, true> : k_field_exp<real, false>;
     if (e0)
         hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep, st,
-                              ch, w, d, use_alpha, E, p.rep0);
+                              ch, w, d, use_alpha, E, p.args);
     else
         hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st, ch, w, d,
-                           use_alpha, E, p.rep0);
+                           use_alpha, E, p.args);
 }
 
 template <typename real>
