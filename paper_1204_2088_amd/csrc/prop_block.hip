@@ -646,9 +646,23 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ b
                 *Gs = gs * S[j];
             } else {
                 // terms of steps N .. 2 in that order, then step 1's (the order of an
-                // accumulation along the backward sweep)
-                double a[2] = {0.0, 0.0};
-                for (int q = N; q >= 2; --q) a[ch.types[q - 1]] += (double)G[(long long)(q - 1) * V + site];
+                // accumulation along the backward sweep); loaded eight at a time so that
+                // their memory round trips overlap (indices below 2 are clamped to a valid
+                // slot and not added)
+                double a0 = 0.0, a1 = 0.0;
+                for (int q0 = N; q0 >= 2; q0 -= 8) {
+                    real v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[u] = G[(long long)(max(q0 - u, 2) - 1) * V + site];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int q = q0 - u;
+                        if (q < 2) break;
+                        if (ch.types[q - 1] == 0) a0 += (double)v[u];
+                        else a1 += (double)v[u];
+                    }
+                }
+                double a[2] = {a0, a1};
                 a[ts] += (double)*Gs * (double)S[j];
 #pragma unroll
                 for (int I = 0; I < 2; ++I) {
