@@ -130,10 +130,13 @@ __device__ void reduce_and_control(RepState &S, int r, const int *__restrict__ b
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int row = wid; row < nslots + ng; row += kBlock / 64) {
         double v = 0.0;
+        // unrolled so that the loads of several iterations are in flight together
         if (row < nslots) {
+#pragma unroll 8
             for (int b = b0 + lane; b < b1; b += 64) v += part[(long long)b * kNQ + row];
         } else {
             const double *base = partG + (long long)(g_first + row - nslots) * nblocks;
+#pragma unroll 8
             for (int b = b0 + lane; b < b1; b += 64) v += base[b];
         }
 #pragma unroll

@@ -419,14 +419,17 @@ __global__ __launch_bounds__(kBlock) void k_field_exp(const int *__restrict__ bl
     const long long V = R.V;
     if (i >= V) return;
     const long long fo = off_field(R, ch.nsp), po = off_poly(R);
-    double x[2];
+    double x[2], dv[2] = {0.0, 0.0};
 #pragma unroll
-    for (int I = 0; I < 2; ++I) x[I] = w[fo + I * V + i];
+    for (int I = 0; I < 2; ++I) {
+        x[I] = w[fo + I * V + i];
+        if (use_alpha) dv[I] = d[po + I * V + i];
+    }
     const double alpha = use_alpha ? st[r].alpha : 0.0;
     if (!act) return;
 #pragma unroll
     for (int I = 0; I < 2; ++I) {
-        if (use_alpha) x[I] = fma(alpha, d[po + I * V + i], x[I]);
+        if (use_alpha) x[I] = fma(alpha, dv[I], x[I]);
         E[po + I * V + i] = (real)exp(-x[I]);
     }
 }
