@@ -24,6 +24,7 @@ struct hsf_ctx {
     int precision = HSF_FP64;
     int hydro = 1;
     int noise = 0;                   // HSF_NOISE_* flags
+    int lb_all = HSF_LB_BGK;         // collision shared by every replica, -1 when mixed
     unsigned long long noise_step = 0;  // generator step word of the next noise draw
     double *noise_flux = nullptr;    // bond fluxes of the composition noise, 3 nsp T (allocated when first on)
     // Crank-Nicolson diffusion (hsf_set_integrator); buffers of n = nsp T doubles
@@ -818,6 +819,9 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     c->plan.nblocks = (int)blk_rep.size();
     c->plan.n_rep = n_rep;
     set_plan_args(c->plan, c->reps.data(), n_rep, blk_first.data());
+    c->lb_all = c->reps[0].lb_mode;
+    for (const Rep &R : c->reps)
+        if (R.lb_mode != c->lb_all) c->lb_all = -1;
     {
         std::vector<int> br, bf;
 #define HSF_SIZE(CX, CY, CZ, K)                                             \
@@ -1082,7 +1086,7 @@ int hsf_lb_advance(hsf_ctx *c, int n_steps, const double *force, int where)
         {
             Timed t(c, HSF_K_LB);
             launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, f, c->rho, c->u, (c->noise & HSF_NOISE_LB) != 0,
-                      c->noise_step, t.a, t.b);
+                      c->noise_step, c->lb_all, t.a, t.b);
         }
         std::swap(c->nA, c->nB);
         if (c->noise) ++c->noise_step;
@@ -1136,7 +1140,7 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
             {
                 Timed t(c, HSF_K_LB);
                 launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, c->force, c->rho, c->u,
-                          (c->noise & HSF_NOISE_LB) != 0, c->noise_step, t.a, t.b);
+                          (c->noise & HSF_NOISE_LB) != 0, c->noise_step, c->lb_all, t.a, t.b);
             }
             std::swap(c->nA, c->nB);
             uu = c->u;

@@ -222,8 +222,10 @@ __device__ __forceinline__ void lb_mode_noise(const Rep &R, int r, long long i, 
 // equilibrium of eq. 11 with rate 1/tau, add the forcing term
 //   F_i = (1 - 1/(2 tau)) w_i [3 (c_i - u).f + 9 (c_i.u)(c_i.f)],
 // and write each post-collision population to the neighbour it streams to.  NOISE adds
-// the mode noise of eq. 13 before streaming.
-template <bool NOISE>
+// the mode noise of eq. 13 before streaming.  MODE: HSF_LB_BGK or HSF_LB_MRT when every
+// replica uses that collision (each variant needs only its own registers), -1 for a batch
+// that mixes them (chosen per replica).
+template <bool NOISE, int MODE>
 __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, const int *__restrict__ blk_first,
                                                const Rep *__restrict__ rep, const double *__restrict__ nsrc,
                                                double *__restrict__ ndst, const double *__restrict__ f,
@@ -256,7 +258,8 @@ __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, 
     }
     const double ux = (jx + 0.5 * fx) / rho, uy = (jy + 0.5 * fy) / rho, uz = (jz + 0.5 * fz) / rho;
     double ns[19];
-    if (R.lb_mode == HSF_LB_MRT) {
+    const bool mrt = MODE == HSF_LB_MRT || (MODE < 0 && R.lb_mode == HSF_LB_MRT);
+    if (mrt) {
         mrt_collide(n, rho, ux, uy, uz, fx, fy, fz, R, ns);
     } else {
         const double om = 1.0 / R.tau, fp = 1.0 - 0.5 / R.tau;
@@ -270,13 +273,19 @@ __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, 
             const double neq = rho * wq * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
             const double F = fp * wq * (3.0 * (cf - uf) + 9.0 * cu * cf);
             ns[q] = n[q] - om * (n[q] - neq) + F;
+            if (!NOISE) {   // stored at once: fewer live registers
+                const int xd = wrap1(x + kCx[q], R.Lx), yd = wrap1(y + kCy[q], R.Ly), zd = wrap1(z + kCz[q], R.Lz);
+                ndst[base + q * V + sidx(R, xd, yd, zd)] = ns[q];
+            }
         }
     }
     if (NOISE) lb_mode_noise(R, sr.r, i, step, rho, ns);
+    if (NOISE || mrt) {
 #pragma unroll
-    for (int q = 0; q < 19; ++q) {
-        const int xd = wrap1(x + kCx[q], R.Lx), yd = wrap1(y + kCy[q], R.Ly), zd = wrap1(z + kCz[q], R.Lz);
-        ndst[base + q * V + sidx(R, xd, yd, zd)] = ns[q];
+        for (int q = 0; q < 19; ++q) {
+            const int xd = wrap1(x + kCx[q], R.Lx), yd = wrap1(y + kCy[q], R.Ly), zd = wrap1(z + kCz[q], R.Lz);
+            ndst[base + q * V + sidx(R, xd, yd, zd)] = ns[q];
+        }
     }
     rho_out[R.site_off + i] = rho;
     u_out[vo + i] = ux;
@@ -395,9 +404,12 @@ void launch_force(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const 
 }
 
 void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc, double *ndst, const double *f,
-               double *rho, double *u, bool noise, unsigned long long step, hipEvent_t e0, hipEvent_t e1)
+               double *rho, double *u, bool noise, unsigned long long step, int lb_mode, hipEvent_t e0,
+               hipEvent_t e1)
 {
-    auto kern = noise ? k_lb<true> : k_lb<false>;
+    auto pick = [&](auto bgk, auto mrt, auto mixed) { return lb_mode == HSF_LB_BGK ? bgk : lb_mode == HSF_LB_MRT ? mrt : mixed; };
+    auto kern = noise ? pick(k_lb<true, HSF_LB_BGK>, k_lb<true, HSF_LB_MRT>, k_lb<true, -1>)
+                      : pick(k_lb<false, HSF_LB_BGK>, k_lb<false, HSF_LB_MRT>, k_lb<false, -1>);
     if (e0)
         hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep,
                               nsrc, ndst, f, rho, u, step);

@@ -135,8 +135,9 @@ void launch_force(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const 
                   const double *mu, double *f);
 // noise: draw the thermal noise of this step (eq. 13 for LB, eq. 5 for CD) with
 // generator step word `step`
+// lb_mode: the collision of every replica (HSF_LB_BGK or HSF_LB_MRT), or -1 when mixed
 void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc, double *ndst,
-               const double *f, double *rho, double *u, bool noise, unsigned long long step,
+               const double *f, double *rho, double *u, bool noise, unsigned long long step, int lb_mode,
                hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // noise_flux: scratch for the composition noise's bond fluxes (3 nsp T doubles), or null
 // for no noise; diff_scale multiplies dt in the diffusive flux (1/2 in the CN step)
