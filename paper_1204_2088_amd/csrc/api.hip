@@ -320,30 +320,37 @@ int set_tile(hsf_ctx *c, const TileCfg &t)
 // One density-functional evaluation for the active replicas.
 //   final_mode 0: densities into out (field layout); 1: gradient phi^t - phi into out
 //   (polymer layout) with the partial dot products against d.
-// Launches: exp of the fields, ceil(N/K) forward launches, the Q reduction,
-// ceil(N/K) backward launches (the last one normalises).
+// Launches with one-step kernels (K = 0): N forward launches, the first also computing
+// the field factors, and N backward launches, the first also computing Q and the last
+// normalising.  With blocked kernels: exp of the fields, ceil(N/K) forward launches, the
+// Q reduction, ceil(N/K) backward launches.
 template <typename real>
 void run_eval(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d, int sums)
 {
     PropBufs<real> b = bufs<real>(c);
     const int N = c->ch.N, K = std::max(1, c->tile.k);
-    {
+    const bool direct = c->tile.k == 0;
+    const bool fold_q = direct && N > 1;   // with N = 1 step 1 is step N: Q first, in its own launch
+    if (!direct) {
         Timed t(c, HSF_K_PREP);
         launch_field_exp<real>(c->stream, c->plan, c->rep_d, c->st_d, c->ch, c->w, c->d, use_alpha, b.E, t.a, t.b);
     }
     for (int s0 = 0; s0 < N; s0 += K) {
         Timed t(c, HSF_K_FWD);
         launch_fwd_block<real>(c->tile, c->stream, c->tplan, c->rep_d, c->st_d, c->ch, s0, std::min(K, N - s0), b,
-                               c->partG, sums, t.a, t.b);
+                               c->partG, sums, direct ? c->w : nullptr, c->d, use_alpha, t.a, t.b);
     }
-    launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_Q, c->ch, c->partG, 0.0, 0, c->st_hd);
+    if (!fold_q)
+        launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_Q, c->ch, c->partG, 0.0, 0,
+                          c->st_hd);
     int parity = 0;
     for (int s_hi = N; s_hi >= 1; s_hi -= K) {
         Timed t(c, HSF_K_BWD);
         const real *gin = b.Gp[parity ^ 1];
         real *gout = b.Gp[parity];
         launch_bwd_block<real>(c->tile, c->stream, c->tplan, c->rep_d, c->st_d, c->ch, s_hi, std::min(K, s_hi), b,
-                               gin, gout, c->acc, final_mode, c->phi, d, out, c->part, t.a, t.b);
+                               gin, gout, c->acc, final_mode, c->phi, d, out, c->part, c->partG, fold_q ? 1 : 0,
+                               t.a, t.b);
         parity ^= 1;
     }
 }

@@ -156,11 +156,9 @@ __device__ void control(RepState &S, int phase, const Chain &ch, const double *r
 
     switch (phase) {
     case PH_Q: {
-        S.q = gsum[ch.N - 1] / V;
-        int cum = 0;
-        for (int s = 0; s < ch.N; ++s) cum += S.scale_e[s];
-        S.ln_q = log(S.q) + cum * 0.69314718055994530942;
-        if (!isfinite(S.q) || S.q <= 0.0) S.nonfinite = 1;
+        bool bad;
+        q_from_sum(gsum[ch.N - 1], V, S.scale_e, ch.N, S.q, S.ln_q, bad);
+        if (bad) S.nonfinite = 1;
         break;
     }
     case PH_TARGET: {

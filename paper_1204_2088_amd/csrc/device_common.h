@@ -18,6 +18,18 @@ __device__ __forceinline__ int plan_block()
     return xcd * q + (xcd < rr ? xcd : rr) + slot;
 }
 
+// Q and ln Q of a replica from the sum over its sites of the stored G_N (the stored
+// propagators carry the per-step factors 2^-e_s), and whether Q left the range.
+__device__ __forceinline__ void q_from_sum(double gsum, double V, const int *scale_e, int N, double &q, double &ln_q,
+                                           bool &bad)
+{
+    q = gsum / V;
+    int cum = 0;
+    for (int s = 0; s < N; ++s) cum += scale_e[s];
+    ln_q = log(q) + cum * 0.69314718055994530942;
+    bad = !isfinite(q) || q <= 0.0;
+}
+
 // Replica and local site of the calling thread in a site plan.
 struct SiteRef {
     int r;

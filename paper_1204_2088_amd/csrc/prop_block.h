@@ -41,13 +41,18 @@ inline size_t tile_lds_bytes(const TileCfg &t, size_t real_bytes)
 template <typename real>
 void launch_field_exp(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, const double *w,
                       const double *d, int use_alpha, real *E, hipEvent_t e0, hipEvent_t e1);
+// w (may be null): with one-step kernels the first forward launch also computes the field
+// factors from w (+ alpha d when use_alpha), in place of launch_field_exp.
 template <typename real>
 void launch_fwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
-                      int s0, int n, PropBufs<real> b, double *partG, int sums, hipEvent_t e0, hipEvent_t e1);
+                      int s0, int n, PropBufs<real> b, double *partG, int sums, const double *w, const double *d,
+                      int use_alpha, hipEvent_t e0, hipEvent_t e1);
+// fold_q: with one-step kernels the first backward launch also computes Q from the forward
+// sweep's partials, in place of the control launch of that phase.
 template <typename real>
 void launch_bwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
                       int s_hi, int n, PropBufs<real> b, const real *gin, real *gout, double *acc, int final_mode,
-                      const double *phit, const double *d, double *out, double *part, hipEvent_t e0,
-                      hipEvent_t e1);
+                      const double *phit, const double *d, double *out, double *part, const double *partG,
+                      int fold_q, hipEvent_t e0, hipEvent_t e1);
 
 }  // namespace hsf

@@ -517,13 +517,17 @@ __device__ __forceinline__ void column_stencil(const real *__restrict__ f, int x
                c3 * (a2[j] + a2[j + 2]);
 }
 
+// With w set, step 1 also computes the field factors E = exp(-(w + alpha d)) of both
+// polymer species at its sites (the tiles cover every site once) and stores them for the
+// later steps, in place of a separate launch.
 template <typename real, int CX, int CY, int CZ, bool ARGS>
 __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ blk_rep,
                                                        const int *__restrict__ blk_first,
                                                        const Rep *__restrict__ rep,
                                                        const RepState *__restrict__ st, Chain ch, int s,
                                                        PropBufs<real> b, double *__restrict__ partG, int nblocks,
-                                                       int sums, ArgReps ar)
+                                                       int sums, const double *__restrict__ w,
+                                                       const double *__restrict__ dvec, int use_alpha, ArgReps ar)
 {
     static_assert(CX * CY == kBlock, "one column per thread");
     int r, x0, y0, z0;
@@ -536,8 +540,9 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ b
     const int nz = min(CZ, R.Lz - z0);
     const bool in = x < R.Lx && y < R.Ly;
     real *G = b.G + (long long)ch.N * R.site_off;
-    const real *E = b.E + off_poly(R);
+    real *E = b.E + off_poly(R);
     const real *Es = E + ch.types[s - 1] * V;
+    const bool fuse_exp = s == 1 && w != nullptr;
     // all loads of the step before the active check and the stores
     real S[CZ], Ev[CZ];
 #pragma unroll
@@ -549,20 +554,38 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ b
         } else {
             column_stencil<real, CZ>(G + (long long)(s - 2) * V, x, y, z0, nz, R, S);
         }
-        if (CZ <= 2) {   // short columns: the field factors join the stencil's loads
+        if (CZ <= 2 && !fuse_exp) {   // short columns: the field factors join the stencil's loads
 #pragma unroll
             for (int j = 0; j < CZ; ++j) Ev[j] = Es[x + R.Lx * (y + R.Ly * min(z0 + j, z0 + nz - 1))];
         }
     }
     const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
+    const double alpha = (fuse_exp && use_alpha) ? st[r].alpha : 0.0;
     if (!act) return;   // uniform for the block
+    if (fuse_exp && in) {
+        const long long fo = off_field(R, ch.nsp), po = off_poly(R);
+        const int t1 = ch.types[0];
+#pragma unroll
+        for (int j = 0; j < CZ; ++j) {
+            if (j >= nz) break;
+            const int site = x + R.Lx * (y + R.Ly * (z0 + j));
+#pragma unroll
+            for (int I = 0; I < 2; ++I) {
+                double xv = w[fo + (long long)I * V + site];
+                if (use_alpha) xv = fma(alpha, dvec[po + (long long)I * V + site], xv);
+                const real e = (real)exp(-xv);
+                E[(long long)I * V + site] = e;
+                if (I == t1) Ev[j] = e;
+            }
+        }
+    }
     double gsum = 0.0, esum[2] = {0.0, 0.0};
     if (in) {
 #pragma unroll
         for (int j = 0; j < CZ; ++j) {
             if (j >= nz) break;
             const int site = x + R.Lx * (y + R.Ly * (z0 + j));
-            const real g = (CZ <= 2 ? Ev[j] : Es[site]) * S[j] * sc;
+            const real g = ((CZ <= 2 || fuse_exp) ? Ev[j] : Es[site]) * S[j] * sc;
             G[(long long)(s - 1) * V + site] = g;
             gsum += (double)g;
             if (s == 1 && sums) {
@@ -583,16 +606,21 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ b
     }
 }
 
+// With fold_q set, step N's launch also finishes the forward sweep's reduction: the
+// first block of each replica sums the replica's G_N partials (partG row N - 1, fixed
+// order) and stores Q, ln Q and the range flag, which step 1 uses for the normalisation,
+// in place of a separate control launch.
 template <typename real, int CX, int CY, int CZ, bool ARGS>
 __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ blk_rep,
                                                        const int *__restrict__ blk_first,
                                                        const Rep *__restrict__ rep,
-                                                       const RepState *__restrict__ st, Chain ch, int s,
+                                                       RepState *__restrict__ st, Chain ch, int s,
                                                        PropBufs<real> b, const real *__restrict__ gin,
                                                        real *__restrict__ gout, double *__restrict__ acc,
                                                        int final_mode, const double *__restrict__ phit,
                                                        const double *__restrict__ d, double *__restrict__ out,
-                                                       double *__restrict__ part, ArgReps ar)
+                                                       double *__restrict__ part, const double *__restrict__ partG,
+                                                       int nblocks, int fold_q, ArgReps ar)
 {
     static_assert(CX * CY == kBlock, "one column per thread");
     int r, x0, y0, z0;
@@ -631,6 +659,26 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ b
     }
     const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
     if (!act) return;   // uniform for the block
+    if (fold_q && s == N && threadIdx.x < 64) {
+        const int pb = plan_block();
+        const int b0 = ARGS ? ar.blk_first[r] : blk_first[r], b1 = ARGS ? ar.blk_first[r + 1] : blk_first[r + 1];
+        if (pb == b0) {
+            double v = 0.0;
+            const double *row = partG + (long long)(N - 1) * nblocks;
+#pragma unroll 8
+            for (int q = b0 + (int)threadIdx.x; q < b1; q += 64) v += row[q];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+            if (threadIdx.x == 0) {
+                double q, lq;
+                bool bad;
+                q_from_sum(v, (double)R.V, st[r].scale_e, N, q, lq, bad);
+                st[r].q = q;
+                st[r].ln_q = lq;
+                if (bad) st[r].nonfinite = 1;
+            }
+        }
+    }
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
     if (in) {
         const double coef = st[r].phibar_p / ((double)N * st[r].q);
@@ -697,16 +745,17 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ b
 template <typename real, int CX, int CY, int CZ, int K>
 struct BlockKernels {
     static void fwd(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int s0, int n,
-                    PropBufs<real> b, double *partG, int sums, hipEvent_t e0, hipEvent_t e1)
+                    PropBufs<real> b, double *partG, int sums, const double *w, const double *d, int use_alpha,
+                    hipEvent_t e0, hipEvent_t e1)
     {
         if constexpr (K == 0) {
             auto kern = p.args.n ? k_fwd_direct<real, CX, CY, CZ, true> : k_fwd_direct<real, CX, CY, CZ, false>;
             if (e0)
                 hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first,
-                                      rep, st, ch, s0 + 1, b, partG, p.nblocks, sums, p.args);
+                                      rep, st, ch, s0 + 1, b, partG, p.nblocks, sums, w, d, use_alpha, p.args);
             else
                 hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st, ch,
-                                   s0 + 1, b, partG, p.nblocks, sums, p.args);
+                                   s0 + 1, b, partG, p.nblocks, sums, w, d, use_alpha, p.args);
         } else {
             if (e0)
                 hipExtLaunchKernelGGL((k_fwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, e0,
@@ -718,16 +767,19 @@ struct BlockKernels {
     }
     static void bwd(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int s_hi, int n,
                     PropBufs<real> b, const real *gin, real *gout, double *acc, int final_mode, const double *phit,
-                    const double *d, double *out, double *part, hipEvent_t e0, hipEvent_t e1)
+                    const double *d, double *out, double *part, const double *partG, int fold_q, hipEvent_t e0,
+                    hipEvent_t e1)
     {
         if constexpr (K == 0) {
             auto kern = p.args.n ? k_bwd_direct<real, CX, CY, CZ, true> : k_bwd_direct<real, CX, CY, CZ, false>;
             if (e0)
                 hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first,
-                                      rep, st, ch, s_hi, b, gin, gout, acc, final_mode, phit, d, out, part, p.args);
+                                      rep, st, ch, s_hi, b, gin, gout, acc, final_mode, phit, d, out, part, partG,
+                                      p.nblocks, fold_q, p.args);
             else
                 hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st, ch,
-                                   s_hi, b, gin, gout, acc, final_mode, phit, d, out, part, p.args);
+                                   s_hi, b, gin, gout, acc, final_mode, phit, d, out, part, partG, p.nblocks, fold_q,
+                                   p.args);
         } else {
             if (e0)
                 hipExtLaunchKernelGGL((k_bwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, e0,
@@ -756,11 +808,13 @@ void launch_field_exp(hipStream_t s, const Plan &p, const Rep *rep, RepState *st
 
 template <typename real>
 void launch_fwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
-                      int s0, int n, PropBufs<real> b, double *partG, int sums, hipEvent_t e0, hipEvent_t e1)
+                      int s0, int n, PropBufs<real> b, double *partG, int sums, const double *w, const double *d,
+                      int use_alpha, hipEvent_t e0, hipEvent_t e1)
 {
 #define HSF_CASE(CX, CY, CZ, K)                                                                   \
     if (cfg.cx == CX && cfg.cy == CY && cfg.cz == CZ && cfg.k == K)                               \
-        return BlockKernels<real, CX, CY, CZ, K>::fwd(s, p, rep, st, ch, s0, n, b, partG, sums, e0, e1);
+        return BlockKernels<real, CX, CY, CZ, K>::fwd(s, p, rep, st, ch, s0, n, b, partG, sums, w, d, use_alpha, \
+                                                      e0, e1);
     HSF_TILE_CONFIGS(HSF_CASE)
 #undef HSF_CASE
 }
@@ -768,13 +822,13 @@ void launch_fwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Re
 template <typename real>
 void launch_bwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
                       int s_hi, int n, PropBufs<real> b, const real *gin, real *gout, double *acc, int final_mode,
-                      const double *phit, const double *d, double *out, double *part, hipEvent_t e0,
-                      hipEvent_t e1)
+                      const double *phit, const double *d, double *out, double *part, const double *partG,
+                      int fold_q, hipEvent_t e0, hipEvent_t e1)
 {
 #define HSF_CASE(CX, CY, CZ, K)                                                                        \
     if (cfg.cx == CX && cfg.cy == CY && cfg.cz == CZ && cfg.k == K)                                    \
         return BlockKernels<real, CX, CY, CZ, K>::bwd(s, p, rep, st, ch, s_hi, n, b, gin, gout, acc,       \
-                                                      final_mode, phit, d, out, part, e0, e1);
+                                                      final_mode, phit, d, out, part, partG, fold_q, e0, e1);
     HSF_TILE_CONFIGS(HSF_CASE)
 #undef HSF_CASE
 }
@@ -785,11 +839,11 @@ void launch_bwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Re
                                          hipEvent_t);                                                     \
     template void launch_fwd_block<real>(const TileCfg &, hipStream_t, const Plan &, const Rep *,         \
                                          RepState *, Chain, int, int, PropBufs<real>, double *, int,      \
-                                         hipEvent_t, hipEvent_t);                                         \
+                                         const double *, const double *, int, hipEvent_t, hipEvent_t);    \
     template void launch_bwd_block<real>(const TileCfg &, hipStream_t, const Plan &, const Rep *,         \
                                          RepState *, Chain, int, int, PropBufs<real>, const real *,       \
                                          real *, double *, int, const double *, const double *, double *, \
-                                         double *, hipEvent_t, hipEvent_t);
+                                         double *, const double *, int, hipEvent_t, hipEvent_t);
 HSF_INST(double)
 HSF_INST(float)
 #undef HSF_INST
