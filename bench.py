@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # profiles/spill_melt192_a8b8_fp32.md (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0
 # after a calibration copy).  Valid only for that workload, precision, tiling and kernel
 # as they stand; anything else reports null.
-MEASURED_TRAFFIC = {("melt64_a8b8", "fp32", (64, 4, 2, 0), "bwd"): 13.71e6,
+MEASURED_TRAFFIC = {("melt64_a8b8", "fp32", (64, 4, 2, 0), "bwd"): 13.72e6,
                     ("melt192_a8b8", "fp32", (64, 4, 8, 0), "bwd"): 185.6e6}
 METRIC = "propagator site·bead updates/s + LB MLUPS; step time learned vs plain at 1e-6"
 
