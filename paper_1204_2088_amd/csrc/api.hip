@@ -536,10 +536,10 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
 // current densities, into eval_out; ln Q, phibar and <exp(-w_S)> stay in the replica
 // states.  An evaluation whose propagators left the floating-point range is repeated
 // with the per-step scales it adapted (at most three more times).
-int evaluate_impl(hsf_ctx *c)
+int evaluate_impl(hsf_ctx *c, bool check_range = true)
 {
     hipStream_t s = c->stream;
-    for (int attempt = 0; attempt < 4; ++attempt) {
+    for (int attempt = 0; attempt < (check_range ? 4 : 1); ++attempt) {
         int rc0 = run_seq(c, hsf_ctx::GK_EVAL, [&] {
             target_setup(c, 0.0, 0);   // phibar_p, phibar_s from the current densities; all replicas active
             run_eval_any(c, 0, 0, c->eval_out, nullptr, 1);
@@ -547,6 +547,7 @@ int evaluate_impl(hsf_ctx *c)
                               c->partG, 0.0, 0, c->st_hd);
         });
         if (rc0) return rc0;
+        if (!check_range) break;
         if ((rc0 = read_status(c))) return rc0;
         bool bad = false;
         for (int r = 0; r < c->n_rep; ++r) bad |= c->st_h[r].nonfinite != 0;
@@ -595,13 +596,13 @@ int cn_axpy(hsf_ctx *c, double *y, const double *V, int k, const double *coef_h)
     return sync(c);   // the pinned staging buffer is reused by the next call
 }
 
-// F_out = F(current fields c->w); leaves phi[w] in eval_out
+// F_out = F(current fields c->w); leaves phi[w] in eval_out.  No host round trip: a Q out
+// of range makes F non-finite, which the solve detects through ||F|| (and the dot
+// products of the Krylov basis).
 int cn_residual(hsf_ctx *c, double *F_out, long long *evals)
 {
-    int rc = evaluate_impl(c);
+    int rc = evaluate_impl(c, false);
     if (rc) return rc;
-    for (int r = 0; r < c->n_rep; ++r)
-        if (c->st_h[r].nonfinite) return fail(c, HSF_ENONFINITE, "non-finite Q in replica %d", r);
     *evals += c->n_rep;
     c->work_evals += c->n_rep;
     for (int r = 0; r < c->n_rep; ++r) c->work_site_evals += (double)c->reps[r].V;
@@ -678,6 +679,7 @@ int cn_solve(hsf_ctx *c, long long *evals_out)
             if ((rc = sync(c))) return rc;
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = c->cn_dots_h[i] + c->cn_dots_h[stride + i];
             const double hn = sqrt(c->cn_dots_h[2 * stride]);
+            if (!std::isfinite(hn)) return fail(c, HSF_ENONFINITE, "non-finite Crank-Nicolson Jacobian product");
             H[(size_t)(j + 1) * m + j] = hn;
             if (hn > 0.0) launch_lincomb(c->stream, vn, 1.0 / hn, vn, 0.0, vn, n);
             // Givens rotations of the new column
