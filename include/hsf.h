@@ -230,6 +230,20 @@ int hsf_cd_advance(hsf_ctx *ctx, const double *mu, const double *u, int where);
 int hsf_step(hsf_ctx *ctx, int n_steps, double tol, int max_iter, hsf_invert_stats *stats,
              long long *total_evals);
 
+/* Checkpoint of the state a continuation reads: densities, fields, LB populations, the
+ * replicas' inversion control state (with the per-step power-of-two scales of the FP32
+ * propagators), the warm-start history, the noise step word and the propagator tiling.
+ * hsf_get_state writes hsf_state_size(ctx) bytes into buf (host memory, size bytes);
+ * hsf_set_state restores them into a context created with the same parameters, after
+ * which further steps reproduce the checkpointed run bit for bit (given the same
+ * solver, warm start, integrator and noise settings, which are configuration, not
+ * state).  HSF_EINVAL for a short buffer, a buffer not written by hsf_get_state, or a
+ * context of different replicas, species, chain, precision or size.  Both wait for the
+ * context's stream. */
+long long hsf_state_size(const hsf_ctx *ctx);
+int hsf_get_state(hsf_ctx *ctx, void *buf, long long size);
+int hsf_set_state(hsf_ctx *ctx, const void *buf, long long size);
+
 /* Integrator of the convection-diffusion update of hsf_step (section 2).
  * HSF_CD_EXPLICIT (default): the explicit conservative step of hsf_cd_advance.
  * HSF_CD_CRANK_NICOLSON: the diffusive part implicit (Crank-Nicolson), convection by

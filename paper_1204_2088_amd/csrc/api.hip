@@ -1335,6 +1335,107 @@ int hsf_get_work(hsf_ctx *c, long long *evals, double *site_evals, int reset)
     return HSF_OK;
 }
 
+// ---- checkpoint: everything a continuation reads ----------------------------------
+//
+// Layout: StateHeader, the replicas' RepState (inversion control and the per-step
+// power-of-two scales), then the FP64 arrays phi, w (field layout), the LB populations
+// (per replica [19][V]) and the warm-start history w_hist[2], phi_hist[2].
+namespace {
+struct StateHeader {
+    unsigned long long magic;        // identifies the layout
+    int version;
+    int n_rep, nsp, N, precision;
+    int types[64];                   // bead species (the per-step scales belong to the chain)
+    long long T;
+    int tile[4];                     // the propagator tiling (summation order of FP32 runs)
+    int n_hist, fields_set;
+    unsigned long long noise_step;
+};
+constexpr unsigned long long kStateMagic = 0x4853465354415445ULL;
+
+long long state_doubles(const hsf_ctx *c) { return (long long)(6 * c->ch.nsp + 19) * c->T; }
+}  // namespace
+
+long long hsf_state_size(const hsf_ctx *c)
+{
+    if (!c) return -1;
+    return (long long)sizeof(StateHeader) + (long long)sizeof(RepState) * c->n_rep +
+           (long long)sizeof(double) * state_doubles(c);
+}
+
+int hsf_get_state(hsf_ctx *c, void *buf, long long size)
+{
+    if (!c || !buf) return HSF_EINVAL;
+    if (size < hsf_state_size(c)) return fail(c, HSF_EINVAL, "state buffer of %lld bytes, %lld needed", size,
+                                              hsf_state_size(c));
+    int rc = sync(c);
+    if (rc) return rc;
+    char *p = static_cast<char *>(buf);
+    StateHeader h{};
+    h.magic = kStateMagic;
+    h.version = 1;
+    h.n_rep = c->n_rep;
+    h.nsp = c->ch.nsp;
+    h.N = c->ch.N;
+    h.precision = c->precision;
+    for (int k = 0; k < 64; ++k) h.types[k] = k < c->ch.N ? c->ch.types[k] : -1;
+    h.T = c->T;
+    h.tile[0] = c->tile.cx;
+    h.tile[1] = c->tile.cy;
+    h.tile[2] = c->tile.cz;
+    h.tile[3] = c->tile.k;
+    h.n_hist = c->n_hist;
+    h.fields_set = c->fields_set;
+    h.noise_step = c->noise_step;
+    memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    HIPCHK(c, hipMemcpy(p, c->st_d, sizeof(RepState) * c->n_rep, hipMemcpyDeviceToHost));
+    p += sizeof(RepState) * c->n_rep;
+    const size_t nf = (size_t)c->ch.nsp * c->T;
+    const double *src[] = {c->phi, c->w, c->nA, c->w_hist[0], c->w_hist[1], c->phi_hist[0], c->phi_hist[1]};
+    const size_t cnt[] = {nf, nf, (size_t)19 * c->T, nf, nf, nf, nf};
+    for (int k = 0; k < 7; ++k) {
+        HIPCHK(c, hipMemcpy(p, src[k], sizeof(double) * cnt[k], hipMemcpyDeviceToHost));
+        p += sizeof(double) * cnt[k];
+    }
+    return HSF_OK;
+}
+
+int hsf_set_state(hsf_ctx *c, const void *buf, long long size)
+{
+    if (!c || !buf) return HSF_EINVAL;
+    if (size < (long long)sizeof(StateHeader)) return fail(c, HSF_EINVAL, "state buffer too small");
+    StateHeader h;
+    memcpy(&h, buf, sizeof h);
+    if (h.magic != kStateMagic || h.version != 1) return fail(c, HSF_EINVAL, "not a state written by hsf_get_state");
+    bool same = h.n_rep == c->n_rep && h.nsp == c->ch.nsp && h.N == c->ch.N && h.precision == c->precision &&
+                h.T == c->T;
+    for (int k = 0; same && k < c->ch.N; ++k) same = h.types[k] == c->ch.types[k];
+    if (!same) return fail(c, HSF_EINVAL, "state of a different context (replicas, species, chain, precision or sites)");
+    if (size < hsf_state_size(c)) return fail(c, HSF_EINVAL, "state buffer truncated");
+    int rc = sync(c);
+    if (rc) return rc;
+    const TileCfg t{h.tile[0], h.tile[1], h.tile[2], h.tile[3]};
+    if (!tile_known(t)) return fail(c, HSF_EINVAL, "state names an unknown tiling");
+    if (t.cx != c->tile.cx || t.cy != c->tile.cy || t.cz != c->tile.cz || t.k != c->tile.k)
+        if ((rc = set_tile(c, t))) return rc;
+    const char *p = static_cast<const char *>(buf) + sizeof h;
+    HIPCHK(c, hipMemcpy(c->st_d, p, sizeof(RepState) * c->n_rep, hipMemcpyHostToDevice));
+    memcpy(c->st_h, p, sizeof(RepState) * c->n_rep);
+    p += sizeof(RepState) * c->n_rep;
+    const size_t nf = (size_t)c->ch.nsp * c->T;
+    double *dst[] = {c->phi, c->w, c->nA, c->w_hist[0], c->w_hist[1], c->phi_hist[0], c->phi_hist[1]};
+    const size_t cnt[] = {nf, nf, (size_t)19 * c->T, nf, nf, nf, nf};
+    for (int k = 0; k < 7; ++k) {
+        HIPCHK(c, hipMemcpy(dst[k], p, sizeof(double) * cnt[k], hipMemcpyHostToDevice));
+        p += sizeof(double) * cnt[k];
+    }
+    c->n_hist = h.n_hist;
+    c->fields_set = h.fields_set;
+    c->noise_step = h.noise_step;
+    return HSF_OK;
+}
+
 int hsf_set_integrator(hsf_ctx *c, int scheme, double tol, int max_newton, int krylov_dim)
 {
     if (!c) return HSF_EINVAL;

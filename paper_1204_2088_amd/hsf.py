@@ -30,7 +30,8 @@ EXPORTED = [
     "hsf_site_offset", "hsf_field_offset", "hsf_num_species", "hsf_set_fields", "hsf_get_fields",
     "hsf_set_densities", "hsf_get_densities", "hsf_evaluate", "hsf_observables", "hsf_invert", "hsf_mu_force",
     "hsf_set_lb", "hsf_get_lb", "hsf_lb_advance", "hsf_get_flow", "hsf_cd_advance", "hsf_step",
-    "hsf_set_hydro", "hsf_set_noise", "hsf_get_noise_step", "hsf_set_integrator", "hsf_get_cn_stats", "hsf_set_timing", "hsf_get_timing", "hsf_set_tile", "hsf_get_tile", "hsf_autotune",
+    "hsf_set_hydro", "hsf_set_noise", "hsf_get_noise_step", "hsf_set_integrator", "hsf_get_cn_stats",
+    "hsf_state_size", "hsf_get_state", "hsf_set_state", "hsf_set_timing", "hsf_get_timing", "hsf_set_tile", "hsf_get_tile", "hsf_autotune",
     "hsf_set_solver", "hsf_get_work", "hsf_set_warm", "hsf_net_create", "hsf_net_destroy",
     "hsf_net_last_error", "hsf_net_set_stream", "hsf_net_num_params", "hsf_net_set_params",
     "hsf_net_get_params", "hsf_net_set_input_norm", "hsf_net_set_output_scale", "hsf_net_forward", "hsf_net_loss_grad",
@@ -126,6 +127,9 @@ def load():
         "hsf_set_noise": ([C, I, ctypes.c_double, ctypes.c_ulonglong, ctypes.c_ulonglong], I),
         "hsf_get_noise_step": ([C, ctypes.POINTER(ctypes.c_ulonglong)], I),
         "hsf_set_integrator": ([C, I, ctypes.c_double, I, I], I),
+        "hsf_state_size": ([C], ctypes.c_longlong),
+        "hsf_get_state": ([C, P, ctypes.c_longlong], I),
+        "hsf_set_state": ([C, P, ctypes.c_longlong], I),
         "hsf_get_cn_stats": ([C, ctypes.POINTER(CnStats)], I),
         "hsf_set_timing": ([C, I], I),
         "hsf_set_solver": ([C, I], I),
@@ -350,6 +354,17 @@ class Context:
         ev = ctypes.c_longlong(0)
         self._check(self._lib.hsf_step(self._h, int(n_steps), float(tol), int(max_iter), st, ctypes.byref(ev)))
         return [s.as_dict() for s in st], ev.value
+
+    def get_state(self):
+        """Checkpoint of the state a continuation reads (bytes)."""
+        n = self._lib.hsf_state_size(self._h)
+        buf = np.empty(n, dtype=np.uint8)
+        self._check(self._lib.hsf_get_state(self._h, ctypes.c_void_p(buf.ctypes.data), n))
+        return buf
+
+    def set_state(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self._lib.hsf_set_state(self._h, ctypes.c_void_p(buf.ctypes.data), buf.size))
 
     def set_integrator(self, crank_nicolson=True, tol=1e-10, max_newton=20, krylov_dim=40):
         """Crank-Nicolson (implicit) or explicit diffusion in the coupled steps."""
