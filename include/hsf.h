@@ -12,8 +12,13 @@
  *   - one D3Q19 lattice-Boltzmann collide-and-stream step (eq. 9-11, with
  *     the single-relaxation-time collision and its forcing term, or the
  *     multiple-relaxation-time collision of eq. 12-14 in the basis of Table 1);
- *   - one conservative update of the convection-diffusion equation (eq. 3);
- *   - the coupled step that alternates the two at equal time steps.
+ *   - one conservative update of the convection-diffusion equation (eq. 3),
+ *     explicit or with Crank-Nicolson diffusion (section 2);
+ *   - the coupled step that alternates the two at equal time steps;
+ *   - thermal noise in both parts (eq. 5 and eq. 13), the free-energy density
+ *     of eq. 1 and the order parameters, and checkpoints of the run's state;
+ *   - a learned warm start for the inversion (a 3-D convolutional network with
+ *     its training kernels; not part of the paper).
  *
  * Units: lattice spacing h = 1, kT = 1, the diffusive time unit of the
  * paper; the LB step equals the diffusive step dt.
