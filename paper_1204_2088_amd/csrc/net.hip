@@ -16,6 +16,7 @@
 // then b[co].
 #include <math.h>
 #include <stdarg.h>
+#include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -42,12 +43,16 @@ struct Layer {
     long long w_off, b_off;          // offsets in the parameter vector
     // input composition: mode (CONV_IN_*) and the activations it reads (-1: network input)
     int in_mode, src1, src2;
+    // inference keeps the activation packed (BF16 [batch][site][cip of its readers]):
+    // every layer that reads it reads it plainly
+    int pack = 0;
     __bf16 *Wm = nullptr, *Wt = nullptr;
     float *dWm = nullptr;            // weight gradient, matrix-core layout
 };
 
 struct Tensor {
     float *p = nullptr;
+    __bf16 *pk = nullptr;   // packed BF16 copy used by inference (activations with Layer::pack)
     int c = 0, level = 0;
 };
 
@@ -146,9 +151,16 @@ int ensure_acts(hsf_net *n, int B, int L, bool grads)
     T(n->x0, n->in_ch, 0);
     for (int l = 0; l < n->n_layers; ++l) {
         const Layer &Ly = n->layer[l];
-        // pre-activations are kept for the backward pass and for the output layer
+        // pre-activations are kept for the backward pass and for the output layer;
+        // FP32 activations for the backward pass and for readers that compose them
         if (grads || !Ly.act) T(n->y[l], Ly.co, Ly.level);
-        if (Ly.act) T(n->a[l], Ly.co, Ly.level);
+        if (Ly.act && (grads || !Ly.pack)) T(n->a[l], Ly.co, Ly.level);
+        if (Ly.pack && rc == HSF_OK) {   // always there, so inference after training finds it
+            n->a[l].c = Ly.co;
+            n->a[l].level = Ly.level;
+            rc = nalloc(n, n->act_allocs, (void **)&n->a[l].pk,
+                        sizeof(__bf16) * (size_t)B * round_up(Ly.co, 8) * vol(L, Ly.level));
+        }
     }
     if (grads) {
         size_t din = 0, wp = 0;
@@ -201,30 +213,69 @@ ConvIn conv_input(const hsf_net *n, const Layer &Ly)
     return in;
 }
 
-// Forward of layer l.  The pre-activation y[l] is kept only when a backward pass
-// follows (training) or the layer has no activation; inference writes the
-// activation alone.
-void conv(hsf_net *n, int l)
+// Forward of layer l.  Training keeps the FP32 pre-activation and activation for the
+// backward pass, reading the normalised input x0.  Inference writes the activation
+// alone (packed when every reader reads it plainly), reads the network input x (with
+// the input normalisation applied while staging) and writes the output layer, with
+// the output scale applied, to y.
+void conv(hsf_net *n, int l, const float *x, float *y)
 {
     const Layer &Ly = n->layer[l];
-    float *y = (Ly.act && !n->training) ? nullptr : n->y[l].p;
-    net_conv_fwd(n->stream, conv_input(n, Ly), n->cur_B, Ly.ci, Ly.cip, Ly.Wm, Ly.kp, Ly.co, Ly.cop,
-                 n->params + Ly.b_off, y, Ly.act ? n->a[l].p : nullptr, n->cur_L >> Ly.level);
+    ConvIn in = conv_input(n, Ly);
+    ConvOut out;
+    if (n->training) {
+        out.Y = n->y[l].p;
+        out.A = Ly.act ? n->a[l].p : nullptr;
+    } else {
+        if (Ly.src1 < 0) {
+            in.x1 = x;
+            in.shift = n->norm;
+            in.scale = n->norm + n->in_ch;
+        } else if (n->layer[Ly.src1].pack) {
+            in.mode = CONV_IN_PACKED;
+            in.x1 = nullptr;
+            in.xp = n->a[Ly.src1].pk;
+        }
+        if (Ly.pack) {
+            out.Ap = n->a[l].pk;
+        } else if (Ly.act) {
+            out.A = n->a[l].p;
+        } else {
+            out.Y = y;
+            if (n->out_scaled) {
+                out.shift = n->norm + 2 * n->in_ch;
+                out.scale = out.shift + n->out_ch;
+            }
+        }
+    }
+    net_conv_fwd(n->stream, in, n->cur_B, Ly.ci, Ly.cip, Ly.Wm, Ly.kp, Ly.co, Ly.cop, n->params + Ly.b_off, out,
+                 n->cur_L >> Ly.level);
 }
 
 long long numel(const hsf_net *n, const Tensor &t) { return (long long)n->cur_B * t.c * vol(n->cur_L, t.level); }
 
 const Tensor &output(const hsf_net *n) { return n->y[n->n_layers - 1]; }
 
-void forward(hsf_net *n)
+// Training forward pass: normalises x0 in place (the weight gradient of the first
+// layer reads it) and keeps every layer's FP32 tensors.  The output scale is 1 here.
+void forward_train(hsf_net *n)
 {
     net_affine(n->stream, n->x0.p, n->in_ch, vol(n->cur_L, 0), numel(n, n->x0), n->norm, n->norm + n->in_ch);
-    for (int l = 0; l < n->n_layers; ++l) conv(n, l);
-    if (n->out_scaled) {
-        const Tensor &y = output(n);
-        const float *o = n->norm + 2 * n->in_ch;
-        net_affine(n->stream, y.p, n->out_ch, vol(n->cur_L, 0), numel(n, y), o, o + n->out_ch);
+    for (int l = 0; l < n->n_layers; ++l) conv(n, l, nullptr, nullptr);
+}
+
+// Inference: network input x ([B][in_ch][V] FP32, not modified) to output y
+// ([B][out_ch][V] FP32).  x is read with 16-byte vector loads where the box allows, so
+// an input that is not 16-byte aligned is copied to x0 first.
+int forward_infer(hsf_net *n, const float *x, float *y)
+{
+    if (reinterpret_cast<uintptr_t>(x) % 16 != 0) {
+        NCHK(n, hipMemcpyAsync(n->x0.p, x, sizeof(float) * numel(n, n->x0), hipMemcpyDeviceToDevice, n->stream));
+        x = n->x0.p;
     }
+    for (int l = 0; l < n->n_layers; ++l) conv(n, l, x, y);
+    NCHK(n, hipGetLastError());
+    return HSF_OK;
 }
 
 // Backward pass from dout (gradient of the loss with respect to the output).  Layers
@@ -251,8 +302,11 @@ void backward(hsf_net *n)
         net_unstage_grad(s, Ly.dWm, Ly.co, Ly.ci, Ly.cip, Ly.kp, n->grad + Ly.w_off);
         net_channel_sum(s, n->dy[l].p, B, Ly.co, V, n->bpart, n->grad + Ly.b_off);
         if (Ly.src1 < 0) continue;   // the network input needs no gradient
-        ConvIn g{n->dy[l].p, nullptr, CONV_IN_PLAIN};
-        net_conv_fwd(s, g, B, Ly.co, Ly.cip_t, Ly.Wt, Ly.kp_t, Ly.ci, Ly.cop_t, nullptr, n->din, nullptr, Ll);
+        ConvIn g;
+        g.x1 = n->dy[l].p;
+        ConvOut gout;
+        gout.Y = n->din;
+        net_conv_fwd(s, g, B, Ly.co, Ly.cip_t, Ly.Wt, Ly.kp_t, Ly.ci, Ly.cop_t, nullptr, gout, Ll);
         const long long nin = input_numel(n, Ly);
         auto give = [&](int j) {   // da[j] (+)= din through the input's composition
             float *dst = n->da[j].p;
@@ -302,7 +356,7 @@ int loss_and_grad(hsf_net *n, double *loss)
     }
     if (n->out_scaled) return nfail(n, HSF_EINVAL, "training needs the output scale reset to 1");
     n->training = 1;
-    forward(n);
+    forward_train(n);
     n->training = 0;
     const long long cnt = numel(n, n->dout);
     const int blocks = net_mse(n->stream, output(n).p, n->target, n->dout.p, cnt, 1.0f / (float)cnt, n->loss_part);
@@ -373,6 +427,17 @@ int hsf_net_create(int in_ch, int out_ch, const int widths[4], unsigned long lon
     }
     add(w[0], out_ch, 0, 0, CONV_IN_PLAIN, prev, -1);
     n->n_layers = nl;
+    for (int l = 0; l < nl; ++l) {   // activations whose readers all read them plainly
+        Layer &Ly = n->layer[l];
+        int readers = 0, plain = 0;
+        for (int j = 0; j < nl; ++j) {
+            const Layer &R = n->layer[j];
+            const bool reads = R.src1 == l || (R.in_mode == CONV_IN_ADD && R.src2 == l);
+            readers += reads;
+            plain += reads && R.in_mode == CONV_IN_PLAIN;
+        }
+        Ly.pack = Ly.act && readers > 0 && plain == readers;
+    }
     long long off = 0;
     for (int l = 0; l < nl; ++l) {
         Layer &Ly = n->layer[l];
@@ -502,10 +567,11 @@ int hsf_net_forward(hsf_net *n, const float *in, float *out, int batch, int L, i
     if (rc) return rc;
     if ((rc = ensure_acts(n, batch, L, false))) return rc;
     if (!n->weights_staged && (rc = stage_weights(n))) return rc;
+    if (!in || !out) return nfail(n, HSF_EINVAL, "null pointer");
+    if (where == HSF_DEVICE) return forward_infer(n, in, out);   // straight from and into the caller's buffers
     if ((rc = copy_f32(n, n->x0.p, in, (size_t)batch * n->in_ch * vol(L, 0), where, hipMemcpyHostToDevice)))
         return rc;
-    forward(n);
-    NCHK(n, hipGetLastError());
+    if ((rc = forward_infer(n, n->x0.p, output(n).p))) return rc;
     return copy_f32(n, out, output(n).p, (size_t)batch * n->out_ch * vol(L, 0), where, hipMemcpyDeviceToHost);
 }
 
@@ -556,15 +622,9 @@ int net_predict(hsf_net *n, hipStream_t s, const float *x, int in_ch, int B, int
         n->stream = saved;
         return rc;
     }
-    hipError_t e = hipMemcpyAsync(n->x0.p, x, sizeof(float) * (size_t)B * in_ch * vol(L, 0), hipMemcpyDeviceToDevice,
-                                  s);
-    if (e == hipSuccess) {
-        forward(n);
-        e = hipMemcpyAsync(pred, output(n).p, sizeof(float) * (size_t)B * n->out_ch * vol(L, 0),
-                           hipMemcpyDeviceToDevice, s);
-    }
+    rc = forward_infer(n, x, pred);
     n->stream = saved;
-    return e == hipSuccess ? HSF_OK : HSF_EHIP;
+    return rc;
 }
 
 int net_channels(const hsf_net *n, int *in_ch, int *out_ch, int *box_multiple)

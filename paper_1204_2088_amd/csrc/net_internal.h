@@ -12,15 +12,32 @@ constexpr int kNetMaxWidth = 32;   // widest layer the weight-gradient kernel su
 //   CONV_IN_ADD    x1 + x2               (both on the convolution's box)
 //   CONV_IN_UP     nearest 2x upsampling of x1 (x1 on the box of half the edge)
 //   CONV_IN_POOL   2x2x2 average of x1   (x1 on the box of twice the edge)
-// x1, x2 are [batch][ci][site] on their own boxes.
-enum { CONV_IN_PLAIN = 0, CONV_IN_ADD = 1, CONV_IN_UP = 2, CONV_IN_POOL = 3 };
+//   CONV_IN_PACKED xp                    (forward only)
+// x1, x2 are FP32 [batch][ci][site] on their own boxes; xp is BF16 [batch][site][cip]
+// (cip = ci rounded up to 8, channels ci..cip-1 zero), the layout the forward
+// convolution stages its tile in.  A plain input may carry a per-channel affine map,
+// applied as (x - shift[c]) scale[c] while staging (forward only).
+enum { CONV_IN_PLAIN = 0, CONV_IN_ADD = 1, CONV_IN_UP = 2, CONV_IN_POOL = 3, CONV_IN_PACKED = 4 };
 struct ConvIn {
-    const float *x1, *x2;
-    int mode;
+    const float *x1 = nullptr, *x2 = nullptr;
+    int mode = CONV_IN_PLAIN;
+    const __bf16 *xp = nullptr;
+    const float *shift = nullptr, *scale = nullptr;
+};
+
+// Outputs of a forward convolution (any may be null):
+//   Y   FP32 [batch][co][site]  acc + bias, then (. - shift[o]) scale[o] if shift is set
+//   A   FP32 [batch][co][site]  silu(acc + bias)
+//   Ap  BF16 [batch][site][cp]  silu(acc + bias) rounded to BF16, cp = co rounded up to
+//       8, channels co..cp-1 written as zero (the CONV_IN_PACKED input of the next layer)
+struct ConvOut {
+    float *Y = nullptr, *A = nullptr;
+    __bf16 *Ap = nullptr;
+    const float *shift = nullptr, *scale = nullptr;
 };
 
 void net_conv_fwd(hipStream_t s, ConvIn in, int B, int ci, int cip, const __bf16 *Wm, int kp, int co, int cop,
-                  const float *bias, float *Y, float *A, int L);
+                  const float *bias, ConvOut out, int L);
 int net_wgrad_slices(int B, int L, int cop, int kp);
 void net_conv_wgrad(hipStream_t s, ConvIn in, int B, int ci, int cip, const float *dY, int co, int cop, int kp,
                     int L, float *part, float *dWm);

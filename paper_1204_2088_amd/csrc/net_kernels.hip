@@ -22,6 +22,7 @@
 namespace hsf {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int wrapL(int v, int L)
@@ -38,15 +39,21 @@ __device__ __forceinline__ float silu_grad(float y)
 }
 
 // ---------------------------------------------------------------- forward convolution
-// Y[b][co][x] = bias[co] + sum_{ci,k} W[co][ci][k] X[b][ci][x + off_k]; optional
-// A = silu(Y); Y may be null when only A is needed (inference).  Block: a TX x TY x TZ tile of one sample (128 sites, 8 MFMA column
-// tiles, two per wave).  The input tile with a one-site halo is staged in LDS as BF16
-// [halo site][cip]; the weights follow in slabs of kSlab K chunks (32 rows of K
-// each), [cop][kSlab * 32 + 8] (the 8 extra columns stagger the rows over the LDS
-// banks), so the K loop reads only LDS.
+// Y[b][co][x] = bias[co] + sum_{ci,k} W[co][ci][k] X[b][ci][x + off_k], written as
+// ConvOut asks (pre-activation, FP32 activation, packed BF16 activation).  The input
+// tile with a one-site halo is staged in LDS as BF16 16-byte units of 8 channels,
+// unit-major: xs[cip / 8][halo site][8].  A B operand read takes one unit of 16
+// consecutive sites, i.e. 16 consecutive units: no two lanes of a 16-lane group share
+// an LDS bank, whatever cip is (site-major rows of cip >= 16 channels would put sites
+// 8 apart on the same banks).  The weights follow in slabs of kSlab K chunks (32 rows
+// of K each), [cop][kSlab * 32 + 8] (the 8 extra columns stagger the rows over the LDS
+// banks), so the K loop reads only LDS; the next slab's loads are in flight while the
+// current one is multiplied.  Small slabs keep a 16x8x4 block of a 16-channel layer
+// under 40 KB of LDS, four blocks per CU.
+// The weight gradient works on TX x TY x TZ tiles (128 sites) staged channel-major.
 constexpr int TX = 8, TY = 4, TZ = 4, TS = TX * TY * TZ;
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HS = HX * HY * HZ;
-constexpr int kSlab = 9;
+constexpr int kSlab = 4;
 constexpr int kSlabRow = kSlab * 32 + 8;
 
 // periodic index for -L <= v < 2L (boxes at least one tile wide), general otherwise
@@ -115,10 +122,9 @@ __device__ __forceinline__ void stage_halo_cm(const ConvIn &in, int b, int ci, i
     }
 }
 
-// A BX x BY x BZ tile site-major, xs[h][cip] with its one-site halo (forward): a work
-// item is one halo site and eight consecutive channels, written to LDS as one 16-byte
-// vector (consecutive items fill consecutive vectors); two items (16 loads) per thread
-// are in flight at once.
+// A BX x BY x BZ tile with its one-site halo, unit-major xs[cip / 8][h][8] (forward): a
+// work item is one halo site and eight consecutive channels, written to LDS as one
+// 16-byte unit; two items (16 loads) per thread are in flight at once.
 template <int BX, int BY, int BZ>
 __device__ __forceinline__ void stage_halo_sm(const ConvIn &in, int b, int ci, int cip, int L, int x0, int y0,
                                               int z0, __bf16 *xs)
@@ -140,7 +146,11 @@ __device__ __forceinline__ void stage_halo_sm(const ConvIn &in, int b, int ci, i
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int c = c8 * 8 + j;
-                v[u][j] = (ok && c < ci) ? conv_input(in, b, c, ci, gx, gy, gz, L) : 0.0f;
+                v[u][j] = 0.0f;
+                if (ok && c < ci) {
+                    v[u][j] = conv_input(in, b, c, ci, gx, gy, gz, L);
+                    if (in.shift) v[u][j] = (v[u][j] - in.shift[c]) * in.scale[c];
+                }
             }
         }
 #pragma unroll
@@ -150,7 +160,7 @@ __device__ __forceinline__ void stage_halo_sm(const ConvIn &in, int b, int ci, i
                 bf16x8 pk;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) pk[j] = (__bf16)v[u][j];
-                *reinterpret_cast<bf16x8 *>(xs + (e / oct) * cip + (e % oct) * 8) = pk;
+                *reinterpret_cast<bf16x8 *>(xs + ((e % oct) * GS + e / oct) * 8) = pk;
             }
         }
     }
@@ -164,7 +174,7 @@ template <int BX, int BY, int BZ>
 __device__ __forceinline__ void stage_halo_rows(const ConvIn &in, int b, int ci, int cip, int L, int x0, int y0,
                                                 int z0, __bf16 *xs)
 {
-    constexpr int GX = BX + 2, GY = BY + 2, GZ = BZ + 2;
+    constexpr int GX = BX + 2, GY = BY + 2, GZ = BZ + 2, GS = GX * GY * GZ;
     constexpr int NG = (BX + 8) / 4;   // float4 groups covering x in [x0 - 4, x0 + BX + 4)
     const int oct = cip / 8, total = GY * GZ * NG * oct;
     const long long V = (long long)L * L * L;
@@ -189,6 +199,7 @@ __device__ __forceinline__ void stage_halo_rows(const ConvIn &in, int b, int ci,
                     const long long a = ((long long)b * ci + c) * V + site;
                     v[u][j] = *reinterpret_cast<const floatv4 *>(in.x1 + a);
                     if (in.mode == CONV_IN_ADD) v[u][j] += *reinterpret_cast<const floatv4 *>(in.x2 + a);
+                    if (in.shift) v[u][j] = (v[u][j] - in.shift[c]) * in.scale[c];
                 }
             }
         }
@@ -205,10 +216,46 @@ __device__ __forceinline__ void stage_halo_rows(const ConvIn &in, int b, int ci,
                         bf16x8 pk;
 #pragma unroll
                         for (int j = 0; j < 8; ++j) pk[j] = (__bf16)v[u][j][q];
-                        *reinterpret_cast<bf16x8 *>(xs + (row * GX + hx) * cip + c8 * 8) = pk;
+                        *reinterpret_cast<bf16x8 *>(xs + (c8 * GS + row * GX + hx) * 8) = pk;
                     }
                 }
             }
+        }
+    }
+}
+
+// The same tile from a packed BF16 input (CONV_IN_PACKED): halo unit e (site e / (cip /
+// 8), channels 8 (e % (cip / 8)) + 0..7) is one 16-byte copy from global memory (site
+// after site, so the loads are contiguous) to its unit-major LDS place; eight copies
+// per thread are in flight at once.
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ void stage_halo_packed(const __bf16 *__restrict__ xp, int b, int cip, int L, int x0,
+                                                  int y0, int z0, __bf16 *xs)
+{
+    constexpr int GX = BX + 2, GY = BY + 2, GS = GX * GY * (BZ + 2);
+    constexpr int BMAX = BX > BY ? (BX > BZ ? BX : BZ) : (BY > BZ ? BY : BZ);
+    constexpr int U = 8;
+    const bool small = L < BMAX;
+    const int oct = cip / 8, total = GS * oct;
+    const __bf16 *base = xp + (long long)b * L * L * L * cip;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * U) {
+        bf16x8 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * 256;
+            if (e < total) {
+                const int c8 = e % oct, h = e / oct;
+                const int hx = h % GX, hy = (h / GX) % GY, hz = h / (GX * GY);
+                const int gx = wrap_tile(x0 + hx - 1, L, small), gy = wrap_tile(y0 + hy - 1, L, small),
+                          gz = wrap_tile(z0 + hz - 1, L, small);
+                const long long site = gx + (long long)L * (gy + (long long)L * gz);
+                v[u] = *reinterpret_cast<const bf16x8 *>(base + site * cip + 8 * c8);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * 256;
+            if (e < total) *reinterpret_cast<bf16x8 *>(xs + ((e % oct) * GS + e / oct) * 8) = v[u];
         }
     }
 }
@@ -223,18 +270,18 @@ constexpr size_t conv_fwd_lds_t(int cip, int cop)
 }
 
 // Block: a BX x BY x BZ tile of one sample; its 16-site MFMA column tiles are dealt to
-// the four waves (NTW each), each with up to two 16-channel output tiles (cop <= 32).
-template <int BX, int BY, int BZ>
+// the four waves (NTW each), each with NM = cop / 16 (1 or 2) 16-channel output tiles.
+template <int BX, int BY, int BZ, int NM>
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvIn in, int ci, int cip, const __bf16 *__restrict__ Wm, int kp,
-                                                   int co, int cop, const float *__restrict__ bias,
-                                                   float *__restrict__ Y, float *__restrict__ A, int L, int tiles_x,
-                                                   int tiles_y, int tiles_per_sample)
+                                                   int co, int cop, const float *__restrict__ bias, ConvOut out, int L,
+                                                   int tiles_x, int tiles_y, int tiles_per_sample)
 {
     constexpr int BS = BX * BY * BZ, GX = BX + 2, GY = BY + 2, GS = GX * GY * (BZ + 2);
     constexpr int NTW = BS / 64;   // column tiles per wave
+    constexpr int NPRE = (NM * 16 * kSlab * 4 + 255) / 256;   // weight vectors per thread and slab
     static_assert(BS % 64 == 0 && BX % 8 == 0, "tile shape");
     extern __shared__ __align__(16) unsigned char smem[];
-    __bf16 *xs = reinterpret_cast<__bf16 *>(smem);   // [GS][cip]
+    __bf16 *xs = reinterpret_cast<__bf16 *>(smem);   // [cip / 8][GS][8]
     __bf16 *ws = xs + GS * cip;                       // [cop][kSlabRow]
     int *koff = reinterpret_cast<int *>(ws + cop * kSlabRow);   // [kp / 8]
     const int bid = plan_block();   // neighbouring tiles on one XCD
@@ -245,25 +292,60 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvIn in, int ci, int cip, co
     const int y0 = (t % tiles_y) * BY;
     const int z0 = (t / tiles_y) * BZ;
     const long long V = (long long)L * L * L;
-    // LDS element offset, relative to a site's halo position times cip, of each group of
-    // eight K rows (tap k, channels c0..c0+7); padding rows point at the centre tap
-    // (zero weights there)
+    // weight slab k0 (rows of kp, k0 .. k0 + kSlab * 32) through registers: load(k0)
+    // issues the loads, store(k0) writes what arrived to LDS
+    bf16x8 wv[NPRE];
+    auto slab_vectors = [&](int k0, int &vec_per_row) {
+        vec_per_row = min(kSlab * 32, kp - k0) / 8;
+        return cop * vec_per_row;
+    };
+    auto load_slab = [&](int k0) {
+        int vpr;
+        const int nvec = slab_vectors(k0, vpr);
+#pragma unroll
+        for (int u = 0; u < NPRE; ++u) {
+            const int e = threadIdx.x + u * 256;
+            if (e < nvec) {
+                const int r = e / vpr, v8 = e - r * vpr;
+                wv[u] = *reinterpret_cast<const bf16x8 *>(Wm + (long long)r * kp + k0 + 8 * v8);
+            }
+        }
+    };
+    auto store_slab = [&](int k0) {
+        int vpr;
+        const int nvec = slab_vectors(k0, vpr);
+#pragma unroll
+        for (int u = 0; u < NPRE; ++u) {
+            const int e = threadIdx.x + u * 256;
+            if (e < nvec) {
+                const int r = e / vpr, v8 = e - r * vpr;
+                *reinterpret_cast<bf16x8 *>(ws + r * kSlabRow + 8 * v8) = wv[u];
+            }
+        }
+    };
+    load_slab(0);   // in flight with the tile's loads
+    // LDS element offset, relative to 8 times a site's halo position, of each group of
+    // eight K rows (tap k, channels c0..c0+7: unit c0 / 8 of the tap's neighbour);
+    // padding rows point at the centre tap (zero weights there)
     for (int g = threadIdx.x; g < kp / 8; g += 256) {
         int k = (8 * g) / cip;
         const int c0 = 8 * g - k * cip;
         if (k > 26) k = 13;
-        koff[g] = (((k / 9) - 1) * GX * GY + (((k / 3) % 3) - 1) * GX + ((k % 3) - 1)) * cip + c0;
+        koff[g] = ((((k / 9) - 1) * GX * GY + (((k / 3) % 3) - 1) * GX + ((k % 3) - 1)) + (c0 / 8) * GS) * 8;
     }
-    if ((in.mode == CONV_IN_PLAIN || in.mode == CONV_IN_ADD) && L % 4 == 0 && L >= BX && L >= BY && L >= BZ)
+    if (in.mode == CONV_IN_PACKED)
+        stage_halo_packed<BX, BY, BZ>(in.xp, b, cip, L, x0, y0, z0, xs);
+    else if ((in.mode == CONV_IN_PLAIN || in.mode == CONV_IN_ADD) && L % 4 == 0 && L >= BX && L >= BY && L >= BZ)
         stage_halo_rows<BX, BY, BZ>(in, b, ci, cip, L, x0, y0, z0, xs);
     else
         stage_halo_sm<BX, BY, BZ>(in, b, ci, cip, L, x0, y0, z0, xs);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane >> 4, col = lane & 15;
-    const int nmt = cop / 16;
-    floatx4 acc[NTW][2];
+    floatx4 acc[NTW][NM];
 #pragma unroll
-    for (int q = 0; q < NTW; ++q) acc[q][0] = acc[q][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < NTW; ++q)
+#pragma unroll
+        for (int m = 0; m < NM; ++m) acc[q][m] = floatx4{0.f, 0.f, 0.f, 0.f};
     // this lane's sites (column of the B operand): LDS element offsets of their halo
     // positions
     int hbase[NTW];
@@ -271,50 +353,35 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvIn in, int ci, int cip, co
     for (int q = 0; q < NTW; ++q) {
         const int n = (wave * NTW + q) * 16 + col;
         const int tx = n % BX, ty = (n / BX) % BY, tz = n / (BX * BY);
-        hbase[q] = ((tz + 1) * GX * GY + (ty + 1) * GX + (tx + 1)) * cip;
+        hbase[q] = ((tz + 1) * GX * GY + (ty + 1) * GX + (tx + 1)) * 8;
     }
     for (int k0 = 0; k0 < kp; k0 += kSlab * 32) {
         const int klen = min(kSlab * 32, kp - k0);
         __syncthreads();   // previous slab consumed (and, the first time, the halo staged)
-        const int vec_per_row = klen / 8, nvec = cop * vec_per_row;
-        for (int e0 = threadIdx.x; e0 < nvec; e0 += 256 * 4) {   // four 16-byte loads in flight
-            bf16x8 wv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = e0 + u * 256;
-                if (e < nvec) {
-                    const int r = e / vec_per_row, v8 = e - r * vec_per_row;
-                    wv[u] = *reinterpret_cast<const bf16x8 *>(Wm + (long long)r * kp + k0 + 8 * v8);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = e0 + u * 256;
-                if (e < nvec) {
-                    const int r = e / vec_per_row, v8 = e - r * vec_per_row;
-                    *reinterpret_cast<bf16x8 *>(ws + r * kSlabRow + 8 * v8) = wv[u];
-                }
-            }
-        }
+        store_slab(k0);
+        if (k0 + kSlab * 32 < kp) load_slab(k0 + kSlab * 32);
         __syncthreads();
         const __bf16 *wa = ws + col * kSlabRow + 8 * grp;
         const int *kg = koff + k0 / 8 + grp;
         for (int kc = 0; kc < klen; kc += 32) {
             const int off = kg[kc / 8];
-            const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(wa + kc);
-            bf16x8 a1 = a0;
-            if (nmt > 1) a1 = *reinterpret_cast<const bf16x8 *>(wa + 16 * kSlabRow + kc);
+            bf16x8 a[NM];
+#pragma unroll
+            for (int m = 0; m < NM; ++m) a[m] = *reinterpret_cast<const bf16x8 *>(wa + m * 16 * kSlabRow + kc);
 #pragma unroll
             for (int q = 0; q < NTW; ++q) {
                 const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(xs + hbase[q] + off);
-                acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv, acc[q][0], 0, 0, 0);
-                if (nmt > 1) acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv, acc[q][1], 0, 0, 0);
+#pragma unroll
+                for (int m = 0; m < NM; ++m)
+                    acc[q][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bv, acc[q][m], 0, 0, 0);
             }
         }
     }
     // epilogue: lane holds rows 4 grp + i of each M tile, column = its site
-    float *Yb = Y ? Y + (long long)b * co * V : nullptr;
-    float *Ab = A ? A + (long long)b * co * V : nullptr;
+    float *Yb = out.Y ? out.Y + (long long)b * co * V : nullptr;
+    float *Ab = out.A ? out.A + (long long)b * co * V : nullptr;
+    const int cpk = (co + 7) & ~7;   // channel stride of the packed activation
+    __bf16 *Pb = out.Ap ? out.Ap + (long long)b * V * cpk : nullptr;
 #pragma unroll
     for (int q = 0; q < NTW; ++q) {
         const int n = (wave * NTW + q) * 16 + col;
@@ -323,15 +390,25 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvIn in, int ci, int cip, co
         if (gx >= L || gy >= L || gz >= L) continue;
         const long long site = gx + (long long)L * (gy + (long long)L * gz);
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            if (m >= nmt) break;
+        for (int m = 0; m < NM; ++m) {
+            const int o0 = m * 16 + 4 * grp;
+            if (Pb && o0 < cpk) {   // four consecutive channels of the site: one 8-byte store
+                bf16x4 pk;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int o = o0 + i;
+                    pk[i] = (__bf16)(o < co ? silu(acc[q][m][i] + (bias ? bias[o] : 0.0f)) : 0.0f);
+                }
+                *reinterpret_cast<bf16x4 *>(Pb + site * cpk + o0) = pk;
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int o = m * 16 + 4 * grp + i;
+                const int o = o0 + i;
                 if (o >= co) continue;
-                const float y = acc[q][m][i] + (bias ? bias[o] : 0.0f);
-                if (Yb) Yb[(long long)o * V + site] = y;
+                float y = acc[q][m][i] + (bias ? bias[o] : 0.0f);
                 if (Ab) Ab[(long long)o * V + site] = silu(y);
+                if (out.shift) y = (y - out.shift[o]) * out.scale[o];
+                if (Yb) Yb[(long long)o * V + site] = y;
             }
         }
     }
@@ -724,28 +801,32 @@ static size_t lds_limit()
 
 template <int BX, int BY, int BZ>
 static void conv_fwd_launch(hipStream_t s, ConvIn in, int B, int ci, int cip, const __bf16 *Wm, int kp, int co,
-                            int cop, const float *bias, float *Y, float *A, int L)
+                            int cop, const float *bias, ConvOut out, int L)
 {
     const int tx = (L + BX - 1) / BX, ty = (L + BY - 1) / BY, tz = (L + BZ - 1) / BZ;
     const int tps = tx * ty * tz;
     const size_t lds = conv_fwd_lds_t<BX, BY, BZ>(cip, cop);
-    hipLaunchKernelGGL((k_conv_fwd<BX, BY, BZ>), dim3(B * tps), dim3(256), lds, s, in, ci, cip, Wm, kp, co, cop, bias,
-                       Y, A, L, tx, ty, tps);
+    if (cop == 16)
+        hipLaunchKernelGGL((k_conv_fwd<BX, BY, BZ, 1>), dim3(B * tps), dim3(256), lds, s, in, ci, cip, Wm, kp, co, cop,
+                           bias, out, L, tx, ty, tps);
+    else
+        hipLaunchKernelGGL((k_conv_fwd<BX, BY, BZ, 2>), dim3(B * tps), dim3(256), lds, s, in, ci, cip, Wm, kp, co, cop,
+                           bias, out, L, tx, ty, tps);
 }
 
 // Tile per layer: the largest of 16x8x4, 8x8x4, 8x4x4 that the box fills and whose LDS
 // (halo tile plus one weight slab) fits.  Larger tiles re-read fewer halo sites and
 // stage the weights for more sites.
 void net_conv_fwd(hipStream_t s, ConvIn in, int B, int ci, int cip, const __bf16 *Wm, int kp, int co, int cop,
-                  const float *bias, float *Y, float *A, int L)
+                  const float *bias, ConvOut out, int L)
 {
     const size_t lim = lds_limit();
     if (L >= 16 && conv_fwd_lds_t<16, 8, 4>(cip, cop) <= lim)
-        conv_fwd_launch<16, 8, 4>(s, in, B, ci, cip, Wm, kp, co, cop, bias, Y, A, L);
+        conv_fwd_launch<16, 8, 4>(s, in, B, ci, cip, Wm, kp, co, cop, bias, out, L);
     else if (L >= 8 && conv_fwd_lds_t<8, 8, 4>(cip, cop) <= lim)
-        conv_fwd_launch<8, 8, 4>(s, in, B, ci, cip, Wm, kp, co, cop, bias, Y, A, L);
+        conv_fwd_launch<8, 8, 4>(s, in, B, ci, cip, Wm, kp, co, cop, bias, out, L);
     else
-        conv_fwd_launch<8, 4, 4>(s, in, B, ci, cip, Wm, kp, co, cop, bias, Y, A, L);
+        conv_fwd_launch<8, 4, 4>(s, in, B, ci, cip, Wm, kp, co, cop, bias, out, L);
 }
 
 // Site slices of the weight gradient: enough blocks (groups x slices, about 1024) to

@@ -100,6 +100,32 @@ def test_forward_matches_oracle(hsf, NO, in_ch, out_ch, widths, B, L):
     net.close()
 
 
+@pytest.mark.parametrize("widths,L", [((16,), 32), ((8, 16, 24, 32), 16)])
+def test_forward_from_device_and_host_agree(hsf, widths, L):
+    """The forward pass reads device inputs in place (16-byte aligned ones with vector
+    loads, others after a copy) and writes device outputs in place: every route gives
+    the same bits as the host route, and the input buffer is left unchanged."""
+    import torch
+    say(f"[net forward routes] widths {widths} L {L}")
+    B, in_ch, out_ch = 2, 4, 2
+    net = hsf.Net(in_ch, out_ch, widths, seed=21)
+    net.set_input_norm([0.5, 0.4, 0.0, 0.1], [3.0, 2.0, 1.5, 1.0])
+    net.set_output_scale([2.0, 0.5])
+    x = smooth_inputs(B, in_ch, L, seed=8).ravel()
+    ref = net.forward(x, B, L)
+    n = x.size
+    for off in (0, 1, 2):   # offsets of 0, 4 and 8 bytes from a 256-byte aligned buffer
+        buf = torch.zeros(n + 4, dtype=torch.float32, device="cuda")
+        buf[off:off + n] = torch.from_numpy(x).cuda()
+        before = buf.clone()
+        y = torch.full((B * out_ch * L ** 3,), float("nan"), dtype=torch.float32, device="cuda")
+        net.forward(buf[off:off + n], B, L, out=y)
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy(), ref), f"offset {off}"
+        assert torch.equal(buf, before)
+    net.close()
+
+
 @pytest.mark.parametrize("B,L,widths", [(2, 16, WIDTHS), (4, 16, WIDTHS), (1, 24, WIDTHS), (2, 12, (8, 16)),
                                          (1, 12, (8, 12, 16)), (2, 7, (8,))])
 def test_gradient_matches_oracle(hsf, NO, B, L, widths):
