@@ -145,12 +145,14 @@ def learned_arm(hsf, workload, precision, steps, warmup, tile, log, precond=Fals
     }
 
 
-def run_arm(hsf, torch, wls, steps, warmup, timing, log, precond=False, tile=None, noise_omega=None):
-    """Build a batched context, autotune, warm up, time `steps` coupled steps."""
+def run_arm(hsf, torch, wls, steps, warmup, timing, log, precond=False, tile=None, noise_omega=None, hydro=True):
+    """Build a batched context, autotune, warm up, time `steps` coupled steps (with the
+    LB flow, or purely diffusive with hydro=False)."""
     from paper_1204_2088_amd import workloads as W
     stream = torch.cuda.current_stream()
     ctx = hsf.Context(wls, stream=stream)
     ctx.set_solver(precond=precond)
+    ctx.set_hydro(hydro)
     if noise_omega:
         ctx.set_noise(cd=True, lb=True, omega=noise_omega, seed=2012)
     phi0 = np.concatenate([W.initial_composition(w).ravel() for w in wls])
@@ -268,6 +270,8 @@ def main():
                     help="LB collision: BGK, or the MRT scheme with the shear viscosity of the workload's tau, "
                          "the same bulk eigenvalue and the kinetic modes relaxed completely")
     ap.add_argument("--no-cn-arm", action="store_true", help="skip the Crank-Nicolson (dt 0.4) arm")
+    ap.add_argument("--no-diffusive-arm", action="store_true",
+                    help="skip the purely diffusive run (LB velocity zeroed) of the 96^3 A4B12 melt")
     ap.add_argument("--cn-dt", type=float, default=0.4, help="time step of the Crank-Nicolson arm")
     ap.add_argument("--noise", type=float, default=None, metavar="OMEGA",
                     help="thermal noise in both the compositions (eq. 5) and the LB modes (eq. 13) "
@@ -398,6 +402,16 @@ def main():
                                            "sim_time_per_s", "newton_tol_rms")}
         cn["fp32"]["speedup_sim_time"] = c32["sim_time_per_s"] / cn["explicit_sim_time_per_s"]
 
+    diffusive = None
+    if args.workload.startswith("melt96") and not args.no_diffusive_arm:
+        # the asymmetric melt is run with and without the flow
+        cd_, _, _, std, (evd, sed), eld, _, _, _ = run_arm(hsf, torch, wls, args.steps, args.warmup, False, log,
+                                                          args.precond, tuple(tile), args.noise, hydro=False)
+        diffusive = {"value": 2 * N * sed / eld, "unit": "site·bead updates/s", "steps": args.steps,
+                     "ms_per_step": 1e3 * eld / args.steps, "evals_per_step": evd / args.steps,
+                     "iterations_last_step": [x["iterations"] for x in std][:8], "tile": list(tile)}
+        cd_.close()
+
     learned = None
     if args.workload in LEARNED and not args.no_learned:
         learned = learned_arm(hsf, args.workload, args.precision, args.steps, args.warmup, tuple(tile), log,
@@ -431,6 +445,7 @@ def main():
                                  "launch": "direct, one event pair per hot kernel"},
         "roofline": roofline,
         "fp64_arm": fp64_arm,
+        "diffusive_arm": diffusive,
         "learned_warm_start": learned,
         "observables": observables,
         "crank_nicolson": cn,
