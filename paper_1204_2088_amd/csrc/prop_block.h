@@ -18,8 +18,11 @@ struct TileCfg {
     X(32, 8, 1, 0)          \
     X(16, 16, 1, 0)         \
     X(64, 4, 2, 0)          \
+    X(32, 8, 2, 0)          \
+    X(16, 16, 2, 0)         \
     X(64, 4, 4, 0)          \
     X(32, 8, 4, 0)          \
+    X(16, 16, 4, 0)         \
     X(64, 4, 8, 0)          \
     X(8, 8, 8, 1)           \
     X(8, 8, 8, 2)           \
