@@ -24,6 +24,7 @@ struct TileCfg {
     X(32, 8, 4, 0)          \
     X(16, 16, 4, 0)         \
     X(64, 4, 8, 0)          \
+    X(16, 16, 8, 0)         \
     X(8, 8, 8, 1)           \
     X(8, 8, 8, 2)           \
     X(8, 8, 8, 3)           \
