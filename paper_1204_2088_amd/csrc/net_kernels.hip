@@ -92,32 +92,45 @@ __device__ __forceinline__ float conv_input(const ConvIn &in, int b, int c, int 
     return in.mode == CONV_IN_ADD ? in.x1[e] + in.x2[e] : in.x1[e];
 }
 
-// Stage the input tile of sample b with its one-site halo into LDS as BF16,
-// channel-major xs[c][HS] (weight gradient); channels ci..cip-1 are zero.  Loads are
-// issued eight elements per thread before any is used, so their latencies overlap.
-__device__ __forceinline__ void stage_halo_cm(const ConvIn &in, int b, int ci, int cip, int L, int x0, int y0,
-                                              int z0, __bf16 *xs)
+// Input rows of a TX x TY x TZ tile for the weight gradient, in LDS as BF16 in three
+// x-shifted copies: xr[d][c][hz][hy][8] holds, for d = dx + 1, the input at x = x0 +
+// dx + 0..7 of halo row (hy, hz) and channel c (channels ci..cip-1 zero; the channel
+// pitch kWgChan pads 6 x 6 x 8 by 8 so the 16 lanes of a B operand read, 16 channels of
+// one row, fall on distinct banks).  Every B operand of the K loop (8 consecutive
+// sites of one channel at one tap) is then one aligned 16-byte read.
+constexpr int kWgRows = (TZ + 2) * (TY + 2);   // halo rows of a tile
+constexpr int kWgChan = kWgRows * TX + 8;      // channel pitch of a copy (elements)
+constexpr int kWgYPitch = TS + 8;               // row pitch of the staged dY tile (odd in 16-byte units)
+__device__ __forceinline__ void stage_rows3(const ConvIn &in, int b, int ci, int cip, int L, int x0, int y0, int z0,
+                                            __bf16 *xr)
 {
+    // a work item is one value (halo position q of a row; consecutive items are
+    // consecutive x, so a wave's loads are contiguous), stored into each copy that holds
+    // it; eight values per thread in flight at once
     const bool small = L < TX;
-    const int total = HS * cip;
+    const int total = cip * kWgRows * (TX + 2);
     for (int e0 = threadIdx.x; e0 < total; e0 += 256 * 8) {
         float v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = e0 + u * 256;
+            const int q = e % (TX + 2), r = e / (TX + 2), c = r / kWgRows, row = r % kWgRows;
+            const int hz = row / HY, hy = row % HY;
             v[u] = 0.0f;
-            const int h = e % HS, c = e / HS;
-            if (e < total && c < ci) {
-                const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
-                const int gx = wrap_tile(x0 + hx - 1, L, small), gy = wrap_tile(y0 + hy - 1, L, small),
-                          gz = wrap_tile(z0 + hz - 1, L, small);
-                v[u] = conv_input(in, b, c, ci, gx, gy, gz, L);
-            }
+            if (e < total && c < ci)
+                v[u] = conv_input(in, b, c, ci, wrap_tile(x0 + q - 1, L, small), wrap_tile(y0 + hy - 1, L, small),
+                                  wrap_tile(z0 + hz - 1, L, small), L);
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = e0 + u * 256;
-            if (e < total) xs[(e / HS) * HS + e % HS] = (__bf16)v[u];
+            if (e >= total) continue;
+            const int q = e % (TX + 2), r = e / (TX + 2), c = r / kWgRows, row = r % kWgRows;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int x = q - d;   // position of this value in copy d
+                if (x >= 0 && x < TX) xr[(d * cip + c) * kWgChan + row * TX + x] = (__bf16)v[u];
+            }
         }
     }
 }
@@ -416,11 +429,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvIn in, int ci, int cip, co
 
 // ---------------------------------------------------------------- weight gradient
 // dW[co][k cip + ci] = sum_b sum_x dY[b][co][x] X[b][ci][x + off_k], as the GEMM
-// C (cop x kp) = A (cop x sites) B (sites x kp).  Block (g, sp): the 16 C tiles of
-// group g (4 per wave, accumulated in registers) over the site tiles sp, sp + nsp, ...
-// (K chunks of 32 sites = 4 x-rows of 8).  Partial C per site slice goes to `part`
-// [sp][cop][kp] and is summed in a fixed order by k_sum_blocks.
-constexpr int WG_TILES_PER_WAVE = 4;
+// C (cop x kp) = A (cop x sites) B (sites x kp).  Block (g, sp): the up to 4 x
+// WG_TILES_PER_WAVE C tiles of group g (WG_TILES_PER_WAVE per wave, accumulated in
+// registers) over the site tiles sp, sp + nsp, ... (K chunks of 32 sites = 4 x-rows of
+// 8).  A operands (dY, [cop][TS]) are shared by a wave's tiles; B operands come from
+// the shifted row copies (one 16-byte read each).  Partial C per site slice goes to
+// `part` [sp][cop][kp] and is summed in a fixed order by k_sum_blocks.
+constexpr int WG_TILES_PER_WAVE = 8;
+constexpr int WG_TILES_PER_BLOCK = 4 * WG_TILES_PER_WAVE;
 
 __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn in, int ci, int cip,
                                                      const float *__restrict__ dY, int co, int cop, int kp,
@@ -429,13 +445,27 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn in, int ci, int cip,
                                                      float *__restrict__ part)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __bf16 *xs = reinterpret_cast<__bf16 *>(smem);      // [cip][HS]   (site fastest)
-    __bf16 *ys = xs + (size_t)cip * HS;                 // [cop][TS]
+    __bf16 *xr = reinterpret_cast<__bf16 *>(smem);        // [3][cip][kWgChan]
+    __bf16 *ys = xr + (size_t)3 * cip * kWgChan;         // [cop][kWgYPitch]
     const int g = blockIdx.x % n_groups, sp = blockIdx.x / n_groups;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane >> 4, col = lane & 15;
     const int nnt = kp / 16, ntiles = (cop / 16) * nnt;
     const long long V = (long long)L * L * L;
+    // this lane's B column of each of the wave's tiles: LDS offset of the row copy at the
+    // tile's centre row (-1 for the zero padding rows of K) and the tile's M tile
+    int boff[WG_TILES_PER_WAVE], mt[WG_TILES_PER_WAVE];
+#pragma unroll
+    for (int j = 0; j < WG_TILES_PER_WAVE; ++j) {
+        const int tix = g * WG_TILES_PER_BLOCK + wave * WG_TILES_PER_WAVE + j;
+        const int nt = tix % nnt, kk = nt * 16 + col, k = kk / cip, c = kk - k * cip;
+        mt[j] = tix / nnt;
+        boff[j] = -1;
+        if (tix < ntiles && k <= 26) {
+            const int dx = (k % 3) - 1, dy = ((k / 3) % 3) - 1, dz = (k / 9) - 1;
+            boff[j] = ((dx + 1) * cip + c) * kWgChan + ((1 + dz) * HY + (1 + dy)) * TX;
+        }
+    }
     floatx4 acc[WG_TILES_PER_WAVE];
 #pragma unroll
     for (int j = 0; j < WG_TILES_PER_WAVE; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -447,7 +477,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn in, int ci, int cip,
         const int y0 = (t % tiles_y) * TY;
         const int z0 = (t / tiles_y) * TZ;
         __syncthreads();
-        stage_halo_cm(in, b, ci, cip, L, x0, y0, z0, xs);
+        stage_rows3(in, b, ci, cip, L, x0, y0, z0, xr);
         for (int e0 = threadIdx.x; e0 < TS * cop; e0 += 256 * 8) {
             float v[8];
 #pragma unroll
@@ -463,34 +493,31 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn in, int ci, int cip,
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int e = e0 + u * 256;
-                if (e < TS * cop) ys[(e / TS) * TS + e % TS] = (__bf16)v[u];
+                if (e < TS * cop) ys[(e / TS) * kWgYPitch + e % TS] = (__bf16)v[u];
             }
         }
         __syncthreads();
+#pragma unroll 1
         for (int kc = 0; kc < TS; kc += 32) {
             // 8 consecutive sites of this lane group: one x-row of the tile
             const int s0 = kc + 8 * grp;
             const int ty = (s0 / TX) % TY, tz = s0 / (TX * TY);
+            const int roff = (tz * HY + ty) * TX;
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(ys + col * kWgYPitch + s0);
+            bf16x8 a1 = a0;
+            if (cop > 16) a1 = *reinterpret_cast<const bf16x8 *>(ys + (16 + col) * kWgYPitch + s0);
 #pragma unroll
             for (int j = 0; j < WG_TILES_PER_WAVE; ++j) {
-                const int tix = g * 16 + wave * WG_TILES_PER_WAVE + j;
+                const int tix = g * WG_TILES_PER_BLOCK + wave * WG_TILES_PER_WAVE + j;
                 if (tix < ntiles) {
-                    const int m = tix / nnt, nt = tix % nnt;
-                    const bf16x8 av = *reinterpret_cast<const bf16x8 *>(ys + (m * 16 + col) * TS + s0);
-                    const int kk = nt * 16 + col;
-                    int k = kk / cip;
-                    const int c = kk - k * cip;
                     bf16x8 bv;
-                    if (k > 26) {
+                    if (boff[j] < 0) {
 #pragma unroll
                         for (int q = 0; q < 8; ++q) bv[q] = (__bf16)0.0f;
                     } else {
-                        const int dx = (k % 3) - 1, dy = ((k / 3) % 3) - 1, dz = (k / 9) - 1;
-                        const __bf16 *row = xs + c * HS + (tz + 1 + dz) * HX * HY + (ty + 1 + dy) * HX + 1 + dx;
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) bv[q] = row[q];
+                        bv = *reinterpret_cast<const bf16x8 *>(xr + boff[j] + roff);
                     }
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mt[j] ? a1 : a0, bv, acc[j], 0, 0, 0);
                 }
             }
         }
@@ -498,7 +525,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn in, int ci, int cip,
     float *P = part + (long long)sp * cop * kp;
 #pragma unroll
     for (int j = 0; j < WG_TILES_PER_WAVE; ++j) {
-        const int tix = g * 16 + wave * WG_TILES_PER_WAVE + j;
+        const int tix = g * WG_TILES_PER_BLOCK + wave * WG_TILES_PER_WAVE + j;
         if (tix < ntiles) {
             const int m = tix / nnt, nt = tix % nnt;
 #pragma unroll
@@ -508,22 +535,23 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn in, int ci, int cip,
 }
 
 // out[e] = sum_b part[b][e], e < n, in a fixed order: thread (j, e) sums the partials
-// b = j, j + 8, ... of element e; the 8 sums are then added in order j = 0..7.
+// b = j, j + 32, ... of element e; the 32 sums are then added in order j = 0..31.  A
+// block covers 8 elements (32-byte rows of consecutive elements per partial).
 __global__ __launch_bounds__(256) void k_sum_blocks(const float *__restrict__ part, int nblk, long long n,
                                                     float *__restrict__ out)
 {
-    __shared__ float red[8][32];
-    const int el = threadIdx.x & 31, j = threadIdx.x >> 5;
-    const long long e = (long long)blockIdx.x * 32 + el;
+    __shared__ float red[32][8];
+    const int el = threadIdx.x & 7, j = threadIdx.x >> 3;
+    const long long e = (long long)blockIdx.x * 8 + el;
     float s = 0.0f;
     if (e < n)
-        for (int b = j; b < nblk; b += 8) s += part[(long long)b * n + e];
+        for (int b = j; b < nblk; b += 32) s += part[(long long)b * n + e];
     red[j][el] = s;
     __syncthreads();
     if (j == 0 && e < n) {
         float t = red[0][el];
 #pragma unroll
-        for (int q = 1; q < 8; ++q) t += red[q][el];
+        for (int q = 1; q < 32; ++q) t += red[q][el];
         out[e] = t;
     }
 }
@@ -836,7 +864,7 @@ int net_wgrad_slices(int B, int L, int cop, int kp)
 {
     const int tx = (L + TX - 1) / TX, ty = (L + TY - 1) / TY, tz = (L + TZ - 1) / TZ;
     const int n_tiles = B * tx * ty * tz;
-    const int groups = ((cop / 16) * (kp / 16) + 15) / 16;
+    const int groups = ((cop / 16) * (kp / 16) + WG_TILES_PER_BLOCK - 1) / WG_TILES_PER_BLOCK;
     const int want = std::max(1, 1024 / groups);
     return std::min(n_tiles, want);
 }
@@ -847,12 +875,12 @@ void net_conv_wgrad(hipStream_t s, ConvIn in, int B, int ci, int cip, const floa
     const int tx = (L + TX - 1) / TX, ty = (L + TY - 1) / TY, tz = (L + TZ - 1) / TZ;
     const int tps = tx * ty * tz, n_tiles = B * tps;
     const int slices = net_wgrad_slices(B, L, cop, kp);
-    const int ntiles = (cop / 16) * (kp / 16), groups = (ntiles + 15) / 16;
-    const size_t lds = ((size_t)cip * HS + (size_t)cop * TS) * sizeof(__bf16);
+    const int ntiles = (cop / 16) * (kp / 16), groups = (ntiles + WG_TILES_PER_BLOCK - 1) / WG_TILES_PER_BLOCK;
+    const size_t lds = ((size_t)3 * cip * kWgChan + (size_t)cop * kWgYPitch) * sizeof(__bf16);
     hipLaunchKernelGGL(k_conv_wgrad, dim3(groups * slices), dim3(256), lds, s, in, ci, cip, dY, co, cop, kp, L, tx,
                        ty, tps, n_tiles, groups, slices, part);
     const long long n = (long long)cop * kp;
-    hipLaunchKernelGGL(k_sum_blocks, dim3(nb(n, 32)), dim3(256), 0, s, part, slices, n, dWm);
+    hipLaunchKernelGGL(k_sum_blocks, dim3(nb(n, 8)), dim3(256), 0, s, part, slices, n, dWm);
 }
 
 void net_silu_bwd(hipStream_t s, const float *dA, const float *Y, float *dY, long long n)
