@@ -125,3 +125,34 @@ def test_melt64_fp32_trajectory_error_on_crop(hsf, orc):
         say(f"[fp32 trajectory] step {10 * (k + 1)}: crop rel err {e:.3e}")
     assert worst < TOL32
     ctx.close()
+
+
+def test_melt64_pair_fp32_2000_steps_error_on_crop(hsf, orc):
+    """The 64^3 A8B8 pair (tau 0.6 and 1.5, one batched context, FP32 propagators,
+    residual 1e-6, LB flow on) over 2000 coupled steps: every 200th step the oracle
+    evaluates phi[w^n] at each replica's own fields over the full box, and the GPU's
+    FP32 densities at the same fields are compared on the 32^3 crop [0, 32)^3."""
+    wls = [W.melt64_a8b8(tau=0.6), W.melt64_a8b8(tau=1.5)]
+    ctx = hsf.Context(wls)
+    ctx.set_densities(np.concatenate([W.initial_composition(wl).ravel() for wl in wls]))
+    ctx.autotune(reps=2)
+    crop = (slice(None), slice(0, 32), slice(0, 32), slice(0, 32))
+    worst = 0.0
+    for k in range(10):
+        st, _ = ctx.step(200, tol=wls[0].tol, max_iter=1000)
+        assert all(s["converged"] for s in st)
+        w_all, phi_all = ctx.get_fields(), ctx.get_densities()
+        got_all, _ = ctx.evaluate()
+        errs = []
+        for r, wl in enumerate(wls):
+            o, n = ctx.field_offset(r), 2 * wl.V
+            w = w_all[o:o + n].reshape((2,) + wl.shape)
+            phi = phi_all[o:o + n].reshape((2,) + wl.shape)
+            got = got_all[o:o + n].reshape((2,) + wl.shape)
+            ref, _ = orc.evaluate(osys(orc, wl), w, phi.sum(0).mean(), 0.0)
+            errs.append(max(np.max(np.abs(got[crop][i] - ref[crop][i])) / np.max(np.abs(ref[crop][i]))
+                            for i in range(2)))
+        worst = max(worst, max(errs))
+        say(f"[fp32 pair trajectory] step {200 * (k + 1)}: crop rel err tau 0.6 {errs[0]:.3e}, tau 1.5 {errs[1]:.3e}")
+    assert worst < TOL32
+    ctx.close()
