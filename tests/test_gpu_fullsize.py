@@ -156,3 +156,30 @@ def test_melt64_pair_fp32_2000_steps_error_on_crop(hsf, orc):
         say(f"[fp32 pair trajectory] step {200 * (k + 1)}: crop rel err tau 0.6 {errs[0]:.3e}, tau 1.5 {errs[1]:.3e}")
     assert worst < TOL32
     ctx.close()
+
+
+@pytest.mark.parametrize("hydro", [True, False], ids=["flow", "diffusive"])
+def test_melt96_fp32_run_error(hsf, orc, hydro):
+    """The 96^3 A4B12 melt (FP32 propagators, residual 1e-6) over 500 coupled steps,
+    with the LB flow and purely diffusive (velocity zeroed): every 100th step the
+    oracle evaluates phi[w^n] at the run's own fields and the GPU's FP32 densities at
+    the same fields are compared over the whole box."""
+    wl = W.melt96_a4b12()
+    ctx = hsf.Context(wl)
+    ctx.set_hydro(hydro)
+    ctx.set_densities(W.initial_composition(wl).ravel())
+    ctx.autotune(reps=2)
+    worst = 0.0
+    for k in range(5):
+        st, _ = ctx.step(100, tol=wl.tol, max_iter=1000)
+        assert st[0]["converged"]
+        w = ctx.get_fields().reshape((2,) + wl.shape)
+        phi = ctx.get_densities().reshape((2,) + wl.shape)
+        got, _ = ctx.evaluate()
+        got = got.reshape((2,) + wl.shape)
+        ref, _ = orc.evaluate(osys(orc, wl), w, phi.sum(0).mean(), 0.0)
+        e = max(np.max(np.abs(got[i] - ref[i])) / np.max(np.abs(ref[i])) for i in range(2))
+        worst = max(worst, e)
+        say(f"[96^3 {'flow' if hydro else 'diffusive'}] step {100 * (k + 1)}: rel err {e:.3e}")
+    assert worst < TOL32
+    ctx.close()
