@@ -183,3 +183,26 @@ def test_melt96_fp32_run_error(hsf, orc, hydro):
         say(f"[96^3 {'flow' if hydro else 'diffusive'}] step {100 * (k + 1)}: rel err {e:.3e}")
     assert worst < TOL32
     ctx.close()
+
+
+@pytest.mark.parametrize("name,steps,every", [("vesicle128_a3b9s", 100, 50), ("batch48_a3b9s", 20, 10)])
+def test_solution_runs_error(hsf, orc, name, steps, every):
+    """The 128^3 vesicle-forming solution and the 48 batched replicas (FP32 propagators,
+    preconditioned inversion to 1e-6, LB flow on) along a run: at checkpoints the oracle
+    evaluates phi[w^n] at the run's own fields (for the batch, one replica of each box
+    size) and the GPU's FP32 densities at the same fields are compared."""
+    wls = [W.vesicle128_a3b9s()] if name == "vesicle128_a3b9s" else W.batch48_a3b9s()
+    say(f"[{name} run]")
+    ctx = hsf.Context(wls)
+    ctx.set_solver(precond=True)
+    ctx.set_densities(np.concatenate([W.initial_composition(w).ravel() for w in wls]))
+    ctx.autotune(reps=2)
+    picks = {}
+    for r, w in enumerate(wls):
+        picks.setdefault(w.L[0], r)
+    for k in range(steps // every):
+        st, _ = ctx.step(every, tol=wls[0].tol, max_iter=3000)
+        assert all(s["converged"] for s in st)
+        say(f" step {every * (k + 1)}:")
+        check_context(hsf, orc, wls, ctx, sorted(picks.values()), TOL32)
+    ctx.close()
