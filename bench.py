@@ -111,17 +111,18 @@ LEARNED = {
 }
 
 
-def learned_arm(hsf, workload, precision, steps, warmup, tile, log, precond=False):
+def learned_arm(hsf, workload, precision, steps, warmup, tile, log, precond=False, widths=None):
     """The learned warm start on the benchmark's own workload: a network trained on
     the GPU from FP64 trajectories of other seeds, then every warm start run on the
     benchmark's seed from the same states: `warmup` steps after the quench (the
-    window the main arm times) and later ones."""
+    window the main arm times) and later ones.  widths: the network's level widths
+    (default: the one-level net of the warm-start module)."""
     from paper_1204_2088_amd import warmnet
     from paper_1204_2088_amd import workloads as W
     rc = LEARNED[workload]
     net, info = warmnet.train_warm_start(lambda seed: rc["train"](W, seed), seeds=rc["seeds"], steps=rc["steps"],
                                          record=rc["record"], iters=rc["iters"], val_seed=5, log=None,
-                                         precond=precond)
+                                         precond=precond, widths=widths or warmnet.DEFAULT_WIDTHS)
     log(f"# warm-start network trained: {info}")
     wls = make_workloads(workload, precision)
     modes = [hsf.WARM_CURRENT, hsf.WARM_EXTRAP, hsf.WARM_NET_EXTRAP]
@@ -267,6 +268,8 @@ def main():
     ap.add_argument("--precond", action="store_true", help="diagonally preconditioned inversion")
     ap.add_argument("--tile", default=None, help="cx,cy,cz,k: use this propagator tiling instead of autotuning")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
+    ap.add_argument("--net-widths", default=None, metavar="WIDTHS",
+                    help="level widths of the learned warm start's network (e.g. 8,16,24,32; default one level of 16)")
     ap.add_argument("--lb", default="bgk", choices=["bgk", "mrt"],
                     help="LB collision: BGK, or the MRT scheme with the shear viscosity of the workload's tau, "
                          "the same bulk eigenvalue and the kinetic modes relaxed completely")
@@ -416,7 +419,8 @@ def main():
     learned = None
     if args.workload in LEARNED and not args.no_learned:
         learned = learned_arm(hsf, args.workload, args.precision, args.steps, args.warmup, tuple(tile), log,
-                              precond=args.precond)
+                              precond=args.precond,
+                              widths=tuple(int(v) for v in args.net_widths.split(",")) if args.net_widths else None)
 
     out = {
         "metric": METRIC,
