@@ -520,3 +520,38 @@ def test_batch_kernel_modes(hsf, orc, n_rep, precision):
             assert res < (1e-8 if precision == "fp64" else 1e-6 + 5e-7), (tile, r, res)
         say(f"  tile {tile}: evaluate ok, inversion iterations {its}")
         ctx.close()
+
+
+@pytest.mark.parametrize("types,L", [([0], (9, 7, 5)), ([1], (6, 8, 5)), (W.chain(1, 1), (7, 6, 9)),
+                                     (W.chain(32, 32), (10, 9, 8)), (W.chain(5, 59), (6, 6, 7))],
+                         ids=["n1_a", "n1_b", "n2_a1b1", "n64_a32b32", "n64_a5b59"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_chain_length_extremes(hsf, orc, types, L, precision):
+    """Single-bead chains (step 1 is step N: Q cannot be folded into the first backward
+    step), the shortest diblock and the longest chain the library takes (64 beads: every
+    slot of the per-step scales and the stored propagators in use), in a one-step and a
+    blocked tiling.  A species the chain does not contain has density exactly zero."""
+    wl = small_melt(L=L, types=types, precision=precision)
+    N = len(types)
+    frac = np.array([types.count(0) / N, types.count(1) / N])
+    phi0 = np.ascontiguousarray(np.broadcast_to(frac[:, None, None, None], (2,) + wl.shape))
+    w = fields_for(wl, seed=13, amp=1.5)
+    ref, qref = orc.evaluate(osys(orc, wl), w, 1.0, 0.0)
+    tol = TOL64 if precision == "fp64" else TOL32
+    ctx = hsf.Context(wl)
+    ctx.set_densities(phi0.ravel())
+    ctx.set_fields(w.ravel())
+    for tile in ((64, 4, 2, 0), (8, 8, 8, 2)):
+        ctx.set_tile(tile)
+        got, q = ctx.evaluate()
+        got = got.reshape(ref.shape)
+        errs = []
+        for i in range(2):
+            if frac[i] == 0:
+                assert np.all(got[i] == 0.0), (tile, i)
+            else:
+                errs.append(np.max(np.abs(got[i] - ref[i])) / np.max(np.abs(ref[i])))
+        say(f"[chain N={N} {types[:3]}...] {precision} tile {tile}: rel err {max(errs):.3e}, "
+            f"Q {q[0]:.6e} vs {qref:.6e}")
+        assert max(errs) < tol and abs(q[0] / qref - 1) < tol, tile
+    ctx.close()
