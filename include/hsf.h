@@ -59,6 +59,10 @@ extern "C" {
 #endif
 
 #define HSF_MAX_BEADS 64
+/* Largest box of one replica, Lx * Ly * Lz sites (site indices within a replica are
+ * 32-bit); hsf_create refuses larger boxes with HSF_EINVAL.  The replicas of a context
+ * together may hold more. */
+#define HSF_MAX_SITES 2147483647LL
 
 enum {
     HSF_OK = 0,

@@ -775,6 +775,7 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
         for (int s = 0; s < p.n_beads; ++s)
             if (p.types[s] != p0.types[s] || p.types[s] < 0 || p.types[s] > 1) return HSF_EINVAL;
         if (p.Lx < 1 || p.Ly < 1 || p.Lz < 1) return HSF_EINVAL;
+        if ((long long)p.Lx * p.Ly * p.Lz > HSF_MAX_SITES) return HSF_EINVAL;
         if (!(p.tau > 0.5) || !(p.dt > 0.0)) return HSF_EINVAL;
         if (p.lb_mode != HSF_LB_BGK && p.lb_mode != HSF_LB_MRT) return HSF_EINVAL;
         if (p.lb_mode == HSF_LB_MRT && !(std::fabs(p.gamma_s) < 1.0 && std::fabs(p.gamma_b) < 1.0 &&

@@ -55,6 +55,16 @@ def test_create_rejects_bad_parameters_without_gpu():
     arr = (hsf.Params * 2)(hsf.params_from_workload(wl), hsf.params_from_workload(wl, precision="fp32"))
     assert lib.hsf_create(arr, 2, ctypes.byref(h)) == hsf.HSF_EINVAL
     assert lib.hsf_create(arr, 0, ctypes.byref(h)) == hsf.HSF_EINVAL
+    # a box above the 32-bit site limit (1291^3 > 2^31 - 1), and one whose edge product
+    # overflows 32 bits outright
+    for L in ((1291, 1291, 1291), (65536, 65536, 2)):
+        p = hsf.params_from_workload(wl)
+        p.Lx, p.Ly, p.Lz = L
+        assert lib.hsf_create(ctypes.byref(p), 1, ctypes.byref(h)) == hsf.HSF_EINVAL, L
+        assert not h.value
+    p = hsf.params_from_workload(wl)
+    p.Lx = 0
+    assert lib.hsf_create(ctypes.byref(p), 1, ctypes.byref(h)) == hsf.HSF_EINVAL
 
 
 def test_param_structs_match_header(tmp_path):
