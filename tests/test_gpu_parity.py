@@ -555,3 +555,32 @@ def test_chain_length_extremes(hsf, orc, types, L, precision):
             f"Q {q[0]:.6e} vs {qref:.6e}")
         assert max(errs) < tol and abs(q[0] / qref - 1) < tol, tile
     ctx.close()
+
+
+@pytest.mark.parametrize("L", [(1, 1, 1), (2, 1, 1), (1, 3, 1), (1, 1, 2)], ids=lambda L: "x".join(map(str, L)))
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_smallest_boxes(hsf, orc, L, precision):
+    """Boxes of one to three sites, where every neighbour of the 27-point stencil wraps
+    onto the same few sites: densities and Q against the oracle in a one-step and a
+    blocked tiling, then one coupled step (inversion, LB, convection-diffusion) keeps
+    each species' amount and stays finite."""
+    wl = small_melt(L=L, types=W.chain(2, 3), precision=precision)
+    phi0 = W.initial_composition(wl)
+    w = fields_for(wl, seed=17, amp=1.0)
+    ref, qref = orc.evaluate(osys(orc, wl), w, phi0.sum(0).mean(), 0.0)
+    tol = TOL64 if precision == "fp64" else TOL32
+    ctx = hsf.Context(wl)
+    ctx.set_densities(phi0.ravel())
+    ctx.set_fields(w.ravel())
+    for tile in ((64, 4, 2, 0), (8, 8, 8, 2)):
+        ctx.set_tile(tile)
+        got, q = ctx.evaluate()
+        e = relerr(got, ref)
+        say(f"[box {L}] {precision} tile {tile}: rel err {e:.3e}, Q {q[0]:.6e} vs {qref:.6e}")
+        assert e < tol and abs(q[0] / qref - 1) < tol, tile
+    st, _ = ctx.step(1, tol=1e-10 if precision == "fp64" else 1e-6, max_iter=500)
+    assert st[0]["converged"]
+    phi1 = ctx.get_densities().reshape(phi0.shape)
+    assert np.all(np.isfinite(phi1))
+    assert np.max(np.abs(phi1.sum(axis=(1, 2, 3)) - phi0.sum(axis=(1, 2, 3)))) < 1e-12
+    ctx.close()
