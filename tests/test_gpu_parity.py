@@ -584,3 +584,50 @@ def test_smallest_boxes(hsf, orc, L, precision):
     assert np.all(np.isfinite(phi1))
     assert np.max(np.abs(phi1.sum(axis=(1, 2, 3)) - phi0.sum(axis=(1, 2, 3)))) < 1e-12
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_error_paths_and_recovery(hsf, orc, precision):
+    """The boundary's error returns on the GPU path, and that a context is usable after
+    each: an inversion stopped at max_iter returns HSF_ENOCONV and keeps its iterate, from
+    which a second inversion converges; a non-finite field makes the evaluation return
+    HSF_ENONFINITE, and after finite fields are set again the context evaluates bit for
+    bit as before; bad arguments return HSF_EINVAL and change nothing."""
+    wl = small_melt(L=(12, 10, 9), types=W.chain(3, 5), precision=precision)
+    tol = 1e-10 if precision == "fp64" else 1e-6
+    phi0 = W.initial_composition(wl)
+    ctx = hsf.Context(wl)
+    ctx.set_densities(phi0.ravel())
+    # HSF_ENOCONV, then convergence from the kept iterate
+    st, rc = ctx.invert(tol=tol, max_iter=2, warm=hsf.WARM_LOCAL, allow_noconv=True)
+    assert rc == hsf.HSF_ENOCONV and st[0]["iterations"] == 2 and not st[0]["converged"]
+    with pytest.raises(hsf.HsfError) as ei:
+        ctx.invert(tol=tol, max_iter=1, warm=hsf.WARM_CURRENT)
+    assert ei.value.code == hsf.HSF_ENOCONV
+    w_kept = ctx.get_fields()
+    assert np.all(np.isfinite(w_kept))
+    st, rc = ctx.invert(tol=tol, max_iter=2000, warm=hsf.WARM_CURRENT)
+    assert rc == hsf.HSF_OK and st[0]["converged"] and st[0]["residual"] <= tol
+    # HSF_ENONFINITE and recovery
+    w_good = ctx.get_fields()
+    ref, q_ref = ctx.evaluate()
+    w_bad = w_good.copy()
+    w_bad[wl.V // 2] = np.nan
+    ctx.set_fields(w_bad)
+    with pytest.raises(hsf.HsfError) as ei:
+        ctx.evaluate()
+    assert ei.value.code == hsf.HSF_ENONFINITE
+    ctx.set_fields(w_good)
+    got, q = ctx.evaluate()
+    assert np.array_equal(got, ref) and np.array_equal(q, q_ref)
+    # HSF_EINVAL leaves the state alone
+    for call in (lambda: ctx.invert(tol=-1.0), lambda: ctx.invert(tol=tol, max_iter=-1),
+                 lambda: ctx.invert(tol=tol, warm=99), lambda: ctx.set_tile((3, 3, 3, 0)),
+                 lambda: ctx.step(-1)):
+        with pytest.raises(hsf.HsfError) as ei:
+            call()
+        assert ei.value.code == hsf.HSF_EINVAL
+    assert np.array_equal(ctx.get_fields(), w_good)
+    got, q = ctx.evaluate()
+    assert np.array_equal(got, ref) and np.array_equal(q, q_ref)
+    ctx.close()
