@@ -517,14 +517,27 @@ __device__ __forceinline__ void column_stencil(const real *__restrict__ f, int x
                c3 * (a2[j] + a2[j + 2]);
 }
 
+// Scalars of one contour-step launch, first among the kernel arguments so that they
+// arrive with the first argument loads (read from the chain description they would take
+// loads at step-dependent offsets): the step s, the chain length N, the species of beads
+// s and 1, and the number of species.
+struct StepInfo {
+    int s, N, ts, t1, nsp;
+};
+
+inline StepInfo step_info(const Chain &ch, int s)
+{
+    return StepInfo{s, ch.N, ch.types[s - 1], ch.types[0], ch.nsp};
+}
+
 // With w set, step 1 also computes the field factors E = exp(-(w + alpha d)) of both
 // polymer species at its sites (the tiles cover every site once) and stores them for the
 // later steps, in place of a separate launch.
 template <typename real, int CX, int CY, int CZ, bool ARGS>
-__global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ blk_rep,
+__global__ __launch_bounds__(kBlock) void k_fwd_direct(StepInfo si, const int *__restrict__ blk_rep,
                                                        const int *__restrict__ blk_first,
                                                        const Rep *__restrict__ rep,
-                                                       const RepState *__restrict__ st, Chain ch, int s,
+                                                       const RepState *__restrict__ st,
                                                        PropBufs<real> b, double *__restrict__ partG, int nblocks,
                                                        int sums, const double *__restrict__ w,
                                                        const double *__restrict__ dvec, int use_alpha, ArgReps ar)
@@ -535,13 +548,14 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ b
     int act;
     direct_tile<CX, CY, CZ, ARGS>(blk_rep, blk_first, rep, st, ar, r, R, x0, y0, z0, act);
     if (!ARGS && !act) return;
+    const int s = si.s;
     const int V = (int)R.V;
     const int x = x0 + (int)threadIdx.x % CX, y = y0 + (int)threadIdx.x / CX;
     const int nz = min(CZ, R.Lz - z0);
     const bool in = x < R.Lx && y < R.Ly;
-    real *G = b.G + (long long)ch.N * R.site_off;
+    real *G = b.G + (long long)si.N * R.site_off;
     real *E = b.E + off_poly(R);
-    const real *Es = E + ch.types[s - 1] * V;
+    const real *Es = E + si.ts * V;
     const bool fuse_exp = s == 1 && w != nullptr;
     // all loads of the step before the active check and the stores
     real S[CZ], Ev[CZ];
@@ -563,8 +577,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ b
     const double alpha = (fuse_exp && use_alpha) ? st[r].alpha : 0.0;
     if (!act) return;   // uniform for the block
     if (fuse_exp && in) {
-        const long long fo = off_field(R, ch.nsp), po = off_poly(R);
-        const int t1 = ch.types[0];
+        const long long fo = off_field(R, si.nsp), po = off_poly(R);
+        const int t1 = si.t1;
 #pragma unroll
         for (int j = 0; j < CZ; ++j) {
             if (j >= nz) break;
@@ -594,15 +608,15 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ b
             }
         }
     }
-    if (sums || s == ch.N) {
+    if (sums || s == si.N) {
         const double t = block_sum(gsum);
         if (threadIdx.x == 0) partG[(long long)(s - 1) * nblocks + plan_block()] = t;
     }
     if (s == 1 && sums) {
         double t = block_sum(esum[0]);
-        if (threadIdx.x == 0) partG[(long long)ch.N * nblocks + plan_block()] = t;
+        if (threadIdx.x == 0) partG[(long long)si.N * nblocks + plan_block()] = t;
         t = block_sum(esum[1]);
-        if (threadIdx.x == 0) partG[(long long)(ch.N + 1) * nblocks + plan_block()] = t;
+        if (threadIdx.x == 0) partG[(long long)(si.N + 1) * nblocks + plan_block()] = t;
     }
 }
 
@@ -611,10 +625,10 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(const int *__restrict__ b
 // order) and stores Q, ln Q and the range flag, which step 1 uses for the normalisation,
 // in place of a separate control launch.
 template <typename real, int CX, int CY, int CZ, bool ARGS>
-__global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ blk_rep,
+__global__ __launch_bounds__(kBlock) void k_bwd_direct(StepInfo si, const int *__restrict__ blk_rep,
                                                        const int *__restrict__ blk_first,
                                                        const Rep *__restrict__ rep,
-                                                       RepState *__restrict__ st, Chain ch, int s,
+                                                       RepState *__restrict__ st, Chain ch,
                                                        PropBufs<real> b, const real *__restrict__ gin,
                                                        real *__restrict__ gout, double *__restrict__ acc,
                                                        int final_mode, const double *__restrict__ phit,
@@ -628,9 +642,10 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ b
     int act;
     direct_tile<CX, CY, CZ, ARGS>(blk_rep, blk_first, rep, st, ar, r, R, x0, y0, z0, act);
     if (!ARGS && !act) return;
+    const int s = si.s;
     const int V = (int)R.V;
-    const int N = ch.N;
-    const int ts = ch.types[s - 1];
+    const int N = si.N;
+    const int ts = si.ts;
     const int x = x0 + (int)threadIdx.x % CX, y = y0 + (int)threadIdx.x / CX;
     const int nz = min(CZ, R.Lz - z0);
     const bool in = x < R.Lx && y < R.Ly;
@@ -682,7 +697,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(const int *__restrict__ b
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
     if (in) {
         const double coef = st[r].phibar_p / ((double)N * st[r].q);
-        const long long fo = off_field(R, ch.nsp);
+        const long long fo = off_field(R, si.nsp);
 #pragma unroll
         for (int j = 0; j < CZ; ++j) {
             if (j >= nz) break;
@@ -751,11 +766,12 @@ struct BlockKernels {
         if constexpr (K == 0) {
             auto kern = p.args.n ? k_fwd_direct<real, CX, CY, CZ, true> : k_fwd_direct<real, CX, CY, CZ, false>;
             if (e0)
-                hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first,
-                                      rep, st, ch, s0 + 1, b, partG, p.nblocks, sums, w, d, use_alpha, p.args);
+                hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, step_info(ch, s0 + 1),
+                                      p.blk_rep, p.blk_first, rep, st, b, partG, p.nblocks, sums, w, d, use_alpha,
+                                      p.args);
             else
-                hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st, ch,
-                                   s0 + 1, b, partG, p.nblocks, sums, w, d, use_alpha, p.args);
+                hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, step_info(ch, s0 + 1), p.blk_rep,
+                                   p.blk_first, rep, st, b, partG, p.nblocks, sums, w, d, use_alpha, p.args);
         } else {
             if (e0)
                 hipExtLaunchKernelGGL((k_fwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, e0,
@@ -773,13 +789,13 @@ struct BlockKernels {
         if constexpr (K == 0) {
             auto kern = p.args.n ? k_bwd_direct<real, CX, CY, CZ, true> : k_bwd_direct<real, CX, CY, CZ, false>;
             if (e0)
-                hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first,
-                                      rep, st, ch, s_hi, b, gin, gout, acc, final_mode, phit, d, out, part, partG,
-                                      p.nblocks, fold_q, p.args);
+                hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, step_info(ch, s_hi),
+                                      p.blk_rep, p.blk_first, rep, st, ch, b, gin, gout, acc, final_mode, phit, d,
+                                      out, part, partG, p.nblocks, fold_q, p.args);
             else
-                hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, st, ch,
-                                   s_hi, b, gin, gout, acc, final_mode, phit, d, out, part, partG, p.nblocks, fold_q,
-                                   p.args);
+                hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, step_info(ch, s_hi), p.blk_rep,
+                                   p.blk_first, rep, st, ch, b, gin, gout, acc, final_mode, phit, d, out, part, partG,
+                                   p.nblocks, fold_q, p.args);
         } else {
             if (e0)
                 hipExtLaunchKernelGGL((k_bwd_block<real, CX, CY, CZ, K>), dim3(p.nblocks), dim3(kBlock), 0, s, e0,
