@@ -631,3 +631,35 @@ def test_error_paths_and_recovery(hsf, orc, precision):
     got, q = ctx.evaluate()
     assert np.array_equal(got, ref) and np.array_equal(q, q_ref)
     ctx.close()
+
+
+def test_user_stream_and_device_buffers(hsf):
+    """A context on a caller's stream (a torch stream other than the default), fed with
+    device tensors written on that stream and evaluating into a device tensor, gives bit
+    for bit the densities, Q and 3-step trajectory of a context on the default stream fed
+    from host arrays."""
+    import torch
+    wl = small_melt(L=(12, 10, 9), types=W.chain(3, 5), precision="fp32")
+    phi0 = W.initial_composition(wl)
+    w = fields_for(wl, seed=3, amp=1.0)
+    ref = hsf.Context(wl)
+    ref.set_densities(phi0.ravel())
+    ref.set_fields(w.ravel())
+    r_phi, r_q = ref.evaluate()
+    ref.step(3, tol=1e-6, max_iter=500)
+    r_after, r_w = ref.get_densities(), ref.get_fields()
+    ref.close()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        phi_d = torch.from_numpy(phi0.ravel().copy()).to("cuda")
+        w_d = torch.from_numpy(w.ravel().copy()).to("cuda")
+        out = torch.full_like(phi_d, float("nan"))
+    ctx = hsf.Context(wl, stream=s)
+    ctx.set_densities(phi_d)
+    ctx.set_fields(w_d)
+    _, q = ctx.evaluate(out=out)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), r_phi) and np.array_equal(q, r_q)
+    ctx.step(3, tol=1e-6, max_iter=500)
+    assert np.array_equal(ctx.get_densities(), r_after) and np.array_equal(ctx.get_fields(), r_w)
+    ctx.close()
