@@ -842,19 +842,32 @@ static void conv_fwd_launch(hipStream_t s, ConvIn in, int B, int ci, int cip, co
                            bias, out, L, tx, ty, tps);
 }
 
-// Tile per layer: the largest of 16x8x4, 8x8x4, 8x4x4 that the box fills and whose LDS
-// (halo tile plus one weight slab) fits.  Larger tiles re-read fewer halo sites and
-// stage the weights for more sites.
+// Tile per layer: the largest of 16x8x4, 8x8x4, 8x4x4 that the box fills, whose LDS
+// (halo tile plus one weight slab) fits, and that still gives the launch at least
+// kMinConvBlocks blocks; else 8x4x2.  Larger tiles re-read fewer halo sites and stage
+// the weights for more sites; on the coarse levels of a U-Net (8^3, 16^3 boxes) they
+// would leave a launch with a handful of blocks, each working through all of its sites
+// in turn.  The tile does not change any result: every output sums its K chunks in the
+// same order.
+constexpr long long kMinConvBlocks = 256;
+
+static long long conv_blocks(int B, int L, int bx, int by, int bz)
+{
+    return (long long)B * ((L + bx - 1) / bx) * ((L + by - 1) / by) * ((L + bz - 1) / bz);
+}
+
 void net_conv_fwd(hipStream_t s, ConvIn in, int B, int ci, int cip, const __bf16 *Wm, int kp, int co, int cop,
                   const float *bias, ConvOut out, int L)
 {
     const size_t lim = lds_limit();
-    if (L >= 16 && conv_fwd_lds_t<16, 8, 4>(cip, cop) <= lim)
+    if (L >= 16 && conv_fwd_lds_t<16, 8, 4>(cip, cop) <= lim && conv_blocks(B, L, 16, 8, 4) >= kMinConvBlocks)
         conv_fwd_launch<16, 8, 4>(s, in, B, ci, cip, Wm, kp, co, cop, bias, out, L);
-    else if (L >= 8 && conv_fwd_lds_t<8, 8, 4>(cip, cop) <= lim)
+    else if (L >= 8 && conv_fwd_lds_t<8, 8, 4>(cip, cop) <= lim && conv_blocks(B, L, 8, 8, 4) >= kMinConvBlocks)
         conv_fwd_launch<8, 8, 4>(s, in, B, ci, cip, Wm, kp, co, cop, bias, out, L);
-    else
+    else if (conv_fwd_lds_t<8, 4, 4>(cip, cop) <= lim && conv_blocks(B, L, 8, 4, 4) >= kMinConvBlocks)
         conv_fwd_launch<8, 4, 4>(s, in, B, ci, cip, Wm, kp, co, cop, bias, out, L);
+    else
+        conv_fwd_launch<8, 4, 2>(s, in, B, ci, cip, Wm, kp, co, cop, bias, out, L);
 }
 
 // Site slices of the weight gradient: enough blocks (groups x slices, about 1024) to
