@@ -361,11 +361,13 @@ def main():
                 kernels[k] = {"launches": cnt, "avg_us": 1e3 * ms / cnt, "total_ms": ms}
         if "lb" in kernels:
             lb_mlups = V_total / (kernels["lb"]["avg_us"] * 1e-6) / 1e6
-        prop = {k: v for k, v in kernels.items() if k in ("fwd", "bwd")}
+        prop = {k: v for k, v in kernels.items() if k in ("fwd", "bwd", "pair")}
         if prop:
             dom = max(prop, key=lambda k: prop[k]["total_ms"])
             avg_s = prop[dom]["avg_us"] * 1e-6
-            steps_per_launch = max(1, tile[3])
+            # a paired launch takes forward step j and (for j < N) a backward step: 2N - 1
+            # steps in N launches per evaluation
+            steps_per_launch = (2 * N - 1) / N if dom == "pair" else max(1, tile[3])
             units = V_total * steps_per_launch
             achieved = b_unit * units / avg_s / 1e9
             traffic = MEASURED_TRAFFIC.get((args.workload, wl.precision, tuple(tile), dom))
@@ -443,7 +445,7 @@ def main():
         "evals_per_step": evals / args.steps,
         "iterations_last_step": [s["iterations"] for s in stats][:8],
         "lb_mlups": lb_mlups,
-        "tile": {"core": list(tile[:3]), "steps_per_launch": tile[3], "autotune_ms_per_eval": tune_ms},
+        "tile": {"core": list(tile[:3]), "steps_per_launch": max(1, tile[3]), "paired": tile[3] == -1, "autotune_ms_per_eval": tune_ms},
         "kernels": kernels,
         "kernel_timing_region": {"steps": t_steps,
                                  "ms_per_step": (1e3 * t_elapsed / t_steps) if t_elapsed else None,

@@ -332,7 +332,10 @@ int hsf_set_solver(hsf_ctx *ctx, int flags);
 int hsf_get_work(hsf_ctx *ctx, long long *evals, double *site_evals, int reset);
 
 /* Propagator tiling (the temporally blocked sweeps): cfg = {cx, cy, cz, k}, a
- * core tile of cx*cy*cz sites per workgroup advanced k contour steps per launch.
+ * core tile of cx*cy*cz sites per workgroup advanced k contour steps per launch;
+ * k = 0: one step per launch, read through the caches; k = -1: as k = 0, but each
+ * launch takes a forward and a backward step together (N + 1 launches per
+ * evaluation instead of 2 N, densities bit for bit those of k = 0).
  * hsf_set_tile accepts only the configurations compiled into the library
  * (HSF_EINVAL otherwise); results do not depend on the choice beyond rounding.
  * hsf_autotune times one density-functional evaluation `reps` times with every
@@ -405,7 +408,8 @@ enum {
     HSF_K_BWD = 2,    /* backward propagator step + density accumulation */
     HSF_K_LB = 3,     /* fused LB collide-and-stream                     */
     HSF_K_CD = 4,     /* convection-diffusion update                     */
-    HSF_K_COUNT = 5
+    HSF_K_PAIR = 5,   /* paired launch: one forward and one backward step */
+    HSF_K_COUNT = 6
 };
 
 /* Measurement aid: when on, every launch of the kernel families above is

@@ -61,7 +61,7 @@ struct hsf_ctx {
     int part_cap = 0;                  // doubles in `part`
     double *obs = nullptr;             // observables scratch; results in its last 3 n_rep doubles
     // propagators in the chosen precision
-    void *E = nullptr, *G = nullptr, *Gp0 = nullptr, *Gp1 = nullptr;
+    void *E = nullptr, *G = nullptr, *Gp0 = nullptr, *Gp1 = nullptr, *Gf0 = nullptr, *Gf1 = nullptr;
     std::vector<void *> allocs;
 
     // hipGraphs of the fixed launch sequences (captured at first use, replayed after)
@@ -324,12 +324,48 @@ int set_tile(hsf_ctx *c, const TileCfg &t)
 // the field factors, and N backward launches, the first also computing Q and the last
 // normalising.  With blocked kernels: exp of the fields, ceil(N/K) forward launches, the
 // Q reduction, ceil(N/K) backward launches.
+// Paired kernels (K = -1, N >= 2): N launches, launch j taking forward step j and backward
+// step N + 1 + (N mod 2) - j (when in 2..N), then backward step 1 alone, which finishes Q
+// and normalises; N + 1 launches instead of 2 N.  A bead's two steps never share a launch
+// (the backward lag N mod 2 sees to that), the forward step of bead s runs first exactly
+// when s <= se = (N + N mod 2) / 2, and the backward step N of launch 1 (even N) forms its
+// field factor itself since step 1 is storing them in the same launch.
+template <typename real>
+void run_eval_paired(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d, int sums)
+{
+    PropBufs<real> b = bufs<real>(c);
+    const int N = c->ch.N, lag = N & 1, se = (N + lag) / 2;
+    real *Gf[2] = {(real *)c->Gf0, (real *)c->Gf1};
+    int parity = 0;
+    for (int j = 1; j <= N; ++j) {
+        PairSteps ps{};
+        ps.sf = j;
+        const int sb = N + 1 + lag - j;
+        ps.sb = (sb >= 2 && sb <= N) ? sb : 0;
+        ps.f_late = j > se;
+        ps.f_from_pp = j >= 2 && j - 1 >= se;
+        ps.f_to_pp = j >= se && j < N;
+        ps.g_late = ps.sb && ps.sb <= se;
+        ps.g_exp = ps.sb == N && j == 1;
+        const real *gin = b.Gp[parity ^ 1];
+        real *gout = b.Gp[parity];
+        if (ps.sb) parity ^= 1;
+        Timed t(c, HSF_K_PAIR);
+        launch_pair_block<real>(c->tile, c->stream, c->tplan, c->rep_d, c->st_d, c->ch, ps, b, Gf[(j - 1) & 1],
+                                Gf[j & 1], gin, gout, c->partG, sums, c->w, c->d, use_alpha, t.a, t.b);
+    }
+    Timed t(c, HSF_K_BWD);
+    launch_bwd_block<real>(c->tile, c->stream, c->tplan, c->rep_d, c->st_d, c->ch, 1, 1, b, b.Gp[parity ^ 1],
+                           b.Gp[parity], c->acc, final_mode, c->phi, d, out, c->part, c->partG, 2, t.a, t.b);
+}
+
 template <typename real>
 void run_eval(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d, int sums)
 {
+    if (c->tile.k < 0 && c->ch.N >= 2) return run_eval_paired<real>(c, use_alpha, final_mode, out, d, sums);
     PropBufs<real> b = bufs<real>(c);
     const int N = c->ch.N, K = std::max(1, c->tile.k);
-    const bool direct = c->tile.k == 0;
+    const bool direct = c->tile.k <= 0;
     const bool fold_q = direct && N > 1;   // with N = 1 step 1 is step N: Q first, in its own launch
     if (!direct) {
         Timed t(c, HSF_K_PREP);
@@ -882,6 +918,8 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     ALLOC(c->G, rs * N * T);
     ALLOC(c->Gp0, rs * T);
     ALLOC(c->Gp1, rs * T);
+    ALLOC(c->Gf0, rs * T);
+    ALLOC(c->Gf1, rs * T);
     for (int h = 0; h < 2; ++h) {
         ALLOC(c->w_hist[h], sizeof(double) * nsp * T);
         ALLOC(c->phi_hist[h], sizeof(double) * nsp * T);

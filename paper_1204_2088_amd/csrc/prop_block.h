@@ -7,7 +7,8 @@ namespace hsf {
 
 // Core tile (cx, cy, cz) and contour steps per launch (k).  k = 0 selects the direct
 // kernels: one contour step per launch, neighbours read through the caches, a block
-// covers cx x cy columns (cx * cy = 256) of cz planes.
+// covers cx x cy columns (cx * cy = 256) of cz planes.  k = -1 selects the paired
+// direct kernels: a launch takes one forward and one backward step (same tiles).
 struct TileCfg {
     int cx, cy, cz, k;
 };
@@ -25,6 +26,12 @@ struct TileCfg {
     X(16, 16, 4, 0)         \
     X(64, 4, 8, 0)          \
     X(16, 16, 8, 0)         \
+    X(64, 4, 2, -1)         \
+    X(32, 8, 2, -1)         \
+    X(16, 16, 2, -1)        \
+    X(32, 8, 4, -1)         \
+    X(16, 16, 4, -1)        \
+    X(16, 16, 8, -1)        \
     X(8, 8, 8, 1)           \
     X(8, 8, 8, 2)           \
     X(8, 8, 8, 3)           \
@@ -37,7 +44,7 @@ struct TileCfg {
 // Bytes of LDS a configuration needs (two staged regions + FP64 core accumulators).
 inline size_t tile_lds_bytes(const TileCfg &t, size_t real_bytes)
 {
-    if (t.k == 0) return 0;
+    if (t.k <= 0) return 0;
     const size_t nr = (size_t)(t.cx + 2 * t.k) * (t.cy + 2 * t.k) * (t.cz + 2 * t.k);
     return 2 * nr * real_bytes + 2 * (size_t)t.cx * t.cy * t.cz * sizeof(double);
 }
@@ -51,12 +58,25 @@ template <typename real>
 void launch_fwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
                       int s0, int n, PropBufs<real> b, double *partG, int sums, const double *w, const double *d,
                       int use_alpha, hipEvent_t e0, hipEvent_t e1);
-// fold_q: with one-step kernels the first backward launch also computes Q from the forward
-// sweep's partials, in place of the control launch of that phase.
+// fold_q: with one-step kernels the first backward launch (1), or with paired kernels the
+// last one (2), also computes Q from the forward sweep's partials, in place of the control
+// launch of that phase.
 template <typename real>
 void launch_bwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
                       int s_hi, int n, PropBufs<real> b, const real *gin, real *gout, double *acc, int final_mode,
                       const double *phit, const double *d, double *out, double *part, const double *partG,
                       int fold_q, hipEvent_t e0, hipEvent_t e1);
+
+// One launch of the paired sweeps: forward step sf and backward step sb (0: none) and
+// where each reads and writes its propagators (the schedule is built by the evaluation).
+struct PairSteps {
+    int sf, sb;
+    int f_late, f_from_pp, f_to_pp, g_late, g_exp;
+};
+template <typename real>
+void launch_pair_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
+                       const PairSteps &ps, PropBufs<real> b, const real *fin, real *fout, const real *gin,
+                       real *gout, double *partG, int sums, const double *w, const double *d, int use_alpha,
+                       hipEvent_t e0, hipEvent_t e1);
 
 }  // namespace hsf

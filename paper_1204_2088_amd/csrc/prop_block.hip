@@ -440,18 +440,18 @@ __global__ __launch_bounds__(kBlock) void k_field_exp(const int *__restrict__ bl
 // every plane it touches, the in-plane class sums (centre, 4 edge-sharing, 4 corner
 // neighbours: 9 loads) once and combines three consecutive planes per site, so a site
 // costs 9 (CZ + 2) / CZ loads instead of 27.
-// Tile of this block for the direct kernels and whether its replica is active.  ARGS:
+// Tile of work item pb (a block's plan_block()) for the direct kernels and whether its
+// replica is active.  ARGS:
 // the batch is in the kernel arguments, so the stencil's loads need no dependent load
 // before them; a one-replica context is active whenever a kernel is launched, the flag
 // of a larger batch is loaded alongside the data and checked before the first store
 // (the caller returns then, uniformly for the block).  Otherwise the tile plan and the
 // descriptors come from device memory and an inactive replica returns at once.
 template <int CX, int CY, int CZ, bool ARGS>
-__device__ __forceinline__ void direct_tile(const int *blk_rep, const int *blk_first, const Rep *rep,
+__device__ __forceinline__ void direct_tile(int pb, const int *blk_rep, const int *blk_first, const Rep *rep,
                                             const RepState *st, const ArgReps &ar, int &r, Rep &R, int &x0,
                                             int &y0, int &z0, int &act)
 {
-    const int pb = plan_block();
     int lb;
     if (ARGS) {
         r = arg_replica(ar, pb);
@@ -546,7 +546,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(StepInfo si, const int *_
     int r, x0, y0, z0;
     Rep R;
     int act;
-    direct_tile<CX, CY, CZ, ARGS>(blk_rep, blk_first, rep, st, ar, r, R, x0, y0, z0, act);
+    direct_tile<CX, CY, CZ, ARGS>(plan_block(), blk_rep, blk_first, rep, st, ar, r, R, x0, y0, z0, act);
     if (!ARGS && !act) return;
     const int s = si.s;
     const int V = (int)R.V;
@@ -620,10 +620,13 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(StepInfo si, const int *_
     }
 }
 
-// With fold_q set, step N's launch also finishes the forward sweep's reduction: the
+// With fold_q = 1, step N's launch also finishes the forward sweep's reduction: the
 // first block of each replica sums the replica's G_N partials (partG row N - 1, fixed
 // order) and stores Q, ln Q and the range flag, which step 1 uses for the normalisation,
-// in place of a separate control launch.
+// in place of a separate control launch.  With fold_q = 2 (the paired sweeps, whose
+// forward step N runs just before step 1), step 1's launch does it: every block sums the
+// partials itself in that same order, so all hold the same Q, and the replica's first
+// block stores it.
 template <typename real, int CX, int CY, int CZ, bool ARGS>
 __global__ __launch_bounds__(kBlock) void k_bwd_direct(StepInfo si, const int *__restrict__ blk_rep,
                                                        const int *__restrict__ blk_first,
@@ -640,7 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(StepInfo si, const int *_
     int r, x0, y0, z0;
     Rep R;
     int act;
-    direct_tile<CX, CY, CZ, ARGS>(blk_rep, blk_first, rep, st, ar, r, R, x0, y0, z0, act);
+    direct_tile<CX, CY, CZ, ARGS>(plan_block(), blk_rep, blk_first, rep, st, ar, r, R, x0, y0, z0, act);
     if (!ARGS && !act) return;
     const int s = si.s;
     const int V = (int)R.V;
@@ -674,7 +677,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(StepInfo si, const int *_
     }
     const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
     if (!act) return;   // uniform for the block
-    if (fold_q && s == N && threadIdx.x < 64) {
+    if (fold_q == 1 && s == N && threadIdx.x < 64) {
         const int pb = plan_block();
         const int b0 = ARGS ? ar.blk_first[r] : blk_first[r], b1 = ARGS ? ar.blk_first[r + 1] : blk_first[r + 1];
         if (pb == b0) {
@@ -694,9 +697,36 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(StepInfo si, const int *_
             }
         }
     }
+    double q_own = 0.0;
+    if (fold_q == 2 && s == 1) {
+        __shared__ double q_sh;
+        if (threadIdx.x < 64) {
+            const int pb = plan_block();
+            const int b0 = ARGS ? ar.blk_first[r] : blk_first[r], b1 = ARGS ? ar.blk_first[r + 1] : blk_first[r + 1];
+            double v = 0.0;
+            const double *row = partG + (long long)(N - 1) * nblocks;
+#pragma unroll 8
+            for (int q = b0 + (int)threadIdx.x; q < b1; q += 64) v += row[q];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+            if (threadIdx.x == 0) {
+                double q, lq;
+                bool bad;
+                q_from_sum(v, (double)R.V, st[r].scale_e, N, q, lq, bad);
+                q_sh = q;
+                if (pb == b0) {
+                    st[r].q = q;
+                    st[r].ln_q = lq;
+                    if (bad) st[r].nonfinite = 1;
+                }
+            }
+        }
+        __syncthreads();
+        q_own = q_sh;
+    }
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
     if (in) {
-        const double coef = st[r].phibar_p / ((double)N * st[r].q);
+        const double coef = st[r].phibar_p / ((double)N * (fold_q == 2 ? q_own : st[r].q));
         const long long fo = off_field(R, si.nsp);
 #pragma unroll
         for (int j = 0; j < CZ; ++j) {
@@ -755,6 +785,220 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(StepInfo si, const int *_
     }
 }
 
+// ---- paired sweeps ------------------------------------------------------------------
+//
+// The backward propagators G+_s do not depend on the forward ones (both start from the
+// field factors), so one launch can advance the forward sweep by a step and the backward
+// sweep by a step: its first pi.nf blocks take forward step pi.f.s, the rest backward step
+// pi.g.s, with the same tiling.  A bead's density term G_s sigma[G+_{s+1}] is formed by
+// whichever of its two steps runs second.  Early forward steps (s <= the crossing) store
+// G_s in slot s - 1 as the one-step kernels do, and the backward step of that bead later
+// replaces it by the term.  Early backward steps (s above the crossing) store
+// sigma_s = sigma[G+_{s+1}] in slot s - 1, and the forward step of that bead later reads
+// it and replaces it by the term; from the crossing on the forward propagator moves
+// through its own ping-pong pair (fin -> fout), since its slots are taken.  Every stored
+// value is the same expression of the same operands as in the one-step sequence, so the
+// densities are bit for bit those of that sequence.  Step 1 of the backward sweep, which
+// sums the terms, runs in a launch of its own after the last paired one.
+struct PairInfo {
+    StepInfo f, g;   // forward and backward step (s = 0: none)
+    int f_late;      // forward: sigma_s is in slot s - 1 and the term replaces it
+    int f_from_pp;   // forward: G_{s-1} is read from fin (else from slot s - 2)
+    int f_to_pp;     // forward: G_s is also written to fout
+    int g_late;      // backward: G_s is in slot s - 1 and the term replaces it (else sigma_s is stored)
+    int g_exp;       // backward: the field factor is computed from w here (step 1's launch, same values)
+    int nf;          // blocks of the forward half (0 or the tile plan's count)
+};
+
+template <typename real, int CX, int CY, int CZ, bool ARGS>
+__device__ __forceinline__ void pair_fwd(const PairInfo &pi, int pb, const int *__restrict__ blk_rep,
+                                         const int *__restrict__ blk_first, const Rep *__restrict__ rep,
+                                         const RepState *__restrict__ st, PropBufs<real> b,
+                                         const real *__restrict__ fin, real *__restrict__ fout,
+                                         double *__restrict__ partG, int nblocks, int sums,
+                                         const double *__restrict__ w, const double *__restrict__ dvec,
+                                         int use_alpha, const ArgReps &ar)
+{
+    int r, x0, y0, z0;
+    Rep R;
+    int act;
+    direct_tile<CX, CY, CZ, ARGS>(pb, blk_rep, blk_first, rep, st, ar, r, R, x0, y0, z0, act);
+    if (!ARGS && !act) return;
+    const StepInfo si = pi.f;
+    const int s = si.s, N = si.N;
+    const int V = (int)R.V;
+    const int x = x0 + (int)threadIdx.x % CX, y = y0 + (int)threadIdx.x / CX;
+    const int nz = min(CZ, R.Lz - z0);
+    const bool in = x < R.Lx && y < R.Ly;
+    real *G = b.G + (long long)N * R.site_off;
+    real *E = b.E + off_poly(R);
+    const real *Es = E + si.ts * V;
+    const bool fuse_exp = s == 1 && w != nullptr;
+    const bool late = pi.f_late != 0, sig_in = late && s < N;
+    real S[CZ], Ev[CZ], Sg[CZ];
+#pragma unroll
+    for (int j = 0; j < CZ; ++j) S[j] = Ev[j] = Sg[j] = (real)0;
+    if (in) {
+        if (s == 1) {
+#pragma unroll
+            for (int j = 0; j < CZ; ++j) S[j] = (real)R.csum;
+        } else {
+            column_stencil<real, CZ>(pi.f_from_pp ? fin + R.site_off : G + (long long)(s - 2) * V, x, y, z0, nz, R, S);
+        }
+        if (CZ <= 2) {
+#pragma unroll
+            for (int j = 0; j < CZ; ++j) {
+                const int site = x + R.Lx * (y + R.Ly * min(z0 + j, z0 + nz - 1));
+                if (!fuse_exp) Ev[j] = Es[site];
+                if (sig_in) Sg[j] = G[(long long)(s - 1) * V + site];
+            }
+        }
+    }
+    const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
+    const double alpha = (fuse_exp && use_alpha) ? st[r].alpha : 0.0;
+    if (!act) return;   // uniform for the block
+    if (fuse_exp && in) {
+        const long long fo = off_field(R, si.nsp), po = off_poly(R);
+        const int t1 = si.t1;
+#pragma unroll
+        for (int j = 0; j < CZ; ++j) {
+            if (j >= nz) break;
+            const int site = x + R.Lx * (y + R.Ly * (z0 + j));
+#pragma unroll
+            for (int I = 0; I < 2; ++I) {
+                double xv = w[fo + (long long)I * V + site];
+                if (use_alpha) xv = fma(alpha, dvec[po + (long long)I * V + site], xv);
+                const real e = (real)exp(-xv);
+                E[(long long)I * V + site] = e;
+                if (I == t1) Ev[j] = e;
+            }
+        }
+    }
+    double gsum = 0.0, esum[2] = {0.0, 0.0};
+    if (in) {
+#pragma unroll
+        for (int j = 0; j < CZ; ++j) {
+            if (j >= nz) break;
+            const int site = x + R.Lx * (y + R.Ly * (z0 + j));
+            const real g = ((CZ <= 2 || fuse_exp) ? Ev[j] : Es[site]) * S[j] * sc;
+            real *slot = G + (long long)(s - 1) * V + site;
+            if (late) {
+                const real sg = s == N ? (real)R.csum : (CZ <= 2 ? Sg[j] : *slot);
+                *slot = g * sg;
+            } else {
+                *slot = g;
+            }
+            if (pi.f_to_pp) fout[R.site_off + site] = g;
+            gsum += (double)g;
+            if (s == 1 && sums) {
+                esum[0] += (double)E[site];
+                esum[1] += (double)E[V + site];
+            }
+        }
+    }
+    if (sums || s == N) {
+        const double t = block_sum(gsum);
+        if (threadIdx.x == 0) partG[(long long)(s - 1) * nblocks + pb] = t;
+    }
+    if (s == 1 && sums) {
+        double t = block_sum(esum[0]);
+        if (threadIdx.x == 0) partG[(long long)N * nblocks + pb] = t;
+        t = block_sum(esum[1]);
+        if (threadIdx.x == 0) partG[(long long)(N + 1) * nblocks + pb] = t;
+    }
+}
+
+template <typename real, int CX, int CY, int CZ, bool ARGS>
+__device__ __forceinline__ void pair_bwd(const PairInfo &pi, int pb, const int *__restrict__ blk_rep,
+                                         const int *__restrict__ blk_first, const Rep *__restrict__ rep,
+                                         const RepState *__restrict__ st, PropBufs<real> b,
+                                         const real *__restrict__ gin, real *__restrict__ gout,
+                                         const double *__restrict__ w, const double *__restrict__ dvec,
+                                         int use_alpha, const ArgReps &ar)
+{
+    int r, x0, y0, z0;
+    Rep R;
+    int act;
+    direct_tile<CX, CY, CZ, ARGS>(pb, blk_rep, blk_first, rep, st, ar, r, R, x0, y0, z0, act);
+    if (!ARGS && !act) return;
+    const StepInfo si = pi.g;
+    const int s = si.s, N = si.N, ts = si.ts;
+    const int V = (int)R.V;
+    const int x = x0 + (int)threadIdx.x % CX, y = y0 + (int)threadIdx.x / CX;
+    const int nz = min(CZ, R.Lz - z0);
+    const bool in = x < R.Lx && y < R.Ly;
+    const long long po = off_poly(R);
+    real *G = b.G + (long long)N * R.site_off;
+    const bool late = pi.g_late != 0, fexp = pi.g_exp != 0;
+    real S[CZ], Ev[CZ], Gv[CZ];
+#pragma unroll
+    for (int j = 0; j < CZ; ++j) S[j] = Ev[j] = Gv[j] = (real)0;
+    if (in) {
+        if (s == N) {
+#pragma unroll
+            for (int j = 0; j < CZ; ++j) S[j] = (real)R.csum;
+        } else {
+            column_stencil<real, CZ>(gin + R.site_off, x, y, z0, nz, R, S);
+        }
+        if (CZ <= 2) {
+#pragma unroll
+            for (int j = 0; j < CZ; ++j) {
+                const int site = x + R.Lx * (y + R.Ly * min(z0 + j, z0 + nz - 1));
+                if (!fexp) Ev[j] = b.E[po + ts * V + site];
+                if (late) Gv[j] = G[(long long)(s - 1) * V + site];
+            }
+        }
+    }
+    const real sc = pow2_neg_b<real>(st[r].scale_e[s - 1]);
+    const double alpha = (fexp && use_alpha) ? st[r].alpha : 0.0;
+    if (!act) return;   // uniform for the block
+    if (in) {
+        const long long fo = off_field(R, si.nsp);
+#pragma unroll
+        for (int j = 0; j < CZ; ++j) {
+            if (j >= nz) break;
+            const int site = x + R.Lx * (y + R.Ly * (z0 + j));
+            real e;
+            if (fexp) {
+                double xv = w[fo + (long long)ts * V + site];
+                if (use_alpha) xv = fma(alpha, dvec[po + (long long)ts * V + site], xv);
+                e = (real)exp(-xv);
+            } else {
+                e = CZ <= 2 ? Ev[j] : b.E[po + ts * V + site];
+            }
+            gout[R.site_off + site] = e * S[j] * sc;
+            real *slot = G + (long long)(s - 1) * V + site;
+            if (late) {
+                const real gs = CZ <= 2 ? Gv[j] : *slot;
+                *slot = gs * S[j];
+            } else if (s < N) {
+                *slot = S[j];
+            }
+        }
+    }
+}
+
+template <typename real, int CX, int CY, int CZ, bool ARGS>
+__global__ __launch_bounds__(kBlock) void k_pair_direct(PairInfo pi, const int *__restrict__ blk_rep,
+                                                        const int *__restrict__ blk_first,
+                                                        const Rep *__restrict__ rep,
+                                                        const RepState *__restrict__ st, PropBufs<real> b,
+                                                        const real *__restrict__ fin, real *__restrict__ fout,
+                                                        const real *__restrict__ gin, real *__restrict__ gout,
+                                                        double *__restrict__ partG, int nblocks, int sums,
+                                                        const double *__restrict__ w,
+                                                        const double *__restrict__ dvec, int use_alpha, ArgReps ar)
+{
+    static_assert(CX * CY == kBlock, "one column per thread");
+    const int pb = plan_block();
+    if (pb < pi.nf)
+        pair_fwd<real, CX, CY, CZ, ARGS>(pi, pb, blk_rep, blk_first, rep, st, b, fin, fout, partG, nblocks, sums, w,
+                                         dvec, use_alpha, ar);
+    else
+        pair_bwd<real, CX, CY, CZ, ARGS>(pi, pb - pi.nf, blk_rep, blk_first, rep, st, b, gin, gout, w, dvec,
+                                         use_alpha, ar);
+}
+
 // ---- launchers ---------------------------------------------------------------------
 
 template <typename real, int CX, int CY, int CZ, int K>
@@ -763,7 +1007,7 @@ struct BlockKernels {
                     PropBufs<real> b, double *partG, int sums, const double *w, const double *d, int use_alpha,
                     hipEvent_t e0, hipEvent_t e1)
     {
-        if constexpr (K == 0) {
+        if constexpr (K <= 0) {   // direct kernels (K = -1: their single steps)
             auto kern = p.args.n ? k_fwd_direct<real, CX, CY, CZ, true> : k_fwd_direct<real, CX, CY, CZ, false>;
             if (e0)
                 hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, step_info(ch, s0 + 1),
@@ -786,7 +1030,7 @@ struct BlockKernels {
                     const double *d, double *out, double *part, const double *partG, int fold_q, hipEvent_t e0,
                     hipEvent_t e1)
     {
-        if constexpr (K == 0) {
+        if constexpr (K <= 0) {   // direct kernels (K = -1: their single steps)
             auto kern = p.args.n ? k_bwd_direct<real, CX, CY, CZ, true> : k_bwd_direct<real, CX, CY, CZ, false>;
             if (e0)
                 hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, step_info(ch, s_hi),
@@ -808,6 +1052,47 @@ struct BlockKernels {
         }
     }
 };
+
+// One paired launch (tiles of the K = -1 configurations): forward step sf and backward
+// step sb (0: none).
+template <typename real, int CX, int CY, int CZ>
+void pair_launch(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, const PairSteps &ps,
+                 PropBufs<real> b, const real *fin, real *fout, const real *gin, real *gout, double *partG,
+                 int sums, const double *w, const double *d, int use_alpha, hipEvent_t e0, hipEvent_t e1)
+{
+    PairInfo pi{};
+    if (ps.sf) pi.f = step_info(ch, ps.sf);
+    if (ps.sb) pi.g = step_info(ch, ps.sb);
+    pi.f_late = ps.f_late;
+    pi.f_from_pp = ps.f_from_pp;
+    pi.f_to_pp = ps.f_to_pp;
+    pi.g_late = ps.g_late;
+    pi.g_exp = ps.g_exp;
+    pi.nf = ps.sf ? p.nblocks : 0;
+    const int grid = pi.nf + (ps.sb ? p.nblocks : 0);
+    auto kern = p.args.n ? k_pair_direct<real, CX, CY, CZ, true> : k_pair_direct<real, CX, CY, CZ, false>;
+    if (e0)
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, e0, e1, 0, pi, p.blk_rep, p.blk_first, rep, st, b,
+                              fin, fout, gin, gout, partG, p.nblocks, sums, w, d, use_alpha, p.args);
+    else
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, pi, p.blk_rep, p.blk_first, rep, st, b, fin, fout,
+                           gin, gout, partG, p.nblocks, sums, w, d, use_alpha, p.args);
+}
+
+template <typename real>
+void launch_pair_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,
+                       const PairSteps &ps, PropBufs<real> b, const real *fin, real *fout, const real *gin,
+                       real *gout, double *partG, int sums, const double *w, const double *d, int use_alpha,
+                       hipEvent_t e0, hipEvent_t e1)
+{
+#define HSF_CASE(CX, CY, CZ, K)                                                                             \
+    if constexpr (K == -1)                                                                                  \
+        if (cfg.cx == CX && cfg.cy == CY && cfg.cz == CZ && cfg.k == K)                                     \
+            return pair_launch<real, CX, CY, CZ>(s, p, rep, st, ch, ps, b, fin, fout, gin, gout, partG, sums, w, \
+                                                 d, use_alpha, e0, e1);
+    HSF_TILE_CONFIGS(HSF_CASE)
+#undef HSF_CASE
+}
 
 template <typename real>
 void launch_field_exp(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, const double *w,
@@ -859,7 +1144,11 @@ void launch_bwd_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Re
     template void launch_bwd_block<real>(const TileCfg &, hipStream_t, const Plan &, const Rep *,         \
                                          RepState *, Chain, int, int, PropBufs<real>, const real *,       \
                                          real *, double *, int, const double *, const double *, double *, \
-                                         double *, const double *, int, hipEvent_t, hipEvent_t);
+                                         double *, const double *, int, hipEvent_t, hipEvent_t);          \
+    template void launch_pair_block<real>(const TileCfg &, hipStream_t, const Plan &, const Rep *,        \
+                                          RepState *, Chain, const PairSteps &, PropBufs<real>,          \
+                                          const real *, real *, const real *, real *, double *, int,     \
+                                          const double *, const double *, int, hipEvent_t, hipEvent_t);
 HSF_INST(double)
 HSF_INST(float)
 #undef HSF_INST

@@ -42,8 +42,8 @@ SOLVER_PRECOND = 1
 LB_BGK, LB_MRT = 0, 1
 NOISE_CD, NOISE_LB = 1, 2
 CD_EXPLICIT, CD_CRANK_NICOLSON = 0, 1
-K_PREP, K_FWD, K_BWD, K_LB, K_CD, K_COUNT = 0, 1, 2, 3, 4, 5
-KERNEL_NAMES = ["prep", "fwd", "bwd", "lb", "cd"]
+K_PREP, K_FWD, K_BWD, K_LB, K_CD, K_PAIR, K_COUNT = 0, 1, 2, 3, 4, 5, 6
+KERNEL_NAMES = ["prep", "fwd", "bwd", "lb", "cd", "pair"]
 
 
 class HsfError(RuntimeError):

@@ -380,7 +380,9 @@ def test_graph_replays_match_direct_launches(hsf, orc, monkeypatch):
 
 TILES = [(64, 4, 1, 0), (32, 8, 1, 0), (16, 16, 1, 0), (64, 4, 2, 0), (32, 8, 2, 0), (16, 16, 2, 0), (64, 4, 4, 0),
          (32, 8, 4, 0), (16, 16, 4, 0), (64, 4, 8, 0), (16, 16, 8, 0), (8, 8, 8, 1), (8, 8, 8, 2), (8, 8, 8, 3), (8, 8, 8, 4), (16, 8, 8, 2), (16, 8, 4, 2), (32, 8, 4, 1),
-         (32, 4, 4, 2)]
+         (32, 4, 4, 2), (64, 4, 2, -1), (32, 8, 2, -1), (16, 16, 2, -1), (32, 8, 4, -1), (16, 16, 4, -1),
+         (16, 16, 8, -1)]
+PAIRED = [t for t in TILES if t[3] == -1]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -541,7 +543,7 @@ def test_chain_length_extremes(hsf, orc, types, L, precision):
     ctx = hsf.Context(wl)
     ctx.set_densities(phi0.ravel())
     ctx.set_fields(w.ravel())
-    for tile in ((64, 4, 2, 0), (8, 8, 8, 2)):
+    for tile in ((64, 4, 2, 0), (8, 8, 8, 2), (64, 4, 2, -1)):
         ctx.set_tile(tile)
         got, q = ctx.evaluate()
         got = got.reshape(ref.shape)
@@ -572,7 +574,7 @@ def test_smallest_boxes(hsf, orc, L, precision):
     ctx = hsf.Context(wl)
     ctx.set_densities(phi0.ravel())
     ctx.set_fields(w.ravel())
-    for tile in ((64, 4, 2, 0), (8, 8, 8, 2)):
+    for tile in ((64, 4, 2, 0), (8, 8, 8, 2), (32, 8, 2, -1)):
         ctx.set_tile(tile)
         got, q = ctx.evaluate()
         e = relerr(got, ref)
@@ -691,3 +693,66 @@ def test_hydro_switched_mid_run(hsf, orc):
             assert np.max(np.abs(ctx.get_lb().reshape(n.shape) - n)) < 1e-14
     assert np.max(np.abs(ctx.get_lb().reshape(n.shape) - n)) < 1e-14
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_paired_sweeps_match_one_step_bitwise(hsf, orc, precision):
+    """Paired launches (one forward and one backward contour step per launch, the
+    density term formed by whichever of a bead's two steps runs second) store every
+    value as the same expression of the same operands as the one-step sequence: for
+    odd and even N, one replica (descriptors as kernel arguments) and six of uneven
+    boxes (descriptors in device tables), the densities and Q are bit for bit those of
+    the one-step kernels of the same tiling, and within tolerance of the oracle."""
+    tol = TOL64 if precision == "fp64" else TOL32
+    for L, types in [((17, 18, 20), W.chain(3, 4)), ((24, 20, 9), W.chain(4, 4)), ((5, 3, 9), W.chain(2, 3)),
+                     ((9, 7, 5), W.chain(1, 1)), ((12, 11, 10), W.chain(5, 11))]:
+        wl = small_melt(L=L, types=types, precision=precision)
+        w = fields_for(wl, seed=21, amp=1.2)
+        ref, qref = orc.evaluate(osys(orc, wl), w, 1.0, 0.0)
+        ctx = hsf.Context(wl)
+        ctx.set_densities(W.initial_composition(wl).ravel())
+        ctx.set_fields(w.ravel())
+        for t in PAIRED:
+            ctx.set_tile(t[:3] + (0,))
+            ctx.evaluate()   # the FP32 scales follow the previous evaluation: same state for both
+            one, q1 = ctx.evaluate()
+            ctx.set_tile(t)
+            two, q2 = ctx.evaluate()
+            say(f"[paired {t}] {L} N={len(types)} {precision}: rel err {relerr(two, ref):.3e}")
+            assert np.array_equal(one, two) and np.array_equal(q1, q2), (t, L)
+            assert relerr(two, ref) < tol and abs(q2[0] / qref - 1) < tol, (t, L)
+        ctx.close()
+    types = W.chain(3, 4)
+    wls = [small_melt(L=Lr, types=types, precision=precision, seed=r)
+           for r, Lr in enumerate([(17, 18, 20), (5, 3, 9), (16, 16, 16), (9, 7, 5), (20, 6, 11), (8, 8, 8)])]
+    ws = [fields_for(wl, seed=30 + r, amp=1.2) for r, wl in enumerate(wls)]
+    ctx = hsf.Context(wls)
+    ctx.set_densities(np.concatenate([W.initial_composition(wl).ravel() for wl in wls]))
+    ctx.set_fields(np.concatenate([w.ravel() for w in ws]))
+    for t in PAIRED:
+        ctx.set_tile(t[:3] + (0,))
+        ctx.evaluate()
+        one, q1 = ctx.evaluate()
+        ctx.set_tile(t)
+        two, q2 = ctx.evaluate()
+        assert np.array_equal(one, two) and np.array_equal(q1, q2), t
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_paired_sweeps_coupled_steps_bitwise(hsf, orc, precision):
+    """Three coupled steps (inversions with their line searches, LB, convection-diffusion)
+    with the paired kernels leave the same densities, fields and Q bit for bit as with the
+    one-step kernels of the same tiling, for a two-replica context."""
+    types = W.chain(4, 4)
+    wls = [small_melt(L=(20, 18, 16), types=types, precision=precision, seed=3),
+           small_melt(L=(12, 12, 12), types=types, precision=precision, seed=4)]
+    out = []
+    for t in [(32, 8, 2, 0), (32, 8, 2, -1)]:
+        ctx = hsf.Context(wls)
+        ctx.set_tile(t)
+        ctx.set_densities(np.concatenate([W.initial_composition(wl).ravel() for wl in wls]))
+        ctx.step(3, tol=1e-8 if precision == "fp64" else 1e-6, max_iter=1000)
+        out.append((ctx.get_densities(), ctx.get_fields()))
+        ctx.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
