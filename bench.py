@@ -41,7 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # as they stand; anything else reports null.
 MEASURED_TRAFFIC = {("melt64_a8b8", "fp32", (64, 4, 2, 0), "bwd"): 13.72e6,
                     ("melt64_a8b8", "fp32", (32, 8, 2, 0), "bwd"): 13.74e6,
-                    ("melt192_a8b8", "fp32", (64, 4, 8, 0), "bwd"): 185.7e6}
+                    ("melt192_a8b8", "fp32", (64, 4, 8, 0), "bwd"): 185.7e6,
+                    ("melt64_a8b8", "fp32", (32, 8, 2, -1), "pair"): 18.45e6}
 METRIC = "propagator site·bead updates/s + LB MLUPS; step time learned vs plain at 1e-6"
 
 
