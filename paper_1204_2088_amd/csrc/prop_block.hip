@@ -620,6 +620,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(StepInfo si, const int *_
     }
 }
 
+// FINAL: the launch of step 1 (only), which sums the stored density terms and normalises;
+// the other steps' instances carry none of its registers.
 // With fold_q = 1, step N's launch also finishes the forward sweep's reduction: the
 // first block of each replica sums the replica's G_N partials (partG row N - 1, fixed
 // order) and stores Q, ln Q and the range flag, which step 1 uses for the normalisation,
@@ -627,7 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(StepInfo si, const int *_
 // forward step N runs just before step 1), step 1's launch does it: every block sums the
 // partials itself in that same order, so all hold the same Q, and the replica's first
 // block stores it.
-template <typename real, int CX, int CY, int CZ, bool ARGS>
+template <typename real, int CX, int CY, int CZ, bool ARGS, bool FINAL>
 __global__ __launch_bounds__(kBlock) void k_bwd_direct(StepInfo si, const int *__restrict__ blk_rep,
                                                        const int *__restrict__ blk_first,
                                                        const Rep *__restrict__ rep,
@@ -665,13 +667,45 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(StepInfo si, const int *_
         } else {
             column_stencil<real, CZ>(gin + R.site_off, x, y, z0, nz, R, S);
         }
-        if (CZ <= 2 && s > 1) {   // short columns: all the step's loads go out together
+        if (CZ <= 2 && !FINAL) {   // short columns: all the step's loads go out together
 #pragma unroll
             for (int j = 0; j < CZ; ++j) {
                 // clamped past a short last chunk (those values are not used)
                 const int site = x + R.Lx * (y + R.Ly * min(z0 + j, z0 + nz - 1));
                 Ev[j] = b.E[po + ts * V + site];
                 Gv[j] = G[(long long)(s - 1) * V + site];
+            }
+        }
+    }
+    // step 1 sums the stored terms of steps N .. 2 (slots N - 1 .. 1) in that order, then
+    // its own: the first TB of them per plane, G_1 and (short columns, gradient mode) the
+    // targets and the direction are loaded here with the stencil, for all planes together
+    constexpr int TB = CZ <= 2 ? (sizeof(real) == 4 ? 32 : 16) / CZ : (sizeof(real) == 4 ? 2 : 1);
+    real tv[CZ][TB], g1[CZ];
+    double pt[CZ][2], pd[CZ][2];
+#pragma unroll
+    for (int j = 0; j < CZ; ++j) {
+        g1[j] = (real)0;
+        pt[j][0] = pt[j][1] = pd[j][0] = pd[j][1] = 0.0;
+#pragma unroll
+        for (int u = 0; u < TB; ++u) tv[j][u] = (real)0;
+    }
+    const long long fo = off_field(R, si.nsp);
+    if (FINAL && in) {
+#pragma unroll
+        for (int j = 0; j < CZ; ++j) {
+            const int site = x + R.Lx * (y + R.Ly * min(z0 + j, z0 + nz - 1));
+            if (N >= 2) {
+#pragma unroll
+                for (int u = 0; u < TB; ++u) tv[j][u] = G[(long long)(max(N - u, 2) - 1) * V + site];
+            }
+            g1[j] = G[site];
+            if (CZ <= 2 && final_mode == 1) {
+#pragma unroll
+                for (int I = 0; I < 2; ++I) {
+                    pt[j][I] = phit[fo + (long long)I * V + site];
+                    if (d) pd[j][I] = d[po + (long long)I * V + site];
+                }
             }
         }
     }
@@ -697,8 +731,35 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(StepInfo si, const int *_
             }
         }
     }
+    // step 1: the sums of the stored terms per species (before the Q fold, whose partials
+    // then take one more round trip)
+    double a0[CZ], a1[CZ];
+#pragma unroll
+    for (int j = 0; j < CZ; ++j) a0[j] = a1[j] = 0.0;
+    if (FINAL && in) {
+        for (int q0 = N; q0 >= 2; q0 -= TB) {
+            if (q0 != N) {
+#pragma unroll
+                for (int j = 0; j < CZ; ++j) {
+                    const int site = x + R.Lx * (y + R.Ly * min(z0 + j, z0 + nz - 1));
+#pragma unroll
+                    for (int u = 0; u < TB; ++u) tv[j][u] = G[(long long)(max(q0 - u, 2) - 1) * V + site];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < CZ; ++j) {
+#pragma unroll
+                for (int u = 0; u < TB; ++u) {
+                    const int q = q0 - u;
+                    if (q < 2) break;
+                    if (ch.types[q - 1] == 0) a0[j] += (double)tv[j][u];
+                    else a1[j] += (double)tv[j][u];
+                }
+            }
+        }
+    }
     double q_own = 0.0;
-    if (fold_q == 2 && s == 1) {
+    if (FINAL && fold_q == 2) {
         __shared__ double q_sh;
         if (threadIdx.x < 64) {
             const int pb = plan_block();
@@ -725,58 +786,45 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(StepInfo si, const int *_
         q_own = q_sh;
     }
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
-    if (in) {
-        const double coef = st[r].phibar_p / ((double)N * (fold_q == 2 ? q_own : st[r].q));
-        const long long fo = off_field(R, si.nsp);
+    if (in && !FINAL) {
 #pragma unroll
         for (int j = 0; j < CZ; ++j) {
             if (j >= nz) break;
             const int site = x + R.Lx * (y + R.Ly * (z0 + j));
             real *Gs = G + (long long)(s - 1) * V + site;
-            if (s > 1) {
-                const real e = CZ <= 2 ? Ev[j] : b.E[po + ts * V + site];
-                const real gs = CZ <= 2 ? Gv[j] : *Gs;
-                gout[R.site_off + site] = e * S[j] * sc;
-                // the density term G_s sigma[G+_{s+1}] replaces G_s in the store (G_s is
-                // not read again in this evaluation); step 1 sums them
-                *Gs = gs * S[j];
-            } else {
-                // terms of steps N .. 2 in that order, then step 1's (the order of an
-                // accumulation along the backward sweep); loaded eight at a time so that
-                // their memory round trips overlap (indices below 2 are clamped to a valid
-                // slot and not added)
-                double a0 = 0.0, a1 = 0.0;
-                for (int q0 = N; q0 >= 2; q0 -= 8) {
-                    real v[8];
+            const real e = CZ <= 2 ? Ev[j] : b.E[po + ts * V + site];
+            const real gs = CZ <= 2 ? Gv[j] : *Gs;
+            gout[R.site_off + site] = e * S[j] * sc;
+            // the density term G_s sigma[G+_{s+1}] replaces G_s in the store (G_s is
+            // not read again in this evaluation); step 1 sums them
+            *Gs = gs * S[j];
+        }
+    }
+    if (in && FINAL) {
+        const double coef = st[r].phibar_p / ((double)N * (fold_q == 2 ? q_own : st[r].q));
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) v[u] = G[(long long)(max(q0 - u, 2) - 1) * V + site];
+        for (int j = 0; j < CZ; ++j) {
+            if (j >= nz) break;
+            const int site = x + R.Lx * (y + R.Ly * (z0 + j));
+            double a[2] = {a0[j], a1[j]};
+            a[ts] += (double)g1[j] * (double)S[j];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int q = q0 - u;
-                        if (q < 2) break;
-                        if (ch.types[q - 1] == 0) a0 += (double)v[u];
-                        else a1 += (double)v[u];
-                    }
-                }
-                double a[2] = {a0, a1};
-                a[ts] += (double)*Gs * (double)S[j];
-#pragma unroll
-                for (int I = 0; I < 2; ++I) {
-                    const double ph = coef * a[I];
-                    if (final_mode == 0) {
-                        out[fo + (long long)I * V + site] = ph;
-                    } else {
-                        const double gI = phit[fo + (long long)I * V + site] - ph;
-                        out[po + (long long)I * V + site] = gI;
-                        if (d) sums[0] += d[po + (long long)I * V + site] * gI;
-                        sums[1] += ch.precond ? gI * gI / phit[fo + (long long)I * V + site] : gI * gI;
-                        sums[2 + I] += gI * gI;
-                    }
+            for (int I = 0; I < 2; ++I) {
+                const double ph = coef * a[I];
+                if (final_mode == 0) {
+                    out[fo + (long long)I * V + site] = ph;
+                } else {
+                    const double tI = CZ <= 2 ? pt[j][I] : phit[fo + (long long)I * V + site];
+                    const double gI = tI - ph;
+                    out[po + (long long)I * V + site] = gI;
+                    if (d) sums[0] += (CZ <= 2 ? pd[j][I] : d[po + (long long)I * V + site]) * gI;
+                    sums[1] += ch.precond ? gI * gI / tI : gI * gI;
+                    sums[2 + I] += gI * gI;
                 }
             }
         }
     }
-    if (s == 1 && final_mode == 1) {
+    if (FINAL && final_mode == 1) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const double t = block_sum(sums[q]);
@@ -1031,7 +1079,10 @@ struct BlockKernels {
                     hipEvent_t e1)
     {
         if constexpr (K <= 0) {   // direct kernels (K = -1: their single steps)
-            auto kern = p.args.n ? k_bwd_direct<real, CX, CY, CZ, true> : k_bwd_direct<real, CX, CY, CZ, false>;
+            auto kern = s_hi == 1 ? (p.args.n ? k_bwd_direct<real, CX, CY, CZ, true, true>
+                                              : k_bwd_direct<real, CX, CY, CZ, false, true>)
+                                  : (p.args.n ? k_bwd_direct<real, CX, CY, CZ, true, false>
+                                              : k_bwd_direct<real, CX, CY, CZ, false, false>);
             if (e0)
                 hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, step_info(ch, s_hi),
                                       p.blk_rep, p.blk_first, rep, st, ch, b, gin, gout, acc, final_mode, phit, d,
