@@ -267,7 +267,7 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing")
     ap.add_argument("--no-fp64-arm", action="store_true", help="skip the all-FP64 arm")
     ap.add_argument("--precond", action="store_true", help="diagonally preconditioned inversion")
-    ap.add_argument("--tile", default=None, help="cx,cy,cz,k: use this propagator tiling instead of autotuning")
+    ap.add_argument("--tile", default=None, help="cx,cy,cz,k: use this propagator tiling instead of autotuning (k = 0: one step per launch, -1: paired forward/backward steps, >= 1: temporally blocked)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
     ap.add_argument("--net-widths", default=None, metavar="WIDTHS",
                     help="level widths of the learned warm start's network (e.g. 8,16,24,32; default one level of 16)")
