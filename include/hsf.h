@@ -70,7 +70,8 @@ enum {
     HSF_ENOMEM = -2,      /* device allocation failed                           */
     HSF_EHIP = -3,        /* HIP runtime error; message has the HIP string      */
     HSF_ENOCONV = -4,     /* inversion hit max_iter; the iterate is kept        */
-    HSF_ENONFINITE = -5   /* a NaN/Inf appeared in a reduction                  */
+    HSF_ENONFINITE = -5   /* a NaN/Inf appeared; hsf_step leaves the state of   */
+                          /* the failing step's start (see hsf_step)            */
 };
 
 enum { HSF_HOST = 0, HSF_DEVICE = 1 };
@@ -140,7 +141,12 @@ typedef struct {
 typedef struct hsf_ctx hsf_ctx;
 
 /* Create a context for n_rep replicas described by reps[0..n_rep-1] on the
- * current HIP device.  All replicas must share n_beads, types, has_solvent and
+ * current HIP device.  The parameters are those of the model of section 2: the
+ * chain architecture A_n B_m (+ monomeric solvent S) of eq. 2, the Flory-Huggins
+ * parameters and Helfand compressibility of the free energy of eq. 1, the segment
+ * length a of the Gaussian bond kernel discretised by the 27-point stencil
+ * (text after eq. 17), the LB relaxation (eq. 10-15) and one time step shared by the
+ * LB and convection-diffusion updates (text after eq. 17).  All replicas must share n_beads, types, has_solvent and
  * precision.  Densities start at zero, fields at zero, LB populations at rest
  * with density 1.  Returns HSF_EINVAL on inconsistent parameters, HSF_ENOMEM
  * when device memory is short. */
@@ -231,15 +237,25 @@ int hsf_get_flow(hsf_ctx *ctx, double *rho, double *u, int where);
  * [3][V], NULL for none). */
 int hsf_cd_advance(hsf_ctx *ctx, const double *mu, const double *u, int where);
 
-/* Coupled steps: for each step, invert (warm start: previous fields), then
- * mu and force, then (hydro on) one LB step giving u, then the
- * convection-diffusion update.  stats (n_rep entries, may be NULL) receives
- * the last step's inversion counts; total_evals (may be NULL) the number of
- * density-functional evaluations over all steps and replicas. */
+/* Coupled steps (section 2, text after eq. 17: LB steps alternate with steps of the
+ * convection-diffusion equation (3) at the same time step, and every such step first
+ * determines the fields self-consistently by Fletcher-Reeves).  For each step: invert
+ * (warm start of hsf_set_warm), then mu and force (eq. 4, 8), then (hydro on) one LB
+ * step giving u (eq. 9-10), then the convection-diffusion update (eq. 3).  stats
+ * (n_rep entries, may be NULL) receives the last step's inversion counts; total_evals
+ * (may be NULL) the number of density-functional evaluations over all steps and
+ * replicas.  Errors: HSF_ENOCONV when an inversion stops at max_iter (its iterate is
+ * kept as the fields; densities and LB state are those of the step's start);
+ * HSF_ENONFINITE when the inversion, an LB moment or an updated density is not finite
+ * in some replica: the whole context is left as at the start of that step (fields,
+ * densities, LB populations, scales, warm-start history, noise step word; the moments
+ * read by hsf_get_flow are those of the failed step), the steps before it are kept. */
 int hsf_step(hsf_ctx *ctx, int n_steps, double tol, int max_iter, hsf_invert_stats *stats,
              long long *total_evals);
 
-/* Checkpoint of the state a continuation reads: densities, fields, LB populations, the
+/* Checkpoint of the state a continuation reads (section 3.2 continues runs from saved
+ * states of earlier ones, e.g. switching the flow on in a state of a diffusion-only run,
+ * Fig. 5-6): densities, fields, LB populations, the
  * replicas' inversion control state (with the per-step power-of-two scales of the FP32
  * propagators), the warm-start history, the noise step word and the propagator tiling.
  * hsf_get_state writes hsf_state_size(ctx) bytes into buf (host memory, size bytes);
@@ -315,7 +331,8 @@ int hsf_set_noise(hsf_ctx *ctx, int flags, double omega, unsigned long long seed
 int hsf_get_noise_step(const hsf_ctx *ctx, unsigned long long *step);
 
 /* Switch convection by the LB flow on or off for every replica (the LB state
- * is kept while off). */
+ * is kept while off).  Off is the diffusion-only model of section 3.1 (eq. 3 with
+ * u = 0); section 3.2 turns the flow on, or off, part way through a run (Fig. 5-7). */
 int hsf_set_hydro(hsf_ctx *ctx, int on);
 
 /* Inversion variant.  0 (default): plain Fletcher-Reeves on the gradient

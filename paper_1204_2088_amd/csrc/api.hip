@@ -43,6 +43,10 @@ struct hsf_ctx {
     RepState *st_d = nullptr;
     RepState *st_h = nullptr;        // pinned mirror for status reads (written by the control kernel)
     RepState *st_hd = nullptr;       // the mirror's device-side address
+    RepState *st_save = nullptr;     // device copy of the replica states at the start of a coupled step
+    double *w_start = nullptr;       // fields at the start of a coupled step (rollback of a failed step)
+    int *bad_h = nullptr;            // pinned flag set by the LB and CD kernels on a non-finite result
+    int *bad_hd = nullptr;           // its device-side address
     Plan plan;                       // site plan: kBlock consecutive sites per block
     TileCfg tile{8, 8, 8, 2};        // propagator tile configuration in use
     Plan tplan;                      // tile plan of `tile`
@@ -480,7 +484,23 @@ int warm_start(hsf_ctx *c, int warm)
     return HSF_OK;
 }
 
-int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats *stats, long long *evals_out)
+// Keep the latest inversion's result and target for the warm starts of the next ones.
+int commit_history(hsf_ctx *c)
+{
+    std::swap(c->w_hist[0], c->w_hist[1]);
+    std::swap(c->phi_hist[0], c->phi_hist[1]);
+    HIPCHK(c, hipMemcpyAsync(c->w_hist[0], c->w, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->phi_hist[0], c->phi, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice,
+                             c->stream));
+    c->n_hist = std::min(c->n_hist + 1, 2);
+    return HSF_OK;
+}
+
+// commit_hist: record the result in the warm-start history here (hsf_invert); a coupled
+// step records it only once the whole step has succeeded.
+int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats *stats, long long *evals_out,
+                bool commit_hist = true)
 {
     if (!(tol >= 0.0) || max_iter < 0) return fail(c, HSF_EINVAL, "bad tol %g or max_iter %d", tol, max_iter);
     if (warm < HSF_WARM_CURRENT || warm > HSF_WARM_NET_EXTRAP) return fail(c, HSF_EINVAL, "bad warm mode %d", warm);
@@ -519,7 +539,9 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
     long long guard = 3LL * max_iter + 3;
     while (any) {
         for (int p = 0; p < kPassesPerRead; ++p) {
-            if (--guard < 0) return fail(c, HSF_EHIP, "inversion control did not progress");
+            if (--guard < 0)   // the iterate is kept, as at max_iter
+                return fail(c, HSF_ENOCONV, "inversion stopped after %lld passes without finishing",
+                            3LL * max_iter + 3);
             rc = run_seq(c, hsf_ctx::GK_TRIAL, [&] {
                 run_eval_any(c, 1, 1, c->gt, c->d, 0);
                 launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_TRIAL, c->ch,
@@ -540,12 +562,6 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
     }
     if ((rc = read_status(c))) return rc;
     HIPCHK(c, hipGetLastError());
-    // keep the result and its target for the warm starts of the next inversions
-    std::swap(c->w_hist[0], c->w_hist[1]);
-    std::swap(c->phi_hist[0], c->phi_hist[1]);
-    HIPCHK(c, hipMemcpyAsync(c->w_hist[0], c->w, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(c->phi_hist[0], c->phi, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice, s));
-    c->n_hist = std::min(c->n_hist + 1, 2);
     int status = HSF_OK;
     long long ev = 0;
     for (int r = 0; r < c->n_rep; ++r) {
@@ -565,6 +581,8 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
             status = fail(c, HSF_ENOCONV, "replica %d stopped at %d iterations, residual %g", r, S.iters, S.res);
     }
     if (evals_out) *evals_out += ev;
+    if (commit_hist && status != HSF_ENONFINITE)
+        if (int rc2 = commit_history(c)) return rc2;
     return status;
 }
 
@@ -892,9 +910,11 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     if (rc == HSF_OK) rc = dalloc(c, (void **)&(ptr), (size_t)(bytes));
     ALLOC(c->rep_d, sizeof(Rep) * n_rep);
     ALLOC(c->st_d, sizeof(RepState) * n_rep);
+    ALLOC(c->st_save, sizeof(RepState) * n_rep);
     ALLOC(c->plan.blk_rep, sizeof(int) * blk_rep.size());
     ALLOC(c->plan.blk_first, sizeof(int) * blk_first.size());
     ALLOC(c->w, sizeof(double) * nsp * T);
+    ALLOC(c->w_start, sizeof(double) * nsp * T);
     ALLOC(c->phi, sizeof(double) * nsp * T);
     ALLOC(c->phi_tmp, sizeof(double) * nsp * T);
     ALLOC(c->mu, sizeof(double) * nsp * T);
@@ -934,6 +954,11 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
         if (e != hipSuccess) rc = fail(c, HSF_ENOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
         else if ((e = hipHostGetDevicePointer((void **)&c->st_hd, c->st_h, 0)) != hipSuccess)
             rc = fail(c, HSF_EHIP, "hipHostGetDevicePointer failed: %s", hipGetErrorString(e));
+        else if ((e = hipHostMalloc((void **)&c->bad_h, sizeof(int), hipHostMallocDefault)) != hipSuccess)
+            rc = fail(c, HSF_ENOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
+        else if ((e = hipHostGetDevicePointer((void **)&c->bad_hd, c->bad_h, 0)) != hipSuccess)
+            rc = fail(c, HSF_EHIP, "hipHostGetDevicePointer failed: %s", hipGetErrorString(e));
+        if (c->bad_h) *c->bad_h = 0;
     }
     if (rc != HSF_OK) {
         hsf_destroy(c);
@@ -994,6 +1019,7 @@ void hsf_destroy(hsf_ctx *c)
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (void *p : c->allocs) (void)hipFree(p);
     if (c->st_h) (void)hipHostFree(c->st_h);
+    if (c->bad_h) (void)hipHostFree(c->bad_h);
     if (c->cn_dots_h) (void)hipHostFree(c->cn_dots_h);
     delete c;
 }
@@ -1171,16 +1197,42 @@ int hsf_cd_advance(hsf_ctx *c, const double *mu, const double *u, int where)
     return HSF_OK;
 }
 
+// A failed coupled step leaves the state of its start: the fields and replica states
+// (scales, control) are copied back, and the densities and LB populations are only
+// replaced once the step has finished with finite results.
+static int rollback_step(hsf_ctx *c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->w, c->w_start, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->st_d, c->st_save, sizeof(RepState) * c->n_rep, hipMemcpyDeviceToDevice, c->stream));
+    return sync(c);
+}
+
 int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats *stats, long long *total_evals)
 {
     if (!c || n_steps < 0) return HSF_EINVAL;
     if (total_evals) *total_evals = 0;
     for (int k = 0; k < n_steps; ++k) {
+        HIPCHK(c, hipMemcpyAsync(c->w_start, c->w, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice,
+                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->st_save, c->st_d, sizeof(RepState) * c->n_rep, hipMemcpyDeviceToDevice,
+                                 c->stream));
         // with Crank-Nicolson the fields of phi^n are already converged (phi^n = phi[w^n]
         // after an implicit step): the inversion only confirms them
         const bool implicit = c->integrator == HSF_CD_CRANK_NICOLSON;
-        int rc = invert_impl(c, tol, max_iter, implicit ? HSF_WARM_CURRENT : c->step_warm, stats, total_evals);
+        int rc = invert_impl(c, tol, max_iter, implicit ? HSF_WARM_CURRENT : c->step_warm, stats, total_evals,
+                             false);
+        if (rc == HSF_ENONFINITE) {
+            std::string msg = c->err;
+            if (int r2 = rollback_step(c)) return r2;
+            return fail(c, HSF_ENONFINITE, "%s; the step was rolled back", msg.c_str());
+        }
+        if (rc == HSF_ENOCONV) {
+            if (int r2 = commit_history(c)) return r2;
+            return rc;
+        }
         if (rc != HSF_OK) return rc;
+        *c->bad_h = 0;   // the kernels below set it on a non-finite result
         launch_mu(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->w, c->mu);
         const double *uu = nullptr;
         if (c->hydro) {
@@ -1188,27 +1240,48 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
             {
                 Timed t(c, HSF_K_LB);
                 launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, c->force, c->rho, c->u,
-                          (c->noise & HSF_NOISE_LB) != 0, c->noise_step, c->lb_all, t.a, t.b);
+                          (c->noise & HSF_NOISE_LB) != 0, c->noise_step, c->lb_all, t.a, t.b, c->bad_hd);
             }
-            std::swap(c->nA, c->nB);
             uu = c->u;
         }
         if (c->integrator == HSF_CD_CRANK_NICOLSON) {
+            // the inversion's fields are kept for the warm starts (the implicit solve replaces
+            // the densities below)
+            if ((rc = commit_history(c))) return rc;
             // right-hand side phi^n + dt/2 B^n - div J^C + xi, then the implicit solve
             launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, uu, c->cn_rhs,
-                      (c->noise & HSF_NOISE_CD) ? c->noise_flux : nullptr, c->noise_step, nullptr, nullptr, 0.5);
-            if (c->noise) ++c->noise_step;
+                      (c->noise & HSF_NOISE_CD) ? c->noise_flux : nullptr, c->noise_step, nullptr, nullptr, 0.5,
+                      c->bad_hd);
             long long ev = 0;
             rc = cn_solve(c, &ev);
             if (total_evals) *total_evals += ev;
+            if (rc == HSF_OK && *c->bad_h) rc = fail(c, HSF_ENONFINITE, "non-finite LB moment or density");
+            if (rc == HSF_ENONFINITE) {   // cn_solve stops before it replaces the densities
+                std::string msg = c->err;
+                if (int r2 = rollback_step(c)) return r2;
+                return fail(c, HSF_ENONFINITE, "%s; the step was rolled back", msg.c_str());
+            }
+            if (c->hydro) std::swap(c->nA, c->nB);
+            if (c->noise) ++c->noise_step;
             if (rc != HSF_OK) return rc;
             continue;
         }
         {
             Timed t(c, HSF_K_CD);
             launch_cd(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, uu, c->phi_tmp,
-                      (c->noise & HSF_NOISE_CD) ? c->noise_flux : nullptr, c->noise_step, t.a, t.b);
+                      (c->noise & HSF_NOISE_CD) ? c->noise_flux : nullptr, c->noise_step, t.a, t.b, 1.0,
+                      c->bad_hd);
         }
+        HIPCHK(c, hipGetLastError());
+        if ((rc = sync(c))) return rc;
+        if (*c->bad_h) {
+            if (int r2 = rollback_step(c)) return r2;
+            return fail(c, HSF_ENONFINITE, "non-finite LB moment or updated density; the step was rolled back");
+        }
+        // the step succeeded: keep its inversion for the warm starts (with the targets phi^n),
+        // then the new populations and densities
+        if ((rc = commit_history(c))) return rc;
+        if (c->hydro) std::swap(c->nA, c->nB);
         if (c->noise) ++c->noise_step;   // both noises of a coupled step share its step word
         // the captured sequences hold the address of phi: copy the update back
         HIPCHK(c, hipMemcpyAsync(c->phi, c->phi_tmp, sizeof(double) * c->ch.nsp * c->T,

@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, 
                                                const Rep *__restrict__ rep, const double *__restrict__ nsrc,
                                                double *__restrict__ ndst, const double *__restrict__ f,
                                                double *__restrict__ rho_out, double *__restrict__ u_out,
-                                               unsigned long long step)
+                                               unsigned long long step, int *__restrict__ bad)
 {
     const SiteRef sr = site_ref(blk_rep, blk_first);
     const Rep &R = rep[sr.r];
@@ -257,6 +257,8 @@ __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, 
         jz += kCz[q] * n[q];
     }
     const double ux = (jx + 0.5 * fx) / rho, uy = (jy + 0.5 * fy) / rho, uz = (jz + 0.5 * fz) / rho;
+    // a non-finite population or force shows in the moments; the host rolls the step back
+    if (bad && !(isfinite(rho) && isfinite(ux) && isfinite(uy) && isfinite(uz))) bad[0] = 1;
     double ns[19];
     const bool mrt = MODE == HSF_LB_MRT || (MODE < 0 && R.lb_mode == HSF_LB_MRT);
     if (mrt) {
@@ -304,7 +306,8 @@ __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, 
                                                const Rep *__restrict__ rep, Chain ch,
                                                const double *__restrict__ phi, const double *__restrict__ mu,
                                                const double *__restrict__ u, double *__restrict__ phi_out,
-                                               const double *__restrict__ jn, double diff_scale)
+                                               const double *__restrict__ jn, double diff_scale,
+                                               int *__restrict__ bad)
 {
     const SiteRef sr = site_ref(blk_rep, blk_first);
     const Rep &R = rep[sr.r];
@@ -342,7 +345,9 @@ __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, 
             }
             div += jh - jl;
         }
-        phi_out[fo + I * V + i] = pr - div;
+        const double pn = pr - div;
+        if (bad && !isfinite(pn)) bad[0] = 1;
+        phi_out[fo + I * V + i] = pn;
     }
 }
 
@@ -405,22 +410,22 @@ void launch_force(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const 
 
 void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc, double *ndst, const double *f,
                double *rho, double *u, bool noise, unsigned long long step, int lb_mode, hipEvent_t e0,
-               hipEvent_t e1)
+               hipEvent_t e1, int *bad)
 {
     auto pick = [&](auto bgk, auto mrt, auto mixed) { return lb_mode == HSF_LB_BGK ? bgk : lb_mode == HSF_LB_MRT ? mrt : mixed; };
     auto kern = noise ? pick(k_lb<true, HSF_LB_BGK>, k_lb<true, HSF_LB_MRT>, k_lb<true, -1>)
                       : pick(k_lb<false, HSF_LB_BGK>, k_lb<false, HSF_LB_MRT>, k_lb<false, -1>);
     if (e0)
         hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep,
-                              nsrc, ndst, f, rho, u, step);
+                              nsrc, ndst, f, rho, u, step, bad);
     else
         hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, nsrc, ndst, f,
-                           rho, u, step);
+                           rho, u, step, bad);
 }
 
 void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi, const double *mu,
                const double *u, double *phi_out, double *noise_flux, unsigned long long step, hipEvent_t e0,
-               hipEvent_t e1, double diff_scale)
+               hipEvent_t e1, double diff_scale, int *bad)
 {
     // with noise the events bracket both kernels: e0 at the start of the flux draw
     if (noise_flux) {
@@ -435,10 +440,10 @@ void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const dou
     auto kern = noise_flux ? k_cd<true> : k_cd<false>;
     if (e0 || e1)
         hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep,
-                              ch, phi, mu, u, phi_out, (const double *)noise_flux, diff_scale);
+                              ch, phi, mu, u, phi_out, (const double *)noise_flux, diff_scale, bad);
     else
         hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch, phi, mu, u,
-                           phi_out, (const double *)noise_flux, diff_scale);
+                           phi_out, (const double *)noise_flux, diff_scale, bad);
 }
 
 void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n)

@@ -138,12 +138,14 @@ void launch_force(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const 
 // lb_mode: the collision of every replica (HSF_LB_BGK or HSF_LB_MRT), or -1 when mixed
 void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc, double *ndst,
                const double *f, double *rho, double *u, bool noise, unsigned long long step, int lb_mode,
-               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, int *bad = nullptr);
+// bad (may be null): set to 1 by the LB and CD kernels when a moment or an updated density is
+// not finite (so that a coupled step can be rolled back)
 // noise_flux: scratch for the composition noise's bond fluxes (3 nsp T doubles), or null
 // for no noise; diff_scale multiplies dt in the diffusive flux (1/2 in the CN step)
 void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi,
                const double *mu, const double *u, double *phi_out, double *noise_flux, unsigned long long step,
-               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, double diff_scale = 1.0);
+               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, double diff_scale = 1.0, int *bad = nullptr);
 void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n);
 
 // vector kernels of the Crank-Nicolson Newton-Krylov solve (cn.hip); vectors of n doubles
