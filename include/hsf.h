@@ -185,6 +185,34 @@ int hsf_get_densities(hsf_ctx *ctx, double *phi, int where);
  * state.  phi_out uses the field layout. */
 int hsf_evaluate(hsf_ctx *ctx, double *phi_out, double *Q_out, int where);
 
+/* ---- allocation-free evaluation ----------------------------------------------
+ * For callers that cannot allocate device memory (work recorded under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the density functional of
+ * hsf_evaluate for ONE replica, without a context.  The call allocates and frees nothing:
+ * its scratch (propagator store, field factors, partial sums, block tables, control
+ * state) is a file-scope device array of HSF_STATIC_SCRATCH_BYTES that every GPU the
+ * library runs on holds until the process ends.  It needs about
+ * s (N + 4) V + 8 (N + 10) V / 256 bytes (s = 4 for FP32, 8 for FP64 propagators):
+ * e.g. a 64^3 box with N <= 27 in FP64 or N <= 59 in FP32; larger problems return
+ * HSF_EINVAL before anything is launched.
+ *   p        one replica's parameters (box, chain, solvent, a or stencil, precision; the
+ *            dynamics parameters are not used);
+ *   w        device pointer, fields in the field layout [nsp][Lz][Ly][Lx], FP64;
+ *   phi      device pointer, densities (same layout) whose amounts phibar_p and phibar_s
+ *            normalise the result, as the current densities do in hsf_evaluate;
+ *   phi_out  device pointer, phi[w] in the field layout;
+ *   q_out    device pointer to one double: Q (NaN when it left the floating-point range);
+ *   hip_stream  the hipStream_t the work is ordered on (NULL: the null stream).
+ * The call only enqueues work and returns; results are ready when the stream is.  FP32
+ * propagators run the evaluation twice, the first pass measuring the per-step
+ * power-of-two scales the second uses.  Calls that overlap on one GPU share the array
+ * and race; the caller orders them (one stream, or waits between streams).  Returns
+ * HSF_OK, HSF_EINVAL (bad parameters, null pointers, box too large) or HSF_EHIP (a
+ * launch failed). */
+#define HSF_STATIC_SCRATCH_BYTES (64LL << 20)
+int hsf_evaluate_static(const hsf_params *p, const double *w, const double *phi, double *phi_out, double *q_out,
+                        void *hip_stream);
+
 /* Observables of the current state (w, phi), n_rep values each (host memory, any
  * may be NULL):
  *   free_energy: the free-energy density v0 F / (kT V) of eq. 1 on the lattice,

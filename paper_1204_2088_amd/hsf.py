@@ -28,7 +28,8 @@ WARM_CURRENT, WARM_LOCAL = 0, 1
 EXPORTED = [
     "hsf_create", "hsf_destroy", "hsf_last_error", "hsf_set_stream", "hsf_total_sites",
     "hsf_site_offset", "hsf_field_offset", "hsf_num_species", "hsf_set_fields", "hsf_get_fields",
-    "hsf_set_densities", "hsf_get_densities", "hsf_evaluate", "hsf_observables", "hsf_invert", "hsf_mu_force",
+    "hsf_set_densities", "hsf_get_densities", "hsf_evaluate", "hsf_evaluate_static", "hsf_observables",
+    "hsf_invert", "hsf_mu_force",
     "hsf_set_lb", "hsf_get_lb", "hsf_lb_advance", "hsf_get_flow", "hsf_cd_advance", "hsf_step",
     "hsf_set_hydro", "hsf_set_noise", "hsf_get_noise_step", "hsf_set_integrator", "hsf_get_cn_stats",
     "hsf_state_size", "hsf_get_state", "hsf_set_state", "hsf_set_timing", "hsf_get_timing", "hsf_set_tile", "hsf_get_tile", "hsf_autotune",
@@ -153,6 +154,7 @@ def load():
         "hsf_get_tile": ([C, ctypes.POINTER(ctypes.c_int)], I),
         "hsf_autotune": ([C, I, ctypes.POINTER(ctypes.c_double)], I),
         "hsf_get_timing": ([C, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)], I),
+        "hsf_evaluate_static": ([ctypes.POINTER(Params), P, P, P, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -216,6 +218,27 @@ def _ptr(a, n):
     assert isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous
     assert a.size >= n, (a.size, n)
     return ctypes.c_void_p(a.ctypes.data), HOST
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def evaluate_static(wl, w, phi, phi_out, q_out, stream=None, precision=None):
+    """hsf_evaluate_static: phi[w] and Q of one replica without a context and without any
+    device allocation.  w, phi, phi_out: contiguous float64 CUDA tensors in the field
+    layout; q_out: a float64 CUDA tensor of one element; stream: a torch stream (default:
+    the current one).  Returns the library's status code (the work is only enqueued)."""
+    import torch
+    lib = load()
+    n = (3 if wl.has_solvent else 2) * wl.V
+    for a in (w, phi, phi_out):
+        assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous() and a.numel() >= n
+    assert q_out.is_cuda and q_out.dtype == torch.float64 and q_out.numel() >= 1
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    p = params_from_workload(wl, precision)
+    return lib.hsf_evaluate_static(ctypes.byref(p), ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(phi.data_ptr()),
+                                   ctypes.c_void_p(phi_out.data_ptr()), ctypes.c_void_p(q_out.data_ptr()),
+                                   ctypes.c_void_p(s))
 
 
 class Context:
