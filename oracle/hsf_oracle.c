@@ -18,6 +18,11 @@
  * Every function here is pinned by tests against values fixed by the paper or
  * by mathematics (closed forms, brute force, Fourier linear response,
  * conservation laws, Taylor-Green decay).  No function is "parity unpinned".
+ *
+ * Timing only: built with -fopenmp (the benchmark's all-core CPU baseline) the
+ * site loops marked "omp" run over z-planes (or sites) in parallel.  Each
+ * iteration writes its own outputs and every sum stays in a serial loop, so
+ * the results are bit for bit those of the plain build.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -90,6 +95,7 @@ void orc_stencil_weights(double a, double c[4])
  */
 void orc_sigma(const orc_sys *s, const double *f, double *out)
 {
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < s->Lz; ++z)
         for (int y = 0; y < s->Ly; ++y)
             for (int x = 0; x < s->Lx; ++x) {
@@ -132,6 +138,7 @@ int orc_evaluate(const orc_sys *s, const double *w, double phibar_p, double phib
         return -1;
     }
     for (int I = 0; I < s->n_poly; ++I)
+#pragma omp parallel for schedule(static)
         for (long r = 0; r < V; ++r)
             E[I * V + r] = exp(-w[I * V + r]);
 
@@ -139,6 +146,7 @@ int orc_evaluate(const orc_sys *s, const double *w, double phibar_p, double phib
     for (int k = 1; k <= N; ++k) {
         const double *Ek = E + (long)s->types[k - 1] * V;
         orc_sigma(s, G + (long)(k - 1) * V, S);
+#pragma omp parallel for schedule(static)
         for (long r = 0; r < V; ++r) G[(long)k * V + r] = Ek[r] * S[r];
     }
     double q = 0.0;
@@ -149,13 +157,14 @@ int orc_evaluate(const orc_sys *s, const double *w, double phibar_p, double phib
     for (int k = N; k >= 1; --k) {
         int I = s->types[k - 1];
         orc_sigma(s, Gp, S);
-        double qs = 0.0;
-        for (long r = 0; r < V; ++r) {
-            double term = G[(long)k * V + r] * S[r];
-            acc[I * V + r] += term;
-            qs += term;
+#pragma omp parallel for schedule(static)
+        for (long r = 0; r < V; ++r) acc[I * V + r] += G[(long)k * V + r] * S[r];
+        if (Qs) {
+            double qs = 0.0;
+            for (long r = 0; r < V; ++r) qs += G[(long)k * V + r] * S[r];
+            Qs[k - 1] = qs / (double)V;
         }
-        if (Qs) Qs[k - 1] = qs / (double)V;
+#pragma omp parallel for schedule(static)
         for (long r = 0; r < V; ++r) Gp[r] = E[I * V + r] * S[r];
     }
     double pref = phibar_p / ((double)N * q);
@@ -717,6 +726,7 @@ static void lb_noise(const orc_sys *s, long r, double rho, double nout[19])
 void orc_lb_step(const orc_sys *s, const double *n, const double *f, double *nout, double *rho, double *u)
 {
     long V = vol(s);
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < s->Lz; ++z)
         for (int y = 0; y < s->Ly; ++y)
             for (int x = 0; x < s->Lx; ++x) {
@@ -846,3 +856,11 @@ int orc_step(const orc_sys *s, double *phi, double *w, double *n, double tol, in
     free(mu); free(f); free(u); free(rho); free(nn); free(pn);
     return rc;
 }
+
+/* Threads the site loops use (1 in the plain build). */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif

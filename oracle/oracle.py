@@ -24,15 +24,21 @@ _LIB = os.path.join(_HERE, "libhsf_oracle.so")
 MAX_BEADS = 64
 
 
+_LIB_OMP = os.path.join(_HERE, "libhsf_oracle_omp.so")
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction, so the arithmetic is
-    exactly the expressions written in the source)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call([
-            "gcc", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math",
-            "-shared", "-fPIC", "-std=c99", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    exactly the expressions written in the source), and its OpenMP build, whose
+    site loops run over z-planes in parallel with bit-identical results (used only
+    to time the oracle on all host cores)."""
+    for lib, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+            tmp = lib + ".tmp"
+            subprocess.check_call([
+                "gcc", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math", *extra,
+                "-shared", "-fPIC", "-std=c99", "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, lib)
     return _LIB
 
 
@@ -61,15 +67,30 @@ class InvertStats(ctypes.Structure):
 
 
 _lib = None
+_libs = {}
 _P = ctypes.POINTER(ctypes.c_double)
+
+
+def set_parallel(on: bool) -> int:
+    """Route every oracle call through the OpenMP build (on) or the plain one; returns
+    the number of threads the site loops then use."""
+    global _lib
+    _lib = _open(_LIB_OMP if on else _LIB)
+    return _lib.orc_threads()
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        _lib = _open(_LIB)
+    return _lib
+
+
+def _open(path):
+    if path not in _libs:
+        if not os.path.exists(path):
             build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         S = ctypes.POINTER(_Sys)
         lib.orc_stencil_weights.argtypes = [ctypes.c_double, _P]
         lib.orc_sigma.argtypes = [S, _P, _P]
@@ -99,8 +120,10 @@ def _load():
         lib.orc_philox4x64.restype = None
         lib.orc_normals.argtypes = [S, ctypes.c_ulonglong, ctypes.c_ulonglong, _P]
         lib.orc_normals.restype = None
-        _lib = lib
-    return _lib
+        lib.orc_threads.argtypes = []
+        lib.orc_threads.restype = ctypes.c_int
+        _libs[path] = lib
+    return _libs[path]
 
 
 def _ptr(a):

@@ -256,3 +256,54 @@ def compare_warm_starts(wls, net, modes, start_steps, measure_steps, tol=1e-6, p
                 f"{res['evals_per_step']:.2f} evaluations/step, {res['iterations_per_replica']:.2f} iterations")
     ctx.close()
     return out
+
+
+def trajectory_arms(wls, net, arms, steps, windows, tol=1e-6, precision="fp32", tile=None, precond=False,
+                    max_iter=1000, log=None):
+    """Each warm start runs the whole trajectory of `wls` from the quench for `steps`
+    coupled steps (same initial state, same tiling), timing every step.  arms: list of
+    (name, warm mode, gate).  windows: list of (first, last) step ranges (last
+    exclusive) over which the per-step times are summarised.  Returns
+    {name: {"whole": {...}, "windows": {"a-b": {...}}}} with the mean, median and 95th
+    percentile step time and the mean evaluations per step of each range."""
+    torch = _torch()
+    out = {}
+    for name, mode, gate in arms:
+        ctx = hsf.Context(wls, precision=precision)
+        ctx.set_solver(precond=precond)
+        phi0, w0 = initial_state(ctx, wls)
+        ctx.set_densities(phi0)
+        ctx.set_fields(w0)
+        if tile is not None:
+            ctx.set_tile(tile)
+        if net is not None:
+            ctx.attach_net(net)
+            ctx.set_net_gate(gate)
+        ctx.set_warm(mode)
+        ts = np.empty(steps)
+        evs = np.empty(steps)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(steps):
+            ta = time.perf_counter()
+            _, ev = ctx.step(1, tol=tol, max_iter=max_iter)   # returns after its last status read
+            ts[k] = time.perf_counter() - ta
+            evs[k] = ev
+            if log and k % 500 == 0:
+                log(f"  {name}: step {k}, {1e3 * ts[k]:.2f} ms, {ev} evaluations "
+                    f"({time.perf_counter() - t_start:.1f} s)")
+        torch.cuda.synchronize()
+        ctx.close()
+
+        def summary(a, b):
+            t = ts[a:b]
+            return {"steps": int(b - a), "ms_mean": 1e3 * float(t.mean()), "ms_median": 1e3 * float(np.median(t)),
+                    "ms_p95": 1e3 * float(np.percentile(t, 95)), "evals_per_step": float(evs[a:b].mean())}
+
+        res = {"whole": summary(0, steps),
+               "windows": {f"{a}-{b}": summary(a, min(b, steps)) for a, b in windows if a < steps}}
+        out[name] = res
+        if log:
+            log(f"  {name}: whole run {res['whole']['ms_mean']:.3f} ms/step mean, "
+                f"{res['whole']['evals_per_step']:.2f} evaluations/step")
+    return out

@@ -1096,3 +1096,25 @@ def test_cn_second_order_and_consistent(orc):
     d2 = np.max(np.abs(runs[0.1] - runs[0.05]))
     assert 3.0 < d1 / d2 < 5.0, (d1, d2)
     assert np.max(np.abs(runs[0.05] - phi)) < 0.02 * change, (np.max(np.abs(runs[0.05] - phi)), change)
+
+
+def test_openmp_build_is_bitwise_the_plain_oracle(orc):
+    """The OpenMP build (used only to time the oracle on all host cores) computes exactly
+    the plain oracle's numbers: its parallel loops write disjoint outputs and every sum
+    stays serial."""
+    wl = W.vesicle128_a3b9s(L=12)
+    sys_ = orc.System(L=wl.L, types=wl.types, has_solvent=True, a=wl.a, chi=wl.chi, kappa=wl.kappa, dt=wl.dt,
+                      tau=wl.tau)
+    w = W.random_fields((3,) + sys_.shape, seed=3, amplitude=0.8)
+    rng = np.random.default_rng(4)
+    n = orc.lb_rest_state(sys_) * (1.0 + 0.01 * rng.uniform(-1, 1, size=(19,) + sys_.shape))
+    f = 1e-3 * rng.uniform(-1, 1, size=(3,) + sys_.shape)
+    res = []
+    for par in (False, True):
+        threads = orc.set_parallel(par)
+        assert (threads == 1) if not par else threads >= 1
+        phi, q, qs = orc.evaluate(sys_, w, 0.12, 0.88, with_qs=True)
+        res.append((phi, q, qs) + orc.lb_step(sys_, n, f))
+    orc.set_parallel(False)
+    for a, b in zip(*res):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
