@@ -330,6 +330,9 @@ def main():
     ap.add_argument("--net-widths", default=None, metavar="WIDTHS",
                     help="level widths of the learned warm start's network (e.g. 8,16,24,32; default one level of 16)")
     ap.add_argument("--no-extra", action="store_true", help="skip the 64^3 melt pair and the 48-replica batch")
+    ap.add_argument("--lean", action="store_true",
+                    help="only the main arm (for profiler runs): no oracle comparison, inversion floor, CPU "
+                         "baseline, learned comparison or other configurations")
     ap.add_argument("--lb", default="bgk", choices=["bgk", "mrt"],
                     help="LB collision: BGK, or the MRT scheme with the shear viscosity of the workload's tau, "
                          "the same bulk eigenvalue and the kinetic modes relaxed completely")
@@ -344,6 +347,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.lean:
+        args.no_cpu_baseline = args.no_learned = args.no_extra = True
 
     if args.copy_probe:
         import torch
@@ -410,10 +415,12 @@ def main():
     value = 2 * N * site_evals / elapsed
     kernels, roofline, lb_roofline = rooflines(timing, wls, tile, args.workload) if timing else ({}, None, None)
 
-    err = oracle_error(ctx, wl)
-    log(f"# error against the oracle at the final fields: {err['max_rel']:.2e}")
-    floor = inversion_floor(ctx, wls, precond)
-    log(f"# inversion floor: {floor['residual_reached']}")
+    err = floor = None
+    if not args.lean:
+        err = oracle_error(ctx, wl)
+        log(f"# error against the oracle at the final fields: {err['max_rel']:.2e}")
+        floor = inversion_floor(ctx, wls, precond)
+        log(f"# inversion floor: {floor['residual_reached']}")
 
     cpu = None
     if not args.no_cpu_baseline:

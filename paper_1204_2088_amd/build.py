@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhsf.so")
-SOURCES = ["api.hip", "prop_block.hip", "ctl.hip", "dyn.hip", "obs.hip", "cn.hip", "net.hip", "net_kernels.hip",
+SOURCES = ["api.hip", "prop_block.hip", "prop_stream.hip", "ctl.hip", "dyn.hip", "obs.hip", "cn.hip", "net.hip", "net_kernels.hip",
            "static_eval.hip"]
 ARCH = os.environ.get("HSF_OFFLOAD_ARCH", "gfx950")
 

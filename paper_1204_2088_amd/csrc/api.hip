@@ -284,8 +284,9 @@ void tile_blocks(const hsf_ctx *c, const TileCfg &t, std::vector<int> &blk_rep, 
     blk_first.clear();
     for (int r = 0; r < c->n_rep; ++r) {
         const Rep &R = c->reps[r];
-        const long long nb = (long long)((R.Lx + t.cx - 1) / t.cx) * ((R.Ly + t.cy - 1) / t.cy) *
-                             ((R.Lz + t.cz - 1) / t.cz);
+        const long long nb = tile_is_stream(t) ? stream_blocks(t, R.Lx, R.Ly, R.Lz)
+                                               : (long long)((R.Lx + t.cx - 1) / t.cx) * ((R.Ly + t.cy - 1) / t.cy) *
+                                                     ((R.Lz + t.cz - 1) / t.cz);
         blk_first.push_back((int)blk_rep.size());
         for (long long b = 0; b < nb; ++b) blk_rep.push_back(r);
     }
@@ -296,7 +297,10 @@ bool tile_known(const TileCfg &t)
 {
 #define HSF_EQ(CX, CY, CZ, K) \
     if (t.cx == CX && t.cy == CY && t.cz == CZ && t.k == K) return true;
+#define HSF_EQS(H, CZ, K) HSF_EQ(64, H, CZ, K)
     HSF_TILE_CONFIGS(HSF_EQ)
+    HSF_STREAM_CONFIGS(HSF_EQS)
+#undef HSF_EQS
 #undef HSF_EQ
     return false;
 }
@@ -363,9 +367,37 @@ void run_eval_paired(hsf_ctx *c, int use_alpha, int final_mode, double *out, con
                            b.Gp[parity], c->acc, final_mode, c->phi, d, out, c->part, c->partG, 2, t.a, t.b);
 }
 
+// Streaming tilings: field factors, ceil(N/K) forward launches, the Q reduction and
+// ceil(N/K) backward launches (steps N, N - K, ...; the last one normalises).
+template <typename real>
+void run_eval_stream(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d, int sums)
+{
+    PropBufs<real> b = bufs<real>(c);
+    const int N = c->ch.N, K = c->tile.k;
+    {
+        Timed t(c, HSF_K_PREP);
+        launch_field_exp<real>(c->stream, c->plan, c->rep_d, c->st_d, c->ch, c->w, c->d, use_alpha, b.E, t.a, t.b);
+    }
+    for (int s0 = 0; s0 < N; s0 += K) {
+        Timed t(c, HSF_K_FWD);
+        launch_fwd_stream<real>(c->tile, c->stream, c->tplan, c->rep_d, c->st_d, c->ch, s0, std::min(K, N - s0), b,
+                                c->partG, sums, t.a, t.b);
+    }
+    launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_Q, c->ch, c->partG, 0.0, 0,
+                      c->st_hd);
+    int parity = 0;
+    for (int s_hi = N; s_hi >= 1; s_hi -= K) {
+        Timed t(c, HSF_K_BWD);
+        launch_bwd_stream<real>(c->tile, c->stream, c->tplan, c->rep_d, c->st_d, c->ch, s_hi, std::min(K, s_hi), b,
+                                b.Gp[parity ^ 1], b.Gp[parity], final_mode, c->phi, d, out, c->part, t.a, t.b);
+        parity ^= 1;
+    }
+}
+
 template <typename real>
 void run_eval(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d, int sums)
 {
+    if (tile_is_stream(c->tile)) return run_eval_stream<real>(c, use_alpha, final_mode, out, d, sums);
     if (c->tile.k < 0 && c->ch.N >= 2) return run_eval_paired<real>(c, use_alpha, final_mode, out, d, sums);
     PropBufs<real> b = bufs<real>(c);
     const int N = c->ch.N, K = std::max(1, c->tile.k);
@@ -891,7 +923,10 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
 #define HSF_SIZE(CX, CY, CZ, K)                                             \
     tile_blocks(c, TileCfg{CX, CY, CZ, K}, br, bf);                         \
     c->max_tile_blocks = std::max(c->max_tile_blocks, (int)br.size());
+#define HSF_SIZES(H, CZ, K) HSF_SIZE(64, H, CZ, K)
         HSF_TILE_CONFIGS(HSF_SIZE)
+        HSF_STREAM_CONFIGS(HSF_SIZES)
+#undef HSF_SIZES
 #undef HSF_SIZE
     }
     {
@@ -1346,7 +1381,10 @@ int hsf_autotune(hsf_ctx *c, int reps, double *best_ms)
     int rc = HSF_OK;
     std::vector<TileCfg> cands;
 #define HSF_CAND(CX, CY, CZ, K) cands.push_back(TileCfg{CX, CY, CZ, K});
+#define HSF_CANDS(H, CZ, K) HSF_CAND(64, H, CZ, K)
     HSF_TILE_CONFIGS(HSF_CAND)
+    HSF_STREAM_CONFIGS(HSF_CANDS)
+#undef HSF_CANDS
 #undef HSF_CAND
     for (const TileCfg &t : cands) {
         if (tile_lds_bytes(t, real_size(c)) > c->lds_limit) continue;

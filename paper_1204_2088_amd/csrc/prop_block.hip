@@ -486,13 +486,47 @@ __device__ __forceinline__ void plane_sums(const real *__restrict__ f, int x, in
     a2 = (pm[xm] + pm[xp]) + (pp[xm] + pp[xp]);
 }
 
-// The stencil at the sites (x, y, z0 + j), j < nz (<= CZ), of f into S[j].
-template <typename real, int CZ>
+// The same for tilings whose rows are 64 sites wide (a wavefront's lanes are consecutive x
+// of one row): 3 loads per plane instead of 9.  The x neighbours come from the adjacent
+// lanes; a lane whose neighbour lies outside the wavefront's row or across the box's
+// periodic edge loads it.  Same values summed in the same order as plane_sums.
+template <typename real>
+__device__ __forceinline__ void plane_sums_x64(const real *__restrict__ f, int x, int y, int z, int Lx, int Ly,
+                                               real &a0, real &a1, real &a2)
+{
+    const int lane = (int)threadIdx.x & 63;
+    const int ym = wrap1(y - 1, Ly), yp = wrap1(y + 1, Ly);
+    const real *p0 = f + ((long long)z * Ly + y) * Lx;
+    const real *pm = f + ((long long)z * Ly + ym) * Lx;
+    const real *pp = f + ((long long)z * Ly + yp) * Lx;
+    const real c = p0[x], m = pm[x], p = pp[x];
+    real cl = from_left(c), ml = from_left(m), pl = from_left(p);
+    real cr = from_right(c), mr = from_right(m), pr = from_right(p);
+    if (lane == 0 || x == 0) {
+        const int xm = wrap1(x - 1, Lx);
+        cl = p0[xm];
+        ml = pm[xm];
+        pl = pp[xm];
+    }
+    if (lane == 63 || x == Lx - 1) {
+        const int xp = wrap1(x + 1, Lx);
+        cr = p0[xp];
+        mr = pm[xp];
+        pr = pp[xp];
+    }
+    a0 = c;
+    a1 = (cl + cr) + (m + p);
+    a2 = (ml + mr) + (pl + pr);
+}
+
+// The stencil at the sites (x, y, z0 + j), j < nz (<= CZ), of f into S[j].  X64: rows of
+// 64 lanes (plane_sums_x64); every lane of a row must take part.
+template <typename real, int CZ, bool X64 = false>
 __device__ __forceinline__ void column_stencil(const real *__restrict__ f, int x, int y, int z0, int nz, const Rep &R,
                                                real *S)
 {
     const real c0 = (real)R.c[0], c1 = (real)R.c[1], c2 = (real)R.c[2], c3 = (real)R.c[3];
-    if (CZ == 1) {
+    if (CZ == 1 && !X64) {
         S[0] = stencil27<real>(f, x, y, z0, R.Lx, R.Ly, R.Lz, c0, c1, c2, c3);
         return;
     }
@@ -505,10 +539,16 @@ __device__ __forceinline__ void column_stencil(const real *__restrict__ f, int x
 #pragma unroll
     for (int q = 0; q < CZ + 2; ++q) {
         if (CZ <= 2) {
-            plane_sums<real>(f, x, y, wrap1(min(z0 - 1 + q, z0 + nz), R.Lz), R.Lx, R.Ly, a0[q], a1[q], a2[q]);
+            const int zq = wrap1(min(z0 - 1 + q, z0 + nz), R.Lz);
+            if (X64) plane_sums_x64<real>(f, x, y, zq, R.Lx, R.Ly, a0[q], a1[q], a2[q]);
+            else plane_sums<real>(f, x, y, zq, R.Lx, R.Ly, a0[q], a1[q], a2[q]);
         } else {
             a0[q] = a1[q] = a2[q] = (real)0;
-            if (q <= nz + 1) plane_sums<real>(f, x, y, wrap1(z0 - 1 + q, R.Lz), R.Lx, R.Ly, a0[q], a1[q], a2[q]);
+            // the plane index is the same for every lane of a row, so a row stays together
+            if (q <= nz + 1) {
+                if (X64) plane_sums_x64<real>(f, x, y, wrap1(z0 - 1 + q, R.Lz), R.Lx, R.Ly, a0[q], a1[q], a2[q]);
+                else plane_sums<real>(f, x, y, wrap1(z0 - 1 + q, R.Lz), R.Lx, R.Ly, a0[q], a1[q], a2[q]);
+            }
         }
     }
 #pragma unroll
@@ -566,7 +606,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(StepInfo si, const int *_
 #pragma unroll
             for (int j = 0; j < CZ; ++j) S[j] = (real)R.csum;
         } else {
-            column_stencil<real, CZ>(G + (long long)(s - 2) * V, x, y, z0, nz, R, S);
+            column_stencil<real, CZ, CX == 64>(G + (long long)(s - 2) * V, x, y, z0, nz, R, S);
         }
         if (CZ <= 2 && !fuse_exp) {   // short columns: the field factors join the stencil's loads
 #pragma unroll
@@ -665,7 +705,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_direct(StepInfo si, const int *_
 #pragma unroll
             for (int j = 0; j < CZ; ++j) S[j] = (real)R.csum;
         } else {
-            column_stencil<real, CZ>(gin + R.site_off, x, y, z0, nz, R, S);
+            column_stencil<real, CZ, CX == 64>(gin + R.site_off, x, y, z0, nz, R, S);
         }
         if (CZ <= 2 && !FINAL) {   // short columns: all the step's loads go out together
 #pragma unroll
@@ -891,7 +931,7 @@ __device__ __forceinline__ void pair_fwd(const PairInfo &pi, int pb, const int *
 #pragma unroll
             for (int j = 0; j < CZ; ++j) S[j] = (real)R.csum;
         } else {
-            column_stencil<real, CZ>(pi.f_from_pp ? fin + R.site_off : G + (long long)(s - 2) * V, x, y, z0, nz, R, S);
+            column_stencil<real, CZ, CX == 64>(pi.f_from_pp ? fin + R.site_off : G + (long long)(s - 2) * V, x, y, z0, nz, R, S);
         }
         if (CZ <= 2) {
 #pragma unroll
@@ -986,7 +1026,7 @@ __device__ __forceinline__ void pair_bwd(const PairInfo &pi, int pb, const int *
 #pragma unroll
             for (int j = 0; j < CZ; ++j) S[j] = (real)R.csum;
         } else {
-            column_stencil<real, CZ>(gin + R.site_off, x, y, z0, nz, R, S);
+            column_stencil<real, CZ, CX == 64>(gin + R.site_off, x, y, z0, nz, R, S);
         }
         if (CZ <= 2) {
 #pragma unroll

@@ -381,8 +381,9 @@ def test_graph_replays_match_direct_launches(hsf, orc, monkeypatch):
 TILES = [(64, 4, 1, 0), (32, 8, 1, 0), (16, 16, 1, 0), (64, 4, 2, 0), (32, 8, 2, 0), (16, 16, 2, 0), (64, 4, 4, 0),
          (32, 8, 4, 0), (16, 16, 4, 0), (64, 4, 8, 0), (16, 16, 8, 0), (8, 8, 8, 1), (8, 8, 8, 2), (8, 8, 8, 3), (8, 8, 8, 4), (16, 8, 8, 2), (16, 8, 4, 2), (32, 8, 4, 1),
          (32, 4, 4, 2), (64, 4, 2, -1), (32, 8, 2, -1), (16, 16, 2, -1), (32, 8, 4, -1), (16, 16, 4, -1),
-         (16, 16, 8, -1)]
+         (16, 16, 8, -1), (64, 8, 8, 2), (64, 8, 16, 2), (64, 16, 8, 2), (64, 16, 16, 2), (64, 16, 32, 2)]
 PAIRED = [t for t in TILES if t[3] == -1]
+STREAM = [t for t in TILES if t[0] == 64 and t[3] >= 1]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -390,11 +391,16 @@ def test_every_tile_configuration(hsf, orc, precision):
     """Every compiled tiling of the blocked sweeps gives the oracle's densities, on
     boxes that are ragged against every tile and smaller than the halo (N not a
     multiple of k either)."""
-    for L, types in [((17, 18, 20), W.chain(3, 4)), ((5, 3, 9), W.chain(2, 3)), ((40, 9, 6), W.chain(4, 4))]:
-        wl = small_melt(L=L, types=types, precision=precision)
+    cases = [small_melt(L=L, types=types, precision=precision) for L, types in
+             [((17, 18, 20), W.chain(3, 4)), ((5, 3, 9), W.chain(2, 3)), ((40, 9, 6), W.chain(4, 4)),
+              ((70, 23, 11), W.chain(1, 3))]]
+    cases.append(small_solution(L=(12, 10, 14), precision=precision))
+    for wl in cases:
+        L = wl.L
         phi0 = W.initial_composition(wl)
         w = fields_for(wl, seed=9, amp=1.2)
-        ref, qref = orc.evaluate(osys(orc, wl), w, 1.0, 0.0)
+        pbar = phi0[:2].sum(0).mean()
+        ref, qref = orc.evaluate(osys(orc, wl), w, pbar, phi0[2].mean() if wl.has_solvent else 0.0)
         ctx = hsf.Context(wl)
         ctx.set_densities(phi0.ravel())
         ctx.set_fields(w.ravel())
