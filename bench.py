@@ -43,9 +43,14 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {}
 METRIC = "propagator site·bead updates/s + LB MLUPS; step time learned vs plain at 1e-6"
 
-# LB bytes per site of the fused collide-and-stream (FP64 populations): 19 read and 19
-# written, the force read, density and velocity written.
-LB_BYTES_PER_SITE = 8 * (2 * 19 + 3 + 4)
+def lb_bytes_per_site(wl):
+    """Algorithmic bytes per site of the fused collide-and-stream: 19 populations read and
+    19 written, the force read, density and velocity written, s bytes each: 360 B with FP64
+    storage; 180 B with the FP32 storage of the FP32 contexts (the kernel's FP64 force,
+    density and velocity make its own compulsory traffic 208 B, so this figure is the
+    stricter one)."""
+    s = 4 if wl.precision == "fp32" else 8
+    return s * (2 * 19 + 3 + 4)
 
 
 def bytes_per_update(wl):
@@ -291,9 +296,11 @@ def rooflines(timing, wls, tile, workload):
                      "bytes_per_update": b_unit, "updates_per_launch": units, "avg_launch_us": prop[dom]["avg_us"]}
     if "lb" in kernels:
         avg_s = kernels["lb"]["avg_us"] * 1e-6
-        achieved = LB_BYTES_PER_SITE * V_total / avg_s / 1e9
+        lb_b = lb_bytes_per_site(wl)
+        achieved = lb_b * V_total / avg_s / 1e9
         lb_roof = {"bound": "hbm", "kernel": "k_lb", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                   "frac": achieved / HBM_PEAK_GBS, "bytes_per_site": LB_BYTES_PER_SITE,
+                   "frac": achieved / HBM_PEAK_GBS, "bytes_per_site": lb_b,
+                   "storage": "fp32 deviations from the rest state" if wl.precision == "fp32" else "fp64",
                    "mlups": V_total / avg_s / 1e6, "avg_launch_us": kernels["lb"]["avg_us"]}
     return kernels, prop_roof, lb_roof
 

@@ -78,7 +78,10 @@ enum { HSF_HOST = 0, HSF_DEVICE = 1 };
 
 /* Precision of the propagators (E = exp(-w), G_s, G+_s).  Reductions (Q,
  * dot products, residual), the density normalisation, the fields and all
- * other phases stay FP64 in both modes. */
+ * other arithmetic stay FP64 in both modes.  With HSF_FP32 the LB populations are
+ * also stored in FP32, as their deviations n_i - w_i from the rest state (arithmetic
+ * in FP64, 180 instead of 360 bytes of traffic per site and step); hsf_set_lb and
+ * hsf_get_lb still take FP64 values. */
 enum { HSF_FP64 = 0, HSF_FP32 = 1 };
 
 /* Starting guess of an inversion. */
@@ -246,7 +249,9 @@ int hsf_invert(hsf_ctx *ctx, double tol, int max_iter, int warm, hsf_invert_stat
  * be NULL. */
 int hsf_mu_force(hsf_ctx *ctx, double *mu, double *force, int where);
 
-/* LB populations of all replicas, per replica [19][V]. */
+/* LB populations of all replicas, per replica [19][V], FP64 at this boundary.  With
+ * FP32 storage (HSF_FP32 contexts) hsf_set_lb rounds each deviation n_i - w_i to FP32
+ * (and allocates a staging buffer of 19 T doubles at the first call with host memory). */
 int hsf_set_lb(hsf_ctx *ctx, const double *n, int where);
 int hsf_get_lb(hsf_ctx *ctx, double *n, int where);
 

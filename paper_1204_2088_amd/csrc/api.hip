@@ -60,7 +60,11 @@ struct hsf_ctx {
     // FP64 state and work arrays
     double *w = nullptr, *phi = nullptr, *phi_tmp = nullptr, *mu = nullptr, *eval_out = nullptr;
     double *g = nullptr, *gt = nullptr, *d = nullptr, *acc = nullptr;
-    double *nA = nullptr, *nB = nullptr, *rho = nullptr, *u = nullptr, *force = nullptr, *uin = nullptr;
+    // LB populations: FP64, or with FP32 propagators FP32 deviations from the rest state
+    void *nA = nullptr, *nB = nullptr;
+    bool lb32 = false;
+    double *lb_stage = nullptr;      // FP64 staging of the populations (FP32 storage; allocated at first use)
+    double *rho = nullptr, *u = nullptr, *force = nullptr, *uin = nullptr;
     double *part = nullptr, *partG = nullptr;
     int part_cap = 0;                  // doubles in `part`
     double *obs = nullptr;             // observables scratch; results in its last 3 n_rep doubles
@@ -516,6 +520,13 @@ int warm_start(hsf_ctx *c, int warm)
     return HSF_OK;
 }
 
+// FP64 staging buffer for the FP32 population storage (set/get and checkpoints).
+int lb_staging(hsf_ctx *c)
+{
+    if (c->lb_stage) return HSF_OK;
+    return dalloc(c, (void **)&c->lb_stage, sizeof(double) * 19 * c->T);
+}
+
 // Keep the latest inversion's result and target for the warm starts of the next ones.
 int commit_history(hsf_ctx *c)
 {
@@ -958,8 +969,9 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     ALLOC(c->gt, sizeof(double) * 2 * T);
     ALLOC(c->d, sizeof(double) * 2 * T);
     ALLOC(c->acc, sizeof(double) * 2 * T);
-    ALLOC(c->nA, sizeof(double) * 19 * T);
-    ALLOC(c->nB, sizeof(double) * 19 * T);
+    c->lb32 = c->precision == HSF_FP32;
+    ALLOC(c->nA, (c->lb32 ? sizeof(float) : sizeof(double)) * 19 * T);
+    ALLOC(c->nB, (c->lb32 ? sizeof(float) : sizeof(double)) * 19 * T);
     ALLOC(c->rho, sizeof(double) * T);
     ALLOC(c->u, sizeof(double) * 3 * T);
     ALLOC(c->uin, sizeof(double) * 3 * T);
@@ -1014,7 +1026,7 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     if (e == hipSuccess) e = hipMemset(c->u, 0, sizeof(double) * 3 * T);
     if (e == hipSuccess) e = hipMemset(c->rho, 0, sizeof(double) * T);
     if (e == hipSuccess) {
-        launch_lb_rest(nullptr, c->plan, c->rep_d, c->nA);
+        launch_lb_rest(nullptr, c->plan, c->rep_d, c->nA, c->lb32);
         e = hipDeviceSynchronize();
     }
     if (e != hipSuccess) {
@@ -1173,13 +1185,35 @@ int hsf_mu_force(hsf_ctx *c, double *mu, double *force, int where)
 int hsf_set_lb(hsf_ctx *c, const double *n, int where)
 {
     if (!c) return HSF_EINVAL;
-    return copy_in(c, c->nA, n, (size_t)19 * c->T, where);
+    if (!c->lb32) return copy_in(c, (double *)c->nA, n, (size_t)19 * c->T, where);
+    const double *src = n;
+    if (where == HSF_HOST) {
+        int rc = lb_staging(c);
+        if (rc == HSF_OK) rc = copy_in(c, c->lb_stage, n, (size_t)19 * c->T, where);
+        if (rc) return rc;
+        src = c->lb_stage;
+    } else if (where != HSF_DEVICE || !n) {
+        return fail(c, HSF_EINVAL, "bad populations pointer or location");
+    }
+    launch_lb_convert(c->stream, c->plan, c->rep_d, true, src, c->nA);
+    HIPCHK(c, hipGetLastError());
+    return HSF_OK;
 }
 
 int hsf_get_lb(hsf_ctx *c, double *n, int where)
 {
     if (!c) return HSF_EINVAL;
-    return copy_out(c, n, c->nA, (size_t)19 * c->T, where);
+    if (!c->lb32) return copy_out(c, n, (const double *)c->nA, (size_t)19 * c->T, where);
+    if (where == HSF_DEVICE && n) {
+        launch_lb_convert(c->stream, c->plan, c->rep_d, false, c->nA, n);
+        HIPCHK(c, hipGetLastError());
+        return HSF_OK;
+    }
+    int rc = lb_staging(c);
+    if (rc) return rc;
+    launch_lb_convert(c->stream, c->plan, c->rep_d, false, c->nA, c->lb_stage);
+    HIPCHK(c, hipGetLastError());
+    return copy_out(c, n, c->lb_stage, (size_t)19 * c->T, where);
 }
 
 int hsf_lb_advance(hsf_ctx *c, int n_steps, const double *force, int where)
@@ -1194,7 +1228,7 @@ int hsf_lb_advance(hsf_ctx *c, int n_steps, const double *force, int where)
     for (int k = 0; k < n_steps; ++k) {
         {
             Timed t(c, HSF_K_LB);
-            launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, f, c->rho, c->u, (c->noise & HSF_NOISE_LB) != 0,
+            launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, c->lb32, f, c->rho, c->u, (c->noise & HSF_NOISE_LB) != 0,
                       c->noise_step, c->lb_all, t.a, t.b);
         }
         std::swap(c->nA, c->nB);
@@ -1274,7 +1308,7 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
             launch_force(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->mu, c->force);
             {
                 Timed t(c, HSF_K_LB);
-                launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, c->force, c->rho, c->u,
+                launch_lb(c->stream, c->plan, c->rep_d, c->nA, c->nB, c->lb32, c->force, c->rho, c->u,
                           (c->noise & HSF_NOISE_LB) != 0, c->noise_step, c->lb_all, t.a, t.b, c->bad_hd);
             }
             uu = c->u;
@@ -1542,7 +1576,14 @@ int hsf_get_state(hsf_ctx *c, void *buf, long long size)
     HIPCHK(c, hipMemcpy(p, c->st_d, sizeof(RepState) * c->n_rep, hipMemcpyDeviceToHost));
     p += sizeof(RepState) * c->n_rep;
     const size_t nf = (size_t)c->ch.nsp * c->T;
-    const double *src[] = {c->phi, c->w, c->nA, c->w_hist[0], c->w_hist[1], c->phi_hist[0], c->phi_hist[1]};
+    const double *lb = (const double *)c->nA;
+    if (c->lb32) {   // the populations as FP64 values (exact: every FP32 deviation is a double)
+        if ((rc = lb_staging(c))) return rc;
+        launch_lb_convert(c->stream, c->plan, c->rep_d, false, c->nA, c->lb_stage);
+        if ((rc = sync(c))) return rc;
+        lb = c->lb_stage;
+    }
+    const double *src[] = {c->phi, c->w, lb, c->w_hist[0], c->w_hist[1], c->phi_hist[0], c->phi_hist[1]};
     const size_t cnt[] = {nf, nf, (size_t)19 * c->T, nf, nf, nf, nf};
     for (int k = 0; k < 7; ++k) {
         HIPCHK(c, hipMemcpy(p, src[k], sizeof(double) * cnt[k], hipMemcpyDeviceToHost));
@@ -1574,11 +1615,17 @@ int hsf_set_state(hsf_ctx *c, const void *buf, long long size)
     memcpy(c->st_h, p, sizeof(RepState) * c->n_rep);
     p += sizeof(RepState) * c->n_rep;
     const size_t nf = (size_t)c->ch.nsp * c->T;
-    double *dst[] = {c->phi, c->w, c->nA, c->w_hist[0], c->w_hist[1], c->phi_hist[0], c->phi_hist[1]};
+    if (c->lb32 && (rc = lb_staging(c))) return rc;
+    double *dst[] = {c->phi, c->w, c->lb32 ? c->lb_stage : (double *)c->nA, c->w_hist[0], c->w_hist[1],
+                     c->phi_hist[0], c->phi_hist[1]};
     const size_t cnt[] = {nf, nf, (size_t)19 * c->T, nf, nf, nf, nf};
     for (int k = 0; k < 7; ++k) {
         HIPCHK(c, hipMemcpy(dst[k], p, sizeof(double) * cnt[k], hipMemcpyHostToDevice));
         p += sizeof(double) * cnt[k];
+    }
+    if (c->lb32) {
+        launch_lb_convert(c->stream, c->plan, c->rep_d, true, c->lb_stage, c->nA);
+        if ((rc = sync(c))) return rc;
     }
     c->n_hist = h.n_hist;
     c->fields_set = h.fields_set;

@@ -20,6 +20,15 @@ constexpr int kCz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, 
 // Weights of eq. 11.
 __host__ __device__ constexpr double lb_w(int q) { return q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
+// LB populations in memory: FP64 values n_i, or (FP32 storage) the deviations n_i - w_i
+// from the rest state, whose magnitude is that of the flow and density perturbations, so
+// FP32 keeps about 7 significant digits of the perturbation rather than of n_i.  All
+// arithmetic is FP64.
+__device__ __forceinline__ double pop_load(const double *p, long long k, int) { return p[k]; }
+__device__ __forceinline__ double pop_load(const float *p, long long k, int q) { return lb_w(q) + (double)p[k]; }
+__device__ __forceinline__ void pop_store(double *p, long long k, int, double v) { p[k] = v; }
+__device__ __forceinline__ void pop_store(float *p, long long k, int q, double v) { p[k] = (float)(v - lb_w(q)); }
+
 __device__ __forceinline__ void site_xyz(const Rep &R, long long i, int &x, int &y, int &z)
 {
     x = (int)(i % R.Lx);
@@ -225,10 +234,10 @@ __device__ __forceinline__ void lb_mode_noise(const Rep &R, int r, long long i, 
 // the mode noise of eq. 13 before streaming.  MODE: HSF_LB_BGK or HSF_LB_MRT when every
 // replica uses that collision (each variant needs only its own registers), -1 for a batch
 // that mixes them (chosen per replica).
-template <bool NOISE, int MODE>
+template <bool NOISE, int MODE, typename pop_t>
 __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, const int *__restrict__ blk_first,
-                                               const Rep *__restrict__ rep, const double *__restrict__ nsrc,
-                                               double *__restrict__ ndst, const double *__restrict__ f,
+                                               const Rep *__restrict__ rep, const pop_t *__restrict__ nsrc,
+                                               pop_t *__restrict__ ndst, const double *__restrict__ f,
                                                double *__restrict__ rho_out, double *__restrict__ u_out,
                                                unsigned long long step, int *__restrict__ bad)
 {
@@ -241,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, 
     const long long base = 19LL * R.site_off, vo = 3LL * R.site_off;
     double n[19];
 #pragma unroll
-    for (int q = 0; q < 19; ++q) n[q] = nsrc[base + q * V + i];
+    for (int q = 0; q < 19; ++q) n[q] = pop_load(nsrc, base + q * V + i, q);
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (f) {
         fx = f[vo + i];
@@ -277,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, 
             ns[q] = n[q] - om * (n[q] - neq) + F;
             if (!NOISE) {   // stored at once: fewer live registers
                 const int xd = wrap1(x + kCx[q], R.Lx), yd = wrap1(y + kCy[q], R.Ly), zd = wrap1(z + kCz[q], R.Lz);
-                ndst[base + q * V + sidx(R, xd, yd, zd)] = ns[q];
+                pop_store(ndst, base + q * V + sidx(R, xd, yd, zd), q, ns[q]);
             }
         }
     }
@@ -286,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, 
 #pragma unroll
         for (int q = 0; q < 19; ++q) {
             const int xd = wrap1(x + kCx[q], R.Lx), yd = wrap1(y + kCy[q], R.Ly), zd = wrap1(z + kCz[q], R.Lz);
-            ndst[base + q * V + sidx(R, xd, yd, zd)] = ns[q];
+            pop_store(ndst, base + q * V + sidx(R, xd, yd, zd), q, ns[q]);
         }
     }
     rho_out[R.site_off + i] = rho;
@@ -384,16 +393,35 @@ __global__ __launch_bounds__(kBlock) void k_cd_noise(const int *__restrict__ blk
 }
 
 // Fluid at rest with density 1: n_i = w_i.
+template <typename pop_t>
 __global__ __launch_bounds__(kBlock) void k_lb_rest(const int *__restrict__ blk_rep,
                                                     const int *__restrict__ blk_first, const Rep *__restrict__ rep,
-                                                    double *__restrict__ n)
+                                                    pop_t *__restrict__ n)
 {
     const SiteRef sr = site_ref(blk_rep, blk_first);
     const Rep &R = rep[sr.r];
     const long long V = R.V, i = sr.i;
     if (i >= V) return;
 #pragma unroll
-    for (int q = 0; q < 19; ++q) n[19LL * R.site_off + q * V + i] = lb_w(q);
+    for (int q = 0; q < 19; ++q) pop_store(n, 19LL * R.site_off + q * V + i, q, lb_w(q));
+}
+
+// FP64 populations to the FP32 deviation storage (to_f32) or back.
+__global__ __launch_bounds__(kBlock) void k_lb_convert(const int *__restrict__ blk_rep,
+                                                       const int *__restrict__ blk_first,
+                                                       const Rep *__restrict__ rep, int to_f32,
+                                                       const void *__restrict__ src, void *__restrict__ dst)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    if (i >= V) return;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        const long long k = 19LL * R.site_off + q * V + i;
+        if (to_f32) pop_store((float *)dst, k, q, ((const double *)src)[k]);
+        else ((double *)dst)[k] = pop_load((const float *)src, k, q);
+    }
 }
 
 void launch_mu(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi, const double *w,
@@ -408,19 +436,38 @@ void launch_force(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const 
     hipLaunchKernelGGL(k_force, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch, phi, mu, f);
 }
 
-void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc, double *ndst, const double *f,
-               double *rho, double *u, bool noise, unsigned long long step, int lb_mode, hipEvent_t e0,
-               hipEvent_t e1, int *bad)
+template <typename pop_t>
+static void launch_lb_t(hipStream_t s, const Plan &p, const Rep *rep, const pop_t *nsrc, pop_t *ndst,
+                        const double *f, double *rho, double *u, bool noise, unsigned long long step, int lb_mode,
+                        hipEvent_t e0, hipEvent_t e1, int *bad)
 {
     auto pick = [&](auto bgk, auto mrt, auto mixed) { return lb_mode == HSF_LB_BGK ? bgk : lb_mode == HSF_LB_MRT ? mrt : mixed; };
-    auto kern = noise ? pick(k_lb<true, HSF_LB_BGK>, k_lb<true, HSF_LB_MRT>, k_lb<true, -1>)
-                      : pick(k_lb<false, HSF_LB_BGK>, k_lb<false, HSF_LB_MRT>, k_lb<false, -1>);
+    auto kern = noise ? pick(k_lb<true, HSF_LB_BGK, pop_t>, k_lb<true, HSF_LB_MRT, pop_t>, k_lb<true, -1, pop_t>)
+                      : pick(k_lb<false, HSF_LB_BGK, pop_t>, k_lb<false, HSF_LB_MRT, pop_t>, k_lb<false, -1, pop_t>);
     if (e0)
         hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep,
                               nsrc, ndst, f, rho, u, step, bad);
     else
         hipLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, nsrc, ndst, f,
                            rho, u, step, bad);
+}
+
+void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const void *nsrc, void *ndst, bool f32, const double *f,
+               double *rho, double *u, bool noise, unsigned long long step, int lb_mode, hipEvent_t e0,
+               hipEvent_t e1, int *bad)
+{
+    if (f32)
+        launch_lb_t<float>(s, p, rep, (const float *)nsrc, (float *)ndst, f, rho, u, noise, step, lb_mode, e0, e1,
+                           bad);
+    else
+        launch_lb_t<double>(s, p, rep, (const double *)nsrc, (double *)ndst, f, rho, u, noise, step, lb_mode, e0,
+                            e1, bad);
+}
+
+void launch_lb_convert(hipStream_t s, const Plan &p, const Rep *rep, bool to_f32, const void *src, void *dst)
+{
+    hipLaunchKernelGGL(k_lb_convert, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep,
+                       to_f32 ? 1 : 0, src, dst);
 }
 
 void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi, const double *mu,
@@ -446,9 +493,14 @@ void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const dou
                            phi_out, (const double *)noise_flux, diff_scale, bad);
 }
 
-void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n)
+void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, void *n, bool f32)
 {
-    hipLaunchKernelGGL(k_lb_rest, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, n);
+    if (f32)
+        hipLaunchKernelGGL(k_lb_rest<float>, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep,
+                           (float *)n);
+    else
+        hipLaunchKernelGGL(k_lb_rest<double>, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep,
+                           (double *)n);
 }
 
 }  // namespace hsf

@@ -136,9 +136,12 @@ void launch_force(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const 
 // noise: draw the thermal noise of this step (eq. 13 for LB, eq. 5 for CD) with
 // generator step word `step`
 // lb_mode: the collision of every replica (HSF_LB_BGK or HSF_LB_MRT), or -1 when mixed
-void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc, double *ndst,
+// f32: populations stored as FP32 deviations n_i - w_i from the rest state (else FP64 n_i)
+void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const void *nsrc, void *ndst, bool f32,
                const double *f, double *rho, double *u, bool noise, unsigned long long step, int lb_mode,
                hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, int *bad = nullptr);
+// FP64 populations (field layout of the boundary) to the FP32 deviation storage, or back
+void launch_lb_convert(hipStream_t s, const Plan &p, const Rep *rep, bool to_f32, const void *src, void *dst);
 // bad (may be null): set to 1 by the LB and CD kernels when a moment or an updated density is
 // not finite (so that a coupled step can be rolled back)
 // noise_flux: scratch for the composition noise's bond fluxes (3 nsp T doubles), or null
@@ -146,7 +149,7 @@ void launch_lb(hipStream_t s, const Plan &p, const Rep *rep, const double *nsrc,
 void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi,
                const double *mu, const double *u, double *phi_out, double *noise_flux, unsigned long long step,
                hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, double diff_scale = 1.0, int *bad = nullptr);
-void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, double *n);
+void launch_lb_rest(hipStream_t s, const Plan &p, const Rep *rep, void *n, bool f32);
 
 // vector kernels of the Crank-Nicolson Newton-Krylov solve (cn.hip); vectors of n doubles
 constexpr int kMaxKrylov = 64;
