@@ -305,6 +305,42 @@ def rooflines(timing, wls, tile, workload):
     return kernels, prop_roof, lb_roof
 
 
+def drift_arm(hsf, torch, steps, log):
+    """The 64^3 A8B8 melt pair (tau 0.6 and 1.5) run twice from the same quench, with FP32
+    propagators (residual 1e-6) and with FP64 ones (residual 1e-8): after every step, the
+    largest density difference between the two trajectories on the 32^3 crop [0, 32)^3, per
+    replica, relative to the largest FP64 density there."""
+    from paper_1204_2088_amd import workloads as W
+    runs = {}
+    for prec in ("fp32", "fp64"):
+        wls = make_workloads("melt64_a8b8", prec)
+        ctx = hsf.Context(wls, stream=torch.cuda.current_stream())
+        ctx.set_densities(np.concatenate([W.initial_composition(w).ravel() for w in wls]))
+        ctx.autotune(reps=2)
+        runs[prec] = (ctx, wls[0].tol)
+    wl = make_workloads("melt64_a8b8", "fp64")[0]
+    V, shp = wl.V, (2,) + wl.shape
+    err = np.zeros((steps, 2))
+    t0 = time.perf_counter()
+    for k in range(steps):
+        phis = {}
+        for prec, (ctx, tol) in runs.items():
+            ctx.step(1, tol=tol, max_iter=4000)
+            phis[prec] = ctx.get_densities()
+        for r in range(2):
+            a = phis["fp32"][2 * V * r:2 * V * (r + 1)].reshape(shp)[:, :32, :32, :32]
+            b = phis["fp64"][2 * V * r:2 * V * (r + 1)].reshape(shp)[:, :32, :32, :32]
+            err[k, r] = np.max(np.abs(a - b)) / np.max(np.abs(b))
+        if k % 500 == 0:
+            log(f"# drift step {k}: {err[k].tolist()} ({time.perf_counter() - t0:.1f} s)")
+    for ctx, _ in runs.values():
+        ctx.close()
+    marks = [s for s in (1, 10, 100, 500, 1000, 1500, 2000) if s <= steps]
+    return {"steps": steps, "crop": "[0, 32)^3", "replicas": "tau 0.6, tau 1.5",
+            "max": err.max(axis=0).tolist(), "at_step": {str(m): err[m - 1].tolist() for m in marks},
+            "argmax_step": (err.argmax(axis=0) + 1).tolist()}
+
+
 def short_run(hsf, torch, name, steps, warmup, log, precond):
     """A shorter run of another configuration: throughput, step time and rooflines."""
     wls = make_workloads(name, "fp32")
@@ -346,6 +382,8 @@ def main():
     ap.add_argument("--noise", type=float, default=None, metavar="OMEGA",
                     help="thermal noise in both the compositions (eq. 5) and the LB modes (eq. 13) "
                          "with noise scaling parameter OMEGA (the paper uses 400)")
+    ap.add_argument("--drift-steps", type=int, default=0,
+                    help="only compare FP32 and FP64 trajectories of the 64^3 melt pair over this many steps")
     ap.add_argument("--cn-arm", action="store_true", help="also time Crank-Nicolson steps (dt --cn-dt)")
     ap.add_argument("--cn-dt", type=float, default=0.4, help="time step of the Crank-Nicolson arm")
     ap.add_argument("--net-probe", default=None, metavar="WIDTHS",
@@ -391,6 +429,14 @@ def main():
             torch.cuda.synchronize()
             out[f"{name}_ms"] = 1e3 * (time.perf_counter() - t0) / reps
         print(json.dumps(out))
+        return
+
+    if args.drift_steps:
+        import torch
+        from paper_1204_2088_amd import hsf
+        torch.cuda.set_device(0)
+        print(json.dumps({"fp32_vs_fp64_trajectory": drift_arm(hsf, torch, args.drift_steps,
+                                                               lambda m: print(m, file=sys.stderr, flush=True))}))
         return
 
     if args.gpus != 1:

@@ -50,6 +50,7 @@ struct hsf_ctx {
     Plan plan;                       // site plan: kBlock consecutive sites per block
     TileCfg tile{8, 8, 8, 2};        // propagator tile configuration in use
     Plan tplan;                      // tile plan of `tile`
+    std::vector<int> tile_blk_first; // host copy of the tile plan's first block per replica
     int max_tile_blocks = 0;         // over every configuration (sizes the partials)
     size_t lds_limit = 65536;
     int tuned = 0;
@@ -319,6 +320,7 @@ int set_tile(hsf_ctx *c, const TileCfg &t)
     HIPCHK(c, hipMemcpy(c->tplan.blk_first, bf.data(), sizeof(int) * bf.size(), hipMemcpyHostToDevice));
     c->tplan.nblocks = (int)br.size();
     c->tplan.n_rep = c->n_rep;
+    c->tile_blk_first = bf;
     set_plan_args(c->tplan, c->reps.data(), c->n_rep, bf.data());
     c->tile = t;
     for (auto &g : c->graphs)
@@ -342,23 +344,36 @@ int set_tile(hsf_ctx *c, const TileCfg &t)
 // (the backward lag N mod 2 sees to that), the forward step of bead s runs first exactly
 // when s <= se = (N + N mod 2) / 2, and the backward step N of launch 1 (even N) forms its
 // field factor itself since step 1 is storing them in the same launch.
+// Launch j (1..N) of the paired schedule for chains of N >= 2 beads (host only; the
+// schedule's read and write sets are checked on the CPU through hsf_paired_schedule).
+PairSteps paired_steps(int N, int j)
+{
+    const int lag = N & 1, se = (N + lag) / 2;
+    PairSteps ps{};
+    ps.sf = j;
+    const int sb = N + 1 + lag - j;
+    ps.sb = (sb >= 2 && sb <= N) ? sb : 0;
+    ps.f_late = j > se;
+    ps.f_from_pp = j >= 2 && j - 1 >= se;
+    ps.f_to_pp = j >= se && j < N;
+    ps.g_late = ps.sb && ps.sb <= se;
+    ps.g_exp = ps.sb == N && j == 1;
+    return ps;
+}
+
+// Blocks per replica above which the paired sweeps' last launch does not fold Q itself
+// (every block would re-sum its replica's row of partials): a control launch does.
+constexpr int kFoldQMaxBlocks = 1024;
+
 template <typename real>
 void run_eval_paired(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d, int sums)
 {
     PropBufs<real> b = bufs<real>(c);
-    const int N = c->ch.N, lag = N & 1, se = (N + lag) / 2;
+    const int N = c->ch.N;
     real *Gf[2] = {(real *)c->Gf0, (real *)c->Gf1};
     int parity = 0;
     for (int j = 1; j <= N; ++j) {
-        PairSteps ps{};
-        ps.sf = j;
-        const int sb = N + 1 + lag - j;
-        ps.sb = (sb >= 2 && sb <= N) ? sb : 0;
-        ps.f_late = j > se;
-        ps.f_from_pp = j >= 2 && j - 1 >= se;
-        ps.f_to_pp = j >= se && j < N;
-        ps.g_late = ps.sb && ps.sb <= se;
-        ps.g_exp = ps.sb == N && j == 1;
+        const PairSteps ps = paired_steps(N, j);
         const real *gin = b.Gp[parity ^ 1];
         real *gout = b.Gp[parity];
         if (ps.sb) parity ^= 1;
@@ -366,9 +381,16 @@ void run_eval_paired(hsf_ctx *c, int use_alpha, int final_mode, double *out, con
         launch_pair_block<real>(c->tile, c->stream, c->tplan, c->rep_d, c->st_d, c->ch, ps, b, Gf[(j - 1) & 1],
                                 Gf[j & 1], gin, gout, c->partG, sums, c->w, c->d, use_alpha, t.a, t.b);
     }
+    int most = 0;
+    for (int r = 0; r < c->n_rep; ++r) most = std::max(most, c->tile_blk_first[r + 1] - c->tile_blk_first[r]);
+    const bool fold = most <= kFoldQMaxBlocks;
+    if (!fold)
+        launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_Q, c->ch, c->partG, 0.0, 0,
+                          c->st_hd);
     Timed t(c, HSF_K_BWD);
     launch_bwd_block<real>(c->tile, c->stream, c->tplan, c->rep_d, c->st_d, c->ch, 1, 1, b, b.Gp[parity ^ 1],
-                           b.Gp[parity], c->acc, final_mode, c->phi, d, out, c->part, c->partG, 2, t.a, t.b);
+                           b.Gp[parity], c->acc, final_mode, c->phi, d, out, c->part, c->partG, fold ? 2 : 0, t.a,
+                           t.b);
 }
 
 // Streaming tilings: field factors, ceil(N/K) forward launches, the Q reduction and
@@ -1357,6 +1379,15 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
                                  hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipGetLastError());
     }
+    return HSF_OK;
+}
+
+int hsf_paired_schedule(int n_beads, int launch, int out[7])
+{
+    if (!out || n_beads < 2 || n_beads > HSF_MAX_BEADS || launch < 1 || launch > n_beads) return HSF_EINVAL;
+    const PairSteps ps = paired_steps(n_beads, launch);
+    const int v[7] = {ps.sf, ps.sb, ps.f_late, ps.f_from_pp, ps.f_to_pp, ps.g_late, ps.g_exp};
+    for (int k = 0; k < 7; ++k) out[k] = v[k];
     return HSF_OK;
 }
 

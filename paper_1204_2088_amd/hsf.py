@@ -36,7 +36,7 @@ EXPORTED = [
     "hsf_set_solver", "hsf_get_work", "hsf_set_warm", "hsf_net_create", "hsf_net_destroy",
     "hsf_net_last_error", "hsf_net_set_stream", "hsf_net_num_params", "hsf_net_set_params",
     "hsf_net_get_params", "hsf_net_set_input_norm", "hsf_net_set_output_scale", "hsf_net_forward", "hsf_net_loss_grad",
-    "hsf_net_train_step", "hsf_attach_net", "hsf_set_net_gate",
+    "hsf_net_train_step", "hsf_attach_net", "hsf_set_net_gate", "hsf_paired_schedule",
 ]
 WARM_EXTRAP, WARM_NET, WARM_NET_DELTA, WARM_NET_EXTRAP = 2, 3, 4, 5
 SOLVER_PRECOND = 1
@@ -155,6 +155,7 @@ def load():
         "hsf_autotune": ([C, I, ctypes.POINTER(ctypes.c_double)], I),
         "hsf_get_timing": ([C, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)], I),
         "hsf_evaluate_static": ([ctypes.POINTER(Params), P, P, P, P, P], I),
+        "hsf_paired_schedule": ([I, I, ctypes.POINTER(ctypes.c_int)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -5,7 +5,8 @@ forward step j and backward step N + 1 + (N mod 2) - j when that lies in 2..N, t
 backward step 1 alone.  Below the crossing se = (N + N mod 2) / 2 the forward step of a
 bead runs first and stores G_s in slot s - 1; above it the backward step runs first and
 stores sigma_s there.  The flags below are the ones the evaluation computes for each launch
-(f_late, f_from_pp, f_to_pp, g_late, g_exp).  This test replays the schedule over symbolic
+(f_late, f_from_pp, f_to_pp, g_late, g_exp), read from the library's host function that
+the evaluation itself calls.  This test replays the schedule over symbolic
 buffers and checks, for every N the library takes, that no launch writes a buffer that
 another workgroup of the same launch reads (through the stencil, or from the other half),
 and that every read sees the value the step needs."""
@@ -13,15 +14,26 @@ import pytest
 
 
 def launches(N):
-    lag = N & 1
-    se = (N + lag) // 2
+    """The library's own schedule (hsf_paired_schedule, host code, no GPU)."""
+    import ctypes
+    from paper_1204_2088_amd import hsf
+    lib = hsf.load()
     out = []
     for j in range(1, N + 1):
-        sb = N + 1 + lag - j
-        sb = sb if 2 <= sb <= N else 0
-        out.append(dict(sf=j, sb=sb, f_late=j > se, f_from_pp=j >= 2 and j - 1 >= se,
-                        f_to_pp=se <= j < N, g_late=bool(sb) and sb <= se, g_exp=sb == N and j == 1))
+        v = (ctypes.c_int * 7)()
+        assert lib.hsf_paired_schedule(N, j, v) == hsf.HSF_OK
+        out.append(dict(sf=v[0], sb=v[1], f_late=bool(v[2]), f_from_pp=bool(v[3]), f_to_pp=bool(v[4]),
+                        g_late=bool(v[5]), g_exp=bool(v[6])))
     return out
+
+
+def test_schedule_arguments_are_checked():
+    import ctypes
+    from paper_1204_2088_amd import hsf
+    lib = hsf.load()
+    v = (ctypes.c_int * 7)()
+    for N, j in ((1, 1), (65, 1), (8, 0), (8, 9)):
+        assert lib.hsf_paired_schedule(N, j, v) == hsf.HSF_EINVAL
 
 
 def replay(N):
