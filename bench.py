@@ -179,35 +179,57 @@ LEARNED = {
 }
 
 
+# Networks trained by the vesicle recipe (python -m paper_1204_2088_amd.warmnet DIR: 40 seeds x
+# 500 steps of the same chemistry at 64^3), shipped with the package.
+RECIPE_NETS = {"vesicle128_a3b9s": ["vesicle_a3b9s_w8-16-24-32.npz", "vesicle_a3b9s_w16.npz"]}
+
+
 def learned_arm(hsf, workload, precision, steps, tile, log, precond=False, widths=None):
-    """The learned warm start on the benchmark's own workload: a network trained on the
-    GPU from FP64 trajectories of other seeds, then the plain (previous fields),
-    extrapolated and learned warm starts each run the benchmark's whole trajectory from the
-    quench (seed 0, same tiling), every step timed."""
+    """The learned warm start on the benchmark's own workload: the recipe's networks
+    (trained on the GPU from FP64 trajectories of other seeds, loaded from the package), or
+    a network trained in this run when they are absent; then the plain (previous fields),
+    extrapolated and learned warm starts (with and without the gate) each run the
+    benchmark's whole trajectory from the quench (seed 0, same tiling), every step timed."""
     from paper_1204_2088_amd import warmnet
     from paper_1204_2088_amd import workloads as W
-    rc = LEARNED[workload]
-    t0 = time.perf_counter()
-    net, info = warmnet.train_warm_start(lambda seed: rc["train"](W, seed), seeds=rc["seeds"], steps=rc["steps"],
-                                         record=rc["record"], iters=rc["iters"], val_seed=5, log=None,
-                                         precond=precond, widths=widths or warmnet.DEFAULT_WIDTHS)
-    info["wall_seconds"] = time.perf_counter() - t0
-    log(f"# warm-start network trained: {info}")
+    nets, infos = {}, {}
+    for fname in RECIPE_NETS.get(workload, []):
+        path = os.path.join(ROOT, "paper_1204_2088_amd", "nets", fname)
+        if os.path.exists(path) and not widths:
+            net, info = warmnet.load_net(path)
+            name = fname.split("_")[-1].replace(".npz", "")
+            nets[name], infos[name] = net, dict(info, file=f"paper_1204_2088_amd/nets/{fname}")
+    if not nets:
+        rc = LEARNED[workload]
+        t0 = time.perf_counter()
+        net, info = warmnet.train_warm_start(lambda seed: rc["train"](W, seed), seeds=rc["seeds"], steps=rc["steps"],
+                                             record=rc["record"], iters=rc["iters"], val_seed=5, log=None,
+                                             precond=precond, widths=widths or warmnet.DEFAULT_WIDTHS)
+        info["wall_seconds"] = time.perf_counter() - t0
+        name = "w" + "-".join(str(w) for w in (widths or warmnet.DEFAULT_WIDTHS))
+        nets[name], infos[name] = net, dict(info, file="trained in this run")
+    log(f"# warm-start networks: {infos}")
     wls = make_workloads(workload, precision)
-    arms = [("plain", hsf.WARM_CURRENT, 0), ("extrapolated", hsf.WARM_EXTRAP, 0),
-            ("learned", hsf.WARM_NET_EXTRAP, 0), ("learned_gate2", hsf.WARM_NET_EXTRAP, 2)]
     windows = [(0, 100), (100, 1000), (1000, 3000)]
-    res = warmnet.trajectory_arms(wls, net, arms, steps, windows, tol=wls[0].tol, precision=precision, tile=tile,
+    base = [("plain", hsf.WARM_CURRENT, 0), ("extrapolated", hsf.WARM_EXTRAP, 0)]
+    res = warmnet.trajectory_arms(wls, None, base, steps, windows, tol=wls[0].tol, precision=precision, tile=tile,
                                   precond=precond, log=log)
-    net.close()
-    best_learned = min(("learned", "learned_gate2"), key=lambda k: res[k]["whole"]["ms_mean"])
+    learned_names = []
+    for name, net in nets.items():
+        arms = [(f"learned_{name}", hsf.WARM_NET_EXTRAP, 0), (f"learned_{name}_gate2", hsf.WARM_NET_EXTRAP, 2)]
+        res.update(warmnet.trajectory_arms(wls, net, arms, steps, windows, tol=wls[0].tol, precision=precision,
+                                           tile=tile, precond=precond, log=log))
+        learned_names += [a[0] for a in arms]
+        net.close()
+    best_learned = min(learned_names, key=lambda k: res[k]["whole"]["ms_mean"])
     best_plain = min(("plain", "extrapolated"), key=lambda k: res[k]["whole"]["ms_mean"])
     ml = res[best_learned]["whole"]["ms_mean"]
     return {
         "tol": wls[0].tol, "steps": steps, "solver": "preconditioned FR" if precond else "FR",
         "protocol": "each warm start runs the whole trajectory from the quench (seed 0), every step timed; "
-                    "windows are step ranges of that trajectory",
-        "network": info,
+                    "windows are step ranges of that trajectory; gate2: the network is used only after an "
+                    "inversion of at least 2 iterations, else the extrapolation",
+        "networks": infos,
         "arms": res,
         "best_learned_arm": best_learned,
         "best_non_learned_arm": best_plain,

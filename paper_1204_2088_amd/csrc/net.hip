@@ -32,6 +32,8 @@ using namespace hsf;
 namespace {
 
 constexpr int kMaxLevels = 4;
+// auxiliary device scratch of a network: 4096 partial sums, then results
+constexpr int kAuxParts = 4096, kAuxDoubles = kAuxParts + 8 + 2 * 64 + 64;
 constexpr int kLayers = 4 * kMaxLevels - 1;   // the most convolutions a network has
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
@@ -79,6 +81,7 @@ struct hsf_net {
     float *target = nullptr, *wpart = nullptr;
     double *bpart = nullptr;         // per-channel partial sums of the bias gradient
     double *loss_part = nullptr;
+    double *aux = nullptr;           // sample assembly and channel moments: partials, rms, results
     int weights_staged = 0;
     int training = 0;                // the current forward pass feeds a backward pass
 };
@@ -459,6 +462,7 @@ int hsf_net_create(int in_ch, int out_ch, const int widths[4], unsigned long lon
     if (rc == HSF_OK) rc = nalloc(n, n->allocs, (void **)&n->m, sizeof(float) * off);
     if (rc == HSF_OK) rc = nalloc(n, n->allocs, (void **)&n->v, sizeof(float) * off);
     if (rc == HSF_OK) rc = nalloc(n, n->allocs, (void **)&n->norm, sizeof(float) * 2 * (in_ch + out_ch));
+    if (rc == HSF_OK) rc = nalloc(n, n->allocs, (void **)&n->aux, sizeof(double) * kAuxDoubles);
     for (int l = 0; l < n->n_layers && rc == HSF_OK; ++l) {
         Layer &Ly = n->layer[l];
         rc = nalloc(n, n->allocs, (void **)&Ly.Wm, sizeof(__bf16) * (size_t)Ly.cop * Ly.kp);
@@ -600,6 +604,58 @@ int hsf_net_train_step(hsf_net *n, const float *in, const float *target, int bat
     const float c1 = 1.0f - powf(b1, (float)n->adam_t), c2 = 1.0f - powf(b2, (float)n->adam_t);
     net_adam(n->stream, n->params, n->grad, n->m, n->v, n->n_params, lr, b1, b2, 1e-8f, c1, c2);
     return stage_weights(n);
+}
+
+int hsf_net_make_sample(hsf_net *n, const double *phi, const double *phi_n, const double *phi_p, const double *w,
+                        const double *w_n, const double *w_p, int nsp, long long V, int mode, float *x, float *y)
+{
+    if (!n) return HSF_EINVAL;
+    if (!phi || !phi_n || !w || !w_n || !x || !y || (mode == 2 && (!phi_p || !w_p)) || (mode != 1 && mode != 2) ||
+        (nsp != 2 && nsp != 3) || V < 1)
+        return nfail(n, HSF_EINVAL, "bad sample arguments");
+    net_sample(n->stream, phi, phi_n, mode == 2 ? phi_p : phi_n, w, w_n, mode == 2 ? w_p : w_n, nsp, V, mode, n->aux,
+               kAuxParts, n->aux + kAuxParts, x, y);
+    NCHK(n, hipGetLastError());
+    return HSF_OK;
+}
+
+int hsf_net_affine(hsf_net *n, float *x, int batch, int channels, long long V, const float *shift,
+                   const float *scale)
+{
+    if (!n) return HSF_EINVAL;
+    if (!x || !shift || !scale || batch < 1 || channels < 1 || channels > 64 || V < 1)
+        return nfail(n, HSF_EINVAL, "bad affine arguments");
+    std::vector<float> h(2 * channels);
+    for (int c = 0; c < channels; ++c) {
+        h[c] = shift[c];
+        h[channels + c] = scale[c];
+    }
+    float *d = reinterpret_cast<float *>(n->aux + kAuxParts + 8 + 2 * 64);   // 2 x 64 floats fit in 64 doubles
+    NCHK(n, hipMemcpyAsync(d, h.data(), sizeof(float) * 2 * channels, hipMemcpyHostToDevice, n->stream));
+    net_affine(n->stream, x, channels, V, (long long)batch * channels * V, d, d + channels);
+    NCHK(n, hipGetLastError());
+    NCHK(n, hipStreamSynchronize(n->stream));   // the host staging array goes out of scope
+    return HSF_OK;
+}
+
+int hsf_net_channel_moments(hsf_net *n, const float *x, int batch, int channels, long long V, double *mean,
+                            double *rms)
+{
+    if (!n) return HSF_EINVAL;
+    if (!x || !mean || !rms || batch < 1 || channels < 1 || channels > 64 || V < 1)
+        return nfail(n, HSF_EINVAL, "bad moment arguments");
+    const int nblk = std::max(1, kAuxParts / (2 * channels));
+    double *out = n->aux + kAuxParts + 8;
+    net_channel_moments(n->stream, x, batch, channels, V, n->aux, nblk, out);
+    NCHK(n, hipGetLastError());
+    std::vector<double> h(2 * channels);
+    NCHK(n, hipMemcpyAsync(h.data(), out, sizeof(double) * 2 * channels, hipMemcpyDeviceToHost, n->stream));
+    NCHK(n, hipStreamSynchronize(n->stream));
+    for (int c = 0; c < channels; ++c) {
+        mean[c] = h[2 * c];
+        rms[c] = h[2 * c + 1];
+    }
+    return HSF_OK;
 }
 
 }  // extern "C"

@@ -61,5 +61,16 @@ void net_warm_apply(hipStream_t s, double *w, const float *p, long long V, int m
                     const double *wh0, const double *wh1);
 void net_shift_fields(hipStream_t s, double *w, const double *wh0, const double *wh1, long long n);
 void net_affine(hipStream_t s, float *x, int C, long long V, long long n, const float *shift, const float *scale);
+// A training sample of one replica from three (phi, w) states in the field layout (nsp x V
+// doubles): x = (phi0, delta phi / r) as the warm start feeds the network, y = delta w / r
+// over the polymer channels, r = rms of delta phi (written to rms[0]); mode 1: delta =
+// new - 0, mode 2: new - 2 * 0 + 1.
+void net_sample(hipStream_t s, const double *phi, const double *phi0, const double *phi1, const double *w,
+                const double *w0, const double *w1, int nsp, long long V, int mode, double *part, int max_parts,
+                double *rms, float *x, float *y);
+// Mean and root mean square per channel of x [batch][C][V] into out[2 C] (device);
+// part holds 2 C nblk doubles.
+void net_channel_moments(hipStream_t s, const float *x, int batch, int C, long long V, double *part, int nblk,
+                         double *out);
 
 }  // namespace hsf

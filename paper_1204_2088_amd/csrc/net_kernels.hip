@@ -791,6 +791,62 @@ __global__ void k_warm_apply(double *__restrict__ w, const float *__restrict__ p
     w[e] = v;
 }
 
+// Training target of one replica: y = delta w / rms over the polymer channels
+// (the first 2 V values of the field layout), delta as in warm_delta.
+__global__ void k_net_target(const double *__restrict__ w, const double *__restrict__ w0,
+                             const double *__restrict__ w1, long long n, int mode, const double *__restrict__ rms,
+                             float *__restrict__ y)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) y[e] = (float)(warm_delta(w, w0, w1, e, mode) / rms[0]);
+}
+
+// Per-channel partial sums of x and x^2 over batch and sites: block (c, k) of a grid of
+// C x nblk blocks covers every nblk-th chunk of 256 values of channel c.
+__global__ __launch_bounds__(256) void k_channel_sums(const float *__restrict__ x, int batch, int C, long long V,
+                                                      int nblk, double *__restrict__ part)
+{
+    const int c = blockIdx.x, k = blockIdx.y;
+    __shared__ double r1[256], r2[256];
+    double s1 = 0.0, s2 = 0.0;
+    const long long n = (long long)batch * V;
+    for (long long e = (long long)k * 256 + threadIdx.x; e < n; e += (long long)nblk * 256) {
+        const long long b = e / V, i = e - b * V;
+        const double v = (double)x[(b * C + c) * V + i];
+        s1 += v;
+        s2 += v * v;
+    }
+    r1[threadIdx.x] = s1;
+    r2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            r1[threadIdx.x] += r1[threadIdx.x + h];
+            r2[threadIdx.x] += r2[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * ((long long)c * nblk + k)] = r1[0];
+        part[2 * ((long long)c * nblk + k) + 1] = r2[0];
+    }
+}
+
+// out[2 c] = mean, out[2 c + 1] = root mean square of channel c (partials summed in order).
+__global__ void k_channel_finish(const double *__restrict__ part, int C, int nblk, double count,
+                                 double *__restrict__ out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k < nblk; ++k) {
+        s1 += part[2 * ((long long)c * nblk + k)];
+        s2 += part[2 * ((long long)c * nblk + k) + 1];
+    }
+    out[2 * c] = s1 / count;
+    out[2 * c + 1] = sqrt(s2 / count);
+}
+
 // w += wh0 - wh1 (plain extrapolation of the fields)
 __global__ void k_shift_fields(double *__restrict__ w, const double *__restrict__ wh0,
                                const double *__restrict__ wh1, long long n)
@@ -972,6 +1028,21 @@ void net_warm_apply(hipStream_t s, double *w, const float *p, long long V, int m
 void net_shift_fields(hipStream_t s, double *w, const double *wh0, const double *wh1, long long n)
 {
     hipLaunchKernelGGL(k_shift_fields, dim3(nb(n, 256)), dim3(256), 0, s, w, wh0, wh1, n);
+}
+
+void net_sample(hipStream_t s, const double *phi, const double *phi0, const double *phi1, const double *w,
+                const double *w0, const double *w1, int nsp, long long V, int mode, double *part, int max_parts,
+                double *rms, float *x, float *y)
+{
+    net_warm_input(s, phi, phi0, phi1, nsp, V, mode, part, max_parts, rms, x);
+    hipLaunchKernelGGL(k_net_target, dim3(nb(2 * V, 256)), dim3(256), 0, s, w, w0, w1, 2 * V, mode, rms, y);
+}
+
+void net_channel_moments(hipStream_t s, const float *x, int batch, int C, long long V, double *part, int nblk,
+                         double *out)
+{
+    hipLaunchKernelGGL(k_channel_sums, dim3(C, nblk), dim3(256), 0, s, x, batch, C, V, nblk, part);
+    hipLaunchKernelGGL(k_channel_finish, dim3(1), dim3(64), 0, s, part, C, nblk, (double)batch * (double)V, out);
 }
 
 void net_affine(hipStream_t s, float *x, int C, long long V, long long n, const float *shift, const float *scale)

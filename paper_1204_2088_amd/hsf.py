@@ -36,7 +36,8 @@ EXPORTED = [
     "hsf_set_solver", "hsf_get_work", "hsf_set_warm", "hsf_net_create", "hsf_net_destroy",
     "hsf_net_last_error", "hsf_net_set_stream", "hsf_net_num_params", "hsf_net_set_params",
     "hsf_net_get_params", "hsf_net_set_input_norm", "hsf_net_set_output_scale", "hsf_net_forward", "hsf_net_loss_grad",
-    "hsf_net_train_step", "hsf_attach_net", "hsf_set_net_gate", "hsf_paired_schedule",
+    "hsf_net_train_step", "hsf_attach_net", "hsf_set_net_gate", "hsf_paired_schedule", "hsf_net_make_sample",
+    "hsf_net_channel_moments", "hsf_net_affine",
 ]
 WARM_EXTRAP, WARM_NET, WARM_NET_DELTA, WARM_NET_EXTRAP = 2, 3, 4, 5
 SOLVER_PRECOND = 1
@@ -156,6 +157,11 @@ def load():
         "hsf_get_timing": ([C, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)], I),
         "hsf_evaluate_static": ([ctypes.POINTER(Params), P, P, P, P, P], I),
         "hsf_paired_schedule": ([I, I, ctypes.POINTER(ctypes.c_int)], I),
+        "hsf_net_make_sample": ([C, P, P, P, P, P, P, I, ctypes.c_longlong, I, P, P], I),
+        "hsf_net_channel_moments": ([C, P, I, I, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)], I),
+        "hsf_net_affine": ([C, P, I, I, ctypes.c_longlong, ctypes.POINTER(ctypes.c_float),
+                            ctypes.POINTER(ctypes.c_float)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -543,3 +549,25 @@ class Net:
         self._check(self._lib.hsf_net_train_step(self._h, pi, pt, int(batch), int(L), ctypes.c_float(lr),
                                                  ctypes.byref(loss), where))
         return loss.value
+
+    def make_sample(self, phi, phi_n, phi_p, w, w_n, w_p, nsp, V, mode, x, y):
+        """hsf_net_make_sample on device tensors (float64 states, float32 outputs)."""
+        def p(t):
+            return None if t is None else ctypes.c_void_p(t.data_ptr())
+        self._check(self._lib.hsf_net_make_sample(self._h, p(phi), p(phi_n), p(phi_p), p(w), p(w_n), p(w_p),
+                                                  int(nsp), int(V), int(mode), p(x), p(y)))
+
+    def affine(self, x, batch, channels, V, shift, scale):
+        """x_c = (x_c - shift[c]) * scale[c] on a float32 device tensor [batch][channels][V]."""
+        sh = (ctypes.c_float * channels)(*[float(v) for v in shift])
+        sc = (ctypes.c_float * channels)(*[float(v) for v in scale])
+        self._check(self._lib.hsf_net_affine(self._h, ctypes.c_void_p(x.data_ptr()), int(batch), int(channels),
+                                             int(V), sh, sc))
+
+    def channel_moments(self, x, batch, channels, V):
+        """Per-channel (mean, rms) of a float32 device tensor [batch][channels][V]."""
+        mean = (ctypes.c_double * channels)()
+        rms = (ctypes.c_double * channels)()
+        self._check(self._lib.hsf_net_channel_moments(self._h, ctypes.c_void_p(x.data_ptr()), int(batch),
+                                                      int(channels), int(V), mean, rms))
+        return list(mean), list(rms)

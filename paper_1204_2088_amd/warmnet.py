@@ -307,3 +307,201 @@ def trajectory_arms(wls, net, arms, steps, windows, tol=1e-6, precision="fp32", 
             log(f"  {name}: whole run {res['whole']['ms_mean']:.3f} ms/step mean, "
                 f"{res['whole']['evals_per_step']:.2f} evaluations/step")
     return out
+
+
+# ---------------------------------------------------------------------------
+# The recipe of the 128^3 vesicle benchmark: a network trained on 20 000 (phi, w) states
+# of plain FP64 runs of the same chemistry at 64^3 (40 seeds x 500 steps), one
+# second-difference sample per replica and step, assembled on the device by the library
+# (hsf_net_make_sample) and stored in half precision (the matrix cores read bfloat16).
+
+def record_recipe_samples(wls, steps, first, tol=1e-10, precond=True, log=None, store_dtype=None, net_io=None):
+    """Run the replicas `wls` (one batched FP64 context, residual tol, extrapolated warm
+    start) for `steps` coupled steps and, for every step k >= first (first >= 2), build one
+    second-difference sample per replica from the states of steps k - 2, k - 1, k.
+    Returns (X [S][2 nsp][V], Y [S][2][V]) device tensors of dtype store_dtype (default
+    float16) and the wall time."""
+    torch = _torch()
+    store_dtype = store_dtype or torch.float16
+    ctx = hsf.Context(wls, precision="fp64")
+    ctx.set_solver(precond=precond)
+    phi0, w0 = initial_state(ctx, wls)
+    ctx.set_densities(phi0)
+    ctx.set_fields(w0)
+    ctx.set_warm(hsf.WARM_EXTRAP)
+    nsp, T = ctx.nsp, ctx.T
+    V = wls[0].V
+    assert all(wl.V == V for wl in wls)
+    R = len(wls)
+    n_samples = R * max(0, steps - first)
+    X = torch.empty((n_samples, 2 * nsp, V), dtype=store_dtype, device="cuda")
+    Y = torch.empty((n_samples, 2, V), dtype=store_dtype, device="cuda")
+    ring_phi = [torch.empty(nsp * T, dtype=torch.float64, device="cuda") for _ in range(3)]
+    ring_w = [torch.empty(nsp * T, dtype=torch.float64, device="cuda") for _ in range(3)]
+    xb = torch.empty((2 * nsp, V), dtype=torch.float32, device="cuda")
+    yb = torch.empty((2, V), dtype=torch.float32, device="cuda")
+    k_s = 0
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ctx.get_densities(out=ring_phi[k % 3])
+        st, _ = ctx.step(1, tol=tol, max_iter=5000)
+        ctx.get_fields(out=ring_w[k % 3])
+        if k >= first:
+            a, b, c = k % 3, (k - 1) % 3, (k - 2) % 3
+            for r in range(R):
+                o = ctx.field_offset(r)
+                sl = slice(o, o + nsp * V)
+                net_io.make_sample(ring_phi[a][sl], ring_phi[b][sl], ring_phi[c][sl], ring_w[a][sl], ring_w[b][sl],
+                                   ring_w[c][sl], nsp, V, 2, xb, yb)
+                X[k_s].copy_(xb)
+                Y[k_s].copy_(yb)
+                k_s += 1
+        if log and k % 50 == 0:
+            log(f"  recipe trajectory step {k}: iterations {min(s['iterations'] for s in st)}.."
+                f"{max(s['iterations'] for s in st)} ({time.perf_counter() - t0:.1f} s, {k_s} samples)")
+    torch.cuda.synchronize()
+    ctx.close()
+    return X[:k_s], Y[:k_s], time.perf_counter() - t0
+
+
+def chunked_moments(net_io, T, chunk=64):
+    """Per-channel mean and rms of a [S][C][V] tensor of any float dtype, through the
+    library's reduction on float32 chunks (combined by sample count)."""
+    torch = _torch()
+    S, C, V = T.shape
+    buf = torch.empty((min(chunk, S), C, V), dtype=torch.float32, device=T.device)
+    m1 = np.zeros(C)
+    m2 = np.zeros(C)
+    for i in range(0, S, chunk):
+        n = min(chunk, S - i)
+        buf[:n].copy_(T[i:i + n])
+        mean, rms = net_io.channel_moments(buf[:n], n, C, V)
+        m1 += n * np.asarray(mean)
+        m2 += n * np.asarray(rms) ** 2
+    return m1 / S, np.sqrt(m2 / S)
+
+
+def train_from_store(net, X, Y, L, iters, batch, lr, lr_end, y_scale, seed=0, log=None, Xv=None, Yv=None):
+    """Adam on minibatches drawn uniformly from the stored samples; targets brought to unit
+    rms per channel on the device (hsf_net_affine).  Returns the training losses and the
+    validation loss (mean square error in the scaled units)."""
+    torch = _torch()
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    S = X.shape[0]
+    xb = torch.empty((batch,) + tuple(X.shape[1:]), dtype=torch.float32, device="cuda")
+    yb = torch.empty((batch,) + tuple(Y.shape[1:]), dtype=torch.float32, device="cuda")
+    C_out, V = Y.shape[1], Y.shape[2]
+    zeros = [0.0] * C_out
+    losses = []
+    t0 = time.perf_counter()
+    for it in range(iters):
+        idx = torch.randint(0, S, (batch,), generator=g).to("cuda")
+        xb.copy_(X[idx])
+        yb.copy_(Y[idx])
+        net.affine(yb, batch, C_out, V, zeros, y_scale)
+        a = lr * (lr_end / lr) ** (it / max(1, iters - 1))
+        losses.append(net.train_step(xb.view(-1), yb.view(-1), batch, L, a))
+        if log and (it % 2000 == 0 or it == iters - 1):
+            log(f"  train iter {it}: loss {np.mean(losses[-100:]):.4e} lr {a:.2e} ({time.perf_counter() - t0:.1f} s)")
+    val = None
+    if Xv is not None:
+        tot = 0.0
+        for i in range(Xv.shape[0]):
+            xb[:1].copy_(Xv[i:i + 1])
+            yb[:1].copy_(Yv[i:i + 1])
+            net.affine(yb[:1], 1, C_out, V, zeros, y_scale)
+            l, _ = net.loss_grad(xb[:1].reshape(-1), yb[:1].reshape(-1), 1, L, with_grad=False)
+            tot += l
+        val = tot / Xv.shape[0]
+    return losses, val, time.perf_counter() - t0
+
+
+def save_net(path, net, widths, in_ch, out_ch, shift, scale, out_scale, info):
+    """Parameters and normalisation of a trained network (no pickled objects)."""
+    import json
+    np.savez(path, params=net.get_params().astype(np.float32), widths=np.asarray(widths, dtype=np.int32),
+             channels=np.asarray([in_ch, out_ch], dtype=np.int32), shift=np.asarray(shift, dtype=np.float32),
+             scale=np.asarray(scale, dtype=np.float32), out_scale=np.asarray(out_scale, dtype=np.float32),
+             info=np.asarray(json.dumps(info)))
+
+
+def load_net(path):
+    """A network saved by save_net, ready for inference (output scale set).  Returns
+    (net, info)."""
+    import json
+    z = np.load(path, allow_pickle=False)
+    widths = tuple(int(v) for v in z["widths"])
+    in_ch, out_ch = (int(v) for v in z["channels"])
+    net = hsf.Net(in_ch, out_ch, widths, seed=0)
+    net.set_params(z["params"].astype(np.float32))
+    net.set_input_norm(z["shift"].tolist(), z["scale"].tolist())
+    net.set_output_scale(z["out_scale"].tolist())
+    return net, json.loads(str(z["info"]))
+
+
+def train_recipe(out_dir, seeds=tuple(range(1, 41)), steps=502, first=2, L=64, widths_list=((8, 16, 24, 32), (16,)),
+                 iters=12000, batch=4, val_seed=99, log=None):
+    """The benchmark's recipe: 40 seeds x 500 recorded steps of the A3B9 + S vesicle
+    chemistry at 64^3 (20 000 (phi, w) states, FP64, residual 1e-10), one second-
+    difference sample per replica and step (about 20 000 samples), a held-out seed for
+    validation, then each network of widths_list trained on the same samples and saved
+    to out_dir.  Returns {name: info}."""
+    import os
+    torch = _torch()
+    os.makedirs(out_dir, exist_ok=True)
+    mk = lambda seed: W.vesicle128_a3b9s(L=L).with_(seed=seed, precision="fp64")
+    nsp = 3
+    io = hsf.Net(2 * nsp, 2, (8,), seed=0)   # sample assembly and reductions
+    X, Y, t_data = record_recipe_samples([mk(s) for s in seeds], steps, first, log=log, net_io=io)
+    Xv, Yv, _ = record_recipe_samples([mk(val_seed)], 40, 10, log=None, net_io=io)
+    states = len(seeds) * (steps - first)
+    if log:
+        log(f"  {X.shape[0]} samples from {states} states in {t_data:.1f} s")
+    xm, xr = chunked_moments(io, X)
+    ym, yr = chunked_moments(io, Y)
+    shift = [float(xm[c]) if c < nsp else 0.0 for c in range(2 * nsp)]
+    scale = [1.0 / max(float(np.sqrt(max(xr[c] ** 2 - xm[c] ** 2, 0.0))), 1e-6) if c < nsp else 1.0
+             for c in range(2 * nsp)]
+    out_rms = [max(float(v), 1e-30) for v in yr]
+    y_scale = [1.0 / v for v in out_rms]
+    io.close()
+    results = {}
+    for widths in widths_list:
+        net = hsf.Net(2 * nsp, 2, widths, seed=1)
+        net.set_input_norm(shift, scale)
+        losses, val, t_train = train_from_store(net, X, Y, L, iters, batch, 1e-3, 1e-4, y_scale, log=log, Xv=Xv,
+                                                Yv=Yv)
+        name = "w" + "-".join(str(w) for w in widths)
+        info = {"recipe": f"{len(seeds)} seeds x {steps - first} steps of the A3B9 + S vesicle chemistry at "
+                          f"{L}^3 (FP64 propagators, preconditioned inversion to 1e-10, extrapolated warm start)",
+                "states": states, "samples": int(X.shape[0]), "sample": "second difference per replica and step",
+                "storage": "float16", "widths": list(widths), "parameters": int(net.n_params),
+                "iterations": iters, "batch": batch, "lr": [1e-3, 1e-4],
+                "loss_first": float(np.mean(losses[:50])), "loss_last": float(np.mean(losses[-500:])),
+                "validation_loss": val, "validation": f"seed {val_seed}, steps 10-39",
+                "loss_units": "mean square error of targets scaled to unit rms per channel",
+                "target_rms": out_rms, "data_seconds": t_data, "train_seconds": t_train}
+        net.set_output_scale(out_rms)
+        save_net(os.path.join(out_dir, f"vesicle_a3b9s_{name}.npz"), net, widths, 2 * nsp, 2, shift, scale, out_rms,
+                 info)
+        results[name] = info
+        if log:
+            log(f"  network {name}: {info}")
+        net.close()
+    return results
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="train the warm-start networks of the vesicle benchmark recipe")
+    ap.add_argument("out_dir")
+    ap.add_argument("--seeds", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=502)
+    ap.add_argument("--iters", type=int, default=12000)
+    args = ap.parse_args()
+    res = train_recipe(args.out_dir, seeds=tuple(range(1, args.seeds + 1)), steps=args.steps, iters=args.iters,
+                       log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps(res))
