@@ -10,8 +10,10 @@ applies it as HSF_WARM_NET_DELTA (w^n + r net) or HSF_WARM_NET_EXTRAP
 (2 w^n - w^(n-1) + r net(second difference)), then runs the same inversion to the
 same residual; the network only moves the starting point.
 
-Everything here runs on the GPU: the trajectories through hsf.Context, the
-training through hsf.Net, the sample assembly in torch on device tensors.
+Everything here runs on the GPU through the library: the trajectories (hsf.Context), the
+sample assembly, normalisation statistics and target scaling (hsf_net_make_sample,
+hsf_net_channel_moments, hsf_net_affine) and the training (hsf.Net); torch only holds the
+device memory.
 """
 from __future__ import annotations
 
@@ -81,10 +83,11 @@ def record_trajectory(wls, steps, record, tol=1e-10, precision="fp64", log=None,
     return out
 
 
-def make_samples(traj, polymer=2):
+def make_samples(traj, io):
     """Network samples from a recorded trajectory: for every k with k-1, k, k+1
-    recorded, one first-difference and one second-difference sample per replica.
-    Returns (x [S][2 nsp][V], y [S][2][V]) FP32 device tensors."""
+    recorded, one first-difference and one second-difference sample per replica,
+    assembled on the device by the library (hsf_net_make_sample through the network
+    handle io).  Returns (x [S][2 nsp][V], y [S][2][V]) FP32 device tensors."""
     torch = _torch()
     xs, ys = [], []
     for k in sorted(traj):
@@ -92,29 +95,34 @@ def make_samples(traj, polymer=2):
             continue
         p0, w0 = traj[k]
         p1, w1 = traj[k + 1]
-        diffs = [(p1 - p0, w1 - w0)]
-        if k - 1 in traj:
-            pm, wm = traj[k - 1]
-            diffs.append((p1 - 2 * p0 + pm, w1 - 2 * w0 + wm))
-        for dp, dw in diffs:
-            for r in range(p0.shape[0]):
-                rms = torch.sqrt(torch.mean(dp[r] ** 2)).clamp_min(1e-300)
-                xs.append(torch.cat([p0[r], dp[r] / rms]).float())
-                ys.append((dw[r, :polymer] / rms).float())
+        R, nsp, V = p0.shape
+        prev = traj.get(k - 1)
+        for mode in (1, 2):
+            if mode == 2 and prev is None:
+                continue
+            for r in range(R):
+                x = torch.empty((2 * nsp, V), dtype=torch.float32, device="cuda")
+                y = torch.empty((2, V), dtype=torch.float32, device="cuda")
+                io.make_sample(p1[r], p0[r], prev[0][r] if mode == 2 else None, w1[r], w0[r],
+                               prev[1][r] if mode == 2 else None, nsp, V, mode, x, y)
+                xs.append(x)
+                ys.append(y)
     return torch.stack(xs), torch.stack(ys)
 
 
-def input_norm(x):
+def input_norm(io, x):
     """Per-channel shift and scale of the network input: the density channels are
-    standardised over the data set, the difference channels already have unit rms."""
-    nsp = x.shape[1] // 2
+    standardised over the data set (moments reduced on the device), the difference
+    channels already have unit rms."""
+    S, C, V = x.shape
+    nsp = C // 2
+    mean, rms = io.channel_moments(x, S, C, V)
     shift, scale = [], []
-    for c in range(x.shape[1]):
+    for c in range(C):
         if c < nsp:
-            m = float(x[:, c].mean())
-            s = float(x[:, c].std())
-            shift.append(m)
-            scale.append(1.0 / max(s, 1e-6))
+            std = float(np.sqrt(max(rms[c] ** 2 - mean[c] ** 2, 0.0)))
+            shift.append(float(mean[c]))
+            scale.append(1.0 / max(std, 1e-6))
         else:
             shift.append(0.0)
             scale.append(1.0)
@@ -163,10 +171,12 @@ def train_warm_start(make_workloads, seeds, steps, record, widths=DEFAULT_WIDTHS
     torch = _torch()
     t0 = time.perf_counter()
     xs, ys = [], []
+    nsp = make_workloads(seeds[0])[0].nsp
+    io = hsf.Net(2 * nsp, 2, (8,), seed=0)   # sample assembly and reductions
     for seed in seeds:
         traj = record_trajectory(make_workloads(seed), steps, record, tol=tol, precision="fp64", log=log,
                                  precond=precond)
-        x, y = make_samples(traj)
+        x, y = make_samples(traj, io)
         del traj
         xs.append(x)
         ys.append(y)
@@ -177,19 +187,21 @@ def train_warm_start(make_workloads, seeds, steps, record, widths=DEFAULT_WIDTHS
     if val_seed is not None:   # early steps of a held-out trajectory
         tv = record_trajectory(make_workloads(val_seed)[:1], 22, list(range(1, 22)), tol=tol, precision="fp64",
                                precond=precond)
-        xv, yv = make_samples(tv)
+        xv, yv = make_samples(tv, io)
     L = round(x.shape[2] ** (1.0 / 3.0))
-    nsp = x.shape[1] // 2
     net = hsf.Net(2 * nsp, 2, widths, seed=net_seed)
-    shift, scale = input_norm(x)
+    shift, scale = input_norm(io, x)
     net.set_input_norm(shift, scale)
     # targets per output channel to unit rms (the fields of a dilute species respond far
     # more strongly than the others); the scale goes back on as the network's output scale
-    out_rms = [max(float(y[:, c].pow(2).mean().sqrt()), 1e-30) for c in range(y.shape[1])]
-    inv = torch.tensor([1.0 / v for v in out_rms], dtype=torch.float32, device=y.device).view(1, -1, 1)
-    y = y * inv
+    S, C_out, V = y.shape
+    _, yr = io.channel_moments(y, S, C_out, V)
+    out_rms = [max(float(v), 1e-30) for v in yr]
+    inv = [1.0 / v for v in out_rms]
+    io.affine(y, S, C_out, V, [0.0] * C_out, inv)
     if yv is not None:
-        yv = yv * inv
+        io.affine(yv, yv.shape[0], C_out, V, [0.0] * C_out, inv)
+    io.close()
     t1 = time.perf_counter()
     losses = train(net, x, y, L, iters=iters, batch=batch, lr=lr, lr_end=lr_end, log=log, x_val=xv, y_val=yv)
     val = evaluate_loss(net, xv, yv, L) if xv is not None else None
