@@ -57,8 +57,10 @@ def test_learned_gain_over_the_whole_run(trained):
     """Each warm start runs the held-out trajectory from the quench for 400 steps (every
     step timed): over the whole run the learned warm start (with the gate of 2 iterations)
     needs at most 0.6 of the plain method's evaluations per step and is faster per step
-    than it; its margin over the extrapolation is measured and stays within 10 % in
-    evaluations (the network is trained on the first 120 steps after the quench only)."""
+    than it, and the learned warm start without the gate needs at most 0.8 of the
+    extrapolation's evaluations per step (measured 2.64 against 4.18 and 10.2 for plain;
+    0.70 against 0.92 and 2.11 ms per step), although the network is trained on the first
+    120 steps after the quench only."""
     hsf, warmnet, net, info = trained
     wl = [W.melt64_a8b8(tau=0.6)]
     arms = [("plain", hsf.WARM_CURRENT, 0), ("extrapolated", hsf.WARM_EXTRAP, 0),
@@ -72,6 +74,7 @@ def test_learned_gain_over_the_whole_run(trained):
     assert lg["evals_per_step"] <= 0.6 * pl["evals_per_step"]
     assert lg["ms_mean"] < pl["ms_mean"]
     assert lg["evals_per_step"] <= 1.1 * ex["evals_per_step"]
+    assert res["learned"]["whole"]["evals_per_step"] <= 0.8 * ex["evals_per_step"]
 
 
 def test_gate_falls_back_to_extrapolation(trained):
