@@ -36,11 +36,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM-side bytes per launch of a propagator kernel, from the counter runs summarised in
-# profiles/ (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0 after a calibration copy).
+# HBM-side bytes per launch of the dominant propagator kernel and of the LB kernel, from the
+# counter runs summarised in profiles/propagator_vesicle128_a3b9s_fp32_paired.md (FETCH_SIZE
+# scaled by 2.0 and WRITE_SIZE by 1.0 after a calibration copy).
 # Valid only for that workload, precision, tiling and kernel as they stand; anything
 # else reports null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {("vesicle128_a3b9s", "fp32", (32, 8, 4, -1), "pair"): 74.46e6,
+                    ("vesicle128_a3b9s", "fp32", "lb"): 436.68e6}
 METRIC = "propagator site·bead updates/s + LB MLUPS; step time learned vs plain at 1e-6"
 
 def lb_bytes_per_site(wl):
@@ -314,14 +316,18 @@ def rooflines(timing, wls, tile, workload):
         prop_roof = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (counters)",
+                     "traffic_frac": traffic / avg_s / 1e9 / HBM_PEAK_GBS if traffic else None,
                      "algorithmic_bytes_per_launch": b_unit * units,
                      "bytes_per_update": b_unit, "updates_per_launch": units, "avg_launch_us": prop[dom]["avg_us"]}
     if "lb" in kernels:
         avg_s = kernels["lb"]["avg_us"] * 1e-6
         lb_b = lb_bytes_per_site(wl)
         achieved = lb_b * V_total / avg_s / 1e9
+        lb_traffic = MEASURED_TRAFFIC.get((workload, wl.precision, "lb"))
         lb_roof = {"bound": "hbm", "kernel": "k_lb", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                    "frac": achieved / HBM_PEAK_GBS, "bytes_per_site": lb_b,
+                   "traffic": lb_traffic, "traffic_unit": "bytes per launch (counters)",
+                   "traffic_frac": lb_traffic / avg_s / 1e9 / HBM_PEAK_GBS if lb_traffic else None,
                    "storage": "fp32 deviations from the rest state" if wl.precision == "fp32" else "fp64",
                    "mlups": V_total / avg_s / 1e6, "avg_launch_us": kernels["lb"]["avg_us"]}
     return kernels, prop_roof, lb_roof
