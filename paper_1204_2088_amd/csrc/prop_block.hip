@@ -574,7 +574,7 @@ inline StepInfo step_info(const Chain &ch, int s)
 // polymer species at its sites (the tiles cover every site once) and stores them for the
 // later steps, in place of a separate launch.
 template <typename real, int CX, int CY, int CZ, bool ARGS>
-__global__ __launch_bounds__(kBlock) void k_fwd_direct(StepInfo si, const int *__restrict__ blk_rep,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 ? 8 : 1))) void k_fwd_direct(StepInfo si, const int *__restrict__ blk_rep,
                                                        const int *__restrict__ blk_first,
                                                        const Rep *__restrict__ rep,
                                                        const RepState *__restrict__ st,
@@ -670,7 +670,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_direct(StepInfo si, const int *_
 // partials itself in that same order, so all hold the same Q, and the replica's first
 // block stores it.
 template <typename real, int CX, int CY, int CZ, bool ARGS, bool FINAL>
-__global__ __launch_bounds__(kBlock) void k_bwd_direct(StepInfo si, const int *__restrict__ blk_rep,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 ? 8 : 1))) void k_bwd_direct(StepInfo si, const int *__restrict__ blk_rep,
                                                        const int *__restrict__ blk_first,
                                                        const Rep *__restrict__ rep,
                                                        RepState *__restrict__ st, Chain ch,
@@ -1067,7 +1067,7 @@ __device__ __forceinline__ void pair_bwd(const PairInfo &pi, int pb, const int *
 }
 
 template <typename real, int CX, int CY, int CZ, bool ARGS>
-__global__ __launch_bounds__(kBlock) void k_pair_direct(PairInfo pi, const int *__restrict__ blk_rep,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 ? 8 : 1))) void k_pair_direct(PairInfo pi, const int *__restrict__ blk_rep,
                                                         const int *__restrict__ blk_first,
                                                         const Rep *__restrict__ rep,
                                                         const RepState *__restrict__ st, PropBufs<real> b,
