@@ -504,6 +504,34 @@ enum {
 int hsf_set_timing(hsf_ctx *ctx, int on);
 int hsf_get_timing(hsf_ctx *ctx, double *total_ms, long long *count);
 
+/* Step log: one record per replica and successful coupled step (hsf_step), kept while
+ * the log is on.  It follows a run the way the paper follows its simulations in time
+ * (section 3: morphologies and order parameters against the time step): the step's
+ * inversion (iterations, evaluations, final residual, ln Q at the converged fields), the
+ * amount of each species and the largest flow speed after the step, and the wall time
+ * of the step's two phases (inversion; LB and convection-diffusion), from HIP events
+ * on the context's stream and shared by the replicas of the step.  Recording costs one
+ * pass over the densities and velocities and one small copy per step.  Failed steps are
+ * not recorded. */
+typedef struct {
+    long long step;       /* successful coupled steps of this context since hsf_create, this one included */
+    int replica;
+    int iterations, evaluations, converged;
+    double residual;
+    double ln_q;
+    double amount[3];     /* site sums of phi_A, phi_B, phi_S (phi_S 0 for melts) after the step */
+    double max_u;         /* largest |u| of the step's LB velocity (0 with the flow off) */
+    double ms_inversion;
+    double ms_dynamics;
+} hsf_step_record;
+/* on = 1 starts keeping records (at most 1 << 20; beyond that the oldest are dropped),
+ * on = 0 stops and drops the unread ones.  HSF_EINVAL for a null context. */
+int hsf_set_step_log(hsf_ctx *ctx, int on);
+/* Moves up to max_records of the oldest unread records into out (host array) and sets
+ * *n_read to their number.  HSF_EINVAL for a null context, out or n_read, or a negative
+ * max_records. */
+int hsf_read_step_log(hsf_ctx *ctx, hsf_step_record *out, int max_records, int *n_read);
+
 #ifdef __cplusplus
 }
 #endif

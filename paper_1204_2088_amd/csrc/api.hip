@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -83,9 +84,22 @@ struct hsf_ctx {
     };
     struct GraphSlot {
         hipGraphExec_t exec = nullptr;
+        const void *key = nullptr;     // the density buffer the sequence was captured with
     };
     enum { GK_START = 0, GK_TRIAL, GK_UPDATE, GK_EVAL, GK_COUNT };
-    GraphSlot graphs[GK_COUNT];
+    // a coupled step rotates the densities among four buffers (current, update, two history
+    // entries), so each sequence has one captured variant per density buffer
+    static constexpr int kGraphVariants = 4;
+    GraphSlot graphs[GK_COUNT][kGraphVariants];
+    void drop_graphs()
+    {
+        for (auto &kind : graphs)
+            for (auto &g : kind) {
+                if (g.exec) (void)hipGraphExecDestroy(g.exec);
+                g.exec = nullptr;
+                g.key = nullptr;
+            }
+    }
 
     // optional per-launch timing of the hot kernels with HIP events on the context stream
     // warm starts
@@ -105,6 +119,14 @@ struct hsf_ctx {
     std::vector<hipEvent_t> pool;      // free events
     double tot_ms[HSF_K_COUNT] = {0};
     long long tot_cnt[HSF_K_COUNT] = {0};
+    // step log (hsf_set_step_log)
+    int step_log = 0;
+    long long steps_done = 0;          // successful coupled steps
+    std::deque<hsf_step_record> log;
+    hipEvent_t log_ev[3] = {nullptr, nullptr, nullptr};   // step start, inversion done, dynamics done
+    double *log_d = nullptr;           // device: 4 doubles per replica
+    std::vector<hsf_invert_stats> log_inv;   // the step's inversion, per replica
+    std::vector<double> log_lnq;
 };
 
 namespace {
@@ -245,8 +267,18 @@ int run_seq(hsf_ctx *c, int kind, F &&body)
         HIPCHK(c, hipGetLastError());
         return HSF_OK;
     }
-    hsf_ctx::GraphSlot &g = c->graphs[kind];
+    hsf_ctx::GraphSlot *slots = c->graphs[kind];
+    int v = 0;
+    while (v < hsf_ctx::kGraphVariants && slots[v].exec && slots[v].key != c->phi) ++v;
+    if (v == hsf_ctx::kGraphVariants) {   // not reached with the four density buffers; recapture
+        v = 0;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        (void)hipGraphExecDestroy(slots[0].exec);
+        slots[0].exec = nullptr;
+    }
+    hsf_ctx::GraphSlot &g = slots[v];
     if (!g.exec) {
+        g.key = c->phi;
         hipStream_t user = c->stream;
         if (!user && !c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         hipStream_t cs = user ? user : c->cap_stream;
@@ -323,11 +355,7 @@ int set_tile(hsf_ctx *c, const TileCfg &t)
     c->tile_blk_first = bf;
     set_plan_args(c->tplan, c->reps.data(), c->n_rep, bf.data());
     c->tile = t;
-    for (auto &g : c->graphs)
-        if (g.exec) {
-            (void)hipGraphExecDestroy(g.exec);
-            g.exec = nullptr;
-        }
+    c->drop_graphs();
     return HSF_OK;
 }
 
@@ -558,6 +586,24 @@ int commit_history(hsf_ctx *c)
                              c->stream));
     HIPCHK(c, hipMemcpyAsync(c->phi_hist[0], c->phi, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice,
                              c->stream));
+    c->n_hist = std::min(c->n_hist + 1, 2);
+    return HSF_OK;
+}
+
+// After a successful explicit coupled step: its inversion's fields become the newest
+// history entry (a copy: w stays the current fields), and the densities rotate without
+// copies: the step's targets phi become the newest history entry, the updated densities
+// phi_tmp the current ones, and the oldest history buffer the next update's target.
+int commit_step(hsf_ctx *c)
+{
+    std::swap(c->w_hist[0], c->w_hist[1]);
+    HIPCHK(c, hipMemcpyAsync(c->w_hist[0], c->w, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice,
+                             c->stream));
+    double *oldest = c->phi_hist[1];
+    c->phi_hist[1] = c->phi_hist[0];
+    c->phi_hist[0] = c->phi;
+    c->phi = c->phi_tmp;
+    c->phi_tmp = oldest;
     c->n_hist = std::min(c->n_hist + 1, 2);
     return HSF_OK;
 }
@@ -1077,14 +1123,15 @@ void hsf_destroy(hsf_ctx *c)
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    for (auto &g : c->graphs)
-        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    c->drop_graphs();
     for (auto &m : c->pending)
         if (m.pooled) {
             (void)hipEventDestroy(m.a);
             (void)hipEventDestroy(m.b);
         }
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->log_ev)
+        if (e) (void)hipEventDestroy(e);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (void *p : c->allocs) (void)hipFree(p);
     if (c->st_h) (void)hipHostFree(c->st_h);
@@ -1299,11 +1346,82 @@ static int rollback_step(hsf_ctx *c)
     return sync(c);
 }
 
+// Step log: the inversion's counts, right after it (later evaluations overwrite the
+// replica states).
+static void log_inversion(hsf_ctx *c)
+{
+    c->log_inv.resize(c->n_rep);
+    c->log_lnq.resize(c->n_rep);
+    for (int r = 0; r < c->n_rep; ++r) {
+        const RepState &S = c->st_h[r];
+        c->log_inv[r] = hsf_invert_stats{S.iters, S.evals, S.restarts, S.converged, S.res};
+        c->log_lnq[r] = S.ln_q;
+    }
+}
+
+// Step log: amounts and flow speed after a successful step, and the phase times.
+static int log_step(hsf_ctx *c, bool flow)
+{
+    launch_step_moments(c->stream, c->plan, c->n_rep, c->rep_d, c->ch.nsp, c->phi, flow ? c->u : nullptr, c->part,
+                        c->log_d);
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> h(4 * (size_t)c->n_rep);
+    if (int rc = copy_out(c, h.data(), c->log_d, h.size(), HSF_HOST)) return rc;
+    float t_inv = 0.0f, t_dyn = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&t_inv, c->log_ev[0], c->log_ev[1]));
+    HIPCHK(c, hipEventElapsedTime(&t_dyn, c->log_ev[1], c->log_ev[2]));
+    constexpr size_t kMaxRecords = (size_t)1 << 20;
+    for (int r = 0; r < c->n_rep; ++r) {
+        hsf_step_record e{};
+        e.step = c->steps_done;
+        e.replica = r;
+        e.iterations = c->log_inv[r].iterations;
+        e.evaluations = c->log_inv[r].evaluations;
+        e.converged = c->log_inv[r].converged;
+        e.residual = c->log_inv[r].residual;
+        e.ln_q = c->log_lnq[r];
+        for (int q = 0; q < 3; ++q) e.amount[q] = h[4 * r + q];
+        e.max_u = h[4 * r + 3];
+        e.ms_inversion = t_inv;
+        e.ms_dynamics = t_dyn;
+        if (c->log.size() >= kMaxRecords) c->log.pop_front();
+        c->log.push_back(e);
+    }
+    return HSF_OK;
+}
+
+int hsf_set_step_log(hsf_ctx *c, int on)
+{
+    if (!c) return HSF_EINVAL;
+    if (on && !c->log_d) {
+        if (int rc = dalloc(c, (void **)&c->log_d, sizeof(double) * 4 * c->n_rep)) return rc;
+        for (hipEvent_t &e : c->log_ev)
+            if (!e) HIPCHK(c, hipEventCreate(&e));
+    }
+    c->step_log = on ? 1 : 0;
+    if (!on) c->log.clear();
+    return HSF_OK;
+}
+
+int hsf_read_step_log(hsf_ctx *c, hsf_step_record *out, int max_records, int *n_read)
+{
+    if (!c || !out || !n_read || max_records < 0) return HSF_EINVAL;
+    int n = 0;
+    while (n < max_records && !c->log.empty()) {
+        out[n++] = c->log.front();
+        c->log.pop_front();
+    }
+    *n_read = n;
+    return HSF_OK;
+}
+
 int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats *stats, long long *total_evals)
 {
     if (!c || n_steps < 0) return HSF_EINVAL;
     if (total_evals) *total_evals = 0;
+    const bool logging = c->step_log != 0;
     for (int k = 0; k < n_steps; ++k) {
+        if (logging) HIPCHK(c, hipEventRecord(c->log_ev[0], c->stream));
         HIPCHK(c, hipMemcpyAsync(c->w_start, c->w, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice,
                                  c->stream));
         HIPCHK(c, hipMemcpyAsync(c->st_save, c->st_d, sizeof(RepState) * c->n_rep, hipMemcpyDeviceToDevice,
@@ -1323,6 +1441,10 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
             return rc;
         }
         if (rc != HSF_OK) return rc;
+        if (logging) {
+            log_inversion(c);
+            HIPCHK(c, hipEventRecord(c->log_ev[1], c->stream));
+        }
         *c->bad_h = 0;   // the kernels below set it on a non-finite result
         launch_mu(c->stream, c->plan, c->rep_d, c->ch, c->phi, c->w, c->mu);
         const double *uu = nullptr;
@@ -1355,6 +1477,11 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
             if (c->hydro) std::swap(c->nA, c->nB);
             if (c->noise) ++c->noise_step;
             if (rc != HSF_OK) return rc;
+            ++c->steps_done;
+            if (logging) {
+                HIPCHK(c, hipEventRecord(c->log_ev[2], c->stream));
+                if ((rc = log_step(c, c->hydro != 0))) return rc;
+            }
             continue;
         }
         {
@@ -1364,6 +1491,7 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
                       c->bad_hd);
         }
         HIPCHK(c, hipGetLastError());
+        if (logging) HIPCHK(c, hipEventRecord(c->log_ev[2], c->stream));
         if ((rc = sync(c))) return rc;
         if (*c->bad_h) {
             if (int r2 = rollback_step(c)) return r2;
@@ -1371,12 +1499,11 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
         }
         // the step succeeded: keep its inversion for the warm starts (with the targets phi^n),
         // then the new populations and densities
-        if ((rc = commit_history(c))) return rc;
+        if ((rc = commit_step(c))) return rc;
         if (c->hydro) std::swap(c->nA, c->nB);
         if (c->noise) ++c->noise_step;   // both noises of a coupled step share its step word
-        // the captured sequences hold the address of phi: copy the update back
-        HIPCHK(c, hipMemcpyAsync(c->phi, c->phi_tmp, sizeof(double) * c->ch.nsp * c->T,
-                                 hipMemcpyDeviceToDevice, c->stream));
+        ++c->steps_done;
+        if (logging && (rc = log_step(c, c->hydro != 0))) return rc;
         HIPCHK(c, hipGetLastError());
     }
     return HSF_OK;
@@ -1508,11 +1635,7 @@ int hsf_set_solver(hsf_ctx *c, int flags)
     if (pc != c->ch.precond) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         c->ch.precond = pc;
-        for (auto &g : c->graphs)   // the flag is a kernel argument of the captured sequences
-            if (g.exec) {
-                (void)hipGraphExecDestroy(g.exec);
-                g.exec = nullptr;
-            }
+        c->drop_graphs();   // the flag is a kernel argument of the captured sequences
     }
     return HSF_OK;
 }

@@ -171,6 +171,10 @@ void launch_cn_residual(hipStream_t s, double *F, const double *p, const double 
 void launch_observables(hipStream_t s, const Plan &p, int n_rep, const Rep *rep, const RepState *st, Chain ch,
                         const double *w, const double *phi, double *part, double *scratch, double *out);
 size_t observables_scratch_doubles(int n_rep);
+// Per replica r: out[4 r + I] = site sum of phi_I (I < nsp, else 0), out[4 r + 3] = max |u|
+// (0 when u is null); part holds kNQ doubles per plan block.
+void launch_step_moments(hipStream_t s, const Plan &p, int n_rep, const Rep *rep, int nsp, const double *phi,
+                         const double *u, double *part, double *out);
 
 }  // namespace hsf
 

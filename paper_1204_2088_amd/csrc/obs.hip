@@ -147,4 +147,80 @@ void launch_observables(hipStream_t s, const Plan &p, int n_rep, const Rep *rep,
 
 size_t observables_scratch_doubles(int n_rep) { return (size_t)n_rep * (kObsStride + 3); }
 
+// ---- per-step record: each species' amount and the largest flow speed ----
+
+// Slots 0-2: sum over the block's sites of phi_I; slot 3: the block's largest |u|^2
+// (0 without a velocity field).
+__global__ __launch_bounds__(kBlock) void k_step_sites(const int *__restrict__ blk_rep,
+                                                       const int *__restrict__ blk_first,
+                                                       const Rep *__restrict__ rep, int nsp,
+                                                       const double *__restrict__ phi,
+                                                       const double *__restrict__ u, double *__restrict__ part)
+{
+    const SiteRef sr = site_ref(blk_rep, blk_first);
+    const Rep &R = rep[sr.r];
+    const long long V = R.V, i = sr.i;
+    double v[3] = {0.0, 0.0, 0.0}, u2 = 0.0;
+    if (i < V) {
+        const double *p = phi + off_field(R, nsp);
+#pragma unroll
+        for (int I = 0; I < 3; ++I)
+            if (I < nsp) v[I] = p[I * V + i];
+        if (u) {
+            const double *uu = u + 3 * R.site_off;
+            const double a = uu[i], b = uu[V + i], c = uu[2 * V + i];
+            u2 = a * a + b * b + c * c;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double t = block_sum(v[q]);
+        if (threadIdx.x == 0) part[(long long)plan_block() * kNQ + q] = t;
+    }
+    __shared__ double wm[kBlock / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) u2 = fmax(u2, __shfl_down(u2, o, 64));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = u2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+#pragma unroll
+        for (int k = 0; k < kBlock / 64; ++k) m = fmax(m, wm[k]);
+        part[(long long)plan_block() * kNQ + 3] = m;
+    }
+}
+
+// One block per replica: out[4 r + I] = sum of phi_I (blocks in order), out[4 r + 3] = max |u|.
+__global__ __launch_bounds__(64) void k_step_reduce(const int *__restrict__ blk_first,
+                                                    const double *__restrict__ part, double *__restrict__ out)
+{
+    const int r = blockIdx.x, lane = threadIdx.x;
+    const int b0 = blk_first[r], b1 = blk_first[r + 1];
+    double s[3] = {0.0, 0.0, 0.0}, m = 0.0;
+    for (int b = b0 + lane; b < b1; b += 64) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s[q] += part[(long long)b * kNQ + q];
+        m = fmax(m, part[(long long)b * kNQ + 3]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s[q] += __shfl_down(s[q], o, 64);
+        m = fmax(m, __shfl_down(m, o, 64));
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) out[4 * r + q] = s[q];
+        out[4 * r + 3] = sqrt(m);
+    }
+}
+
+void launch_step_moments(hipStream_t s, const Plan &p, int n_rep, const Rep *rep, int nsp, const double *phi,
+                         const double *u, double *part, double *out)
+{
+    hipLaunchKernelGGL(k_step_sites, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, nsp, phi, u,
+                       part);
+    hipLaunchKernelGGL(k_step_reduce, dim3(n_rep), dim3(64), 0, s, p.blk_first, (const double *)part, out);
+}
+
 }  // namespace hsf

@@ -37,7 +37,7 @@ EXPORTED = [
     "hsf_net_last_error", "hsf_net_set_stream", "hsf_net_num_params", "hsf_net_set_params",
     "hsf_net_get_params", "hsf_net_set_input_norm", "hsf_net_set_output_scale", "hsf_net_forward", "hsf_net_loss_grad",
     "hsf_net_train_step", "hsf_attach_net", "hsf_set_net_gate", "hsf_paired_schedule", "hsf_net_make_sample",
-    "hsf_net_channel_moments", "hsf_net_affine",
+    "hsf_net_channel_moments", "hsf_net_affine", "hsf_set_step_log", "hsf_read_step_log",
 ]
 WARM_EXTRAP, WARM_NET, WARM_NET_DELTA, WARM_NET_EXTRAP = 2, 3, 4, 5
 SOLVER_PRECOND = 1
@@ -60,6 +60,18 @@ class CnStats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class StepRecord(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_longlong), ("replica", ctypes.c_int), ("iterations", ctypes.c_int),
+                ("evaluations", ctypes.c_int), ("converged", ctypes.c_int), ("residual", ctypes.c_double),
+                ("ln_q", ctypes.c_double), ("amount", ctypes.c_double * 3), ("max_u", ctypes.c_double),
+                ("ms_inversion", ctypes.c_double), ("ms_dynamics", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["amount"] = list(self.amount)
+        return d
 
 
 class Params(ctypes.Structure):
@@ -134,6 +146,8 @@ def load():
         "hsf_set_state": ([C, P, ctypes.c_longlong], I),
         "hsf_get_cn_stats": ([C, ctypes.POINTER(CnStats)], I),
         "hsf_set_timing": ([C, I], I),
+        "hsf_set_step_log": ([C, I], I),
+        "hsf_read_step_log": ([C, ctypes.POINTER(StepRecord), I, ctypes.POINTER(I)], I),
         "hsf_set_solver": ([C, I], I),
         "hsf_set_warm": ([C, I], I),
         "hsf_net_create": ([I, I, ctypes.POINTER(ctypes.c_int), ctypes.c_ulonglong, ctypes.POINTER(C)], I),
@@ -467,6 +481,30 @@ class Context:
         cnt = (ctypes.c_longlong * K_COUNT)()
         self._check(self._lib.hsf_get_timing(self._h, ms, cnt))
         return {KERNEL_NAMES[k]: (ms[k], cnt[k]) for k in range(K_COUNT)}
+
+    def set_step_log(self, on=True):
+        """Keep one record per replica and successful coupled step (hsf_set_step_log)."""
+        self._check(self._lib.hsf_set_step_log(self._h, int(bool(on))))
+
+    def read_step_log(self, max_records=4096):
+        """The unread step records, oldest first, as dicts (hsf_read_step_log)."""
+        out = []
+        buf = (StepRecord * max_records)()
+        while True:
+            n = ctypes.c_int(0)
+            self._check(self._lib.hsf_read_step_log(self._h, buf, int(max_records), ctypes.byref(n)))
+            out.extend(buf[k].as_dict() for k in range(n.value))
+            if n.value < max_records:
+                return out
+
+    def write_step_log(self, path):
+        """Append the unread step records to a JSON-lines file; returns how many."""
+        import json
+        recs = self.read_step_log()
+        with open(path, "a") as f:
+            for r in recs:
+                f.write(json.dumps(r) + "\n")
+        return len(recs)
 
 
 class Net:

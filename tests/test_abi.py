@@ -77,7 +77,8 @@ def test_param_structs_match_header(tmp_path):
     if gcc is None:
         pytest.skip("no host C compiler")
     from paper_1204_2088_amd import hsf
-    structs = {"hsf_params": hsf.Params, "hsf_invert_stats": hsf.InvertStats, "hsf_cn_stats": hsf.CnStats}
+    structs = {"hsf_params": hsf.Params, "hsf_invert_stats": hsf.InvertStats, "hsf_cn_stats": hsf.CnStats,
+               "hsf_step_record": hsf.StepRecord}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hsf.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
