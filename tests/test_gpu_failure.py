@@ -127,3 +127,29 @@ def test_nonfinite_step_rolls_back(hsf, precision, where):
         assert np.array_equal(a, b)
     ctx.close()
     ref.close()
+
+
+def test_unstable_time_step_is_reported(hsf):
+    """A time step far above the explicit scheme's stability limit (dt = 0.25 against a
+    limit of about 0.015 for kappa = 10): the composition's short-wavelength modes grow
+    every step until a step's inversion can no longer reach its targets; hsf_step then
+    reports the failure (HSF_ENOCONV or HSF_ENONFINITE) with the densities of that step's
+    start.  The same run at dt = 0.01 takes every step."""
+    wl = W.melt16_a4b4().with_(L=(12, 12, 12))
+    fails = None
+    for dt, steps in ((0.01, 40), (0.25, 40)):
+        ctx = hsf.Context(wl.with_(dt=dt))
+        ctx.set_densities(W.initial_composition(wl).ravel())
+        for k in range(steps):
+            before = ctx.get_densities()
+            try:
+                ctx.step(1, tol=1e-8, max_iter=300)
+            except hsf.HsfError as e:
+                assert dt == 0.25, (dt, k, e)
+                assert e.code in (hsf.HSF_ENOCONV, hsf.HSF_ENONFINITE)
+                fails = (k, e.code, float(np.abs(before - before.mean()).max()))
+                assert np.array_equal(ctx.get_densities(), before)
+                break
+        say(f"[unstable dt] dt {dt}: {'failure at step %d (code %d, max |dphi| %.3g)' % fails if dt == 0.25 else 'all steps taken'}")
+        ctx.close()
+    assert fails is not None, "the unstable run took every step"
