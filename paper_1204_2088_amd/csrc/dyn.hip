@@ -41,7 +41,40 @@ __device__ __forceinline__ long long sidx(const Rep &R, int x, int y, int z)
     return (long long)x + (long long)R.Lx * ((long long)y + (long long)R.Ly * z);
 }
 
-// mu_I = -w_I + sum_J chi_IJ sigma[phi_J] + kappa (sum_J phi_J - 1)
+// x-neighbours by lane exchange.  In a site plan the lanes of a wavefront hold
+// consecutive sites of one replica, so the lane to the left holds site x - 1 of the same
+// row unless the site is the first of its row or the lane the first of its wavefront,
+// and likewise to the right; those lanes load the neighbour instead.  Every lane takes
+// part in the exchange (lanes past the box's end work on its last site and store
+// nothing); the values are the loads they replace, so results are unchanged bit for bit.
+struct XLanes {
+    bool lw, rw;   // the neighbour is held by the adjacent lane
+    int dl, dr;    // offsets of the periodic x - 1 and x + 1 from the site
+};
+
+__device__ __forceinline__ XLanes x_lanes(int x, int Lx)
+{
+    const int lane = threadIdx.x & 63;
+    XLanes n;
+    n.lw = lane > 0 && x > 0;
+    n.rw = lane < 63 && x < Lx - 1;
+    n.dl = x > 0 ? -1 : Lx - 1;
+    n.dr = x < Lx - 1 ? 1 : 1 - Lx;
+    return n;
+}
+
+// f at x - 1 and x + 1 of site k, given c = f[k].
+__device__ __forceinline__ void x_pair(const double *f, long long k, double c, const XLanes &n, double &l, double &r)
+{
+    l = from_left(c);
+    r = from_right(c);
+    if (!n.lw) l = f[k + n.dl];
+    if (!n.rw) r = f[k + n.dr];
+}
+
+// mu_I = -w_I + sum_J chi_IJ sigma[phi_J] + kappa (sum_J phi_J - 1); the stencil sums
+// are formed per class (centre, faces, edges, corners) as in stencil27.
+template <int NSP>
 __global__ __launch_bounds__(kBlock) void k_mu(const int *__restrict__ blk_rep, const int *__restrict__ blk_first,
                                                const Rep *__restrict__ rep, Chain ch,
                                                const double *__restrict__ phi, const double *__restrict__ w,
@@ -49,19 +82,47 @@ __global__ __launch_bounds__(kBlock) void k_mu(const int *__restrict__ blk_rep, 
 {
     const SiteRef sr = site_ref(blk_rep, blk_first);
     const Rep &R = rep[sr.r];
-    const long long V = R.V, i = sr.i;
-    if (i >= V) return;
+    const long long V = R.V;
+    const bool live = sr.i < V;
+    const long long i = live ? sr.i : V - 1;
     int x, y, z;
     site_xyz(R, i, x, y, z);
-    const long long fo = off_field(R, ch.nsp);
+    const XLanes xn = x_lanes(x, R.Lx);
+    const long long fo = off_field(R, NSP);
+    const int ym = wrap1(y - 1, R.Ly), yp = wrap1(y + 1, R.Ly), zm = wrap1(z - 1, R.Lz), zp = wrap1(z + 1, R.Lz);
+    auto at = [&](int yy, int zz) { return (long long)x + (long long)R.Lx * ((long long)yy + (long long)R.Ly * zz); };
+    const long long k0 = at(y, z), k1[4] = {at(ym, z), at(yp, z), at(y, zm), at(y, zp)},
+                    k2[4] = {at(ym, zm), at(ym, zp), at(yp, zm), at(yp, zp)};
     double sp[3] = {0, 0, 0}, tot = 0.0;
-    for (int J = 0; J < ch.nsp; ++J) {
-        sp[J] = stencil27<double>(phi + fo + J * V, x, y, z, R.Lx, R.Ly, R.Lz, R.c[0], R.c[1], R.c[2], R.c[3]);
-        tot += phi[fo + J * V + i];
+#pragma unroll 1   // one species at a time: unrolled over the species the kernel needs 172 registers
+    for (int J = 0; J < NSP; ++J) {
+        const double *f = phi + fo + J * V;
+        double c = f[k0], l, r;
+        x_pair(f, k0, c, xn, l, r);
+        double s0 = c, s1 = l + r, s2 = 0, s3 = 0;
+        tot += c;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {   // rows with exactly one of (dy, dz) non-zero
+            c = f[k1[q]];
+            x_pair(f, k1[q], c, xn, l, r);
+            s1 += c;
+            s2 += l + r;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {   // rows with both non-zero
+            c = f[k2[q]];
+            x_pair(f, k2[q], c, xn, l, r);
+            s2 += c;
+            s3 += l + r;
+        }
+        sp[J] = R.c[0] * s0 + R.c[1] * s1 + R.c[2] * s2 + R.c[3] * s3;
     }
-    for (int I = 0; I < ch.nsp; ++I) {
+    if (!live) return;
+#pragma unroll
+    for (int I = 0; I < NSP; ++I) {
         double inter = 0.0;
-        for (int J = 0; J < ch.nsp; ++J) inter += R.chi[I][J] * sp[J];
+#pragma unroll
+        for (int J = 0; J < NSP; ++J) inter += R.chi[I][J] * sp[J];
         mu[fo + I * V + i] = -w[fo + I * V + i] + inter + R.kappa * (tot - 1.0);
     }
 }
@@ -310,7 +371,7 @@ __global__ __launch_bounds__(kBlock) void k_lb(const int *__restrict__ blk_rep, 
 // phi_new(r) = phi(r) - sum_a (J(r + e_a/2) - J(r - e_a/2)).
 // NOISE adds the composition noise of eq. 5 as a random flux on every bond, drawn
 // beforehand by k_cd_noise into jn.
-template <bool NOISE>
+template <bool NOISE, int NSP>
 __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, const int *__restrict__ blk_first,
                                                const Rep *__restrict__ rep, Chain ch,
                                                const double *__restrict__ phi, const double *__restrict__ mu,
@@ -320,41 +381,66 @@ __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, 
 {
     const SiteRef sr = site_ref(blk_rep, blk_first);
     const Rep &R = rep[sr.r];
-    const long long V = R.V, i = sr.i;
-    if (i >= V) return;
+    const long long V = R.V;
+    const bool live = sr.i < V;
+    const long long i = live ? sr.i : V - 1;
     int x, y, z;
     site_xyz(R, i, x, y, z);
-    const long long fo = off_field(R, ch.nsp), vo = 3LL * R.site_off;
-    const long long nb[6] = {sidx(R, wrap1(x - 1, R.Lx), y, z), sidx(R, wrap1(x + 1, R.Lx), y, z),
+    const XLanes xn = x_lanes(x, R.Lx);
+    const long long fo = off_field(R, NSP), vo = 3LL * R.site_off;
+    const long long nb[6] = {i + xn.dl, i + xn.dr,
                              sidx(R, x, wrap1(y - 1, R.Ly), z), sidx(R, x, wrap1(y + 1, R.Ly), z),
                              sidx(R, x, y, wrap1(z - 1, R.Lz)), sidx(R, x, y, wrap1(z + 1, R.Lz))};
     const double dt = R.dt * diff_scale;   // diffusive flux over dt (or dt/2 in the CN step)
-    for (int I = 0; I < ch.nsp; ++I) {
+    // the velocity at the site and its six neighbours, shared by the species
+    double ul[3] = {0, 0, 0}, ur[3] = {0, 0, 0}, uh[3] = {0, 0, 0};
+    if (u) {
+        const double *ux = u + vo;
+        ur[0] = ux[i];
+        x_pair(ux, i, ur[0], xn, ul[0], uh[0]);
+#pragma unroll
+        for (int a = 1; a < 3; ++a) {
+            const double *ua = u + vo + a * V;
+            ul[a] = ua[nb[2 * a]];
+            ur[a] = ua[i];
+            uh[a] = ua[nb[2 * a + 1]];
+        }
+    }
+#pragma unroll
+    for (int I = 0; I < NSP; ++I) {
         const double *p = phi + fo + I * V;
         const double *m = mu + fo + I * V;
         const double pr = p[i], mr = m[i];
+        double pn_l[3], pn_h[3], mn_l[3], mn_h[3];
+        x_pair(p, i, pr, xn, pn_l[0], pn_h[0]);
+        x_pair(m, i, mr, xn, mn_l[0], mn_h[0]);
+#pragma unroll
+        for (int a = 1; a < 3; ++a) {
+            pn_l[a] = p[nb[2 * a]];
+            pn_h[a] = p[nb[2 * a + 1]];
+            mn_l[a] = m[nb[2 * a]];
+            mn_h[a] = m[nb[2 * a + 1]];
+        }
         double div = 0.0;
         const double *jI = NOISE ? jn + 3 * fo + 3 * I * V : nullptr;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const long long lo = nb[2 * a], hi = nb[2 * a + 1];
             // face between lo and r, then between r and hi
-            const double pl = p[lo], ph = p[hi];
-            double jl = dt * (-0.5 * (pl + pr) * (mr - m[lo]));
-            double jh = dt * (-0.5 * (pr + ph) * (m[hi] - mr));
+            const double pl = pn_l[a], ph = pn_h[a];
+            double jl = dt * (-0.5 * (pl + pr) * (mr - mn_l[a]));
+            double jh = dt * (-0.5 * (pr + ph) * (mn_h[a] - mr));
             if (u) {
-                const double *ua = u + vo + a * V;
-                const double ul = ua[lo], ur = ua[i], uh = ua[hi];
-                jl += (0.5 * (pl + pr) - 0.5 * (pr * ur - pl * ul)) * (0.5 * (ul + ur));
-                jh += (0.5 * (pr + ph) - 0.5 * (ph * uh - pr * ur)) * (0.5 * (ur + uh));
+                jl += (0.5 * (pl + pr) - 0.5 * (pr * ur[a] - pl * ul[a])) * (0.5 * (ul[a] + ur[a]));
+                jh += (0.5 * (pr + ph) - 0.5 * (ph * uh[a] - pr * ur[a])) * (0.5 * (ur[a] + uh[a]));
             }
             if (NOISE) {
-                jl += jI[a * V + lo];
+                jl += jI[a * V + nb[2 * a]];
                 jh += jI[a * V + i];
             }
             div += jh - jl;
         }
         const double pn = pr - div;
+        if (!live) continue;
         if (bad && !isfinite(pn)) bad[0] = 1;
         phi_out[fo + I * V + i] = pn;
     }
@@ -427,7 +513,8 @@ __global__ __launch_bounds__(kBlock) void k_lb_convert(const int *__restrict__ b
 void launch_mu(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi, const double *w,
                double *mu)
 {
-    hipLaunchKernelGGL(k_mu, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first, rep, ch, phi, w, mu);
+    hipLaunchKernelGGL(ch.nsp == 3 ? k_mu<3> : k_mu<2>, dim3(p.nblocks), dim3(kBlock), 0, s, p.blk_rep, p.blk_first,
+                       rep, ch, phi, w, mu);
 }
 
 void launch_force(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const double *phi, const double *mu,
@@ -484,7 +571,7 @@ void launch_cd(hipStream_t s, const Plan &p, const Rep *rep, Chain ch, const dou
                                phi, noise_flux, step);
         e0 = nullptr;
     }
-    auto kern = noise_flux ? k_cd<true> : k_cd<false>;
+    auto kern = noise_flux ? (ch.nsp == 3 ? k_cd<true, 3> : k_cd<true, 2>) : (ch.nsp == 3 ? k_cd<false, 3> : k_cd<false, 2>);
     if (e0 || e1)
         hipExtLaunchKernelGGL(kern, dim3(p.nblocks), dim3(kBlock), 0, s, e0, e1, 0, p.blk_rep, p.blk_first, rep,
                               ch, phi, mu, u, phi_out, (const double *)noise_flux, diff_scale, bad);
