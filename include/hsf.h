@@ -371,8 +371,18 @@ int hsf_set_hydro(hsf_ctx *ctx, int on);
 /* Inversion variant.  0 (default): plain Fletcher-Reeves on the gradient
  * g = phi^t - phi[w].  HSF_SOLVER_PRECOND: the steepest-descent vector is
  * z = g / phi^t (diagonal preconditioning by the target densities), with
- * beta = (g_new.z_new)/(g_old.z_old); same line search and stopping test. */
-enum { HSF_SOLVER_PRECOND = 1 };
+ * beta = (g_new.z_new)/(g_old.z_old); same line search and stopping test.
+ * HSF_SOLVER_REFINE (FP32 contexts; no effect in FP64 ones): the FP32 propagators'
+ * rounding bounds the residual an inversion can reach (1e-7 to 3e-6, by box and
+ * composition); with this flag an inversion asked for a residual below 1e-5 iterates with
+ * FP32 evaluations down to 1e-5 and then with FP64 evaluations (the same iteration,
+ * restarted along the steepest descent direction) down to tol, each phase with at most
+ * max_iter iterations; the
+ * statistics add up both phases.  The first call that sets it allocates the FP64
+ * propagators (8 (N + 6) bytes per site; HSF_ENOMEM if short); HSF_EINVAL if the tiling
+ * in use does not fit the LDS in FP64, and while it is on hsf_set_tile and hsf_autotune
+ * only take tilings that do. */
+enum { HSF_SOLVER_PRECOND = 1, HSF_SOLVER_REFINE = 2 };
 int hsf_set_solver(hsf_ctx *ctx, int flags);
 
 /* Work done by inversions since creation or the last reset: the number of

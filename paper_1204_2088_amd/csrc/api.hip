@@ -72,6 +72,10 @@ struct hsf_ctx {
     double *obs = nullptr;             // observables scratch; results in its last 3 n_rep doubles
     // propagators in the chosen precision
     void *E = nullptr, *G = nullptr, *Gp0 = nullptr, *Gp1 = nullptr, *Gf0 = nullptr, *Gf1 = nullptr;
+    // FP64 propagators of the refinement phase of FP32 contexts (HSF_SOLVER_REFINE)
+    int refine = 0;
+    bool eval64 = false;               // evaluations currently run in FP64
+    void *E64 = nullptr, *G64 = nullptr, *Gp64[2] = {nullptr, nullptr}, *Gf64[2] = {nullptr, nullptr};
     std::vector<void *> allocs;
 
     // hipGraphs of the fixed launch sequences (captured at first use, replayed after)
@@ -85,11 +89,13 @@ struct hsf_ctx {
     struct GraphSlot {
         hipGraphExec_t exec = nullptr;
         const void *key = nullptr;     // the density buffer the sequence was captured with
+        bool key64 = false;            // and whether its evaluations ran in FP64
     };
     enum { GK_START = 0, GK_TRIAL, GK_UPDATE, GK_EVAL, GK_COUNT };
     // a coupled step rotates the densities among four buffers (current, update, two history
-    // entries), so each sequence has one captured variant per density buffer
-    static constexpr int kGraphVariants = 4;
+    // entries), so each sequence has one captured variant per density buffer, and one per
+    // precision of the evaluations
+    static constexpr int kGraphVariants = 8;
     GraphSlot graphs[GK_COUNT][kGraphVariants];
     void drop_graphs()
     {
@@ -98,6 +104,7 @@ struct hsf_ctx {
                 if (g.exec) (void)hipGraphExecDestroy(g.exec);
                 g.exec = nullptr;
                 g.key = nullptr;
+                g.key64 = false;
             }
     }
 
@@ -269,7 +276,8 @@ int run_seq(hsf_ctx *c, int kind, F &&body)
     }
     hsf_ctx::GraphSlot *slots = c->graphs[kind];
     int v = 0;
-    while (v < hsf_ctx::kGraphVariants && slots[v].exec && slots[v].key != c->phi) ++v;
+    while (v < hsf_ctx::kGraphVariants && slots[v].exec && (slots[v].key != c->phi || slots[v].key64 != c->eval64))
+        ++v;
     if (v == hsf_ctx::kGraphVariants) {   // not reached with the four density buffers; recapture
         v = 0;
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -279,6 +287,7 @@ int run_seq(hsf_ctx *c, int kind, F &&body)
     hsf_ctx::GraphSlot &g = slots[v];
     if (!g.exec) {
         g.key = c->phi;
+        g.key64 = c->eval64;
         hipStream_t user = c->stream;
         if (!user && !c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         hipStream_t cs = user ? user : c->cap_stream;
@@ -307,12 +316,22 @@ template <typename real>
 PropBufs<real> bufs(hsf_ctx *c)
 {
     PropBufs<real> b;
+    if (sizeof(real) == sizeof(double) && c->precision == HSF_FP32) {   // refinement phase
+        b.E = (real *)c->E64;
+        b.G = (real *)c->G64;
+        b.Gp[0] = (real *)c->Gp64[0];
+        b.Gp[1] = (real *)c->Gp64[1];
+        return b;
+    }
     b.E = (real *)c->E;
     b.G = (real *)c->G;
     b.Gp[0] = (real *)c->Gp0;
     b.Gp[1] = (real *)c->Gp1;
     return b;
 }
+
+// Real size the tilings must fit in LDS: the context's, or FP64 while refinement is on.
+size_t lds_real_size(const hsf_ctx *c) { return c->refine ? sizeof(double) : real_size(c); }
 
 // Blocks of the tile plan of configuration t for every replica.
 void tile_blocks(const hsf_ctx *c, const TileCfg &t, std::vector<int> &blk_rep, std::vector<int> &blk_first)
@@ -398,7 +417,8 @@ void run_eval_paired(hsf_ctx *c, int use_alpha, int final_mode, double *out, con
 {
     PropBufs<real> b = bufs<real>(c);
     const int N = c->ch.N;
-    real *Gf[2] = {(real *)c->Gf0, (real *)c->Gf1};
+    const bool alt = sizeof(real) == sizeof(double) && c->precision == HSF_FP32;   // refinement phase
+    real *Gf[2] = {(real *)(alt ? c->Gf64[0] : c->Gf0), (real *)(alt ? c->Gf64[1] : c->Gf1)};
     int parity = 0;
     for (int j = 1; j <= N; ++j) {
         const PairSteps ps = paired_steps(N, j);
@@ -484,7 +504,7 @@ void run_eval(hsf_ctx *c, int use_alpha, int final_mode, double *out, const doub
 // sums: also produce the per-step propagator sums that update the FP32 scales
 void run_eval_any(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d, int sums)
 {
-    if (c->precision == HSF_FP32)
+    if (c->precision == HSF_FP32 && !c->eval64)
         run_eval<float>(c, use_alpha, final_mode, out, d, sums);
     else
         run_eval<double>(c, use_alpha, final_mode, out, d, sums);
@@ -610,8 +630,8 @@ int commit_step(hsf_ctx *c)
 
 // commit_hist: record the result in the warm-start history here (hsf_invert); a coupled
 // step records it only once the whole step has succeeded.
-int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats *stats, long long *evals_out,
-                bool commit_hist = true)
+int invert_once(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats *stats, long long *evals_out,
+                bool commit_hist)
 {
     if (!(tol >= 0.0) || max_iter < 0) return fail(c, HSF_EINVAL, "bad tol %g or max_iter %d", tol, max_iter);
     if (warm < HSF_WARM_CURRENT || warm > HSF_WARM_NET_EXTRAP) return fail(c, HSF_EINVAL, "bad warm mode %d", warm);
@@ -695,6 +715,40 @@ int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
     if (commit_hist && status != HSF_ENONFINITE)
         if (int rc2 = commit_history(c)) return rc2;
     return status;
+}
+
+// Residual down to which an FP32 context with refinement iterates with FP32 evaluations
+// before it switches to FP64 ones: above the level where the FP32 evaluations' rounding
+// stalls the iteration (measured 1e-7 to 3e-6 relative, by box and composition), so the
+// FP32 phase does not stall.
+constexpr double kRefineTol = 1e-5;
+
+// The inversion.  FP32 contexts with refinement (HSF_SOLVER_REFINE) asked for a residual
+// below kRefineTol run two phases: FP32 evaluations to kRefineTol, then FP64 evaluations
+// from those fields (the same Fletcher-Reeves iteration, restarted from its steepest
+// descent direction) to tol; the counts of both phases are added.
+int invert_impl(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats *stats, long long *evals_out,
+                bool commit_hist = true)
+{
+    if (!(c->refine && c->precision == HSF_FP32 && tol < kRefineTol))
+        return invert_once(c, tol, max_iter, warm, stats, evals_out, commit_hist);
+    if (!(tol >= 0.0) || max_iter < 0) return fail(c, HSF_EINVAL, "bad tol %g or max_iter %d", tol, max_iter);
+    std::vector<hsf_invert_stats> first(c->n_rep);
+    int rc = invert_once(c, kRefineTol, max_iter, warm, first.data(), evals_out, false);
+    // a first phase stopped by its iteration limit still hands its fields to the second
+    if (rc != HSF_OK && rc != HSF_ENOCONV) return rc;
+    c->eval64 = true;
+    std::vector<hsf_invert_stats> second(c->n_rep);
+    rc = invert_once(c, tol, max_iter, HSF_WARM_CURRENT, second.data(), evals_out, commit_hist);
+    c->eval64 = false;
+    if (stats)
+        for (int r = 0; r < c->n_rep; ++r) {
+            stats[r] = second[r];
+            stats[r].iterations += first[r].iterations;
+            stats[r].evaluations += first[r].evaluations;
+            stats[r].restarts += first[r].restarts;
+        }
+    return rc;
 }
 
 // One evaluation of the density functional at the current fields, with phibar from the
@@ -1544,7 +1598,7 @@ int hsf_set_tile(hsf_ctx *c, const int cfg[4])
     if (!c || !cfg) return HSF_EINVAL;
     TileCfg t{cfg[0], cfg[1], cfg[2], cfg[3]};
     if (!tile_known(t)) return fail(c, HSF_EINVAL, "tile %d,%d,%d,%d is not instantiated", t.cx, t.cy, t.cz, t.k);
-    if (tile_lds_bytes(t, real_size(c)) > c->lds_limit) return fail(c, HSF_EINVAL, "tile exceeds the LDS limit");
+    if (tile_lds_bytes(t, lds_real_size(c)) > c->lds_limit) return fail(c, HSF_EINVAL, "tile exceeds the LDS limit");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return set_tile(c, t);
 }
@@ -1579,7 +1633,7 @@ int hsf_autotune(hsf_ctx *c, int reps, double *best_ms)
 #undef HSF_CANDS
 #undef HSF_CAND
     for (const TileCfg &t : cands) {
-        if (tile_lds_bytes(t, real_size(c)) > c->lds_limit) continue;
+        if (tile_lds_bytes(t, lds_real_size(c)) > c->lds_limit) continue;
         if ((rc = set_tile(c, t)) != HSF_OK) break;
         // `reps` evaluations (exp, sweeps, Q, normalisation; state untouched), captured in a
         // graph and replayed as the inversion replays them
@@ -1630,8 +1684,22 @@ int hsf_autotune(hsf_ctx *c, int reps, double *best_ms)
 
 int hsf_set_solver(hsf_ctx *c, int flags)
 {
-    if (!c || (flags & ~HSF_SOLVER_PRECOND)) return HSF_EINVAL;
+    if (!c || (flags & ~(HSF_SOLVER_PRECOND | HSF_SOLVER_REFINE))) return HSF_EINVAL;
     const int pc = (flags & HSF_SOLVER_PRECOND) ? 1 : 0;
+    const int rf = (flags & HSF_SOLVER_REFINE) && c->precision == HSF_FP32 ? 1 : 0;
+    if (rf && !c->refine) {
+        if (tile_lds_bytes(c->tile, sizeof(double)) > c->lds_limit)
+            return fail(c, HSF_EINVAL, "the tiling in use does not fit the LDS in FP64");
+        // the FP64 propagators of the refinement phase, made once (each buffer only if a
+        // call before ran out of memory before reaching it)
+        const size_t T = (size_t)c->T;
+        void **bufs64[6] = {&c->E64, &c->G64, &c->Gp64[0], &c->Gp64[1], &c->Gf64[0], &c->Gf64[1]};
+        const size_t sizes[6] = {2 * T, (size_t)c->ch.N * T, T, T, T, T};
+        for (int k = 0; k < 6; ++k)
+            if (!*bufs64[k])
+                if (int rc = dalloc(c, bufs64[k], sizeof(double) * sizes[k])) return rc;
+    }
+    c->refine = rf;
     if (pc != c->ch.precond) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         c->ch.precond = pc;

@@ -40,7 +40,7 @@ EXPORTED = [
     "hsf_net_channel_moments", "hsf_net_affine", "hsf_set_step_log", "hsf_read_step_log",
 ]
 WARM_EXTRAP, WARM_NET, WARM_NET_DELTA, WARM_NET_EXTRAP = 2, 3, 4, 5
-SOLVER_PRECOND = 1
+SOLVER_PRECOND, SOLVER_REFINE = 1, 2
 LB_BGK, LB_MRT = 0, 1
 NOISE_CD, NOISE_LB = 1, 2
 CD_EXPLICIT, CD_CRANK_NICOLSON = 0, 1
@@ -448,9 +448,11 @@ class Context:
         self._check(self._lib.hsf_autotune(self._h, int(reps), ctypes.byref(ms)))
         return self.get_tile(), ms.value
 
-    def set_solver(self, precond=False):
-        """Plain Fletcher-Reeves (default) or the diagonally preconditioned variant."""
-        self._check(self._lib.hsf_set_solver(self._h, SOLVER_PRECOND if precond else 0))
+    def set_solver(self, precond=False, refine=False):
+        """Plain Fletcher-Reeves (default) or the diagonally preconditioned variant; refine:
+        FP32 contexts finish inversions below a residual of 1e-5 with FP64 evaluations."""
+        flags = (SOLVER_PRECOND if precond else 0) | (SOLVER_REFINE if refine else 0)
+        self._check(self._lib.hsf_set_solver(self._h, flags))
 
     def get_work(self, reset=False):
         """(evaluations, sum over replicas of evaluations x sites) since the last reset."""

@@ -799,3 +799,78 @@ def test_paired_sweeps_coupled_steps_bitwise(hsf, orc, precision):
         out.append((ctx.get_densities(), ctx.get_fields()))
         ctx.close()
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("kind", ["melt", "solution"])
+def test_fp32_refinement_below_the_fp32_floor(hsf, orc, kind):
+    """FP32 contexts with HSF_SOLVER_REFINE reach a residual the FP32 evaluations cannot
+    (1e-10; on these boxes FP32 alone stalls near 3e-6): without the flag the inversion stops at
+    max_iter; with it the FP64 oracle's densities at the GPU's fields reproduce the target
+    to 1e-9 relative, the fields equal those of an FP64 context after gauge fixing (1e-7
+    relative), and the statistics add both phases.  Coupled steps with the flag keep every
+    step's residual below the tolerance; a context on a caller's tiling that does not fit
+    FP64 LDS refuses the flag."""
+    if kind == "melt":
+        wl = small_melt(L=(16, 12, 10), types=W.chain(4, 4)).with_(precision="fp32")
+        sysw = osys(orc, wl)
+        wt = fields_for(wl, seed=7, amp=0.8)
+        phit, _ = orc.evaluate(sysw, wt - wt.mean(axis=(1, 2, 3), keepdims=True), 1.0, 0.0)
+    else:
+        wl = small_solution(precision="fp32")
+        sysw = osys(orc, wl)
+        phit = W.initial_composition(wl)
+    say(f"[refine {kind}]")
+    ctx = hsf.Context(wl)
+    ctx.set_densities(phit.ravel())
+    st, rc = ctx.invert(tol=1e-10, max_iter=200, warm=hsf.WARM_LOCAL, allow_noconv=True)
+    say(f"  fp32 alone: {st[0]}")
+    assert rc == hsf.HSF_ENOCONV and st[0]["residual"] > 1e-8
+    ctx.set_solver(refine=True)
+    ctx.set_fields(np.zeros(ctx.nsp * ctx.T))
+    st, rc = ctx.invert(tol=1e-10, max_iter=2000, warm=hsf.WARM_LOCAL)
+    say(f"  refined: {st[0]}")
+    assert rc == hsf.HSF_OK and st[0]["converged"] and st[0]["residual"] <= 1e-10
+    w = ctx.get_fields().reshape((wl.nsp,) + wl.shape)
+    phibar_s = phit[2].mean() if wl.nsp == 3 else 0.0
+    ref, _ = orc.evaluate(sysw, w, phit[:2].sum(0).mean(), phibar_s)
+    e = max(np.max(np.abs(ref[I] - phit[I])) / np.max(np.abs(phit[I])) for I in range(wl.nsp))
+    say(f"  FP64 oracle residual at the refined fields {e:.2e}")
+    assert e < 1e-9
+    c64 = hsf.Context(wl.with_(precision="fp64"))
+    c64.set_densities(phit.ravel())
+    c64.invert(tol=1e-11, max_iter=2000, warm=hsf.WARM_LOCAL)
+    w64 = c64.get_fields().reshape(w.shape)
+    for I in range(2):
+        d = (w[I] - w[I].mean()) - (w64[I] - w64[I].mean())
+        assert np.max(np.abs(d)) <= 1e-7 * max(1.0, np.max(np.abs(w64[I]))), I
+    c64.close()
+    # coupled steps with refinement
+    ctx.set_densities(W.initial_composition(wl).ravel())
+    for _ in range(3):
+        st, _ = ctx.step(1, tol=1e-9, max_iter=2000)
+        assert st[0]["converged"] and st[0]["residual"] <= 1e-9
+    ctx.close()
+
+
+def test_refinement_refuses_tilings_that_do_not_fit(hsf):
+    """The 8x8x8 tiling with 4 levels needs 40 KiB of LDS in FP32 and 72 KiB in FP64: where
+    the device's limit per workgroup lies between the two, the flag is refused while that
+    tiling is in use, and while the flag is on hsf_set_tile refuses that tiling."""
+    wl = small_melt(L=(16, 16, 16), types=W.chain(4, 4)).with_(precision="fp32")
+    ctx = hsf.Context(wl)
+    ctx.set_tile((8, 8, 8, 4))
+    try:
+        ctx.set_solver(refine=True)
+    except hsf.HsfError as e:
+        assert e.code == hsf.HSF_EINVAL
+        ctx.set_tile((32, 8, 2, -1))
+        ctx.set_solver(refine=True)
+        with pytest.raises(hsf.HsfError) as ei:
+            ctx.set_tile((8, 8, 8, 4))
+        assert ei.value.code == hsf.HSF_EINVAL
+        ctx.set_solver(refine=False)
+        ctx.set_tile((8, 8, 8, 4))
+        say("[refine tiles] 8x8x8x4 refused with refinement on")
+    else:
+        say("[refine tiles] the LDS limit holds the FP64 8x8x8x4 tiling: nothing to refuse")
+    ctx.close()
