@@ -311,11 +311,9 @@ __global__ __launch_bounds__(kBlock) void k_target_stats(const int *__restrict__
         v[4] = w[fo + i];
         v[5] = w[fo + V + i];
     }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const double t = block_sum(v[q]);
-        if (threadIdx.x == 0) part[(long long)plan_block() * kNQ + q] = t;
-    }
+    block_sums(v);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 6; ++q) part[(long long)plan_block() * kNQ + q] = v[q];
 }
 
 void launch_target_stats(hipStream_t s, const Plan &p, const Rep *rep, RepState *, Chain ch,
@@ -417,10 +415,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const int *__restrict__ bl
             dhd += dI * dI * phit[fo + I * V + i];
         }
     }
-    double t = block_sum(dg);
-    if (threadIdx.x == 0) part[(long long)plan_block() * kNQ + 0] = t;
-    t = block_sum(dhd);
-    if (threadIdx.x == 0) part[(long long)plan_block() * kNQ + 1] = t;
+    double t[2] = {dg, dhd};
+    block_sums(t);
+    if (threadIdx.x == 0) {
+        part[(long long)plan_block() * kNQ + 0] = t[0];
+        part[(long long)plan_block() * kNQ + 1] = t[1];
+    }
 }
 
 void launch_cg_update(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch, int init,

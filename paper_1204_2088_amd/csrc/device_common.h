@@ -91,6 +91,33 @@ __device__ __forceinline__ double block_sum(double v)
     return t;
 }
 
+// Block sums of NV values at once, each bit for bit block_sum's (the same shuffle tree
+// and the same order over the wavefronts), with one barrier pair for all of them.  Every
+// thread must call it; the results are valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV])
+{
+    __shared__ double ws[NV][kBlock / 64];
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) ws[q][wid] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < kBlock / 64; ++k) t += ws[q][k];
+            v[q] = t;
+        }
+    __syncthreads();
+}
+
 // 27-point linkage stencil at (x, y, z): weights by the number of non-zero offset
 // components, summed per class (centre, 6 faces, 12 edges, 8 corners).
 template <typename real>

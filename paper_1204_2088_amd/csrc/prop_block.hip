@@ -355,11 +355,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd_block(const int *__restrict__ bl
         }
     }
     if (s_lo == 1 && final_mode == 1) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const double t = block_sum(sums[q]);
-            if (threadIdx.x == 0) part[(long long)plan_block() * kNQ + q] = t;
-        }
+        block_sums(sums);
+        if (threadIdx.x == 0)
+            for (int q = 0; q < 4; ++q) part[(long long)plan_block() * kNQ + q] = sums[q];
     }
 }
 
@@ -865,11 +863,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(r
         }
     }
     if (FINAL && final_mode == 1) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const double t = block_sum(sums[q]);
-            if (threadIdx.x == 0) part[(long long)plan_block() * kNQ + q] = t;
-        }
+        block_sums(sums);
+        if (threadIdx.x == 0)
+            for (int q = 0; q < 4; ++q) part[(long long)plan_block() * kNQ + q] = sums[q];
     }
 }
 

@@ -405,11 +405,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd_stream(const int *__restrict__ b
         for (int j = 0; j < H; ++j) pend[j] = pnew[j];
     }
     if (fin && final_mode == 1) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const double v = block_sum(sums[q]);
-            if (threadIdx.x == 0) part[(long long)pb * kNQ + q] = v;
-        }
+        block_sums(sums);
+        if (threadIdx.x == 0)
+            for (int q = 0; q < 4; ++q) part[(long long)pb * kNQ + q] = sums[q];
     }
 }
 
