@@ -1400,17 +1400,12 @@ static int rollback_step(hsf_ctx *c)
     return sync(c);
 }
 
-// Step log: the inversion's counts, right after it (later evaluations overwrite the
-// replica states).
+// Step log: ln Q of the inversion's last evaluation, right after it (later evaluations
+// overwrite the replica states); the counts arrive in log_inv from the inversion.
 static void log_inversion(hsf_ctx *c)
 {
-    c->log_inv.resize(c->n_rep);
     c->log_lnq.resize(c->n_rep);
-    for (int r = 0; r < c->n_rep; ++r) {
-        const RepState &S = c->st_h[r];
-        c->log_inv[r] = hsf_invert_stats{S.iters, S.evals, S.restarts, S.converged, S.res};
-        c->log_lnq[r] = S.ln_q;
-    }
+    for (int r = 0; r < c->n_rep; ++r) c->log_lnq[r] = c->st_h[r].ln_q;
 }
 
 // Step log: amounts and flow speed after a successful step, and the phase times.
@@ -1474,6 +1469,9 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
     if (!c || n_steps < 0) return HSF_EINVAL;
     if (total_evals) *total_evals = 0;
     const bool logging = c->step_log != 0;
+    if (logging) c->log_inv.assign(c->n_rep, hsf_invert_stats{});
+    // the step log needs the counts of every step's inversion (both phases with refinement)
+    hsf_invert_stats *inv = logging ? c->log_inv.data() : stats;
     for (int k = 0; k < n_steps; ++k) {
         if (logging) HIPCHK(c, hipEventRecord(c->log_ev[0], c->stream));
         HIPCHK(c, hipMemcpyAsync(c->w_start, c->w, sizeof(double) * c->ch.nsp * c->T, hipMemcpyDeviceToDevice,
@@ -1483,8 +1481,9 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
         // with Crank-Nicolson the fields of phi^n are already converged (phi^n = phi[w^n]
         // after an implicit step): the inversion only confirms them
         const bool implicit = c->integrator == HSF_CD_CRANK_NICOLSON;
-        int rc = invert_impl(c, tol, max_iter, implicit ? HSF_WARM_CURRENT : c->step_warm, stats, total_evals,
+        int rc = invert_impl(c, tol, max_iter, implicit ? HSF_WARM_CURRENT : c->step_warm, inv, total_evals,
                              false);
+        if (logging && stats) std::copy(c->log_inv.begin(), c->log_inv.end(), stats);
         if (rc == HSF_ENONFINITE) {
             std::string msg = c->err;
             if (int r2 = rollback_step(c)) return r2;

@@ -121,3 +121,23 @@ def test_step_log_skips_failed_steps_and_stops(hsf):
     ctx.step(1, tol=1e-9, max_iter=2000)
     assert ctx.read_step_log() == []
     ctx.close()
+
+
+def test_step_log_counts_both_refinement_phases(hsf):
+    """With FP64 refinement on (FP32 contexts), a record's counts are the step's whole
+    inversion, both phases, as hsf_step's statistics give them."""
+    wls = [w.with_(precision="fp32") for w in batch(True)]
+    ctx = hsf.Context(wls)
+    ctx.set_densities(np.concatenate([W.initial_composition(w).ravel() for w in wls]))
+    ctx.set_solver(refine=True)
+    ctx.set_step_log(True)
+    for _ in range(2):
+        stats, _ = ctx.step(1, tol=1e-9, max_iter=2000)
+    recs = ctx.read_step_log()
+    assert len(recs) == 4
+    for r in range(2):
+        rec = recs[2 + r]
+        assert rec["iterations"] == stats[r]["iterations"] and rec["evaluations"] == stats[r]["evaluations"]
+        assert rec["residual"] == stats[r]["residual"] and rec["residual"] <= 1e-9
+    say(f"[step log, refined] {recs[-1]}")
+    ctx.close()
