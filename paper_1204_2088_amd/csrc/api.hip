@@ -91,7 +91,7 @@ struct hsf_ctx {
         const void *key = nullptr;     // the density buffer the sequence was captured with
         bool key64 = false;            // and whether its evaluations ran in FP64
     };
-    enum { GK_START = 0, GK_TRIAL, GK_UPDATE, GK_EVAL, GK_COUNT };
+    enum { GK_START = 0, GK_PASS, GK_EVAL, GK_COUNT };
     // a coupled step rotates the densities among four buffers (current, update, two history
     // entries), so each sequence has one captured variant per density buffer, and one per
     // precision of the evaluations
@@ -673,13 +673,11 @@ int invert_once(hsf_ctx *c, double tol, int max_iter, int warm, hsf_invert_stats
             if (--guard < 0)   // the iterate is kept, as at max_iter
                 return fail(c, HSF_ENOCONV, "inversion stopped after %lld passes without finishing",
                             3LL * max_iter + 3);
-            rc = run_seq(c, hsf_ctx::GK_TRIAL, [&] {
+            // the pass (trial evaluation and update) as one captured sequence: one launch
+            rc = run_seq(c, hsf_ctx::GK_PASS, [&] {
                 run_eval_any(c, 1, 1, c->gt, c->d, 0);
                 launch_reduce_ctl(c->stream, c->n_rep, c->tplan, c->st_d, c->rep_d, c->part, PH_TRIAL, c->ch,
                                   c->partG, 0.0, 0, c->st_hd);
-            });
-            if (rc) return rc;
-            rc = run_seq(c, hsf_ctx::GK_UPDATE, [&] {
                 launch_cg_update(c->stream, c->plan, c->rep_d, c->st_d, c->ch, 0, c->w, c->g, c->gt, c->d, c->phi,
                                  c->part);
                 launch_reduce_ctl(c->stream, c->n_rep, c->plan, c->st_d, c->rep_d, c->part, PH_BEGIN, c->ch,
