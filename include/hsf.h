@@ -152,7 +152,12 @@ typedef struct hsf_ctx hsf_ctx;
  * LB and convection-diffusion updates (text after eq. 17).  All replicas must share n_beads, types, has_solvent and
  * precision.  Densities start at zero, fields at zero, LB populations at rest
  * with density 1.  Returns HSF_EINVAL on inconsistent parameters, HSF_ENOMEM
- * when device memory is short. */
+ * when device memory is short.  Environment, read here: HSF_TILE=cx,cy,cz,k sets the
+ * starting tiling; HSF_NO_GRAPHS=1 launches every kernel directly instead of replaying
+ * captured sequences; HSF_POISON=1 fills every device buffer the context allocates (now
+ * or later) with 0xff bytes, a NaN in FP32 and FP64, so that results that depend on memory
+ * no kernel has written come out different (a checking aid; results are otherwise
+ * unchanged). */
 int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out);
 
 /* Free every device buffer of the context (waits for its stream). */

@@ -81,6 +81,7 @@ struct hsf_ctx {
     // hipGraphs of the fixed launch sequences (captured at first use, replayed after)
     hipStream_t cap_stream = nullptr;  // own stream for capture when the caller's is the null stream
     int use_graphs = 1;
+    int poison = 0;                    // new buffers filled with NaN bytes (HSF_POISON=1)
     struct EvPair {
         int kind;
         hipEvent_t a, b;
@@ -162,6 +163,8 @@ int dalloc(hsf_ctx *c, void **p, size_t bytes)
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) return fail(c, HSF_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     c->allocs.push_back(*p);
+    if (c->poison && (e = hipMemset(*p, 0xff, bytes)) != hipSuccess)
+        return fail(c, HSF_EHIP, "hipMemset failed: %s", hipGetErrorString(e));
     return HSF_OK;
 }
 
@@ -1002,6 +1005,10 @@ int hsf_create(const hsf_params *reps, int n_rep, hsf_ctx **out)
     hsf_ctx *c = new hsf_ctx();
     const char *ng = getenv("HSF_NO_GRAPHS");   // debugging aid: launch every kernel directly
     c->use_graphs = (ng && ng[0] == '1') ? 0 : 1;
+    // checking aid: every device buffer the context allocates starts filled with NaN bytes
+    // (0xff), so a kernel that reads memory no kernel or copy has written yet spreads NaN
+    const char *pz = getenv("HSF_POISON");
+    c->poison = (pz && pz[0] == '1') ? 1 : 0;
     c->n_rep = n_rep;
     c->precision = p0.precision;
     c->hydro = p0.hydro ? 1 : 0;
