@@ -200,9 +200,10 @@ RECIPE_NETS = {"vesicle128_a3b9s": ["vesicle_a3b9s_w8-16-24-32.npz", "vesicle_a3
 def learned_arm(hsf, workload, precision, steps, tile, log, precond=False, widths=None):
     """The learned warm start on the benchmark's own workload: the recipe's networks
     (trained on the GPU from FP64 trajectories of other seeds, loaded from the package), or
-    a network trained in this run when they are absent; then the plain (previous fields),
-    extrapolated and learned warm starts (with and without the gate) each run the
-    benchmark's whole trajectory from the quench (seed 0, same tiling), every step timed."""
+    a network trained in this run when they are absent; then the cold (local guess), plain
+    (previous fields), extrapolated and learned warm starts (with and without the gate) each
+    run the benchmark's whole trajectory from the quench (seed 0, same tiling), every step
+    timed."""
     from paper_1204_2088_amd import warmnet
     from paper_1204_2088_amd import workloads as W
     nets, infos = {}, {}
@@ -223,10 +224,17 @@ def learned_arm(hsf, workload, precision, steps, tile, log, precond=False, width
         nets[name], infos[name] = net, dict(info, file="trained in this run")
     log(f"# warm-start networks: {infos}")
     wls = make_workloads(workload, precision)
-    windows = [(0, 100), (100, 1000), (1000, 3000)]
+    cold_steps = min(steps, 300)
+    windows = [(0, 100), (100, 1000), (1000, 3000), (0, cold_steps)]
+    # cold: every inversion from the local ideal-gas guess w_I = -ln phi_I (no memory of the
+    # previous step; about 25 times slower per step, so it runs the first cold_steps steps
+    # only); plain: the previous step's fields; extrapolated: 2 w^n - w^(n-1)
+    res = warmnet.trajectory_arms(wls, None, [("cold", hsf.WARM_LOCAL, 0)], cold_steps,
+                                  [(0, 100), (100, cold_steps), (0, cold_steps)], tol=wls[0].tol,
+                                  precision=precision, tile=tile, precond=precond, log=log)
     base = [("plain", hsf.WARM_CURRENT, 0), ("extrapolated", hsf.WARM_EXTRAP, 0)]
-    res = warmnet.trajectory_arms(wls, None, base, steps, windows, tol=wls[0].tol, precision=precision, tile=tile,
-                                  precond=precond, log=log)
+    res.update(warmnet.trajectory_arms(wls, None, base, steps, windows, tol=wls[0].tol, precision=precision,
+                                       tile=tile, precond=precond, log=log))
     learned_names = []
     for name, net in nets.items():
         arms = [(f"learned_{name}", hsf.WARM_NET_EXTRAP, 0), (f"learned_{name}_gate2", hsf.WARM_NET_EXTRAP, 2)]
@@ -239,13 +247,17 @@ def learned_arm(hsf, workload, precision, steps, tile, log, precond=False, width
     ml = res[best_learned]["whole"]["ms_mean"]
     return {
         "tol": wls[0].tol, "steps": steps, "solver": "preconditioned FR" if precond else "FR",
-        "protocol": "each warm start runs the whole trajectory from the quench (seed 0), every step timed; "
-                    "windows are step ranges of that trajectory; gate2: the network is used only after an "
-                    "inversion of at least 2 iterations, else the extrapolation",
+        "protocol": "each warm start runs the whole trajectory from the quench (seed 0), every step timed "
+                    "(the cold start its first cold_steps steps, compared with the same steps of the best "
+                    "learned arm); windows are step ranges of that trajectory; gate2: the network is used "
+                    "only after an inversion of at least 2 iterations, else the extrapolation",
         "networks": infos,
         "arms": res,
         "best_learned_arm": best_learned,
         "best_non_learned_arm": best_plain,
+        "speedup_learned_vs_cold": res["cold"]["whole"]["ms_mean"]
+        / res[best_learned]["windows"][f"0-{cold_steps}"]["ms_mean"],
+        "cold_steps": cold_steps,
         "speedup_learned_vs_plain": res["plain"]["whole"]["ms_mean"] / ml,
         "speedup_learned_vs_extrapolated": res["extrapolated"]["whole"]["ms_mean"] / ml,
         "speedup_learned_vs_best_non_learned": res[best_plain]["whole"]["ms_mean"] / ml,
