@@ -195,9 +195,13 @@ LEARNED = {
 # Networks trained by the vesicle recipe (python -m paper_1204_2088_amd.warmnet DIR: 40 seeds x
 # 500 steps of the same chemistry at 64^3), shipped with the package.
 RECIPE_NETS = {"vesicle128_a3b9s": ["vesicle_a3b9s_w8-16-24-32.npz", "vesicle_a3b9s_w16.npz"]}
+# The other learned warm starts of the same recipe (--extra-arms): the first-difference
+# network (NET_DELTA) and the direct map phi -> w (NET).
+RECIPE_EXTRA = {"vesicle128_a3b9s": [("delta", "vesicle_a3b9s_delta_w16.npz", "WARM_NET_DELTA"),
+                                     ("direct", "vesicle_a3b9s_direct_w16.npz", "WARM_NET")]}
 
 
-def learned_arm(hsf, workload, precision, steps, tile, log, precond=False, widths=None):
+def learned_arm(hsf, workload, precision, steps, tile, log, precond=False, widths=None, extra=False):
     """The learned warm start on the benchmark's own workload: the recipe's networks
     (trained on the GPU from FP64 trajectories of other seeds, loaded from the package), or
     a network trained in this run when they are absent; then the cold (local guess), plain
@@ -242,6 +246,18 @@ def learned_arm(hsf, workload, precision, steps, tile, log, precond=False, width
                                            tile=tile, precond=precond, log=log))
         learned_names += [a[0] for a in arms]
         net.close()
+    if extra:
+        for tag, fname, mode in RECIPE_EXTRA.get(workload, []):
+            path = os.path.join(ROOT, "paper_1204_2088_amd", "nets", fname)
+            if not os.path.exists(path):
+                continue
+            net, info = warmnet.load_net(path)
+            infos[f"{tag}_w16"] = dict(info, file=f"paper_1204_2088_amd/nets/{fname}")
+            arms = [(f"learned_{tag}_w16", getattr(hsf, mode), 0)]
+            res.update(warmnet.trajectory_arms(wls, net, arms, steps, windows, tol=wls[0].tol, precision=precision,
+                                               tile=tile, precond=precond, log=log))
+            learned_names += [a[0] for a in arms]
+            net.close()
     best_learned = min(learned_names, key=lambda k: res[k]["whole"]["ms_mean"])
     best_plain = min(("plain", "extrapolated"), key=lambda k: res[k]["whole"]["ms_mean"])
     ml = res[best_learned]["whole"]["ms_mean"]
@@ -419,6 +435,9 @@ def main():
                     help="diagonally preconditioned inversion (auto: on for solutions)")
     ap.add_argument("--tile", default=None, help="cx,cy,cz,k: use this propagator tiling instead of autotuning (k = 0: one step per launch, -1: paired forward/backward steps, >= 1: temporally blocked)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
+    ap.add_argument("--extra-arms", action="store_true",
+                    help="also run the NET_DELTA and NET warm starts of the recipe (first-difference and direct-map "
+                         "networks) over the same trajectory")
     ap.add_argument("--compare-steps", type=int, default=3000,
                     help="trajectory length of each warm start in the learned comparison")
     ap.add_argument("--net-widths", default=None, metavar="WIDTHS",
@@ -541,7 +560,8 @@ def main():
     if args.workload in LEARNED and not args.no_learned:
         learned = learned_arm(hsf, args.workload, args.precision, args.compare_steps, tuple(tile), log,
                               precond=precond,
-                              widths=tuple(int(v) for v in args.net_widths.split(",")) if args.net_widths else None)
+                              widths=tuple(int(v) for v in args.net_widths.split(",")) if args.net_widths else None,
+                              extra=args.extra_arms)
 
     extra = {}
     if not args.no_extra and args.workload == "vesicle128_a3b9s":

@@ -465,15 +465,17 @@ int hsf_net_loss_grad(hsf_net *net, const float *in, const float *target, int ba
 /* one Adam step (beta 0.9, 0.999, eps 1e-8) on the mean square error */
 int hsf_net_train_step(hsf_net *net, const float *in, const float *target, int batch, int L, float lr,
                        double *loss, int where);
-/* Training data of the delta warm starts, assembled on the device (the network's
- * stream), for one replica from three states of an inversion trajectory: the target
- * densities and converged fields phi, w of a step, phi_n, w_n of the step before and
- * phi_p, w_p of the one before that (device pointers, field layout [nsp][V], FP64).
- * x (device, FP32 [2 nsp][V]) receives the input HSF_WARM_NET_DELTA (mode 1) or
- * HSF_WARM_NET_EXTRAP (mode 2) feeds the network, (phi_n, delta phi / r), and y (device,
- * FP32 [2][V]) the matching target delta w / r of the polymer fields, with delta the
- * first (mode 1: phi - phi_n) or second (mode 2: phi - 2 phi_n + phi_p) difference and r
- * the rms of delta phi over species and sites.  phi_p, w_p may be NULL in mode 1. */
+/* Training data of the warm starts, assembled on the device (the network's stream), for
+ * one replica from up to three states of an inversion trajectory: the target densities
+ * and converged fields phi, w of a step, phi_n, w_n of the step before and phi_p, w_p of
+ * the one before that (device pointers, field layout [nsp][V], FP64).  Mode 0 (the direct
+ * map of HSF_WARM_NET): x (device, FP32 [nsp][V]) receives phi and y (device, FP32 [2][V])
+ * the polymer fields w; phi_n, w_n, phi_p, w_p may be NULL.  Modes 1 and 2: x (FP32
+ * [2 nsp][V]) receives the input HSF_WARM_NET_DELTA (mode 1) or HSF_WARM_NET_EXTRAP
+ * (mode 2) feeds the network, (phi_n, delta phi / r), and y (FP32 [2][V]) the matching
+ * target delta w / r of the polymer fields, with delta the first (mode 1: phi - phi_n) or
+ * second (mode 2: phi - 2 phi_n + phi_p) difference and r the rms of delta phi over
+ * species and sites; phi_p, w_p may be NULL in mode 1. */
 int hsf_net_make_sample(hsf_net *net, const double *phi, const double *phi_n, const double *phi_p, const double *w,
                         const double *w_n, const double *w_p, int nsp, long long V, int mode, float *x, float *y);
 /* x_c = (x_c - shift[c]) * scale[c] for each channel c of x (device, FP32

@@ -610,9 +610,13 @@ int hsf_net_make_sample(hsf_net *n, const double *phi, const double *phi_n, cons
                         const double *w_n, const double *w_p, int nsp, long long V, int mode, float *x, float *y)
 {
     if (!n) return HSF_EINVAL;
-    if (!phi || !phi_n || !w || !w_n || !x || !y || (mode == 2 && (!phi_p || !w_p)) || (mode != 1 && mode != 2) ||
-        (nsp != 2 && nsp != 3) || V < 1)
+    if (!phi || !w || !x || !y || (mode >= 1 && (!phi_n || !w_n)) || (mode == 2 && (!phi_p || !w_p)) || mode < 0 ||
+        mode > 2 || (nsp != 2 && nsp != 3) || V < 1)
         return nfail(n, HSF_EINVAL, "bad sample arguments");
+    if (mode == 0) {   // the direct map: only the step's own state is read
+        phi_n = phi_p = phi;
+        w_n = w_p = w;
+    }
     net_sample(n->stream, phi, phi_n, mode == 2 ? phi_p : phi_n, w, w_n, mode == 2 ? w_p : w_n, nsp, V, mode, n->aux,
                kAuxParts, n->aux + kAuxParts, x, y);
     NCHK(n, hipGetLastError());

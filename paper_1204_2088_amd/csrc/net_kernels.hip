@@ -791,14 +791,15 @@ __global__ void k_warm_apply(double *__restrict__ w, const float *__restrict__ p
     w[e] = v;
 }
 
-// Training target of one replica: y = delta w / rms over the polymer channels
-// (the first 2 V values of the field layout), delta as in warm_delta.
+// Training target of one replica over the polymer channels (the first 2 V values of the
+// field layout): mode 0, the fields themselves; modes 1 and 2, delta w / rms with delta as
+// in warm_delta.
 __global__ void k_net_target(const double *__restrict__ w, const double *__restrict__ w0,
                              const double *__restrict__ w1, long long n, int mode, const double *__restrict__ rms,
                              float *__restrict__ y)
 {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) y[e] = (float)(warm_delta(w, w0, w1, e, mode) / rms[0]);
+    if (e < n) y[e] = (float)(mode == 0 ? w[e] : warm_delta(w, w0, w1, e, mode) / rms[0]);
 }
 
 // Per-channel partial sums of x and x^2 over batch and sites: block (c, k) of a grid of

@@ -327,12 +327,14 @@ def trajectory_arms(wls, net, arms, steps, windows, tol=1e-6, precision="fp32", 
 # second-difference sample per replica and step, assembled on the device by the library
 # (hsf_net_make_sample) and stored in half precision (the matrix cores read bfloat16).
 
-def record_recipe_samples(wls, steps, first, tol=1e-10, precond=True, log=None, store_dtype=None, net_io=None):
+def record_recipe_samples(wls, steps, first, tol=1e-10, precond=True, log=None, store_dtype=None, net_io=None,
+                          modes=(2,)):
     """Run the replicas `wls` (one batched FP64 context, residual tol, extrapolated warm
     start) for `steps` coupled steps and, for every step k >= first (first >= 2), build one
-    second-difference sample per replica from the states of steps k - 2, k - 1, k.
-    Returns (X [S][2 nsp][V], Y [S][2][V]) device tensors of dtype store_dtype (default
-    float16) and the wall time."""
+    sample per replica and mode from the states of steps k - 2, k - 1, k: mode 2, the
+    second difference (NET_EXTRAP); mode 1, the first difference (NET_DELTA); mode 0, the
+    direct map phi -> w (NET).  Returns ({mode: (X [S][C][V], Y [S][2][V])}, wall time), the
+    tensors on the device in store_dtype (default float16), C = nsp in mode 0, else 2 nsp."""
     torch = _torch()
     store_dtype = store_dtype or torch.float16
     ctx = hsf.Context(wls, precision="fp64")
@@ -346,12 +348,13 @@ def record_recipe_samples(wls, steps, first, tol=1e-10, precond=True, log=None, 
     assert all(wl.V == V for wl in wls)
     R = len(wls)
     n_samples = R * max(0, steps - first)
-    X = torch.empty((n_samples, 2 * nsp, V), dtype=store_dtype, device="cuda")
-    Y = torch.empty((n_samples, 2, V), dtype=store_dtype, device="cuda")
+    chans = {m: (nsp if m == 0 else 2 * nsp) for m in modes}
+    store = {m: (torch.empty((n_samples, chans[m], V), dtype=store_dtype, device="cuda"),
+                 torch.empty((n_samples, 2, V), dtype=store_dtype, device="cuda")) for m in modes}
     ring_phi = [torch.empty(nsp * T, dtype=torch.float64, device="cuda") for _ in range(3)]
     ring_w = [torch.empty(nsp * T, dtype=torch.float64, device="cuda") for _ in range(3)]
-    xb = torch.empty((2 * nsp, V), dtype=torch.float32, device="cuda")
-    yb = torch.empty((2, V), dtype=torch.float32, device="cuda")
+    bufs = {m: (torch.empty((chans[m], V), dtype=torch.float32, device="cuda"),
+                torch.empty((2, V), dtype=torch.float32, device="cuda")) for m in modes}
     k_s = 0
     t0 = time.perf_counter()
     for k in range(steps):
@@ -363,17 +366,21 @@ def record_recipe_samples(wls, steps, first, tol=1e-10, precond=True, log=None, 
             for r in range(R):
                 o = ctx.field_offset(r)
                 sl = slice(o, o + nsp * V)
-                net_io.make_sample(ring_phi[a][sl], ring_phi[b][sl], ring_phi[c][sl], ring_w[a][sl], ring_w[b][sl],
-                                   ring_w[c][sl], nsp, V, 2, xb, yb)
-                X[k_s].copy_(xb)
-                Y[k_s].copy_(yb)
+                for m in modes:
+                    xb, yb = bufs[m]
+                    net_io.make_sample(ring_phi[a][sl], ring_phi[b][sl] if m >= 1 else None,
+                                       ring_phi[c][sl] if m == 2 else None, ring_w[a][sl],
+                                       ring_w[b][sl] if m >= 1 else None, ring_w[c][sl] if m == 2 else None,
+                                       nsp, V, m, xb, yb)
+                    store[m][0][k_s].copy_(xb)
+                    store[m][1][k_s].copy_(yb)
                 k_s += 1
         if log and k % 50 == 0:
             log(f"  recipe trajectory step {k}: iterations {min(s['iterations'] for s in st)}.."
                 f"{max(s['iterations'] for s in st)} ({time.perf_counter() - t0:.1f} s, {k_s} samples)")
     torch.cuda.synchronize()
     ctx.close()
-    return X[:k_s], Y[:k_s], time.perf_counter() - t0
+    return {m: (X[:k_s], Y[:k_s]) for m, (X, Y) in store.items()}, time.perf_counter() - t0
 
 
 def chunked_moments(net_io, T, chunk=64):
@@ -452,55 +459,67 @@ def load_net(path):
     return net, json.loads(str(z["info"]))
 
 
+# File name of a recipe network per sample mode (2: the benchmark's NET_EXTRAP networks).
+RECIPE_PREFIX = {2: "vesicle_a3b9s", 1: "vesicle_a3b9s_delta", 0: "vesicle_a3b9s_direct"}
+RECIPE_SAMPLE = {2: "second difference per replica and step", 1: "first difference per replica and step",
+                 0: "the state itself (phi -> w) per replica and step"}
+
+
 def train_recipe(out_dir, seeds=tuple(range(1, 41)), steps=502, first=2, L=64, widths_list=((8, 16, 24, 32), (16,)),
-                 iters=12000, batch=4, val_seed=99, log=None):
+                 iters=12000, batch=4, val_seed=99, log=None, modes=(2,)):
     """The benchmark's recipe: 40 seeds x 500 recorded steps of the A3B9 + S vesicle
-    chemistry at 64^3 (20 000 (phi, w) states, FP64, residual 1e-10), one second-
-    difference sample per replica and step (about 20 000 samples), a held-out seed for
-    validation, then each network of widths_list trained on the same samples and saved
-    to out_dir.  Returns {name: info}."""
+    chemistry at 64^3 (20 000 (phi, w) states, FP64, residual 1e-10), one sample per
+    replica, step and mode (second difference, mode 2, for the benchmark's networks; first
+    difference, mode 1, and the direct map, mode 0, for the other warm starts), a held-out
+    seed for validation, then each network of widths_list trained on the same samples and
+    saved to out_dir.  Returns {file name: info}."""
     import os
     torch = _torch()
     os.makedirs(out_dir, exist_ok=True)
     mk = lambda seed: W.vesicle128_a3b9s(L=L).with_(seed=seed, precision="fp64")
     nsp = 3
     io = hsf.Net(2 * nsp, 2, (8,), seed=0)   # sample assembly and reductions
-    X, Y, t_data = record_recipe_samples([mk(s) for s in seeds], steps, first, log=log, net_io=io)
-    Xv, Yv, _ = record_recipe_samples([mk(val_seed)], 40, 10, log=None, net_io=io)
+    data, t_data = record_recipe_samples([mk(s) for s in seeds], steps, first, log=log, net_io=io, modes=modes)
+    vdata, _ = record_recipe_samples([mk(val_seed)], 40, 10, log=None, net_io=io, modes=modes)
     states = len(seeds) * (steps - first)
-    if log:
-        log(f"  {X.shape[0]} samples from {states} states in {t_data:.1f} s")
-    xm, xr = chunked_moments(io, X)
-    ym, yr = chunked_moments(io, Y)
-    shift = [float(xm[c]) if c < nsp else 0.0 for c in range(2 * nsp)]
-    scale = [1.0 / max(float(np.sqrt(max(xr[c] ** 2 - xm[c] ** 2, 0.0))), 1e-6) if c < nsp else 1.0
-             for c in range(2 * nsp)]
-    out_rms = [max(float(v), 1e-30) for v in yr]
-    y_scale = [1.0 / v for v in out_rms]
-    io.close()
     results = {}
-    for widths in widths_list:
-        net = hsf.Net(2 * nsp, 2, widths, seed=1)
-        net.set_input_norm(shift, scale)
-        losses, val, t_train = train_from_store(net, X, Y, L, iters, batch, 1e-3, 1e-4, y_scale, log=log, Xv=Xv,
-                                                Yv=Yv)
-        name = "w" + "-".join(str(w) for w in widths)
-        info = {"recipe": f"{len(seeds)} seeds x {steps - first} steps of the A3B9 + S vesicle chemistry at "
-                          f"{L}^3 (FP64 propagators, preconditioned inversion to 1e-10, extrapolated warm start)",
-                "states": states, "samples": int(X.shape[0]), "sample": "second difference per replica and step",
-                "storage": "float16", "widths": list(widths), "parameters": int(net.n_params),
-                "iterations": iters, "batch": batch, "lr": [1e-3, 1e-4],
-                "loss_first": float(np.mean(losses[:50])), "loss_last": float(np.mean(losses[-500:])),
-                "validation_loss": val, "validation": f"seed {val_seed}, steps 10-39",
-                "loss_units": "mean square error of targets scaled to unit rms per channel",
-                "target_rms": out_rms, "data_seconds": t_data, "train_seconds": t_train}
-        net.set_output_scale(out_rms)
-        save_net(os.path.join(out_dir, f"vesicle_a3b9s_{name}.npz"), net, widths, 2 * nsp, 2, shift, scale, out_rms,
-                 info)
-        results[name] = info
+    for mode in modes:
+        X, Y = data[mode]
+        Xv, Yv = vdata[mode]
+        cin = X.shape[1]
         if log:
-            log(f"  network {name}: {info}")
-        net.close()
+            log(f"  mode {mode}: {X.shape[0]} samples from {states} states in {t_data:.1f} s")
+        xm, xr = chunked_moments(io, X)
+        ym, yr = chunked_moments(io, Y)
+        # density channels standardised over the data; difference channels are unit rms already
+        shift = [float(xm[c]) if c < nsp else 0.0 for c in range(cin)]
+        scale = [1.0 / max(float(np.sqrt(max(xr[c] ** 2 - xm[c] ** 2, 0.0))), 1e-6) if c < nsp else 1.0
+                 for c in range(cin)]
+        out_rms = [max(float(v), 1e-30) for v in yr]
+        y_scale = [1.0 / v for v in out_rms]
+        for widths in widths_list:
+            net = hsf.Net(cin, 2, widths, seed=1)
+            net.set_input_norm(shift, scale)
+            losses, val, t_train = train_from_store(net, X, Y, L, iters, batch, 1e-3, 1e-4, y_scale, log=log, Xv=Xv,
+                                                    Yv=Yv)
+            name = "w" + "-".join(str(w) for w in widths)
+            info = {"recipe": f"{len(seeds)} seeds x {steps - first} steps of the A3B9 + S vesicle chemistry at "
+                              f"{L}^3 (FP64 propagators, preconditioned inversion to 1e-10, extrapolated warm start)",
+                    "states": states, "samples": int(X.shape[0]), "sample": RECIPE_SAMPLE[mode], "mode": mode,
+                    "storage": "float16", "widths": list(widths), "parameters": int(net.n_params),
+                    "iterations": iters, "batch": batch, "lr": [1e-3, 1e-4],
+                    "loss_first": float(np.mean(losses[:50])), "loss_last": float(np.mean(losses[-500:])),
+                    "validation_loss": val, "validation": f"seed {val_seed}, steps 10-39",
+                    "loss_units": "mean square error of targets scaled to unit rms per channel",
+                    "target_rms": out_rms, "data_seconds": t_data, "train_seconds": t_train}
+            net.set_output_scale(out_rms)
+            fname = f"{RECIPE_PREFIX[mode]}_{name}.npz"
+            save_net(os.path.join(out_dir, fname), net, widths, cin, 2, shift, scale, out_rms, info)
+            results[fname] = info
+            if log:
+                log(f"  network {fname}: {info}")
+            net.close()
+    io.close()
     return results
 
 
@@ -513,7 +532,12 @@ if __name__ == "__main__":
     ap.add_argument("--seeds", type=int, default=40)
     ap.add_argument("--steps", type=int, default=502)
     ap.add_argument("--iters", type=int, default=12000)
+    ap.add_argument("--modes", default="2", help="sample modes, comma separated (2: second difference, "
+                    "1: first difference, 0: direct map)")
+    ap.add_argument("--widths", default="8,16,24,32;16", help="networks to train, widths separated by ';'")
     args = ap.parse_args()
     res = train_recipe(args.out_dir, seeds=tuple(range(1, args.seeds + 1)), steps=args.steps, iters=args.iters,
-                       log=lambda m: print(m, file=sys.stderr, flush=True))
+                       log=lambda m: print(m, file=sys.stderr, flush=True),
+                       modes=tuple(int(m) for m in args.modes.split(",")),
+                       widths_list=tuple(tuple(int(v) for v in w.split(",")) for w in args.widths.split(";")))
     print(json.dumps(res))

@@ -410,15 +410,16 @@ def test_output_scale(hsf):
     net.train_step(x.ravel(), t.ravel(), 1, 16, 1e-3)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_sample_assembly_matches_numpy(hsf, mode):
     """The training samples, channel statistics and target scaling the library assembles
-    on the device against the header's formulas evaluated with numpy in FP64: x = (phi_n,
-    delta phi / r), y = delta w / r over the two polymer fields, delta the first (mode 1)
-    or second (mode 2) difference and r the rms of delta phi over species and sites; the
-    per-channel mean and rms over samples and sites; x_c = (x_c - shift_c) scale_c.  A
-    ragged box of 40 x 41 x 17 sites (several hundred blocks per launch); the FP32 outputs
-    within 1e-6 relative of the FP64 values (one rounding)."""
+    on the device against the header's formulas evaluated with numpy in FP64: mode 0,
+    x = phi and y = the two polymer fields; modes 1 and 2, x = (phi_n, delta phi / r),
+    y = delta w / r over the two polymer fields, delta the first (mode 1) or second
+    (mode 2) difference and r the rms of delta phi over species and sites; the per-channel
+    mean and rms over samples and sites; x_c = (x_c - shift_c) scale_c.  A ragged box of
+    40 x 41 x 17 sites (several hundred blocks per launch); the FP32 outputs within 1e-6
+    relative of the FP64 values (one rounding)."""
     import torch
     rng = np.random.default_rng(31 + mode)
     nsp, V = 3, 40 * 41 * 17
@@ -426,33 +427,37 @@ def test_sample_assembly_matches_numpy(hsf, mode):
     ws = [rng.standard_normal(nsp * V) for _ in range(3)]
     dev = [torch.as_tensor(a, device="cuda") for a in st + ws]
     phi, phi_n, phi_p, w, w_n, w_p = dev
-    net = hsf.Net(2 * nsp, 2, (8,), seed=2)
+    cin = nsp if mode == 0 else 2 * nsp
+    net = hsf.Net(cin, 2, (8,), seed=2)
     B = 3
-    x = torch.empty(B, 2 * nsp, V, dtype=torch.float32, device="cuda")
+    x = torch.empty(B, cin, V, dtype=torch.float32, device="cuda")
     y = torch.empty(B, 2, V, dtype=torch.float32, device="cuda")
     for b in range(B):   # shifted copies make distinct samples
-        net.make_sample(phi, phi_n, phi_p if mode == 2 else None, torch.roll(w, b), w_n, w_p if mode == 2 else None,
-                        nsp, V, mode, x[b], y[b])
+        net.make_sample(phi, phi_n if mode >= 1 else None, phi_p if mode == 2 else None, torch.roll(w, b),
+                        w_n if mode >= 1 else None, w_p if mode == 2 else None, nsp, V, mode, x[b], y[b])
     torch.cuda.synchronize()
-    dphi = st[0] - st[1] if mode == 1 else st[0] - 2 * st[1] + st[2]
-    r = np.sqrt(np.mean(dphi ** 2))
-    xr = np.concatenate([st[1], dphi / r])
+    if mode == 0:
+        r, xr = 1.0, st[0]
+    else:
+        dphi = st[0] - st[1] if mode == 1 else st[0] - 2 * st[1] + st[2]
+        r = np.sqrt(np.mean(dphi ** 2))
+        xr = np.concatenate([st[1], dphi / r])
     got = x.cpu().numpy().astype(np.float64)
     for b in range(B):
         wb = np.roll(ws[0], b)
-        dw = (wb - ws[1]) if mode == 1 else (wb - 2 * ws[1] + ws[2])
+        dw = wb if mode == 0 else ((wb - ws[1]) if mode == 1 else (wb - 2 * ws[1] + ws[2]))
         assert np.max(np.abs(got[b].ravel() - xr)) <= 1e-6 * np.max(np.abs(xr))
         yr = dw[:2 * V] / r
         assert np.max(np.abs(y[b].cpu().numpy().astype(np.float64).ravel() - yr)) <= 1e-6 * np.max(np.abs(yr))
-    mean, rms = net.channel_moments(x, B, 2 * nsp, V)
-    for c in range(2 * nsp):
+    mean, rms = net.channel_moments(x, B, cin, V)
+    for c in range(cin):
         v = got[:, c, :]
         assert abs(mean[c] - v.mean()) <= 1e-12 * (1 + abs(v.mean()))
         assert abs(rms[c] - np.sqrt(np.mean(v ** 2))) <= 1e-12 * np.sqrt(np.mean(v ** 2))
-    shift = [0.25 * c for c in range(2 * nsp)]
-    scale = [1.0 / (1.0 + c) for c in range(2 * nsp)]
+    shift = [0.25 * c for c in range(cin)]
+    scale = [1.0 / (1.0 + c) for c in range(cin)]
     want = (x.cpu().numpy() - np.array(shift, np.float32)[None, :, None]) * np.array(scale, np.float32)[None, :, None]
-    net.affine(x, B, 2 * nsp, V, shift, scale)
+    net.affine(x, B, cin, V, shift, scale)
     torch.cuda.synchronize()
     d = np.abs(x.cpu().numpy().astype(np.float64) - want.astype(np.float64))
     assert np.max(d) <= 1e-6 * np.max(np.abs(want))
