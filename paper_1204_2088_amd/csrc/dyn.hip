@@ -64,7 +64,8 @@ __device__ __forceinline__ XLanes x_lanes(int x, int Lx)
 }
 
 // f at x - 1 and x + 1 of site k, given c = f[k].
-__device__ __forceinline__ void x_pair(const double *f, long long k, double c, const XLanes &n, double &l, double &r)
+template <typename Idx>
+__device__ __forceinline__ void x_pair(const double *f, Idx k, double c, const XLanes &n, double &l, double &r)
 {
     l = from_left(c);
     r = from_right(c);
@@ -72,8 +73,34 @@ __device__ __forceinline__ void x_pair(const double *f, long long k, double c, c
     if (!n.rw) r = f[k + n.dr];
 }
 
+// The same for NR rows at once: every row's centre load is issued before the first lane
+// exchange, and the edge lanes' loads of all rows go in one masked group per side, so a
+// wavefront waits for memory twice per group of rows rather than once per row.
+template <int NR, typename Idx>
+__device__ __forceinline__ void x_rows(const double *f, const Idx (&k)[NR], const XLanes &n, double (&c)[NR],
+                                       double (&l)[NR], double (&r)[NR])
+{
+#pragma unroll
+    for (int q = 0; q < NR; ++q) c[q] = f[k[q]];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        l[q] = from_left(c[q]);
+        r[q] = from_right(c[q]);
+    }
+    if (!n.lw) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) l[q] = f[k[q] + n.dl];
+    }
+    if (!n.rw) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) r[q] = f[k[q] + n.dr];
+    }
+}
+
 // mu_I = -w_I + sum_J chi_IJ sigma[phi_J] + kappa (sum_J phi_J - 1); the stencil sums
-// are formed per class (centre, faces, edges, corners) as in stencil27.
+// are formed per class (centre, faces, edges, corners) as in stencil27.  Sites are
+// addressed by 32-bit offsets from each species' base (a replica holds fewer than 2^31
+// sites), and the nine rows of every species are loaded together.
 template <int NSP>
 __global__ __launch_bounds__(kBlock) void k_mu(const int *__restrict__ blk_rep, const int *__restrict__ blk_first,
                                                const Rep *__restrict__ rep, Chain ch,
@@ -82,38 +109,33 @@ __global__ __launch_bounds__(kBlock) void k_mu(const int *__restrict__ blk_rep, 
 {
     const SiteRef sr = site_ref(blk_rep, blk_first);
     const Rep &R = rep[sr.r];
-    const long long V = R.V;
+    const int V = (int)R.V, Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
     const bool live = sr.i < V;
-    const long long i = live ? sr.i : V - 1;
-    int x, y, z;
-    site_xyz(R, i, x, y, z);
-    const XLanes xn = x_lanes(x, R.Lx);
+    const int i = live ? (int)sr.i : V - 1;
+    const int x = i % Lx, y = (i / Lx) % Ly, z = i / (Lx * Ly);
+    const XLanes xn = x_lanes(x, Lx);
     const long long fo = off_field(R, NSP);
-    const int ym = wrap1(y - 1, R.Ly), yp = wrap1(y + 1, R.Ly), zm = wrap1(z - 1, R.Lz), zp = wrap1(z + 1, R.Lz);
-    auto at = [&](int yy, int zz) { return (long long)x + (long long)R.Lx * ((long long)yy + (long long)R.Ly * zz); };
-    const long long k0 = at(y, z), k1[4] = {at(ym, z), at(yp, z), at(y, zm), at(y, zp)},
-                    k2[4] = {at(ym, zm), at(ym, zp), at(yp, zm), at(yp, zp)};
+    const int dym = (wrap1(y - 1, Ly) - y) * Lx, dyp = (wrap1(y + 1, Ly) - y) * Lx;
+    const int dzm = (wrap1(z - 1, Lz) - z) * Lx * Ly, dzp = (wrap1(z + 1, Lz) - z) * Lx * Ly;
+    // rows: the site's, four with exactly one of (dy, dz) non-zero, four with both
+    const int k[9] = {i, i + dym, i + dyp, i + dzm, i + dzp, i + dym + dzm, i + dym + dzp, i + dyp + dzm, i + dyp + dzp};
     double sp[3] = {0, 0, 0}, tot = 0.0;
-#pragma unroll 1   // one species at a time: unrolled over the species the kernel needs 172 registers
+#pragma unroll 1
     for (int J = 0; J < NSP; ++J) {
-        const double *f = phi + fo + J * V;
-        double c = f[k0], l, r;
-        x_pair(f, k0, c, xn, l, r);
-        double s0 = c, s1 = l + r, s2 = 0, s3 = 0;
-        tot += c;
+        const double *f = phi + fo + (long long)J * V;
+        double c[9], l[9], r[9];
+        x_rows(f, k, xn, c, l, r);
+        double s0 = c[0], s1 = l[0] + r[0], s2 = 0, s3 = 0;
+        tot += c[0];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {   // rows with exactly one of (dy, dz) non-zero
-            c = f[k1[q]];
-            x_pair(f, k1[q], c, xn, l, r);
-            s1 += c;
-            s2 += l + r;
+        for (int q = 1; q < 5; ++q) {
+            s1 += c[q];
+            s2 += l[q] + r[q];
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {   // rows with both non-zero
-            c = f[k2[q]];
-            x_pair(f, k2[q], c, xn, l, r);
-            s2 += c;
-            s3 += l + r;
+        for (int q = 5; q < 9; ++q) {
+            s2 += c[q];
+            s3 += l[q] + r[q];
         }
         sp[J] = R.c[0] * s0 + R.c[1] * s1 + R.c[2] * s2 + R.c[3] * s3;
     }
@@ -123,7 +145,8 @@ __global__ __launch_bounds__(kBlock) void k_mu(const int *__restrict__ blk_rep, 
         double inter = 0.0;
 #pragma unroll
         for (int J = 0; J < NSP; ++J) inter += R.chi[I][J] * sp[J];
-        mu[fo + I * V + i] = -w[fo + I * V + i] + inter + R.kappa * (tot - 1.0);
+        const long long k = fo + (long long)I * V;
+        mu[k + i] = -w[k + i] + inter + R.kappa * (tot - 1.0);
     }
 }
 
@@ -381,48 +404,84 @@ __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, 
 {
     const SiteRef sr = site_ref(blk_rep, blk_first);
     const Rep &R = rep[sr.r];
-    const long long V = R.V;
+    const int V = (int)R.V, Lx = R.Lx, Ly = R.Ly, Lz = R.Lz;
     const bool live = sr.i < V;
-    const long long i = live ? sr.i : V - 1;
-    int x, y, z;
-    site_xyz(R, i, x, y, z);
-    const XLanes xn = x_lanes(x, R.Lx);
+    const int i = live ? (int)sr.i : V - 1;
+    const int x = i % Lx, y = (i / Lx) % Ly, z = i / (Lx * Ly);
+    const XLanes xn = x_lanes(x, Lx);
     const long long fo = off_field(R, NSP), vo = 3LL * R.site_off;
-    const long long nb[6] = {i + xn.dl, i + xn.dr,
-                             sidx(R, x, wrap1(y - 1, R.Ly), z), sidx(R, x, wrap1(y + 1, R.Ly), z),
-                             sidx(R, x, y, wrap1(z - 1, R.Lz)), sidx(R, x, y, wrap1(z + 1, R.Lz))};
+    // y and z neighbours (32-bit offsets: a replica holds fewer than 2^31 sites)
+    const int nb[6] = {i + xn.dl, i + xn.dr,
+                       i + (wrap1(y - 1, Ly) - y) * Lx, i + (wrap1(y + 1, Ly) - y) * Lx,
+                       i + (wrap1(z - 1, Lz) - z) * Lx * Ly, i + (wrap1(z + 1, Lz) - z) * Lx * Ly};
     const double dt = R.dt * diff_scale;   // diffusive flux over dt (or dt/2 in the CN step)
+    // Every load is issued before the first lane exchange: the rows that take their x
+    // neighbours from the adjacent lanes (phi and mu of each species, u_x), the y and z
+    // neighbours of all of them, then the edge lanes' x neighbours in one masked group
+    // per side.  Without a velocity field the u rows read phi and are replaced by zero.
+    constexpr int NR = 2 * NSP + 1;
+    const double *rows[NR];
+#pragma unroll
+    for (int I = 0; I < NSP; ++I) {
+        rows[2 * I] = phi + fo + (long long)I * V;
+        rows[2 * I + 1] = mu + fo + (long long)I * V;
+    }
+    const double *ub = u ? u + vo : phi + fo;
+    rows[2 * NSP] = ub;
+    double c[NR], lo[NR], hi[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) c[q] = rows[q][i];
+    double uyz[2][3];   // u_y, u_z at (lower neighbour, site, upper neighbour)
+#pragma unroll
+    for (int a = 1; a < 3; ++a) {
+        const double *ua = u ? ub + (long long)a * V : ub;
+        uyz[a - 1][0] = ua[nb[2 * a]];
+        uyz[a - 1][1] = ua[i];
+        uyz[a - 1][2] = ua[nb[2 * a + 1]];
+    }
+    double pyz[NSP][4], myz[NSP][4];   // (y-, y+, z-, z+)
+#pragma unroll
+    for (int I = 0; I < NSP; ++I) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            pyz[I][q] = rows[2 * I][nb[2 + q]];
+            myz[I][q] = rows[2 * I + 1][nb[2 + q]];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        lo[q] = from_left(c[q]);
+        hi[q] = from_right(c[q]);
+    }
+    if (!xn.lw) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) lo[q] = rows[q][nb[0]];
+    }
+    if (!xn.rw) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) hi[q] = rows[q][nb[1]];
+    }
     // the velocity at the site and its six neighbours, shared by the species
     double ul[3] = {0, 0, 0}, ur[3] = {0, 0, 0}, uh[3] = {0, 0, 0};
     if (u) {
-        const double *ux = u + vo;
-        ur[0] = ux[i];
-        x_pair(ux, i, ur[0], xn, ul[0], uh[0]);
+        ul[0] = lo[2 * NSP];
+        ur[0] = c[2 * NSP];
+        uh[0] = hi[2 * NSP];
 #pragma unroll
         for (int a = 1; a < 3; ++a) {
-            const double *ua = u + vo + a * V;
-            ul[a] = ua[nb[2 * a]];
-            ur[a] = ua[i];
-            uh[a] = ua[nb[2 * a + 1]];
+            ul[a] = uyz[a - 1][0];
+            ur[a] = uyz[a - 1][1];
+            uh[a] = uyz[a - 1][2];
         }
     }
 #pragma unroll
     for (int I = 0; I < NSP; ++I) {
-        const double *p = phi + fo + I * V;
-        const double *m = mu + fo + I * V;
-        const double pr = p[i], mr = m[i];
-        double pn_l[3], pn_h[3], mn_l[3], mn_h[3];
-        x_pair(p, i, pr, xn, pn_l[0], pn_h[0]);
-        x_pair(m, i, mr, xn, mn_l[0], mn_h[0]);
-#pragma unroll
-        for (int a = 1; a < 3; ++a) {
-            pn_l[a] = p[nb[2 * a]];
-            pn_h[a] = p[nb[2 * a + 1]];
-            mn_l[a] = m[nb[2 * a]];
-            mn_h[a] = m[nb[2 * a + 1]];
-        }
+        const double pr = c[2 * I], mr = c[2 * I + 1];
+        const double pn_l[3] = {lo[2 * I], pyz[I][0], pyz[I][2]}, pn_h[3] = {hi[2 * I], pyz[I][1], pyz[I][3]};
+        const double mn_l[3] = {lo[2 * I + 1], myz[I][0], myz[I][2]},
+                     mn_h[3] = {hi[2 * I + 1], myz[I][1], myz[I][3]};
         double div = 0.0;
-        const double *jI = NOISE ? jn + 3 * fo + 3 * I * V : nullptr;
+        const double *jI = NOISE ? jn + 3 * fo + 3 * (long long)I * V : nullptr;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             // face between lo and r, then between r and hi
@@ -434,15 +493,15 @@ __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, 
                 jh += (0.5 * (pr + ph) - 0.5 * (ph * uh[a] - pr * ur[a])) * (0.5 * (ur[a] + uh[a]));
             }
             if (NOISE) {
-                jl += jI[a * V + nb[2 * a]];
-                jh += jI[a * V + i];
+                jl += jI[(long long)a * V + nb[2 * a]];
+                jh += jI[(long long)a * V + i];
             }
             div += jh - jl;
         }
         const double pn = pr - div;
         if (!live) continue;
         if (bad && !isfinite(pn)) bad[0] = 1;
-        phi_out[fo + I * V + i] = pn;
+        phi_out[fo + (long long)I * V + i] = pn;
     }
 }
 
