@@ -18,8 +18,9 @@ inversions needed, divided by the wall time of the steps.
 The JSON line also carries: the roofline of the dominant propagator kernel and of the
 LB kernel (algorithmic bytes per unit of the store-all scheme, HIP-event launch times
 of the same run), the FP32 error against the FP64 oracle at the run's final fields, the
-FP32 inversion floor, the oracle timed on one host core and on all of them (propagator
-updates/s and LB MLUPS), the learned warm start against the plain and extrapolated ones
+FP32 inversion floor, the evaluation rate through the C ABI with device and with host
+buffers (the latter including the PCIe copies), the oracle timed on one host core and on
+all of them (propagator updates/s and LB MLUPS), the learned warm start against the plain and extrapolated ones
 over whole trajectories, and shorter runs of the 64^3 melt pair and the 48-replica
 batch.  Inputs are synthetic (seeded) and resident in HBM before the timed region.
 """
@@ -280,6 +281,40 @@ def learned_arm(hsf, workload, precision, steps, tile, log, precond=False, width
     }
 
 
+def boundary_rates(ctx, torch, wl, reps=20):
+    """Evaluation rate through the C ABI with the fields set and the densities read back
+    on each call, the buffers on the device (what `value` assumes: inputs resident in HBM)
+    or on the host (pageable numpy arrays, or pinned torch tensors), so the host rate
+    includes the PCIe copies of w in and phi out (FP64, n_species x V each)."""
+    n = ctx.nsp * ctx.T
+    w_dev = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.get_fields(out=w_dev)
+    out_dev = torch.empty(n, dtype=torch.float64, device="cuda")
+    w_np = w_dev.cpu().numpy().copy()
+    out_np = np.empty(n)
+    w_pin = torch.empty(n, dtype=torch.float64, pin_memory=True)
+    w_pin.copy_(torch.from_numpy(w_np))
+    out_pin = torch.empty(n, dtype=torch.float64, pin_memory=True)
+    cases = {"device": (w_dev, out_dev), "host_pageable": (w_np, out_np), "host_pinned": (w_pin, out_pin)}
+    upd = 2 * wl.N * ctx.T
+    res = {}
+    for name, (w, o) in cases.items():
+        for _ in range(3):
+            ctx.set_fields(w)
+            ctx.evaluate(o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.set_fields(w)
+            ctx.evaluate(o)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        res[name] = {"ms_per_call": 1e3 * el, "updates_per_s": upd / el}
+    res["bytes_per_call"] = 2 * 8 * n
+    res["calls"] = reps
+    return res
+
+
 def run_arm(hsf, torch, wls, steps, warmup, timing, log, precond=False, tile=None, noise_omega=None, hydro=True):
     """Build a batched context, autotune, warm up, time `steps` coupled steps (with the
     LB flow, or purely diffusive with hydro=False), then (timing) half as many steps with
@@ -538,13 +573,16 @@ def main():
     value = 2 * N * site_evals / elapsed
     kernels, roofline, lb_roofline = rooflines(timing, wls, tile, args.workload) if timing else ({}, None, None)
 
-    err = floor = None
+    err = floor = boundary = None
     if not args.lean:
         err = oracle_error(ctx, wl)
         log(f"# error against the oracle at the final fields: {err['max_rel']:.2e}")
         floor = inversion_floor(ctx, wls, precond)
         log(f"# inversion floor: {floor['residual_reached']}; with FP64 refinement: "
             f"{floor.get('refined', {}).get('residual_reached')}")
+        boundary = boundary_rates(ctx, torch, wl)
+        log("# evaluation through the ABI: " + ", ".join(
+            f"{k} {v['ms_per_call']:.3f} ms" for k, v in boundary.items() if isinstance(v, dict)))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -617,6 +655,7 @@ def main():
         "lb_roofline": lb_roofline,
         "error_vs_oracle": err,
         "inversion_floor": floor,
+        "host_boundary": boundary,
         "learned_warm_start": learned,
         "other_configs": extra or None,
         "crank_nicolson": cn,
