@@ -413,14 +413,16 @@ int hsf_autotune(hsf_ctx *ctx, int reps, double *best_ms);
 /* Schedule of the paired sweeps (tilings with k = -1) for chains of n_beads >= 2 beads,
  * the order in which eq. 17's forward steps and eq. 16-17's backward steps are launched:
  * launch j (1..n_beads) takes forward step out[0] = j and backward step out[1] (0: none),
- * with the flags out[2..6] = f_late (the forward step finds sigma[G+_{s+1}] in the store
+ * with the flags out[2..7] = f_late (the forward step finds sigma[G+_{s+1}] in the store
  * slot of its bead and stores the density term), f_from_pp (it reads G_{s-1} from its
  * ping-pong pair), f_to_pp (it also writes G_s there), g_late (the backward step finds G_s
- * in the slot and stores the term; else it stores sigma[G+_{s+1}]) and g_exp (it forms its
- * field factor from the fields).  Backward step 1 follows alone.  Host computation only
- * (the evaluation uses the same function); HSF_EINVAL for n_beads outside 2..64 or launch
- * outside 1..n_beads. */
-int hsf_paired_schedule(int n_beads, int launch, int out[7]);
+ * in the slot and stores the term; else it stores sigma[G+_{s+1}]), g_exp (it forms its
+ * field factor from the fields) and g_from_e (backward step N - 1 of an even chain of at
+ * least 4 beads, whose backward step N has no launch: its stencil reads G+_N as bead N's
+ * stored field factor times csum and the step-N scale).  Backward step 1 follows alone.
+ * Host computation only (the evaluation uses the same function); HSF_EINVAL for n_beads
+ * outside 2..64 or launch outside 1..n_beads. */
+int hsf_paired_schedule(int n_beads, int launch, int out[8]);
 
 /* Warm start used by hsf_step's inversions (default HSF_WARM_CURRENT). */
 int hsf_set_warm(hsf_ctx *ctx, int warm);

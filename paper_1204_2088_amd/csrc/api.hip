@@ -391,9 +391,12 @@ int set_tile(hsf_ctx *c, const TileCfg &t)
 // Paired kernels (K = -1, N >= 2): N launches, launch j taking forward step j and backward
 // step N + 1 + (N mod 2) - j (when in 2..N), then backward step 1 alone, which finishes Q
 // and normalises; N + 1 launches instead of 2 N.  A bead's two steps never share a launch
-// (the backward lag N mod 2 sees to that), the forward step of bead s runs first exactly
-// when s <= se = (N + N mod 2) / 2, and the backward step N of launch 1 (even N) forms its
-// field factor itself since step 1 is storing them in the same launch.
+// (the backward lag N mod 2 sees to that), and the forward step of bead s runs first exactly
+// when s <= se = (N + N mod 2) / 2.  For even N the backward step N would share launch 1
+// with forward step 1, which stores the field factors: with N = 2 it forms its factor from
+// the fields itself; with N >= 4 it has no launch of its own, and backward step N - 1
+// (launch 2) reads G+_N through its stencil as bead N's stored factor times csum and the
+// step-N scale, the values step N would have stored.
 // Launch j (1..N) of the paired schedule for chains of N >= 2 beads (host only; the
 // schedule's read and write sets are checked on the CPU through hsf_paired_schedule).
 PairSteps paired_steps(int N, int j)
@@ -406,8 +409,11 @@ PairSteps paired_steps(int N, int j)
     ps.f_late = j > se;
     ps.f_from_pp = j >= 2 && j - 1 >= se;
     ps.f_to_pp = j >= se && j < N;
+    const bool fold_n = lag == 0 && N >= 4;   // backward step N folded into step N - 1
+    if (fold_n && j == 1) ps.sb = 0;
     ps.g_late = ps.sb && ps.sb <= se;
     ps.g_exp = ps.sb == N && j == 1;
+    ps.g_from_e = fold_n && j == 2;
     return ps;
 }
 
@@ -1567,12 +1573,12 @@ int hsf_step(hsf_ctx *c, int n_steps, double tol, int max_iter, hsf_invert_stats
     return HSF_OK;
 }
 
-int hsf_paired_schedule(int n_beads, int launch, int out[7])
+int hsf_paired_schedule(int n_beads, int launch, int out[8])
 {
     if (!out || n_beads < 2 || n_beads > HSF_MAX_BEADS || launch < 1 || launch > n_beads) return HSF_EINVAL;
     const PairSteps ps = paired_steps(n_beads, launch);
-    const int v[7] = {ps.sf, ps.sb, ps.f_late, ps.f_from_pp, ps.f_to_pp, ps.g_late, ps.g_exp};
-    for (int k = 0; k < 7; ++k) out[k] = v[k];
+    const int v[8] = {ps.sf, ps.sb, ps.f_late, ps.f_from_pp, ps.f_to_pp, ps.g_late, ps.g_exp, ps.g_from_e};
+    for (int k = 0; k < 8; ++k) out[k] = v[k];
     return HSF_OK;
 }
 

@@ -102,7 +102,7 @@ void launch_bwd_stream(const TileCfg &cfg, hipStream_t s, const Plan &p, const R
 // where each reads and writes its propagators (the schedule is built by the evaluation).
 struct PairSteps {
     int sf, sb;
-    int f_late, f_from_pp, f_to_pp, g_late, g_exp;
+    int f_late, f_from_pp, f_to_pp, g_late, g_exp, g_from_e;
 };
 template <typename real>
 void launch_pair_block(const TileCfg &cfg, hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Chain ch,

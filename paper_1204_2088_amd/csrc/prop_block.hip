@@ -13,6 +13,7 @@
 // 2^(e_1+..+e_N): the same per-step power of two divides both sweeps, so every
 // product G_s sigma[G+_{s+1}] carries one common factor that cancels in phi.
 #include <hip/hip_ext.h>
+#include <type_traits>
 
 #include "device_common.h"
 #include "prop_block.h"
@@ -469,48 +470,61 @@ __device__ __forceinline__ void direct_tile(int pb, const int *blk_rep, const in
     z0 = (lb / nty) * CZ;
 }
 
-// In-plane class sums of f around (x, y) in plane z (9 loads).
+// What a stencil applies to each loaded value before summing it: nothing, or (v m1) m2,
+// the two products by which a backward step N forms G+_N = (E csum) sc from its field
+// factor (so a stencil of the field factor through Scale sums the values that step stores).
 template <typename real>
+struct NoXf {
+    __device__ __forceinline__ real operator()(real v) const { return v; }
+};
+template <typename real>
+struct ScaleXf {
+    real m1, m2;
+    __device__ __forceinline__ real operator()(real v) const { return (v * m1) * m2; }
+};
+
+// In-plane class sums of f around (x, y) in plane z (9 loads).
+template <typename real, typename Xf = NoXf<real>>
 __device__ __forceinline__ void plane_sums(const real *__restrict__ f, int x, int y, int z, int Lx, int Ly,
-                                           real &a0, real &a1, real &a2)
+                                           real &a0, real &a1, real &a2, Xf xf = Xf())
 {
     const int xm = wrap1(x - 1, Lx), xp = wrap1(x + 1, Lx);
     const int ym = wrap1(y - 1, Ly), yp = wrap1(y + 1, Ly);
     const real *p0 = f + ((long long)z * Ly + y) * Lx;
     const real *pm = f + ((long long)z * Ly + ym) * Lx;
     const real *pp = f + ((long long)z * Ly + yp) * Lx;
-    a0 = p0[x];
-    a1 = (p0[xm] + p0[xp]) + (pm[x] + pp[x]);
-    a2 = (pm[xm] + pm[xp]) + (pp[xm] + pp[xp]);
+    a0 = xf(p0[x]);
+    a1 = (xf(p0[xm]) + xf(p0[xp])) + (xf(pm[x]) + xf(pp[x]));
+    a2 = (xf(pm[xm]) + xf(pm[xp])) + (xf(pp[xm]) + xf(pp[xp]));
 }
 
 // The same for tilings whose rows are 64 sites wide (a wavefront's lanes are consecutive x
 // of one row): 3 loads per plane instead of 9.  The x neighbours come from the adjacent
 // lanes; a lane whose neighbour lies outside the wavefront's row or across the box's
 // periodic edge loads it.  Same values summed in the same order as plane_sums.
-template <typename real>
+template <typename real, typename Xf = NoXf<real>>
 __device__ __forceinline__ void plane_sums_x64(const real *__restrict__ f, int x, int y, int z, int Lx, int Ly,
-                                               real &a0, real &a1, real &a2)
+                                               real &a0, real &a1, real &a2, Xf xf = Xf())
 {
     const int lane = (int)threadIdx.x & 63;
     const int ym = wrap1(y - 1, Ly), yp = wrap1(y + 1, Ly);
     const real *p0 = f + ((long long)z * Ly + y) * Lx;
     const real *pm = f + ((long long)z * Ly + ym) * Lx;
     const real *pp = f + ((long long)z * Ly + yp) * Lx;
-    const real c = p0[x], m = pm[x], p = pp[x];
+    const real c = xf(p0[x]), m = xf(pm[x]), p = xf(pp[x]);
     real cl = from_left(c), ml = from_left(m), pl = from_left(p);
     real cr = from_right(c), mr = from_right(m), pr = from_right(p);
     if (lane == 0 || x == 0) {
         const int xm = wrap1(x - 1, Lx);
-        cl = p0[xm];
-        ml = pm[xm];
-        pl = pp[xm];
+        cl = xf(p0[xm]);
+        ml = xf(pm[xm]);
+        pl = xf(pp[xm]);
     }
     if (lane == 63 || x == Lx - 1) {
         const int xp = wrap1(x + 1, Lx);
-        cr = p0[xp];
-        mr = pm[xp];
-        pr = pp[xp];
+        cr = xf(p0[xp]);
+        mr = xf(pm[xp]);
+        pr = xf(pp[xp]);
     }
     a0 = c;
     a1 = (cl + cr) + (m + p);
@@ -519,12 +533,12 @@ __device__ __forceinline__ void plane_sums_x64(const real *__restrict__ f, int x
 
 // The stencil at the sites (x, y, z0 + j), j < nz (<= CZ), of f into S[j].  X64: rows of
 // 64 lanes (plane_sums_x64); every lane of a row must take part.
-template <typename real, int CZ, bool X64 = false>
+template <typename real, int CZ, bool X64 = false, typename Xf = NoXf<real>>
 __device__ __forceinline__ void column_stencil(const real *__restrict__ f, int x, int y, int z0, int nz, const Rep &R,
-                                               real *S)
+                                               real *S, Xf xf = Xf())
 {
     const real c0 = (real)R.c[0], c1 = (real)R.c[1], c2 = (real)R.c[2], c3 = (real)R.c[3];
-    if (CZ == 1 && !X64) {
+    if (CZ == 1 && !X64 && std::is_same<Xf, NoXf<real>>::value) {
         S[0] = stencil27<real>(f, x, y, z0, R.Lx, R.Ly, R.Lz, c0, c1, c2, c3);
         return;
     }
@@ -538,14 +552,14 @@ __device__ __forceinline__ void column_stencil(const real *__restrict__ f, int x
     for (int q = 0; q < CZ + 2; ++q) {
         if (CZ <= 2) {
             const int zq = wrap1(min(z0 - 1 + q, z0 + nz), R.Lz);
-            if (X64) plane_sums_x64<real>(f, x, y, zq, R.Lx, R.Ly, a0[q], a1[q], a2[q]);
-            else plane_sums<real>(f, x, y, zq, R.Lx, R.Ly, a0[q], a1[q], a2[q]);
+            if (X64) plane_sums_x64<real>(f, x, y, zq, R.Lx, R.Ly, a0[q], a1[q], a2[q], xf);
+            else plane_sums<real>(f, x, y, zq, R.Lx, R.Ly, a0[q], a1[q], a2[q], xf);
         } else {
             a0[q] = a1[q] = a2[q] = (real)0;
             // the plane index is the same for every lane of a row, so a row stays together
             if (q <= nz + 1) {
-                if (X64) plane_sums_x64<real>(f, x, y, wrap1(z0 - 1 + q, R.Lz), R.Lx, R.Ly, a0[q], a1[q], a2[q]);
-                else plane_sums<real>(f, x, y, wrap1(z0 - 1 + q, R.Lz), R.Lx, R.Ly, a0[q], a1[q], a2[q]);
+                if (X64) plane_sums_x64<real>(f, x, y, wrap1(z0 - 1 + q, R.Lz), R.Lx, R.Ly, a0[q], a1[q], a2[q], xf);
+                else plane_sums<real>(f, x, y, wrap1(z0 - 1 + q, R.Lz), R.Lx, R.Ly, a0[q], a1[q], a2[q], xf);
             }
         }
     }
@@ -891,6 +905,9 @@ struct PairInfo {
     int f_to_pp;     // forward: G_s is also written to fout
     int g_late;      // backward: G_s is in slot s - 1 and the term replaces it (else sigma_s is stored)
     int g_exp;       // backward: the field factor is computed from w here (step 1's launch, same values)
+    int g_from_e;    // backward step N - 1: its stencil reads G+_N as bead N's field factor times csum
+                     // and the step-N scale, the two products backward step N would store
+    int g_tn;        // species of bead N
     int nf;          // blocks of the forward half (0 or the tile plan's count)
 };
 
@@ -1021,6 +1038,9 @@ __device__ __forceinline__ void pair_bwd(const PairInfo &pi, int pb, const int *
         if (s == N) {
 #pragma unroll
             for (int j = 0; j < CZ; ++j) S[j] = (real)R.csum;
+        } else if (pi.g_from_e) {
+            const ScaleXf<real> xf{(real)R.csum, pow2_neg_b<real>(st[r].scale_e[N - 1])};
+            column_stencil<real, CZ, CX == 64>(b.E + po + (long long)pi.g_tn * V, x, y, z0, nz, R, S, xf);
         } else {
             column_stencil<real, CZ, CX == 64>(gin + R.site_off, x, y, z0, nz, R, S);
         }
@@ -1155,6 +1175,8 @@ void pair_launch(hipStream_t s, const Plan &p, const Rep *rep, RepState *st, Cha
     pi.f_to_pp = ps.f_to_pp;
     pi.g_late = ps.g_late;
     pi.g_exp = ps.g_exp;
+    pi.g_from_e = ps.g_from_e;
+    pi.g_tn = ch.types[ch.N - 1];
     pi.nf = ps.sf ? p.nblocks : 0;
     const int grid = pi.nf + (ps.sb ? p.nblocks : 0);
     auto kern = p.args.n ? k_pair_direct<real, CX, CY, CZ, true> : k_pair_direct<real, CX, CY, CZ, false>;

@@ -2,11 +2,12 @@
 
 The evaluation with paired kernels (tiles with k = -1) runs N launches, launch j taking
 forward step j and backward step N + 1 + (N mod 2) - j when that lies in 2..N, then
-backward step 1 alone.  Below the crossing se = (N + N mod 2) / 2 the forward step of a
-bead runs first and stores G_s in slot s - 1; above it the backward step runs first and
-stores sigma_s there.  The flags below are the ones the evaluation computes for each launch
-(f_late, f_from_pp, f_to_pp, g_late, g_exp), read from the library's host function that
-the evaluation itself calls.  This test replays the schedule over symbolic
+backward step 1 alone; for even N >= 4 backward step N has no launch (launch 1 takes none)
+and backward step N - 1 forms G+_N from bead N's stored field factor.  Below the crossing
+se = (N + N mod 2) / 2 the forward step of a bead runs first and stores G_s in slot s - 1;
+above it the backward step runs first and stores sigma_s there.  The flags below are the
+ones the evaluation computes for each launch (f_late, f_from_pp, f_to_pp, g_late, g_exp,
+g_from_e), read from the library's host function that the evaluation itself calls.  This test replays the schedule over symbolic
 buffers and checks, for every N the library takes, that no launch writes a buffer that
 another workgroup of the same launch reads (through the stencil, or from the other half),
 and that every read sees the value the step needs."""
@@ -20,10 +21,10 @@ def launches(N):
     lib = hsf.load()
     out = []
     for j in range(1, N + 1):
-        v = (ctypes.c_int * 7)()
+        v = (ctypes.c_int * 8)()
         assert lib.hsf_paired_schedule(N, j, v) == hsf.HSF_OK
         out.append(dict(sf=v[0], sb=v[1], f_late=bool(v[2]), f_from_pp=bool(v[3]), f_to_pp=bool(v[4]),
-                        g_late=bool(v[5]), g_exp=bool(v[6])))
+                        g_late=bool(v[5]), g_exp=bool(v[6]), g_from_e=bool(v[7])))
     return out
 
 
@@ -31,7 +32,7 @@ def test_schedule_arguments_are_checked():
     import ctypes
     from paper_1204_2088_amd import hsf
     lib = hsf.load()
-    v = (ctypes.c_int * 7)()
+    v = (ctypes.c_int * 8)()
     for N, j in ((1, 1), (65, 1), (8, 0), (8, 9)):
         assert lib.hsf_paired_schedule(N, j, v) == hsf.HSF_EINVAL
 
@@ -62,7 +63,10 @@ def replay(N):
         if sb:
             gin, gout = ("Gp", par ^ 1), ("Gp", par)
             par ^= 1
-            if sb < N:
+            if L["g_from_e"]:   # G+_N from bead N's field factor, stored by forward step 1
+                assert sb == N - 1
+                acc.append(("b", "E", "s")); reads.append(("E", "E"))
+            elif sb < N:
                 acc.append(("b", gin, "s")); reads.append((gin, ("G+", sb + 1)))
             if not L["g_exp"]:
                 acc.append(("b", "E", "r")); reads.append(("E", "E"))
@@ -89,7 +93,9 @@ def test_paired_schedule_is_race_free_and_complete(N):
         steps_f.add(L["sf"])
         if L["sb"]:
             steps_b.add(L["sb"])
-    assert steps_f == set(range(1, N + 1)) and steps_b == set(range(2, N + 1))
+    folded = N % 2 == 0 and N >= 4   # backward step N formed inside step N - 1
+    assert steps_f == set(range(1, N + 1)) and steps_b == set(range(2, N if folded else N + 1))
+    assert sum(L["g_from_e"] for L in launches(N)) == (1 if folded else 0)
     for acc, reads, writes in replay(N):
         by = {}
         for h, b, m in acc:
