@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # scaled by 2.0 and WRITE_SIZE by 1.0 after a calibration copy).
 # Valid only for that workload, precision, tiling and kernel as they stand; anything
 # else reports null.
-MEASURED_TRAFFIC = {("vesicle128_a3b9s", "fp32", (32, 8, 4, -1), "pair"): 74.46e6,
+MEASURED_TRAFFIC = {("vesicle128_a3b9s", "fp32", (32, 8, 4, -1), "pair"): 70.31e6,
                     ("vesicle128_a3b9s", "fp32", "lb"): 436.68e6}
 METRIC = "propagator site·bead updates/s + LB MLUPS; step time learned vs plain at 1e-6"
 

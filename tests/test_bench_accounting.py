@@ -46,8 +46,8 @@ def test_rooflines_from_launch_times(bench):
     assert prop["algorithmic_bytes_per_launch"] == pytest.approx(5.5 * units)
     achieved = 5.5 * units / 19.5e-6 / 1e9
     assert prop["achieved"] == pytest.approx(achieved) and prop["frac"] == pytest.approx(achieved / 8000.0)
-    assert prop["traffic"] == 74.46e6
-    assert prop["traffic_frac"] == pytest.approx(74.46e6 / 19.5e-6 / 1e9 / 8000.0)
+    assert prop["traffic"] == 70.31e6
+    assert prop["traffic_frac"] == pytest.approx(70.31e6 / 19.5e-6 / 1e9 / 8000.0)
     assert lb["mlups"] == pytest.approx(V / 74e-6 / 1e6)
     assert lb["frac"] == pytest.approx(180 * V / 74e-6 / 1e9 / 8000.0)
     assert lb["traffic"] == 436.68e6
