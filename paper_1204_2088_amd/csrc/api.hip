@@ -418,8 +418,10 @@ PairSteps paired_steps(int N, int j)
 }
 
 // Blocks per replica above which the paired sweeps' last launch does not fold Q itself
-// (every block would re-sum its replica's row of partials): a control launch does.
-constexpr int kFoldQMaxBlocks = 1024;
+// (every block re-sums its replica's row of partials, so the reads grow as the square of
+// the blocks): a control launch does.  At 2048 blocks (a 128^3 box in 32x8x4 tiles) the
+// fold costs the last launch about 2 us and saves the control launch, about 3 us more.
+constexpr int kFoldQMaxBlocks = 2048;
 
 template <typename real>
 void run_eval_paired(hsf_ctx *c, int use_alpha, int final_mode, double *out, const double *d, int sums)
