@@ -73,25 +73,29 @@ __device__ __forceinline__ void x_pair(const double *f, Idx k, double c, const X
     if (!n.rw) r = f[k + n.dr];
 }
 
-// The same for NR rows at once: every row's centre load is issued before the first lane
-// exchange, and the edge lanes' loads of all rows go in one masked group per side, so a
-// wavefront waits for memory twice per group of rows rather than once per row.
+// The same for NR rows at once, in one round trip to memory: with every row's centre each
+// lane also loads one more value, its outer x neighbour if it is an edge lane (the left one
+// if it lacks the left, else the right one) and its own site otherwise, so the edge values
+// arrive with the centres; only a lane lacking both neighbours (rows shorter than a
+// wavefront) loads its right neighbour afterwards.
 template <int NR, typename Idx>
 __device__ __forceinline__ void x_rows(const double *f, const Idx (&k)[NR], const XLanes &n, double (&c)[NR],
                                        double (&l)[NR], double (&r)[NR])
 {
-#pragma unroll
-    for (int q = 0; q < NR; ++q) c[q] = f[k[q]];
+    const int eo = !n.lw ? n.dl : (!n.rw ? n.dr : 0);
+    double e[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-        l[q] = from_left(c[q]);
-        r[q] = from_right(c[q]);
+        c[q] = f[k[q]];
+        e[q] = f[k[q] + eo];
     }
-    if (!n.lw) {
 #pragma unroll
-        for (int q = 0; q < NR; ++q) l[q] = f[k[q] + n.dl];
+    for (int q = 0; q < NR; ++q) {
+        const double fl = from_left(c[q]), fr = from_right(c[q]);
+        l[q] = n.lw ? fl : e[q];
+        r[q] = n.rw ? fr : e[q];
     }
-    if (!n.rw) {
+    if (!n.lw && !n.rw) {
 #pragma unroll
         for (int q = 0; q < NR; ++q) r[q] = f[k[q] + n.dr];
     }
@@ -416,9 +420,10 @@ __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, 
                        i + (wrap1(z - 1, Lz) - z) * Lx * Ly, i + (wrap1(z + 1, Lz) - z) * Lx * Ly};
     const double dt = R.dt * diff_scale;   // diffusive flux over dt (or dt/2 in the CN step)
     // Every load is issued before the first lane exchange: the rows that take their x
-    // neighbours from the adjacent lanes (phi and mu of each species, u_x), the y and z
-    // neighbours of all of them, then the edge lanes' x neighbours in one masked group
-    // per side.  Without a velocity field the u rows read phi and are replaced by zero.
+    // neighbours from the adjacent lanes (phi and mu of each species, u_x) with one more
+    // value per row (an edge lane's outer x neighbour, else its own site), and the y and z
+    // neighbours of all of them.  Without a velocity field the u rows read phi and are
+    // replaced by zero.
     constexpr int NR = 2 * NSP + 1;
     const double *rows[NR];
 #pragma unroll
@@ -428,9 +433,13 @@ __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, 
     }
     const double *ub = u ? u + vo : phi + fo;
     rows[2 * NSP] = ub;
-    double c[NR], lo[NR], hi[NR];
+    double c[NR], lo[NR], hi[NR], ex[NR];
+    const int eo = !xn.lw ? xn.dl : (!xn.rw ? xn.dr : 0);   // an edge lane's outer neighbour
 #pragma unroll
-    for (int q = 0; q < NR; ++q) c[q] = rows[q][i];
+    for (int q = 0; q < NR; ++q) {
+        c[q] = rows[q][i];
+        ex[q] = rows[q][i + eo];
+    }
     double uyz[2][3];   // u_y, u_z at (lower neighbour, site, upper neighbour)
 #pragma unroll
     for (int a = 1; a < 3; ++a) {
@@ -450,14 +459,11 @@ __global__ __launch_bounds__(kBlock) void k_cd(const int *__restrict__ blk_rep, 
     }
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-        lo[q] = from_left(c[q]);
-        hi[q] = from_right(c[q]);
+        const double fl = from_left(c[q]), fr = from_right(c[q]);
+        lo[q] = xn.lw ? fl : ex[q];
+        hi[q] = xn.rw ? fr : ex[q];
     }
-    if (!xn.lw) {
-#pragma unroll
-        for (int q = 0; q < NR; ++q) lo[q] = rows[q][nb[0]];
-    }
-    if (!xn.rw) {
+    if (!xn.lw && !xn.rw) {   // rows shorter than a wavefront: both neighbours from memory
 #pragma unroll
         for (int q = 0; q < NR; ++q) hi[q] = rows[q][nb[1]];
     }
