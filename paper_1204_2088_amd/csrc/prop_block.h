@@ -27,6 +27,7 @@ struct TileCfg {
     X(64, 4, 8, 0)          \
     X(16, 16, 8, 0)         \
     X(64, 4, 2, -1)         \
+    X(64, 4, 4, -1)         \
     X(32, 8, 2, -1)         \
     X(16, 16, 2, -1)        \
     X(32, 8, 4, -1)         \

@@ -499,9 +499,12 @@ __device__ __forceinline__ void plane_sums(const real *__restrict__ f, int x, in
 }
 
 // The same for tilings whose rows are 64 sites wide (a wavefront's lanes are consecutive x
-// of one row): 3 loads per plane instead of 9.  The x neighbours come from the adjacent
-// lanes; a lane whose neighbour lies outside the wavefront's row or across the box's
-// periodic edge loads it.  Same values summed in the same order as plane_sums.
+// of one row): the x neighbours come from the adjacent lanes.  A lane whose neighbour lies
+// outside the wavefront's row or across the box's periodic edge needs it from memory: with
+// each row's centre every lane loads one more value, that outer neighbour if it is an edge
+// lane and its own site otherwise, so the edge values arrive in the same round trip (a
+// lane lacking both neighbours, in rows of one site, loads the right one after).  6 loads
+// per plane instead of 9; same values summed in the same order as plane_sums.
 template <typename real, typename Xf = NoXf<real>>
 __device__ __forceinline__ void plane_sums_x64(const real *__restrict__ f, int x, int y, int z, int Lx, int Ly,
                                                real &a0, real &a1, real &a2, Xf xf = Xf())
@@ -511,16 +514,15 @@ __device__ __forceinline__ void plane_sums_x64(const real *__restrict__ f, int x
     const real *p0 = f + ((long long)z * Ly + y) * Lx;
     const real *pm = f + ((long long)z * Ly + ym) * Lx;
     const real *pp = f + ((long long)z * Ly + yp) * Lx;
+    const bool lw = !(lane == 0 || x == 0), rw = !(lane == 63 || x == Lx - 1);
+    const int xe = !lw ? wrap1(x - 1, Lx) : (!rw ? wrap1(x + 1, Lx) : x);
     const real c = xf(p0[x]), m = xf(pm[x]), p = xf(pp[x]);
-    real cl = from_left(c), ml = from_left(m), pl = from_left(p);
-    real cr = from_right(c), mr = from_right(m), pr = from_right(p);
-    if (lane == 0 || x == 0) {
-        const int xm = wrap1(x - 1, Lx);
-        cl = xf(p0[xm]);
-        ml = xf(pm[xm]);
-        pl = xf(pp[xm]);
-    }
-    if (lane == 63 || x == Lx - 1) {
+    const real ce = xf(p0[xe]), me = xf(pm[xe]), pe = xf(pp[xe]);
+    const real fcl = from_left(c), fml = from_left(m), fpl = from_left(p);
+    const real fcr = from_right(c), fmr = from_right(m), fpr = from_right(p);
+    real cl = lw ? fcl : ce, ml = lw ? fml : me, pl = lw ? fpl : pe;
+    real cr = rw ? fcr : ce, mr = rw ? fmr : me, pr = rw ? fpr : pe;
+    if (!lw && !rw) {
         const int xp = wrap1(x + 1, Lx);
         cr = xf(p0[xp]);
         mr = xf(pm[xp]);

@@ -417,7 +417,7 @@ def test_graph_replays_match_direct_launches(hsf, orc, monkeypatch):
 
 TILES = [(64, 4, 1, 0), (32, 8, 1, 0), (16, 16, 1, 0), (64, 4, 2, 0), (32, 8, 2, 0), (16, 16, 2, 0), (64, 4, 4, 0),
          (32, 8, 4, 0), (16, 16, 4, 0), (64, 4, 8, 0), (16, 16, 8, 0), (8, 8, 8, 1), (8, 8, 8, 2), (8, 8, 8, 3), (8, 8, 8, 4), (16, 8, 8, 2), (16, 8, 4, 2), (32, 8, 4, 1),
-         (32, 4, 4, 2), (64, 4, 2, -1), (32, 8, 2, -1), (16, 16, 2, -1), (32, 8, 4, -1), (16, 16, 4, -1),
+         (32, 4, 4, 2), (64, 4, 2, -1), (64, 4, 4, -1), (32, 8, 2, -1), (16, 16, 2, -1), (32, 8, 4, -1), (16, 16, 4, -1),
          (16, 16, 8, -1), (64, 8, 8, 2), (64, 8, 16, 2), (64, 16, 8, 2), (64, 16, 16, 2), (64, 16, 32, 2)]
 PAIRED = [t for t in TILES if t[3] == -1]
 STREAM = [t for t in TILES if t[0] == 64 and t[3] >= 1]
