@@ -372,15 +372,17 @@ void launch_init_fields(hipStream_t s, const Plan &p, const Rep *rep, RepState *
 }
 
 // Conjugate-gradient vector update, z = g (or g / phi^t when preconditioned).
-//   init = 1 (replicas pending their first iteration): d = -z
-//   init = 0 (replicas whose trial was accepted): w += alpha d, g = g_trial and,
-//            unless the replica is done, d = -z + beta d
+//   init = 1 (replicas pending their first iteration): d = -z, g from the start evaluation
+//   init = 0 (replicas whose trial was accepted): w += alpha d and, unless the replica is
+//            done, d = -z + beta d with g the accepted trial's gradient g_trial (read in
+//            place: only the scalars of g are needed later, and the next start evaluation
+//            rewrites the vector g)
 // Partial sums d.g and sum d^2 phi^t for the next alpha_0.
 __global__ __launch_bounds__(kBlock) void k_cg_update(const int *__restrict__ blk_rep,
                                                       const int *__restrict__ blk_first,
                                                       const Rep *__restrict__ rep, const RepState *__restrict__ st,
                                                       Chain ch, int init, double *__restrict__ w,
-                                                      double *__restrict__ g, const double *__restrict__ gt,
+                                                      const double *__restrict__ g, const double *__restrict__ gt,
                                                       double *__restrict__ d, const double *__restrict__ phit,
                                                       double *__restrict__ part)
 {
@@ -404,7 +406,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const int *__restrict__ bl
             } else {
                 w[fo + I * V + i] = fma(alpha, dI, w[fo + I * V + i]);
                 gI = gt[k];
-                g[k] = gI;
             }
             if (upd_d) {
                 const double zI = ch.precond ? gI / phit[fo + I * V + i] : gI;
