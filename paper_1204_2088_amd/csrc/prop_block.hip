@@ -472,7 +472,7 @@ __device__ __forceinline__ void direct_tile(int pb, const int *blk_rep, const in
 
 // What a stencil applies to each loaded value before summing it: nothing, or (v m1) m2,
 // the two products by which a backward step N forms G+_N = (E csum) sc from its field
-// factor (so a stencil of the field factor through Scale sums the values that step stores).
+// factor (so a stencil of the field factor through ScaleXf sums the values that step stores).
 template <typename real>
 struct NoXf {
     __device__ __forceinline__ real operator()(real v) const { return v; }

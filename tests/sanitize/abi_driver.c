@@ -36,7 +36,7 @@ static hsf_params melt(int L)
 int main(void)
 {
     /* the paired schedule: every launch of every chain length, then bad arguments */
-    int out[7];
+    int out[8];
     long long total = 0;
     for (int n = 2; n <= HSF_MAX_BEADS; ++n)
         for (int j = 1; j <= n; ++j) {
