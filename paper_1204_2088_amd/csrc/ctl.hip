@@ -60,7 +60,11 @@ __device__ void reduce_and_control(RepState &S, int r, const int *__restrict__ b
                                    const double *__restrict__ part, int phase, const Chain &ch,
                                    const double *__restrict__ partG, int nblocks, double tol, int max_iter);
 
-__global__ __launch_bounds__(kBlock) void k_reduce_ctl(const int *__restrict__ blk_first,
+// One workgroup of kCtlBlock threads per replica: its reductions are chains of dependent
+// load batches, so more wavefronts per row shorten them.
+constexpr int kCtlBlock = 1024;
+
+__global__ __launch_bounds__(kCtlBlock) void k_reduce_ctl(const int *__restrict__ blk_first,
                                                        RepState *__restrict__ st, const Rep *__restrict__ rep,
                                                        const double *__restrict__ part, int phase, Chain ch,
                                                        const double *__restrict__ partG, int nblocks,
@@ -74,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_ctl(const int *__restrict__ b
         static_assert(sizeof(RepState) % 4 == 0, "RepState is copied as 32-bit words");
         const int *src = reinterpret_cast<const int *>(&st[r]);
         int *dst = reinterpret_cast<int *>(&S);
-        for (int k = threadIdx.x; k < (int)(sizeof(RepState) / 4); k += kBlock) dst[k] = src[k];
+        for (int k = threadIdx.x; k < (int)(sizeof(RepState) / 4); k += kCtlBlock) dst[k] = src[k];
     }
     __syncthreads();
 
@@ -97,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_ctl(const int *__restrict__ b
         const int *src = reinterpret_cast<const int *>(&S);
         int *dst = reinterpret_cast<int *>(&st[r]);
         int *hm = mirror ? reinterpret_cast<int *>(&mirror[r]) : nullptr;
-        for (int k = threadIdx.x; k < (int)(sizeof(RepState) / 4); k += kBlock) {
+        for (int k = threadIdx.x; k < (int)(sizeof(RepState) / 4); k += kCtlBlock) {
             dst[k] = src[k];
             if (hm) hm[k] = src[k];
         }
@@ -125,25 +129,47 @@ __device__ void reduce_and_control(RepState &S, int r, const int *__restrict__ b
     case PH_SOLVENT: nslots = 1; break;
     default: break;
     }
-    // one row per wavefront at a time: lanes stride over the replica's blocks, then a
-    // fixed shuffle tree; the order of additions is fixed, so results are reproducible
+    // Each row is split into contiguous parts of the replica's blocks, one wavefront per
+    // part (as many parts as the wavefronts allow, the same for every row of the phase);
+    // within a part the lanes stride over the blocks and a fixed shuffle tree adds them,
+    // then the parts are added in order: the order of additions is fixed, so results are
+    // reproducible.
+    constexpr int kWaves = kCtlBlock / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int row = wid; row < nslots + ng; row += kBlock / 64) {
-        double v = 0.0;
-        // unrolled so that the loads of several iterations are in flight together
-        if (row < nslots) {
+    const int nrows = nslots + ng;
+    const int parts = nrows > 0 ? (nrows >= kWaves ? 1 : kWaves / nrows) : 1;
+    const int span = (b1 - b0 + parts - 1) / parts;
+    __shared__ double psum[kWaves];
+    for (int t0 = 0; t0 < nrows * parts; t0 += kWaves) {
+        const int t = t0 + wid, row = t / parts, pt = t % parts;
+        if (row < nrows) {
+            const int lo = b0 + pt * span, hi = lo + span < b1 ? lo + span : b1;
+            double v = 0.0;
+            // unrolled so that the loads of several iterations are in flight together
+            if (row < nslots) {
 #pragma unroll 8
-            for (int b = b0 + lane; b < b1; b += 64) v += part[(long long)b * kNQ + row];
-        } else {
-            const double *base = partG + (long long)(g_first + row - nslots) * nblocks;
+                for (int b = lo + lane; b < hi; b += 64) v += part[(long long)b * kNQ + row];
+            } else {
+                const double *base = partG + (long long)(g_first + row - nslots) * nblocks;
 #pragma unroll 8
-            for (int b = b0 + lane; b < b1; b += 64) v += base[b];
-        }
+                for (int b = lo + lane; b < hi; b += 64) v += base[b];
+            }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-        if (lane == 0) vals[row] = v;
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+            if (lane == 0) psum[wid] = v;
+        }
+        __syncthreads();
+        // the rows completed in this round: their parts are the wavefronts t0 .. t0 + kWaves
+        if (threadIdx.x < kWaves / parts) {
+            const int row = t0 / parts + threadIdx.x;
+            if (row < nrows) {
+                double v = 0.0;
+                for (int q = 0; q < parts; ++q) v += psum[threadIdx.x * parts + q];
+                vals[row] = v;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const double *red = vals;
     const double *gsum = vals + nslots - g_first;   // gsum[s] = sum of stored G_{s+1}
     if (threadIdx.x == 0) control(S, phase, ch, red, gsum, V, rep[r].csum, tol, max_iter);
@@ -285,7 +311,7 @@ void launch_reduce_ctl(hipStream_t s, int n_rep, const Plan &p, RepState *st, co
                        const double *part, int phase, Chain ch, const double *partG, double tol,
                        int max_iter, RepState *mirror)
 {
-    hipLaunchKernelGGL(k_reduce_ctl, dim3(n_rep), dim3(kBlock), 0, s, p.blk_first, st, rep, part, phase, ch,
+    hipLaunchKernelGGL(k_reduce_ctl, dim3(n_rep), dim3(kCtlBlock), 0, s, p.blk_first, st, rep, part, phase, ch,
                        partG, p.nblocks, tol, max_iter, mirror);
 }
 
