@@ -202,7 +202,7 @@ RECIPE_EXTRA = {"vesicle128_a3b9s": [("delta", "vesicle_a3b9s_delta_w16.npz", "W
                                      ("direct", "vesicle_a3b9s_direct_w16.npz", "WARM_NET")]}
 
 
-def learned_arm(hsf, workload, precision, steps, tile, log, precond=False, widths=None, extra=False):
+def learned_arm(hsf, workload, precision, steps, tile, log, precond=False, widths=None, extra=False, refine=False):
     """The learned warm start on the benchmark's own workload: the recipe's networks
     (trained on the GPU from FP64 trajectories of other seeds, loaded from the package), or
     a network trained in this run when they are absent; then the cold (local guess), plain
@@ -236,15 +236,15 @@ def learned_arm(hsf, workload, precision, steps, tile, log, precond=False, width
     # only); plain: the previous step's fields; extrapolated: 2 w^n - w^(n-1)
     res = warmnet.trajectory_arms(wls, None, [("cold", hsf.WARM_LOCAL, 0)], cold_steps,
                                   [(0, 100), (100, cold_steps), (0, cold_steps)], tol=wls[0].tol,
-                                  precision=precision, tile=tile, precond=precond, log=log)
+                                  precision=precision, tile=tile, precond=precond, log=log, refine=refine)
     base = [("plain", hsf.WARM_CURRENT, 0), ("extrapolated", hsf.WARM_EXTRAP, 0)]
     res.update(warmnet.trajectory_arms(wls, None, base, steps, windows, tol=wls[0].tol, precision=precision,
-                                       tile=tile, precond=precond, log=log))
+                                       tile=tile, precond=precond, log=log, refine=refine))
     learned_names = []
     for name, net in nets.items():
         arms = [(f"learned_{name}", hsf.WARM_NET_EXTRAP, 0), (f"learned_{name}_gate2", hsf.WARM_NET_EXTRAP, 2)]
         res.update(warmnet.trajectory_arms(wls, net, arms, steps, windows, tol=wls[0].tol, precision=precision,
-                                           tile=tile, precond=precond, log=log))
+                                           tile=tile, precond=precond, log=log, refine=refine))
         learned_names += [a[0] for a in arms]
         net.close()
     if extra:
@@ -256,14 +256,15 @@ def learned_arm(hsf, workload, precision, steps, tile, log, precond=False, width
             infos[f"{tag}_w16"] = dict(info, file=f"paper_1204_2088_amd/nets/{fname}")
             arms = [(f"learned_{tag}_w16", getattr(hsf, mode), 0)]
             res.update(warmnet.trajectory_arms(wls, net, arms, steps, windows, tol=wls[0].tol, precision=precision,
-                                               tile=tile, precond=precond, log=log))
+                                               tile=tile, precond=precond, log=log, refine=refine))
             learned_names += [a[0] for a in arms]
             net.close()
     best_learned = min(learned_names, key=lambda k: res[k]["whole"]["ms_mean"])
     best_plain = min(("plain", "extrapolated"), key=lambda k: res[k]["whole"]["ms_mean"])
     ml = res[best_learned]["whole"]["ms_mean"]
     return {
-        "tol": wls[0].tol, "steps": steps, "solver": "preconditioned FR" if precond else "FR",
+        "tol": wls[0].tol, "steps": steps,
+        "solver": ("preconditioned FR" if precond else "FR") + (", FP64 evaluations below 1e-5" if refine else ""),
         "protocol": "each warm start runs the whole trajectory from the quench (seed 0), every step timed "
                     "(the cold start its first cold_steps steps, compared with the same steps of the best "
                     "learned arm); windows are step ranges of that trajectory; gate2: the network is used "
@@ -470,6 +471,9 @@ def main():
                     help="diagonally preconditioned inversion (auto: on for solutions)")
     ap.add_argument("--tile", default=None, help="cx,cy,cz,k: use this propagator tiling instead of autotuning (k = 0: one step per launch, -1: paired forward/backward steps, >= 1: temporally blocked)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start comparison")
+    ap.add_argument("--arms-refine", action="store_true",
+                    help="run the warm-start arms with FP64 evaluations below a residual of 1e-5 (their "
+                         "evaluation counts then no longer depend on FP32 rounding near the inversion floor)")
     ap.add_argument("--extra-arms", action="store_true",
                     help="also run the NET_DELTA and NET warm starts of the recipe (first-difference and direct-map "
                          "networks) over the same trajectory")
@@ -599,7 +603,7 @@ def main():
         learned = learned_arm(hsf, args.workload, args.precision, args.compare_steps, tuple(tile), log,
                               precond=precond,
                               widths=tuple(int(v) for v in args.net_widths.split(",")) if args.net_widths else None,
-                              extra=args.extra_arms)
+                              extra=args.extra_arms, refine=args.arms_refine)
 
     extra = {}
     if not args.no_extra and args.workload == "vesicle128_a3b9s":

@@ -271,18 +271,19 @@ def compare_warm_starts(wls, net, modes, start_steps, measure_steps, tol=1e-6, p
 
 
 def trajectory_arms(wls, net, arms, steps, windows, tol=1e-6, precision="fp32", tile=None, precond=False,
-                    max_iter=1000, log=None):
+                    max_iter=1000, log=None, refine=False):
     """Each warm start runs the whole trajectory of `wls` from the quench for `steps`
     coupled steps (same initial state, same tiling), timing every step.  arms: list of
     (name, warm mode, gate).  windows: list of (first, last) step ranges (last
-    exclusive) over which the per-step times are summarised.  Returns
+    exclusive) over which the per-step times are summarised.  refine: FP32 contexts finish
+    each inversion below a residual of 1e-5 with FP64 evaluations.  Returns
     {name: {"whole": {...}, "windows": {"a-b": {...}}}} with the mean, median and 95th
     percentile step time and the mean evaluations per step of each range."""
     torch = _torch()
     out = {}
     for name, mode, gate in arms:
         ctx = hsf.Context(wls, precision=precision)
-        ctx.set_solver(precond=precond)
+        ctx.set_solver(precond=precond, refine=refine)
         phi0, w0 = initial_state(ctx, wls)
         ctx.set_densities(phi0)
         ctx.set_fields(w0)
