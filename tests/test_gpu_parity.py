@@ -743,12 +743,14 @@ def test_paired_sweeps_match_one_step_bitwise(hsf, orc, precision):
     """Paired launches (one forward and one backward contour step per launch, the
     density term formed by whichever of a bead's two steps runs second) store every
     value as the same expression of the same operands as the one-step sequence: for
-    odd and even N, one replica (descriptors as kernel arguments) and six of uneven
+    odd and even N (N = 2, where backward step N forms its own field factor, and even
+    N >= 4, where backward step N - 1 forms G+_N from the stored factor), one replica
+    (descriptors as kernel arguments) and six of uneven
     boxes (descriptors in device tables), the densities and Q are bit for bit those of
     the one-step kernels of the same tiling, and within tolerance of the oracle."""
     tol = TOL64 if precision == "fp64" else TOL32
     for L, types in [((17, 18, 20), W.chain(3, 4)), ((24, 20, 9), W.chain(4, 4)), ((5, 3, 9), W.chain(2, 3)),
-                     ((9, 7, 5), W.chain(1, 1)), ((12, 11, 10), W.chain(5, 11))]:
+                     ((9, 7, 5), W.chain(1, 1)), ((12, 11, 10), W.chain(5, 11)), ((13, 9, 11), W.chain(1, 3))]:
         wl = small_melt(L=L, types=types, precision=precision)
         w = fields_for(wl, seed=21, amp=1.2)
         ref, qref = orc.evaluate(osys(orc, wl), w, 1.0, 0.0)
